@@ -1,0 +1,203 @@
+/*
+ * expwave.h -- C ABI of the exponential wave-propagation library (gfx950).
+ *
+ * Method: Ravelo, Schreiber, Peixoto, "High-order exponential integration for
+ * seismic wave modeling" (arXiv 2401.16322).
+ *
+ *   Sec. 3 (time integration methods): semi-discrete system U' = H U + f(t).
+ *   Sec. 3.2, Faber approximation: u^{n+1} = sum_{j=0..m} a_j F_j(H~) [u^n; e_p],
+ *       F_0 = I, F_1 = H/gamma - c0 I, F_2 = F_1^2 - 2 c1 I,
+ *       F_j = F_1 F_{j-1} - c1 F_{j-2}.
+ *   Sec. 3.2, Krylov subspace projection: Arnoldi (modified Gram-Schmidt)
+ *       then the small Hessenberg exponential by Pade.
+ *   Sec. 3.2, augmented matrix H~ = [[H, W], [0, J]]: the source and its
+ *       first p-1 derivatives folded into one exponential.
+ *   Sec. 3.1, low order methods: classical RK4 and leap-frog (baselines).
+ *   Sec. 2: absorbing layer with the quadratic profile
+ *       sigma(d) = sigma_max (1 - d/delta)^2, zero values outside the domain.
+ *   Sec. 2.1: staggered first-derivative stencils (order 4 or the paper's 8).
+ *
+ * The operator is the first-order pressure/velocity system with a diagonal
+ * damping layer and rho = 1:
+ *     (H U)_p   = -c^2 sum_a D-_a v_a - (sum_a sigma_a(x_a)) p
+ *     (H U)_v_a = -D+_a p - sigma_a(x_a + h/2) v_a
+ * with p on nodes and v_a half a cell forward along axis a.
+ *
+ * Conventions
+ * - State layout (canonical, unpadded, field-major): [p | v_0 | ... | v_{d-1}],
+ *   each field n_0 * n_1 (* n_2) values with axis 0 (x) fastest. In 2D the
+ *   axes are (x, z); in 3D (x, y, z). The velocity slots of the leap-frog
+ *   state hold v at t - dt/2.
+ * - Element type of every device array (state, c^2, traces) is the grid dtype.
+ * - Ownership: the caller allocates and owns every device buffer (c^2, state,
+ *   traces, receiver indices, workspace). The library never allocates device
+ *   memory; destroy frees only the host-side handle.
+ * - Streams: device work is enqueued on the handle's stream (a hipStream_t
+ *   passed as void*; NULL is the legacy default stream) and is asynchronous,
+ *   except where noted ("synchronizes").
+ * - Errors: every entry point returns an expw_status. Arguments are validated
+ *   before any launch; on a non-OK status nothing was enqueued and
+ *   expw_last_error() returns a message (thread-local). Device launch
+ *   failures return EXPW_EDEVICE.
+ * - Host-math entry points (marked "host only") touch no GPU and may be
+ *   called on a machine without one.
+ */
+#ifndef EXPWAVE_H
+#define EXPWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct expw_op expw_op; /* opaque host-side handle */
+
+typedef enum {
+  EXPW_OK = 0,
+  EXPW_EINVAL = -1,       /* invalid argument (message says which) */
+  EXPW_ENOMEM = -2,       /* caller-supplied workspace too small */
+  EXPW_EDEVICE = -3,      /* HIP runtime or launch failure */
+  EXPW_ENONFINITE = -4,   /* NaN/Inf in c^2 */
+  EXPW_EUNSUPPORTED = -5  /* valid but not supported combination */
+} expw_status;
+
+typedef enum { EXPW_F32 = 0, EXPW_F64 = 1 } expw_dtype;
+typedef enum { EXPW_BC_ZERO = 0, EXPW_BC_PERIODIC = 1 } expw_bc;
+
+enum {
+  EXPW_MAX_KRYLOV = 64, /* largest Krylov dimension k */
+  EXPW_MAX_TAYLOR = 16, /* largest source Taylor order p */
+  EXPW_MAX_SOURCES = 64 /* largest number of point sources */
+};
+
+typedef struct {
+  int32_t ndim;      /* 2 or 3 */
+  int32_t order;     /* staggered stencil order: 4 or 8 */
+  int64_t n[3];      /* (nx, nz, 1) in 2D, (nx, ny, nz) in 3D; each >= 1 */
+  double h;          /* grid spacing (m), > 0 */
+  int32_t dtype;     /* expw_dtype of every device array */
+  int32_t bc;        /* expw_bc: zero ghost values (Sec. 2.1) or periodic */
+  int32_t abc_cells; /* damping-layer thickness L in cells (delta = L h), >= 0 */
+  int32_t reserved;  /* must be 0 */
+  double sigma_max;  /* peak damping sigma_max (1/s), >= 0; must be 0 with periodic bc */
+} expw_grid;
+
+/* ------------------------------------------------------------------ host only */
+
+/* Library ABI version (currently 1). */
+int32_t expw_version(void);
+
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char* expw_last_error(void);
+
+/* Bytes of device workspace expw_op_create needs for a grid, a largest Krylov
+ * dimension max_krylov_k (0 = Krylov unused, <= EXPW_MAX_KRYLOV) and a largest
+ * source Taylor order max_taylor_p (<= EXPW_MAX_TAYLOR). */
+int32_t expw_workspace_size(const expw_grid* grid, int32_t max_krylov_k, int32_t max_taylor_p,
+                            size_t* bytes);
+
+/* Sec. 2, absorption profile: out[i] = sigma at x_i = i h (half = 0) or
+ * (i + 1/2) h (half = 1); distance to the nearest outer node (0 or n-1),
+ * clamped at 0; sigma_max (1 - d/delta)^2 for d < delta = cells h, else 0. */
+int32_t expw_damping_profile(int64_t n, double h, int32_t cells, double sigma_max, int32_t half,
+                             double* out);
+
+/* Field-of-values rectangle [x_lo, 0] x i[-B, B] of H for a grid whose largest
+ * c^2 is c2_max: B = sqrt(c2_max) sqrt(ndim) (2/h) sum |alpha_l|, x_lo = -max damping. */
+int32_t expw_spectrum_rectangle(const expw_grid* grid, double c2_max, double* x_lo, double* B);
+
+/* Faber ellipse (gamma, c0, c1) of the minimum-area ellipse around the
+ * rectangle (Sec. 3.2: the parameters of F_1 = H/gamma - c0 I). */
+int32_t expw_ellipse(double x_lo, double B, double* gamma, double* c0, double* c1);
+
+/* Faber coefficients a_0..a_m of exp(dt z) on that ellipse: the Laurent
+ * coefficients of exp(dt gamma (w + c0 + c1/w)). a has m+1 entries. */
+int32_t expw_faber_coefficients(double gamma, double c0, double c1, double dt, int32_t m, double* a);
+
+/* Ricker wavelet g(t) = (1 - 2 a tau^2) exp(-a tau^2), a = (pi f_peak)^2,
+ * tau = t - t_delay, and its derivatives: out[k] = g^(k)(t), k = 0..p-1. */
+int32_t expw_ricker_derivatives(double t, double f_peak, double t_delay, int32_t p, double* out);
+
+/* Source scalars of one Faber step (Sec. 3.2, augmented matrix): with the tail
+ * tau_0 = e_p run through the same three-term recurrence under J,
+ * q[j-1] = (G . tau_{j-1}) / gamma for j = 1..m, where G[c] = g^(p-1-c)(t_n).
+ * G has p entries; q has m entries. */
+int32_t expw_faber_source_scalars(double gamma, double c0, double c1, int32_t m, int32_t p,
+                                  const double* G, double* q);
+
+/* Matrix exponential of a k x k row-major matrix (scaling and squaring with
+ * the [13/13] Pade approximant; k <= EXPW_MAX_KRYLOV + 1). */
+int32_t expw_expm(int32_t k, const double* A, double* E);
+
+/* ------------------------------------------------------------------ device */
+
+/* Create an operator from c^2 (device array, one field of the grid dtype) and
+ * the damping layer in *grid. Synchronizes: computes max c^2 on the device
+ * (EXPW_ENONFINITE on NaN/Inf or c^2 <= 0), then the spectrum rectangle and
+ * the Faber ellipse on the host in FP64, and uploads the 1D damping profiles
+ * into the workspace. c2_dev and workspace_dev must stay valid and unmodified
+ * (except by the library) while the handle lives. */
+int32_t expw_op_create(const expw_grid* grid, const void* c2_dev, int32_t max_krylov_k,
+                       int32_t max_taylor_p, void* workspace_dev, size_t workspace_bytes,
+                       void* hip_stream, expw_op** out);
+int32_t expw_op_destroy(expw_op* op);
+
+/* Stream for subsequent launches (hipStream_t as void*). */
+int32_t expw_set_stream(expw_op* op, void* hip_stream);
+
+/* Host values of the spectrum rectangle and of the ellipse in use. */
+int32_t expw_get_spectrum(const expw_op* op, double* x_lo, double* B);
+int32_t expw_get_ellipse(const expw_op* op, double* gamma, double* c0, double* c1);
+/* Override the ellipse (gamma > 0, |c1| < 1); the next Faber step uses it. */
+int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
+
+/* Kernel tuning for the Faber step: fuse = recurrence terms per HBM sweep
+ * (0 = automatic, 1 = one term per sweep, up to 8), tile_x/tile_y = output
+ * tile of the fused kernel (0 = automatic). Results do not depend on these
+ * beyond rounding order. */
+int32_t expw_set_tuning(expw_op* op, int32_t fuse, int32_t tile_x, int32_t tile_y);
+
+/* y = H x (no source), x and y device state arrays (must not alias). */
+int32_t expw_apply(expw_op* op, const void* x_dev, void* y_dev);
+
+/* Point sources sharing one Ricker wavelet (f_peak, t_delay) entering the
+ * pressure equation at flat node indices node_idx_host[s] (0 <= idx < points)
+ * with strength amp_host[s] / h^ndim; taylor_p (1..max_taylor_p given at
+ * create) is the Taylor order of the augmented matrix used by the Faber and
+ * Krylov steps. n_src = 0 removes the sources. Synchronizes (small upload). */
+int32_t expw_set_source_ricker(expw_op* op, int32_t n_src, const int64_t* node_idx_host,
+                               const double* amp_host, double f_peak, double t_delay,
+                               int32_t taylor_p);
+
+/* Receivers: n_rec flat pressure-node indices in a caller-owned device int64
+ * array (validated once, synchronizes). After every step the pressure at the
+ * receivers is written to traces[step * n_rec + r] when a step call is given
+ * a non-NULL traces_dev. n_rec = 0 removes the receivers. */
+int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* node_idx_dev);
+
+/* Advance the state nsteps steps of size dt starting at time t0 (step s runs
+ * from t0 + s dt). traces_dev: NULL or an array of nsteps * n_rec elements. */
+int32_t expw_step_faber(expw_op* op, void* state_dev, double t0, double dt, int32_t m,
+                        int64_t nsteps, void* traces_dev);
+/* Krylov steps synchronize once per step (the k x k Hessenberg matrix is
+ * exponentiated on the host in FP64). Requires k <= max_krylov_k. */
+int32_t expw_step_krylov(expw_op* op, void* state_dev, double t0, double dt, int32_t k,
+                         int64_t nsteps, void* traces_dev);
+int32_t expw_step_rk4(expw_op* op, void* state_dev, double t0, double dt, int64_t nsteps,
+                      void* traces_dev);
+int32_t expw_step_leapfrog(expw_op* op, void* state_dev, double t0, double dt, int64_t nsteps,
+                           void* traces_dev);
+
+/* Synchronizes the stream and reports a pending device error. */
+int32_t expw_sync_status(expw_op* op);
+
+/* Effective dimension and beta of the last Krylov step (host values). */
+int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXPWAVE_H */

@@ -1,0 +1,167 @@
+// Device-side building blocks: grid geometry, the staggered operator at one
+// point, source injection and deterministic grid-wide FP64 reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace expw {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kRedMaxBlocks = 1024;  // grid cap (and partials length) of reduction kernels
+
+// Geometry and coefficients of H on one grid, passed to kernels by value.
+// Axis a has extent n[a] and flat stride st[a] (axis 0 fastest); w[l-1] =
+// alpha_l / h; sint/shalf are the damping profiles at integer / half points.
+template <typename T, int K, int DIM>
+struct Geo {
+  int64_t n[3];
+  int64_t st[3];
+  int64_t N;  // points per field
+  T w[K];
+  const T* __restrict__ c2;
+  const T* __restrict__ sint[3];
+  const T* __restrict__ shalf[3];
+};
+
+template <int DIM>
+__device__ __forceinline__ void decompose(const int64_t* n, int64_t idx, int64_t* ic) {
+  ic[0] = idx % n[0];
+  const int64_t r = idx / n[0];
+  if (DIM == 2) {
+    ic[1] = r;
+    ic[2] = 0;
+  } else {
+    ic[1] = r % n[1];
+    ic[2] = r / n[1];
+  }
+}
+
+// f at the point shifted by s along an axis of extent n and stride st, for a
+// point at coordinate i of that axis: zero outside (Sec. 2.1 ghost rule), or
+// wrapped for the periodic closed-form tests.
+template <typename T, int BC>
+__device__ __forceinline__ T ldn(const T* __restrict__ f, int64_t idx, int64_t i, int64_t n,
+                                 int64_t st, int s) {
+  const int64_t j = i + s;
+  if (BC == 0) return (j >= 0 && j < n) ? f[idx + s * st] : T(0);
+  int64_t jj = j % n;
+  if (jj < 0) jj += n;
+  return f[idx + (jj - i) * st];
+}
+
+// out = H x at one point (all DIM+1 fields), self = x at that point:
+//   out_p   = -c2 sum_a D-_a v_a - (sum_a sigma_a) p
+//   out_v_a = -D+_a p - sigma_a(half) v_a
+template <typename T, int K, int BC, int DIM>
+__device__ __forceinline__ void apply_point(const Geo<T, K, DIM>& g, const T* __restrict__ x,
+                                            int64_t idx, const int64_t* ic, T* out, T* self) {
+  const T* __restrict__ p = x;
+  const T pc = p[idx];
+  self[0] = pc;
+  T div = T(0), sp = T(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* __restrict__ v = x + (1 + a) * g.N;
+    T dv = T(0), dp = T(0);
+#pragma unroll
+    for (int l = 1; l <= K; ++l) {
+      dv += g.w[l - 1] * (ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], l - 1) -
+                          ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], -l));
+      dp += g.w[l - 1] * (ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], l) -
+                          ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], 1 - l));
+    }
+    div += dv;
+    sp += g.sint[a][ic[a]];
+    const T vc = v[idx];
+    self[1 + a] = vc;
+    out[1 + a] = -dp - g.shalf[a][ic[a]] * vc;
+  }
+  out[0] = -g.c2[idx] * div - sp * pc;
+}
+
+// Point sources: flat pressure indices idx[s] with amplitudes amp[s];
+// [lo, hi] bounds the indices so that other threads skip the search.
+template <typename T>
+struct Src {
+  int32_t n;
+  int64_t lo, hi;
+  const int64_t* __restrict__ idx;
+  const T* __restrict__ amp;
+  T q;  // scalar multiplying every amplitude for this launch
+};
+
+template <typename T>
+__device__ __forceinline__ T src_value(const Src<T>& s, int64_t idx) {
+  T r = T(0);
+  if (s.n > 0 && idx >= s.lo && idx <= s.hi)
+    for (int i = 0; i < s.n; ++i)
+      if (s.idx[i] == idx) r += s.q * s.amp[i];
+  return r;
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Block-wide reduction; the result is valid in thread 0. Ends with a barrier
+// so that the shared scratch can be reused right away.
+template <bool MAX>
+__device__ __forceinline__ double block_reduce(double v) {
+  __shared__ double sh[kBlock / 64];
+  v = MAX ? wave_max(v) : wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = MAX ? -INFINITY : 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBlock / 64; ++i) r = MAX ? fmax(r, sh[i]) : r + sh[i];
+  __syncthreads();
+  return r;
+}
+
+// Grid-wide reduction in a fixed order: every block stores its partial, the
+// last block to arrive (device-scope counter) combines the partials in block
+// order and writes *out, then resets the counter for the next launch. The
+// fences publish the partials across the L2s of all XCDs before the counter
+// increment, and make the last block observe them.
+template <bool MAX>
+__device__ void grid_reduce(double v, double* __restrict__ partials, unsigned* counter,
+                            double* out) {
+  __shared__ int s_last;
+  const double b = block_reduce<MAX>(v);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = b;
+    __threadfence();
+    const unsigned prev =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    double acc = MAX ? -INFINITY : 0.0;
+    for (unsigned i = threadIdx.x; i < gridDim.x; i += kBlock) {
+      const double pv = __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      acc = MAX ? fmax(acc, pv) : acc + pv;
+    }
+    const double tot = block_reduce<MAX>(acc);
+    if (threadIdx.x == 0) {
+      *out = tot;
+      __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+}  // namespace expw

@@ -1,0 +1,696 @@
+// C ABI of the exponential wave-propagation library: handle, validation,
+// workspace layout and the host drivers of the Faber, Krylov, RK4 and
+// leap-frog steps. All device work is enqueued on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fused.h"
+#include "internal.h"
+#include "kernels.h"
+
+struct expw_op {
+  expw_grid g;
+  int K;
+  double alpha[4];
+  const void* c2;
+  char* ws;
+  size_t ws_bytes;
+  hipStream_t stream;
+  int kmax, pmax;
+  // workspace layout (byte offsets)
+  size_t off_sig[3][2];
+  size_t off_src_idx, off_src_amp, off_part, off_cnt, off_scal, off_hess, off_ss, off_big;
+  int64_t naug_pad;  // stride of a Krylov basis vector (elements)
+  // spectrum and ellipse (host FP64)
+  double c2max, x_lo, B, gamma, c0, c1;
+  // sources
+  int n_src;
+  std::vector<int64_t> src_idx;
+  std::vector<double> src_amp;
+  int64_t src_lo, src_hi;
+  double f_peak, t_delay;
+  int taylor_p;
+  // receivers
+  int n_rec;
+  const int64_t* rec_dev;
+  // tuning
+  int fuse, tile_x, tile_y;
+  // last Krylov step
+  int last_keff;
+  double last_beta;
+};
+
+namespace expw {
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+int64_t npts(const expw_grid& g) { return g.n[0] * g.n[1] * (g.ndim == 3 ? g.n[2] : 1); }
+size_t elem_size(const expw_grid& g) { return g.dtype == EXPW_F32 ? 4 : 8; }
+constexpr int kHessLd = EXPW_MAX_KRYLOV;  // leading dimension of the Hessenberg matrix
+
+int32_t validate_grid(const expw_grid* g) {
+  if (!g) return fail(EXPW_EINVAL, "grid is NULL");
+  if (g->ndim != 2 && g->ndim != 3) return fail(EXPW_EINVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
+  if (g->order != 4 && g->order != 8) return fail(EXPW_EINVAL, "order must be 4 or 8 (got %d)", g->order);
+  for (int a = 0; a < g->ndim; ++a)
+    if (g->n[a] < 1) return fail(EXPW_EINVAL, "n[%d] must be >= 1", a);
+  if (g->ndim == 2 && g->n[2] != 1) return fail(EXPW_EINVAL, "n[2] must be 1 for a 2D grid");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(EXPW_EINVAL, "h must be positive and finite");
+  if (g->dtype != EXPW_F32 && g->dtype != EXPW_F64) return fail(EXPW_EINVAL, "dtype must be EXPW_F32 or EXPW_F64");
+  if (g->bc != EXPW_BC_ZERO && g->bc != EXPW_BC_PERIODIC) return fail(EXPW_EINVAL, "bc must be EXPW_BC_ZERO or EXPW_BC_PERIODIC");
+  if (g->abc_cells < 0) return fail(EXPW_EINVAL, "abc_cells must be >= 0");
+  if (!(g->sigma_max >= 0.0) || !std::isfinite(g->sigma_max)) return fail(EXPW_EINVAL, "sigma_max must be >= 0 and finite");
+  if (g->bc == EXPW_BC_PERIODIC && g->sigma_max != 0.0 && g->abc_cells > 0)
+    return fail(EXPW_EINVAL, "a periodic grid takes no damping layer");
+  if (g->reserved != 0) return fail(EXPW_EINVAL, "reserved must be 0");
+  if (npts(*g) > (int64_t(1) << 40)) return fail(EXPW_EINVAL, "grid too large");
+  return EXPW_OK;
+}
+
+struct Layout {
+  size_t sig[3][2];
+  size_t src_idx, src_amp, part, cnt, scal, hess, ss, big, total;
+  int64_t naug_pad;
+};
+
+Layout layout(const expw_grid& g, int kmax, int pmax) {
+  Layout L{};
+  const size_t es = elem_size(g);
+  size_t off = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int hf = 0; hf < 2; ++hf) {
+      L.sig[a][hf] = off;
+      if (a < g.ndim) off = align_up(off + g.n[a] * es);
+    }
+  L.src_idx = off; off = align_up(off + EXPW_MAX_SOURCES * sizeof(int64_t));
+  L.src_amp = off; off = align_up(off + EXPW_MAX_SOURCES * es);
+  L.part = off; off = align_up(off + kRedMaxBlocks * sizeof(double));
+  L.cnt = off; off = align_up(off + 64 * sizeof(unsigned));
+  L.scal = off; off = align_up(off + 64 * sizeof(double));
+  L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
+  L.ss = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * sizeof(double));
+  L.big = off;
+  const int64_t ns = (g.ndim + 1) * npts(g);
+  L.naug_pad = (ns + pmax + 63) / 64 * 64;
+  size_t big = 5 * static_cast<size_t>(ns) * es;  // Faber: v pairs (2 x 2) + partial sum
+  if (kmax > 0) big = std::max(big, static_cast<size_t>(kmax + 1) * L.naug_pad * es);
+  L.total = align_up(off + big);
+  return L;
+}
+
+template <typename T, int K, int BC, int DIM>
+struct Cfg {
+  using type = T;
+  static constexpr int k = K, bc = BC, dim = DIM;
+};
+
+template <typename T, class Fn>
+int32_t dispatch_t(const expw_op* op, Fn& fn) {
+  const bool per = op->g.bc == EXPW_BC_PERIODIC;
+  const bool d3 = op->g.ndim == 3;
+  if (op->K == 2) {
+    if (d3) return per ? fn(Cfg<T, 2, 1, 3>{}) : fn(Cfg<T, 2, 0, 3>{});
+    return per ? fn(Cfg<T, 2, 1, 2>{}) : fn(Cfg<T, 2, 0, 2>{});
+  }
+  if (d3) return per ? fn(Cfg<T, 4, 1, 3>{}) : fn(Cfg<T, 4, 0, 3>{});
+  return per ? fn(Cfg<T, 4, 1, 2>{}) : fn(Cfg<T, 4, 0, 2>{});
+}
+
+template <class Fn>
+int32_t dispatch(const expw_op* op, Fn&& fn) {
+  if (op->g.dtype == EXPW_F32) return dispatch_t<float>(op, fn);
+  return dispatch_t<double>(op, fn);
+}
+
+template <typename T, int K, int DIM>
+Geo<T, K, DIM> make_geo(const expw_op* op) {
+  Geo<T, K, DIM> g{};
+  g.n[0] = op->g.n[0];
+  g.n[1] = op->g.n[1];
+  g.n[2] = DIM == 3 ? op->g.n[2] : 1;
+  g.st[0] = 1;
+  g.st[1] = g.n[0];
+  g.st[2] = g.n[0] * g.n[1];
+  g.N = g.n[0] * g.n[1] * g.n[2];
+  for (int l = 0; l < K; ++l) g.w[l] = static_cast<T>(op->alpha[l] / op->g.h);
+  g.c2 = static_cast<const T*>(op->c2);
+  for (int a = 0; a < 3; ++a) {
+    g.sint[a] = reinterpret_cast<const T*>(op->ws + op->off_sig[a][0]);
+    g.shalf[a] = reinterpret_cast<const T*>(op->ws + op->off_sig[a][1]);
+  }
+  return g;
+}
+
+template <typename T>
+Src<T> make_src(const expw_op* op, double q) {
+  Src<T> s{};
+  s.n = op->n_src;
+  s.lo = op->src_lo;
+  s.hi = op->src_hi;
+  s.idx = reinterpret_cast<const int64_t*>(op->ws + op->off_src_idx);
+  s.amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
+  s.q = static_cast<T>(q);
+  return s;
+}
+
+int32_t check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(EXPW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return EXPW_OK;
+}
+
+unsigned grid_for(int64_t n) {
+  return static_cast<unsigned>(std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+}
+unsigned red_grid_for(int64_t n) {
+  return static_cast<unsigned>(std::min<int64_t>(kRedMaxBlocks, std::max<int64_t>(1, (n + 4 * kBlock - 1) / (4 * kBlock))));
+}
+
+double src_scale(const expw_op* op) { return 1.0 / std::pow(op->g.h, op->g.ndim); }
+
+template <typename T>
+int32_t gather(expw_op* op, const T* S, T* traces, int64_t step) {
+  if (!traces || op->n_rec == 0) return EXPW_OK;
+  k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec,
+                                                                 traces + step * op->n_rec);
+  return check_launch("gather");
+}
+
+// ---------------------------------------------------------------- Faber step
+
+template <typename T, int K, int BC, int DIM>
+int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, T* S, T* Abuf, T* Bbuf, T* Cbuf,
+                      const double* a, const double* q, int m) {
+  const int64_t ns = (DIM + 1) * g.N;
+  const unsigned grid = grid_for(g.N);
+  FaberTerm<T> c{};
+  c.inv_gamma = static_cast<T>(1.0 / op->gamma);
+  c.c0 = static_cast<T>(op->c0);
+  // j = 1: v1 = F1 v0 into A; acc = a0 v0 + a1 v1 into C
+  c.cpp = T(0);
+  c.first = 1;
+  c.a_first = static_cast<T>(a[0]);
+  c.a_j = static_cast<T>(a[1]);
+  k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, nullptr, m == 1 ? nullptr : Abuf,
+                                                               nullptr, Cbuf, c, make_src<T>(op, q[0]));
+  if (m == 1) {
+    if (hipMemcpyAsync(S, Cbuf, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
+      return fail(EXPW_EDEVICE, "faber: copy failed");
+    return check_launch("faber j=1");
+  }
+  // j = 2: v2 = F1 v1 - 2 c1 v0 into B (v0 = S read pointwise)
+  c.first = 0;
+  c.a_first = T(0);
+  c.cpp = static_cast<T>(2.0 * op->c1);
+  c.a_j = static_cast<T>(a[2]);
+  k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(
+      g, Abuf, S, m == 2 ? nullptr : Bbuf, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
+  T* last = Bbuf;   // v_{j-1}
+  T* older = Abuf;  // v_{j-2}
+  c.cpp = static_cast<T>(op->c1);
+  for (int j = 3; j <= m; ++j) {
+    c.a_j = static_cast<T>(a[j]);
+    const bool fin = (j == m);
+    k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(
+        g, last, older, fin ? nullptr : older, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
+    std::swap(last, older);
+  }
+  return check_launch("faber term");
+}
+
+template <typename T, int K, int BC, int DIM>
+int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nsteps, T* traces) {
+  const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
+  const int64_t ns = (DIM + 1) * g.N;
+  T* Abuf = reinterpret_cast<T*>(op->ws + op->off_big);
+  T* Bbuf = Abuf + ns;
+  T* Cbuf = Bbuf + ns;
+  std::vector<double> a(m + 1), q(m, 0.0), der(EXPW_MAX_TAYLOR), G(EXPW_MAX_TAYLOR);
+  faber_coefficients(op->gamma, op->c0, op->c1, dt, m, a.data());
+  const int p = op->taylor_p;
+  T* Dbuf = Cbuf + ns;
+  T* Ebuf = Dbuf + ns;
+  const int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m);
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const double t = t0 + st * dt;
+    if (op->n_src > 0) {
+      ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
+      for (int c = 0; c < p; ++c) G[c] = der[p - 1 - c];
+      faber_source_scalars(op->gamma, op->c0, op->c1, m, p, G.data(), q.data());
+      const double sc = src_scale(op);
+      for (int j = 0; j < m; ++j) q[j] *= sc;
+    }
+    int32_t rc;
+    if (fuse > 1)
+      rc = faber_fused<T, K, BC, DIM>(op->stream, g, make_src<T>(op, 0.0), S, Abuf, Bbuf, Cbuf,
+                                      Dbuf, Ebuf, a.data(), q.data(), m, fuse, op->gamma, op->c0,
+                                      op->c1);
+    else
+      rc = faber_unfused<T, K, BC, DIM>(op, g, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
+    if (rc != EXPW_OK) return rc;
+    if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+  }
+  return EXPW_OK;
+}
+
+// ---------------------------------------------------------------- RK4 and leap-frog
+
+template <typename T, int K, int BC, int DIM>
+int32_t rk4_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T* traces) {
+  const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
+  const int64_t ns = (DIM + 1) * g.N;
+  T* Abuf = reinterpret_cast<T*>(op->ws + op->off_big);
+  T* Bbuf = Abuf + ns;
+  T* Cbuf = Bbuf + ns;
+  const unsigned grid = grid_for(g.N);
+  const double sc = src_scale(op);
+  double der[1];
+  auto srcq = [&](double t) {
+    if (op->n_src == 0) return make_src<T>(op, 0.0);
+    ricker_derivatives(t, op->f_peak, op->t_delay, 1, der);
+    return make_src<T>(op, der[0] * sc);
+  };
+  const T h2 = static_cast<T>(0.5 * dt), h1 = static_cast<T>(dt), s6 = static_cast<T>(dt / 6.0),
+          s3 = static_cast<T>(dt / 3.0);
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const double t = t0 + st * dt;
+    k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, S, nullptr, Abuf, Cbuf, h2, s6, srcq(t));
+    k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Abuf, S, Cbuf, Bbuf, Cbuf, h2, s3, srcq(t + 0.5 * dt));
+    k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Bbuf, S, Cbuf, Abuf, Cbuf, h1, s3, srcq(t + 0.5 * dt));
+    k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Abuf, nullptr, Cbuf, nullptr, S, T(0), s6, srcq(t + dt));
+    int32_t rc = check_launch("rk4 stage");
+    if (rc != EXPW_OK) return rc;
+    if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+  }
+  return EXPW_OK;
+}
+
+template <typename T, int K, int BC, int DIM>
+int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T* traces) {
+  const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
+  const unsigned grid = grid_for(g.N);
+  const double sc = src_scale(op);
+  double der[1];
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const double t = t0 + st * dt;
+    k_lf_v<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, static_cast<T>(dt));
+    double q = 0.0;
+    if (op->n_src > 0) {
+      ricker_derivatives(t + 0.5 * dt, op->f_peak, op->t_delay, 1, der);
+      q = dt * der[0] * sc;
+    }
+    k_lf_p<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, static_cast<T>(dt), make_src<T>(op, q));
+    int32_t rc = check_launch("leapfrog");
+    if (rc != EXPW_OK) return rc;
+    if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+  }
+  return EXPW_OK;
+}
+
+// ---------------------------------------------------------------- Krylov step
+
+template <typename T, int K, int BC, int DIM>
+int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nsteps, T* traces) {
+  const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
+  const int64_t ns = (DIM + 1) * g.N;
+  const int p = op->n_src > 0 ? op->taylor_p : 0;
+  const int64_t naug = ns + p;
+  const int64_t ld = op->naug_pad;
+  T* Q = reinterpret_cast<T*>(op->ws + op->off_big);
+  double* part = reinterpret_cast<double*>(op->ws + op->off_part);
+  unsigned* cnt = reinterpret_cast<unsigned*>(op->ws + op->off_cnt);
+  double* scal = reinterpret_cast<double*>(op->ws + op->off_scal);
+  double* hess = reinterpret_cast<double*>(op->ws + op->off_hess);
+  double* ssq = reinterpret_cast<double*>(op->ws + op->off_ss);
+  const T* amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
+  const unsigned rg_vec = red_grid_for(naug);
+  const unsigned rg_pts = red_grid_for(g.N + p);
+  const double tol = 1e-14;
+  std::vector<double> hh((EXPW_MAX_KRYLOV + 1) * kHessLd), hk(k * k), E(k * k), der(EXPW_MAX_TAYLOR);
+  std::vector<double> scal_h(2);
+  KrySrc ks{};
+  ks.n = op->n_src;
+  ks.p = p;
+  ks.lo = op->src_lo;
+  ks.hi = op->src_hi;
+  ks.idx = reinterpret_cast<const int64_t*>(op->ws + op->off_src_idx);
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const double t = t0 + st * dt;
+    if (p > 0) {
+      ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
+      const double sc = src_scale(op);
+      for (int c = 0; c < p; ++c) ks.G[c] = der[p - 1 - c] * sc;
+    }
+    // q_1 = [S; e_p] / beta
+    k_norm2<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, ns, part, cnt, scal + 0);
+    k_kry_init<T><<<red_grid_for(naug), kBlock, 0, op->stream>>>(S, ns, Q, naug, scal + 0,
+                                                                    p > 0 ? 1.0 : 0.0, scal + 1);
+    for (int j = 0; j < k; ++j) {
+      T* w = Q + (j + 1) * ld;
+      k_kry_matvec<T, K, BC, DIM><<<rg_pts, kBlock, 0, op->stream>>>(g, Q + j * ld, w, Q, ks, amp,
+                                                                     part, cnt, hess + 0 * kHessLd + j);
+      for (int i = 0; i <= j; ++i) {
+        const bool lastc = (i == j);
+        k_kry_mgs<T><<<rg_vec, kBlock, 0, op->stream>>>(
+            w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld, naug, hess + i * kHessLd + j, part,
+            cnt, lastc ? ssq + j : hess + (i + 1) * kHessLd + j);
+      }
+      k_kry_normalize<T><<<rg_vec, kBlock, 0, op->stream>>>(w, naug, ssq + j,
+                                                              hess + (j + 1) * kHessLd + j, scal + 1, tol);
+    }
+    int32_t rc = check_launch("arnoldi");
+    if (rc != EXPW_OK) return rc;
+    // the small Hessenberg exponential on the host (one sync per step)
+    if (hipMemcpyAsync(hh.data(), hess, hh.size() * sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+        hipMemcpyAsync(scal_h.data(), scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+        hipStreamSynchronize(op->stream) != hipSuccess)
+      return fail(EXPW_EDEVICE, "krylov: device to host copy failed: %s", hipGetErrorString(hipGetLastError()));
+    const double beta = scal_h[1];
+    int keff = k;
+    for (int j = 0; j < k; ++j)
+      if (!(hh[(j + 1) * kHessLd + j] > tol * beta)) {
+        keff = j + 1;
+        break;
+      }
+    op->last_beta = beta;
+    if (beta == 0.0) {
+      op->last_keff = 0;
+      // zero state and no source: the state stays zero
+    } else {
+      op->last_keff = keff;
+      for (int r = 0; r < keff; ++r)
+        for (int c = 0; c < keff; ++c) hk[r * keff + c] = dt * hh[r * kHessLd + c];
+      if (!expm(keff, hk.data(), E.data())) return fail(EXPW_ENONFINITE, "krylov: non-finite Hessenberg matrix");
+      KryCoef y{};
+      for (int r = 0; r < keff; ++r) y.y[r] = E[r * keff + 0];
+      k_kry_combine<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, keff, y, beta);
+      if ((rc = check_launch("krylov combine")) != EXPW_OK) return rc;
+    }
+    if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+  }
+  return EXPW_OK;
+}
+
+template <typename T, int K, int BC, int DIM>
+int32_t apply_impl(expw_op* op, const T* x, T* y) {
+  const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
+  k_apply<T, K, BC, DIM><<<grid_for(g.N), kBlock, 0, op->stream>>>(g, x, y);
+  return check_launch("apply");
+}
+
+int32_t check_op(const expw_op* op) {
+  if (!op) return fail(EXPW_EINVAL, "op is NULL");
+  return EXPW_OK;
+}
+
+int32_t check_step_args(const expw_op* op, const void* state, double dt, int64_t nsteps) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!state) return fail(EXPW_EINVAL, "state is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(EXPW_EINVAL, "dt must be positive and finite");
+  if (nsteps < 0) return fail(EXPW_EINVAL, "nsteps must be >= 0");
+  return EXPW_OK;
+}
+
+}  // namespace
+}  // namespace expw
+
+using namespace expw;
+
+extern "C" {
+
+int32_t expw_workspace_size(const expw_grid* g, int32_t max_k, int32_t max_p, size_t* bytes) {
+  if (int32_t rc = validate_grid(g)) return rc;
+  if (max_k < 0 || max_k > EXPW_MAX_KRYLOV) return fail(EXPW_EINVAL, "max_krylov_k must be in [0, %d]", EXPW_MAX_KRYLOV);
+  if (max_p < 0 || max_p > EXPW_MAX_TAYLOR) return fail(EXPW_EINVAL, "max_taylor_p must be in [0, %d]", EXPW_MAX_TAYLOR);
+  if (!bytes) return fail(EXPW_EINVAL, "bytes is NULL");
+  *bytes = layout(*g, max_k, max_p).total;
+  return EXPW_OK;
+}
+
+int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, int32_t max_p,
+                       void* ws, size_t ws_bytes, void* stream, expw_op** out) {
+  clear_error();
+  size_t need = 0;
+  if (int32_t rc = expw_workspace_size(g, max_k, max_p, &need)) return rc;
+  if (!out) return fail(EXPW_EINVAL, "out is NULL");
+  if (!c2_dev) return fail(EXPW_EINVAL, "c2_dev is NULL");
+  if (!ws) return fail(EXPW_EINVAL, "workspace_dev is NULL");
+  if (ws_bytes < need) return fail(EXPW_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return fail(EXPW_EINVAL, "workspace must be 256-byte aligned");
+  expw_op* op = new expw_op();
+  op->g = *g;
+  stagger_weights(g->order, op->alpha, &op->K);
+  op->c2 = c2_dev;
+  op->ws = static_cast<char*>(ws);
+  op->ws_bytes = ws_bytes;
+  op->stream = static_cast<hipStream_t>(stream);
+  op->kmax = max_k;
+  op->pmax = max_p;
+  const Layout L = layout(*g, max_k, max_p);
+  std::memcpy(op->off_sig, L.sig, sizeof(L.sig));
+  op->off_src_idx = L.src_idx;
+  op->off_src_amp = L.src_amp;
+  op->off_part = L.part;
+  op->off_cnt = L.cnt;
+  op->off_scal = L.scal;
+  op->off_hess = L.hess;
+  op->off_ss = L.ss;
+  op->off_big = L.big;
+  op->naug_pad = L.naug_pad;
+  op->n_src = 0;
+  op->n_rec = 0;
+  op->rec_dev = nullptr;
+  op->taylor_p = std::max(1, std::min(8, max_p));
+  op->fuse = 0;
+  op->tile_x = op->tile_y = 0;
+  op->last_keff = 0;
+  op->last_beta = 0.0;
+
+  // damping profiles (FP64 on the host, stored in the grid dtype)
+  std::vector<std::vector<char>> staging;
+  const size_t es = elem_size(*g);
+  for (int a = 0; a < g->ndim; ++a)
+    for (int hf = 0; hf < 2; ++hf) {
+      std::vector<double> prof(g->n[a]);
+      damping_profile(g->n[a], g->h, g->abc_cells, g->sigma_max, hf == 1, prof.data());
+      std::vector<char> buf(g->n[a] * es);
+      for (int64_t i = 0; i < g->n[a]; ++i) {
+        if (g->dtype == EXPW_F32) reinterpret_cast<float*>(buf.data())[i] = static_cast<float>(prof[i]);
+        else reinterpret_cast<double*>(buf.data())[i] = prof[i];
+      }
+      if (hipMemcpyAsync(op->ws + L.sig[a][hf], buf.data(), buf.size(), hipMemcpyHostToDevice,
+                         op->stream) != hipSuccess) {
+        delete op;
+        return fail(EXPW_EDEVICE, "expw_op_create: profile upload failed");
+      }
+      staging.push_back(std::move(buf));
+    }
+  unsigned* cnt = reinterpret_cast<unsigned*>(op->ws + L.cnt);
+  k_fill_u32<<<1, 64, 0, op->stream>>>(cnt, 64, 0u);
+  double* part = reinterpret_cast<double*>(op->ws + L.part);
+  double* scal = reinterpret_cast<double*>(op->ws + L.scal);
+  const int64_t N = npts(*g);
+  if (g->dtype == EXPW_F32)
+    k_c2_max<float><<<red_grid_for(N), kBlock, 0, op->stream>>>(static_cast<const float*>(c2_dev), N, part, cnt, scal + 2);
+  else
+    k_c2_max<double><<<red_grid_for(N), kBlock, 0, op->stream>>>(static_cast<const double*>(c2_dev), N, part, cnt, scal + 2);
+  double c2max = 0.0;
+  hipError_t e = hipMemcpyAsync(&c2max, scal + 2, sizeof(double), hipMemcpyDeviceToHost, op->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
+  if (e != hipSuccess || hipGetLastError() != hipSuccess) {
+    delete op;
+    return fail(EXPW_EDEVICE, "expw_op_create: device error: %s", hipGetErrorString(e));
+  }
+  if (!std::isfinite(c2max)) {
+    delete op;
+    return fail(EXPW_ENONFINITE, "c2 holds a non-finite or non-positive value");
+  }
+  op->c2max = c2max;
+  expw_spectrum_rectangle(g, c2max, &op->x_lo, &op->B);
+  expw_ellipse(op->x_lo, op->B, &op->gamma, &op->c0, &op->c1);
+  *out = op;
+  return EXPW_OK;
+}
+
+int32_t expw_op_destroy(expw_op* op) {
+  delete op;
+  return EXPW_OK;
+}
+
+int32_t expw_set_stream(expw_op* op, void* stream) {
+  if (int32_t rc = check_op(op)) return rc;
+  op->stream = static_cast<hipStream_t>(stream);
+  return EXPW_OK;
+}
+
+int32_t expw_get_spectrum(const expw_op* op, double* x_lo, double* B) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!x_lo || !B) return fail(EXPW_EINVAL, "NULL output");
+  *x_lo = op->x_lo;
+  *B = op->B;
+  return EXPW_OK;
+}
+
+int32_t expw_get_ellipse(const expw_op* op, double* gamma, double* c0, double* c1) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!gamma || !c0 || !c1) return fail(EXPW_EINVAL, "NULL output");
+  *gamma = op->gamma;
+  *c0 = op->c0;
+  *c1 = op->c1;
+  return EXPW_OK;
+}
+
+int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!(gamma > 0.0) || !std::isfinite(gamma) || !std::isfinite(c0) || !(std::fabs(c1) < 1.0))
+    return fail(EXPW_EINVAL, "ellipse needs gamma > 0 and |c1| < 1");
+  op->gamma = gamma;
+  op->c0 = c0;
+  op->c1 = c1;
+  return EXPW_OK;
+}
+
+int32_t expw_set_tuning(expw_op* op, int32_t fuse, int32_t tile_x, int32_t tile_y) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (fuse < 0 || fuse > kMaxFuse) return fail(EXPW_EINVAL, "fuse must be in [0, %d]", kMaxFuse);
+  if (tile_x < 0 || tile_y < 0) return fail(EXPW_EINVAL, "tiles must be >= 0");
+  if (int32_t rc = check_tiles(op->g.ndim, tile_x, tile_y)) return rc;
+  op->fuse = fuse;
+  op->tile_x = tile_x;
+  op->tile_y = tile_y;
+  return EXPW_OK;
+}
+
+int32_t expw_apply(expw_op* op, const void* x, void* y) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!x || !y) return fail(EXPW_EINVAL, "NULL vector");
+  if (x == y) return fail(EXPW_EINVAL, "x and y must not alias");
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return apply_impl<T, C::k, C::bc, C::dim>(op, static_cast<const T*>(x), static_cast<T*>(y));
+  });
+}
+
+int32_t expw_set_source_ricker(expw_op* op, int32_t n_src, const int64_t* idx, const double* amp,
+                               double f_peak, double t_delay, int32_t taylor_p) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (n_src < 0 || n_src > EXPW_MAX_SOURCES) return fail(EXPW_EINVAL, "n_src must be in [0, %d]", EXPW_MAX_SOURCES);
+  if (n_src == 0) {
+    op->n_src = 0;
+    return EXPW_OK;
+  }
+  if (!idx || !amp) return fail(EXPW_EINVAL, "NULL source arrays");
+  if (!(f_peak > 0.0) || !std::isfinite(f_peak) || !std::isfinite(t_delay)) return fail(EXPW_EINVAL, "f_peak must be > 0");
+  if (taylor_p < 1 || taylor_p > op->pmax) return fail(EXPW_EINVAL, "taylor_p must be in [1, %d] (max_taylor_p at create)", op->pmax);
+  const int64_t N = npts(op->g);
+  for (int s = 0; s < n_src; ++s) {
+    if (idx[s] < 0 || idx[s] >= N) return fail(EXPW_EINVAL, "source %d index %lld out of range", s, (long long)idx[s]);
+    if (!std::isfinite(amp[s])) return fail(EXPW_EINVAL, "source %d amplitude not finite", s);
+  }
+  op->src_idx.assign(idx, idx + n_src);
+  op->src_amp.assign(amp, amp + n_src);
+  std::vector<char> ampbuf(n_src * elem_size(op->g));
+  for (int s = 0; s < n_src; ++s) {
+    if (op->g.dtype == EXPW_F32) reinterpret_cast<float*>(ampbuf.data())[s] = static_cast<float>(amp[s]);
+    else reinterpret_cast<double*>(ampbuf.data())[s] = amp[s];
+  }
+  if (hipMemcpyAsync(op->ws + op->off_src_idx, op->src_idx.data(), n_src * sizeof(int64_t),
+                     hipMemcpyHostToDevice, op->stream) != hipSuccess ||
+      hipMemcpyAsync(op->ws + op->off_src_amp, ampbuf.data(), ampbuf.size(), hipMemcpyHostToDevice,
+                     op->stream) != hipSuccess ||
+      hipStreamSynchronize(op->stream) != hipSuccess)
+    return fail(EXPW_EDEVICE, "source upload failed");
+  op->n_src = n_src;
+  op->src_lo = *std::min_element(op->src_idx.begin(), op->src_idx.end());
+  op->src_hi = *std::max_element(op->src_idx.begin(), op->src_idx.end());
+  op->f_peak = f_peak;
+  op->t_delay = t_delay;
+  op->taylor_p = taylor_p;
+  return EXPW_OK;
+}
+
+int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* idx_dev) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (n_rec < 0) return fail(EXPW_EINVAL, "n_rec must be >= 0");
+  if (n_rec == 0) {
+    op->n_rec = 0;
+    op->rec_dev = nullptr;
+    return EXPW_OK;
+  }
+  if (!idx_dev) return fail(EXPW_EINVAL, "NULL receiver array");
+  std::vector<int64_t> h(n_rec);
+  if (hipMemcpyAsync(h.data(), idx_dev, n_rec * sizeof(int64_t), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+      hipStreamSynchronize(op->stream) != hipSuccess)
+    return fail(EXPW_EDEVICE, "receiver index read failed");
+  const int64_t N = npts(op->g);
+  for (int r = 0; r < n_rec; ++r)
+    if (h[r] < 0 || h[r] >= N) return fail(EXPW_EINVAL, "receiver %d index %lld out of range", r, (long long)h[r]);
+  op->n_rec = n_rec;
+  op->rec_dev = idx_dev;
+  return EXPW_OK;
+}
+
+int32_t expw_step_faber(expw_op* op, void* state, double t0, double dt, int32_t m, int64_t nsteps,
+                        void* traces) {
+  if (int32_t rc = check_step_args(op, state, dt, nsteps)) return rc;
+  if (m < 1 || m > 1024) return fail(EXPW_EINVAL, "Faber degree m must be in [1, 1024]");
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces));
+  });
+}
+
+int32_t expw_step_krylov(expw_op* op, void* state, double t0, double dt, int32_t k, int64_t nsteps,
+                         void* traces) {
+  if (int32_t rc = check_step_args(op, state, dt, nsteps)) return rc;
+  if (k < 1 || k > op->kmax) return fail(EXPW_EINVAL, "Krylov dimension k must be in [1, %d] (max_krylov_k at create)", op->kmax);
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return krylov_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, k, nsteps, static_cast<T*>(traces));
+  });
+}
+
+int32_t expw_step_rk4(expw_op* op, void* state, double t0, double dt, int64_t nsteps, void* traces) {
+  if (int32_t rc = check_step_args(op, state, dt, nsteps)) return rc;
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return rk4_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, nsteps, static_cast<T*>(traces));
+  });
+}
+
+int32_t expw_step_leapfrog(expw_op* op, void* state, double t0, double dt, int64_t nsteps, void* traces) {
+  if (int32_t rc = check_step_args(op, state, dt, nsteps)) return rc;
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return leapfrog_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, nsteps, static_cast<T*>(traces));
+  });
+}
+
+int32_t expw_sync_status(expw_op* op) {
+  if (int32_t rc = check_op(op)) return rc;
+  const hipError_t e = hipStreamSynchronize(op->stream);
+  if (e != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGetLastError();
+  if (e2 != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e2));
+  return EXPW_OK;
+}
+
+int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!k_eff || !beta) return fail(EXPW_EINVAL, "NULL output");
+  *k_eff = op->last_keff;
+  *beta = op->last_beta;
+  return EXPW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,391 @@
+"""Python binding of libexpwave.so (the C ABI in include/expwave.h).
+
+Argument marshalling only: every step of the method runs in the native
+library on the GPU. The functions below carry the C names and raise
+`ExpwError` on a non-OK status. `Operator` is a thin convenience wrapper that
+takes PyTorch tensors for device memory and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libexpwave.so")
+
+EXPW_OK, EXPW_EINVAL, EXPW_ENOMEM, EXPW_EDEVICE, EXPW_ENONFINITE, EXPW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+EXPW_F32, EXPW_F64 = 0, 1
+EXPW_BC_ZERO, EXPW_BC_PERIODIC = 0, 1
+EXPW_MAX_KRYLOV, EXPW_MAX_TAYLOR, EXPW_MAX_SOURCES = 64, 16, 64
+
+
+class ExpwError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"expwave status {status}: {message}")
+        self.status = status
+
+
+class ExpwGrid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+                ("dtype", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("abc_cells", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sigma_max", ctypes.c_double)]
+
+
+_i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pgrid = ctypes.POINTER(ExpwGrid)
+
+# name -> (restype, argtypes); the list is the full C ABI of include/expwave.h
+SIGNATURES = {
+    "expw_version": (_i32, []),
+    "expw_last_error": (ctypes.c_char_p, []),
+    "expw_workspace_size": (_i32, [_pgrid, _i32, _i32, ctypes.POINTER(_sz)]),
+    "expw_damping_profile": (_i32, [_i64, _dbl, _i32, _dbl, _i32, _pd]),
+    "expw_spectrum_rectangle": (_i32, [_pgrid, _dbl, _pd, _pd]),
+    "expw_ellipse": (_i32, [_dbl, _dbl, _pd, _pd, _pd]),
+    "expw_faber_coefficients": (_i32, [_dbl, _dbl, _dbl, _dbl, _i32, _pd]),
+    "expw_ricker_derivatives": (_i32, [_dbl, _dbl, _dbl, _i32, _pd]),
+    "expw_faber_source_scalars": (_i32, [_dbl, _dbl, _dbl, _i32, _i32, _pd, _pd]),
+    "expw_expm": (_i32, [_i32, _pd, _pd]),
+    "expw_op_create": (_i32, [_pgrid, _vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "expw_op_destroy": (_i32, [_vp]),
+    "expw_set_stream": (_i32, [_vp, _vp]),
+    "expw_get_spectrum": (_i32, [_vp, _pd, _pd]),
+    "expw_get_ellipse": (_i32, [_vp, _pd, _pd, _pd]),
+    "expw_set_ellipse": (_i32, [_vp, _dbl, _dbl, _dbl]),
+    "expw_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
+    "expw_apply": (_i32, [_vp, _vp, _vp]),
+    "expw_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
+    "expw_set_receivers": (_i32, [_vp, _i32, _vp]),
+    "expw_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
+    "expw_step_krylov": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
+    "expw_step_rk4": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
+    "expw_step_leapfrog": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
+    "expw_sync_status": (_i32, [_vp]),
+    "expw_krylov_info": (_i32, [_vp, _pi32, _pd]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libexpwave.so (built in-tree); fails loudly when it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2401_16322_amd.build_native`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status):
+    if status != EXPW_OK:
+        msg = load().expw_last_error()
+        raise ExpwError(status, msg.decode() if msg else "")
+    return status
+
+
+def _dptr(arr):
+    return arr.ctypes.data_as(_pd)
+
+
+def make_grid(n, h, order=4, dtype=EXPW_F32, bc=EXPW_BC_ZERO, abc_cells=0, sigma_max=0.0):
+    g = ExpwGrid()
+    g.ndim = len(n)
+    g.order = order
+    nn = list(n) + [1] * (3 - len(n))
+    for a in range(3):
+        g.n[a] = int(nn[a])
+    g.h = float(h)
+    g.dtype = int(dtype)
+    g.bc = int(bc)
+    g.abc_cells = int(abc_cells)
+    g.reserved = 0
+    g.sigma_max = float(sigma_max)
+    return g
+
+
+# ---------------------------------------------------------------- host-only entry points
+
+def expw_version():
+    return load().expw_version()
+
+
+def expw_last_error():
+    return load().expw_last_error().decode()
+
+
+def expw_workspace_size(grid, max_krylov_k, max_taylor_p):
+    out = _sz(0)
+    _check(load().expw_workspace_size(ctypes.byref(grid), max_krylov_k, max_taylor_p, ctypes.byref(out)))
+    return out.value
+
+
+def expw_damping_profile(n, h, cells, sigma_max, half):
+    out = np.zeros(n)
+    _check(load().expw_damping_profile(n, h, cells, sigma_max, int(half), _dptr(out)))
+    return out
+
+
+def expw_spectrum_rectangle(grid, c2_max):
+    x_lo, B = _dbl(), _dbl()
+    _check(load().expw_spectrum_rectangle(ctypes.byref(grid), c2_max, ctypes.byref(x_lo), ctypes.byref(B)))
+    return x_lo.value, B.value
+
+
+def expw_ellipse(x_lo, B):
+    g, c0, c1 = _dbl(), _dbl(), _dbl()
+    _check(load().expw_ellipse(x_lo, B, ctypes.byref(g), ctypes.byref(c0), ctypes.byref(c1)))
+    return g.value, c0.value, c1.value
+
+
+def expw_faber_coefficients(gamma, c0, c1, dt, m):
+    out = np.zeros(m + 1)
+    _check(load().expw_faber_coefficients(gamma, c0, c1, dt, m, _dptr(out)))
+    return out
+
+
+def expw_ricker_derivatives(t, f_peak, t_delay, p):
+    out = np.zeros(p)
+    _check(load().expw_ricker_derivatives(t, f_peak, t_delay, p, _dptr(out)))
+    return out
+
+
+def expw_faber_source_scalars(gamma, c0, c1, m, G):
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    out = np.zeros(m)
+    _check(load().expw_faber_source_scalars(gamma, c0, c1, m, G.size, _dptr(G), _dptr(out)))
+    return out
+
+
+def expw_expm(A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    E = np.zeros_like(A)
+    _check(load().expw_expm(A.shape[0], _dptr(A), _dptr(E)))
+    return E
+
+
+# ---------------------------------------------------------------- device entry points (raw)
+
+def expw_op_create(grid, c2_ptr, max_krylov_k, max_taylor_p, ws_ptr, ws_bytes, stream):
+    h = _vp()
+    _check(load().expw_op_create(ctypes.byref(grid), c2_ptr, max_krylov_k, max_taylor_p, ws_ptr,
+                                 ws_bytes, stream, ctypes.byref(h)))
+    return h.value
+
+
+def expw_op_destroy(op):
+    _check(load().expw_op_destroy(op))
+
+
+def expw_set_stream(op, stream):
+    _check(load().expw_set_stream(op, stream))
+
+
+def expw_get_spectrum(op):
+    x_lo, B = _dbl(), _dbl()
+    _check(load().expw_get_spectrum(op, ctypes.byref(x_lo), ctypes.byref(B)))
+    return x_lo.value, B.value
+
+
+def expw_get_ellipse(op):
+    g, c0, c1 = _dbl(), _dbl(), _dbl()
+    _check(load().expw_get_ellipse(op, ctypes.byref(g), ctypes.byref(c0), ctypes.byref(c1)))
+    return g.value, c0.value, c1.value
+
+
+def expw_set_ellipse(op, gamma, c0, c1):
+    _check(load().expw_set_ellipse(op, gamma, c0, c1))
+
+
+def expw_set_tuning(op, fuse, tile_x=0, tile_y=0):
+    _check(load().expw_set_tuning(op, fuse, tile_x, tile_y))
+
+
+def expw_apply(op, x_ptr, y_ptr):
+    _check(load().expw_apply(op, x_ptr, y_ptr))
+
+
+def expw_set_source_ricker(op, nodes, amps, f_peak, t_delay, taylor_p):
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    amps = np.ascontiguousarray(amps, dtype=np.float64)
+    if nodes.size != amps.size:
+        raise ValueError("nodes and amps differ in length")
+    _check(load().expw_set_source_ricker(op, nodes.size, nodes.ctypes.data_as(_pi64), _dptr(amps),
+                                         f_peak, t_delay, taylor_p))
+
+
+def expw_set_receivers(op, n_rec, idx_ptr):
+    _check(load().expw_set_receivers(op, n_rec, idx_ptr))
+
+
+def expw_step_faber(op, state_ptr, t0, dt, m, nsteps, traces_ptr=None):
+    _check(load().expw_step_faber(op, state_ptr, t0, dt, m, nsteps, traces_ptr))
+
+
+def expw_step_krylov(op, state_ptr, t0, dt, k, nsteps, traces_ptr=None):
+    _check(load().expw_step_krylov(op, state_ptr, t0, dt, k, nsteps, traces_ptr))
+
+
+def expw_step_rk4(op, state_ptr, t0, dt, nsteps, traces_ptr=None):
+    _check(load().expw_step_rk4(op, state_ptr, t0, dt, nsteps, traces_ptr))
+
+
+def expw_step_leapfrog(op, state_ptr, t0, dt, nsteps, traces_ptr=None):
+    _check(load().expw_step_leapfrog(op, state_ptr, t0, dt, nsteps, traces_ptr))
+
+
+def expw_sync_status(op):
+    _check(load().expw_sync_status(op))
+
+
+def expw_krylov_info(op):
+    k, b = _i32(), _dbl()
+    _check(load().expw_krylov_info(op, ctypes.byref(k), ctypes.byref(b)))
+    return k.value, b.value
+
+
+# ---------------------------------------------------------------- torch convenience wrapper
+
+class Operator:
+    """The operator H on one grid, with device buffers held as torch tensors.
+
+    c2: torch tensor on the GPU (float32 or float64) of numpy shape
+    (nz, nx) or (nz, ny, nx). States are flat tensors of (ndim+1) * points
+    values in the canonical layout [p | v_0 | ... | v_{d-1}].
+    """
+
+    def __init__(self, n, h, c2, order=4, bc="zero", abc_cells=0, sigma_max=0.0,
+                 max_krylov_k=0, max_taylor_p=8):
+        import torch
+        self._torch = torch
+        if not c2.is_cuda:
+            raise ValueError("c2 must be a GPU tensor")
+        if c2.dtype not in (torch.float32, torch.float64):
+            raise ValueError("c2 must be float32 or float64")
+        self.dtype = c2.dtype
+        self.device = c2.device
+        self.n = tuple(int(v) for v in n)
+        self.ndim = len(self.n)
+        self.npts = int(np.prod(self.n))
+        self.nstate = (self.ndim + 1) * self.npts
+        self.grid = make_grid(self.n, h, order,
+                              EXPW_F32 if c2.dtype == torch.float32 else EXPW_F64,
+                              EXPW_BC_PERIODIC if bc == "periodic" else EXPW_BC_ZERO,
+                              abc_cells, sigma_max)
+        self.c2 = c2.contiguous()
+        if self.c2.numel() != self.npts:
+            raise ValueError("c2 has the wrong number of points")
+        nbytes = expw_workspace_size(self.grid, max_krylov_k, max_taylor_p)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._rec = None
+        self.op = expw_op_create(self.grid, self.c2.data_ptr(), max_krylov_k, max_taylor_p,
+                                 self.workspace.data_ptr(), nbytes, self._stream())
+
+    def _stream(self):
+        return self._torch.cuda.current_stream(self.device).cuda_stream
+
+    def _sync_stream(self):
+        expw_set_stream(self.op, self._stream())
+
+    def _check_state(self, state):
+        if state.dtype != self.dtype or not state.is_cuda or state.numel() != self.nstate \
+                or not state.is_contiguous():
+            raise ValueError("state must be a contiguous GPU tensor of the grid dtype and size")
+
+    def _traces_ptr(self, traces, nsteps):
+        if traces is None:
+            return None
+        if self._rec is None:
+            raise ValueError("no receivers set")
+        if traces.dtype != self.dtype or traces.numel() < nsteps * self._rec.numel() \
+                or not traces.is_contiguous():
+            raise ValueError("traces must hold nsteps * n_rec values of the grid dtype")
+        return traces.data_ptr()
+
+    @property
+    def ellipse(self):
+        return expw_get_ellipse(self.op)
+
+    @ellipse.setter
+    def ellipse(self, val):
+        expw_set_ellipse(self.op, *val)
+
+    @property
+    def spectrum(self):
+        return expw_get_spectrum(self.op)
+
+    def set_tuning(self, fuse=0, tile_x=0, tile_y=0):
+        expw_set_tuning(self.op, fuse, tile_x, tile_y)
+
+    def apply(self, x, out=None):
+        self._check_state(x)
+        y = self._torch.empty_like(x) if out is None else out
+        self._sync_stream()
+        expw_apply(self.op, x.data_ptr(), y.data_ptr())
+        return y
+
+    def set_source_ricker(self, nodes, amps, f_peak, t_delay, taylor_p=8):
+        self._sync_stream()
+        expw_set_source_ricker(self.op, nodes, amps, f_peak, t_delay, taylor_p)
+
+    def set_receivers(self, nodes):
+        torch = self._torch
+        if nodes is None or len(nodes) == 0:
+            self._rec = None
+            self._sync_stream()
+            expw_set_receivers(self.op, 0, None)
+            return
+        rec = torch.as_tensor(np.asarray(nodes, dtype=np.int64), device=self.device)
+        self._rec = rec
+        self._sync_stream()
+        expw_set_receivers(self.op, rec.numel(), rec.data_ptr())
+
+    def step_faber(self, state, t0, dt, m, nsteps=1, traces=None):
+        self._check_state(state)
+        self._sync_stream()
+        expw_step_faber(self.op, state.data_ptr(), t0, dt, m, nsteps, self._traces_ptr(traces, nsteps))
+
+    def step_krylov(self, state, t0, dt, k, nsteps=1, traces=None):
+        self._check_state(state)
+        self._sync_stream()
+        expw_step_krylov(self.op, state.data_ptr(), t0, dt, k, nsteps, self._traces_ptr(traces, nsteps))
+
+    def step_rk4(self, state, t0, dt, nsteps=1, traces=None):
+        self._check_state(state)
+        self._sync_stream()
+        expw_step_rk4(self.op, state.data_ptr(), t0, dt, nsteps, self._traces_ptr(traces, nsteps))
+
+    def step_leapfrog(self, state, t0, dt, nsteps=1, traces=None):
+        self._check_state(state)
+        self._sync_stream()
+        expw_step_leapfrog(self.op, state.data_ptr(), t0, dt, nsteps, self._traces_ptr(traces, nsteps))
+
+    def sync(self):
+        expw_sync_status(self.op)
+
+    def krylov_info(self):
+        return expw_krylov_info(self.op)
+
+    def close(self):
+        if getattr(self, "op", None):
+            expw_op_destroy(self.op)
+            self.op = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,245 @@
+"""GPU parity of the HIP library against the FP64 oracle (element by element).
+
+Tolerances: FP64 1e-11 and FP32 1e-5 relative L2 per state for the steppers;
+the operator itself is compared in the max norm relative to max |H x|.
+"""
+import numpy as np
+import pytest
+
+from oracle.operator import apply_H, split_state
+from oracle.steppers import run
+from gpu_cases import TOL, make_case, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["float64", "float32"]
+APPLY_TOL = {"float64": 1e-13, "float32": 2e-6}
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,order,bc", [
+    ((37, 29), 4, "zero"), ((130, 67), 4, "zero"), ((64, 48), 8, "zero"),
+    ((24, 20), 4, "periodic"), ((24, 20), 8, "periodic"),
+    ((21, 17, 13), 4, "zero"), ((16, 12, 10), 8, "periodic"), ((1, 9), 4, "zero"), ((7, 1), 4, "zero"),
+])
+def test_apply_matches_oracle(dtype, n, order, bc):
+    case = make_case(n, dtype, order, bc, abc=3, src=False, seed=1)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(case.prob.grid.nstate)
+    y = case.op.apply(to_dev(case, x)).cpu().numpy()
+    ref = apply_H(case.prob.grid, case.prob.c2, x)
+    assert np.max(np.abs(y - ref)) <= APPLY_TOL[dtype] * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,fuse", [(1, 1), (2, 1), (3, 1), (7, 1), (16, 1), (2, 2), (5, 2), (16, 4),
+                                    (7, 3), (16, 8), (12, 6), (10, 4)])
+def test_faber_steps_match_oracle(dtype, m, fuse):
+    if dtype == "float64" and fuse > 4:
+        fuse = 4
+    case = make_case((150, 70), dtype, seed=2)     # several 64x16 tiles and ragged edges
+    case.op.set_tuning(fuse)
+    dt, nst = 1.5e-3, 3
+    U = to_dev(case, case.U0)
+    case.op.step_faber(U, 0.02, dt, m, nst)
+    ref, _, _ = run(case.prob, "faber", case.U0, 0.02, dt, nst, m=m, p=case.p)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fuse", [2, 4, 8])
+def test_fused_and_unfused_faber_agree_to_rounding(dtype, fuse):
+    """Tiling/fusion invariance: results depend on the fusion depth only through rounding."""
+    case = make_case((200, 90), dtype, seed=3, n_src=3)
+    outs = []
+    for f in (1, fuse):
+        case.op.set_tuning(f)
+        U = to_dev(case, case.U0)
+        case.op.step_faber(U, 0.03, 2e-3, 16, 2)
+        outs.append(U.cpu().numpy())
+    assert rel_l2(outs[1], outs[0]) <= (1e-14 if dtype == "float64" else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [(5, 3), (1, 40), (70, 1), (13, 11, 9)])
+def test_faber_tiny_and_degenerate_grids(dtype, n):
+    case = make_case(n, dtype, abc=1, seed=4)
+    U = to_dev(case, case.U0)
+    case.op.step_faber(U, 0.04, 1e-3, 8, 2)
+    ref, _, _ = run(case.prob, "faber", case.U0, 0.04, 1e-3, 2, m=8, p=case.p)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("k,src", [(1, True), (5, True), (20, True), (12, False)])
+def test_krylov_steps_match_oracle(dtype, k, src):
+    case = make_case((45, 33), dtype, src=src, seed=5, max_k=24)
+    dt, nst = 1e-3, 2
+    U = to_dev(case, case.U0)
+    case.op.step_krylov(U, 0.03, dt, k, nst)
+    ref, _, _ = run(case.prob, "krylov", case.U0, 0.03, dt, nst, k=k, p=case.p)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+
+
+def test_krylov_happy_breakdown_on_tiny_grid():
+    case = make_case((3, 3), "float64", abc=1, src=False, seed=6, max_k=30)
+    U = to_dev(case, case.U0)
+    case.op.step_krylov(U, 0.0, 5e-3, 27, 1)
+    ref, _, _ = run(case.prob, "krylov", case.U0, 0.0, 5e-3, 1, k=27)
+    keff, beta = case.op.krylov_info()
+    assert keff <= 27 and beta > 0
+    assert rel_l2(U.cpu().numpy(), ref) <= 1e-11
+
+
+def test_krylov_zero_state_without_source_stays_zero():
+    case = make_case((20, 10), "float64", src=False, seed=7, max_k=8, smooth=False)
+    U = to_dev(case, case.U0)
+    case.op.step_krylov(U, 0.0, 1e-3, 6, 2)
+    assert float(U.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [(60, 41), (17, 13, 11)])
+def test_rk4_matches_oracle(dtype, n):
+    case = make_case(n, dtype, seed=8)
+    dt, nst = 5e-4, 6
+    U = to_dev(case, case.U0)
+    case.op.step_rk4(U, 0.03, dt, nst)
+    ref, _, _ = run(case.prob, "rk4", case.U0, 0.03, dt, nst)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [(60, 41), (17, 13, 11)])
+def test_leapfrog_matches_oracle(dtype, n):
+    case = make_case(n, dtype, seed=9)
+    dt, nst = 5e-4, 10
+    U = to_dev(case, case.U0)
+    case.op.step_leapfrog(U, 0.03, dt, nst)
+    ref, _, _ = run(case.prob, "leapfrog", case.U0, 0.03, dt, nst)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("method", ["faber", "krylov", "rk4", "leapfrog"])
+def test_receiver_traces_match_oracle(method):
+    import torch
+    case = make_case((80, 50), "float64", seed=10, max_k=10, n_src=2)
+    g = case.prob.grid
+    rec = np.array([0, g.npts - 1, 5 * 80 + 7, 25 * 80 + 40, 49 * 80 + 79], dtype=np.int64)
+    case.op.set_receivers(rec)
+    nst = 5
+    kw = {"faber": dict(m=12, p=case.p), "krylov": dict(k=10, p=case.p)}.get(method, {})
+    dt = 1e-3 if method in ("faber", "krylov") else 3e-4
+    U = to_dev(case, case.U0)
+    tr = torch.zeros(nst * rec.size, dtype=torch.float64, device="cuda")
+    getattr(case.op, "step_" + method)(U, 0.02, dt, *([kw["m"]] if method == "faber" else
+                                                     [kw["k"]] if method == "krylov" else []),
+                                       nsteps=nst, traces=tr)
+    _, traces, _ = run(case.prob, method, case.U0, 0.02, dt, nst, receivers=rec, **kw)
+    assert rel_l2(tr.cpu().numpy().reshape(nst, rec.size), traces) <= 1e-11
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_homogeneous_101_full_run(dtype):
+    """The 101x101 homogeneous case in full: Faber degree 16, dt = 4 ms, 100 steps
+    (T = 0.4 s), 15 Hz Ricker at the centre with 0.18 s delay, zero initial state;
+    every 10th snapshot compared (pressure, physical interior)."""
+    import torch
+    from oracle.operator import Grid, rel_l2_pressure
+    from oracle.source import PointSources
+    from oracle.steppers import Problem
+    from paper_2401_16322_amd.expwave import Operator
+    from synthetic import get_workload
+    w = get_workload("homog2d_101")
+    g = Grid(w.n, w.h, 4, abc_cells=w.abc_cells, sigma_max=w.sigma_max)
+    c2 = w.velocity() ** 2
+    prob = Problem(g, c2, PointSources((w.source_node(),), (1.0,), w.f_peak, w.t_delay))
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    op = Operator(w.n, w.h, torch.tensor(c2, dtype=tdt, device="cuda"), abc_cells=w.abc_cells,
+                  sigma_max=w.sigma_max, max_taylor_p=w.taylor_p)
+    op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+    U = torch.zeros(g.nstate, dtype=tdt, device="cuda")
+    nsteps = int(round(w.T / w.dt))
+    _, _, snaps = run(prob, "faber", np.zeros(g.nstate), 0.0, w.dt, nsteps, snapshot_every=10,
+                      m=w.faber_m, p=w.taylor_p)
+    pmax = max(np.linalg.norm(split_state(g, s)[0]) for s in snaps.values())
+    for s in range(10, nsteps + 1, 10):
+        op.step_faber(U, (s - 10) * w.dt, w.dt, w.faber_m, 10)
+        ref = snaps[s]
+        err = rel_l2_pressure(g, U.cpu().numpy(), ref)
+        if np.linalg.norm(split_state(g, ref)[0]) >= 1e-3 * pmax:
+            assert err <= TOL[dtype], (s, err)
+
+
+def test_layered_1001x501_steps_at_full_size():
+    """The 1001x501 layered medium at full size in the bench's launch
+    configuration (FP32, Faber degree 16, fused passes of 4 terms), three
+    steps of 2 ms from a seeded smooth state, with the surface receiver line."""
+    import torch
+    from oracle.operator import Grid
+    from oracle.source import PointSources
+    from oracle.steppers import Problem
+    from paper_2401_16322_amd.expwave import Operator
+    from synthetic import get_workload, smooth_state
+    w = get_workload("layered2d_1001x501")
+    g = Grid(w.n, w.h, 4, abc_cells=w.abc_cells, sigma_max=w.sigma_max)
+    c2 = w.velocity() ** 2
+    prob = Problem(g, c2, PointSources((w.source_node(),), (1.0,), w.f_peak, w.t_delay))
+    U0 = smooth_state(w.n, seed=2001, width_cells=12.0)
+    rec = w.receiver_nodes()
+    _, traces, _ = run(prob, "faber", U0, 0.15, w.dt, 3, receivers=rec, m=w.faber_m, p=w.taylor_p)
+    for dtype, tdt in (("float32", torch.float32), ("float64", torch.float64)):
+        op = Operator(w.n, w.h, torch.tensor(c2, dtype=tdt, device="cuda"), abc_cells=w.abc_cells,
+                      sigma_max=w.sigma_max, max_taylor_p=w.taylor_p)
+        op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+        op.set_receivers(rec)
+        U = torch.tensor(U0, dtype=tdt, device="cuda")
+        tr = torch.zeros(3 * rec.size, dtype=tdt, device="cuda")
+        op.step_faber(U, 0.15, w.dt, w.faber_m, 3, traces=tr)
+        ref, _, _ = run(prob, "faber", U0, 0.15, w.dt, 3, m=w.faber_m, p=w.taylor_p)
+        assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+        assert rel_l2(tr.cpu().numpy().reshape(3, -1), traces) <= TOL[dtype]
+
+
+def test_source_at_grid_corners_and_many_sources():
+    case = make_case((66, 40), "float64", seed=11, n_src=0, src=False)
+    import numpy as _np
+    from oracle.source import PointSources
+    g = case.prob.grid
+    nodes = _np.array([0, g.npts - 1, 65, 39 * 66, 1000, 1001, 1066], dtype=_np.int64)
+    amps = _np.linspace(0.5, 2.0, nodes.size)
+    case.op.set_source_ricker(nodes, amps, 15.0, 0.05, 8)
+    case.prob.src = PointSources(tuple(nodes), tuple(amps), 15.0, 0.05)
+    for fuse in (1, 4):
+        case.op.set_tuning(fuse)
+        U = to_dev(case, case.U0)
+        case.op.step_faber(U, 0.04, 1e-3, 9, 2)
+        ref, _, _ = run(case.prob, "faber", case.U0, 0.04, 1e-3, 2, m=9, p=8)
+        assert rel_l2(U.cpu().numpy(), ref) <= 1e-11
+
+
+def test_zero_steps_leave_state_unchanged():
+    case = make_case((30, 20), "float64", seed=12)
+    U = to_dev(case, case.U0)
+    case.op.step_faber(U, 0.0, 1e-3, 8, 0)
+    case.op.sync()
+    assert np.array_equal(U.cpu().numpy(), case.U0)
+
+
+def test_invalid_arguments_raise():
+    import torch
+    from paper_2401_16322_amd.expwave import ExpwError, Operator
+    case = make_case((30, 20), "float64", seed=13, max_k=4)
+    U = to_dev(case, case.U0)
+    with pytest.raises(ExpwError):
+        case.op.step_krylov(U, 0.0, 1e-3, 5, 1)        # k above max_krylov_k
+    with pytest.raises(ExpwError):
+        case.op.step_faber(U, 0.0, -1e-3, 8, 1)        # dt <= 0
+    with pytest.raises(ExpwError):
+        case.op.set_source_ricker([600], [1.0], 15.0, 0.1, 8)   # index out of range
+    with pytest.raises(ExpwError):
+        case.op.set_receivers([-1])
+    bad = torch.full((30, 20), float("nan"), dtype=torch.float64, device="cuda")
+    with pytest.raises(ExpwError) as e:
+        Operator((20, 30), 10.0, bad)
+    assert e.value.status == -4

@@ -1,0 +1,155 @@
+"""CPU tests of the native library: exports, host math and argument validation.
+
+No GPU is touched: only the host-only entry points are called, plus device
+entry points with arguments that validation rejects before any launch.
+"""
+import ctypes
+import os
+import re
+from math import factorial
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from oracle.operator import Grid, damping_profile
+from oracle.source import ricker_derivatives
+from oracle.spectrum import ellipse_from_rectangle, faber_coefficients, spectrum_rectangle
+
+from paper_2401_16322_amd import expwave as xw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    if not os.path.exists(xw.LIB_PATH):
+        from paper_2401_16322_amd.build_native import build
+        build()
+    return xw.load()
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "expwave.h")).read()
+    declared = set(re.findall(r"\b(expw_[a-z0-9_]+)\s*\(", header))
+    assert len(declared) >= 20
+    lib = ctypes.CDLL(xw.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    # the binding covers the same set
+    assert declared == set(xw.SIGNATURES)
+    assert xw.expw_version() == 1
+
+
+@pytest.mark.parametrize("n,cells,half", [(30, 5, False), (30, 5, True), (101, 20, True), (7, 0, False)])
+def test_damping_profile_matches_oracle(n, cells, half):
+    ours = xw.expw_damping_profile(n, 10.0, cells, 300.0, half)
+    ref = damping_profile(n, 10.0, cells, 300.0, half)
+    assert np.allclose(ours, ref, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n,order", [((101, 101), 4), ((40, 30), 8), ((12, 10, 9), 4)])
+def test_spectrum_and_ellipse_match_oracle(n, order):
+    g = Grid(n, 10.0, order, abc_cells=3, sigma_max=300.0)
+    c2 = np.full(g.shape, 2500.0 ** 2)
+    grid = xw.make_grid(n, 10.0, order, abc_cells=3, sigma_max=300.0)
+    x_lo, B = xw.expw_spectrum_rectangle(grid, 2500.0 ** 2)
+    rx, rB = spectrum_rectangle(g, c2)
+    assert np.isclose(x_lo, rx, rtol=1e-14) and np.isclose(B, rB, rtol=1e-14)
+    assert np.allclose(xw.expw_ellipse(x_lo, B), ellipse_from_rectangle(rx, rB), rtol=1e-14)
+
+
+def test_ellipse_of_undamped_segment():
+    gamma, c0, c1 = xw.expw_ellipse(0.0, 500.0)
+    assert gamma == 250.0 and c0 == 0.0 and c1 == -1.0
+
+
+@pytest.mark.parametrize("ell", [(678.8, -0.442, -0.375), (1262.1, -0.2377, -0.6639),
+                                 (50.0, 0.3, 0.4), (30.0, -0.2, 0.0)])
+@pytest.mark.parametrize("dt", [1e-3, 4e-3, 1.2e-2])
+def test_faber_coefficients_match_oracle_bessel(ell, dt):
+    m = 40
+    ours = xw.expw_faber_coefficients(*ell, dt, m)
+    ref = faber_coefficients(*ell, dt, m)
+    # trapezoidal Laurent coefficients carry rounding relative to max |exp(dt psi)| on |w| = 1
+    gamma, c0, c1 = ell
+    fmax = np.exp(dt * gamma * (c0 + 1.0 + abs(c1)))
+    assert np.max(np.abs(ours - ref)) <= 4e-15 * max(1.0, fmax)
+
+
+@pytest.mark.parametrize("t", [0.0, 0.12, 0.18, 0.2, 0.35])
+def test_ricker_derivatives_match_oracle(t):
+    ours = xw.expw_ricker_derivatives(t, 15.0, 0.18, 12)
+    ref = ricker_derivatives(t, 15.0, 0.18, 12)
+    assert np.allclose(ours, ref, rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("ell", [(678.8, -0.442, -0.375), (50.0, 0.3, 0.4)])
+def test_faber_source_scalars_reproduce_exp_of_shift(ell):
+    """With G = e_c the scalars give tau_{j-1}[c] / gamma; the Faber sum of the
+    tail then equals exp(dt J) e_p, whose entries are dt^(p-c)/(p-c)!."""
+    gamma, c0, c1 = ell
+    p, m, dt = 6, 40, 2.0 / gamma
+    a = xw.expw_faber_coefficients(gamma, c0, c1, dt, m + 1)
+    tail = np.zeros(p)
+    for c in range(p):
+        G = np.zeros(p)
+        G[c] = 1.0
+        q = xw.expw_faber_source_scalars(gamma, c0, c1, m + 1, G)   # q[j] = tau_j[c] / gamma
+        tail[c] = np.dot(a[: m + 1], gamma * q)
+    closed = np.array([dt ** (p - 1 - c) / factorial(p - 1 - c) for c in range(p)])
+    assert np.allclose(tail, closed, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 20, 41, 65])
+@pytest.mark.parametrize("scale", [1e-3, 1.0, 30.0])
+def test_expm_matches_scipy(k, scale):
+    rng = np.random.default_rng(k)
+    A = np.triu(rng.standard_normal((k, k)), -1) * scale   # Hessenberg
+    E = xw.expw_expm(A)
+    R = expm(A)
+    assert np.linalg.norm(E - R) <= 1e-12 * np.linalg.norm(R) * max(1.0, scale)
+
+
+def test_expm_of_skew_matrix_is_rotation():
+    th = 2.5
+    E = xw.expw_expm(np.array([[0.0, -th], [th, 0.0]]))
+    assert np.allclose(E, [[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]], atol=1e-15)
+
+
+def test_validation_errors_without_gpu():
+    good = xw.make_grid((10, 10), 10.0)
+    assert xw.expw_workspace_size(good, 8, 8) > 0
+    bad = xw.make_grid((10, 10), 10.0, order=6)
+    with pytest.raises(xw.ExpwError) as e:
+        xw.expw_workspace_size(bad, 8, 8)
+    assert e.value.status == xw.EXPW_EINVAL and "order" in str(e.value)
+    with pytest.raises(xw.ExpwError):
+        xw.expw_workspace_size(good, xw.EXPW_MAX_KRYLOV + 1, 8)
+    g3 = xw.make_grid((10, 10), 10.0)
+    g3.n[2] = 5
+    with pytest.raises(xw.ExpwError):
+        xw.expw_workspace_size(g3, 0, 0)
+    # create rejects a NULL c2 / workspace and a too-small workspace before any launch
+    with pytest.raises(xw.ExpwError) as e:
+        xw.expw_op_create(good, None, 0, 8, None, 0, None)
+    assert e.value.status == xw.EXPW_EINVAL
+    with pytest.raises(xw.ExpwError) as e:
+        xw.expw_op_create(good, 256, 0, 8, 256, 16, None)
+    assert e.value.status == xw.EXPW_ENOMEM
+    # NULL handle
+    with pytest.raises(xw.ExpwError):
+        xw.expw_step_faber(None, 256, 0.0, 1e-3, 4, 1)
+    with pytest.raises(xw.ExpwError):
+        xw.expw_faber_coefficients(1.0, 0.0, 1.5, 1e-3, 4)
+    with pytest.raises(xw.ExpwError):
+        xw.expw_expm(np.zeros((70, 70)))
+
+
+def test_workspace_grows_with_krylov_dimension():
+    g = xw.make_grid((101, 101), 10.0, dtype=xw.EXPW_F64)
+    w0 = xw.expw_workspace_size(g, 0, 8)
+    w40 = xw.expw_workspace_size(g, 40, 8)
+    ns = 3 * 101 * 101
+    assert w0 >= 5 * ns * 8
+    assert w40 >= 41 * ns * 8
