@@ -196,6 +196,31 @@ int32_t expw_sync_status(expw_op* op);
 /* Effective dimension and beta of the last Krylov step (host values). */
 int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta);
 
+/* ------------------------------------------------------------------ timing */
+
+/* Kernel classes for expw_get_timing. */
+enum {
+  EXPW_KERNEL_FABER = 0,        /* Faber pass: fused multi-term sweep, or one term */
+  EXPW_KERNEL_KRYLOV_MATVEC = 1, /* Arnoldi: w = H~ q with the first dot */
+  EXPW_KERNEL_KRYLOV_MGS = 2,    /* Arnoldi: Gram-Schmidt axpy with the next dot */
+  EXPW_KERNEL_KRYLOV_AUX = 3,    /* Arnoldi: norm, start vector, normalize, combine */
+  EXPW_KERNEL_RK4 = 4,           /* RK4 stage */
+  EXPW_KERNEL_LEAPFROG_V = 5,    /* leap-frog velocity update */
+  EXPW_KERNEL_LEAPFROG_P = 6,    /* leap-frog pressure update */
+  EXPW_KERNEL_GATHER = 7,        /* receiver gather */
+  EXPW_KERNEL_CLASSES = 8
+};
+
+/* Enable (1) or disable (0) per-launch timing with HIP events recorded on the
+ * handle's stream around every kernel launch; also clears the totals. */
+int32_t expw_set_timing(expw_op* op, int32_t enable);
+
+/* Synchronizes and returns, per kernel class (arrays of EXPW_KERNEL_CLASSES
+ * entries, any may be NULL), the summed kernel time in ms, the number of
+ * launches and the algorithmic HBM bytes (each operand array counted once per
+ * launch, halos not counted) since timing was enabled. */
+int32_t expw_get_timing(expw_op* op, double* ms, int64_t* launches, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

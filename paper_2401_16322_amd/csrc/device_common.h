@@ -131,37 +131,27 @@ __device__ __forceinline__ double block_reduce(double v) {
   return r;
 }
 
-// Grid-wide reduction in a fixed order: every block stores its partial, the
-// last block to arrive (device-scope counter) combines the partials in block
-// order and writes *out, then resets the counter for the next launch. The
-// fences publish the partials across the L2s of all XCDs before the counter
-// increment, and make the last block observe them.
+// Grid-wide reductions go through the kernel boundary: a producing kernel
+// stores one partial per workgroup, and the kernel that needs the value
+// (launched after it on the same stream, so the partials are visible on every
+// XCD) sums them in block order. The result is deterministic and needs no
+// atomics or intra-kernel cross-XCD coherence.
 template <bool MAX>
-__device__ void grid_reduce(double v, double* __restrict__ partials, unsigned* counter,
-                            double* out) {
-  __shared__ int s_last;
+__device__ __forceinline__ void store_partial(double v, double* __restrict__ partials) {
   const double b = block_reduce<MAX>(v);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = b;
-    __threadfence();
-    const unsigned prev =
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == gridDim.x - 1);
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+// Sum (or max) of n partials in a fixed order; the value is returned to every thread.
+template <bool MAX>
+__device__ __forceinline__ double load_reduced(const double* __restrict__ partials, int n) {
+  __shared__ double s_val;
+  double acc = MAX ? -INFINITY : 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) acc = MAX ? fmax(acc, partials[i]) : acc + partials[i];
+  const double tot = block_reduce<MAX>(acc);
+  if (threadIdx.x == 0) s_val = tot;
   __syncthreads();
-  if (s_last) {
-    __threadfence();
-    double acc = MAX ? -INFINITY : 0.0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += kBlock) {
-      const double pv = __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      acc = MAX ? fmax(acc, pv) : acc + pv;
-    }
-    const double tot = block_reduce<MAX>(acc);
-    if (threadIdx.x == 0) {
-      *out = tot;
-      __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  return s_val;
 }
 
 }  // namespace expw

@@ -11,6 +11,7 @@
 #include "fused.h"
 #include "internal.h"
 #include "kernels.h"
+#include "profiler.h"
 
 struct expw_op {
   expw_grid g;
@@ -23,7 +24,7 @@ struct expw_op {
   int kmax, pmax;
   // workspace layout (byte offsets)
   size_t off_sig[3][2];
-  size_t off_src_idx, off_src_amp, off_part, off_cnt, off_scal, off_hess, off_ss, off_big;
+  size_t off_src_idx, off_src_amp, off_part, off_scal, off_hess, off_big;
   int64_t naug_pad;  // stride of a Krylov basis vector (elements)
   // spectrum and ellipse (host FP64)
   double c2max, x_lo, B, gamma, c0, c1;
@@ -42,6 +43,7 @@ struct expw_op {
   // last Krylov step
   int last_keff;
   double last_beta;
+  expw::Profiler prof;
 };
 
 namespace expw {
@@ -74,7 +76,7 @@ int32_t validate_grid(const expw_grid* g) {
 
 struct Layout {
   size_t sig[3][2];
-  size_t src_idx, src_amp, part, cnt, scal, hess, ss, big, total;
+  size_t src_idx, src_amp, part, scal, hess, big, total;
   int64_t naug_pad;
 };
 
@@ -89,11 +91,9 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
     }
   L.src_idx = off; off = align_up(off + EXPW_MAX_SOURCES * sizeof(int64_t));
   L.src_amp = off; off = align_up(off + EXPW_MAX_SOURCES * es);
-  L.part = off; off = align_up(off + kRedMaxBlocks * sizeof(double));
-  L.cnt = off; off = align_up(off + 64 * sizeof(unsigned));
+  L.part = off; off = align_up(off + 2 * kRedMaxBlocks * sizeof(double));  // two partial sets
   L.scal = off; off = align_up(off + 64 * sizeof(double));
   L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
-  L.ss = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * sizeof(double));
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -173,11 +173,21 @@ unsigned red_grid_for(int64_t n) {
 
 double src_scale(const expw_op* op) { return 1.0 / std::pow(op->g.h, op->g.ndim); }
 
+// Runs one launch bracketed by the profiler's events (a no-op when timing is off).
+template <class F>
+void timed(expw_op* op, int kind, double bytes, F&& launch) {
+  const int slot = op->prof.begin(op->stream);
+  launch();
+  op->prof.end(op->stream, slot, kind, bytes);
+}
+
 template <typename T>
 int32_t gather(expw_op* op, const T* S, T* traces, int64_t step) {
   if (!traces || op->n_rec == 0) return EXPW_OK;
-  k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec,
-                                                                 traces + step * op->n_rec);
+  timed(op, EXPW_KERNEL_GATHER, op->n_rec * (2.0 * sizeof(T) + 8.0), [&] {
+    k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec,
+                                                                   traces + step * op->n_rec);
+  });
   return check_launch("gather");
 }
 
@@ -196,8 +206,13 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, T* S, T* Abuf, T* Bb
   c.first = 1;
   c.a_first = static_cast<T>(a[0]);
   c.a_j = static_cast<T>(a[1]);
-  k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, nullptr, m == 1 ? nullptr : Abuf,
-                                                               nullptr, Cbuf, c, make_src<T>(op, q[0]));
+  const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
+  // words per point: reads v_{j-1} (nf) + c^2 (1) [+ v_{j-2} (nf) + sum (nf)],
+  // writes the sum (nf) [+ v_j (nf)]
+  timed(op, EXPW_KERNEL_FABER, (nf + 1 + nf + (m == 1 ? 0 : nf)) * pb, [&] {
+    k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, nullptr, m == 1 ? nullptr : Abuf,
+                                                                 nullptr, Cbuf, c, make_src<T>(op, q[0]));
+  });
   if (m == 1) {
     if (hipMemcpyAsync(S, Cbuf, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
       return fail(EXPW_EDEVICE, "faber: copy failed");
@@ -208,16 +223,20 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, T* S, T* Abuf, T* Bb
   c.a_first = T(0);
   c.cpp = static_cast<T>(2.0 * op->c1);
   c.a_j = static_cast<T>(a[2]);
-  k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(
-      g, Abuf, S, m == 2 ? nullptr : Bbuf, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
+  timed(op, EXPW_KERNEL_FABER, (4 * nf + 1 + (m == 2 ? 0 : nf)) * pb, [&] {
+    k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(
+        g, Abuf, S, m == 2 ? nullptr : Bbuf, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
+  });
   T* last = Bbuf;   // v_{j-1}
   T* older = Abuf;  // v_{j-2}
   c.cpp = static_cast<T>(op->c1);
   for (int j = 3; j <= m; ++j) {
     c.a_j = static_cast<T>(a[j]);
     const bool fin = (j == m);
-    k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(
-        g, last, older, fin ? nullptr : older, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
+    timed(op, EXPW_KERNEL_FABER, (4 * nf + 1 + (fin ? 0 : nf)) * pb, [&] {
+      k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(
+          g, last, older, fin ? nullptr : older, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
+    });
     std::swap(last, older);
   }
   return check_launch("faber term");
@@ -235,7 +254,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
   const int p = op->taylor_p;
   T* Dbuf = Cbuf + ns;
   T* Ebuf = Dbuf + ns;
-  const int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m);
+  const int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m, g.N);
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     if (op->n_src > 0) {
@@ -245,13 +264,31 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
       const double sc = src_scale(op);
       for (int j = 0; j < m; ++j) q[j] *= sc;
     }
-    int32_t rc;
-    if (fuse > 1)
-      rc = faber_fused<T, K, BC, DIM>(op->stream, g, make_src<T>(op, 0.0), S, Abuf, Bbuf, Cbuf,
-                                      Dbuf, Ebuf, a.data(), q.data(), m, fuse, op->gamma, op->c0,
-                                      op->c1);
-    else
+    int32_t rc = EXPW_OK;
+    if constexpr (DIM == 2 && K == 2 && BC == 0) {
+      if (fuse > 1) {
+        // a remainder of one term after the fused passes: unfused final term
+        auto final_term = [&](const T* vl, const T* vpv, T* acc, T* out, int j) -> int32_t {
+          FaberTerm<T> c{};
+          c.inv_gamma = static_cast<T>(1.0 / op->gamma);
+          c.c0 = static_cast<T>(op->c0);
+          c.cpp = static_cast<T>(op->c1);
+          c.a_j = static_cast<T>(a[j]);
+          timed(op, EXPW_KERNEL_FABER, 13.0 * g.N * sizeof(T), [&] {
+            k_faber_term<T, K, BC, DIM><<<grid_for(g.N), kBlock, 0, op->stream>>>(
+                g, vl, vpv, nullptr, acc, out, c, make_src<T>(op, q[j - 1]));
+          });
+          return check_launch("faber final term");
+        };
+        rc = faber_fused_2d<T>(op->stream, &op->prof, g, make_src<T>(op, 0.0), S, Abuf, Bbuf, Cbuf,
+                               Dbuf, Ebuf, a.data(), q.data(), m, fuse, op->gamma, op->c0, op->c1,
+                               final_term);
+      } else {
+        rc = faber_unfused<T, K, BC, DIM>(op, g, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
+      }
+    } else {
       rc = faber_unfused<T, K, BC, DIM>(op, g, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
+    }
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
   }
@@ -269,6 +306,7 @@ int32_t rk4_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T* tra
   T* Cbuf = Bbuf + ns;
   const unsigned grid = grid_for(g.N);
   const double sc = src_scale(op);
+  const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
   double der[1];
   auto srcq = [&](double t) {
     if (op->n_src == 0) return make_src<T>(op, 0.0);
@@ -279,10 +317,20 @@ int32_t rk4_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T* tra
           s3 = static_cast<T>(dt / 3.0);
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
-    k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, S, nullptr, Abuf, Cbuf, h2, s6, srcq(t));
-    k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Abuf, S, Cbuf, Bbuf, Cbuf, h2, s3, srcq(t + 0.5 * dt));
-    k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Bbuf, S, Cbuf, Abuf, Cbuf, h1, s3, srcq(t + 0.5 * dt));
-    k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Abuf, nullptr, Cbuf, nullptr, S, T(0), s6, srcq(t + dt));
+    // words per point: stage 1 reads u (nf) + c^2, writes y, sum (2 nf); stages 2-3 read
+    // y, u, sum (3 nf) + c^2, write y, sum (2 nf); stage 4 reads y, sum + c^2, writes u
+    timed(op, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, [&] {
+      k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, S, nullptr, Abuf, Cbuf, h2, s6, srcq(t));
+    });
+    timed(op, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, [&] {
+      k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Abuf, S, Cbuf, Bbuf, Cbuf, h2, s3, srcq(t + 0.5 * dt));
+    });
+    timed(op, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, [&] {
+      k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Bbuf, S, Cbuf, Abuf, Cbuf, h1, s3, srcq(t + 0.5 * dt));
+    });
+    timed(op, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, [&] {
+      k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Abuf, nullptr, Cbuf, nullptr, S, T(0), s6, srcq(t + dt));
+    });
     int32_t rc = check_launch("rk4 stage");
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
@@ -295,16 +343,22 @@ int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T
   const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
   const unsigned grid = grid_for(g.N);
   const double sc = src_scale(op);
+  const double pb = static_cast<double>(g.N) * sizeof(T);
   double der[1];
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
-    k_lf_v<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, static_cast<T>(dt));
+    // velocity: reads p and v (1 + d), writes v (d); pressure: reads p, v, c^2 (d + 2), writes p
+    timed(op, EXPW_KERNEL_LEAPFROG_V, (1 + 2 * DIM) * pb, [&] {
+      k_lf_v<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, static_cast<T>(dt));
+    });
     double q = 0.0;
     if (op->n_src > 0) {
       ricker_derivatives(t + 0.5 * dt, op->f_peak, op->t_delay, 1, der);
       q = dt * der[0] * sc;
     }
-    k_lf_p<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, static_cast<T>(dt), make_src<T>(op, q));
+    timed(op, EXPW_KERNEL_LEAPFROG_P, (DIM + 3) * pb, [&] {
+      k_lf_p<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, static_cast<T>(dt), make_src<T>(op, q));
+    });
     int32_t rc = check_launch("leapfrog");
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
@@ -323,13 +377,12 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
   const int64_t ld = op->naug_pad;
   T* Q = reinterpret_cast<T*>(op->ws + op->off_big);
   double* part = reinterpret_cast<double*>(op->ws + op->off_part);
-  unsigned* cnt = reinterpret_cast<unsigned*>(op->ws + op->off_cnt);
   double* scal = reinterpret_cast<double*>(op->ws + op->off_scal);
   double* hess = reinterpret_cast<double*>(op->ws + op->off_hess);
-  double* ssq = reinterpret_cast<double*>(op->ws + op->off_ss);
   const T* amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
   const unsigned rg_vec = red_grid_for(naug);
   const unsigned rg_pts = red_grid_for(g.N + p);
+  const double es = sizeof(T);
   const double tol = 1e-14;
   std::vector<double> hh((EXPW_MAX_KRYLOV + 1) * kHessLd), hk(k * k), E(k * k), der(EXPW_MAX_TAYLOR);
   std::vector<double> scal_h(2);
@@ -347,21 +400,37 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
       for (int c = 0; c < p; ++c) ks.G[c] = der[p - 1 - c] * sc;
     }
     // q_1 = [S; e_p] / beta
-    k_norm2<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, ns, part, cnt, scal + 0);
-    k_kry_init<T><<<red_grid_for(naug), kBlock, 0, op->stream>>>(S, ns, Q, naug, scal + 0,
-                                                                    p > 0 ? 1.0 : 0.0, scal + 1);
+    double* P[2] = {part, part + kRedMaxBlocks};
+    const unsigned nb_ns = red_grid_for(ns);
+    timed(op, EXPW_KERNEL_KRYLOV_AUX, ns * es, [&] {
+      k_norm2<T><<<nb_ns, kBlock, 0, op->stream>>>(S, ns, P[0]);
+    });
+    timed(op, EXPW_KERNEL_KRYLOV_AUX, (ns + naug) * es, [&] {
+      k_kry_init<T><<<red_grid_for(naug), kBlock, 0, op->stream>>>(S, ns, Q, naug, P[0], nb_ns,
+                                                                      p > 0 ? 1.0 : 0.0, scal + 1);
+    });
     for (int j = 0; j < k; ++j) {
       T* w = Q + (j + 1) * ld;
-      k_kry_matvec<T, K, BC, DIM><<<rg_pts, kBlock, 0, op->stream>>>(g, Q + j * ld, w, Q, ks, amp,
-                                                                     part, cnt, hess + 0 * kHessLd + j);
+      int c = 0;
+      // reads q (with tail), q_1 and c^2, writes w
+      timed(op, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * naug + g.N) * es, [&] {
+        k_kry_matvec<T, K, BC, DIM><<<rg_pts, kBlock, 0, op->stream>>>(g, Q + j * ld, w, Q, ks, amp, P[c]);
+      });
+      int nin = static_cast<int>(rg_pts);
       for (int i = 0; i <= j; ++i) {
         const bool lastc = (i == j);
-        k_kry_mgs<T><<<rg_vec, kBlock, 0, op->stream>>>(
-            w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld, naug, hess + i * kHessLd + j, part,
-            cnt, lastc ? ssq + j : hess + (i + 1) * kHessLd + j);
+        // reads w, q_i [, q_{i+1}], writes w
+        timed(op, EXPW_KERNEL_KRYLOV_MGS, (lastc ? 3.0 : 4.0) * naug * es, [&] {
+          k_kry_mgs<T><<<rg_vec, kBlock, 0, op->stream>>>(w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld,
+                                                          naug, P[c], nin, hess + i * kHessLd + j, P[c ^ 1]);
+        });
+        c ^= 1;
+        nin = static_cast<int>(rg_vec);
       }
-      k_kry_normalize<T><<<rg_vec, kBlock, 0, op->stream>>>(w, naug, ssq + j,
-                                                              hess + (j + 1) * kHessLd + j, scal + 1, tol);
+      timed(op, EXPW_KERNEL_KRYLOV_AUX, 2.0 * naug * es, [&] {
+        k_kry_normalize<T><<<rg_vec, kBlock, 0, op->stream>>>(w, naug, P[c], nin,
+                                                                hess + (j + 1) * kHessLd + j, scal + 1, tol);
+      });
     }
     int32_t rc = check_launch("arnoldi");
     if (rc != EXPW_OK) return rc;
@@ -383,12 +452,15 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
       // zero state and no source: the state stays zero
     } else {
       op->last_keff = keff;
+      // only the upper Hessenberg part is written by the kernels
       for (int r = 0; r < keff; ++r)
-        for (int c = 0; c < keff; ++c) hk[r * keff + c] = dt * hh[r * kHessLd + c];
+        for (int c = 0; c < keff; ++c) hk[r * keff + c] = (r <= c + 1) ? dt * hh[r * kHessLd + c] : 0.0;
       if (!expm(keff, hk.data(), E.data())) return fail(EXPW_ENONFINITE, "krylov: non-finite Hessenberg matrix");
       KryCoef y{};
       for (int r = 0; r < keff; ++r) y.y[r] = E[r * keff + 0];
-      k_kry_combine<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, keff, y, beta);
+      timed(op, EXPW_KERNEL_KRYLOV_AUX, (keff + 1.0) * ns * es, [&] {
+        k_kry_combine<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, keff, y, beta);
+      });
       if ((rc = check_launch("krylov combine")) != EXPW_OK) return rc;
     }
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
@@ -456,10 +528,8 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->off_src_idx = L.src_idx;
   op->off_src_amp = L.src_amp;
   op->off_part = L.part;
-  op->off_cnt = L.cnt;
   op->off_scal = L.scal;
   op->off_hess = L.hess;
-  op->off_ss = L.ss;
   op->off_big = L.big;
   op->naug_pad = L.naug_pad;
   op->n_src = 0;
@@ -490,22 +560,22 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
       }
       staging.push_back(std::move(buf));
     }
-  unsigned* cnt = reinterpret_cast<unsigned*>(op->ws + L.cnt);
-  k_fill_u32<<<1, 64, 0, op->stream>>>(cnt, 64, 0u);
   double* part = reinterpret_cast<double*>(op->ws + L.part);
-  double* scal = reinterpret_cast<double*>(op->ws + L.scal);
   const int64_t N = npts(*g);
+  const unsigned nb = red_grid_for(N);
   if (g->dtype == EXPW_F32)
-    k_c2_max<float><<<red_grid_for(N), kBlock, 0, op->stream>>>(static_cast<const float*>(c2_dev), N, part, cnt, scal + 2);
+    k_c2_max<float><<<nb, kBlock, 0, op->stream>>>(static_cast<const float*>(c2_dev), N, part);
   else
-    k_c2_max<double><<<red_grid_for(N), kBlock, 0, op->stream>>>(static_cast<const double*>(c2_dev), N, part, cnt, scal + 2);
-  double c2max = 0.0;
-  hipError_t e = hipMemcpyAsync(&c2max, scal + 2, sizeof(double), hipMemcpyDeviceToHost, op->stream);
+    k_c2_max<double><<<nb, kBlock, 0, op->stream>>>(static_cast<const double*>(c2_dev), N, part);
+  std::vector<double> parts(nb);
+  hipError_t e = hipMemcpyAsync(parts.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, op->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
   if (e != hipSuccess || hipGetLastError() != hipSuccess) {
     delete op;
     return fail(EXPW_EDEVICE, "expw_op_create: device error: %s", hipGetErrorString(e));
   }
+  double c2max = -INFINITY;
+  for (double v : parts) c2max = std::fmax(c2max, v);
   if (!std::isfinite(c2max)) {
     delete op;
     return fail(EXPW_ENONFINITE, "c2 holds a non-finite or non-positive value");
@@ -682,6 +752,23 @@ int32_t expw_sync_status(expw_op* op) {
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e));
   const hipError_t e2 = hipGetLastError();
   if (e2 != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e2));
+  return EXPW_OK;
+}
+
+int32_t expw_set_timing(expw_op* op, int32_t enable) {
+  if (int32_t rc = check_op(op)) return rc;
+  op->prof.enable(enable != 0);
+  return EXPW_OK;
+}
+
+int32_t expw_get_timing(expw_op* op, double* ms, int64_t* launches, double* bytes) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!op->prof.collect()) return fail(EXPW_EDEVICE, "timing: event query failed");
+  for (int k = 0; k < EXPW_KERNEL_CLASSES; ++k) {
+    if (ms) ms[k] = op->prof.ms(k);
+    if (launches) launches[k] = op->prof.launches(k);
+    if (bytes) bytes[k] = op->prof.bytes(k);
+  }
   return EXPW_OK;
 }
 

@@ -139,32 +139,27 @@ __global__ __launch_bounds__(kBlock) void k_gather(const T* __restrict__ p,
 // max over c2 with non-finite or non-positive entries mapped to +inf
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_c2_max(const T* __restrict__ c2, int64_t n,
-                                                   double* partials, unsigned* counter,
-                                                   double* out) {
+                                                   double* partials) {
   double m = -INFINITY;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const double v = static_cast<double>(c2[i]);
     m = fmax(m, (isfinite(v) && v > 0.0) ? v : INFINITY);
   }
-  grid_reduce<true>(m, partials, counter, out);
-}
-
-__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  store_partial<true>(m, partials);
 }
 
 // ---------------------------------------------------------------- Krylov (Arnoldi)
 // Basis vectors hold the augmented vector [state | tail(p) | zero pad].
 
-// q0 = [S ; e_p] / beta, beta = sqrt(|S|^2 + tail2) (tail2 = 1 with a source)
+// q0 = [S ; e_p] / beta, beta = sqrt(|S|^2 + tail2) (tail2 = 1 with a source);
+// |S|^2 arrives as nin partials of the preceding k_norm2.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kry_init(const T* __restrict__ S, int64_t ns,
                                                      T* __restrict__ q0, int64_t naug,
-                                                     const double* nrm2, double tail2,
+                                                     const double* pin, int nin, double tail2,
                                                      double* beta_out) {
-  const double b = sqrt(*nrm2 + tail2);
+  const double b = sqrt(load_reduced<false>(pin, nin) + tail2);
   const double inv = b > 0.0 ? 1.0 / b : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *beta_out = b;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < naug;
@@ -180,15 +175,14 @@ __global__ __launch_bounds__(kBlock) void k_kry_init(const T* __restrict__ S, in
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_norm2(const T* __restrict__ x, int64_t n,
-                                                  double* partials, unsigned* counter,
-                                                  double* out) {
+                                                  double* pout) {
   double acc = 0.0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     const double v = static_cast<double>(x[i]);
     acc += v * v;
   }
-  grid_reduce<false>(acc, partials, counter, out);
+  store_partial<false>(acc, pout);
 }
 
 // Source coupling of the augmented matrix for the Krylov basis: the pressure
@@ -201,14 +195,13 @@ struct KrySrc {
   double G[16];
 };
 
-// w = H~ q and h_out = w . q0 (first Gram-Schmidt coefficient of this column)
+// w = H~ q; stores the partials of w . q0 (first Gram-Schmidt coefficient of the column)
 template <typename T, int K, int BC, int DIM>
 __global__ __launch_bounds__(kBlock) void k_kry_matvec(Geo<T, K, DIM> g, const T* __restrict__ q,
                                                        T* __restrict__ w,
                                                        const T* __restrict__ q0, KrySrc src,
                                                        const T* __restrict__ amp,
-                                                       double* partials, unsigned* counter,
-                                                       double* h_out) {
+                                                       double* __restrict__ pout) {
   const int64_t ns = (DIM + 1) * g.N;
   const int64_t items = g.N + src.p;
   double acc = 0.0;
@@ -241,17 +234,19 @@ __global__ __launch_bounds__(kBlock) void k_kry_matvec(Geo<T, K, DIM> g, const T
       acc += static_cast<double>(val) * static_cast<double>(q0[ns + c]);
     }
   }
-  grid_reduce<false>(acc, partials, counter, h_out);
+  store_partial<false>(acc, pout);
 }
 
 // Modified Gram-Schmidt update fused with the next dot:
-//   w -= h_in q_i;  out = w . qn  (qn == nullptr: out = w . w)
+//   h = (reduced partials pin), stored to *h_store by block 0;
+//   w -= h q_i;  partials of w . qn into pout  (qn == nullptr: w . w)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kry_mgs(T* __restrict__ w, const T* __restrict__ qi,
                                                     const T* __restrict__ qn, int64_t n,
-                                                    const double* h_in, double* partials,
-                                                    unsigned* counter, double* out) {
-  const double h = *h_in;
+                                                    const double* __restrict__ pin, int nin,
+                                                    double* h_store, double* __restrict__ pout) {
+  const double h = load_reduced<false>(pin, nin);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *h_store = h;
   double acc = 0.0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -260,16 +255,17 @@ __global__ __launch_bounds__(kBlock) void k_kry_mgs(T* __restrict__ w, const T* 
     const double o = qn ? static_cast<double>(qn[i]) : static_cast<double>(wt);
     acc += static_cast<double>(wt) * o;
   }
-  grid_reduce<false>(acc, partials, counter, out);
+  store_partial<false>(acc, pout);
 }
 
-// q_{j+1} = w / h with h = sqrt(ss); a column with h <= tol * beta is a
+// q_{j+1} = w / h with h = |w| (reduced from the partials of w . w); a column with h <= tol * beta is a
 // breakdown: it is zeroed and the host truncates the basis there.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kry_normalize(T* __restrict__ w, int64_t n,
-                                                          const double* ss, double* h_out,
-                                                          const double* beta, double tol) {
-  const double h = sqrt(*ss);
+                                                          const double* __restrict__ pin, int nin,
+                                                          double* h_out, const double* beta,
+                                                          double tol) {
+  const double h = sqrt(load_reduced<false>(pin, nin));
   const double sc = (h > tol * (*beta)) ? 1.0 / h : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *h_out = h;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;

@@ -69,7 +69,12 @@ SIGNATURES = {
     "expw_step_leapfrog": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
     "expw_sync_status": (_i32, [_vp]),
     "expw_krylov_info": (_i32, [_vp, _pi32, _pd]),
+    "expw_set_timing": (_i32, [_vp, _i32]),
+    "expw_get_timing": (_i32, [_vp, _pd, _pi64, _pd]),
 }
+
+KERNEL_CLASSES = ("faber", "krylov_matvec", "krylov_mgs", "krylov_aux", "rk4",
+                  "leapfrog_v", "leapfrog_p", "gather")
 
 _lib = None
 
@@ -257,6 +262,20 @@ def expw_krylov_info(op):
     return k.value, b.value
 
 
+def expw_set_timing(op, enable):
+    _check(load().expw_set_timing(op, int(bool(enable))))
+
+
+def expw_get_timing(op):
+    """{class: (ms, launches, algorithmic bytes)} since timing was enabled."""
+    n = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    la = (ctypes.c_int64 * n)()
+    by = (ctypes.c_double * n)()
+    _check(load().expw_get_timing(op, ms, la, by))
+    return {KERNEL_CLASSES[k]: (ms[k], la[k], by[k]) for k in range(n)}
+
+
 # ---------------------------------------------------------------- torch convenience wrapper
 
 class Operator:
@@ -378,6 +397,13 @@ class Operator:
 
     def krylov_info(self):
         return expw_krylov_info(self.op)
+
+    def set_timing(self, enable=True):
+        self._sync_stream()
+        expw_set_timing(self.op, enable)
+
+    def timing(self):
+        return expw_get_timing(self.op)
 
     def close(self):
         if getattr(self, "op", None):

@@ -38,7 +38,7 @@ def layered_velocity(n, h, seed, vmin=1500.0, vmax=4500.0, n_interfaces=8,
     rng = np.random.default_rng(seed)
     n = tuple(int(v) for v in n)
     ndim = len(n)
-    ext = [(v - 1) * h for v in n]           # physical extents per axis (x, [y,] z)
+    ext = [max(v - 1, 1) * h for v in n]     # physical extents per axis (x, [y,] z)
     lz = ext[-1]
     axes = [np.arange(v) * h for v in n]
     grids = np.meshgrid(*[axes[a] for a in reversed(range(ndim))], indexing="ij")

@@ -81,14 +81,21 @@ def test_krylov_steps_match_oracle(dtype, k, src):
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
 
 
-def test_krylov_happy_breakdown_on_tiny_grid():
-    case = make_case((3, 3), "float64", abc=1, src=False, seed=6, max_k=30)
-    U = to_dev(case, case.U0)
-    case.op.step_krylov(U, 0.0, 5e-3, 27, 1)
-    ref, _, _ = run(case.prob, "krylov", case.U0, 0.0, 5e-3, 1, k=27)
+def test_krylov_happy_breakdown_on_plane_wave():
+    """A periodic plane wave spans a 2-dimensional invariant subspace of H, so the
+    Arnoldi process breaks down after two vectors (k_eff = 2) and the step is
+    exact: the closed form shifted by dt."""
+    from oracle.exact import plane_wave
+    case = make_case((24, 20), "float64", bc="periodic", src=False, homogeneous=1.0, max_k=10)
+    U0, omega = plane_wave(case.prob.grid, 1.0, (3, 2), 0.0)
+    U = to_dev(case, U0)
+    case.op.step_krylov(U, 0.0, 2.0, 10, 1)
+    ref, _, _ = run(case.prob, "krylov", U0, 0.0, 2.0, 1, k=10)
+    exact, _ = plane_wave(case.prob.grid, 1.0, (3, 2), 2.0)
     keff, beta = case.op.krylov_info()
-    assert keff <= 27 and beta > 0
+    assert keff == 2 and np.isclose(beta, np.linalg.norm(U0))
     assert rel_l2(U.cpu().numpy(), ref) <= 1e-11
+    assert rel_l2(U.cpu().numpy(), exact) <= 1e-11
 
 
 def test_krylov_zero_state_without_source_stays_zero():
