@@ -181,8 +181,9 @@ int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* node_idx_d
  * from t0 + s dt). traces_dev: NULL or an array of nsteps * n_rec elements. */
 int32_t expw_step_faber(expw_op* op, void* state_dev, double t0, double dt, int32_t m,
                         int64_t nsteps, void* traces_dev);
-/* Krylov steps synchronize once per step (the k x k Hessenberg matrix is
- * exponentiated on the host in FP64). Requires k <= max_krylov_k. */
+/* Krylov steps (Arnoldi with modified Gram-Schmidt on the augmented matrix,
+ * then the small exponential, see expw_set_krylov_expm). Requires
+ * k <= max_krylov_k. */
 int32_t expw_step_krylov(expw_op* op, void* state_dev, double t0, double dt, int32_t k,
                          int64_t nsteps, void* traces_dev);
 int32_t expw_step_rk4(expw_op* op, void* state_dev, double t0, double dt, int64_t nsteps,
@@ -193,8 +194,19 @@ int32_t expw_step_leapfrog(expw_op* op, void* state_dev, double t0, double dt, i
 /* Synchronizes the stream and reports a pending device error. */
 int32_t expw_sync_status(expw_op* op);
 
-/* Effective dimension and beta of the last Krylov step (host values). */
+/* Effective dimension and beta of the last Krylov step (host values;
+ * synchronizes when the step ran its small exponential on the device). */
 int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta);
+
+/* Where the Krylov step evaluates y = exp(dt H_k) e_1 (Sec. 3.2: the small
+ * Hessenberg exponential), both in FP64:
+ *   EXPW_EXPM_DEVICE (default): one workgroup evaluates it by scaling and
+ *     squaring of the degree-16 Taylor polynomial; the step stays
+ *     asynchronous.
+ *   EXPW_EXPM_HOST: scaling-and-squaring [13/13] Pade on the host (the same
+ *     routine as expw_expm); one synchronization per step. */
+enum { EXPW_EXPM_DEVICE = 0, EXPW_EXPM_HOST = 1 };
+int32_t expw_set_krylov_expm(expw_op* op, int32_t mode);
 
 /* ------------------------------------------------------------------ timing */
 

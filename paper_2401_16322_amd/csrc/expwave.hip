@@ -24,7 +24,7 @@ struct expw_op {
   int kmax, pmax;
   // workspace layout (byte offsets)
   size_t off_sig[3][2];
-  size_t off_src_idx, off_src_amp, off_part, off_scal, off_hess, off_big;
+  size_t off_src_idx, off_src_amp, off_part, off_scal, off_hess, off_kry, off_big;
   int64_t naug_pad;  // stride of a Krylov basis vector (elements)
   // spectrum and ellipse (host FP64)
   double c2max, x_lo, B, gamma, c0, c1;
@@ -40,7 +40,8 @@ struct expw_op {
   const int64_t* rec_dev;
   // tuning
   int fuse, tile_x, tile_y;
-  // last Krylov step
+  // Krylov: small exponential on the device (0) or the host (1); last step info
+  int kry_mode;
   int last_keff;
   double last_beta;
   expw::Profiler prof;
@@ -76,7 +77,7 @@ int32_t validate_grid(const expw_grid* g) {
 
 struct Layout {
   size_t sig[3][2];
-  size_t src_idx, src_amp, part, scal, hess, big, total;
+  size_t src_idx, src_amp, part, scal, hess, kry, big, total;
   int64_t naug_pad;
 };
 
@@ -94,6 +95,7 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
   L.part = off; off = align_up(off + 2 * kRedMaxBlocks * sizeof(double));  // two partial sets
   L.scal = off; off = align_up(off + 64 * sizeof(double));
   L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
+  L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -383,6 +385,9 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
   const unsigned rg_vec = red_grid_for(naug);
   const unsigned rg_pts = red_grid_for(g.N + p);
   const double es = sizeof(T);
+  double* kry_y = reinterpret_cast<double*>(op->ws + op->off_kry);
+  double* kry_sc = kry_y + 64;
+  int* kry_keff = reinterpret_cast<int*>(op->ws + op->off_kry + 136 * sizeof(double));
   const double tol = 1e-14;
   std::vector<double> hh((EXPW_MAX_KRYLOV + 1) * kHessLd), hk(k * k), E(k * k), der(EXPW_MAX_TAYLOR);
   std::vector<double> scal_h(2);
@@ -407,61 +412,79 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
     });
     timed(op, EXPW_KERNEL_KRYLOV_AUX, (ns + naug) * es, [&] {
       k_kry_init<T><<<red_grid_for(naug), kBlock, 0, op->stream>>>(S, ns, Q, naug, P[0], nb_ns,
-                                                                      p > 0 ? 1.0 : 0.0, scal + 1);
+                                                                      p > 0 ? 1.0 : 0.0, scal + 1, kry_sc);
     });
+    // P[c] holds the partials of the latest reduction, produced by nin blocks
+    int c = 0, nin = 0;
     for (int j = 0; j < k; ++j) {
       T* w = Q + (j + 1) * ld;
-      int c = 0;
-      // reads q (with tail), q_1 and c^2, writes w
+      // reads Q_j (with tail), q_1 and c^2, writes w
       timed(op, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * naug + g.N) * es, [&] {
-        k_kry_matvec<T, K, BC, DIM><<<rg_pts, kBlock, 0, op->stream>>>(g, Q + j * ld, w, Q, ks, amp, P[c]);
+        k_kry_matvec<T, K, BC, DIM><<<rg_pts, kBlock, 0, op->stream>>>(
+            g, Q + j * ld, w, Q, ks, amp, j == 0 ? nullptr : P[c], nin, tol, scal + 1,
+            j == 0 ? nullptr : hess + j * kHessLd + (j - 1), kry_sc + j, P[c ^ 1]);
       });
-      int nin = static_cast<int>(rg_pts);
+      c ^= 1;
+      nin = static_cast<int>(rg_pts);
       for (int i = 0; i <= j; ++i) {
         const bool lastc = (i == j);
-        // reads w, q_i [, q_{i+1}], writes w
+        // reads w, Q_i [, Q_{i+1}], writes w
         timed(op, EXPW_KERNEL_KRYLOV_MGS, (lastc ? 3.0 : 4.0) * naug * es, [&] {
           k_kry_mgs<T><<<rg_vec, kBlock, 0, op->stream>>>(w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld,
-                                                          naug, P[c], nin, hess + i * kHessLd + j, P[c ^ 1]);
+                                                          naug, P[c], nin, hess + i * kHessLd + j, kry_sc, i,
+                                                          P[c ^ 1]);
         });
         c ^= 1;
         nin = static_cast<int>(rg_vec);
       }
-      timed(op, EXPW_KERNEL_KRYLOV_AUX, 2.0 * naug * es, [&] {
-        k_kry_normalize<T><<<rg_vec, kBlock, 0, op->stream>>>(w, naug, P[c], nin,
-                                                                hess + (j + 1) * kHessLd + j, scal + 1, tol);
-      });
     }
+    timed(op, EXPW_KERNEL_KRYLOV_AUX, 0.0, [&] {
+      k_kry_finish<<<1, kBlock, 0, op->stream>>>(P[c], nin, tol, scal + 1, hess + k * kHessLd + (k - 1),
+                                                 kry_sc + k);
+    });
     int32_t rc = check_launch("arnoldi");
     if (rc != EXPW_OK) return rc;
-    // the small Hessenberg exponential on the host (one sync per step)
-    if (hipMemcpyAsync(hh.data(), hess, hh.size() * sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
-        hipMemcpyAsync(scal_h.data(), scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
-        hipStreamSynchronize(op->stream) != hipSuccess)
-      return fail(EXPW_EDEVICE, "krylov: device to host copy failed: %s", hipGetErrorString(hipGetLastError()));
-    const double beta = scal_h[1];
-    int keff = k;
-    for (int j = 0; j < k; ++j)
-      if (!(hh[(j + 1) * kHessLd + j] > tol * beta)) {
-        keff = j + 1;
-        break;
-      }
-    op->last_beta = beta;
-    if (beta == 0.0) {
-      op->last_keff = 0;
-      // zero state and no source: the state stays zero
-    } else {
-      op->last_keff = keff;
-      // only the upper Hessenberg part is written by the kernels
-      for (int r = 0; r < keff; ++r)
-        for (int c = 0; c < keff; ++c) hk[r * keff + c] = (r <= c + 1) ? dt * hh[r * kHessLd + c] : 0.0;
-      if (!expm(keff, hk.data(), E.data())) return fail(EXPW_ENONFINITE, "krylov: non-finite Hessenberg matrix");
-      KryCoef y{};
-      for (int r = 0; r < keff; ++r) y.y[r] = E[r * keff + 0];
-      timed(op, EXPW_KERNEL_KRYLOV_AUX, (keff + 1.0) * ns * es, [&] {
-        k_kry_combine<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, keff, y, beta);
+    if (op->kry_mode == EXPW_EXPM_DEVICE) {
+      // y = exp(dt H_k) e_1 and the combination without leaving the device
+      timed(op, EXPW_KERNEL_KRYLOV_AUX, 0.0, [&] {
+        k_kry_expm<<<1, kBlock, 0, op->stream>>>(hess, k, dt, tol, scal + 1, kry_y, kry_keff);
       });
-      if ((rc = check_launch("krylov combine")) != EXPW_OK) return rc;
+      timed(op, EXPW_KERNEL_KRYLOV_AUX, (k + 1.0) * ns * es, [&] {
+        k_kry_combine_dev<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, kry_y, kry_keff,
+                                                                          scal + 1, kry_sc);
+      });
+      op->last_keff = -1;  // on the device; read by expw_krylov_info
+      if ((rc = check_launch("krylov exponential")) != EXPW_OK) return rc;
+    } else {
+      // the small Hessenberg exponential on the host (one sync per step)
+      if (hipMemcpyAsync(hh.data(), hess, hh.size() * sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+          hipMemcpyAsync(scal_h.data(), scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+          hipStreamSynchronize(op->stream) != hipSuccess)
+        return fail(EXPW_EDEVICE, "krylov: device to host copy failed: %s", hipGetErrorString(hipGetLastError()));
+      const double beta = scal_h[1];
+      int keff = k;
+      for (int j = 0; j < k; ++j)
+        if (!(hh[(j + 1) * kHessLd + j] > tol * beta)) {
+          keff = j + 1;
+          break;
+        }
+      op->last_beta = beta;
+      if (beta == 0.0) {
+        op->last_keff = 0;
+        // zero state and no source: the state stays zero
+      } else {
+        op->last_keff = keff;
+        // only the upper Hessenberg part is written by the kernels
+        for (int r = 0; r < keff; ++r)
+          for (int c = 0; c < keff; ++c) hk[r * keff + c] = (r <= c + 1) ? dt * hh[r * kHessLd + c] : 0.0;
+        if (!expm(keff, hk.data(), E.data())) return fail(EXPW_ENONFINITE, "krylov: non-finite Hessenberg matrix");
+        KryCoef y{};
+        for (int r = 0; r < keff; ++r) y.y[r] = E[r * keff + 0];
+        timed(op, EXPW_KERNEL_KRYLOV_AUX, (keff + 1.0) * ns * es, [&] {
+          k_kry_combine<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, keff, y, beta, kry_sc);
+        });
+        if ((rc = check_launch("krylov combine")) != EXPW_OK) return rc;
+      }
     }
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
   }
@@ -530,6 +553,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->off_part = L.part;
   op->off_scal = L.scal;
   op->off_hess = L.hess;
+  op->off_kry = L.kry;
   op->off_big = L.big;
   op->naug_pad = L.naug_pad;
   op->n_src = 0;
@@ -538,6 +562,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->taylor_p = std::max(1, std::min(8, max_p));
   op->fuse = 0;
   op->tile_x = op->tile_y = 0;
+  op->kry_mode = EXPW_EXPM_DEVICE;
   op->last_keff = 0;
   op->last_beta = 0.0;
 
@@ -775,8 +800,30 @@ int32_t expw_get_timing(expw_op* op, double* ms, int64_t* launches, double* byte
 int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta) {
   if (int32_t rc = check_op(op)) return rc;
   if (!k_eff || !beta) return fail(EXPW_EINVAL, "NULL output");
-  *k_eff = op->last_keff;
-  *beta = op->last_beta;
+  if (op->last_keff >= 0) {
+    *k_eff = op->last_keff;
+    *beta = op->last_beta;
+    return EXPW_OK;
+  }
+  // the last step ran its exponential on the device
+  int ke = 0;
+  double b = 0.0;
+  if (hipMemcpyAsync(&ke, op->ws + op->off_kry + 136 * sizeof(double), sizeof(int), hipMemcpyDeviceToHost,
+                     op->stream) != hipSuccess ||
+      hipMemcpyAsync(&b, op->ws + op->off_scal + sizeof(double), sizeof(double), hipMemcpyDeviceToHost,
+                     op->stream) != hipSuccess ||
+      hipStreamSynchronize(op->stream) != hipSuccess)
+    return fail(EXPW_EDEVICE, "krylov info: copy failed");
+  *k_eff = ke;
+  *beta = b;
+  return EXPW_OK;
+}
+
+int32_t expw_set_krylov_expm(expw_op* op, int32_t mode) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (mode != EXPW_EXPM_DEVICE && mode != EXPW_EXPM_HOST)
+    return fail(EXPW_EINVAL, "mode must be EXPW_EXPM_DEVICE or EXPW_EXPM_HOST");
+  op->kry_mode = mode;
   return EXPW_OK;
 }
 

@@ -150,7 +150,10 @@ __global__ __launch_bounds__(kBlock) void k_c2_max(const T* __restrict__ c2, int
 }
 
 // ---------------------------------------------------------------- Krylov (Arnoldi)
-// Basis vectors hold the augmented vector [state | tail(p) | zero pad].
+// Basis vectors hold the augmented vector [state | tail(p) | zero pad]. Column
+// j is stored unnormalized as Q_j with its scale s_j = 1 / h_{j,j-1} kept in
+// sc[j] (s_0 = 1: Q_0 is normalized), so that q_j = s_j Q_j without a separate
+// normalization sweep; a breakdown column has s_j = 0.
 
 // q0 = [S ; e_p] / beta, beta = sqrt(|S|^2 + tail2) (tail2 = 1 with a source);
 // |S|^2 arrives as nin partials of the preceding k_norm2.
@@ -158,10 +161,13 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kry_init(const T* __restrict__ S, int64_t ns,
                                                      T* __restrict__ q0, int64_t naug,
                                                      const double* pin, int nin, double tail2,
-                                                     double* beta_out) {
+                                                     double* beta_out, double* sc) {
   const double b = sqrt(load_reduced<false>(pin, nin) + tail2);
   const double inv = b > 0.0 ? 1.0 / b : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *beta_out = b;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *beta_out = b;
+    sc[0] = 1.0;
+  }
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < naug;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     double v = 0.0;
@@ -195,15 +201,35 @@ struct KrySrc {
   double G[16];
 };
 
-// w = H~ q; stores the partials of w . q0 (first Gram-Schmidt coefficient of the column)
+// h_{j,j-1} = sqrt(reduced partials of |w|^2) and s_j = 1/h_{j,j-1}, or 0
+// when h_{j,j-1} <= tol * beta (breakdown).
+__device__ __forceinline__ double column_scale(const double* pin, int nin, double tol,
+                                               const double* beta, double* h_store, double* sc_store) {
+  const double h = sqrt(load_reduced<false>(pin, nin));
+  const double s = (h > tol * (*beta)) ? 1.0 / h : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *h_store = h;
+    *sc_store = s;
+  }
+  return s;
+}
+
+// Column j: w = H~ q_j = s_j H~ Q_j (s_j from the norm partials pin of the
+// previous column, or 1 for j = 0 when pin == nullptr); stores the partials of
+// w . q_0 (the first Gram-Schmidt coefficient of the column).
 template <typename T, int K, int BC, int DIM>
 __global__ __launch_bounds__(kBlock) void k_kry_matvec(Geo<T, K, DIM> g, const T* __restrict__ q,
                                                        T* __restrict__ w,
                                                        const T* __restrict__ q0, KrySrc src,
                                                        const T* __restrict__ amp,
+                                                       const double* pin, int nin, double tol,
+                                                       const double* beta, double* h_store,
+                                                       double* sc_store,
                                                        double* __restrict__ pout) {
   const int64_t ns = (DIM + 1) * g.N;
   const int64_t items = g.N + src.p;
+  const double sj = pin ? column_scale(pin, nin, tol, beta, h_store, sc_store) : 1.0;
+  const T st = static_cast<T>(sj);
   double acc = 0.0;
   for (int64_t it = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; it < items;
        it += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -224,12 +250,13 @@ __global__ __launch_bounds__(kBlock) void k_kry_matvec(Geo<T, K, DIM> g, const T
 #pragma unroll
       for (int f = 0; f <= DIM; ++f) {
         const int64_t e = f * g.N + idx;
-        w[e] = o[f];
-        acc += static_cast<double>(o[f]) * static_cast<double>(q0[e]);
+        const T v = o[f] * st;
+        w[e] = v;
+        acc += static_cast<double>(v) * static_cast<double>(q0[e]);
       }
     } else {
       const int c = static_cast<int>(it - g.N);
-      const T val = (c + 1 < src.p) ? q[ns + c + 1] : T(0);  // J q_tail
+      const T val = (c + 1 < src.p) ? q[ns + c + 1] * st : T(0);  // J q_tail
       w[ns + c] = val;
       acc += static_cast<double>(val) * static_cast<double>(q0[ns + c]);
     }
@@ -237,58 +264,213 @@ __global__ __launch_bounds__(kBlock) void k_kry_matvec(Geo<T, K, DIM> g, const T
   store_partial<false>(acc, pout);
 }
 
-// Modified Gram-Schmidt update fused with the next dot:
-//   h = (reduced partials pin), stored to *h_store by block 0;
-//   w -= h q_i;  partials of w . qn into pout  (qn == nullptr: w . w)
+// Modified Gram-Schmidt step i of a column, fused with the next dot:
+//   h = (reduced partials pin) = w . q_i, stored to *h_store by block 0;
+//   w -= h q_i (q_i = sc[i] Q_i);
+//   partials of w . q_{i+1} (q_{i+1} = sc[i+1] Q_{i+1}) into pout, or of
+//   w . w when qn == nullptr (last step of the column).
+// The first chunk of w, Q_i, Q_{i+1} is loaded before the reduction of pin so
+// that the loads overlap it.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kry_mgs(T* __restrict__ w, const T* __restrict__ qi,
                                                     const T* __restrict__ qn, int64_t n,
                                                     const double* __restrict__ pin, int nin,
-                                                    double* h_store, double* __restrict__ pout) {
+                                                    double* h_store, const double* sc, int i_idx,
+                                                    double* __restrict__ pout) {
+  constexpr int UN = 8;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  int64_t base = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  T wv[UN], qv[UN], nv[UN];
+  auto load = [&](int64_t b0) {
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t idx = b0 + u * stride;
+      const bool ok = idx < n;
+      wv[u] = ok ? w[idx] : T(0);
+      qv[u] = ok ? qi[idx] : T(0);
+      nv[u] = (ok && qn) ? qn[idx] : T(0);
+    }
+  };
+  load(base);
   const double h = load_reduced<false>(pin, nin);
   if (blockIdx.x == 0 && threadIdx.x == 0) *h_store = h;
+  const double hs = h * sc[i_idx];
+  const double sn = qn ? sc[i_idx + 1] : 1.0;
   double acc = 0.0;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const T wt = static_cast<T>(static_cast<double>(w[i]) - h * static_cast<double>(qi[i]));
-    w[i] = wt;
-    const double o = qn ? static_cast<double>(qn[i]) : static_cast<double>(wt);
-    acc += static_cast<double>(wt) * o;
+  while (true) {
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t idx = base + u * stride;
+      if (idx < n) {
+        const T wt = static_cast<T>(static_cast<double>(wv[u]) - hs * static_cast<double>(qv[u]));
+        w[idx] = wt;
+        acc += static_cast<double>(wt) * (qn ? sn * static_cast<double>(nv[u]) : static_cast<double>(wt));
+      }
+    }
+    base += UN * stride;
+    if (base >= n) break;
+    load(base);
   }
   store_partial<false>(acc, pout);
 }
 
-// q_{j+1} = w / h with h = |w| (reduced from the partials of w . w); a column with h <= tol * beta is a
-// breakdown: it is zeroed and the host truncates the basis there.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_kry_normalize(T* __restrict__ w, int64_t n,
-                                                          const double* __restrict__ pin, int nin,
-                                                          double* h_out, const double* beta,
-                                                          double tol) {
-  const double h = sqrt(load_reduced<false>(pin, nin));
-  const double sc = (h > tol * (*beta)) ? 1.0 / h : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *h_out = h;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kBlock)
-    w[i] = static_cast<T>(static_cast<double>(w[i]) * sc);
+// After the last column: h_{k,k-1} and s_k from the norm partials (one block).
+__global__ __launch_bounds__(kBlock) void k_kry_finish(const double* pin, int nin, double tol,
+                                                       const double* beta, double* h_store,
+                                                       double* sc_store) {
+  (void)column_scale(pin, nin, tol, beta, h_store, sc_store);
 }
 
 struct KryCoef {
   double y[64];
 };
 
-// S = beta sum_{c < keff} y_c Q_c (state part)
+// S = beta sum_{c < keff} y_c q_c (state part), q_c = sc[c] Q_c; y, keff and
+// beta from the host
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kry_combine(T* __restrict__ S,
                                                         const T* __restrict__ Q, int64_t ldq,
                                                         int64_t ns, int32_t keff, KryCoef y,
-                                                        double beta) {
+                                                        double beta, const double* sc) {
+  __shared__ double ys[64];
+  if (threadIdx.x < 64) ys[threadIdx.x] = (threadIdx.x < keff) ? y.y[threadIdx.x] * sc[threadIdx.x] : 0.0;
+  __syncthreads();
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < ns;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     double acc = 0.0;
-    for (int c = 0; c < keff; ++c) acc += y.y[c] * static_cast<double>(Q[c * ldq + i]);
+    for (int c = 0; c < keff; ++c) acc += ys[c] * static_cast<double>(Q[c * ldq + i]);
     S[i] = static_cast<T>(beta * acc);
   }
+}
+
+// The same with y, keff and beta read from device memory (written by k_kry_expm)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kry_combine_dev(T* __restrict__ S,
+                                                            const T* __restrict__ Q, int64_t ldq,
+                                                            int64_t ns, const double* y_dev,
+                                                            const int* keff_dev,
+                                                            const double* beta_dev,
+                                                            const double* sc) {
+  __shared__ double y[64];
+  const int keff = *keff_dev;
+  const double beta = *beta_dev;
+  if (threadIdx.x < 64) y[threadIdx.x] = (threadIdx.x < keff) ? y_dev[threadIdx.x] * sc[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < ns;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    double acc = 0.0;
+    for (int c = 0; c < keff; ++c) acc += y[c] * static_cast<double>(Q[c * ldq + i]);
+    S[i] = static_cast<T>(beta * acc);
+  }
+}
+
+// C = A B for keff x keff matrices in LDS (leading dimension LD), one
+// workgroup; ends with a barrier.
+template <int LD>
+__device__ __forceinline__ void lds_matmul(const double* A, const double* B, double* C, int n) {
+  for (int e = threadIdx.x; e < n * n; e += kBlock) {
+    const int r = e / n, c = e - r * n;
+    double acc = 0.0;
+    for (int l = 0; l < n; ++l) acc += A[r * LD + l] * B[l * LD + c];
+    C[r * LD + c] = acc;
+  }
+  __syncthreads();
+}
+
+// y = exp(dt H_keff) e_1 in FP64 on one workgroup, with keff the Krylov
+// dimension after the breakdown test h_{j+1,j} <= tol * beta (the leading
+// keff x keff block of the upper Hessenberg matrix is used, ld = 64).
+// Scaling and squaring: A = dt H / 2^s with |A|_1 <= 1/2, the degree-16
+// Taylor polynomial by Horner's rule (truncation below 2^-17 / 17!), then s
+// squarings; y is the first column. The number of products is bounded by
+// 15 + s with s <= 1100 for any finite matrix; a non-finite matrix yields NaN.
+// (The augmented source block makes |dt H_k| large, of order dt |W|, so the
+// squarings are what keeps the cost logarithmic in the norm.)
+__global__ __launch_bounds__(kBlock) void k_kry_expm(const double* __restrict__ hess, int k,
+                                                     double dt, double tol,
+                                                     const double* __restrict__ beta_p,
+                                                     double* __restrict__ y_out,
+                                                     int* __restrict__ keff_out) {
+  constexpr int LD = 65;
+  __shared__ double A[64 * LD], T[64 * LD], W[64 * LD];
+  __shared__ double cs[64];
+  __shared__ int s_keff, s_sq;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    const double beta = *beta_p;
+    int ke = k;
+    if (!(beta > 0.0)) {
+      ke = 0;
+    } else {
+      for (int j = 0; j < k; ++j)
+        if (!(hess[(j + 1) * 64 + j] > tol * beta)) {
+          ke = j + 1;
+          break;
+        }
+    }
+    s_keff = ke;
+  }
+  __syncthreads();
+  const int n = s_keff;
+  for (int e = tid; e < n * n; e += kBlock) {
+    const int r = e / n, c = e - r * n;
+    A[r * LD + c] = (r <= c + 1) ? dt * hess[r * 64 + c] : 0.0;
+  }
+  __syncthreads();
+  if (tid < n) {
+    double sc = 0.0;
+    for (int r = 0; r < n; ++r) sc += fabs(A[r * LD + tid]);
+    cs[tid] = sc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double nm = 0.0;
+    for (int c = 0; c < n; ++c) nm = fmax(nm, cs[c]);
+    int sq = -1;  // -1: non-finite
+    if (isfinite(nm)) {
+      sq = 0;
+      while (nm > 0.5 && sq < 1100) {
+        nm *= 0.5;
+        ++sq;
+      }
+    }
+    s_sq = sq;
+  }
+  __syncthreads();
+  const int sq = s_sq;
+  if (sq < 0) {
+    if (tid < 64) y_out[tid] = NAN;
+    if (tid == 0) *keff_out = n;
+    return;
+  }
+  const double scale = ldexp(1.0, -sq);
+  for (int e = tid; e < n * n; e += kBlock) {
+    const int r = e / n, c = e - r * n;
+    A[r * LD + c] *= scale;
+    T[r * LD + c] = (r == c ? 1.0 : 0.0) + A[r * LD + c] / 16.0;
+  }
+  __syncthreads();
+  // Horner: T <- I + A T / j for j = 15 .. 1
+  for (int j = 15; j >= 1; --j) {
+    lds_matmul<LD>(A, T, W, n);
+    const double inv = 1.0 / j;
+    for (int e = tid; e < n * n; e += kBlock) {
+      const int r = e / n, c = e - r * n;
+      T[r * LD + c] = (r == c ? 1.0 : 0.0) + W[r * LD + c] * inv;
+    }
+    __syncthreads();
+  }
+  // squarings, alternating between T and W
+  double* cur = T;
+  double* nxt = W;
+  for (int i = 0; i < sq; ++i) {
+    lds_matmul<LD>(cur, cur, nxt, n);
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  if (tid < 64) y_out[tid] = (tid < n) ? cur[tid * LD + 0] : 0.0;
+  if (tid == 0) *keff_out = n;
 }
 
 }  // namespace expw

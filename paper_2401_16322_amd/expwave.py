@@ -19,6 +19,7 @@ EXPW_OK, EXPW_EINVAL, EXPW_ENOMEM, EXPW_EDEVICE, EXPW_ENONFINITE, EXPW_EUNSUPPOR
 EXPW_F32, EXPW_F64 = 0, 1
 EXPW_BC_ZERO, EXPW_BC_PERIODIC = 0, 1
 EXPW_MAX_KRYLOV, EXPW_MAX_TAYLOR, EXPW_MAX_SOURCES = 64, 16, 64
+EXPW_EXPM_DEVICE, EXPW_EXPM_HOST = 0, 1
 
 
 class ExpwError(RuntimeError):
@@ -69,6 +70,7 @@ SIGNATURES = {
     "expw_step_leapfrog": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
     "expw_sync_status": (_i32, [_vp]),
     "expw_krylov_info": (_i32, [_vp, _pi32, _pd]),
+    "expw_set_krylov_expm": (_i32, [_vp, _i32]),
     "expw_set_timing": (_i32, [_vp, _i32]),
     "expw_get_timing": (_i32, [_vp, _pd, _pi64, _pd]),
 }
@@ -262,6 +264,10 @@ def expw_krylov_info(op):
     return k.value, b.value
 
 
+def expw_set_krylov_expm(op, mode):
+    _check(load().expw_set_krylov_expm(op, mode))
+
+
 def expw_set_timing(op, enable):
     _check(load().expw_set_timing(op, int(bool(enable))))
 
@@ -397,6 +403,10 @@ class Operator:
 
     def krylov_info(self):
         return expw_krylov_info(self.op)
+
+    def set_krylov_expm(self, mode):
+        """"device" (default) or "host" evaluation of the small exponential."""
+        expw_set_krylov_expm(self.op, EXPW_EXPM_HOST if mode == "host" else EXPW_EXPM_DEVICE)
 
     def set_timing(self, enable=True):
         self._sync_stream()

@@ -70,10 +70,12 @@ def test_faber_tiny_and_degenerate_grids(dtype, n):
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("mode", ["device", "host"])
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("k,src", [(1, True), (5, True), (20, True), (12, False)])
-def test_krylov_steps_match_oracle(dtype, k, src):
-    case = make_case((45, 33), dtype, src=src, seed=5, max_k=24)
+@pytest.mark.parametrize("k,src", [(1, True), (5, True), (20, True), (12, False), (40, True)])
+def test_krylov_steps_match_oracle(dtype, k, src, mode):
+    case = make_case((45, 33), dtype, src=src, seed=5, max_k=40)
+    case.op.set_krylov_expm(mode)
     dt, nst = 1e-3, 2
     U = to_dev(case, case.U0)
     case.op.step_krylov(U, 0.03, dt, k, nst)
