@@ -223,9 +223,10 @@ enum {
   EXPW_KERNEL_CLASSES = 8
 };
 
-/* Enable (1) or disable (0) per-launch timing with HIP events recorded on the
- * handle's stream around every kernel launch; also clears the totals. */
-int32_t expw_set_timing(expw_op* op, int32_t enable);
+/* Per-launch timing with HIP events recorded on the handle's stream around
+ * every launch of the kernel classes whose bit is set in class_mask (bit k =
+ * class k; 0 = off, -1 = all classes); also clears the totals. */
+int32_t expw_set_timing(expw_op* op, int32_t class_mask);
 
 /* Synchronizes and returns, per kernel class (arrays of EXPW_KERNEL_CLASSES
  * entries, any may be NULL), the summed kernel time in ms, the number of

@@ -178,7 +178,7 @@ double src_scale(const expw_op* op) { return 1.0 / std::pow(op->g.h, op->g.ndim)
 // Runs one launch bracketed by the profiler's events (a no-op when timing is off).
 template <class F>
 void timed(expw_op* op, int kind, double bytes, F&& launch) {
-  const int slot = op->prof.begin(op->stream);
+  const int slot = op->prof.begin(op->stream, kind);
   launch();
   op->prof.end(op->stream, slot, kind, bytes);
 }
@@ -780,9 +780,9 @@ int32_t expw_sync_status(expw_op* op) {
   return EXPW_OK;
 }
 
-int32_t expw_set_timing(expw_op* op, int32_t enable) {
+int32_t expw_set_timing(expw_op* op, int32_t class_mask) {
   if (int32_t rc = check_op(op)) return rc;
-  op->prof.enable(enable != 0);
+  op->prof.enable(static_cast<uint32_t>(class_mask));
   return EXPW_OK;
 }
 

@@ -18,8 +18,9 @@ class Profiler {
     for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
   }
 
-  void enable(bool on) {
-    on_ = on;
+  // mask: bit k enables timing of kernel class k (0 = off)
+  void enable(uint32_t mask) {
+    mask_ = mask;
     recs_.clear();
     used_ = 0;
     for (int k = 0; k < EXPW_KERNEL_CLASSES; ++k) {
@@ -29,9 +30,10 @@ class Profiler {
     }
   }
 
-  // Records a start event before a launch; returns its slot (-1 when off).
-  int begin(hipStream_t st) {
-    if (!on_) return -1;
+  // Records a start event before a launch of class kind; returns its slot
+  // (-1 when that class is not timed).
+  int begin(hipStream_t st, int kind) {
+    if (!(mask_ >> kind & 1u)) return -1;
     while (pool_.size() < used_ + 2) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -74,7 +76,7 @@ class Profiler {
     int slot;
     double bytes;
   };
-  bool on_ = false;
+  uint32_t mask_ = 0;
   std::vector<hipEvent_t> pool_;
   size_t used_ = 0;
   std::vector<Rec> recs_;

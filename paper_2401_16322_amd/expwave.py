@@ -268,8 +268,8 @@ def expw_set_krylov_expm(op, mode):
     _check(load().expw_set_krylov_expm(op, mode))
 
 
-def expw_set_timing(op, enable):
-    _check(load().expw_set_timing(op, int(bool(enable))))
+def expw_set_timing(op, class_mask):
+    _check(load().expw_set_timing(op, int(class_mask)))
 
 
 def expw_get_timing(op):
@@ -408,9 +408,17 @@ class Operator:
         """"device" (default) or "host" evaluation of the small exponential."""
         expw_set_krylov_expm(self.op, EXPW_EXPM_HOST if mode == "host" else EXPW_EXPM_DEVICE)
 
-    def set_timing(self, enable=True):
+    def set_timing(self, classes=None):
+        """Time every launch of the given kernel classes (names of KERNEL_CLASSES;
+        None = all, [] = off)."""
         self._sync_stream()
-        expw_set_timing(self.op, enable)
+        if classes is None:
+            mask = -1
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << KERNEL_CLASSES.index(c)
+        expw_set_timing(self.op, mask)
 
     def timing(self):
         return expw_get_timing(self.op)

@@ -82,6 +82,12 @@ WORKLOADS = {
         name="layered2d_1001x501", n=(1001, 501), h=10.0, abc_cells=40, sigma_max=300.0,
         f_peak=15.0, t_delay=0.18, T=2.0, src=(500, 42), medium="layered",
         seed=2000, faber_m=16, dt=2e-3, taylor_p=8, receivers="surface_row"),
+    # 8192x4096 layered: an added HBM-bound 2D shape (working set far above the
+    # 256 MB Infinity Cache), same generator and layer as the 1001x501 medium
+    "layered2d_8192x4096": Workload(
+        name="layered2d_8192x4096", n=(8192, 4096), h=10.0, abc_cells=40, sigma_max=300.0,
+        f_peak=15.0, t_delay=0.18, T=2.0, src=(4096, 42), medium="layered",
+        seed=2100, faber_m=16, dt=2e-3, taylor_p=8, receivers="surface_row"),
     # 256^3 layered, 20-cell layer, centre source, T = 1 s, Faber degree 24
     "layered3d_256": Workload(
         name="layered3d_256", n=(256, 256, 256), h=10.0, abc_cells=20, sigma_max=300.0,
