@@ -145,7 +145,7 @@ def main():
                    "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else None,
                    "GB_per_s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
                for k, v in kt_warm.items() if v[1]}
-    cls = {"faber": ["faber"], "krylov": ["krylov_matvec", "krylov_mgs", "krylov_aux"],
+    cls = {"faber": ["faber"], "krylov": ["krylov_matvec", "krylov_mgs", "krylov_aux", "krylov_arnoldi"],
            "rk4": ["rk4"], "leapfrog": ["leapfrog_v", "leapfrog_p"]}
     per_method = {}
     for m in methods:

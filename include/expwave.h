@@ -191,7 +191,9 @@ int32_t expw_step_rk4(expw_op* op, void* state_dev, double t0, double dt, int64_
 int32_t expw_step_leapfrog(expw_op* op, void* state_dev, double t0, double dt, int64_t nsteps,
                            void* traces_dev);
 
-/* Synchronizes the stream and reports a pending device error. */
+/* Synchronizes the stream and reports a pending device error (including a
+ * grid barrier of the persistent Arnoldi kernel that exceeded its bounded
+ * wait). */
 int32_t expw_sync_status(expw_op* op);
 
 /* Effective dimension and beta of the last Krylov step (host values;
@@ -208,6 +210,13 @@ int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta);
 enum { EXPW_EXPM_DEVICE = 0, EXPW_EXPM_HOST = 1 };
 int32_t expw_set_krylov_expm(expw_op* op, int32_t mode);
 
+/* allow = 1 (default): when the augmented vectors fit in registers across one
+ * cooperative grid, the Arnoldi process runs as one persistent launch (grid
+ * barriers between Gram-Schmidt steps); otherwise, and with allow = 0, one
+ * launch per matrix-vector product and per Gram-Schmidt step. Results agree
+ * to rounding. */
+int32_t expw_set_krylov_persistent(expw_op* op, int32_t allow);
+
 /* ------------------------------------------------------------------ timing */
 
 /* Kernel classes for expw_get_timing. */
@@ -220,7 +229,8 @@ enum {
   EXPW_KERNEL_LEAPFROG_V = 5,    /* leap-frog velocity update */
   EXPW_KERNEL_LEAPFROG_P = 6,    /* leap-frog pressure update */
   EXPW_KERNEL_GATHER = 7,        /* receiver gather */
-  EXPW_KERNEL_CLASSES = 8
+  EXPW_KERNEL_KRYLOV_ARNOLDI = 8, /* Arnoldi: the whole basis in one persistent launch */
+  EXPW_KERNEL_CLASSES = 9
 };
 
 /* Per-launch timing with HIP events recorded on the handle's stream around

@@ -115,18 +115,19 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Block-wide reduction; the result is valid in thread 0. Ends with a barrier
-// so that the shared scratch can be reused right away.
-template <bool MAX>
+// Block-wide reduction over NT threads; the result is valid in thread 0.
+// Ends with a barrier so that the shared scratch can be reused right away.
+template <bool MAX, int NT = kBlock>
 __device__ __forceinline__ double block_reduce(double v) {
-  __shared__ double sh[kBlock / 64];
+  static_assert(NT % 64 == 0 && NT <= 1024, "block of whole waves");
+  __shared__ double sh[NT / 64];
   v = MAX ? wave_max(v) : wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   double r = MAX ? -INFINITY : 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < kBlock / 64; ++i) r = MAX ? fmax(r, sh[i]) : r + sh[i];
+    for (int i = 0; i < NT / 64; ++i) r = MAX ? fmax(r, sh[i]) : r + sh[i];
   __syncthreads();
   return r;
 }

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <vector>
 
+#include "arnoldi.h"
 #include "fused.h"
 #include "internal.h"
 #include "kernels.h"
@@ -24,7 +25,7 @@ struct expw_op {
   int kmax, pmax;
   // workspace layout (byte offsets)
   size_t off_sig[3][2];
-  size_t off_src_idx, off_src_amp, off_part, off_scal, off_hess, off_kry, off_big;
+  size_t off_src_idx, off_src_amp, off_part, off_scal, off_hess, off_kry, off_bar, off_big;
   int64_t naug_pad;  // stride of a Krylov basis vector (elements)
   // spectrum and ellipse (host FP64)
   double c2max, x_lo, B, gamma, c0, c1;
@@ -42,6 +43,8 @@ struct expw_op {
   int fuse, tile_x, tile_y;
   // Krylov: small exponential on the device (0) or the host (1); last step info
   int kry_mode;
+  int kry_persistent;  // 1: allow the persistent Arnoldi kernel
+  int coop_blocks;     // co-resident blocks of the persistent kernel (0 = unknown)
   int last_keff;
   double last_beta;
   expw::Profiler prof;
@@ -77,7 +80,7 @@ int32_t validate_grid(const expw_grid* g) {
 
 struct Layout {
   size_t sig[3][2];
-  size_t src_idx, src_amp, part, scal, hess, kry, big, total;
+  size_t src_idx, src_amp, part, scal, hess, kry, bar, big, total;
   int64_t naug_pad;
 };
 
@@ -96,6 +99,7 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
   L.scal = off; off = align_up(off + 64 * sizeof(double));
   L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
   L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
+  L.bar = off; off = align_up(off + 1024 * sizeof(unsigned));  // grid barrier words
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -175,21 +179,11 @@ unsigned red_grid_for(int64_t n) {
 
 double src_scale(const expw_op* op) { return 1.0 / std::pow(op->g.h, op->g.ndim); }
 
-// Runs one launch bracketed by the profiler's events (a no-op when timing is off).
-template <class F>
-void timed(expw_op* op, int kind, double bytes, F&& launch) {
-  const int slot = op->prof.begin(op->stream, kind);
-  launch();
-  op->prof.end(op->stream, slot, kind, bytes);
-}
 
 template <typename T>
 int32_t gather(expw_op* op, const T* S, T* traces, int64_t step) {
   if (!traces || op->n_rec == 0) return EXPW_OK;
-  timed(op, EXPW_KERNEL_GATHER, op->n_rec * (2.0 * sizeof(T) + 8.0), [&] {
-    k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec,
-                                                                   traces + step * op->n_rec);
-  });
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_GATHER, op->n_rec * (2.0 * sizeof(T) + 8.0), k_gather<T>, dim3(grid_for(op->n_rec)), dim3(kBlock), S, op->rec_dev, op->n_rec, traces + step * op->n_rec);
   return check_launch("gather");
 }
 
@@ -211,10 +205,7 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, T* S, T* Abuf, T* Bb
   const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
   // words per point: reads v_{j-1} (nf) + c^2 (1) [+ v_{j-2} (nf) + sum (nf)],
   // writes the sum (nf) [+ v_j (nf)]
-  timed(op, EXPW_KERNEL_FABER, (nf + 1 + nf + (m == 1 ? 0 : nf)) * pb, [&] {
-    k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, nullptr, m == 1 ? nullptr : Abuf,
-                                                                 nullptr, Cbuf, c, make_src<T>(op, q[0]));
-  });
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1 + nf + (m == 1 ? 0 : nf)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, nullptr, m == 1 ? nullptr : Abuf, nullptr, Cbuf, c, make_src<T>(op, q[0]));
   if (m == 1) {
     if (hipMemcpyAsync(S, Cbuf, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
       return fail(EXPW_EDEVICE, "faber: copy failed");
@@ -225,20 +216,14 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, T* S, T* Abuf, T* Bb
   c.a_first = T(0);
   c.cpp = static_cast<T>(2.0 * op->c1);
   c.a_j = static_cast<T>(a[2]);
-  timed(op, EXPW_KERNEL_FABER, (4 * nf + 1 + (m == 2 ? 0 : nf)) * pb, [&] {
-    k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(
-        g, Abuf, S, m == 2 ? nullptr : Bbuf, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
-  });
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (m == 2 ? 0 : nf)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, S, m == 2 ? nullptr : Bbuf, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
   T* last = Bbuf;   // v_{j-1}
   T* older = Abuf;  // v_{j-2}
   c.cpp = static_cast<T>(op->c1);
   for (int j = 3; j <= m; ++j) {
     c.a_j = static_cast<T>(a[j]);
     const bool fin = (j == m);
-    timed(op, EXPW_KERNEL_FABER, (4 * nf + 1 + (fin ? 0 : nf)) * pb, [&] {
-      k_faber_term<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(
-          g, last, older, fin ? nullptr : older, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
-    });
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (fin ? 0 : nf)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, last, older, fin ? nullptr : older, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
     std::swap(last, older);
   }
   return check_launch("faber term");
@@ -276,10 +261,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
           c.c0 = static_cast<T>(op->c0);
           c.cpp = static_cast<T>(op->c1);
           c.a_j = static_cast<T>(a[j]);
-          timed(op, EXPW_KERNEL_FABER, 13.0 * g.N * sizeof(T), [&] {
-            k_faber_term<T, K, BC, DIM><<<grid_for(g.N), kBlock, 0, op->stream>>>(
-                g, vl, vpv, nullptr, acc, out, c, make_src<T>(op, q[j - 1]));
-          });
+          launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, 13.0 * g.N * sizeof(T), k_faber_term<T, K, BC, DIM>, dim3(grid_for(g.N)), dim3(kBlock), g, vl, vpv, nullptr, acc, out, c, make_src<T>(op, q[j - 1]));
           return check_launch("faber final term");
         };
         rc = faber_fused_2d<T>(op->stream, &op->prof, g, make_src<T>(op, 0.0), S, Abuf, Bbuf, Cbuf,
@@ -321,18 +303,10 @@ int32_t rk4_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T* tra
     const double t = t0 + st * dt;
     // words per point: stage 1 reads u (nf) + c^2, writes y, sum (2 nf); stages 2-3 read
     // y, u, sum (3 nf) + c^2, write y, sum (2 nf); stage 4 reads y, sum + c^2, writes u
-    timed(op, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, [&] {
-      k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, S, nullptr, Abuf, Cbuf, h2, s6, srcq(t));
-    });
-    timed(op, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, [&] {
-      k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Abuf, S, Cbuf, Bbuf, Cbuf, h2, s3, srcq(t + 0.5 * dt));
-    });
-    timed(op, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, [&] {
-      k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Bbuf, S, Cbuf, Abuf, Cbuf, h1, s3, srcq(t + 0.5 * dt));
-    });
-    timed(op, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, [&] {
-      k_rk4_stage<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, Abuf, nullptr, Cbuf, nullptr, S, T(0), s6, srcq(t + dt));
-    });
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, S, nullptr, Abuf, Cbuf, h2, s6, srcq(t));
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, S, Cbuf, Bbuf, Cbuf, h2, s3, srcq(t + 0.5 * dt));
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Bbuf, S, Cbuf, Abuf, Cbuf, h1, s3, srcq(t + 0.5 * dt));
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, nullptr, Cbuf, nullptr, S, T(0), s6, srcq(t + dt));
     int32_t rc = check_launch("rk4 stage");
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
@@ -350,17 +324,13 @@ int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     // velocity: reads p and v (1 + d), writes v (d); pressure: reads p, v, c^2 (d + 2), writes p
-    timed(op, EXPW_KERNEL_LEAPFROG_V, (1 + 2 * DIM) * pb, [&] {
-      k_lf_v<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, static_cast<T>(dt));
-    });
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_LEAPFROG_V, (1 + 2 * DIM) * pb, k_lf_v<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, static_cast<T>(dt));
     double q = 0.0;
     if (op->n_src > 0) {
       ricker_derivatives(t + 0.5 * dt, op->f_peak, op->t_delay, 1, der);
       q = dt * der[0] * sc;
     }
-    timed(op, EXPW_KERNEL_LEAPFROG_P, (DIM + 3) * pb, [&] {
-      k_lf_p<T, K, BC, DIM><<<grid, kBlock, 0, op->stream>>>(g, S, static_cast<T>(dt), make_src<T>(op, q));
-    });
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_LEAPFROG_P, (DIM + 3) * pb, k_lf_p<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, static_cast<T>(dt), make_src<T>(op, q));
     int32_t rc = check_launch("leapfrog");
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
@@ -369,6 +339,73 @@ int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T
 }
 
 // ---------------------------------------------------------------- Krylov step
+
+// Elements per thread of the persistent Arnoldi kernel for this problem (0 =
+// use the launch-per-step path): the augmented vector must fit in UN
+// registers per thread over all co-resident blocks.
+template <typename T, int K, int BC, int DIM>
+int persistent_un(expw_op* op, int64_t naug) {
+  if (!op->kry_persistent) return 0;
+  if (op->coop_blocks == 0) {
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 8>), kArnNT, 0) !=
+            hipSuccess ||
+        !coop || per_cu < 1) {
+      op->coop_blocks = -1;
+    } else {
+      op->coop_blocks = std::min(256, cus * per_cu);
+    }
+  }
+  if (op->coop_blocks <= 0) return 0;
+  const int64_t threads = static_cast<int64_t>(op->coop_blocks) * kArnNT;
+  for (int un : {2, 4, 8})
+    if (naug <= un * threads) return un;
+  return 0;
+}
+
+template <typename T, int K, int BC, int DIM>
+int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T* S, T* Q,
+                           const KrySrc& ks, const T* amp, int64_t ns, int64_t naug, int64_t ld,
+                           int k, double tail2, double tol, double* part, unsigned* bar, int* err,
+                           double* hess, double* sc, double* beta_out) {
+  ArnArgs aa{};
+  aa.ns = ns;
+  aa.naug = naug;
+  aa.ld = ld;
+  aa.k = k;
+  aa.tail2 = tail2;
+  aa.tol = tol;
+  aa.spin_limit = 1u << 20;  // about a second of polling
+  k_zero_u32<<<4, 256, 0, op->stream>>>(bar, op->coop_blocks);
+  Geo<T, K, DIM> gg = g;
+  const T* Sp = S;
+  T* Qp = Q;
+  KrySrc kk = ks;
+  const T* ap = amp;
+  void* args[] = {&gg, &Sp, &Qp, &kk, &ap, &aa, &part, &bar, &err, &hess, &sc, &beta_out};
+  const void* fn = nullptr;
+  if (un == 2) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2>);
+  else if (un == 4) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 4>);
+  else fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 8>);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int slot = op->prof.acquire(EXPW_KERNEL_KRYLOV_ARNOLDI, &e0, &e1);
+  if (slot >= 0) (void)hipEventRecord(e0, op->stream);
+  const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(op->coop_blocks), dim3(kArnNT), args, 0,
+                                                  op->stream);
+  if (slot >= 0) {
+    (void)hipEventRecord(e1, op->stream);
+    // reads S; per column: Q_j with its stencil and c^2, Q_1..Q_j; writes Q_0..Q_k
+    const double es = sizeof(T);
+    const double words = ns + naug + k * (2.0 * naug + g.N) + naug * (k * (k - 1) / 2.0);
+    op->prof.commit(slot, EXPW_KERNEL_KRYLOV_ARNOLDI, words * es);
+  }
+  if (e != hipSuccess) return fail(EXPW_EDEVICE, "persistent Arnoldi launch: %s", hipGetErrorString(e));
+  return EXPW_OK;
+}
 
 template <typename T, int K, int BC, int DIM>
 int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nsteps, T* traces) {
@@ -388,6 +425,9 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
   double* kry_y = reinterpret_cast<double*>(op->ws + op->off_kry);
   double* kry_sc = kry_y + 64;
   int* kry_keff = reinterpret_cast<int*>(op->ws + op->off_kry + 136 * sizeof(double));
+  unsigned* kry_bar = reinterpret_cast<unsigned*>(op->ws + op->off_bar);
+  int* kry_err = kry_keff + 8;
+  const int unp = persistent_un<T, K, BC, DIM>(op, naug);
   const double tol = 1e-14;
   std::vector<double> hh((EXPW_MAX_KRYLOV + 1) * kHessLd), hk(k * k), E(k * k), der(EXPW_MAX_TAYLOR);
   std::vector<double> scal_h(2);
@@ -404,55 +444,42 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
       const double sc = src_scale(op);
       for (int c = 0; c < p; ++c) ks.G[c] = der[p - 1 - c] * sc;
     }
-    // q_1 = [S; e_p] / beta
-    double* P[2] = {part, part + kRedMaxBlocks};
-    const unsigned nb_ns = red_grid_for(ns);
-    timed(op, EXPW_KERNEL_KRYLOV_AUX, ns * es, [&] {
-      k_norm2<T><<<nb_ns, kBlock, 0, op->stream>>>(S, ns, P[0]);
-    });
-    timed(op, EXPW_KERNEL_KRYLOV_AUX, (ns + naug) * es, [&] {
-      k_kry_init<T><<<red_grid_for(naug), kBlock, 0, op->stream>>>(S, ns, Q, naug, P[0], nb_ns,
-                                                                      p > 0 ? 1.0 : 0.0, scal + 1, kry_sc);
-    });
-    // P[c] holds the partials of the latest reduction, produced by nin blocks
-    int c = 0, nin = 0;
-    for (int j = 0; j < k; ++j) {
-      T* w = Q + (j + 1) * ld;
-      // reads Q_j (with tail), q_1 and c^2, writes w
-      timed(op, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * naug + g.N) * es, [&] {
-        k_kry_matvec<T, K, BC, DIM><<<rg_pts, kBlock, 0, op->stream>>>(
-            g, Q + j * ld, w, Q, ks, amp, j == 0 ? nullptr : P[c], nin, tol, scal + 1,
-            j == 0 ? nullptr : hess + j * kHessLd + (j - 1), kry_sc + j, P[c ^ 1]);
-      });
-      c ^= 1;
-      nin = static_cast<int>(rg_pts);
-      for (int i = 0; i <= j; ++i) {
-        const bool lastc = (i == j);
-        // reads w, Q_i [, Q_{i+1}], writes w
-        timed(op, EXPW_KERNEL_KRYLOV_MGS, (lastc ? 3.0 : 4.0) * naug * es, [&] {
-          k_kry_mgs<T><<<rg_vec, kBlock, 0, op->stream>>>(w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld,
-                                                          naug, P[c], nin, hess + i * kHessLd + j, kry_sc, i,
-                                                          P[c ^ 1]);
-        });
+    if (unp > 0) {
+      // the whole Arnoldi process in one cooperative launch
+      int32_t rc = arnoldi_persistent<T, K, BC, DIM>(op, unp, g, S, Q, ks, amp, ns, naug, ld, k,
+                                                     p > 0 ? 1.0 : 0.0, tol, part, kry_bar, kry_err,
+                                                     hess, kry_sc, scal + 1);
+      if (rc != EXPW_OK) return rc;
+    } else {
+      // q_1 = [S; e_p] / beta
+      double* P[2] = {part, part + kRedMaxBlocks};
+      const unsigned nb_ns = red_grid_for(ns);
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, ns * es, k_norm2<T>, dim3(nb_ns), dim3(kBlock), S, ns, P[0]);
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (ns + naug) * es, k_kry_init<T>, dim3(red_grid_for(naug)), dim3(kBlock), S, ns, Q, naug, P[0], nb_ns, p > 0 ? 1.0 : 0.0, scal + 1, kry_sc);
+      // P[c] holds the partials of the latest reduction, produced by nin blocks
+      int c = 0, nin = 0;
+      for (int j = 0; j < k; ++j) {
+        T* w = Q + (j + 1) * ld;
+        // reads Q_j (with tail), q_1 and c^2, writes w
+        launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * naug + g.N) * es, k_kry_matvec<T, K, BC, DIM>, dim3(rg_pts), dim3(kBlock), g, Q + j * ld, w, Q, ks, amp, j == 0 ? nullptr : P[c], nin, tol, scal + 1, j == 0 ? nullptr : hess + j * kHessLd + (j - 1), kry_sc + j, P[c ^ 1]);
         c ^= 1;
-        nin = static_cast<int>(rg_vec);
+        nin = static_cast<int>(rg_pts);
+        for (int i = 0; i <= j; ++i) {
+          const bool lastc = (i == j);
+          // reads w, Q_i [, Q_{i+1}], writes w
+          launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MGS, (lastc ? 3.0 : 4.0) * naug * es, k_kry_mgs<T>, dim3(rg_vec), dim3(kBlock), w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld, naug, P[c], nin, hess + i * kHessLd + j, kry_sc, i, P[c ^ 1]);
+          c ^= 1;
+          nin = static_cast<int>(rg_vec);
+        }
       }
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, k_kry_finish, dim3(1), dim3(kBlock), P[c], nin, tol, scal + 1, hess + k * kHessLd + (k - 1), kry_sc + k);
     }
-    timed(op, EXPW_KERNEL_KRYLOV_AUX, 0.0, [&] {
-      k_kry_finish<<<1, kBlock, 0, op->stream>>>(P[c], nin, tol, scal + 1, hess + k * kHessLd + (k - 1),
-                                                 kry_sc + k);
-    });
     int32_t rc = check_launch("arnoldi");
     if (rc != EXPW_OK) return rc;
     if (op->kry_mode == EXPW_EXPM_DEVICE) {
       // y = exp(dt H_k) e_1 and the combination without leaving the device
-      timed(op, EXPW_KERNEL_KRYLOV_AUX, 0.0, [&] {
-        k_kry_expm<<<1, kBlock, 0, op->stream>>>(hess, k, dt, tol, scal + 1, kry_y, kry_keff);
-      });
-      timed(op, EXPW_KERNEL_KRYLOV_AUX, (k + 1.0) * ns * es, [&] {
-        k_kry_combine_dev<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, kry_y, kry_keff,
-                                                                          scal + 1, kry_sc);
-      });
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, k_kry_expm, dim3(1), dim3(kBlock), hess, k, dt, tol, scal + 1, kry_y, kry_keff);
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (k + 1.0) * ns * es, k_kry_combine_dev<T>, dim3(red_grid_for(ns)), dim3(kBlock), S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc);
       op->last_keff = -1;  // on the device; read by expw_krylov_info
       if ((rc = check_launch("krylov exponential")) != EXPW_OK) return rc;
     } else {
@@ -480,9 +507,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
         if (!expm(keff, hk.data(), E.data())) return fail(EXPW_ENONFINITE, "krylov: non-finite Hessenberg matrix");
         KryCoef y{};
         for (int r = 0; r < keff; ++r) y.y[r] = E[r * keff + 0];
-        timed(op, EXPW_KERNEL_KRYLOV_AUX, (keff + 1.0) * ns * es, [&] {
-          k_kry_combine<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, keff, y, beta, kry_sc);
-        });
+        launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (keff + 1.0) * ns * es, k_kry_combine<T>, dim3(red_grid_for(ns)), dim3(kBlock), S, Q, ld, ns, keff, y, beta, kry_sc);
         if ((rc = check_launch("krylov combine")) != EXPW_OK) return rc;
       }
     }
@@ -554,6 +579,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->off_scal = L.scal;
   op->off_hess = L.hess;
   op->off_kry = L.kry;
+  op->off_bar = L.bar;
   op->off_big = L.big;
   op->naug_pad = L.naug_pad;
   op->n_src = 0;
@@ -563,6 +589,8 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->fuse = 0;
   op->tile_x = op->tile_y = 0;
   op->kry_mode = EXPW_EXPM_DEVICE;
+  op->kry_persistent = 1;
+  op->coop_blocks = 0;
   op->last_keff = 0;
   op->last_beta = 0.0;
 
@@ -585,6 +613,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
       }
       staging.push_back(std::move(buf));
     }
+  k_zero_u32<<<1, 64, 0, op->stream>>>(reinterpret_cast<unsigned*>(op->ws + L.kry + 136 * sizeof(double)), 64);
   double* part = reinterpret_cast<double*>(op->ws + L.part);
   const int64_t N = npts(*g);
   const unsigned nb = red_grid_for(N);
@@ -777,6 +806,11 @@ int32_t expw_sync_status(expw_op* op) {
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e));
   const hipError_t e2 = hipGetLastError();
   if (e2 != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e2));
+  int err = 0;
+  const char* flag = op->ws + op->off_kry + 136 * sizeof(double) + 8 * sizeof(int);
+  if (hipMemcpy(&err, flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(EXPW_EDEVICE, "status read failed");
+  if (err) return fail(EXPW_EDEVICE, "a grid barrier of the persistent Arnoldi kernel timed out");
   return EXPW_OK;
 }
 
@@ -816,6 +850,12 @@ int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta) {
     return fail(EXPW_EDEVICE, "krylov info: copy failed");
   *k_eff = ke;
   *beta = b;
+  return EXPW_OK;
+}
+
+int32_t expw_set_krylov_persistent(expw_op* op, int32_t allow) {
+  if (int32_t rc = check_op(op)) return rc;
+  op->kry_persistent = allow != 0;
   return EXPW_OK;
 }
 

@@ -236,10 +236,9 @@ int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<
   // algorithmic words per point: v_{j-1} (3), c^2 (1), and unless first v_{j-2}
   // and the partial sum (3 + 3); writes: the sum (3), and unless last the pair (3 + 3)
   const double words = 3 + 1 + (first ? 0 : 6) + 3 + (out_last ? 6 : 0);
-  const int slot = prof->begin(st, EXPW_KERNEL_FABER);
-  k_faber_fused2d<T, S, kFusedTX, kFusedTY, kFusedNT><<<blocks, kFusedNT, 0, st>>>(
-      g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src);
-  prof->end(st, slot, EXPW_KERNEL_FABER, words * g.N * sizeof(T));
+  launch_timed(prof, st, EXPW_KERNEL_FABER, words * g.N * sizeof(T),
+               k_faber_fused2d<T, S, kFusedTX, kFusedTY, kFusedNT>, dim3(blocks), dim3(kFusedNT), g,
+               vp, vpp, acc_in, out_last, out_prev, acc_out, c, src);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "fused Faber pass: %s", hipGetErrorString(e));
   return EXPW_OK;

@@ -3,6 +3,7 @@
 // array counted once per launch, halos not counted).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -30,9 +31,10 @@ class Profiler {
     }
   }
 
-  // Records a start event before a launch of class kind; returns its slot
-  // (-1 when that class is not timed).
-  int begin(hipStream_t st, int kind) {
+  // A start/stop event pair for the next launch of class kind, to be attached
+  // to the dispatch itself; returns its slot (-1 when that class is not timed).
+  int acquire(int kind, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
     if (!(mask_ >> kind & 1u)) return -1;
     while (pool_.size() < used_ + 2) {
       hipEvent_t e;
@@ -41,14 +43,13 @@ class Profiler {
     }
     const int slot = static_cast<int>(used_);
     used_ += 2;
-    (void)hipEventRecord(pool_[slot], st);
+    *e0 = pool_[slot];
+    *e1 = pool_[slot + 1];
     return slot;
   }
 
-  void end(hipStream_t st, int slot, int kind, double bytes) {
-    if (slot < 0) return;
-    (void)hipEventRecord(pool_[slot + 1], st);
-    recs_.push_back({kind, slot, bytes});
+  void commit(int slot, int kind, double bytes) {
+    if (slot >= 0) recs_.push_back({kind, slot, bytes});
   }
 
   // Waits for the recorded launches and folds them into the per-class totals.
@@ -84,5 +85,22 @@ class Profiler {
   double bytes_[EXPW_KERNEL_CLASSES] = {};
   int64_t launches_[EXPW_KERNEL_CLASSES] = {};
 };
+
+// Launches kernel on stream st. When kind is a timed class, the profiler's
+// events are attached to the dispatch (hipExtLaunchKernel), so they hold the
+// kernel's own start and end times.
+// Launch errors surface through hipGetLastError() at the caller's next check.
+template <typename F, typename... Args>
+void launch_timed(Profiler* prof, hipStream_t st, int kind, double bytes, F kernel, dim3 grid,
+                  dim3 block, Args... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int slot = prof ? prof->acquire(kind, &e0, &e1) : -1;
+  if (slot < 0) {
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    return;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+  prof->commit(slot, kind, bytes);
+}
 
 }  // namespace expw

@@ -71,12 +71,13 @@ SIGNATURES = {
     "expw_sync_status": (_i32, [_vp]),
     "expw_krylov_info": (_i32, [_vp, _pi32, _pd]),
     "expw_set_krylov_expm": (_i32, [_vp, _i32]),
+    "expw_set_krylov_persistent": (_i32, [_vp, _i32]),
     "expw_set_timing": (_i32, [_vp, _i32]),
     "expw_get_timing": (_i32, [_vp, _pd, _pi64, _pd]),
 }
 
 KERNEL_CLASSES = ("faber", "krylov_matvec", "krylov_mgs", "krylov_aux", "rk4",
-                  "leapfrog_v", "leapfrog_p", "gather")
+                  "leapfrog_v", "leapfrog_p", "gather", "krylov_arnoldi")
 
 _lib = None
 
@@ -268,6 +269,10 @@ def expw_set_krylov_expm(op, mode):
     _check(load().expw_set_krylov_expm(op, mode))
 
 
+def expw_set_krylov_persistent(op, allow):
+    _check(load().expw_set_krylov_persistent(op, int(bool(allow))))
+
+
 def expw_set_timing(op, class_mask):
     _check(load().expw_set_timing(op, int(class_mask)))
 
@@ -407,6 +412,9 @@ class Operator:
     def set_krylov_expm(self, mode):
         """"device" (default) or "host" evaluation of the small exponential."""
         expw_set_krylov_expm(self.op, EXPW_EXPM_HOST if mode == "host" else EXPW_EXPM_DEVICE)
+
+    def set_krylov_persistent(self, allow=True):
+        expw_set_krylov_persistent(self.op, allow)
 
     def set_timing(self, classes=None):
         """Time every launch of the given kernel classes (names of KERNEL_CLASSES;
