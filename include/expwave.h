@@ -154,10 +154,10 @@ int32_t expw_get_ellipse(const expw_op* op, double* gamma, double* c0, double* c
 int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
 
 /* Kernel tuning for the Faber step: fuse = recurrence terms per HBM sweep
- * (0 = automatic, 1 = one term per sweep, up to 8), tile_x/tile_y = output
- * tile of the fused kernel (0 = automatic). Results do not depend on these
- * beyond rounding order. */
-int32_t expw_set_tuning(expw_op* op, int32_t fuse, int32_t tile_x, int32_t tile_y);
+ * (0 = automatic, 1 = one term per sweep, up to 8; 2D FP32 takes up to 8,
+ * 2D FP64 up to 4, 3D runs one term per sweep). The fused kernel's tile
+ * follows the depth. Results do not depend on it beyond rounding order. */
+int32_t expw_set_tuning(expw_op* op, int32_t fuse);
 
 /* y = H x (no source), x and y device state arrays (must not alias). */
 int32_t expw_apply(expw_op* op, const void* x_dev, void* y_dev);

@@ -40,7 +40,7 @@ struct expw_op {
   int n_rec;
   const int64_t* rec_dev;
   // tuning
-  int fuse, tile_x, tile_y;
+  int fuse;
   // Krylov: small exponential on the device (0) or the host (1); last step info
   int kry_mode;
   int kry_persistent;  // 1: allow the persistent Arnoldi kernel
@@ -587,7 +587,6 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->rec_dev = nullptr;
   op->taylor_p = std::max(1, std::min(8, max_p));
   op->fuse = 0;
-  op->tile_x = op->tile_y = 0;
   op->kry_mode = EXPW_EXPM_DEVICE;
   op->kry_persistent = 1;
   op->coop_blocks = 0;
@@ -679,14 +678,10 @@ int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1) {
   return EXPW_OK;
 }
 
-int32_t expw_set_tuning(expw_op* op, int32_t fuse, int32_t tile_x, int32_t tile_y) {
+int32_t expw_set_tuning(expw_op* op, int32_t fuse) {
   if (int32_t rc = check_op(op)) return rc;
   if (fuse < 0 || fuse > kMaxFuse) return fail(EXPW_EINVAL, "fuse must be in [0, %d]", kMaxFuse);
-  if (tile_x < 0 || tile_y < 0) return fail(EXPW_EINVAL, "tiles must be >= 0");
-  if (int32_t rc = check_tiles(op->g.ndim, tile_x, tile_y)) return rc;
   op->fuse = fuse;
-  op->tile_x = tile_x;
-  op->tile_y = tile_y;
   return EXPW_OK;
 }
 

@@ -1,19 +1,25 @@
 // Temporally blocked Faber pass for 2D grids: S consecutive terms of the
 // three-term recurrence per HBM sweep.
 //
-// A workgroup owns a TX x TY output tile. It stages v_{j-1}, v_{j-2} (all
-// three fields) and c^2 over the tile plus a halo of K*S cells in LDS, then
-// runs S recurrence terms in LDS: term r is computed on the tile grown by
-// K*(n-1-r) cells (n = terms of this pass), each term reading only the ring
-// the previous term produced, so no other workgroup's data is needed until
-// the pass ends. v_j overwrites v_{j-2} in place (the recurrence reads
-// v_{j-2} only at the same point). The Faber sum for the tile's own points
-// stays in registers. Only the tile is written back: v_{last}, v_{last-1}
-// and the partial sum, i.e. 19 words per point per pass instead of 16 per
-// term for one-term sweeps.
+// A workgroup owns a TX x TY output tile. Term r of the pass is computed on the
+// tile grown by K*(S-1-r) cells (the ring the next term needs), so after S
+// terms the tile itself is exact and no other workgroup's data was needed.
+// The tile size follows S so that the largest region is exactly 64 columns by
+// 48 rows: wave w of the 16 handles rows w, w+16, w+32 of it, lane l column
+// l, so every LDS row access of a wave is one contiguous 64-element segment
+// and every point's role is fixed for the whole pass. The current generation
+// v_{j-1} (three fields) lives in LDS over the tile plus a halo of K*S cells
+// and is read with its stencil neighbours; everything the recurrence needs
+// only at the point itself stays in registers: v_{j-2}, c^2, the damping
+// values, the last term in which the point is still needed, its source
+// amplitude and the new values. Each term computes into registers, then
+// (after a barrier) writes v_j over v_{j-1} in LDS. The tile's Faber partial
+// sum is kept in LDS. Only the tile is written back: v_last, v_last-1 and the
+// partial sum, i.e. 19 words per point per pass instead of 16 per term for
+// one-term sweeps.
 //
-// Tiles are mapped to workgroups so that each XCD (block id mod 8) gets a
-// contiguous range of tiles in raster order: halo rows shared by adjacent
+// Tiles are mapped to workgroups so that each XCD (block id mod 8) owns a
+// band of tile columns walked row by row: halo rows shared by neighbouring
 // tiles then hit in that XCD's L2.
 #pragma once
 
@@ -24,171 +30,195 @@
 namespace expw {
 
 constexpr int kMaxFuse = 8;
-constexpr int kFusedTX = 64, kFusedTY = 16, kFusedNT = 512;
+constexpr int kFusedNT = 1024;             // 16 waves
+constexpr int kFusedRX = 64, kFusedRY = 48;  // largest region of a pass
+
+// Output tile of a pass of S terms (stencil half-width K = 2).
+template <int S>
+struct FusedTile {
+  static constexpr int TX = kFusedRX - 4 * (S - 1);
+  static constexpr int TY = kFusedRY - 4 * (S - 1);
+};
 
 template <typename T, int S>
 struct FusedArgs {
   T inv_gamma, c0, a_first;
   int32_t first;  // first pass of a step: acc = a_first * v0, no v_{j-2}
-  int32_t tiles_x, tiles, tiles_per_xcd;
+  int32_t tiles_x, tiles_y, band_w;
   T a[S], cpp[S], q[S];
 };
 
 // One pass of exactly S recurrence terms. 2D grids with 3 * points < 2^31.
-template <typename T, int S, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_faber_fused2d(Geo<T, 2, 2> g, const T* __restrict__ vp,
-                                                      const T* __restrict__ vpp,
-                                                      const T* acc_in, T* __restrict__ out_last,
-                                                      T* __restrict__ out_prev, T* acc_out,
-                                                      FusedArgs<T, S> c, Src<T> src) {
+template <typename T, int S>
+__global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d(
+    Geo<T, 2, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp, const T* acc_in,
+    T* __restrict__ out_last, T* __restrict__ out_prev, T* acc_out, FusedArgs<T, S> c, Src<T> src) {
   constexpr int K = 2;
   constexpr int H = K * S;
+  constexpr int TX = FusedTile<S>::TX, TY = FusedTile<S>::TY;
   constexpr int EX = TX + 2 * H, EY = TY + 2 * H, E = EX * EY;
-  constexpr int PPT = TX * TY / NT;
-  static_assert(TX * TY % NT == 0, "tile must be a multiple of the block");
-  __shared__ T lds[7 * E];
-  __shared__ T s_xi[EX], s_xh[EX], s_zi[EY], s_zh[EY];
+  constexpr int X0 = H - K * (S - 1);  // first column/row of the largest region (= K)
+  constexpr int NSL = kFusedRY / 16;   // rows per wave
+  static_assert(TX + 2 * K * (S - 1) == 64, "largest region is one wave wide");
+  __shared__ T cur[3 * E];
+  __shared__ T sacc[3 * TX * TY];
 
-  // XCD-aware tile index: block b runs on XCD b % 8 and takes tile
-  // (b % 8) * tiles_per_xcd + b / 8.
+  // XCD-aware tile order: block b runs on XCD b % 8, which owns a band of
+  // band_w tile columns and walks it row by row (k = b / 8), so the tiles
+  // above and below a tile run on the same XCD at about the same time and
+  // their shared halo rows are read from its L2.
   const int b = blockIdx.x;
-  const int tile = (b & 7) * c.tiles_per_xcd + (b >> 3);
-  if (tile >= c.tiles) return;
-  const int ty_ = tile / c.tiles_x, tx_ = tile - ty_ * c.tiles_x;
+  const int kk = b >> 3;
+  const int ty_ = kk / c.band_w;
+  const int tx_ = (b & 7) * c.band_w + (kk - ty_ * c.band_w);
+  if (tx_ >= c.tiles_x || ty_ >= c.tiles_y) return;
   const int nx = static_cast<int>(g.n[0]), nz = static_cast<int>(g.n[1]);
   const int N = static_cast<int>(g.N);
   const int x0 = tx_ * TX - H;  // global x of LDS column 0
   const int z0 = ty_ * TY - H;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
 
-  T* cur = lds;
-  T* old = lds + 3 * E;
-  T* lc2 = lds + 6 * E;
-
+  // v_{j-1} over tile + halo into LDS (zero outside the domain)
 #pragma unroll 4
-  for (int e = tid; e < E; e += NT) {
+  for (int e = tid; e < E; e += kFusedNT) {
     const int ly = e / EX, lx = e - ly * EX;
     const int gx = x0 + lx, gz = z0 + ly;
     const bool in = gx >= 0 && gx < nx && gz >= 0 && gz < nz;
     const int gi = in ? gz * nx + gx : 0;
-    const T p0 = in ? vp[gi] : T(0), p1 = in ? vp[N + gi] : T(0), p2 = in ? vp[2 * N + gi] : T(0);
-    const bool rd = in && !c.first;
-    const T o0 = rd ? vpp[gi] : T(0), o1 = rd ? vpp[N + gi] : T(0), o2 = rd ? vpp[2 * N + gi] : T(0);
-    const T cc = in ? g.c2[gi] : T(0);
-    cur[e] = p0;
-    cur[E + e] = p1;
-    cur[2 * E + e] = p2;
-    old[e] = o0;
-    old[E + e] = o1;
-    old[2 * E + e] = o2;
-    lc2[e] = cc;
+    cur[e] = in ? vp[gi] : T(0);
+    cur[E + e] = in ? vp[N + gi] : T(0);
+    cur[2 * E + e] = in ? vp[2 * N + gi] : T(0);
   }
-  for (int e = tid; e < EX; e += NT) {
-    const int gx = x0 + e;
-    const bool in = gx >= 0 && gx < nx;
-    s_xi[e] = in ? g.sint[0][gx] : T(0);
-    s_xh[e] = in ? g.shalf[0][gx] : T(0);
-  }
-  for (int e = tid; e < EY; e += NT) {
-    const int gz = z0 + e;
-    const bool in = gz >= 0 && gz < nz;
-    s_zi[e] = in ? g.sint[1][gz] : T(0);
-    s_zh[e] = in ? g.shalf[1][gz] : T(0);
-  }
-
-  // the partial Faber sum of this thread's tile points (read before the barrier
-  // so that the global loads overlap the LDS fill)
-  T acc[PPT][3];
+  // this thread's points: column X0 + lane of rows X0 + wave + 16 i
+  const int lx = X0 + lane;
+  const int gx = x0 + lx;
+  const int dx = lx < H ? H - lx : (lx >= H + TX ? lx - (H + TX - 1) : 0);
+  const T sxi = (gx >= 0 && gx < nx) ? g.sint[0][gx] : T(0);
+  const T sxh = (gx >= 0 && gx < nx) ? g.shalf[0][gx] : T(0);
+  int last[NSL];  // last term that needs the point (-1: outside the domain)
+  T old[NSL][3], cc2[NSL], sp[NSL], szh[NSL], amp[NSL], nv[NSL][3];
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int t = tid + i * NT;
-    const int ty = t / TX, tx = t - ty * TX;
-    const int gx = x0 + H + tx, gz = z0 + H + ty;
-    const bool in = !c.first && gx < nx && gz < nz;
+  for (int i = 0; i < NSL; ++i) {
+    const int ly = X0 + wave + 16 * i;
+    const int gz = z0 + ly;
+    const bool in = gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+    const int dz = ly < H ? H - ly : (ly >= H + TY ? ly - (H + TY - 1) : 0);
+    const int ring = dx > dz ? dx : dz;  // cells outside the tile
+    last[i] = in ? S - 1 - (ring + K - 1) / K : -1;
     const int gi = in ? gz * nx + gx : 0;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) acc[i][f] = in ? acc_in[f * N + gi] : T(0);
+    const bool rd = in && !c.first;
+    old[i][0] = rd ? vpp[gi] : T(0);
+    old[i][1] = rd ? vpp[N + gi] : T(0);
+    old[i][2] = rd ? vpp[2 * N + gi] : T(0);
+    cc2[i] = in ? g.c2[gi] : T(0);
+    const T szi = in ? g.sint[1][gz] : T(0);
+    szh[i] = in ? g.shalf[1][gz] : T(0);
+    sp[i] = sxi + szi;
+    // sum of the source amplitudes at this point
+    T am = T(0);
+    if (in && src.n > 0 && gi >= src.lo && gi <= src.hi)
+      for (int s2 = 0; s2 < src.n; ++s2)
+        if (src.idx[s2] == gi) am += src.amp[s2];
+    amp[i] = am;
+    nv[i][0] = nv[i][1] = nv[i][2] = T(0);
+  }
+  // the partial sum of the tile (not read on the first pass)
+  if (!c.first) {
+    for (int t = tid; t < TX * TY; t += kFusedNT) {
+      const int ty = t / TX, tx = t - ty * TX;
+      const int gxx = x0 + H + tx, gz = z0 + H + ty;
+      const bool in = gxx < nx && gz < nz;
+      const int gi = in ? gz * nx + gxx : 0;
+      sacc[t] = in ? acc_in[gi] : T(0);
+      sacc[TX * TY + t] = in ? acc_in[N + gi] : T(0);
+      sacc[2 * TX * TY + t] = in ? acc_in[2 * N + gi] : T(0);
+    }
   }
   __syncthreads();
   if (c.first) {
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const int t = tid + i * NT;
+    for (int t = tid; t < TX * TY; t += kFusedNT) {
       const int ty = t / TX, tx = t - ty * TX;
       const int l = (ty + H) * EX + tx + H;
-#pragma unroll
-      for (int f = 0; f < 3; ++f) acc[i][f] = c.a_first * cur[f * E + l];
+      sacc[t] = c.a_first * cur[l];
+      sacc[TX * TY + t] = c.a_first * cur[E + l];
+      sacc[2 * TX * TY + t] = c.a_first * cur[2 * E + l];
     }
   }
 
   const T w0 = g.w[0], w1 = g.w[1];
+  const T* cp = cur;
+  const T* cvx = cur + E;
+  const T* cvz = cur + 2 * E;
 #pragma unroll
   for (int r = 0; r < S; ++r) {
-    const int ext = K * (S - 1 - r);
-    const int RW = TX + 2 * ext, RH = TY + 2 * ext;
-    const int lx0 = H - ext, ly0 = H - ext;
     const T cpp = c.cpp[r];
-    Src<T> sr = src;
-    sr.q = c.q[r];
-    const T* cp = cur;
-    const T* cvx = cur + E;
-    const T* cvz = cur + 2 * E;
-    T* op_ = old;
-    T* ovx = old + E;
-    T* ovz = old + 2 * E;
-    for (int e = tid; e < RW * RH; e += NT) {
-      const int ry = e / RW;
-      const int lx = lx0 + (e - ry * RW), ly = ly0 + ry;
-      const int gx = x0 + lx, gz = z0 + ly;
-      if (gx < 0 || gx >= nx || gz < 0 || gz >= nz) continue;  // ghosts stay zero
-      const int l = ly * EX + lx;
-      const T dvx = w0 * (cvx[l] - cvx[l - 1]) + w1 * (cvx[l + 1] - cvx[l - 2]);
-      const T dvz = w0 * (cvz[l] - cvz[l - EX]) + w1 * (cvz[l + EX] - cvz[l - 2 * EX]);
-      const T dpx = w0 * (cp[l + 1] - cp[l]) + w1 * (cp[l + 2] - cp[l - 1]);
-      const T dpz = w0 * (cp[l + EX] - cp[l]) + w1 * (cp[l + 2 * EX] - cp[l - EX]);
-      const T pc = cp[l], vxc = cvx[l], vzc = cvz[l];
-      const T hp = -lc2[l] * (dvx + dvz) - (s_xi[lx] + s_zi[ly]) * pc;
-      const T hvx = -dpx - s_xh[lx] * vxc;
-      const T hvz = -dpz - s_zh[ly] * vzc;
-      T np = hp * c.inv_gamma - c.c0 * pc - cpp * op_[l];
-      np += src_value(sr, static_cast<int64_t>(gz) * nx + gx);
-      const T nvx = hvx * c.inv_gamma - c.c0 * vxc - cpp * ovx[l];
-      const T nvz = hvz * c.inv_gamma - c.c0 * vzc - cpp * ovz[l];
-      op_[l] = np;
-      ovx[l] = nvx;
-      ovz[l] = nvz;
+    const T qr = c.q[r];
+#pragma unroll
+    for (int i = 0; i < NSL; ++i) {
+      if (r <= last[i]) {
+        const int l = (X0 + wave + 16 * i) * EX + lx;
+        const T pc = cp[l], vxc = cvx[l], vzc = cvz[l];
+        const T dvx = w0 * (vxc - cvx[l - 1]) + w1 * (cvx[l + 1] - cvx[l - 2]);
+        const T dvz = w0 * (vzc - cvz[l - EX]) + w1 * (cvz[l + EX] - cvz[l - 2 * EX]);
+        const T dpx = w0 * (cp[l + 1] - pc) + w1 * (cp[l + 2] - cp[l - 1]);
+        const T dpz = w0 * (cp[l + EX] - pc) + w1 * (cp[l + 2 * EX] - cp[l - EX]);
+        const T hp = -cc2[i] * (dvx + dvz) - sp[i] * pc;
+        const T hvx = -dpx - sxh * vxc;
+        const T hvz = -dpz - szh[i] * vzc;
+        nv[i][0] = hp * c.inv_gamma - c.c0 * pc - cpp * old[i][0] + qr * amp[i];
+        nv[i][1] = hvx * c.inv_gamma - c.c0 * vxc - cpp * old[i][1];
+        nv[i][2] = hvz * c.inv_gamma - c.c0 * vzc - cpp * old[i][2];
+      }
     }
-    __syncthreads();
-    T* tmp = cur;
-    cur = old;
-    old = tmp;
+    __syncthreads();  // every read of v_{j-1} is done
     const T aj = c.a[r];
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const int t = tid + i * NT;
-      const int ty = t / TX, tx = t - ty * TX;
-      const int l = (ty + H) * EX + tx + H;
-#pragma unroll
-      for (int f = 0; f < 3; ++f) acc[i][f] += aj * cur[f * E + l];
+    for (int i = 0; i < NSL; ++i) {
+      if (r <= last[i]) {
+        // only this thread writes point l, so v_{j-1} is still there to keep
+        const int ly = X0 + wave + 16 * i;
+        const int l = ly * EX + lx;
+        old[i][0] = cur[l];
+        old[i][1] = cur[E + l];
+        old[i][2] = cur[2 * E + l];
+        cur[l] = nv[i][0];
+        cur[E + l] = nv[i][1];
+        cur[2 * E + l] = nv[i][2];
+        if (last[i] == S - 1 && lx >= H && lx < H + TX && ly >= H && ly < H + TY) {
+          const int t = (ly - H) * TX + (lx - H);
+          sacc[t] += aj * nv[i][0];
+          sacc[TX * TY + t] += aj * nv[i][1];
+          sacc[2 * TX * TY + t] += aj * nv[i][2];
+        }
+      }
     }
+    __syncthreads();  // v_j complete in LDS
   }
 
+  // write back the tile: the pair (v_last, v_last-1) from registers, the sum from LDS
+  if (out_last) {
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int t = tid + i * NT;
-    const int ty = t / TX, tx = t - ty * TX;
-    const int gx = x0 + H + tx, gz = z0 + H + ty;
-    if (gx >= nx || gz >= nz) continue;
-    const int l = (ty + H) * EX + tx + H;
-    const int gi = gz * nx + gx;
+    for (int i = 0; i < NSL; ++i) {
+      const int ly = X0 + wave + 16 * i;
+      if (last[i] == S - 1 && lx >= H && lx < H + TX && ly >= H && ly < H + TY) {
+        const int gi = (z0 + ly) * nx + gx;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      if (out_last) {
-        out_last[f * N + gi] = cur[f * E + l];
-        out_prev[f * N + gi] = old[f * E + l];
+        for (int f = 0; f < 3; ++f) {
+          out_last[f * N + gi] = nv[i][f];
+          out_prev[f * N + gi] = old[i][f];
+        }
       }
-      acc_out[f * N + gi] = acc[i][f];
     }
+  }
+  for (int t = tid; t < TX * TY; t += kFusedNT) {
+    const int ty = t / TX, tx = t - ty * TX;
+    const int gxx = x0 + H + tx, gz = z0 + H + ty;
+    if (gxx >= nx || gz >= nz) continue;
+    const int gi = gz * nx + gxx;
+    acc_out[gi] = sacc[t];
+    acc_out[N + gi] = sacc[TX * TY + t];
+    acc_out[2 * N + gi] = sacc[2 * TX * TY + t];
   }
 }
 
@@ -202,13 +232,6 @@ int fused_depth(int requested, int m, int64_t npts) {
   if (s > smax) s = smax;
   if (s > m) s = m;
   return s < 2 ? 1 : s;
-}
-
-inline int32_t check_tiles(int ndim, int tile_x, int tile_y) {
-  (void)ndim;
-  if ((tile_x != 0 && tile_x != kFusedTX) || (tile_y != 0 && tile_y != kFusedTY))
-    return fail(EXPW_EUNSUPPORTED, "fused tile must be %dx%d", kFusedTX, kFusedTY);
-  return EXPW_OK;
 }
 
 template <typename T, int S>
@@ -227,18 +250,18 @@ int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<
     c.cpp[r] = static_cast<T>(jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1));
     c.q[r] = static_cast<T>(q[jj - 1]);
   }
-  const int tx = static_cast<int>((g.n[0] + kFusedTX - 1) / kFusedTX);
-  const int ty = static_cast<int>((g.n[1] + kFusedTY - 1) / kFusedTY);
+  constexpr int TX = FusedTile<S>::TX, TY = FusedTile<S>::TY;
+  const int tx = static_cast<int>((g.n[0] + TX - 1) / TX);
+  const int ty = static_cast<int>((g.n[1] + TY - 1) / TY);
   c.tiles_x = tx;
-  c.tiles = tx * ty;
-  c.tiles_per_xcd = (c.tiles + 7) / 8;
-  const unsigned blocks = 8u * static_cast<unsigned>(c.tiles_per_xcd);
+  c.tiles_y = ty;
+  c.band_w = (tx + 7) / 8;
+  const unsigned blocks = 8u * static_cast<unsigned>(c.band_w) * static_cast<unsigned>(ty);
   // algorithmic words per point: v_{j-1} (3), c^2 (1), and unless first v_{j-2}
   // and the partial sum (3 + 3); writes: the sum (3), and unless last the pair (3 + 3)
   const double words = 3 + 1 + (first ? 0 : 6) + 3 + (out_last ? 6 : 0);
-  launch_timed(prof, st, EXPW_KERNEL_FABER, words * g.N * sizeof(T),
-               k_faber_fused2d<T, S, kFusedTX, kFusedTY, kFusedNT>, dim3(blocks), dim3(kFusedNT), g,
-               vp, vpp, acc_in, out_last, out_prev, acc_out, c, src);
+  launch_timed(prof, st, EXPW_KERNEL_FABER, words * g.N * sizeof(T), k_faber_fused2d<T, S>,
+               dim3(blocks), dim3(kFusedNT), g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "fused Faber pass: %s", hipGetErrorString(e));
   return EXPW_OK;

@@ -60,7 +60,7 @@ SIGNATURES = {
     "expw_get_spectrum": (_i32, [_vp, _pd, _pd]),
     "expw_get_ellipse": (_i32, [_vp, _pd, _pd, _pd]),
     "expw_set_ellipse": (_i32, [_vp, _dbl, _dbl, _dbl]),
-    "expw_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
+    "expw_set_tuning": (_i32, [_vp, _i32]),
     "expw_apply": (_i32, [_vp, _vp, _vp]),
     "expw_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
     "expw_set_receivers": (_i32, [_vp, _i32, _vp]),
@@ -218,8 +218,8 @@ def expw_set_ellipse(op, gamma, c0, c1):
     _check(load().expw_set_ellipse(op, gamma, c0, c1))
 
 
-def expw_set_tuning(op, fuse, tile_x=0, tile_y=0):
-    _check(load().expw_set_tuning(op, fuse, tile_x, tile_y))
+def expw_set_tuning(op, fuse):
+    _check(load().expw_set_tuning(op, fuse))
 
 
 def expw_apply(op, x_ptr, y_ptr):
@@ -357,8 +357,8 @@ class Operator:
     def spectrum(self):
         return expw_get_spectrum(self.op)
 
-    def set_tuning(self, fuse=0, tile_x=0, tile_y=0):
-        expw_set_tuning(self.op, fuse, tile_x, tile_y)
+    def set_tuning(self, fuse=0):
+        expw_set_tuning(self.op, fuse)
 
     def apply(self, x, out=None):
         self._check_state(x)
