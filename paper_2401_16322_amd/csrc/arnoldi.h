@@ -9,18 +9,23 @@
 // again. Columns are written unnormalized with their scale s_j = 1/h_{j,j-1}
 // (s_0 = 1), as in the launch-per-step path.
 //
-// Data that crosses workgroups inside the launch (reduction partials, the
-// basis vectors Q_j, the arrival flags) is read and written with
-// device-coherent accesses (agent-scope relaxed atomics, i.e. sc1 loads and
-// stores that do not stop in an XCD's L2), so no cache-wide writeback or
-// invalidation is needed. A grid-wide reduction is also the barrier, and uses
-// no read-modify-write: after waiting for its own accesses (s_waitcnt 0),
-// block b stores its partial, then its flag word = the barrier's sequence
-// number; every block then waits, one thread per block b', until flag b'
-// reaches that number and loads partial b'. Flags only grow, so a block that
-// runs ahead cannot be missed. Every wait is bounded: a wait longer than
-// spin_limit polls sets *err and gives up, and once *err is set no wait lasts
-// more than 1024 polls, so every wave always reaches the end of the kernel.
+// Data that crosses workgroups inside the launch (reduction partials and the
+// basis vectors Q_j) is read and written with device-coherent accesses
+// (agent-scope relaxed atomics, i.e. sc1 loads and stores that do not stop in
+// an XCD's L2), so no cache-wide writeback or invalidation is needed. A
+// grid-wide reduction is also the barrier, and uses no read-modify-write:
+// each block's partial is its own arrival word. Slots start out holding a
+// signalling-NaN pattern that no arithmetic produces; block b stores its
+// partial (after waiting for its earlier stores, s_waitcnt 0) into slot b of
+// the barrier's buffer, and every block waits, one thread per slot, until the
+// slot no longer holds that pattern, taking the value it finds. Three
+// buffers rotate: when barrier s completes, every block has read the values
+// of barrier s-1, so each block then restores the pattern in its slot of that
+// buffer, which is next written at barrier s+2. One store and one successful
+// load per block and barrier, against two of each with separate flags. Every
+// wait is bounded: a wait longer than spin_limit polls sets *err and gives up,
+// and once *err is set no wait lasts more than 1024 polls, so every wave
+// always reaches the end of the kernel.
 #pragma once
 
 #include "device_common.h"
@@ -40,43 +45,49 @@ __device__ __forceinline__ void st_coherent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits until the coherent word *w reaches v (bounded; see above).
-__device__ __forceinline__ void wait_word(const unsigned* w, unsigned v, unsigned spin_limit,
-                                          int* err) {
-  unsigned polls = 0;
-  while (ld_coherent(w) < v) {
-    __builtin_amdgcn_s_sleep(1);
-    if (++polls > spin_limit ||
-        ((polls & 1023u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      break;
-    }
-  }
-}
+// Contents of an empty slot of the grid-wide reduction (a signalling NaN;
+// a NaN partial is stored as the default quiet NaN instead).
+constexpr unsigned long long kSlotEmpty = 0x7FF4DEADBEEF0001ull;
+constexpr int kSlotBuffers = 3;
 
 // Grid-wide sum of v (blocks of NT threads, at most NT blocks): returns the
-// sum of the per-block partials in block order to every thread. flags[b] is
-// block b's arrival word; seq numbers the barriers of the launch (1, 2, ...;
-// the flags start at 0); part alternates between two buffers.
+// sum of the per-block partials in block order to every thread. slots holds
+// kSlotBuffers buffers of kRedMaxBlocks words, all kSlotEmpty at launch; seq
+// numbers the barriers of the launch (1, 2, ...).
 template <int NT>
-__device__ __forceinline__ double grid_sum(double v, double* part, unsigned* flags, unsigned seq,
+__device__ __forceinline__ double grid_sum(double v, unsigned long long* slots, unsigned seq,
                                            unsigned spin_limit, int* err) {
   __shared__ double s_tot;
+  unsigned long long* cur = slots + (seq % kSlotBuffers) * kRedMaxBlocks;
+  unsigned long long* prev = slots + ((seq + kSlotBuffers - 1) % kSlotBuffers) * kRedMaxBlocks;
   const double b = block_reduce<false, NT>(v);
   __builtin_amdgcn_s_waitcnt(0);  // this thread's coherent stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
-    st_coherent(part + blockIdx.x, b);
-    __builtin_amdgcn_s_waitcnt(0);
-    st_coherent(flags + blockIdx.x, seq);
+    const unsigned long long bits = (b != b) ? 0x7FF8000000000000ull : __double_as_longlong(b);
+    st_coherent(cur + blockIdx.x, bits);
   }
   double pv = 0.0;
   if (threadIdx.x < gridDim.x) {
-    wait_word(flags + threadIdx.x, seq, spin_limit, err);
-    pv = ld_coherent(part + threadIdx.x);
+    unsigned polls = 0;
+    unsigned long long x;
+    while ((x = ld_coherent(cur + threadIdx.x)) == kSlotEmpty) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++polls > spin_limit ||
+          ((polls & 1023u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    pv = __longlong_as_double(x);
   }
   const double tot = block_reduce<false, NT>(pv);
-  if (threadIdx.x == 0) s_tot = tot;
+  if (threadIdx.x == 0) {
+    s_tot = tot;
+    // all blocks arrived at this barrier, so all have read barrier seq-1's
+    // values; the store completes before this block's next arrival (s_waitcnt)
+    st_coherent(prev + blockIdx.x, kSlotEmpty);
+  }
   __syncthreads();
   return s_tot;
 }
@@ -131,22 +142,16 @@ struct ArnArgs {
 template <typename T, int K, int BC, int DIM, int UN>
 __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     Geo<T, K, DIM> g, const T* __restrict__ S, T* Q, KrySrc src, const T* __restrict__ amp,
-    ArnArgs a, double* part, unsigned* bar, int* err, double* hess, double* sc, double* beta_out) {
+    ArnArgs a, unsigned long long* slots, int* err, double* hess, double* sc, double* beta_out) {
   __shared__ double s_scale[65];
   const unsigned nb = gridDim.x;
   const int64_t nthreads = static_cast<int64_t>(nb) * kArnNT;
   const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kArnNT + threadIdx.x;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-  double* P[2] = {part, part + kRedMaxBlocks};
-  int c = 0;
   unsigned seq = 0;
 
   // grid-wide sums double as the barriers between Gram-Schmidt steps
-  auto publish = [&](double v) {
-    const double r = grid_sum<kArnNT>(v, P[c], bar, ++seq, a.spin_limit, err);
-    c ^= 1;
-    return r;
-  };
+  auto publish = [&](double v) { return grid_sum<kArnNT>(v, slots, ++seq, a.spin_limit, err); };
 
   // q_0 = [S; e_p] / beta
   double acc = 0.0;
@@ -272,6 +277,11 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
 __global__ void k_zero_u32(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 }  // namespace expw

@@ -99,7 +99,7 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
   L.scal = off; off = align_up(off + 64 * sizeof(double));
   L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
   L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
-  L.bar = off; off = align_up(off + 1024 * sizeof(unsigned));  // grid barrier words
+  L.bar = off; off = align_up(off + kSlotBuffers * kRedMaxBlocks * sizeof(unsigned long long));  // grid reduction slots
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -370,7 +370,7 @@ int persistent_un(expw_op* op, int64_t naug) {
 template <typename T, int K, int BC, int DIM>
 int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T* S, T* Q,
                            const KrySrc& ks, const T* amp, int64_t ns, int64_t naug, int64_t ld,
-                           int k, double tail2, double tol, double* part, unsigned* bar, int* err,
+                           int k, double tail2, double tol, unsigned long long* slots, int* err,
                            double* hess, double* sc, double* beta_out) {
   ArnArgs aa{};
   aa.ns = ns;
@@ -380,13 +380,14 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   aa.tail2 = tail2;
   aa.tol = tol;
   aa.spin_limit = 1u << 20;  // about a second of polling
-  k_zero_u32<<<4, 256, 0, op->stream>>>(bar, op->coop_blocks);
+  constexpr int nslots = kSlotBuffers * kRedMaxBlocks;
+  k_fill_u64<<<(nslots + 255) / 256, 256, 0, op->stream>>>(slots, nslots, kSlotEmpty);
   Geo<T, K, DIM> gg = g;
   const T* Sp = S;
   T* Qp = Q;
   KrySrc kk = ks;
   const T* ap = amp;
-  void* args[] = {&gg, &Sp, &Qp, &kk, &ap, &aa, &part, &bar, &err, &hess, &sc, &beta_out};
+  void* args[] = {&gg, &Sp, &Qp, &kk, &ap, &aa, &slots, &err, &hess, &sc, &beta_out};
   const void* fn = nullptr;
   if (un == 2) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2>);
   else if (un == 4) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 4>);
@@ -425,7 +426,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
   double* kry_y = reinterpret_cast<double*>(op->ws + op->off_kry);
   double* kry_sc = kry_y + 64;
   int* kry_keff = reinterpret_cast<int*>(op->ws + op->off_kry + 136 * sizeof(double));
-  unsigned* kry_bar = reinterpret_cast<unsigned*>(op->ws + op->off_bar);
+  unsigned long long* kry_slots = reinterpret_cast<unsigned long long*>(op->ws + op->off_bar);
   int* kry_err = kry_keff + 8;
   const int unp = persistent_un<T, K, BC, DIM>(op, naug);
   const double tol = 1e-14;
@@ -447,7 +448,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
     if (unp > 0) {
       // the whole Arnoldi process in one cooperative launch
       int32_t rc = arnoldi_persistent<T, K, BC, DIM>(op, unp, g, S, Q, ks, amp, ns, naug, ld, k,
-                                                     p > 0 ? 1.0 : 0.0, tol, part, kry_bar, kry_err,
+                                                     p > 0 ? 1.0 : 0.0, tol, kry_slots, kry_err,
                                                      hess, kry_sc, scal + 1);
       if (rc != EXPW_OK) return rc;
     } else {
