@@ -46,6 +46,11 @@ def parse():
                     help="run a plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--tts", type=int, default=1,
+                    help="1 = also measure time-to-solution at --tts-tol over the full simulated time")
+    ap.add_argument("--tts-tol", type=float, default=1e-5)
+    ap.add_argument("--tts-dtypes", default="f32,f64")
+    ap.add_argument("--tts-repeats", type=int, default=3)
     return ap.parse_args()
 
 
@@ -178,9 +183,135 @@ def main():
         "methods": per_method,
         "kernels": kernels,
     }
+    if args.tts:
+        del states, traces
+        op.close()
+        out["time_to_solution"] = time_to_solution(w, c2_np, args)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, methods, mvos, dts, args, c2_np, rec)
     print(json.dumps(out), flush=True)
+
+
+# dt ladder (ms): every value divides the 0.5 s snapshot spacing
+TTS_DTS_MS = (12.5, 10.0, 5.0, 4.0, 2.5, 2.0, 1.0, 0.5)
+TTS_CANDIDATES = (("faber", 8), ("faber", 16), ("faber", 24), ("faber", 32), ("faber", 40),
+                  ("krylov", 10), ("krylov", 20), ("krylov", 30), ("krylov", 40),
+                  ("rk4", 4), ("leapfrog", 1))
+
+
+def time_to_solution(w, c2_np, args):
+    """Largest dt per method and order whose pressure snapshots every 0.5 s
+    up to the final time stay within tol (relative L2 over the physical
+    domain, damping layer excluded) of a converged FP64 reference; the wall
+    time of that whole run (receiver recording included) is the time to
+    solution. The reference is the library's FP64 Faber path at degree 40
+    and dt = 0.5 ms, checked against dt = 1 ms; that path is itself held to
+    the FP64 oracle by the parity tests (a CPU oracle run at this size would
+    take about an hour)."""
+    import torch
+    from paper_2401_16322_amd import expwave as xw
+    dev = torch.device("cuda:0")
+    L = w.abc_cells
+    T = w.T
+    snap_every = 0.5
+    nsnap = int(round(T / snap_every))
+    rec = w.receiver_nodes()
+    src = w.source_node()
+    npts = w.npts
+
+    def make_op(tdt, kmax):
+        op = xw.Operator(w.n, w.h, torch.tensor(c2_np, dtype=tdt, device=dev),
+                         abc_cells=w.abc_cells, sigma_max=w.sigma_max,
+                         max_krylov_k=kmax, max_taylor_p=w.taylor_p)
+        op.set_source_ricker([src], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+        op.set_receivers(rec)
+        return op
+
+    def interior(state):
+        p = state[:npts].view(*reversed(w.n))
+        sl = tuple(slice(L, n - L) for n in reversed(w.n))
+        return p[sl].double()
+
+    def run(op, tdt, method, order, dt, ref=None, tol=None):
+        """Full run; returns (max snapshot error, wall seconds, snapshots)."""
+        state = torch.zeros((w.ndim + 1) * npts, dtype=tdt, device=dev)
+        nper = int(round(snap_every / dt))
+        traces = torch.zeros(nper * max(rec.size, 1), dtype=tdt, device=dev)
+        snaps, err = [], 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(nsnap):
+            t = s * snap_every
+            tr = traces if rec.size else None
+            if method == "faber":
+                op.step_faber(state, t, dt, order, nper, traces=tr)
+            elif method == "krylov":
+                op.step_krylov(state, t, dt, order, nper, traces=tr)
+            elif method == "rk4":
+                op.step_rk4(state, t, dt, nper, traces=tr)
+            else:
+                op.step_leapfrog(state, t, dt, nper, traces=tr)
+            if ref is None:
+                snaps.append(interior(state).clone())
+            else:
+                # the error check is outside the method; it stops a failing run early
+                torch.cuda.synchronize()
+                t_pause = time.perf_counter()
+                r = ref[s]
+                e = (torch.linalg.vector_norm(interior(state) - r) / torch.linalg.vector_norm(r)).item()
+                if not np.isfinite(e):
+                    e = float("inf")
+                err = max(err, e)
+                t0 += time.perf_counter() - t_pause
+                if err > tol:
+                    break
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        op.sync()
+        return err, wall, snaps
+
+    # converged FP64 reference
+    op64 = make_op(torch.float64, 0)
+    _, _, ref = run(op64, torch.float64, "faber", 40, 0.5e-3)
+    _, _, ref2 = run(op64, torch.float64, "faber", 40, 1.0e-3)
+    ref_check = max((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a)).item()
+                    for a, b in zip(ref, ref2))
+    op64.close()
+
+    kmax = max(k for m, k in TTS_CANDIDATES if m == "krylov")
+    mvo_step = {"rk4": 4, "leapfrog": 1}
+    out = {"tol": args.tts_tol, "T_s": T,
+           "snapshots_s": [snap_every * (i + 1) for i in range(nsnap)],
+           "error": "relative L2 of pressure over the physical domain, max over snapshots",
+           "reference": {"method": "faber", "order": 40, "dt_ms": 0.5, "dtype": "f64",
+                         "vs_dt_1ms": ref_check},
+           "dt_ladder_ms": list(TTS_DTS_MS)}
+    for dname in [d for d in args.tts_dtypes.split(",") if d]:
+        tdt = {"f32": torch.float32, "f64": torch.float64}[dname]
+        op = make_op(tdt, kmax)
+        results = []
+        for method, order in TTS_CANDIDATES:
+            best, tried = None, []
+            for dt_ms in TTS_DTS_MS:
+                dt = dt_ms * 1e-3
+                err, _, _ = run(op, tdt, method, order, dt, ref=ref, tol=args.tts_tol)
+                tried.append([dt_ms, float(f"{err:.3g}")])
+                if err <= args.tts_tol:
+                    walls = [run(op, tdt, method, order, dt, ref=ref, tol=args.tts_tol)[1]
+                             for _ in range(args.tts_repeats)]
+                    nsteps = int(round(T / dt))
+                    best = {"method": method, "order": order, "dt_ms": dt_ms, "max_rel_l2": err,
+                            "wall_s": float(np.median(walls)), "n_steps": nsteps,
+                            "n_op": nsteps * mvo_step.get(method, order), "n_mem": nsteps}
+                    break
+            r = best if best else {"method": method, "order": order, "dt_ms": None}
+            r["tried"] = tried  # [dt_ms, error at the first snapshot that failed, or the max]
+            results.append(r)
+        op.close()
+        ok = [r for r in results if r.get("dt_ms")]
+        out[dname] = {"runs": results,
+                      "fastest": min(ok, key=lambda r: r["wall_s"]) if ok else None}
+    return out
 
 
 def cpu_baseline(w, methods, mvos, dts, args, c2_np, rec):
