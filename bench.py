@@ -28,6 +28,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_2401_16322_amd", "csrc")
+
+
+def kernel_sources_digest():
+    """sha256 over the library's kernel sources (names and contents)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, dtype):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy), or
+    None when there is none for this case or the kernels changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest = kernel_sources_digest()
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 5 and not line.startswith("#") and f[:3] == [kernel, workload, dtype]:
+                return float(f[3]) if f[4] == digest else None
+    return None
 METRIC = "grid-pt matvecs/s + HBM % of peak; time-to-solution at 1e-5 rel. L2 error"
 
 
@@ -178,7 +206,9 @@ def main():
                    "receivers": int(rec.size), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(1e3 * ms / launches, 3),
+                     "traffic": measured_traffic(dom, w.name, args.dtype),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
+                     "avg_launch_us": round(1e3 * ms / launches, 3),
                      "launches": launches},
         "methods": per_method,
         "kernels": kernels,
