@@ -219,7 +219,7 @@ def main():
         out["time_to_solution"] = time_to_solution(w, c2_np, args)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, methods, mvos, dts, args, c2_np, rec)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 # dt ladder (ms): every value divides the 0.5 s snapshot spacing
@@ -325,7 +325,7 @@ def time_to_solution(w, c2_np, args):
             for dt_ms in TTS_DTS_MS:
                 dt = dt_ms * 1e-3
                 err, _, _ = run(op, tdt, method, order, dt, ref=ref, tol=args.tts_tol)
-                tried.append([dt_ms, float(f"{err:.3g}")])
+                tried.append([dt_ms, float(f"{err:.3g}") if np.isfinite(err) else None])
                 if err <= args.tts_tol:
                     walls = [run(op, tdt, method, order, dt, ref=ref, tol=args.tts_tol)[1]
                              for _ in range(args.tts_repeats)]
