@@ -53,10 +53,13 @@ constexpr int kSlotBuffers = 3;
 // Grid-wide sum of v (blocks of NT threads, at most NT blocks): returns the
 // sum of the per-block partials in block order to every thread. slots holds
 // kSlotBuffers buffers of kRedMaxBlocks words, all kSlotEmpty at launch; seq
-// numbers the barriers of the launch (1, 2, ...).
-template <int NT>
+// numbers the barriers of the launch (1, 2, ...). after() runs in every
+// thread once this block has arrived: loads it issues overlap the wait (the
+// s_waitcnt before the arrival waits for every outstanding memory operation,
+// so loads issued earlier would be waited for there).
+template <int NT, typename F>
 __device__ __forceinline__ double grid_sum(double v, unsigned long long* slots, unsigned seq,
-                                           unsigned spin_limit, int* err) {
+                                           unsigned spin_limit, int* err, F&& after) {
   __shared__ double s_tot;
   unsigned long long* cur = slots + (seq % kSlotBuffers) * kRedMaxBlocks;
   unsigned long long* prev = slots + ((seq + kSlotBuffers - 1) % kSlotBuffers) * kRedMaxBlocks;
@@ -67,6 +70,7 @@ __device__ __forceinline__ double grid_sum(double v, unsigned long long* slots, 
     const unsigned long long bits = (b != b) ? 0x7FF8000000000000ull : __double_as_longlong(b);
     st_coherent(cur + blockIdx.x, bits);
   }
+  after();
   double pv = 0.0;
   if (threadIdx.x < gridDim.x) {
     unsigned polls = 0;
@@ -151,7 +155,9 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   unsigned seq = 0;
 
   // grid-wide sums double as the barriers between Gram-Schmidt steps
-  auto publish = [&](double v) { return grid_sum<kArnNT>(v, slots, ++seq, a.spin_limit, err); };
+  auto publish = [&](double v) {
+    return grid_sum<kArnNT>(v, slots, ++seq, a.spin_limit, err, [] {});
+  };
 
   // q_0 = [S; e_p] / beta
   double acc = 0.0;
@@ -185,7 +191,8 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   (void)publish(0.0);  // Q_0 complete everywhere
 
   // qa holds q_i's stored column Q_i, qb the next one Q_{i+1}; the next
-  // column is loaded before each grid-wide sum so the load overlaps the wait
+  // column is loaded as soon as this block has arrived at a grid-wide sum, so
+  // the load overlaps the wait for the other blocks
   T w[UN], qa[UN], qb[UN];
   auto load_col = [&](T* dst, int col) {
     const T* qc = Q + col * a.ld;
@@ -229,8 +236,9 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       qa[u] = q0[u];
       acc += static_cast<double>(v) * static_cast<double>(q0[u]);
     }
-    if (j >= 1) load_col(qb, 1);
-    double h = publish(acc);
+    double h = grid_sum<kArnNT>(acc, slots, ++seq, a.spin_limit, err, [&] {
+      if (j >= 1) load_col(qb, 1);
+    });
     if (lead) hess[0 * 64 + j] = h;
     double sa = 1.0;
     for (int i = 0; i <= j; ++i) {
@@ -253,9 +261,10 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       if (!lastc) {
 #pragma unroll
         for (int u = 0; u < UN; ++u) qa[u] = qb[u];
-        if (i + 2 <= j) load_col(qb, i + 2);
       }
-      const double r = publish(acc);
+      const double r = grid_sum<kArnNT>(acc, slots, ++seq, a.spin_limit, err, [&] {
+        if (!lastc && i + 2 <= j) load_col(qb, i + 2);
+      });
       if (!lastc) {
         h = r;
         if (lead) hess[(i + 1) * 64 + j] = h;
