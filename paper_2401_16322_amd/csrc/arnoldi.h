@@ -50,8 +50,8 @@ __device__ __forceinline__ void st_coherent(T* p, T v) {
 constexpr unsigned long long kSlotEmpty = 0x7FF4DEADBEEF0001ull;
 constexpr int kSlotBuffers = 3;
 
-// Grid-wide sum of v (blocks of NT threads, at most NT blocks): returns the
-// sum of the per-block partials in block order to every thread. slots holds
+// Grid-wide sum of v (blocks of NT threads, at most 1024 blocks): returns the
+// sum of the per-block partials, added in a fixed order, to every thread. slots holds
 // kSlotBuffers buffers of kRedMaxBlocks words, all kSlotEmpty at launch; seq
 // numbers the barriers of the launch (1, 2, ...). after() runs in every
 // thread once this block has arrived: loads it issues overlap the wait (the
@@ -60,17 +60,27 @@ constexpr int kSlotBuffers = 3;
 template <int NT, typename F>
 __device__ __forceinline__ double grid_sum(double v, unsigned long long* slots, unsigned seq,
                                            unsigned spin_limit, int* err, F&& after) {
-  __shared__ double s_tot;
+  static_assert(NT % 64 == 0 && NT <= 1024, "block of whole waves");
+  __shared__ double s_part[NT / 64];
+  __shared__ double s_poll[2][kRedMaxBlocks / 64];
   unsigned long long* cur = slots + (seq % kSlotBuffers) * kRedMaxBlocks;
   unsigned long long* prev = slots + ((seq + kSlotBuffers - 1) % kSlotBuffers) * kRedMaxBlocks;
-  const double b = block_reduce<false, NT>(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // the block's partial: wave sums, then wave 0 sums them
+  v = wave_sum_fixed(v);
+  if (lane == 0) s_part[wid] = v;
   __builtin_amdgcn_s_waitcnt(0);  // this thread's coherent stores have completed
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned long long bits = (b != b) ? 0x7FF8000000000000ull : __double_as_longlong(b);
-    st_coherent(cur + blockIdx.x, bits);
+  if (wid == 0) {
+    double b = lane < NT / 64 ? s_part[lane] : 0.0;
+    b = wave_sum_fixed(b);
+    if (lane == 0) {
+      const unsigned long long bits = (b != b) ? 0x7FF8000000000000ull : __double_as_longlong(b);
+      st_coherent(cur + blockIdx.x, bits);
+    }
   }
   after();
+  // every block's partial, one thread per slot
   double pv = 0.0;
   if (threadIdx.x < gridDim.x) {
     unsigned polls = 0;
@@ -85,15 +95,23 @@ __device__ __forceinline__ double grid_sum(double v, unsigned long long* slots, 
     }
     pv = __longlong_as_double(x);
   }
-  const double tot = block_reduce<false, NT>(pv);
+  // sum in block order: per wave of slots, then the waves in order (every
+  // thread adds the same values in the same order)
+  const int nw = (static_cast<int>(gridDim.x) + 63) / 64;
+  double* sp = s_poll[seq & 1u];
+  if (wid < nw) {
+    pv = wave_sum_fixed(pv);
+    if (lane == 0) sp[wid] = pv;
+  }
+  __syncthreads();
+  double tot = 0.0;
+  for (int w = 0; w < nw; ++w) tot += sp[w];
   if (threadIdx.x == 0) {
-    s_tot = tot;
     // all blocks arrived at this barrier, so all have read barrier seq-1's
     // values; the store completes before this block's next arrival (s_waitcnt)
     st_coherent(prev + blockIdx.x, kSlotEmpty);
   }
-  __syncthreads();
-  return s_tot;
+  return tot;
 }
 
 // x at the point shifted by s along one axis (zero outside or wrapped), read

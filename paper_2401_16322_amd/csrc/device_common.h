@@ -115,6 +115,32 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// x moved across lanes by one DPP pattern (lanes of rows outside ROW_MASK get 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), returned to every lane.
+// Lane shuffles by DPP: pairs and quads (quad permutations), the four quads of
+// each 16-lane row (row rotations by 4 and 8), then rows 0+1 and 2+3 (row
+// broadcast of lane 15) and finally all four (row broadcast of lane 31). The
+// value of lane 63 is taken, so the order of the additions is fixed and every
+// wave with the same inputs gets the same bits.
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124, 0xF>(v);  // row_ror:4
+  v += dpp_move<0x128, 0xF>(v);  // row_ror:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // Block-wide reduction over NT threads; the result is valid in thread 0.
 // Ends with a barrier so that the shared scratch can be reused right away.
 template <bool MAX, int NT = kBlock>
