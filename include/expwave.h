@@ -178,7 +178,12 @@ int32_t expw_set_source_ricker(expw_op* op, int32_t n_src, const int64_t* node_i
 int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* node_idx_dev);
 
 /* Advance the state nsteps steps of size dt starting at time t0 (step s runs
- * from t0 + s dt). traces_dev: NULL or an array of nsteps * n_rec elements. */
+ * from t0 + s dt). traces_dev: NULL or an array of nsteps * n_rec elements.
+ * Faber steps (Sec. 3.2, Faber recurrence and sum, degree m = m products with
+ * the augmented matrix): the recurrence runs with 1/gamma, c0 and c1 of the
+ * ellipse rounded to the state precision, and the coefficients are computed
+ * in FP64 for that rounded ellipse (in FP32 this keeps the coefficients
+ * consistent with the recurrence; expw_get_ellipse reports the unrounded one). */
 int32_t expw_step_faber(expw_op* op, void* state_dev, double t0, double dt, int32_t m,
                         int64_t nsteps, void* traces_dev);
 /* Krylov steps (Arnoldi with modified Gram-Schmidt on the augmented matrix,

@@ -189,19 +189,37 @@ int32_t gather(expw_op* op, const T* S, T* traces, int64_t step) {
 
 // ---------------------------------------------------------------- Faber step
 
+// The ellipse a Faber step in precision T runs with: 1/gamma, c0 and c1 are
+// rounded to T first (gamma taken back from the rounded 1/gamma) and the
+// coefficients are computed in FP64 for that ellipse. The recurrence then
+// uses exactly the scalars its coefficients assume; rounding them after the
+// fact would perturb every step the same way, and in FP32 that systematic
+// error grows linearly with the number of steps. The change of the ellipse
+// itself is a relative 1e-7 at most, well inside the slack of the bound.
+template <typename T>
+struct WorkEllipse {
+  double gamma, c0, c1;
+  explicit WorkEllipse(const expw_op* op) {
+    const T ig = static_cast<T>(1.0 / op->gamma);
+    gamma = 1.0 / static_cast<double>(ig);
+    c0 = static_cast<double>(static_cast<T>(op->c0));
+    c1 = static_cast<double>(static_cast<T>(op->c1));
+  }
+};
+
 template <typename T, int K, int BC, int DIM>
-int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, T* S, T* Abuf, T* Bbuf, T* Cbuf,
-                      const double* a, const double* q, int m) {
+int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse<T>& el, T* S,
+                      T* Abuf, T* Bbuf, T* Cbuf, const double* a, const double* q, int m) {
   const int64_t ns = (DIM + 1) * g.N;
   const unsigned grid = grid_for(g.N);
   FaberTerm<T> c{};
-  c.inv_gamma = static_cast<T>(1.0 / op->gamma);
-  c.c0 = static_cast<T>(op->c0);
+  c.inv_gamma = static_cast<T>(1.0 / el.gamma);
+  c.c0 = static_cast<T>(el.c0);
   // j = 1: v1 = F1 v0 into A; acc = a0 v0 + a1 v1 into C
   c.cpp = T(0);
   c.first = 1;
-  c.a_first = static_cast<T>(a[0]);
-  c.a_j = static_cast<T>(a[1]);
+  split_weight(a[0], &c.a_first, &c.a_first_lo);
+  split_weight(a[1], &c.a_j, &c.a_j_lo);
   const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
   // words per point: reads v_{j-1} (nf) + c^2 (1) [+ v_{j-2} (nf) + sum (nf)],
   // writes the sum (nf) [+ v_j (nf)]
@@ -213,15 +231,15 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, T* S, T* Abuf, T* Bb
   }
   // j = 2: v2 = F1 v1 - 2 c1 v0 into B (v0 = S read pointwise)
   c.first = 0;
-  c.a_first = T(0);
-  c.cpp = static_cast<T>(2.0 * op->c1);
-  c.a_j = static_cast<T>(a[2]);
+  c.a_first = c.a_first_lo = T(0);
+  c.cpp = static_cast<T>(2.0 * el.c1);
+  split_weight(a[2], &c.a_j, &c.a_j_lo);
   launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (m == 2 ? 0 : nf)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, S, m == 2 ? nullptr : Bbuf, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
   T* last = Bbuf;   // v_{j-1}
   T* older = Abuf;  // v_{j-2}
-  c.cpp = static_cast<T>(op->c1);
+  c.cpp = static_cast<T>(el.c1);
   for (int j = 3; j <= m; ++j) {
-    c.a_j = static_cast<T>(a[j]);
+    split_weight(a[j], &c.a_j, &c.a_j_lo);
     const bool fin = (j == m);
     launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (fin ? 0 : nf)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, last, older, fin ? nullptr : older, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
     std::swap(last, older);
@@ -237,7 +255,8 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
   T* Bbuf = Abuf + ns;
   T* Cbuf = Bbuf + ns;
   std::vector<double> a(m + 1), q(m, 0.0), der(EXPW_MAX_TAYLOR), G(EXPW_MAX_TAYLOR);
-  faber_coefficients(op->gamma, op->c0, op->c1, dt, m, a.data());
+  const WorkEllipse<T> el(op);
+  faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a.data());
   const int p = op->taylor_p;
   T* Dbuf = Cbuf + ns;
   T* Ebuf = Dbuf + ns;
@@ -247,7 +266,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
     if (op->n_src > 0) {
       ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
       for (int c = 0; c < p; ++c) G[c] = der[p - 1 - c];
-      faber_source_scalars(op->gamma, op->c0, op->c1, m, p, G.data(), q.data());
+      faber_source_scalars(el.gamma, el.c0, el.c1, m, p, G.data(), q.data());
       const double sc = src_scale(op);
       for (int j = 0; j < m; ++j) q[j] *= sc;
     }
@@ -257,21 +276,21 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
         // a remainder of one term after the fused passes: unfused final term
         auto final_term = [&](const T* vl, const T* vpv, T* acc, T* out, int j) -> int32_t {
           FaberTerm<T> c{};
-          c.inv_gamma = static_cast<T>(1.0 / op->gamma);
-          c.c0 = static_cast<T>(op->c0);
-          c.cpp = static_cast<T>(op->c1);
-          c.a_j = static_cast<T>(a[j]);
+          c.inv_gamma = static_cast<T>(1.0 / el.gamma);
+          c.c0 = static_cast<T>(el.c0);
+          c.cpp = static_cast<T>(el.c1);
+          split_weight(a[j], &c.a_j, &c.a_j_lo);
           launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, 13.0 * g.N * sizeof(T), k_faber_term<T, K, BC, DIM>, dim3(grid_for(g.N)), dim3(kBlock), g, vl, vpv, nullptr, acc, out, c, make_src<T>(op, q[j - 1]));
           return check_launch("faber final term");
         };
         rc = faber_fused_2d<T>(op->stream, &op->prof, g, make_src<T>(op, 0.0), S, Abuf, Bbuf, Cbuf,
-                               Dbuf, Ebuf, a.data(), q.data(), m, fuse, op->gamma, op->c0, op->c1,
+                               Dbuf, Ebuf, a.data(), q.data(), m, fuse, el.gamma, el.c0, el.c1,
                                final_term);
       } else {
-        rc = faber_unfused<T, K, BC, DIM>(op, g, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
+        rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
       }
     } else {
-      rc = faber_unfused<T, K, BC, DIM>(op, g, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
+      rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
     }
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;

@@ -42,10 +42,10 @@ struct FusedTile {
 
 template <typename T, int S>
 struct FusedArgs {
-  T inv_gamma, c0, a_first;
+  T inv_gamma, c0, a_first, a_first_lo;  // weights as hi + lo (see FaberTerm)
   int32_t first;  // first pass of a step: acc = a_first * v0, no v_{j-2}
   int32_t tiles_x, tiles_y, band_w;
-  T a[S], cpp[S], q[S];
+  T a[S], a_lo[S], cpp[S], q[S];
 };
 
 // One pass of exactly S recurrence terms. 2D grids with 3 * points < 2^31.
@@ -140,9 +140,9 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
     for (int t = tid; t < TX * TY; t += kFusedNT) {
       const int ty = t / TX, tx = t - ty * TX;
       const int l = (ty + H) * EX + tx + H;
-      sacc[t] = c.a_first * cur[l];
-      sacc[TX * TY + t] = c.a_first * cur[E + l];
-      sacc[2 * TX * TY + t] = c.a_first * cur[2 * E + l];
+      sacc[t] = add_weighted(T(0), c.a_first, c.a_first_lo, cur[l]);
+      sacc[TX * TY + t] = add_weighted(T(0), c.a_first, c.a_first_lo, cur[E + l]);
+      sacc[2 * TX * TY + t] = add_weighted(T(0), c.a_first, c.a_first_lo, cur[2 * E + l]);
     }
   }
 
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
       }
     }
     __syncthreads();  // every read of v_{j-1} is done
-    const T aj = c.a[r];
+    const T aj = c.a[r], ajl = c.a_lo[r];
 #pragma unroll
     for (int i = 0; i < NSL; ++i) {
       if (r <= last[i]) {
@@ -187,9 +187,9 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
         cur[2 * E + l] = nv[i][2];
         if (last[i] == S - 1 && lx >= H && lx < H + TX && ly >= H && ly < H + TY) {
           const int t = (ly - H) * TX + (lx - H);
-          sacc[t] += aj * nv[i][0];
-          sacc[TX * TY + t] += aj * nv[i][1];
-          sacc[2 * TX * TY + t] += aj * nv[i][2];
+          sacc[t] = add_weighted(sacc[t], aj, ajl, nv[i][0]);
+          sacc[TX * TY + t] = add_weighted(sacc[TX * TY + t], aj, ajl, nv[i][1]);
+          sacc[2 * TX * TY + t] = add_weighted(sacc[2 * TX * TY + t], aj, ajl, nv[i][2]);
         }
       }
     }
@@ -243,10 +243,10 @@ int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<
   c.inv_gamma = static_cast<T>(1.0 / gamma);
   c.c0 = static_cast<T>(c0);
   c.first = first ? 1 : 0;
-  c.a_first = first ? static_cast<T>(a[0]) : T(0);
+  if (first) split_weight(a[0], &c.a_first, &c.a_first_lo);
   for (int r = 0; r < S; ++r) {
     const int jj = j + r;
-    c.a[r] = static_cast<T>(a[jj]);
+    split_weight(a[jj], &c.a[r], &c.a_lo[r]);
     c.cpp[r] = static_cast<T>(jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1));
     c.q[r] = static_cast<T>(q[jj - 1]);
   }

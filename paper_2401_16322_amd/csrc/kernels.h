@@ -24,12 +24,29 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo<T, K, DIM> g, const T* __r
 //   v_j = (H~ v_{j-1}) / gamma - c0 v_{j-1} - cpp v_{j-2}
 //   acc = (first ? a_first v_{j-1} : acc) + a_j v_j
 // cpp is 0 for j = 1, 2 c1 for j = 2 and c1 beyond; the source adds
-// src.q * amp_s to the pressure of v_j at each source node.
+// src.q * amp_s to the pressure of v_j at each source node. Each weight a is
+// given as hi + lo in T (lo = a - hi, zero in FP64): the same rounding of a
+// weight would otherwise repeat in every step and accumulate.
 template <typename T>
 struct FaberTerm {
-  T inv_gamma, c0, cpp, a_first, a_j;
+  T inv_gamma, c0, cpp, a_first, a_j, a_first_lo, a_j_lo;
   int32_t first;
 };
+
+// acc + (hi + lo) x, hi and lo the two parts of one weight.
+template <typename T>
+__device__ __forceinline__ T add_weighted(T acc, T hi, T lo, T x) {
+  acc = fma(hi, x, acc);
+  if constexpr (sizeof(T) == 4) acc = fma(lo, x, acc);
+  return acc;
+}
+
+// The two parts of a weight in T.
+template <typename T>
+inline void split_weight(double a, T* hi, T* lo) {
+  *hi = static_cast<T>(a);
+  *lo = static_cast<T>(a - static_cast<double>(*hi));
+}
 
 // vout may alias vpp and acc_out may alias acc_in or vpp (pointwise reuse);
 // vp is read with a halo and must not alias any output. vout == nullptr skips
@@ -50,8 +67,8 @@ __global__ __launch_bounds__(kBlock) void k_faber_term(Geo<T, K, DIM> g, const T
     T v = o[f] * c.inv_gamma - c.c0 * s[f];
     if (vpp) v -= c.cpp * vpp[e];
     if (f == 0) v += src_value(src, idx);
-    T acc = c.first ? c.a_first * s[f] : acc_in[e];
-    acc += c.a_j * v;
+    T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, s[f]) : acc_in[e];
+    acc = add_weighted(acc, c.a_j, c.a_j_lo, v);
     if (vout) vout[e] = v;
     acc_out[e] = acc;
   }
