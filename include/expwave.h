@@ -116,6 +116,20 @@ int32_t expw_ellipse(double x_lo, double B, double* gamma, double* c0, double* c
  * coefficients of exp(dt gamma (w + c0 + c1/w)). a has m+1 entries. */
 int32_t expw_faber_coefficients(double gamma, double c0, double c1, double dt, int32_t m, double* a);
 
+/* The ellipse a Faber step with state dtype runs with (see expw_step_faber):
+ * 1/gamma, c0 and c1 rounded to that precision, gamma = 1/(rounded 1/gamma).
+ * The identity for EXPW_F64. */
+int32_t expw_step_ellipse(int32_t dtype, double gamma, double c0, double c1, double* gamma_step,
+                          double* c0_step, double* c1_step);
+
+/* Dense-output weights (Sec. 3.2, Faber approximation): the terms
+ * v_j = F_j(H~) [u_n; e_p] of one step combine to the solution at any
+ * t_n + tau, tau >= 0, with the Faber coefficients of exp(tau z) on the same
+ * ellipse: coef[t * (m + 1) + j] = a_j(taus[t]) (a_j(0) = delta_j0). Pass the
+ * step ellipse (expw_step_ellipse) to match a library step exactly. */
+int32_t expw_faber_dense_coefficients(double gamma, double c0, double c1, int32_t m, int32_t n_tau,
+                                      const double* taus, double* coef);
+
 /* Ricker wavelet g(t) = (1 - 2 a tau^2) exp(-a tau^2), a = (pi f_peak)^2,
  * tau = t - t_delay, and its derivatives: out[k] = g^(k)(t), k = 0..p-1. */
 int32_t expw_ricker_derivatives(double t, double f_peak, double t_delay, int32_t p, double* out);
@@ -186,6 +200,24 @@ int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* node_idx_d
  * consistent with the recurrence; expw_get_ellipse reports the unrounded one). */
 int32_t expw_step_faber(expw_op* op, void* state_dev, double t0, double dt, int32_t m,
                         int64_t nsteps, void* traces_dev);
+/* Faber steps that also record every term at the receivers: the pressure of
+ * v_j = F_j(H~) [u_n; e_p], j = 0..m, at receiver r goes to
+ * term_traces_dev[(s * (m + 1) + j) * n_rec + r] for step s (device array of
+ * nsteps * (m + 1) * n_rec elements, state dtype; requires receivers). The
+ * state and traces are those of expw_step_faber (terms are computed one per
+ * sweep here). */
+int32_t expw_step_faber_dense(expw_op* op, void* state_dev, double t0, double dt, int32_t m,
+                              int64_t nsteps, void* traces_dev, void* term_traces_dev);
+/* Receiver values between steps from recorded terms:
+ * out_dev[i * n_rec + r] = sum_j coef_dev[i * (m + 1) + j] *
+ * term_traces_dev[(sample_step_dev[i] * (m + 1) + j) * n_rec + r] for the
+ * n_samples samples i (sample_step_dev: int64 step indices in [0, nsteps);
+ * an index outside gives NaN; coef_dev: FP64 weights from
+ * expw_faber_dense_coefficients). Sums in FP64; out_dev in the state dtype. */
+int32_t expw_faber_dense_output(expw_op* op, int32_t m, int64_t n_samples,
+                                const int64_t* sample_step_dev, const double* coef_dev,
+                                const void* term_traces_dev, int64_t nsteps, void* out_dev);
+
 /* Krylov steps (Arnoldi with modified Gram-Schmidt on the augmented matrix,
  * then the small exponential, see expw_set_krylov_expm). Requires
  * k <= max_krylov_k. */

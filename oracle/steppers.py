@@ -92,6 +92,42 @@ def faber_step(prob, U, t, dt, m, p=8, ellipse=None):
     return acc[: prob.grid.nstate].copy()
 
 
+def faber_terms(prob, U, t, m, p=8, ellipse=None):
+    """The terms v_j = F_j(H~) [U; e_p], j = 0..m, of a Faber step from t.
+
+    They depend on the ellipse and on t (through the source columns) but not
+    on the step size: only the weights a_j(dt) do (Sec. 3.2, Faber series).
+    """
+    gamma, c0, c1 = ellipse if ellipse is not None else prob.ellipse()
+    G = prob.src.w_columns(t, p) if prob.src is not None else None
+    terms = [_augment(prob, U, p)]
+    for j in range(1, m + 1):
+        v = apply_Htilde(prob, terms[j - 1], G) / gamma - c0 * terms[j - 1]
+        if j == 2:
+            v = v - 2.0 * c1 * terms[0]
+        elif j > 2:
+            v = v - c1 * terms[j - 2]
+        terms.append(v)
+    return terms
+
+
+def faber_dense(prob, U, t, m, taus, nodes, p=8, ellipse=None):
+    """Pressure at `nodes` at t + tau for each tau in taus from one set of
+    Faber terms: sum_j a_j(tau) v_j, with a_j(0) = delta_j0 (exp(0) = I)."""
+    gamma, c0, c1 = ellipse if ellipse is not None else prob.ellipse()
+    nodes = np.asarray(nodes, dtype=np.int64)
+    at_nodes = np.array([v[nodes] for v in faber_terms(prob, U, t, m, p, (gamma, c0, c1))])
+    out = np.zeros((len(taus), nodes.size))
+    for i, tau in enumerate(taus):
+        if tau == 0.0:
+            a = np.zeros(m + 1)
+            a[0] = 1.0
+        else:
+            a = faber_coefficients(gamma, c0, c1, tau, m)
+        out[i] = a @ at_nodes
+    return out
+
+
 def arnoldi(prob, x, G, k, breakdown=1e-14):
     """Arnoldi with modified Gram-Schmidt on H~: (beta, Q list, Hess, k_eff)."""
     beta = float(np.linalg.norm(x))

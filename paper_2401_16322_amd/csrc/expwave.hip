@@ -200,18 +200,24 @@ template <typename T>
 struct WorkEllipse {
   double gamma, c0, c1;
   explicit WorkEllipse(const expw_op* op) {
-    const T ig = static_cast<T>(1.0 / op->gamma);
-    gamma = 1.0 / static_cast<double>(ig);
-    c0 = static_cast<double>(static_cast<T>(op->c0));
-    c1 = static_cast<double>(static_cast<T>(op->c1));
+    step_ellipse(sizeof(T) == 4 ? EXPW_F32 : EXPW_F64, op->gamma, op->c0, op->c1, &gamma, &c0,
+                 &c1);
   }
 };
 
+// One Faber step, one term per sweep. term_out (nullable): receives the
+// pressure of every term v_0..v_m at the receivers ((m + 1) * n_rec values).
 template <typename T, int K, int BC, int DIM>
 int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse<T>& el, T* S,
-                      T* Abuf, T* Bbuf, T* Cbuf, const double* a, const double* q, int m) {
+                      T* Abuf, T* Bbuf, T* Cbuf, const double* a, const double* q, int m,
+                      T* term_out) {
   const int64_t ns = (DIM + 1) * g.N;
   const unsigned grid = grid_for(g.N);
+  const bool keep = term_out != nullptr && op->n_rec > 0;
+  auto record = [&](const T* v, int j) -> int32_t {
+    return keep ? gather<T>(op, v, term_out + static_cast<int64_t>(j) * op->n_rec, 0) : EXPW_OK;
+  };
+  if (int32_t rc = record(S, 0)) return rc;
   FaberTerm<T> c{};
   c.inv_gamma = static_cast<T>(1.0 / el.gamma);
   c.c0 = static_cast<T>(el.c0);
@@ -223,32 +229,44 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse<T>
   const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
   // words per point: reads v_{j-1} (nf) + c^2 (1) [+ v_{j-2} (nf) + sum (nf)],
   // writes the sum (nf) [+ v_j (nf)]
-  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1 + nf + (m == 1 ? 0 : nf)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, nullptr, m == 1 ? nullptr : Abuf, nullptr, Cbuf, c, make_src<T>(op, q[0]));
+  T* v1 = (m == 1 && !keep) ? nullptr : Abuf;
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1 + nf + (v1 ? nf : 0)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, nullptr, v1, nullptr, Cbuf, c, make_src<T>(op, q[0]));
+  if (int32_t rc = check_launch("faber j=1")) return rc;
+  if (int32_t rc = record(Abuf, 1)) return rc;
   if (m == 1) {
     if (hipMemcpyAsync(S, Cbuf, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
       return fail(EXPW_EDEVICE, "faber: copy failed");
-    return check_launch("faber j=1");
+    return EXPW_OK;
   }
   // j = 2: v2 = F1 v1 - 2 c1 v0 into B (v0 = S read pointwise)
   c.first = 0;
   c.a_first = c.a_first_lo = T(0);
   c.cpp = static_cast<T>(2.0 * el.c1);
   split_weight(a[2], &c.a_j, &c.a_j_lo);
-  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (m == 2 ? 0 : nf)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, S, m == 2 ? nullptr : Bbuf, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
+  T* v2 = (m == 2 && !keep) ? nullptr : Bbuf;
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (v2 ? nf : 0)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, S, v2, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
+  if (int32_t rc = check_launch("faber j=2")) return rc;
+  if (int32_t rc = record(Bbuf, 2)) return rc;
   T* last = Bbuf;   // v_{j-1}
   T* older = Abuf;  // v_{j-2}
   c.cpp = static_cast<T>(el.c1);
   for (int j = 3; j <= m; ++j) {
     split_weight(a[j], &c.a_j, &c.a_j_lo);
     const bool fin = (j == m);
-    launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (fin ? 0 : nf)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, last, older, fin ? nullptr : older, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
+    T* vj = (fin && !keep) ? nullptr : older;
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (vj ? nf : 0)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, last, older, vj, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
+    if (int32_t rc = check_launch("faber term")) return rc;
+    if (int32_t rc = record(older, j)) return rc;
     std::swap(last, older);
   }
-  return check_launch("faber term");
+  return EXPW_OK;
 }
 
+// Faber steps; term_traces (nullable) records every term at the receivers
+// and then runs the terms one per sweep.
 template <typename T, int K, int BC, int DIM>
-int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nsteps, T* traces) {
+int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nsteps, T* traces,
+                   T* term_traces) {
   const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
   const int64_t ns = (DIM + 1) * g.N;
   T* Abuf = reinterpret_cast<T*>(op->ws + op->off_big);
@@ -271,8 +289,9 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
       for (int j = 0; j < m; ++j) q[j] *= sc;
     }
     int32_t rc = EXPW_OK;
+    T* term_out = term_traces ? term_traces + st * (m + 1) * op->n_rec : nullptr;
     if constexpr (DIM == 2 && K == 2 && BC == 0) {
-      if (fuse > 1) {
+      if (fuse > 1 && !term_out) {
         // a remainder of one term after the fused passes: unfused final term
         auto final_term = [&](const T* vl, const T* vpv, T* acc, T* out, int j) -> int32_t {
           FaberTerm<T> c{};
@@ -287,10 +306,12 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
                                Dbuf, Ebuf, a.data(), q.data(), m, fuse, el.gamma, el.c0, el.c1,
                                final_term);
       } else {
-        rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
+        rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m,
+                                          term_out);
       }
     } else {
-      rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m);
+      rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m,
+                                        term_out);
     }
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
@@ -782,8 +803,40 @@ int32_t expw_step_faber(expw_op* op, void* state, double t0, double dt, int32_t 
   return dispatch(op, [&](auto cfg) {
     using C = decltype(cfg);
     using T = typename C::type;
-    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces));
+    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), nullptr);
   });
+}
+
+int32_t expw_step_faber_dense(expw_op* op, void* state, double t0, double dt, int32_t m,
+                              int64_t nsteps, void* traces, void* term_traces) {
+  if (int32_t rc = check_step_args(op, state, dt, nsteps)) return rc;
+  if (m < 1 || m > 1024) return fail(EXPW_EINVAL, "Faber degree m must be in [1, 1024]");
+  if (op->n_rec == 0) return fail(EXPW_EINVAL, "dense output needs receivers (expw_set_receivers)");
+  if (!term_traces) return fail(EXPW_EINVAL, "term_traces is NULL");
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), static_cast<T*>(term_traces));
+  });
+}
+
+int32_t expw_faber_dense_output(expw_op* op, int32_t m, int64_t n_samples,
+                                const int64_t* sample_step, const double* coef,
+                                const void* term_traces, int64_t nsteps, void* out) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (m < 0 || m > 1024 || n_samples < 0 || nsteps < 0)
+    return fail(EXPW_EINVAL, "expw_faber_dense_output: invalid sizes");
+  if (op->n_rec == 0) return fail(EXPW_EINVAL, "dense output needs receivers (expw_set_receivers)");
+  if (n_samples == 0) return EXPW_OK;
+  if (!sample_step || !coef || !term_traces || !out)
+    return fail(EXPW_EINVAL, "expw_faber_dense_output: NULL array");
+  const int64_t items = n_samples * op->n_rec;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(65536, (items + kBlock - 1) / kBlock));
+  if (op->g.dtype == EXPW_F32)
+    k_dense_combine<float><<<grid, kBlock, 0, op->stream>>>(m, op->n_rec, n_samples, sample_step, coef, static_cast<const float*>(term_traces), nsteps, static_cast<float*>(out));
+  else
+    k_dense_combine<double><<<grid, kBlock, 0, op->stream>>>(m, op->n_rec, n_samples, sample_step, coef, static_cast<const double*>(term_traces), nsteps, static_cast<double*>(out));
+  return check_launch("dense output");
 }
 
 int32_t expw_step_krylov(expw_op* op, void* state, double t0, double dt, int32_t k, int64_t nsteps,

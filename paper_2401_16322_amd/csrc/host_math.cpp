@@ -239,6 +239,20 @@ bool expm(int k, const double* A, double* E) {
   return true;
 }
 
+
+void step_ellipse(int dtype, double gamma, double c0, double c1, double* gs, double* c0s,
+                  double* c1s) {
+  if (dtype == EXPW_F32) {
+    const float ig = static_cast<float>(1.0 / gamma);
+    *gs = 1.0 / static_cast<double>(ig);
+    *c0s = static_cast<double>(static_cast<float>(c0));
+    *c1s = static_cast<double>(static_cast<float>(c1));
+  } else {
+    *gs = gamma;
+    *c0s = c0;
+    *c1s = c1;
+  }
+}
 }  // namespace expw
 
 // ------------------------------------------------------------------ C ABI (host only)
@@ -309,6 +323,34 @@ int32_t expw_faber_coefficients(double gamma, double c0, double c1, double dt, i
       !std::isfinite(c0))
     return expw::fail(EXPW_EINVAL, "expw_faber_coefficients: invalid argument");
   expw::faber_coefficients(gamma, c0, c1, dt, m, a);
+  return EXPW_OK;
+}
+
+int32_t expw_step_ellipse(int32_t dtype, double gamma, double c0, double c1, double* gs,
+                          double* c0s, double* c1s) {
+  if ((dtype != EXPW_F32 && dtype != EXPW_F64) || !(gamma > 0.0) || !std::isfinite(gamma) ||
+      !std::isfinite(c0) || !(std::fabs(c1) < 1.0) || !gs || !c0s || !c1s)
+    return expw::fail(EXPW_EINVAL, "expw_step_ellipse: invalid argument");
+  expw::step_ellipse(dtype, gamma, c0, c1, gs, c0s, c1s);
+  return EXPW_OK;
+}
+
+int32_t expw_faber_dense_coefficients(double gamma, double c0, double c1, int32_t m, int32_t n_tau,
+                                      const double* taus, double* coef) {
+  if (!(gamma > 0.0) || !std::isfinite(gamma) || m < 0 || n_tau < 0 || !(std::fabs(c1) < 1.0) ||
+      !std::isfinite(c0) || (n_tau > 0 && (!taus || !coef)))
+    return expw::fail(EXPW_EINVAL, "expw_faber_dense_coefficients: invalid argument");
+  for (int32_t t = 0; t < n_tau; ++t)
+    if (!(taus[t] >= 0.0) || !std::isfinite(taus[t]))
+      return expw::fail(EXPW_EINVAL, "expw_faber_dense_coefficients: tau must be finite and >= 0");
+  for (int32_t t = 0; t < n_tau; ++t) {
+    double* a = coef + static_cast<int64_t>(t) * (m + 1);
+    if (taus[t] == 0.0) {  // exp(0) = I: only F_0 = I contributes
+      for (int j = 0; j <= m; ++j) a[j] = j == 0 ? 1.0 : 0.0;
+    } else {
+      expw::faber_coefficients(gamma, c0, c1, taus[t], m, a);
+    }
+  }
   return EXPW_OK;
 }
 

@@ -24,5 +24,9 @@ void ricker_derivatives(double t, double f_peak, double t_delay, int p, double* 
 void faber_source_scalars(double gamma, double c0, double c1, int m, int p, const double* G,
                           double* q);
 bool expm(int k, const double* A, double* E);
+// The ellipse a Faber step in state precision dtype runs with: 1/gamma, c0
+// and c1 rounded to that precision, gamma taken back from the rounded 1/gamma.
+void step_ellipse(int dtype, double gamma, double c0, double c1, double* gs, double* c0s,
+                  double* c1s);
 
 }  // namespace expw

@@ -153,6 +153,32 @@ __global__ __launch_bounds__(kBlock) void k_gather(const T* __restrict__ p,
   if (i < n) out[i] = p[rec[i]];
 }
 
+// Dense output: out[i * n_rec + r] = sum_j coef[i * (m + 1) + j] *
+// term[(step_i * (m + 1) + j) * n_rec + r] (FP64 sums); a step index outside
+// [0, nsteps) gives NaN. Grid-stride over the n_samples * n_rec items.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_combine(int32_t m, int32_t n_rec, int64_t n_samples,
+                                                          const int64_t* __restrict__ sample_step,
+                                                          const double* __restrict__ coef,
+                                                          const T* __restrict__ term, int64_t nsteps,
+                                                          T* __restrict__ out) {
+  const int64_t items = n_samples * n_rec;
+  for (int64_t it = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; it < items;
+       it += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t i = it / n_rec, r = it - i * n_rec;
+    const int64_t st = sample_step[i];
+    double acc = 0.0;
+    if (st < 0 || st >= nsteps) {
+      acc = __builtin_nan("");
+    } else {
+      const T* tv = term + st * (m + 1) * n_rec + r;
+      const double* c = coef + i * (m + 1);
+      for (int j = 0; j <= m; ++j) acc += c[j] * static_cast<double>(tv[static_cast<int64_t>(j) * n_rec]);
+    }
+    out[it] = static_cast<T>(acc);
+  }
+}
+
 // max over c2 with non-finite or non-positive entries mapped to +inf
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_c2_max(const T* __restrict__ c2, int64_t n,

@@ -51,6 +51,8 @@ SIGNATURES = {
     "expw_spectrum_rectangle": (_i32, [_pgrid, _dbl, _pd, _pd]),
     "expw_ellipse": (_i32, [_dbl, _dbl, _pd, _pd, _pd]),
     "expw_faber_coefficients": (_i32, [_dbl, _dbl, _dbl, _dbl, _i32, _pd]),
+    "expw_step_ellipse": (_i32, [_i32, _dbl, _dbl, _dbl, _pd, _pd, _pd]),
+    "expw_faber_dense_coefficients": (_i32, [_dbl, _dbl, _dbl, _i32, _i32, _pd, _pd]),
     "expw_ricker_derivatives": (_i32, [_dbl, _dbl, _dbl, _i32, _pd]),
     "expw_faber_source_scalars": (_i32, [_dbl, _dbl, _dbl, _i32, _i32, _pd, _pd]),
     "expw_expm": (_i32, [_i32, _pd, _pd]),
@@ -65,6 +67,8 @@ SIGNATURES = {
     "expw_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
     "expw_set_receivers": (_i32, [_vp, _i32, _vp]),
     "expw_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
+    "expw_step_faber_dense": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp, _vp]),
+    "expw_faber_dense_output": (_i32, [_vp, _i32, _i64, _vp, _vp, _vp, _i64, _vp]),
     "expw_step_krylov": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_rk4": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
     "expw_step_leapfrog": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
@@ -165,6 +169,20 @@ def expw_faber_coefficients(gamma, c0, c1, dt, m):
     return out
 
 
+def expw_step_ellipse(dtype, gamma, c0, c1):
+    g, a, b = _dbl(), _dbl(), _dbl()
+    _check(load().expw_step_ellipse(int(dtype), gamma, c0, c1, ctypes.byref(g), ctypes.byref(a),
+                                    ctypes.byref(b)))
+    return g.value, a.value, b.value
+
+
+def expw_faber_dense_coefficients(gamma, c0, c1, m, taus):
+    taus = np.ascontiguousarray(taus, dtype=np.float64).ravel()
+    out = np.zeros((taus.size, m + 1))
+    _check(load().expw_faber_dense_coefficients(gamma, c0, c1, m, taus.size, _dptr(taus), _dptr(out)))
+    return out
+
+
 def expw_ricker_derivatives(t, f_peak, t_delay, p):
     out = np.zeros(p)
     _check(load().expw_ricker_derivatives(t, f_peak, t_delay, p, _dptr(out)))
@@ -243,6 +261,16 @@ def expw_step_faber(op, state_ptr, t0, dt, m, nsteps, traces_ptr=None):
     _check(load().expw_step_faber(op, state_ptr, t0, dt, m, nsteps, traces_ptr))
 
 
+def expw_step_faber_dense(op, state_ptr, t0, dt, m, nsteps, traces_ptr, term_traces_ptr):
+    _check(load().expw_step_faber_dense(op, state_ptr, t0, dt, m, nsteps, traces_ptr, term_traces_ptr))
+
+
+def expw_faber_dense_output(op, m, n_samples, sample_step_ptr, coef_ptr, term_traces_ptr, nsteps,
+                            out_ptr):
+    _check(load().expw_faber_dense_output(op, m, n_samples, sample_step_ptr, coef_ptr,
+                                          term_traces_ptr, nsteps, out_ptr))
+
+
 def expw_step_krylov(op, state_ptr, t0, dt, k, nsteps, traces_ptr=None):
     _check(load().expw_step_krylov(op, state_ptr, t0, dt, k, nsteps, traces_ptr))
 
@@ -306,6 +334,7 @@ class Operator:
         if c2.dtype not in (torch.float32, torch.float64):
             raise ValueError("c2 must be float32 or float64")
         self.dtype = c2.dtype
+        self.dtype_code = EXPW_F32 if c2.dtype == torch.float32 else EXPW_F64
         self.device = c2.device
         self.n = tuple(int(v) for v in n)
         self.ndim = len(self.n)
@@ -387,6 +416,44 @@ class Operator:
         self._check_state(state)
         self._sync_stream()
         expw_step_faber(self.op, state.data_ptr(), t0, dt, m, nsteps, self._traces_ptr(traces, nsteps))
+
+    def step_faber_dense(self, state, t0, dt, m, nsteps, term_traces, traces=None):
+        """Faber steps that record every term v_0..v_m at the receivers into
+        term_traces (nsteps * (m + 1) * n_rec values of the grid dtype)."""
+        self._check_state(state)
+        if self._rec is None:
+            raise ValueError("no receivers set")
+        need = nsteps * (m + 1) * self._rec.numel()
+        if term_traces.dtype != self.dtype or not term_traces.is_cuda \
+                or term_traces.numel() < need or not term_traces.is_contiguous():
+            raise ValueError("term_traces must hold nsteps * (m + 1) * n_rec values of the grid dtype")
+        self._sync_stream()
+        expw_step_faber_dense(self.op, state.data_ptr(), t0, dt, m, nsteps,
+                              self._traces_ptr(traces, nsteps), term_traces.data_ptr())
+
+    def dense_coefficients(self, m, taus):
+        """Weights a_j(tau) (len(taus) x (m + 1)) of the ellipse the steps run with."""
+        g, c0, c1 = expw_step_ellipse(self.dtype_code, *self.ellipse)
+        return expw_faber_dense_coefficients(g, c0, c1, m, taus)
+
+    def dense_output(self, m, term_traces, nsteps, sample_step, coef):
+        """Receiver values at sample i: sum_j coef[i, j] * term j of step
+        sample_step[i] (torch tensors on the GPU: int64 steps, float64 coef)."""
+        torch = self._torch
+        if self._rec is None:
+            raise ValueError("no receivers set")
+        sample_step = sample_step.to(device=term_traces.device, dtype=torch.int64).contiguous()
+        coef = coef.to(device=term_traces.device, dtype=torch.float64).contiguous()
+        ns = sample_step.numel()
+        if coef.numel() != ns * (m + 1):
+            raise ValueError("coef must hold n_samples * (m + 1) weights")
+        if term_traces.dtype != self.dtype or term_traces.numel() < nsteps * (m + 1) * self._rec.numel():
+            raise ValueError("term_traces too small")
+        out = torch.empty(ns * self._rec.numel(), dtype=self.dtype, device=term_traces.device)
+        self._sync_stream()
+        expw_faber_dense_output(self.op, m, ns, sample_step.data_ptr(), coef.data_ptr(),
+                                term_traces.data_ptr(), nsteps, out.data_ptr())
+        return out.view(ns, self._rec.numel())
 
     def step_krylov(self, state, t0, dt, k, nsteps=1, traces=None):
         self._check_state(state)

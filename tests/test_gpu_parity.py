@@ -288,3 +288,70 @@ def test_invalid_arguments_raise():
     with pytest.raises(ExpwError) as e:
         Operator((20, 30), 10.0, bad)
     assert e.value.status == -4
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_faber_dense_output_matches_oracle(dtype):
+    """Faber steps that record every term at the receivers: the state equals
+    the oracle's (and the default fused path's), the recorded terms equal the
+    oracle's terms at the receivers, and the dense output at tau in
+    {0, dt/3, dt/2, dt} equals the oracle's sum of a_j(tau) v_j."""
+    import torch
+    from oracle.steppers import faber_dense, faber_step, faber_terms
+    case = make_case((70, 45), dtype, seed=21, n_src=2)
+    g = case.prob.grid
+    rec = np.array(sorted({0, g.npts - 1, 7 * 70 + 3, 22 * 70 + 35, 44 * 70 + 69, case.nodes[0]}),
+                   dtype=np.int64)
+    case.op.set_receivers(rec)
+    m, dt, nst, t0 = 12, 2e-3, 3, 0.03
+    tdt = case.torch_dtype
+    U = to_dev(case, case.U0)
+    terms = torch.zeros(nst * (m + 1) * rec.size, dtype=tdt, device="cuda")
+    tr = torch.zeros(nst * rec.size, dtype=tdt, device="cuda")
+    case.op.step_faber_dense(U, t0, dt, m, nst, terms, traces=tr)
+    U2 = to_dev(case, case.U0)
+    case.op.step_faber(U2, t0, dt, m, nst)
+    ell = case.prob.ellipse()
+    Us = [case.U0]
+    for s in range(nst):
+        Us.append(faber_step(case.prob, Us[-1], t0 + s * dt, dt, m, p=case.p, ellipse=ell))
+    tol = TOL[dtype]
+    tight = 1e-13 if dtype == "float64" else 2e-6
+    assert rel_l2(U.cpu().numpy(), Us[-1]) <= tol
+    assert rel_l2(U.cpu().numpy(), U2.cpu().numpy()) <= tight
+    gt = terms.cpu().numpy().reshape(nst, m + 1, rec.size)
+    for s in range(nst):
+        ot = np.array([v[rec] for v in faber_terms(case.prob, Us[s], t0 + s * dt, m, case.p, ell)])
+        assert rel_l2(gt[s], ot) <= tol
+    taus = [0.0, dt / 3, dt / 2, dt]
+    coef = case.op.dense_coefficients(m, taus)
+    steps = torch.tensor(np.repeat(np.arange(nst), len(taus)))
+    coefs = torch.tensor(np.tile(coef, (nst, 1)))
+    out = case.op.dense_output(m, terms, nst, steps, coefs).cpu().numpy()
+    for s in range(nst):
+        od = faber_dense(case.prob, Us[s], t0 + s * dt, m, taus, rec, case.p, ell)
+        assert rel_l2(out[s * 4:(s + 1) * 4], od) <= tol
+    # tau = dt reproduces the receiver trace of the same step
+    assert rel_l2(out[3::4], tr.view(nst, -1).cpu().numpy()) <= tight
+
+
+@pytest.mark.gpu
+def test_faber_dense_output_edge_cases():
+    """An out-of-range step index gives NaN; dense steps need receivers."""
+    import torch
+    from paper_2401_16322_amd import expwave as xw
+    case = make_case((20, 12), "float64", seed=22)
+    U = to_dev(case, case.U0)
+    with pytest.raises(xw.ExpwError):
+        xw.expw_step_faber_dense(case.op.op, U.data_ptr(), 0.0, 1e-3, 4, 1, None,
+                                 torch.zeros(100, dtype=torch.float64, device="cuda").data_ptr())
+    rec = np.array([5, 17], dtype=np.int64)
+    case.op.set_receivers(rec)
+    terms = torch.zeros(2 * 5 * rec.size, dtype=torch.float64, device="cuda")
+    case.op.step_faber_dense(U, 0.0, 1e-3, 4, 2, terms)
+    out = case.op.dense_output(4, terms, 2, torch.tensor([1, 2, -1]),
+                               torch.ones(3 * 5, dtype=torch.float64)).cpu().numpy()
+    assert np.all(np.isfinite(out[0])) and np.all(np.isnan(out[1])) and np.all(np.isnan(out[2]))
+    t = terms.cpu().numpy().reshape(2, 5, rec.size)
+    assert np.allclose(out[0], t[1].sum(axis=0), rtol=1e-14, atol=0)

@@ -153,3 +153,28 @@ def test_workspace_grows_with_krylov_dimension():
     ns = 3 * 101 * 101
     assert w0 >= 5 * ns * 8
     assert w40 >= 41 * ns * 8
+
+
+@pytest.mark.parametrize("ell", [(1262.1, -0.2377, -0.6639), (678.8, -0.4420, -0.3750)])
+def test_step_ellipse_rounds_to_the_state_precision(ell):
+    g, c0, c1 = ell
+    assert xw.expw_step_ellipse(xw.EXPW_F64, g, c0, c1) == (g, c0, c1)
+    gs, c0s, c1s = xw.expw_step_ellipse(xw.EXPW_F32, g, c0, c1)
+    # the recurrence's scalars are exactly representable in FP32
+    assert float(np.float32(1.0 / gs)) == 1.0 / gs
+    assert float(np.float32(c0s)) == c0s and float(np.float32(c1s)) == c1s
+    assert abs(gs - g) <= 2 ** -23 * g and abs(c0s - c0) <= 2 ** -24 * abs(c0) \
+        and abs(c1s - c1) <= 2 ** -24 * abs(c1)
+
+
+def test_dense_coefficients_match_oracle_and_identity_at_zero():
+    g, c0, c1 = 1262.1, -0.2377, -0.6639
+    taus = [0.0, 3e-4, 1e-3, 4e-3]
+    C = xw.expw_faber_dense_coefficients(g, c0, c1, 24, taus)
+    assert C.shape == (4, 25)
+    assert C[0, 0] == 1.0 and not np.any(C[0, 1:])
+    for i, tau in enumerate(taus[1:], start=1):
+        ref = faber_coefficients(g, c0, c1, tau, 24)
+        assert np.max(np.abs(C[i] - ref)) <= 1e-13 * np.max(np.abs(ref))
+    with pytest.raises(xw.ExpwError):
+        xw.expw_faber_dense_coefficients(g, c0, c1, 8, [-1e-3])

@@ -155,3 +155,32 @@ def test_augmented_source_run_matches_duhamel_over_many_steps():
     Uf, _, _ = run(prob, "faber", U0, 0.0, dt, ns, m=24, p=12)
     Ue = ExactPropagator(prob, nquad=30).run(U0, 0.0, dt, ns)
     assert np.linalg.norm(Uf - Ue) <= 1e-10 * np.linalg.norm(Ue)
+
+
+def test_dense_output_at_zero_and_full_step():
+    """Dense output from one set of terms: tau = 0 gives the state itself,
+    tau = dt gives the Faber step (computed separately by faber_step)."""
+    from oracle.steppers import faber_dense
+    prob = _small_problem()
+    U0 = smooth_state(prob.grid.n, seed=3, width_cells=2.0)
+    nodes = np.arange(0, prob.grid.npts, 7)
+    dt, m = 2e-3, 20
+    d = faber_dense(prob, U0, 0.04, m, [0.0, dt], nodes, p=12)
+    assert np.array_equal(d[0], U0[nodes])
+    Uf = faber_step(prob, U0, 0.04, dt, m, p=12)
+    assert np.linalg.norm(d[1] - Uf[nodes]) <= 1e-13 * np.linalg.norm(Uf[nodes])
+
+
+def test_dense_output_between_steps_matches_variation_of_constants():
+    """At intermediate tau the same terms reproduce exp(tau H) with the source
+    (expm + Duhamel quadrature), i.e. the solution between two steps."""
+    from oracle.steppers import faber_dense
+    prob = _small_problem()
+    U0 = smooth_state(prob.grid.n, seed=4, width_cells=2.0)
+    nodes = np.arange(3, prob.grid.npts, 5)
+    ex = ExactPropagator(prob, nquad=30)
+    taus = [2.5e-4, 1e-3, 1.7e-3]
+    d = faber_dense(prob, U0, 0.05, 28, taus, nodes, p=12)
+    for i, tau in enumerate(taus):
+        Ue = ex.step(U0, 0.05, tau)[nodes]
+        assert np.linalg.norm(d[i] - Ue) <= 1e-11 * np.linalg.norm(Ue)
