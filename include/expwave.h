@@ -164,7 +164,8 @@ int32_t expw_set_stream(expw_op* op, void* hip_stream);
 /* Host values of the spectrum rectangle and of the ellipse in use. */
 int32_t expw_get_spectrum(const expw_op* op, double* x_lo, double* B);
 int32_t expw_get_ellipse(const expw_op* op, double* gamma, double* c0, double* c1);
-/* Override the ellipse (gamma > 0, |c1| < 1); the next Faber step uses it. */
+/* Override the ellipse (gamma > 0, |c1| <= 1; c1 = -1 is the segment of an
+ * undamped operator); the next Faber step uses it. */
 int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
 
 /* Kernel tuning for the Faber step: fuse = recurrence terms per HBM sweep

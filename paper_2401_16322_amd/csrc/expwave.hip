@@ -711,7 +711,7 @@ int32_t expw_get_ellipse(const expw_op* op, double* gamma, double* c0, double* c
 
 int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1) {
   if (int32_t rc = check_op(op)) return rc;
-  if (!(gamma > 0.0) || !std::isfinite(gamma) || !std::isfinite(c0) || !(std::fabs(c1) < 1.0))
+  if (!(gamma > 0.0) || !std::isfinite(gamma) || !std::isfinite(c0) || !(std::fabs(c1) <= 1.0))
     return fail(EXPW_EINVAL, "ellipse needs gamma > 0 and |c1| < 1");
   op->gamma = gamma;
   op->c0 = c0;

@@ -319,7 +319,7 @@ int32_t expw_spectrum_rectangle(const expw_grid* g, double c2_max, double* x_lo,
 
 int32_t expw_faber_coefficients(double gamma, double c0, double c1, double dt, int32_t m,
                                 double* a) {
-  if (!(gamma > 0.0) || !(dt > 0.0) || m < 0 || !a || !(std::fabs(c1) < 1.0) ||
+  if (!(gamma > 0.0) || !(dt > 0.0) || m < 0 || !a || !(std::fabs(c1) <= 1.0) ||
       !std::isfinite(c0))
     return expw::fail(EXPW_EINVAL, "expw_faber_coefficients: invalid argument");
   expw::faber_coefficients(gamma, c0, c1, dt, m, a);
@@ -329,7 +329,7 @@ int32_t expw_faber_coefficients(double gamma, double c0, double c1, double dt, i
 int32_t expw_step_ellipse(int32_t dtype, double gamma, double c0, double c1, double* gs,
                           double* c0s, double* c1s) {
   if ((dtype != EXPW_F32 && dtype != EXPW_F64) || !(gamma > 0.0) || !std::isfinite(gamma) ||
-      !std::isfinite(c0) || !(std::fabs(c1) < 1.0) || !gs || !c0s || !c1s)
+      !std::isfinite(c0) || !(std::fabs(c1) <= 1.0) || !gs || !c0s || !c1s)
     return expw::fail(EXPW_EINVAL, "expw_step_ellipse: invalid argument");
   expw::step_ellipse(dtype, gamma, c0, c1, gs, c0s, c1s);
   return EXPW_OK;
@@ -337,7 +337,7 @@ int32_t expw_step_ellipse(int32_t dtype, double gamma, double c0, double c1, dou
 
 int32_t expw_faber_dense_coefficients(double gamma, double c0, double c1, int32_t m, int32_t n_tau,
                                       const double* taus, double* coef) {
-  if (!(gamma > 0.0) || !std::isfinite(gamma) || m < 0 || n_tau < 0 || !(std::fabs(c1) < 1.0) ||
+  if (!(gamma > 0.0) || !std::isfinite(gamma) || m < 0 || n_tau < 0 || !(std::fabs(c1) <= 1.0) ||
       !std::isfinite(c0) || (n_tau > 0 && (!taus || !coef)))
     return expw::fail(EXPW_EINVAL, "expw_faber_dense_coefficients: invalid argument");
   for (int32_t t = 0; t < n_tau; ++t)

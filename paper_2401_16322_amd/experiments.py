@@ -1,0 +1,152 @@
+"""Single-signal dispersion and dissipation experiment on one GPU
+(Sec. 4.2, single signal experiment; metric of Sec. 4.1).
+
+Homogeneous 6 km x 5 km medium (c = 3 km/s, h = 10 m, no absorbing layer), a
+15 Hz Ricker source 10 m above the bottom edge and one receiver at mid-depth;
+the receiver is sampled every 0.417 ms over [0.6, 1.3] s.
+- Faber steps of any size record their terms at the receiver and the samples
+  come from the dense output (no change of step size needed).
+- Krylov and RK4 follow the sampling protocol of the paper: steps of dt up to
+  0.6 s, then steps of 0.417 ms.
+The reference is the FP64 Faber path at degree 40 and dt = 0.5 ms (checked
+against dt = 1 ms) on the same grid, so the errors here are those of the time
+integration only (the paper's reference also changes the grid).
+
+    python -m paper_2401_16322_amd.experiments [--dtype f64|f32]
+prints one JSON object.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+SAMPLE_DT = 0.417e-3
+T_SAMPLE0 = 0.6
+
+
+def _operator(w, dtype, kmax):
+    import torch
+    from paper_2401_16322_amd.expwave import Operator
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    c2 = torch.tensor(w.velocity() ** 2, dtype=tdt, device="cuda")
+    op = Operator(w.n, w.h, c2, abc_cells=w.abc_cells, sigma_max=w.sigma_max,
+                  max_krylov_k=kmax, max_taylor_p=w.taylor_p)
+    op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+    op.set_receivers(w.receiver_nodes())
+    return op, tdt
+
+
+def sample_times(w):
+    n = int(math.floor((w.T - T_SAMPLE0) / SAMPLE_DT + 1e-9)) + 1
+    return T_SAMPLE0 + SAMPLE_DT * np.arange(n)
+
+
+def faber_signal(op, tdt, w, m, dt, ts):
+    """Receiver samples at times ts from Faber steps of size dt (dense output)."""
+    import torch
+    nsteps = int(math.ceil(ts[-1] / dt - 1e-9))
+    nrec = w.receiver_nodes().size
+    U = torch.zeros((w.ndim + 1) * w.npts, dtype=tdt, device="cuda")
+    terms = torch.zeros(nsteps * (m + 1) * nrec, dtype=tdt, device="cuda")
+    op.step_faber_dense(U, 0.0, dt, m, nsteps, terms)
+    steps = np.minimum(np.floor(ts / dt + 1e-9).astype(np.int64), nsteps - 1)
+    taus = np.maximum(ts - steps * dt, 0.0)
+    coef = op.dense_coefficients(m, taus)
+    out = op.dense_output(m, terms, nsteps, torch.tensor(steps), torch.tensor(coef))
+    op.sync()
+    return out[:, 0].double().cpu().numpy()
+
+
+def switched_signal(op, tdt, w, method, order, dt, ts):
+    """Steps of dt up to the first sample time, then steps of SAMPLE_DT."""
+    import torch
+    U = torch.zeros((w.ndim + 1) * w.npts, dtype=tdt, device="cuda")
+    nrec = w.receiver_nodes().size
+
+    def advance(t, h, n, traces=None):
+        if n <= 0:
+            return t
+        if method == "krylov":
+            op.step_krylov(U, t, h, order, n, traces=traces)
+        else:
+            op.step_rk4(U, t, h, n, traces=traces)
+        return t + n * h
+
+    n1 = int(math.floor(T_SAMPLE0 / dt + 1e-9))
+    t = advance(0.0, dt, n1)
+    rest = T_SAMPLE0 - n1 * dt
+    if rest > 1e-12:
+        t = advance(t, rest, 1)
+    first = U[w.receiver_nodes()[0]].clone()
+    tr = torch.zeros((ts.size - 1) * nrec, dtype=tdt, device="cuda")
+    advance(T_SAMPLE0, SAMPLE_DT, ts.size - 1, traces=tr)
+    op.sync()
+    return np.concatenate([[first.double().item()], tr.view(-1, nrec)[:, 0].double().cpu().numpy()])
+
+
+def run(dtype="f64", faber_orders=(8, 16, 24, 32, 40), krylov_orders=(10, 20, 30),
+        faber_dts_ms=(1, 2, 4, 6, 8, 10), krylov_dts_ms=(1, 2, 4, 6, 8, 10),
+        rk4_dts_ms=(0.5, 1.0, 1.5)):
+    from paper_2401_16322_amd.analysis import dispersion_dissipation
+    from synthetic import get_workload
+    w = get_workload("homog2d_single_signal")
+    ts = sample_times(w)
+    op64, t64 = _operator(w, "f64", 0)
+    ref = faber_signal(op64, t64, w, 40, 0.5e-3, ts)
+    ref2 = faber_signal(op64, t64, w, 40, 1.0e-3, ts)
+    op64.close()
+    chk = dispersion_dissipation(ref, ref2, SAMPLE_DT)
+    op, tdt = _operator(w, dtype, max(krylov_orders) if krylov_orders else 0)
+    rows = []
+
+    def record(method, order, dt_ms, sig, wall):
+        if not np.all(np.isfinite(sig)):
+            rows.append({"method": method, "order": order, "dt_ms": dt_ms, "diverged": True})
+            return
+        e = dispersion_dissipation(ref, sig, SAMPLE_DT)
+        rows.append({"method": method, "order": order, "dt_ms": dt_ms,
+                     "dispersion": e["dispersion"], "dissipation": e["dissipation"],
+                     "wall_s": wall})
+
+    for m in faber_orders:
+        for d in faber_dts_ms:
+            t0 = time.perf_counter()
+            sig = faber_signal(op, tdt, w, m, d * 1e-3, ts)
+            record("faber", m, d, sig, time.perf_counter() - t0)
+    for k in krylov_orders:
+        for d in krylov_dts_ms:
+            t0 = time.perf_counter()
+            sig = switched_signal(op, tdt, w, "krylov", k, d * 1e-3, ts)
+            record("krylov", k, d, sig, time.perf_counter() - t0)
+    for d in rk4_dts_ms:
+        t0 = time.perf_counter()
+        sig = switched_signal(op, tdt, w, "rk4", 4, d * 1e-3, ts)
+        record("rk4", 4, d, sig, time.perf_counter() - t0)
+    op.close()
+    return {"experiment": "single signal", "workload": w.name, "dtype": dtype,
+            "samples": int(ts.size), "sample_dt_ms": SAMPLE_DT * 1e3,
+            "reference": {"method": "faber", "order": 40, "dt_ms": 0.5,
+                          "vs_dt_1ms": {"dispersion": chk["dispersion"],
+                                        "dissipation": chk["dissipation"]}},
+            "runs": rows}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dtype", default="f64", choices=["f32", "f64"])
+    args = ap.parse_args()
+    print(json.dumps(run(args.dtype), allow_nan=False), flush=True)
+
+
+if __name__ == "__main__":
+    main()

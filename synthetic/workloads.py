@@ -30,7 +30,8 @@ class Workload:
     faber_m: int = 16
     dt: float = 4e-3
     taylor_p: int = 8
-    receivers: str = "none"   # "none", "surface_row"
+    receivers: str = "none"   # "none", "surface_row", "nodes"
+    rec_nodes: tuple = ()     # receiver nodes for receivers == "nodes"
     extra: dict = field(default_factory=dict)
 
     @property
@@ -68,6 +69,8 @@ class Workload:
             j = self.n[1] // 2
             return np.array([self.flat_index((i, j, row)) for i in range(self.n[0])],
                             dtype=np.int64)
+        if self.receivers == "nodes":
+            return np.array([self.flat_index(v) for v in self.rec_nodes], dtype=np.int64)
         raise ValueError(self.receivers)
 
 
@@ -88,6 +91,14 @@ WORKLOADS = {
         name="layered2d_8192x4096", n=(8192, 4096), h=10.0, abc_cells=40, sigma_max=300.0,
         f_peak=15.0, t_delay=0.18, T=2.0, src=(4096, 42), medium="layered",
         seed=2100, faber_m=16, dt=2e-3, taylor_p=8, receivers="surface_row"),
+    # single-signal experiment: homogeneous 6 km x 5 km at h = 10 m, c = 3 km/s,
+    # no absorbing layer, source 10 m above the bottom edge, one receiver at
+    # mid-depth, T = 1.3 s (the receiver is sampled uniformly over [0.6, 1.3] s)
+    "homog2d_single_signal": Workload(
+        name="homog2d_single_signal", n=(601, 501), h=10.0, abc_cells=0, sigma_max=0.0,
+        f_peak=15.0, t_delay=0.18, T=1.3, src=(300, 499), medium="homogeneous",
+        c_homog=3000.0, faber_m=16, dt=2e-3, taylor_p=8, receivers="nodes",
+        rec_nodes=((300, 250),)),
     # 256^3 layered, 20-cell layer, centre source, T = 1 s, Faber degree 24
     "layered3d_256": Workload(
         name="layered3d_256", n=(256, 256, 256), h=10.0, abc_cells=20, sigma_max=300.0,
