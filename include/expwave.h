@@ -219,6 +219,27 @@ int32_t expw_faber_dense_output(expw_op* op, int32_t m, int64_t n_samples,
                                 const int64_t* sample_step_dev, const double* coef_dev,
                                 const void* term_traces_dev, int64_t nsteps, void* out_dev);
 
+/* Adjoint (gradient) support. The transpose of the step is built from the
+ * same recurrence run backwards (Sec. 3.2, Faber recurrence; the adjoint
+ * itself is not in the paper): with (D+)^T = -D-,
+ * (H^T y)_p = sum_a D-_a y_{v_a} - sigma_p y_p and
+ * (H^T y)_{v_a} = D+_a (c^2 y_p) - sigma_a y_{v_a}. */
+/* y = H^T x (device state arrays, must not alias). */
+int32_t expw_apply_adjoint(expw_op* op, const void* x_dev, void* y_dev);
+/* Reverse of one Faber step of degree m from t with state u_dev (the state
+ * at t, not modified): on entry lam_dev holds d(loss)/d(state at t + dt), on
+ * return d(loss)/d(state at t) through this step; grad_c2_dev (one value per
+ * point) is incremented by -(1/gamma) sum_j mu_{j,p} (sum_a D-_a v_{j-1,a}),
+ * the derivative with respect to c^2 at fixed ellipse and coefficients.
+ * terms_dev: caller scratch of (m - 1) state vectors (NULL when m = 1). The
+ * ellipse, coefficients and source are those of expw_step_faber at t, so
+ * this is the exact transpose of that step's linear part. Uses the workspace. */
+int32_t expw_faber_adjoint_step(expw_op* op, const void* u_dev, void* lam_dev, double t, double dt,
+                                int32_t m, void* grad_c2_dev, void* terms_dev);
+/* state_dev pressure at the receivers += scale * values_dev[r] (adjoint
+ * sources; device atomics, so repeated receivers add up). */
+int32_t expw_inject_receivers(expw_op* op, const void* values_dev, double scale, void* state_dev);
+
 /* Krylov steps (Arnoldi with modified Gram-Schmidt on the augmented matrix,
  * then the small exponential, see expw_set_krylov_expm). Requires
  * k <= max_krylov_k. */

@@ -1,0 +1,128 @@
+// Adjoint of the Faber step (Sec. 3.2, Faber recurrence, transposed) and of
+// the operator: the kernels of a reverse sweep for gradients with respect to
+// c^2. With (D+)^T = -D- (zero ghosts or periodic),
+//   (H^T y)_p   = sum_a D-_a y_{v_a} - sigma_p y_p
+//   (H^T y)_v_a = D+_a (c^2 y_p) - sigma_a(half) y_{v_a}
+// and for u' = sum_j a_j v_j (v_j = A v_{j-1} - c_j v_{j-2}, A = H/gamma - c0)
+// the derivatives mu_j of <lam, u'> with respect to v_j run from j = m down:
+//   mu_j = a_j lam + A^T mu_{j+1} - c_{j+2} mu_{j+2},
+// with d<lam, u'>/du = mu_0 and
+//   d<lam, u'>/dc^2 = -(1/gamma) sum_{j>=1} mu_{j,p} (sum_a D-_a v_{j-1,a}).
+#pragma once
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace expw {
+
+// (H^T y) at one point for every field; self = y at the point.
+template <typename T, int K, int BC, int DIM>
+__device__ __forceinline__ void apply_point_adjoint(const Geo<T, K, DIM>& g,
+                                                    const T* __restrict__ y, int64_t idx,
+                                                    const int64_t* ic, T* out, T* self) {
+  const T* __restrict__ p = y;
+  const T pc = p[idx];
+  self[0] = pc;
+  T div = T(0), sp = T(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* __restrict__ v = y + (1 + a) * g.N;
+    T dv = T(0), dcp = T(0);
+#pragma unroll
+    for (int l = 1; l <= K; ++l) {
+      dv += g.w[l - 1] * (ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], l - 1) -
+                          ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], -l));
+      dcp += g.w[l - 1] * (ldn<T, BC>(g.c2, idx, ic[a], g.n[a], g.st[a], l) *
+                               ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], l) -
+                           ldn<T, BC>(g.c2, idx, ic[a], g.n[a], g.st[a], 1 - l) *
+                               ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], 1 - l));
+    }
+    div += dv;
+    sp += g.sint[a][ic[a]];
+    const T vc = v[idx];
+    self[1 + a] = vc;
+    out[1 + a] = dcp - g.shalf[a][ic[a]] * vc;
+  }
+  out[0] = div - sp * pc;
+}
+
+// sum_a D-_a v_a at one point (the factor of c^2 in the pressure row of H).
+template <typename T, int K, int BC, int DIM>
+__device__ __forceinline__ T velocity_divergence(const Geo<T, K, DIM>& g, const T* __restrict__ x,
+                                                 int64_t idx, const int64_t* ic) {
+  T div = T(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* __restrict__ v = x + (1 + a) * g.N;
+#pragma unroll
+    for (int l = 1; l <= K; ++l)
+      div += g.w[l - 1] * (ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], l - 1) -
+                           ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], -l));
+  }
+  return div;
+}
+
+// y = H^T x
+template <typename T, int K, int BC, int DIM>
+__global__ __launch_bounds__(kBlock) void k_apply_adjoint(Geo<T, K, DIM> g, const T* __restrict__ x,
+                                                          T* __restrict__ y) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  if (idx >= g.N) return;
+  int64_t ic[3];
+  decompose<DIM>(g.n, idx, ic);
+  T o[DIM + 1], s[DIM + 1];
+  apply_point_adjoint<T, K, BC, DIM>(g, x, idx, ic, o, s);
+#pragma unroll
+  for (int f = 0; f <= DIM; ++f) y[f * g.N + idx] = o[f];
+}
+
+// Coefficients of one reverse term j: mu_j = a_j lam + (H^T mu1)/gamma
+// - c0 mu1 - cnext mu2 (cnext = c_{j+2}; a_j as hi + lo, see FaberTerm).
+template <typename T>
+struct AdjointTerm {
+  T inv_gamma, c0, cnext, a_j, a_j_lo;
+};
+
+// One reverse term. mu1 (read with a halo) and mu2 may be NULL (zero);
+// vprev = v_{j-1} (read with a halo) and grad are NULL for j = 0. mu_out may
+// alias lam (pointwise); it must not alias mu1, mu2 or vprev.
+template <typename T, int K, int BC, int DIM>
+__global__ __launch_bounds__(kBlock) void k_faber_adjoint_term(Geo<T, K, DIM> g, const T* mu1,
+                                                               const T* mu2, const T* lam,
+                                                               const T* vprev, T* mu_out, T* grad,
+                                                               AdjointTerm<T> c) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  if (idx >= g.N) return;
+  int64_t ic[3];
+  decompose<DIM>(g.n, idx, ic);
+  T o[DIM + 1], s[DIM + 1];
+  if (mu1) {
+    apply_point_adjoint<T, K, BC, DIM>(g, mu1, idx, ic, o, s);
+  } else {
+#pragma unroll
+    for (int f = 0; f <= DIM; ++f) o[f] = s[f] = T(0);
+  }
+  T mp = T(0);
+#pragma unroll
+  for (int f = 0; f <= DIM; ++f) {
+    const int64_t e = f * g.N + idx;
+    T mu = add_weighted(T(0), c.a_j, c.a_j_lo, lam[e]);
+    mu += o[f] * c.inv_gamma - c.c0 * s[f];
+    if (mu2) mu -= c.cnext * mu2[e];
+    mu_out[e] = mu;
+    if (f == 0) mp = mu;
+  }
+  if (grad) grad[idx] -= c.inv_gamma * mp * velocity_divergence<T, K, BC, DIM>(g, vprev, idx, ic);
+}
+
+// state_p[rec[r]] += scale * vals[r] (adjoint sources at the receivers;
+// repeated receivers add up).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter_add(const T* __restrict__ vals,
+                                                        const int64_t* __restrict__ rec, int32_t n,
+                                                        T scale, T* state) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) atomicAdd(state + rec[i], scale * vals[i]);
+}
+
+}  // namespace expw

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <vector>
 
+#include "adjoint.h"
 #include "arnoldi.h"
 #include "fused.h"
 #include "internal.h"
@@ -564,6 +565,73 @@ int32_t apply_impl(expw_op* op, const T* x, T* y) {
   return check_launch("apply");
 }
 
+template <typename T, int K, int BC, int DIM>
+int32_t apply_adjoint_impl(expw_op* op, const T* x, T* y) {
+  const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
+  k_apply_adjoint<T, K, BC, DIM><<<grid_for(g.N), kBlock, 0, op->stream>>>(g, x, y);
+  return check_launch("apply adjoint");
+}
+
+// Adjoint of one Faber step from t (the same ellipse, coefficients and source
+// scalars as the forward step): recomputes v_1..v_{m-1} into terms, then runs
+// the transposed recurrence with three rotating workspace vectors, adding the
+// c^2 gradient into grad; lam becomes mu_0 in place.
+template <typename T, int K, int BC, int DIM>
+int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt, int m, T* grad,
+                           T* terms) {
+  const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
+  const int64_t ns = (DIM + 1) * g.N;
+  const unsigned grid = grid_for(g.N);
+  const WorkEllipse<T> el(op);
+  std::vector<double> a(m + 1), q(m, 0.0), der(EXPW_MAX_TAYLOR), G(EXPW_MAX_TAYLOR);
+  faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a.data());
+  const int p = op->taylor_p;
+  if (op->n_src > 0) {
+    ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
+    for (int c = 0; c < p; ++c) G[c] = der[p - 1 - c];
+    faber_source_scalars(el.gamma, el.c0, el.c1, m, p, G.data(), q.data());
+    const double sc = src_scale(op);
+    for (int j = 0; j < m; ++j) q[j] *= sc;
+  }
+  auto v = [&](int j) -> const T* { return j == 0 ? U : terms + (j - 1) * ns; };
+  // forward: v_j = F1 v_{j-1} - c_j v_{j-2} + source, j = 1..m-1
+  FaberTerm<T> f{};
+  f.inv_gamma = static_cast<T>(1.0 / el.gamma);
+  f.c0 = static_cast<T>(el.c0);
+  const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
+  for (int j = 1; j < m; ++j) {
+    f.cpp = static_cast<T>(j == 1 ? 0.0 : (j == 2 ? 2.0 * el.c1 : el.c1));
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1 + (j > 1 ? nf : 0) + nf) * pb,
+                 k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, v(j - 1),
+                 j > 1 ? v(j - 2) : nullptr, terms + (j - 1) * ns, nullptr, nullptr, f,
+                 make_src<T>(op, q[j - 1]));
+    if (int32_t rc = check_launch("adjoint: forward terms")) return rc;
+  }
+  // reverse: mu_j for j = m..0 (mu_j into buffer j mod 3, mu_0 into lam)
+  T* mbuf[3] = {reinterpret_cast<T*>(op->ws + op->off_big), nullptr, nullptr};
+  mbuf[1] = mbuf[0] + ns;
+  mbuf[2] = mbuf[1] + ns;
+  auto cc = [&](int j) { return j < 2 ? 0.0 : (j == 2 ? 2.0 * el.c1 : el.c1); };
+  AdjointTerm<T> c{};
+  c.inv_gamma = f.inv_gamma;
+  c.c0 = f.c0;
+  for (int j = m; j >= 0; --j) {
+    split_weight(a[j], &c.a_j, &c.a_j_lo);
+    c.cnext = static_cast<T>(cc(j + 2));
+    const T* mu1 = j + 1 <= m ? mbuf[(j + 1) % 3] : nullptr;
+    const T* mu2 = j + 2 <= m ? mbuf[(j + 2) % 3] : nullptr;
+    T* out = j == 0 ? lam : mbuf[j % 3];
+    // reads lam, mu1 (+ c^2 with the stencil), mu2, v_{j-1}; writes mu_j, grad RMW
+    const double words = nf + (mu1 ? nf + 1 : 0) + (mu2 ? nf : 0) + nf + (j > 0 ? DIM + 2 : 0);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, words * pb,
+                 k_faber_adjoint_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, mu1, mu2,
+                 static_cast<const T*>(lam), j > 0 ? v(j - 1) : nullptr, out,
+                 j > 0 ? grad : nullptr, c);
+    if (int32_t rc = check_launch("adjoint term")) return rc;
+  }
+  return EXPW_OK;
+}
+
 int32_t check_op(const expw_op* op) {
   if (!op) return fail(EXPW_EINVAL, "op is NULL");
   return EXPW_OK;
@@ -735,6 +803,43 @@ int32_t expw_apply(expw_op* op, const void* x, void* y) {
     using T = typename C::type;
     return apply_impl<T, C::k, C::bc, C::dim>(op, static_cast<const T*>(x), static_cast<T*>(y));
   });
+}
+
+int32_t expw_apply_adjoint(expw_op* op, const void* x, void* y) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!x || !y) return fail(EXPW_EINVAL, "NULL vector");
+  if (x == y) return fail(EXPW_EINVAL, "x and y must not alias");
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return apply_adjoint_impl<T, C::k, C::bc, C::dim>(op, static_cast<const T*>(x), static_cast<T*>(y));
+  });
+}
+
+int32_t expw_faber_adjoint_step(expw_op* op, const void* u, void* lam, double t, double dt,
+                                int32_t m, void* grad, void* terms) {
+  if (int32_t rc = check_step_args(op, u, dt, 1)) return rc;
+  if (m < 1 || m > 1024) return fail(EXPW_EINVAL, "Faber degree m must be in [1, 1024]");
+  if (!lam || !grad) return fail(EXPW_EINVAL, "NULL lam or grad");
+  if (m > 1 && !terms) return fail(EXPW_EINVAL, "terms is NULL (m - 1 state vectors needed)");
+  if (lam == u || lam == grad) return fail(EXPW_EINVAL, "lam must not alias u or grad");
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return faber_adjoint_impl<T, C::k, C::bc, C::dim>(op, static_cast<const T*>(u), static_cast<T*>(lam), t, dt, m, static_cast<T*>(grad), static_cast<T*>(terms));
+  });
+}
+
+int32_t expw_inject_receivers(expw_op* op, const void* values, double scale, void* state) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (op->n_rec == 0) return fail(EXPW_EINVAL, "no receivers set");
+  if (!values || !state) return fail(EXPW_EINVAL, "NULL array");
+  const unsigned grid = grid_for(op->n_rec);
+  if (op->g.dtype == EXPW_F32)
+    k_scatter_add<float><<<grid, kBlock, 0, op->stream>>>(static_cast<const float*>(values), op->rec_dev, op->n_rec, static_cast<float>(scale), static_cast<float*>(state));
+  else
+    k_scatter_add<double><<<grid, kBlock, 0, op->stream>>>(static_cast<const double*>(values), op->rec_dev, op->n_rec, scale, static_cast<double*>(state));
+  return check_launch("inject receivers");
 }
 
 int32_t expw_set_source_ricker(expw_op* op, int32_t n_src, const int64_t* idx, const double* amp,

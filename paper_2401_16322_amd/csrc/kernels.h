@@ -50,7 +50,8 @@ inline void split_weight(double a, T* hi, T* lo) {
 
 // vout may alias vpp and acc_out may alias acc_in or vpp (pointwise reuse);
 // vp is read with a halo and must not alias any output. vout == nullptr skips
-// storing v_j (last term of a step).
+// storing v_j (last term of a step); acc_out == nullptr skips the sum (terms
+// recomputed for the adjoint).
 template <typename T, int K, int BC, int DIM>
 __global__ __launch_bounds__(kBlock) void k_faber_term(Geo<T, K, DIM> g, const T* vp,
                                                        const T* vpp, T* vout, const T* acc_in,
@@ -67,10 +68,11 @@ __global__ __launch_bounds__(kBlock) void k_faber_term(Geo<T, K, DIM> g, const T
     T v = o[f] * c.inv_gamma - c.c0 * s[f];
     if (vpp) v -= c.cpp * vpp[e];
     if (f == 0) v += src_value(src, idx);
-    T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, s[f]) : acc_in[e];
-    acc = add_weighted(acc, c.a_j, c.a_j_lo, v);
     if (vout) vout[e] = v;
-    acc_out[e] = acc;
+    if (acc_out) {
+      T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, s[f]) : acc_in[e];
+      acc_out[e] = add_weighted(acc, c.a_j, c.a_j_lo, v);
+    }
   }
 }
 

@@ -64,6 +64,9 @@ SIGNATURES = {
     "expw_set_ellipse": (_i32, [_vp, _dbl, _dbl, _dbl]),
     "expw_set_tuning": (_i32, [_vp, _i32]),
     "expw_apply": (_i32, [_vp, _vp, _vp]),
+    "expw_apply_adjoint": (_i32, [_vp, _vp, _vp]),
+    "expw_faber_adjoint_step": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
+    "expw_inject_receivers": (_i32, [_vp, _vp, _dbl, _vp]),
     "expw_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
     "expw_set_receivers": (_i32, [_vp, _i32, _vp]),
     "expw_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
@@ -244,6 +247,18 @@ def expw_apply(op, x_ptr, y_ptr):
     _check(load().expw_apply(op, x_ptr, y_ptr))
 
 
+def expw_apply_adjoint(op, x_ptr, y_ptr):
+    _check(load().expw_apply_adjoint(op, x_ptr, y_ptr))
+
+
+def expw_faber_adjoint_step(op, u_ptr, lam_ptr, t, dt, m, grad_ptr, terms_ptr):
+    _check(load().expw_faber_adjoint_step(op, u_ptr, lam_ptr, t, dt, m, grad_ptr, terms_ptr))
+
+
+def expw_inject_receivers(op, values_ptr, scale, state_ptr):
+    _check(load().expw_inject_receivers(op, values_ptr, scale, state_ptr))
+
+
 def expw_set_source_ricker(op, nodes, amps, f_peak, t_delay, taylor_p):
     nodes = np.ascontiguousarray(nodes, dtype=np.int64)
     amps = np.ascontiguousarray(amps, dtype=np.float64)
@@ -395,6 +410,42 @@ class Operator:
         self._sync_stream()
         expw_apply(self.op, x.data_ptr(), y.data_ptr())
         return y
+
+    def apply_adjoint(self, x, out=None):
+        """y = H^T x."""
+        self._check_state(x)
+        y = self._torch.empty_like(x) if out is None else out
+        self._sync_stream()
+        expw_apply_adjoint(self.op, x.data_ptr(), y.data_ptr())
+        return y
+
+    def faber_adjoint_step(self, u, lam, t, dt, m, grad, terms=None):
+        """lam <- (Faber step from t)^T lam in place; grad (one value per
+        point) += the c^2 gradient of <lam, step(u)>. terms: scratch of
+        (m - 1) * nstate values (allocated when None)."""
+        self._check_state(u)
+        self._check_state(lam)
+        if grad.dtype != self.dtype or grad.numel() != self.npts or not grad.is_contiguous():
+            raise ValueError("grad must hold one value per grid point of the grid dtype")
+        if m > 1:
+            if terms is None:
+                terms = self._torch.empty((m - 1) * self.nstate, dtype=self.dtype, device=u.device)
+            if terms.dtype != self.dtype or terms.numel() < (m - 1) * self.nstate:
+                raise ValueError("terms must hold (m - 1) * nstate values")
+        self._sync_stream()
+        expw_faber_adjoint_step(self.op, u.data_ptr(), lam.data_ptr(), t, dt, m, grad.data_ptr(),
+                                terms.data_ptr() if m > 1 else None)
+        return lam
+
+    def inject_receivers(self, values, state, scale=1.0):
+        """state pressure at the receivers += scale * values."""
+        self._check_state(state)
+        if self._rec is None:
+            raise ValueError("no receivers set")
+        if values.dtype != self.dtype or values.numel() < self._rec.numel() or not values.is_contiguous():
+            raise ValueError("values must hold n_rec values of the grid dtype")
+        self._sync_stream()
+        expw_inject_receivers(self.op, values.data_ptr(), scale, state.data_ptr())
 
     def set_source_ricker(self, nodes, amps, f_peak, t_delay, taylor_p=8):
         self._sync_stream()

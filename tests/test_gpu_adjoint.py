@@ -1,0 +1,116 @@
+"""GPU parity of the adjoint path (H^T, the reverse Faber step, the
+checkpointed misfit gradient and the autograd wrapper) against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_cases import TOL, make_case, rel_l2, to_dev
+from oracle.adjoint import apply_HT, faber_adjoint_step, misfit_gradient
+
+DTYPES = ["float64", "float32"]
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,order,bc", [((37, 29), 4, "zero"), ((33, 20), 8, "zero"),
+                                        ((24, 16), 4, "periodic"), ((13, 11, 9), 4, "zero")])
+def test_apply_adjoint_matches_oracle(dtype, n, order, bc):
+    case = make_case(n, dtype, order=order, bc=bc, src=False, seed=31)
+    x = case.U0
+    y = case.op.apply_adjoint(to_dev(case, x)).cpu().numpy()
+    ref = apply_HT(case.prob.grid, case.prob.c2, x)
+    assert rel_l2(y, ref) <= (1e-13 if dtype == "float64" else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m", [1, 2, 5, 12])
+def test_faber_adjoint_step_matches_oracle(dtype, m):
+    import torch
+    case = make_case((70, 45), dtype, seed=32, n_src=2)
+    g = case.prob.grid
+    ell = case.op.ellipse
+    lam0 = np.random.default_rng(3).normal(size=g.nstate)
+    u = case.U0
+    lam = to_dev(case, lam0)
+    grad = torch.zeros(g.npts, dtype=case.torch_dtype, device="cuda")
+    case.op.faber_adjoint_step(to_dev(case, u), lam, 0.05, 2e-3, m, grad)
+    mu0, gref = faber_adjoint_step(case.prob, u, lam0, 0.05, 2e-3, m, p=case.p, ellipse=ell)
+    tol = TOL[dtype]
+    assert rel_l2(lam.cpu().numpy(), mu0) <= tol
+    assert rel_l2(grad.cpu().numpy(), gref) <= tol * (1 if dtype == "float64" else 5)
+
+
+def test_adjoint_step_dot_product_on_gpu():
+    """Without a source: <step(u), lam> = <u, step^T lam> in FP64."""
+    import torch
+    case = make_case((64, 40), "float64", seed=33, src=False)
+    g = case.prob.grid
+    rng = np.random.default_rng(4)
+    u = to_dev(case, rng.normal(size=g.nstate))
+    lam = to_dev(case, rng.normal(size=g.nstate))
+    su = u.clone()
+    case.op.step_faber(su, 0.0, 3e-3, 14, 1)
+    lhs = float(su @ lam)
+    grad = torch.zeros(g.npts, dtype=torch.float64, device="cuda")
+    case.op.faber_adjoint_step(u, lam, 0.0, 3e-3, 14, grad)
+    rhs = float(u @ lam)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs) + 1e-14
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_checkpointed_misfit_gradient_matches_oracle(dtype):
+    """12 steps with a source, 4 receivers, checkpoints every 5 steps."""
+    import torch
+    from paper_2401_16322_amd.fwi import misfit_gradient as gpu_misfit_gradient
+    case = make_case((40, 30), dtype, seed=34, n_src=1)
+    g = case.prob.grid
+    rec = np.array([41, 377, 615, 1170], dtype=np.int64)
+    case.op.set_receivers(rec)
+    rng = np.random.default_rng(5)
+    nst, dt, m, t0 = 12, 2e-3, 8, 0.04
+    d_obs = rng.normal(size=(nst, rec.size)) * 1e-4
+    U0 = 1e-3 * case.U0
+    ell = case.op.ellipse
+    L, grad, lam, traces = gpu_misfit_gradient(case.op, to_dev(case, U0), t0, dt, nst, m,
+                                               torch.tensor(d_obs), checkpoint_every=5)
+    Lr, gr, lr = misfit_gradient(case.prob, U0, t0, dt, nst, m, rec, d_obs, p=case.p, ellipse=ell)
+    tol = 1e-10 if dtype == "float64" else 5e-5
+    assert L == pytest.approx(Lr, rel=tol)
+    assert rel_l2(grad.cpu().numpy(), gr) <= tol
+    assert rel_l2(lam.cpu().numpy(), lr) <= tol
+
+
+def test_autograd_wrapper_gradients():
+    """torch autograd through faber_traces equals the explicit adjoint, and a
+    directional finite difference of the GPU misfit (FP64)."""
+    import torch
+    from paper_2401_16322_amd.fwi import faber_traces, misfit_gradient as gpu_misfit_gradient
+    case = make_case((36, 28), "float64", seed=35, n_src=1)
+    rec = np.array([30, 300, 700], dtype=np.int64)
+    case.op.set_receivers(rec)
+    nst, dt, m, t0 = 9, 2e-3, 10, 0.04
+    rng = np.random.default_rng(6)
+    d_obs = torch.tensor(rng.normal(size=(nst, rec.size)) * 1e-4, device="cuda")
+    c2 = case.op.c2
+    c2.requires_grad_(True)
+    U0 = to_dev(case, 1e-3 * case.U0).requires_grad_(True)
+    tr = faber_traces(case.op, c2, U0, t0, dt, nst, m, checkpoint_every=4)
+    loss = 0.5 * ((tr - d_obs) ** 2).sum()
+    loss.backward()
+    L, grad, lam, _ = gpu_misfit_gradient(case.op, U0.detach(), t0, dt, nst, m, d_obs,
+                                          checkpoint_every=3)
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-12)
+    assert rel_l2(c2.grad.flatten().cpu().numpy(), grad.cpu().numpy()) <= 1e-11
+    assert rel_l2(U0.grad.cpu().numpy(), lam.cpu().numpy()) <= 1e-11
+    c2.requires_grad_(False)
+
+
+def test_inject_receivers_adds_at_receivers():
+    import torch
+    case = make_case((20, 10), "float64", seed=36, src=False)
+    rec = np.array([3, 50, 50, 199], dtype=np.int64)
+    case.op.set_receivers(rec)
+    s = torch.zeros(case.prob.grid.nstate, dtype=torch.float64, device="cuda")
+    case.op.inject_receivers(torch.tensor([1.0, 2.0, 3.0, 4.0], dtype=torch.float64, device="cuda"), s, scale=0.5)
+    out = s.cpu().numpy()
+    assert out[3] == 0.5 and out[50] == 2.5 and out[199] == 2.0
+    assert np.count_nonzero(out) == 3
