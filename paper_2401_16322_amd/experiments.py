@@ -12,8 +12,9 @@ The reference is the FP64 Faber path at degree 40 and dt = 0.5 ms (checked
 against dt = 1 ms) on the same grid, so the errors here are those of the time
 integration only (the paper's reference also changes the grid).
 
-    python -m paper_2401_16322_amd.experiments [--dtype f64|f32]
-prints one JSON object.
+    python -m paper_2401_16322_amd.experiments [dispersion] [--dtype f64|f32]
+    python -m paper_2401_16322_amd.experiments gradient [--dtype f32|f64] [--shots N]
+print one JSON object each (the second times the inversion gradient).
 """
 from __future__ import annotations
 
@@ -141,11 +142,72 @@ def run(dtype="f64", faber_orders=(8, 16, 24, 32, 40), krylov_orders=(10, 20, 30
             "runs": rows}
 
 
+def gradient(dtype="f32", shots=None):
+    """Inversion gradient on the 601 x 301 case: observed traces from the true
+    model, then the misfit gradient with respect to c^2 at the smoothed start
+    model, shot by shot (forward with checkpoints + reverse sweep). Returns the
+    timings and the misfit."""
+    import torch
+    from paper_2401_16322_amd.expwave import Operator
+    from paper_2401_16322_amd.fwi import _forward, misfit_gradient
+    from synthetic import get_workload, smoothed
+    w = get_workload("fwi2d_601x301")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    c_true = w.velocity()
+    c_start = smoothed(c_true, w.extra["smooth_cells"])
+    nshots = int(shots or w.extra["shots"])
+    xs = np.linspace(w.abc_cells + 10, w.n[0] - w.abc_cells - 11, nshots).round().astype(int)
+    rec = w.receiver_nodes()
+    nsteps = int(round(w.T / w.dt))
+
+    def make(c):
+        op = Operator(w.n, w.h, torch.tensor(c ** 2, dtype=tdt, device="cuda"),
+                      abc_cells=w.abc_cells, sigma_max=w.sigma_max, max_taylor_p=w.taylor_p)
+        op.set_receivers(rec)
+        return op
+
+    op_true, op = make(c_true), make(c_start)
+    op.ellipse = op_true.ellipse   # one ellipse for both models
+    U0 = torch.zeros((w.ndim + 1) * w.npts, dtype=tdt, device="cuda")
+    grad = torch.zeros(w.npts, dtype=torch.float64, device="cuda")
+    total_L, t_fwd, t_grad = 0.0, 0.0, 0.0
+    for x in xs:
+        node = w.flat_index((int(x), w.src[1]))
+        for o in (op_true, op):
+            o.set_source_ricker([node], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+        d_obs, _, _ = _forward(op_true, U0, 0.0, w.dt, nsteps, w.faber_m, 1, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _forward(op, U0, 0.0, w.dt, nsteps, w.faber_m, 1, False)
+        torch.cuda.synchronize()
+        t_fwd += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        L, g, _, _ = misfit_gradient(op, U0, 0.0, w.dt, nsteps, w.faber_m, d_obs,
+                                     checkpoint_every=w.extra["checkpoint_every"])
+        torch.cuda.synchronize()
+        t_grad += time.perf_counter() - t0
+        grad += g.double()
+        total_L += L
+    op.sync()
+    return {"experiment": "inversion gradient", "workload": w.name, "dtype": dtype,
+            "shots": nshots, "steps_per_shot": nsteps, "faber_m": w.faber_m, "dt_ms": w.dt * 1e3,
+            "checkpoint_every": w.extra["checkpoint_every"], "misfit": total_L,
+            "grad_norm": float(torch.linalg.vector_norm(grad)),
+            "forward_s_per_shot": t_fwd / nshots, "gradient_s_per_shot": t_grad / nshots,
+            "gradient_over_forward": t_grad / t_fwd if t_fwd > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--dtype", default="f64", choices=["f32", "f64"])
+    ap.add_argument("which", nargs="?", default="dispersion", choices=["dispersion", "gradient"])
+    ap.add_argument("--dtype", default=None, choices=["f32", "f64"])
+    ap.add_argument("--shots", type=int, default=None)
     args = ap.parse_args()
-    print(json.dumps(run(args.dtype), allow_nan=False), flush=True)
+    if args.which == "dispersion":
+        out = run(args.dtype or "f64")
+    else:
+        out = gradient(args.dtype or "f32", args.shots)
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

@@ -106,3 +106,9 @@ def smooth_state(n, seed, n_pulses=6, width_cells=6.0, v_scale=1e-3):
             acc += a * np.exp(-r2 / (2.0 * w * w))
         fields.append(acc * (1.0 if f == 0 else v_scale))
     return np.concatenate([fl.ravel() for fl in fields])
+
+
+def smoothed(c, cells):
+    """Gaussian-smoothed copy of a velocity model (a starting model for
+    inversion), width `cells` grid cells."""
+    return gaussian_filter(np.asarray(c, dtype=np.float64), cells, mode="nearest")

@@ -99,6 +99,15 @@ WORKLOADS = {
         f_peak=15.0, t_delay=0.18, T=1.3, src=(300, 499), medium="homogeneous",
         c_homog=3000.0, faber_m=16, dt=2e-3, taylor_p=8, receivers="nodes",
         rec_nodes=((300, 250),)),
+    # inversion gradient: 601 x 301 layered (seed 5000) true model, start model =
+    # the true model smoothed over 15 cells, 16 shots evenly spaced on row 42,
+    # 601 receivers on row 42, T = 1.5 s, Faber degree 20, dt = 3 ms,
+    # checkpoints every 10 steps
+    "fwi2d_601x301": Workload(
+        name="fwi2d_601x301", n=(601, 301), h=10.0, abc_cells=40, sigma_max=300.0,
+        f_peak=15.0, t_delay=0.18, T=1.5, src=(300, 42), medium="layered",
+        seed=5000, faber_m=20, dt=3e-3, taylor_p=8, receivers="surface_row",
+        extra={"shots": 16, "checkpoint_every": 10, "smooth_cells": 15.0}),
     # 256^3 layered, 20-cell layer, centre source, T = 1 s, Faber degree 24
     "layered3d_256": Workload(
         name="layered3d_256", n=(256, 256, 256), h=10.0, abc_cells=20, sigma_max=300.0,
