@@ -169,9 +169,11 @@ int32_t expw_get_ellipse(const expw_op* op, double* gamma, double* c0, double* c
 int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
 
 /* Kernel tuning for the Faber step: fuse = recurrence terms per HBM sweep
- * (0 = automatic, 1 = one term per sweep, up to 8; 2D FP32 takes up to 8,
- * 2D FP64 up to 4, 3D runs one term per sweep). The fused kernel's tile
- * follows the depth. Results do not depend on it beyond rounding order. */
+ * (0 = automatic, 1 = one term per sweep, up to 8; 2D FP32 takes up to 8 and
+ * 2D FP64 up to 4, automatic = 4; 3D FP32 takes 2 when asked for, automatic
+ * = 1; 3D FP64 runs one term per sweep). Only order 4 with zero ghosts fuses.
+ * The fused kernels' tiles follow the depth. Results do not depend on it
+ * beyond rounding order. */
 int32_t expw_set_tuning(expw_op* op, int32_t fuse);
 
 /* y = H x (no source), x and y device state arrays (must not alias). */

@@ -11,6 +11,7 @@
 #include "adjoint.h"
 #include "arnoldi.h"
 #include "fused.h"
+#include "fused3d.h"
 #include "internal.h"
 #include "kernels.h"
 #include "profiler.h"
@@ -291,28 +292,34 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
     }
     int32_t rc = EXPW_OK;
     T* term_out = term_traces ? term_traces + st * (m + 1) * op->n_rec : nullptr;
-    if constexpr (DIM == 2 && K == 2 && BC == 0) {
-      if (fuse > 1 && !term_out) {
-        // a remainder of one term after the fused passes: unfused final term
-        auto final_term = [&](const T* vl, const T* vpv, T* acc, T* out, int j) -> int32_t {
-          FaberTerm<T> c{};
-          c.inv_gamma = static_cast<T>(1.0 / el.gamma);
-          c.c0 = static_cast<T>(el.c0);
-          c.cpp = static_cast<T>(el.c1);
-          split_weight(a[j], &c.a_j, &c.a_j_lo);
-          launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, 13.0 * g.N * sizeof(T), k_faber_term<T, K, BC, DIM>, dim3(grid_for(g.N)), dim3(kBlock), g, vl, vpv, nullptr, acc, out, c, make_src<T>(op, q[j - 1]));
-          return check_launch("faber final term");
-        };
-        rc = faber_fused_2d<T>(op->stream, &op->prof, g, make_src<T>(op, 0.0), S, Abuf, Bbuf, Cbuf,
-                               Dbuf, Ebuf, a.data(), q.data(), m, fuse, el.gamma, el.c0, el.c1,
-                               final_term);
+    // a remainder of one term after the fused passes: unfused final term
+    auto final_term = [&](const T* vl, const T* vpv, T* acc, T* out, int j) -> int32_t {
+      FaberTerm<T> c{};
+      c.inv_gamma = static_cast<T>(1.0 / el.gamma);
+      c.c0 = static_cast<T>(el.c0);
+      c.cpp = static_cast<T>(el.c1);
+      split_weight(a[j], &c.a_j, &c.a_j_lo);
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (3.0 * (DIM + 1) + 1) * g.N * sizeof(T), k_faber_term<T, K, BC, DIM>, dim3(grid_for(g.N)), dim3(kBlock), g, vl, vpv, nullptr, acc, out, c, make_src<T>(op, q[j - 1]));
+      return check_launch("faber final term");
+    };
+    const Src<T> src0 = make_src<T>(op, 0.0);
+    if (fuse > 1 && !term_out) {
+      if constexpr (K == 2 && BC == 0 && DIM == 2) {
+        rc = faber_fused_passes<T>(op->stream, ns, S, Abuf, Bbuf, Cbuf, Dbuf, Ebuf, m, fuse, final_term,
+            [&](int n, const T* vp, const T* vpp, const T* acc_in, T* ol, T* opv, T* acc_out, int j, bool first) {
+              return launch_pass<T>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, j, first, a.data(), q.data(), el.gamma, el.c0, el.c1);
+            });
+      } else if constexpr (K == 2 && BC == 0 && DIM == 3) {
+        rc = faber_fused_passes<T>(op->stream, ns, S, Abuf, Bbuf, Cbuf, Dbuf, Ebuf, m, 2, final_term,
+            [&](int n, const T* vp, const T* vpp, const T* acc_in, T* ol, T* opv, T* acc_out, int j, bool first) {
+              (void)n;
+              return launch_fused3d<T>(op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, j, first, a.data(), q.data(), el.gamma, el.c0, el.c1);
+            });
       } else {
-        rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m,
-                                          term_out);
+        rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m, term_out);
       }
     } else {
-      rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m,
-                                        term_out);
+      rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m, term_out);
     }
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;

@@ -222,10 +222,15 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
   }
 }
 
-// Fusion depth actually used for a request (1 = unfused kernels).
+// Fusion depth actually used for a request (1 = unfused kernels): 2D order 4
+// with zero ghosts up to 8 (FP32) or 4 (FP64) terms, default 4; 3D FP32 order
+// 4 with zero ghosts 2 terms when asked for (fuse >= 2), one term by default
+// (the one-term sweep already runs at the streaming limit in 3D and the
+// two-term pass gains little; in FP64 it spills registers).
 template <typename T, int K, int BC, int DIM>
 int fused_depth(int requested, int m, int64_t npts) {
-  if (DIM != 2 || K != 2 || BC != 0) return 1;
+  if (K != 2 || BC != 0) return 1;
+  if (DIM == 3) return (sizeof(T) == 4 && requested >= 2 && m >= 2) ? 2 : 1;
   if (3 * npts >= (int64_t(1) << 31)) return 1;
   const int smax = sizeof(T) == 4 ? 8 : 4;
   int s = requested == 0 ? 4 : requested;  // default depth
@@ -295,11 +300,11 @@ int32_t launch_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g
 // remainder; a remainder of one term runs as an unfused final term).
 // Buffers: S0 = state (v0), A/B and D/E alternate as (v_last, v_prev), C holds
 // the partial sum; the last pass writes the sum into S0 unless it also read S0.
-template <typename T, class Term>
-int32_t faber_fused_2d(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<T> src, T* S0,
-                       T* A, T* B, T* C, T* D, T* E, const double* a, const double* q, int m,
-                       int s, double gamma, double c0, double c1, Term&& final_term) {
-  const int64_t ns = 3 * g.N;
+// pass(n, vp, vpp, acc_in, out_last, out_prev, acc_out, j, first) launches
+// one pass of n terms starting at term j.
+template <typename T, class Term, class Pass>
+int32_t faber_fused_passes(hipStream_t st, int64_t ns, T* S0, T* A, T* B, T* C, T* D, T* E, int m,
+                           int s, Term&& final_term, Pass&& pass) {
   const T* in_last = S0;
   const T* in_prev = nullptr;
   T* pair[2][2] = {{A, B}, {D, E}};
@@ -317,8 +322,7 @@ int32_t faber_fused_2d(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Sr
     T* acc_out = (last && !first) ? S0 : C;
     T* ol = last ? nullptr : pair[which][0];
     T* opv = last ? nullptr : pair[which][1];
-    int32_t rc = launch_pass<T>(n, st, prof, g, src, in_last, in_prev, first ? nullptr : C, ol,
-                                opv, acc_out, j, first, a, q, gamma, c0, c1);
+    int32_t rc = pass(n, in_last, in_prev, first ? nullptr : C, ol, opv, acc_out, j, first);
     if (rc != EXPW_OK) return rc;
     if (last && first)
       if (hipMemcpyAsync(S0, C, ns * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
