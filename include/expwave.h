@@ -242,6 +242,29 @@ int32_t expw_faber_adjoint_step(expw_op* op, const void* u_dev, void* lam_dev, d
  * sources; device atomics, so repeated receivers add up). */
 int32_t expw_inject_receivers(expw_op* op, const void* values_dev, double scale, void* state_dev);
 
+/* Batches of independent problems (shots) stepped together: term j of every
+ * shot with degree >= j runs in one launch (Faber recurrence, Sec. 3.2), so
+ * a step costs max(m) + 1 launches instead of sum(m) + n. The shots keep
+ * their own operators, grids, ellipses, sources and receivers but must share
+ * dtype, ndim, order and bc; each shot uses its operator's workspace. */
+typedef struct expw_batch expw_batch;
+/* Device bytes of the descriptor table of n_ops shots with grids like g. */
+int32_t expw_batch_table_bytes(int32_t n_ops, const expw_grid* g, size_t* bytes);
+/* Binds n_ops shots: ops[i] stepped with degree m[i] in [2, 64] and step
+ * dt[i] on state states_dev[i]; traces_dev (NULL, or per shot NULL or an
+ * array of steps * n_rec values) records the shot's receivers after every
+ * step. The sources and receivers in effect on each operator now are the
+ * ones used (recreate the batch after changing them). table_dev: caller
+ * buffer of expw_batch_table_bytes bytes, 256-byte aligned, written here
+ * (synchronizes). stream: HIP stream of all batch work (NULL = default). */
+int32_t expw_batch_create(expw_op* const* ops, int32_t n_ops, const int32_t* m, const double* dt,
+                          void* const* states_dev, void* const* traces_dev, void* table_dev,
+                          size_t table_bytes, void* stream, expw_batch** out);
+/* nsteps steps of every shot; shot i's step s runs from t0 + s dt[i]. The
+ * traces of step s go to row trace_step0 + s. */
+int32_t expw_batch_step_faber(expw_batch* b, double t0, int64_t nsteps, int64_t trace_step0);
+int32_t expw_batch_destroy(expw_batch* b);
+
 /* Krylov steps (Arnoldi with modified Gram-Schmidt on the augmented matrix,
  * then the small exponential, see expw_set_krylov_expm). Requires
  * k <= max_krylov_k. */

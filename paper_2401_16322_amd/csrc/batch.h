@@ -1,0 +1,152 @@
+// Faber steps of many independent problems (shots) in the same launches
+// (Sec. 3.2, Faber recurrence; the shots share nothing but the launch). Term
+// j of every shot whose degree is at least j runs in one launch: the shots
+// are sorted by degree, so the participating shots are a prefix of the list
+// and a block finds its shot by a binary search over the prefix sums of the
+// shots' block counts. Every per-shot constant (grid, buffers, ellipse,
+// coefficients, source, receivers) sits in a device table built once; the
+// source scalar of a term is formed on the device from the Ricker
+// derivatives at the step time (the same FP64 formula as the host path) and
+// per-shot tail projections, so nothing is uploaded per step. One launch per
+// term index instead of one per term and shot.
+#pragma once
+
+#include "device_common.h"
+#include "expwave.h"
+#include "kernels.h"
+
+namespace expw {
+
+constexpr int kBatchMaxM = 64;
+
+template <typename T, int K, int DIM>
+struct BatchShot {
+  Geo<T, K, DIM> g;
+  T *S, *A, *B, *C;  // state and three workspace vectors of the shot
+  int32_t m, n_src, p, n_rec;
+  int64_t src_lo, src_hi;
+  const int64_t* src_idx;
+  const T* src_amp;
+  const int64_t* rec;
+  T* traces;  // NULL: not recorded
+  double f_peak, t_delay, dt;
+  T inv_gamma, c0, c1;
+  T a_hi[kBatchMaxM + 1], a_lo[kBatchMaxM + 1];
+  double qtab[kBatchMaxM][EXPW_MAX_TAYLOR];  // source scalar of term j: sum_c G_c(t) qtab[j-1][c]
+};
+
+// g^(k)(t), k = 0..p-1, of the Ricker wavelet (physicists' Hermite form, as
+// the host computes it).
+__device__ __forceinline__ void ricker_derivatives_dev(double t, double f_peak, double t_delay,
+                                                       int p, double* out) {
+  const double pi = 3.14159265358979323846264338327950;
+  const double a = (pi * f_peak) * (pi * f_peak);
+  const double tau = t - t_delay;
+  const double sa = sqrt(a);
+  const double xs = sa * tau;
+  const double e = exp(-a * tau * tau);
+  double hm1 = 1.0, h0 = 2.0 * xs;  // H_0, H_1
+  double apow = a;
+  for (int n = 1; n < p + 2; ++n) {  // H_{n+1}
+    const double h1 = 2.0 * xs * h0 - 2.0 * n * hm1;
+    hm1 = h0;
+    h0 = h1;
+    const int k = n - 1;  // H_{k+2} = h0
+    if (k < p) {
+      out[k] = -(1.0 / (2.0 * a)) * ((k % 2 == 0) ? 1.0 : -1.0) * apow * h0 * e;
+      apow *= sa;
+    }
+  }
+}
+
+// Shot of this block among the first n_part shots (prefix[s] = first block of shot s).
+__device__ __forceinline__ int batch_shot(const int64_t* prefix, int n_part) {
+  int lo = 0, hi = n_part - 1;
+  const int64_t b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Term j of every shot with m >= j. Buffers per shot as in the one-shot
+// unfused step: v1 -> A, v2 -> B, then v_j overwrites v_{j-2}; the sum in C,
+// the last term writes it into S (degree >= 2).
+template <typename T, int K, int BC, int DIM>
+__global__ __launch_bounds__(kBlock) void k_faber_batch_term(const BatchShot<T, K, DIM>* shots,
+                                                             const int64_t* prefix, int n_part,
+                                                             int j, double t0, int64_t step) {
+  const int s = batch_shot(prefix, n_part);
+  const BatchShot<T, K, DIM>& sh = shots[s];
+  const Geo<T, K, DIM>& g = sh.g;
+  const int64_t idx = (static_cast<int64_t>(blockIdx.x) - prefix[s]) * kBlock + threadIdx.x;
+  if (idx >= g.N) return;
+  const bool fin = (j == sh.m);
+  const T *vp, *vpp;
+  T *vout, *acc_out;
+  const T* acc_in = sh.C;
+  T cpp;
+  if (j == 1) {
+    vp = sh.S, vpp = nullptr, vout = sh.A, acc_in = nullptr, acc_out = sh.C, cpp = T(0);
+  } else if (j == 2) {
+    vp = sh.A, vpp = sh.S, vout = fin ? nullptr : sh.B, acc_out = fin ? sh.S : sh.C;
+    cpp = T(2) * sh.c1;
+  } else {
+    vp = (j & 1) ? sh.B : sh.A;
+    vpp = (j & 1) ? sh.A : sh.B;
+    vout = fin ? nullptr : const_cast<T*>(vpp);
+    acc_out = fin ? sh.S : sh.C;
+    cpp = sh.c1;
+  }
+  int64_t ic[3];
+  decompose<DIM>(g.n, idx, ic);
+  T o[DIM + 1], sv[DIM + 1];
+  apply_point<T, K, BC, DIM>(g, vp, idx, ic, o, sv);
+  // source at this point (rare): scalar of term j at the step time
+  T src = T(0);
+  if (sh.n_src > 0 && idx >= sh.src_lo && idx <= sh.src_hi) {
+    T am = T(0);
+    for (int k = 0; k < sh.n_src; ++k)
+      if (sh.src_idx[k] == idx) am += sh.src_amp[k];
+    if (am != T(0)) {
+      double der[EXPW_MAX_TAYLOR];
+      ricker_derivatives_dev(t0 + step * sh.dt, sh.f_peak, sh.t_delay, sh.p, der);
+      double q = 0.0;
+      for (int c = 0; c < sh.p; ++c) q += der[sh.p - 1 - c] * sh.qtab[j - 1][c];
+      src = static_cast<T>(q) * am;
+    }
+  }
+#pragma unroll
+  for (int f = 0; f <= DIM; ++f) {
+    const int64_t e = f * g.N + idx;
+    T v = o[f] * sh.inv_gamma - sh.c0 * sv[f];
+    if (vpp) v -= cpp * vpp[e];
+    if (f == 0) v += src;
+    T acc = (j == 1) ? add_weighted(T(0), sh.a_hi[0], sh.a_lo[0], sv[f]) : acc_in[e];
+    acc = add_weighted(acc, sh.a_hi[j], sh.a_lo[j], v);
+    if (vout) vout[e] = v;
+    acc_out[e] = acc;
+  }
+}
+
+// traces of every recording shot for one step (prefix_rec[s] = first item of shot s).
+template <typename T, int K, int DIM>
+__global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchShot<T, K, DIM>* shots,
+                                                         const int64_t* prefix_rec, int n_shots,
+                                                         int64_t step) {
+  const int64_t it = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  if (it >= prefix_rec[n_shots]) return;
+  int lo = 0, hi = n_shots - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix_rec[mid] <= it) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchShot<T, K, DIM>& sh = shots[lo];
+  const int64_t r = it - prefix_rec[lo];
+  if (sh.traces && r < sh.n_rec) sh.traces[step * sh.n_rec + r] = sh.S[sh.rec[r]];
+}
+
+}  // namespace expw

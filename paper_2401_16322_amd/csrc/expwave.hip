@@ -10,6 +10,7 @@
 
 #include "adjoint.h"
 #include "arnoldi.h"
+#include "batch.h"
 #include "fused.h"
 #include "fused3d.h"
 #include "internal.h"
@@ -50,6 +51,19 @@ struct expw_op {
   int last_keff;
   double last_beta;
   expw::Profiler prof;
+};
+
+struct expw_batch {
+  int n;
+  expw_grid g;  // dtype, ndim, order, bc shared by the shots
+  int K;
+  hipStream_t stream;
+  void* table;       // device: shots (sorted by degree), block prefix, receiver prefix
+  size_t off_prefix, off_prefix_rec;
+  int max_m;
+  std::vector<int> count_ge;        // count_ge[j] = shots with degree >= j
+  std::vector<int64_t> prefix;      // host copy of the block prefix
+  int64_t rec_items;
 };
 
 namespace expw {
@@ -639,6 +653,114 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
   return EXPW_OK;
 }
 
+template <typename T, int K, int DIM>
+size_t batch_table_bytes(int n) {
+  return align_up(n * sizeof(BatchShot<T, K, DIM>)) + 2 * align_up((n + 1) * sizeof(int64_t));
+}
+
+template <typename T, int K, int BC, int DIM>
+int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const double* dt,
+                          void* const* states, void* const* traces, expw_batch* b) {
+  using Shot = BatchShot<T, K, DIM>;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return m[x] > m[y]; });
+  // plain bytes: the descriptors are filled field by field and copied as bytes
+  std::vector<unsigned char> bytes(n * sizeof(Shot), 0);
+  Shot* host = reinterpret_cast<Shot*>(bytes.data());
+  std::vector<int64_t> prefix(n + 1, 0), prefix_rec(n + 1, 0);
+  for (int r = 0; r < n; ++r) {
+    const int i = order[r];
+    expw_op* op = ops[i];
+    Shot& sh = host[r];
+    const Geo<T, K, DIM> geo = make_geo<T, K, DIM>(op);
+    std::memcpy(static_cast<void*>(&sh.g), &geo, sizeof(geo));
+    const int64_t ns = (DIM + 1) * sh.g.N;
+    sh.S = static_cast<T*>(states[i]);
+    sh.A = reinterpret_cast<T*>(op->ws + op->off_big);
+    sh.B = sh.A + ns;
+    sh.C = sh.B + ns;
+    sh.m = m[i];
+    sh.dt = dt[i];
+    const WorkEllipse<T> el(op);
+    sh.inv_gamma = static_cast<T>(1.0 / el.gamma);
+    sh.c0 = static_cast<T>(el.c0);
+    sh.c1 = static_cast<T>(el.c1);
+    std::vector<double> a(m[i] + 1);
+    faber_coefficients(el.gamma, el.c0, el.c1, dt[i], m[i], a.data());
+    for (int j = 0; j <= m[i]; ++j) split_weight(a[j], &sh.a_hi[j], &sh.a_lo[j]);
+    if (op->n_src > 0) {
+      sh.n_src = op->n_src;
+      sh.p = op->taylor_p;
+      sh.src_lo = op->src_lo;
+      sh.src_hi = op->src_hi;
+      sh.src_idx = reinterpret_cast<const int64_t*>(op->ws + op->off_src_idx);
+      sh.src_amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
+      sh.f_peak = op->f_peak;
+      sh.t_delay = op->t_delay;
+      // tail projections: the source scalar is linear in the derivative vector G
+      std::vector<double> e(sh.p), qc(m[i]);
+      const double sc = src_scale(op);
+      for (int c = 0; c < sh.p; ++c) {
+        std::fill(e.begin(), e.end(), 0.0);
+        e[c] = 1.0;
+        faber_source_scalars(el.gamma, el.c0, el.c1, m[i], sh.p, e.data(), qc.data());
+        for (int j = 0; j < m[i]; ++j) sh.qtab[j][c] = qc[j] * sc;
+      }
+    }
+    sh.n_rec = op->n_rec;
+    sh.rec = op->rec_dev;
+    sh.traces = (traces && traces[i] && op->n_rec > 0) ? static_cast<T*>(traces[i]) : nullptr;
+    prefix[r + 1] = prefix[r] + (sh.g.N + kBlock - 1) / kBlock;
+    prefix_rec[r + 1] = prefix_rec[r] + (sh.traces ? sh.n_rec : 0);
+  }
+  if (prefix[n] > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "batch too large for one launch");
+  char* t = static_cast<char*>(b->table);
+  b->off_prefix = align_up(n * sizeof(Shot));
+  b->off_prefix_rec = b->off_prefix + align_up((n + 1) * sizeof(int64_t));
+  if (hipMemcpyAsync(t, bytes.data(), n * sizeof(Shot), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipMemcpyAsync(t + b->off_prefix, prefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipMemcpyAsync(t + b->off_prefix_rec, prefix_rec.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return fail(EXPW_EDEVICE, "batch table upload failed");
+  b->max_m = m[order[0]];
+  b->count_ge.assign(b->max_m + 1, 0);
+  for (int r = 0; r < n; ++r)
+    for (int j = 1; j <= host[r].m; ++j) b->count_ge[j]++;
+  b->prefix = prefix;
+  b->rec_items = prefix_rec[n];
+  return EXPW_OK;
+}
+
+template <typename T, int K, int BC, int DIM>
+int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t trace_step0) {
+  using Shot = BatchShot<T, K, DIM>;
+  const Shot* shots = static_cast<const Shot*>(b->table);
+  const int64_t* prefix = reinterpret_cast<const int64_t*>(static_cast<char*>(b->table) + b->off_prefix);
+  const int64_t* prefix_rec = reinterpret_cast<const int64_t*>(static_cast<char*>(b->table) + b->off_prefix_rec);
+  for (int64_t st = 0; st < nsteps; ++st) {
+    for (int j = 1; j <= b->max_m; ++j) {
+      const int np = b->count_ge[j];
+      const unsigned grid = static_cast<unsigned>(b->prefix[np]);
+      k_faber_batch_term<T, K, BC, DIM><<<grid, kBlock, 0, b->stream>>>(shots, prefix, np, j, t0, st);
+      if (int32_t rc = check_launch("batch term")) return rc;
+    }
+    if (b->rec_items > 0) {
+      k_batch_gather<T, K, DIM><<<grid_for(b->rec_items), kBlock, 0, b->stream>>>(shots, prefix_rec, b->n, trace_step0 + st);
+      if (int32_t rc = check_launch("batch gather")) return rc;
+    }
+  }
+  return EXPW_OK;
+}
+
+template <class Fn>
+int32_t dispatch_batch(const expw_batch* b, Fn&& fn) {
+  expw_op probe{};
+  probe.g = b->g;
+  probe.K = b->K;
+  return dispatch(&probe, fn);
+}
+
 int32_t check_op(const expw_op* op) {
   if (!op) return fail(EXPW_EINVAL, "op is NULL");
   return EXPW_OK;
@@ -847,6 +969,76 @@ int32_t expw_inject_receivers(expw_op* op, const void* values, double scale, voi
   else
     k_scatter_add<double><<<grid, kBlock, 0, op->stream>>>(static_cast<const double*>(values), op->rec_dev, op->n_rec, scale, static_cast<double*>(state));
   return check_launch("inject receivers");
+}
+
+int32_t expw_batch_table_bytes(int32_t n_ops, const expw_grid* g, size_t* bytes) {
+  if (int32_t rc = validate_grid(g)) return rc;
+  if (n_ops < 1 || !bytes) return fail(EXPW_EINVAL, "n_ops must be >= 1 and bytes non-NULL");
+  expw_op probe{};
+  probe.g = *g;
+  probe.K = g->order / 2;
+  const int64_t n = n_ops;
+  return dispatch(&probe, [&](auto cfg) {
+    using C = decltype(cfg);
+    *bytes = batch_table_bytes<typename C::type, C::k, C::dim>(static_cast<int>(n));
+    return EXPW_OK;
+  });
+}
+
+int32_t expw_batch_create(expw_op* const* ops, int32_t n_ops, const int32_t* m, const double* dt,
+                          void* const* states_dev, void* const* traces_dev, void* table_dev,
+                          size_t table_bytes, void* stream, expw_batch** out) {
+  if (!out) return fail(EXPW_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ops || n_ops < 1 || !m || !dt || !states_dev || !table_dev)
+    return fail(EXPW_EINVAL, "NULL argument or n_ops < 1");
+  for (int i = 0; i < n_ops; ++i) {
+    if (!ops[i] || !states_dev[i]) return fail(EXPW_EINVAL, "shot %d: NULL operator or state", i);
+    const expw_grid& g0 = ops[0]->g;
+    const expw_grid& gi = ops[i]->g;
+    if (gi.dtype != g0.dtype || gi.ndim != g0.ndim || gi.order != g0.order || gi.bc != g0.bc)
+      return fail(EXPW_EINVAL, "shot %d: dtype, ndim, order and bc must match shot 0", i);
+    if (m[i] < 2 || m[i] > kBatchMaxM) return fail(EXPW_EINVAL, "shot %d: degree must be in [2, %d]", i, kBatchMaxM);
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(EXPW_EINVAL, "shot %d: dt must be positive", i);
+    for (int k = 0; k < i; ++k)
+      if (ops[k] == ops[i] || states_dev[k] == states_dev[i])
+        return fail(EXPW_EINVAL, "shots %d and %d share an operator or a state", k, i);
+  }
+  size_t need = 0;
+  if (int32_t rc = expw_batch_table_bytes(n_ops, &ops[0]->g, &need)) return rc;
+  if (table_bytes < need) return fail(EXPW_EINVAL, "batch table too small (%zu < %zu bytes)", table_bytes, need);
+  if (reinterpret_cast<uintptr_t>(table_dev) % kAlign) return fail(EXPW_EINVAL, "batch table must be 256-byte aligned");
+  auto* b = new (std::nothrow) expw_batch();
+  if (!b) return fail(EXPW_ENOMEM, "out of host memory");
+  b->n = n_ops;
+  b->g = ops[0]->g;
+  b->K = ops[0]->K;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->table = table_dev;
+  const int32_t rc = dispatch_batch(b, [&](auto cfg) {
+    using C = decltype(cfg);
+    return batch_create_impl<typename C::type, C::k, C::bc, C::dim>(ops, n_ops, m, dt, states_dev, traces_dev, b);
+  });
+  if (rc != EXPW_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return EXPW_OK;
+}
+
+int32_t expw_batch_step_faber(expw_batch* b, double t0, int64_t nsteps, int64_t trace_step0) {
+  if (!b) return fail(EXPW_EINVAL, "batch is NULL");
+  if (nsteps < 0 || trace_step0 < 0) return fail(EXPW_EINVAL, "nsteps and trace_step0 must be >= 0");
+  return dispatch_batch(b, [&](auto cfg) {
+    using C = decltype(cfg);
+    return batch_step_impl<typename C::type, C::k, C::bc, C::dim>(b, t0, nsteps, trace_step0);
+  });
+}
+
+int32_t expw_batch_destroy(expw_batch* b) {
+  delete b;
+  return EXPW_OK;
 }
 
 int32_t expw_set_source_ricker(expw_op* op, int32_t n_src, const int64_t* idx, const double* amp,

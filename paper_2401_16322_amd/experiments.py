@@ -14,7 +14,9 @@ integration only (the paper's reference also changes the grid).
 
     python -m paper_2401_16322_amd.experiments [dispersion] [--dtype f64|f32]
     python -m paper_2401_16322_amd.experiments gradient [--dtype f32|f64] [--shots N]
-print one JSON object each (the second times the inversion gradient).
+    python -m paper_2401_16322_amd.experiments shots [--dtype f32|f64] [--shots N]
+print one JSON object each (the second times the inversion gradient, the
+third compares batched and shot-by-shot stepping of uneven shots).
 """
 from __future__ import annotations
 
@@ -197,16 +199,78 @@ def gradient(dtype="f32", shots=None):
             "gradient_over_forward": t_grad / t_fwd if t_fwd > 0 else None}
 
 
+def shots(dtype="f32", nshots=64, steps=20, seed0=4000):
+    """Many uneven 2D shots: nx ~ U[200, 1000], nz ~ U[200, 500], Faber degree
+    ~ U{12..32}, a layered model per shot (seed seed0 + s), the source at the
+    surface centre, receivers on row 42. The same steps run (a) shot by shot
+    with each operator's default (fused) path and (b) as one batch; returns
+    both rates in grid-point matrix-vector products per second."""
+    import torch
+    from paper_2401_16322_amd.expwave import Batch, Operator
+    from synthetic import layered_velocity
+    rng = np.random.default_rng(seed0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ops, states, ms, dts, npts = [], [], [], [], []
+    for s_ in range(nshots):
+        nx, nz = int(rng.integers(200, 1001)), int(rng.integers(200, 501))
+        m = int(rng.integers(12, 33))
+        c = layered_velocity((nx, nz), 10.0, seed0 + s_)
+        op = Operator((nx, nz), 10.0, torch.tensor(c ** 2, dtype=tdt, device="cuda"),
+                      abc_cells=40, sigma_max=300.0, max_taylor_p=8)
+        op.set_source_ricker([nx // 2 + 42 * nx], [1.0], 15.0, 0.18, 8)
+        op.set_receivers(np.arange(nx, dtype=np.int64) + 42 * nx)
+        # a step a little below the degree's reach (about 0.16 ms per term)
+        ops.append(op)
+        ms.append(m)
+        dts.append(1.6e-4 * m)
+        npts.append(nx * nz)
+        states.append(torch.zeros(3 * nx * nz, dtype=tdt, device="cuda"))
+    work = sum(n * m for n, m in zip(npts, ms)) * steps
+
+    def sequential():
+        for st in range(steps):
+            for op, S, m, dt in zip(ops, states, ms, dts):
+                op.step_faber(S, st * dt, dt, m, 1)
+
+    sequential()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sequential()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    b = Batch(ops, ms, dts, states)
+    b.step(0.0, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(0.0, steps)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    for S in states:
+        if not torch.isfinite(S).all():
+            raise RuntimeError("non-finite state")
+    b.close()
+    return {"experiment": "uneven shots", "dtype": dtype, "shots": nshots, "steps": steps,
+            "points": int(sum(npts)), "degrees": [min(ms), max(ms), float(np.mean(ms))],
+            "sequential_s": t_seq, "batched_s": t_bat,
+            "sequential_grid_pt_matvecs_per_s": work / t_seq,
+            "batched_grid_pt_matvecs_per_s": work / t_bat,
+            "launches_per_step": {"sequential_unfused_equiv": int(sum(ms) + nshots),
+                                  "batched": int(max(ms) + 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", nargs="?", default="dispersion", choices=["dispersion", "gradient"])
+    ap.add_argument("which", nargs="?", default="dispersion",
+                    choices=["dispersion", "gradient", "shots"])
     ap.add_argument("--dtype", default=None, choices=["f32", "f64"])
     ap.add_argument("--shots", type=int, default=None)
     args = ap.parse_args()
     if args.which == "dispersion":
         out = run(args.dtype or "f64")
-    else:
+    elif args.which == "gradient":
         out = gradient(args.dtype or "f32", args.shots)
+    else:
+        out = shots(args.dtype or "f32", args.shots or 64)
     print(json.dumps(out, allow_nan=False), flush=True)
 
 

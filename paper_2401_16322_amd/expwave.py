@@ -72,6 +72,11 @@ SIGNATURES = {
     "expw_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_faber_dense": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp, _vp]),
     "expw_faber_dense_output": (_i32, [_vp, _i32, _i64, _vp, _vp, _vp, _i64, _vp]),
+    "expw_batch_table_bytes": (_i32, [_i32, _pgrid, ctypes.POINTER(_sz)]),
+    "expw_batch_create": (_i32, [ctypes.POINTER(_vp), _i32, _pi32, _pd, ctypes.POINTER(_vp),
+                                 ctypes.POINTER(_vp), _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "expw_batch_step_faber": (_i32, [_vp, _dbl, _i64, _i64]),
+    "expw_batch_destroy": (_i32, [_vp]),
     "expw_step_krylov": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_rk4": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
     "expw_step_leapfrog": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
@@ -284,6 +289,32 @@ def expw_faber_dense_output(op, m, n_samples, sample_step_ptr, coef_ptr, term_tr
                             out_ptr):
     _check(load().expw_faber_dense_output(op, m, n_samples, sample_step_ptr, coef_ptr,
                                           term_traces_ptr, nsteps, out_ptr))
+
+
+def expw_batch_table_bytes(n_ops, grid):
+    out = _sz(0)
+    _check(load().expw_batch_table_bytes(n_ops, ctypes.byref(grid), ctypes.byref(out)))
+    return out.value
+
+
+def expw_batch_create(ops, m, dt, state_ptrs, trace_ptrs, table_ptr, table_bytes, stream):
+    n = len(ops)
+    P = _vp * n
+    m_arr = (ctypes.c_int32 * n)(*[int(v) for v in m])
+    dt_arr = (ctypes.c_double * n)(*[float(v) for v in dt])
+    tr = P(*[p if p else None for p in trace_ptrs]) if trace_ptrs is not None else None
+    h = _vp()
+    _check(load().expw_batch_create(P(*ops), n, m_arr, dt_arr, P(*state_ptrs), tr, table_ptr,
+                                    table_bytes, stream, ctypes.byref(h)))
+    return h.value
+
+
+def expw_batch_step_faber(batch, t0, nsteps, trace_step0=0):
+    _check(load().expw_batch_step_faber(batch, t0, nsteps, trace_step0))
+
+
+def expw_batch_destroy(batch):
+    _check(load().expw_batch_destroy(batch))
 
 
 def expw_step_krylov(op, state_ptr, t0, dt, k, nsteps, traces_ptr=None):
@@ -553,6 +584,47 @@ class Operator:
         if getattr(self, "op", None):
             expw_op_destroy(self.op)
             self.op = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Faber steps of several Operators (shots) in shared launches.
+
+    ops: Operators of one dtype, ndim, order and bc; m, dt: per-shot degree
+    and step; states: per-shot state tensors; traces: None or per-shot
+    tensors (or None) of steps * n_rec values. The sources and receivers set
+    on the operators now are the ones used.
+    """
+
+    def __init__(self, ops, m, dt, states, traces=None):
+        import torch
+        self._torch = torch
+        if not (len(ops) == len(m) == len(dt) == len(states)):
+            raise ValueError("ops, m, dt and states differ in length")
+        for o, s in zip(ops, states):
+            o._check_state(s)
+        self.ops, self.states, self.traces = list(ops), list(states), traces
+        nbytes = expw_batch_table_bytes(len(ops), ops[0].grid)
+        self.table = torch.empty(nbytes, dtype=torch.uint8, device=ops[0].device)
+        tptr = None
+        if traces is not None:
+            tptr = [t.data_ptr() if t is not None else None for t in traces]
+        stream = torch.cuda.current_stream(ops[0].device).cuda_stream
+        self.handle = expw_batch_create([o.op for o in ops], m, dt, [s.data_ptr() for s in states],
+                                        tptr, self.table.data_ptr(), nbytes, stream)
+
+    def step(self, t0, nsteps=1, trace_step0=0):
+        expw_batch_step_faber(self.handle, t0, nsteps, trace_step0)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            expw_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

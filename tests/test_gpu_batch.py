@@ -1,0 +1,83 @@
+"""Batched Faber steps of several shots against one-shot steps and the oracle."""
+import numpy as np
+import pytest
+
+from gpu_cases import TOL, make_case, rel_l2, to_dev
+from oracle.steppers import run
+
+pytestmark = pytest.mark.gpu
+DTYPES = ["float64", "float32"]
+
+
+def _shots(dtype, dims):
+    cases = []
+    for i, n in enumerate(dims):
+        c = make_case(n, dtype, seed=50 + i, n_src=1 + i % 2, abc=3)
+        g = c.prob.grid
+        rec = np.unique(np.linspace(0, g.npts - 1, 7).astype(np.int64))
+        c.op.set_receivers(rec)
+        cases.append((c, rec))
+    return cases
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_matches_single_shots_and_oracle(dtype):
+    import torch
+    from paper_2401_16322_amd.expwave import Batch
+    dims = [(90, 40), (33, 71), (128, 65), (20, 18), (257, 30)]
+    ms = [2, 3, 16, 7, 12]
+    dts = [1e-3, 2e-3, 2e-3, 1.5e-3, 3e-3]
+    cases = _shots(dtype, dims)
+    nst, t0 = 3, 0.02
+    states = [to_dev(c, c.U0) for c, _ in cases]
+    traces = [torch.zeros(nst * r.size, dtype=c.torch_dtype, device="cuda") for c, r in cases]
+    b = Batch([c.op for c, _ in cases], ms, dts, states, traces)
+    b.step(t0, nst)
+    torch.cuda.synchronize()
+    tight = 1e-13 if dtype == "float64" else 2e-6
+    for (c, rec), S, tr, m, dt in zip(cases, states, traces, ms, dts):
+        U = to_dev(c, c.U0)
+        tr1 = torch.zeros(nst * rec.size, dtype=c.torch_dtype, device="cuda")
+        c.op.set_tuning(1)
+        c.op.step_faber(U, t0, dt, m, nst, traces=tr1)
+        assert rel_l2(S.cpu().numpy(), U.cpu().numpy()) <= tight
+        assert rel_l2(tr.cpu().numpy(), tr1.cpu().numpy()) <= tight
+    c, rec = cases[2]
+    Uref, trref, _ = run(c.prob, "faber", c.U0, t0, dts[2], nst, receivers=rec, m=ms[2], p=c.p,
+                         ellipse=c.op.ellipse)
+    assert rel_l2(states[2].cpu().numpy(), Uref) <= TOL[dtype]
+    assert rel_l2(traces[2].cpu().numpy().reshape(nst, -1), trref) <= TOL[dtype]
+    b.close()
+
+
+def test_batch_3d_and_trace_offset():
+    import torch
+    from paper_2401_16322_amd.expwave import Batch
+    cases = _shots("float64", [(17, 13, 11), (9, 20, 14)])
+    states = [to_dev(c, c.U0) for c, _ in cases]
+    traces = [torch.zeros(4 * r.size, dtype=torch.float64, device="cuda") for c, r in cases]
+    b = Batch([c.op for c, _ in cases], [5, 8], [2e-3, 1e-3], states, [traces[0], None])
+    b.step(0.03, 2, trace_step0=2)
+    torch.cuda.synchronize()
+    for (c, rec), S, m, dt in zip(cases, states, [5, 8], [2e-3, 1e-3]):
+        Uref, _, _ = run(c.prob, "faber", c.U0, 0.03, dt, 2, m=m, p=c.p, ellipse=c.op.ellipse)
+        assert rel_l2(S.cpu().numpy(), Uref) <= 1e-11
+    t = traces[0].cpu().numpy().reshape(4, -1)
+    assert not np.any(t[:2]) and np.all(np.isfinite(t[2:])) and np.any(t[2:])
+    assert not np.any(traces[1].cpu().numpy())
+    b.close()
+
+
+def test_batch_validation():
+    import torch
+    from paper_2401_16322_amd.expwave import Batch, ExpwError
+    a = make_case((20, 10), "float64", seed=60)
+    b = make_case((20, 10), "float32", seed=61)
+    sa, sb = to_dev(a, a.U0), to_dev(b, b.U0)
+    with pytest.raises(ExpwError):
+        Batch([a.op, b.op], [4, 4], [1e-3, 1e-3], [sa, sb])       # mixed dtype
+    with pytest.raises(ExpwError):
+        Batch([a.op], [1], [1e-3], [sa])                        # degree < 2
+    c = make_case((20, 10), "float64", seed=62)
+    with pytest.raises(ExpwError):
+        Batch([a.op, c.op], [4, 4], [1e-3, 1e-3], [sa, sa])     # shared state
