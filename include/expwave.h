@@ -242,11 +242,13 @@ int32_t expw_faber_adjoint_step(expw_op* op, const void* u_dev, void* lam_dev, d
  * sources; device atomics, so repeated receivers add up). */
 int32_t expw_inject_receivers(expw_op* op, const void* values_dev, double scale, void* state_dev);
 
-/* Batches of independent problems (shots) stepped together: term j of every
- * shot with degree >= j runs in one launch (Faber recurrence, Sec. 3.2), so
- * a step costs max(m) + 1 launches instead of sum(m) + n. The shots keep
- * their own operators, grids, ellipses, sources and receivers but must share
- * dtype, ndim, order and bc; each shot uses its operator's workspace. */
+/* Batches of independent problems (shots) stepped together (Faber
+ * recurrence, Sec. 3.2): 2D order-4 zero-ghost shots run passes of 4 terms,
+ * pass p of every shot still running in one launch (ceil(max m / 4) + 1
+ * launches per step); other shots run term j of every shot with degree >= j
+ * in one launch (max m + 1 launches). The shots keep their own operators,
+ * grids, ellipses, sources and receivers but must share dtype, ndim, order
+ * and bc; each shot uses its operator's workspace. */
 typedef struct expw_batch expw_batch;
 /* Device bytes of the descriptor table of n_ops shots with grids like g. */
 int32_t expw_batch_table_bytes(int32_t n_ops, const expw_grid* g, size_t* bytes);

@@ -13,6 +13,7 @@
 
 #include "device_common.h"
 #include "expwave.h"
+#include "fused.h"
 #include "kernels.h"
 
 namespace expw {
@@ -147,6 +148,98 @@ __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchShot<T, K, D
   const BatchShot<T, K, DIM>& sh = shots[lo];
   const int64_t r = it - prefix_rec[lo];
   if (sh.traces && r < sh.n_rec) sh.traces[step * sh.n_rec + r] = sh.S[sh.rec[r]];
+}
+
+// Fused passes for batches of 2D order-4 zero-ghost shots: pass p of every
+// shot still running applies its terms 1 + p S .. min(m, (p + 1) S) over the
+// shot's tiles in one launch (a last pass with n < S terms runs the last n
+// terms of the S-term tile schedule). Buffers per shot as in the one-shot
+// fused step: (A, B) and (D, E) alternate as (v_last, v_prev), C holds the
+// sum, the last pass writes it into S (a shot of one pass writes C, copied
+// afterwards).
+constexpr int kBatchFuse = 4;
+
+template <typename T>
+struct FusedShot {
+  Geo<T, 2, 2> g;
+  T *S, *A, *B, *C, *D, *E;
+  int32_t m, tiles_x, tiles_y, n_src, p, pad_;
+  int64_t src_lo, src_hi;
+  const int64_t* src_idx;
+  const T* src_amp;
+  double f_peak, t_delay, dt;
+  T inv_gamma, c0, c1;
+  T a_hi[kBatchMaxM + 1], a_lo[kBatchMaxM + 1];
+  double qtab[kBatchMaxM][EXPW_MAX_TAYLOR];
+};
+
+template <typename T, int S>
+__global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d_batch(
+    const FusedShot<T>* shots, const int64_t* prefix, int n_part, int pass, double t0,
+    int64_t step) {
+  const int s = batch_shot(prefix, n_part);
+  const FusedShot<T>& sh = shots[s];
+  const int t = static_cast<int>(static_cast<int64_t>(blockIdx.x) - prefix[s]);
+  const int tx_ = t % sh.tiles_x, ty_ = t / sh.tiles_x;
+  const int j0 = 1 + pass * S;
+  const int n = min(S, sh.m - j0 + 1);
+  const int r0 = S - n;
+  const bool first = (pass == 0);
+  const bool last = (j0 + n - 1 == sh.m);
+  FusedArgs<T, S> c{};
+  c.inv_gamma = sh.inv_gamma;
+  c.c0 = sh.c0;
+  c.first = first ? 1 : 0;
+  c.a_first = sh.a_hi[0];
+  c.a_first_lo = sh.a_lo[0];
+  // source scalars of the pass's terms: q_r = sum_c g^(p-1-c)(t) qtab[j_r - 1][c],
+  // accumulated while the Ricker derivatives are generated (no arrays)
+  double q[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) q[r] = 0.0;
+  if (sh.n_src > 0) {
+    const double pi = 3.14159265358979323846264338327950;
+    const double a = (pi * sh.f_peak) * (pi * sh.f_peak);
+    const double tau = t0 + step * sh.dt - sh.t_delay;
+    const double sa = sqrt(a);
+    const double xs = sa * tau;
+    const double e = exp(-a * tau * tau);
+    double hm1 = 1.0, h0 = 2.0 * xs, apow = a;
+    for (int nn = 1; nn <= sh.p; ++nn) {
+      const double h1 = 2.0 * xs * h0 - 2.0 * nn * hm1;  // H_{nn+1}
+      hm1 = h0;
+      h0 = h1;
+      const int k = nn - 1;                             // g^(k) uses H_{k+2}
+      const double gk = -(1.0 / (2.0 * a)) * ((k % 2 == 0) ? 1.0 : -1.0) * apow * h0 * e;
+      apow *= sa;
+      const int cc = sh.p - 1 - k;
+#pragma unroll
+      for (int r = 0; r < S; ++r)
+        if (r >= r0) q[r] += gk * sh.qtab[j0 + (r - r0) - 1][cc];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    const int j = j0 + (r - r0);
+    const bool on = r >= r0;
+    c.a[r] = on ? sh.a_hi[j] : T(0);
+    c.a_lo[r] = on ? sh.a_lo[j] : T(0);
+    c.cpp[r] = (!on || j == 1) ? T(0) : (j == 2 ? T(2) * sh.c1 : sh.c1);
+    c.q[r] = static_cast<T>(q[r]);
+  }
+  const bool odd_in = ((pass - 1) & 1) != 0, odd_out = (pass & 1) != 0;
+  const T* vp = first ? sh.S : (odd_in ? sh.D : sh.A);
+  const T* vpp = first ? nullptr : (odd_in ? sh.E : sh.B);
+  T* ol = last ? nullptr : (odd_out ? sh.D : sh.A);
+  T* opv = last ? nullptr : (odd_out ? sh.E : sh.B);
+  T* acc_out = (last && !first) ? sh.S : sh.C;
+  Src<T> src{};
+  src.n = sh.n_src;
+  src.lo = sh.src_lo;
+  src.hi = sh.src_hi;
+  src.idx = sh.src_idx;
+  src.amp = sh.src_amp;
+  fused2d_pass<T, S>(sh.g, vp, vpp, first ? nullptr : sh.C, ol, opv, acc_out, c, src, tx_, ty_, r0);
 }
 
 }  // namespace expw

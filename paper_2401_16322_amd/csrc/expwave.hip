@@ -64,6 +64,14 @@ struct expw_batch {
   std::vector<int> count_ge;        // count_ge[j] = shots with degree >= j
   std::vector<int64_t> prefix;      // host copy of the block prefix
   int64_t rec_items;
+  // fused passes (2D, order 4, zero ghosts)
+  bool fused;
+  size_t off_fshots, off_fprefix;
+  int max_passes;
+  std::vector<int> count_pass;      // count_pass[p] = shots with more than p passes
+  std::vector<int64_t> fprefix;     // host copy of the tile prefix
+  std::vector<void*> copy_dst, copy_src;  // one-pass shots: sum C -> state
+  std::vector<size_t> copy_bytes;
 };
 
 namespace expw {
@@ -655,7 +663,10 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
 
 template <typename T, int K, int DIM>
 size_t batch_table_bytes(int n) {
-  return align_up(n * sizeof(BatchShot<T, K, DIM>)) + 2 * align_up((n + 1) * sizeof(int64_t));
+  size_t b = align_up(n * sizeof(BatchShot<T, K, DIM>)) + 2 * align_up((n + 1) * sizeof(int64_t));
+  if (K == 2 && DIM == 2)
+    b += align_up(n * sizeof(FusedShot<T>)) + align_up((n + 1) * sizeof(int64_t));
+  return b;
 }
 
 template <typename T, int K, int BC, int DIM>
@@ -729,6 +740,72 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
     for (int j = 1; j <= host[r].m; ++j) b->count_ge[j]++;
   b->prefix = prefix;
   b->rec_items = prefix_rec[n];
+  b->fused = false;
+  if constexpr (K == 2 && BC == 0 && DIM == 2) {
+    bool ok = true;
+    for (int r = 0; r < n; ++r) ok = ok && 3 * host[r].g.N < (int64_t(1) << 31);
+    if (ok) {
+      constexpr int S = kBatchFuse;
+      constexpr int TX = FusedTile<S>::TX, TY = FusedTile<S>::TY;
+      std::vector<unsigned char> fb(n * sizeof(FusedShot<T>), 0);
+      auto* fs = reinterpret_cast<FusedShot<T>*>(fb.data());
+      std::vector<int64_t> fprefix(n + 1, 0);
+      b->copy_dst.clear();
+      b->copy_src.clear();
+      b->copy_bytes.clear();
+      b->max_passes = 0;
+      for (int r = 0; r < n; ++r) {
+        const Shot& h = host[r];
+        FusedShot<T>& f = fs[r];
+        std::memcpy(static_cast<void*>(&f.g), &h.g, sizeof(h.g));
+        const int64_t ns = 3 * h.g.N;
+        f.S = h.S;
+        f.A = h.A;
+        f.B = h.B;
+        f.C = h.C;
+        f.D = h.C + ns;
+        f.E = f.D + ns;
+        f.m = h.m;
+        f.tiles_x = static_cast<int32_t>((h.g.n[0] + TX - 1) / TX);
+        f.tiles_y = static_cast<int32_t>((h.g.n[1] + TY - 1) / TY);
+        f.n_src = h.n_src;
+        f.p = h.p;
+        f.src_lo = h.src_lo;
+        f.src_hi = h.src_hi;
+        f.src_idx = h.src_idx;
+        f.src_amp = h.src_amp;
+        f.f_peak = h.f_peak;
+        f.t_delay = h.t_delay;
+        f.dt = h.dt;
+        f.inv_gamma = h.inv_gamma;
+        f.c0 = h.c0;
+        f.c1 = h.c1;
+        std::memcpy(f.a_hi, h.a_hi, sizeof(h.a_hi));
+        std::memcpy(f.a_lo, h.a_lo, sizeof(h.a_lo));
+        std::memcpy(f.qtab, h.qtab, sizeof(h.qtab));
+        fprefix[r + 1] = fprefix[r] + static_cast<int64_t>(f.tiles_x) * f.tiles_y;
+        const int passes = (h.m + S - 1) / S;
+        b->max_passes = std::max(b->max_passes, passes);
+        if (passes == 1) {
+          b->copy_dst.push_back(h.S);
+          b->copy_src.push_back(h.C);
+          b->copy_bytes.push_back(ns * sizeof(T));
+        }
+      }
+      b->count_pass.assign(b->max_passes, 0);
+      for (int r = 0; r < n; ++r)
+        for (int p = 0; p < (host[r].m + S - 1) / S; ++p) b->count_pass[p]++;
+      b->off_fshots = b->off_prefix_rec + align_up((n + 1) * sizeof(int64_t));
+      b->off_fprefix = b->off_fshots + align_up(n * sizeof(FusedShot<T>));
+      if (fprefix[n] > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "batch too large for one launch");
+      if (hipMemcpyAsync(t + b->off_fshots, fb.data(), fb.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+          hipMemcpyAsync(t + b->off_fprefix, fprefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+          hipStreamSynchronize(b->stream) != hipSuccess)
+        return fail(EXPW_EDEVICE, "batch table upload failed");
+      b->fprefix = fprefix;
+      b->fused = true;
+    }
+  }
   return EXPW_OK;
 }
 
@@ -739,11 +816,31 @@ int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t trace_
   const int64_t* prefix = reinterpret_cast<const int64_t*>(static_cast<char*>(b->table) + b->off_prefix);
   const int64_t* prefix_rec = reinterpret_cast<const int64_t*>(static_cast<char*>(b->table) + b->off_prefix_rec);
   for (int64_t st = 0; st < nsteps; ++st) {
-    for (int j = 1; j <= b->max_m; ++j) {
-      const int np = b->count_ge[j];
-      const unsigned grid = static_cast<unsigned>(b->prefix[np]);
-      k_faber_batch_term<T, K, BC, DIM><<<grid, kBlock, 0, b->stream>>>(shots, prefix, np, j, t0, st);
-      if (int32_t rc = check_launch("batch term")) return rc;
+    bool done = false;
+    if constexpr (K == 2 && BC == 0 && DIM == 2) {
+      if (b->fused) {
+        char* t = static_cast<char*>(b->table);
+        const auto* fshots = reinterpret_cast<const FusedShot<T>*>(t + b->off_fshots);
+        const auto* fprefix = reinterpret_cast<const int64_t*>(t + b->off_fprefix);
+        for (int p = 0; p < b->max_passes; ++p) {
+          const int np = b->count_pass[p];
+          const unsigned grid = static_cast<unsigned>(b->fprefix[np]);
+          k_faber_fused2d_batch<T, kBatchFuse><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, t0, st);
+          if (int32_t rc = check_launch("batch fused pass")) return rc;
+        }
+        for (size_t i = 0; i < b->copy_dst.size(); ++i)
+          if (hipMemcpyAsync(b->copy_dst[i], b->copy_src[i], b->copy_bytes[i], hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+            return fail(EXPW_EDEVICE, "batch: copy failed");
+        done = true;
+      }
+    }
+    if (!done) {
+      for (int j = 1; j <= b->max_m; ++j) {
+        const int np = b->count_ge[j];
+        const unsigned grid = static_cast<unsigned>(b->prefix[np]);
+        k_faber_batch_term<T, K, BC, DIM><<<grid, kBlock, 0, b->stream>>>(shots, prefix, np, j, t0, st);
+        if (int32_t rc = check_launch("batch term")) return rc;
+      }
     }
     if (b->rec_items > 0) {
       k_batch_gather<T, K, DIM><<<grid_for(b->rec_items), kBlock, 0, b->stream>>>(shots, prefix_rec, b->n, trace_step0 + st);

@@ -48,11 +48,15 @@ struct FusedArgs {
   T a[S], a_lo[S], cpp[S], q[S];
 };
 
-// One pass of exactly S recurrence terms. 2D grids with 3 * points < 2^31.
+// One pass over tile (tx_, ty_) of the recurrence terms r0..S-1 of an S-term
+// pass (r0 > 0 runs the last S - r0 terms only: a shorter pass on the same
+// tile). 2D grids with 3 * points < 2^31.
 template <typename T, int S>
-__global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d(
-    Geo<T, 2, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp, const T* acc_in,
-    T* __restrict__ out_last, T* __restrict__ out_prev, T* acc_out, FusedArgs<T, S> c, Src<T> src) {
+__device__ __forceinline__ void fused2d_pass(const Geo<T, 2, 2>& g, const T* __restrict__ vp,
+                                             const T* __restrict__ vpp, const T* acc_in,
+                                             T* __restrict__ out_last, T* __restrict__ out_prev,
+                                             T* acc_out, const FusedArgs<T, S>& c,
+                                             const Src<T>& src, int tx_, int ty_, int r0) {
   constexpr int K = 2;
   constexpr int H = K * S;
   constexpr int TX = FusedTile<S>::TX, TY = FusedTile<S>::TY;
@@ -63,15 +67,6 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
   __shared__ T cur[3 * E];
   __shared__ T sacc[3 * TX * TY];
 
-  // XCD-aware tile order: block b runs on XCD b % 8, which owns a band of
-  // band_w tile columns and walks it row by row (k = b / 8), so the tiles
-  // above and below a tile run on the same XCD at about the same time and
-  // their shared halo rows are read from its L2.
-  const int b = blockIdx.x;
-  const int kk = b >> 3;
-  const int ty_ = kk / c.band_w;
-  const int tx_ = (b & 7) * c.band_w + (kk - ty_ * c.band_w);
-  if (tx_ >= c.tiles_x || ty_ >= c.tiles_y) return;
   const int nx = static_cast<int>(g.n[0]), nz = static_cast<int>(g.n[1]);
   const int N = static_cast<int>(g.N);
   const int x0 = tx_ * TX - H;  // global x of LDS column 0
@@ -152,6 +147,7 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
   const T* cvz = cur + 2 * E;
 #pragma unroll
   for (int r = 0; r < S; ++r) {
+    if (r < r0) continue;  // block-uniform
     const T cpp = c.cpp[r];
     const T qr = c.q[r];
 #pragma unroll
@@ -220,6 +216,23 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
     acc_out[N + gi] = sacc[TX * TY + t];
     acc_out[2 * N + gi] = sacc[2 * TX * TY + t];
   }
+}
+
+// One pass of exactly S recurrence terms over every tile of the grid.
+// XCD-aware tile order: block b runs on XCD b % 8, which owns a band of
+// band_w tile columns and walks it row by row (k = b / 8), so the tiles above
+// and below a tile run on the same XCD at about the same time and their
+// shared halo rows are read from its L2.
+template <typename T, int S>
+__global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d(
+    Geo<T, 2, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp, const T* acc_in,
+    T* __restrict__ out_last, T* __restrict__ out_prev, T* acc_out, FusedArgs<T, S> c, Src<T> src) {
+  const int b = blockIdx.x;
+  const int kk = b >> 3;
+  const int ty_ = kk / c.band_w;
+  const int tx_ = (b & 7) * c.band_w + (kk - ty_ * c.band_w);
+  if (tx_ >= c.tiles_x || ty_ >= c.tiles_y) return;
+  fused2d_pass<T, S>(g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src, tx_, ty_, 0);
 }
 
 // Fusion depth actually used for a request (1 = unfused kernels): 2D order 4

@@ -254,8 +254,8 @@ def shots(dtype="f32", nshots=64, steps=20, seed0=4000):
             "sequential_s": t_seq, "batched_s": t_bat,
             "sequential_grid_pt_matvecs_per_s": work / t_seq,
             "batched_grid_pt_matvecs_per_s": work / t_bat,
-            "launches_per_step": {"sequential_unfused_equiv": int(sum(ms) + nshots),
-                                  "batched": int(max(ms) + 1)}}
+            "launches_per_step": {"sequential": int(sum(math.ceil(m / 4) for m in ms)),
+                                  "batched": int(math.ceil(max(ms) / 4))}}
 
 
 def main():
