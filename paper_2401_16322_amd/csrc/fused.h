@@ -165,6 +165,10 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, 2, 2>& g, const T* __r
         nv[i][0] = hp * c.inv_gamma - c.c0 * pc - cpp * old[i][0] + qr * amp[i];
         nv[i][1] = hvx * c.inv_gamma - c.c0 * vxc - cpp * old[i][1];
         nv[i][2] = hvz * c.inv_gamma - c.c0 * vzc - cpp * old[i][2];
+        // v_{j-1} at the point becomes the next term's v_{j-2}
+        old[i][0] = pc;
+        old[i][1] = vxc;
+        old[i][2] = vzc;
       }
     }
     __syncthreads();  // every read of v_{j-1} is done
@@ -172,12 +176,8 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, 2, 2>& g, const T* __r
 #pragma unroll
     for (int i = 0; i < NSL; ++i) {
       if (r <= last[i]) {
-        // only this thread writes point l, so v_{j-1} is still there to keep
         const int ly = X0 + wave + 16 * i;
         const int l = ly * EX + lx;
-        old[i][0] = cur[l];
-        old[i][1] = cur[E + l];
-        old[i][2] = cur[2 * E + l];
         cur[l] = nv[i][0];
         cur[E + l] = nv[i][1];
         cur[2 * E + l] = nv[i][2];

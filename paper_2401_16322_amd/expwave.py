@@ -396,6 +396,7 @@ class Operator:
         nbytes = expw_workspace_size(self.grid, max_krylov_k, max_taylor_p)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._rec = None
+        self.fuse = 0
         self.op = expw_op_create(self.grid, self.c2.data_ptr(), max_krylov_k, max_taylor_p,
                                  self.workspace.data_ptr(), nbytes, self._stream())
 
@@ -434,6 +435,36 @@ class Operator:
 
     def set_tuning(self, fuse=0):
         expw_set_tuning(self.op, fuse)
+        self.fuse = fuse
+
+    def autotune_fuse(self, m, dt, candidates=None, steps=3, repeats=2):
+        """Pick the Faber fusion depth (terms per sweep) that runs fastest
+        for degree m on this grid: each candidate runs `steps` steps on a
+        scratch state (twice, the better time counts; HIP events on the
+        operator's stream), then the fastest is set. Returns
+        (best, {depth: ms per step})."""
+        torch = self._torch
+        if candidates is None:
+            candidates = (1, 2, 3, 4, 5, 6, 8) if self.dtype == torch.float32 else (1, 2, 3, 4)
+        scratch = torch.zeros(self.nstate, dtype=self.dtype, device=self.device)
+        times = {}
+        for f in candidates:
+            self.set_tuning(f)
+            self.step_faber(scratch, 0.0, dt, m, 1)   # warm-up (and first-use set-up)
+            best = None
+            for _ in range(repeats):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                self.step_faber(scratch, 0.0, dt, m, steps)
+                e1.record()
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / steps
+                best = ms if best is None else min(best, ms)
+            times[f] = best
+        fbest = min(times, key=times.get)
+        self.set_tuning(fbest)
+        return fbest, times
 
     def apply(self, x, out=None):
         self._check_state(x)

@@ -81,3 +81,18 @@ def test_batch_validation():
     c = make_case((20, 10), "float64", seed=62)
     with pytest.raises(ExpwError):
         Batch([a.op, c.op], [4, 4], [1e-3, 1e-3], [sa, sa])     # shared state
+
+
+def test_autotune_fuse_picks_a_depth_with_the_same_results():
+    """The autotuner times the depths and keeps the fastest; any depth gives
+    the same step (rounding order aside)."""
+    case = make_case((300, 140), "float32", seed=70)
+    best, times = case.op.autotune_fuse(16, 2e-3, candidates=(1, 2, 4, 8), steps=2, repeats=1)
+    assert best in times and times[best] == min(times.values())
+    assert case.op.fuse == best
+    U = to_dev(case, case.U0)
+    case.op.step_faber(U, 0.0, 2e-3, 16, 2)
+    case.op.set_tuning(1)
+    V = to_dev(case, case.U0)
+    case.op.step_faber(V, 0.0, 2e-3, 16, 2)
+    assert rel_l2(U.cpu().numpy(), V.cpu().numpy()) <= 2e-6
