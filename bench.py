@@ -32,11 +32,19 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_2401_16322_amd", "csrc")
 
 
-def kernel_sources_digest():
-    """sha256 over the library's kernel sources (names and contents)."""
+# the sources each timed kernel class is compiled from (its own header and
+# the device headers it includes)
+KERNEL_SOURCES = {
+    "krylov_arnoldi": ("arnoldi.h", "device_common.h", "kernels.h"),
+    "faber": ("fused.h", "device_common.h", "kernels.h"),
+}
+
+
+def kernel_sources_digest(kernel):
+    """sha256 over the sources of one kernel class (names and contents)."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in KERNEL_SOURCES.get(kernel, tuple(sorted(os.listdir(CSRC)))):
         h.update(f.encode())
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
@@ -49,7 +57,7 @@ def measured_traffic(kernel, workload, dtype):
     None when there is none for this case or the kernels changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    digest = kernel_sources_digest()
+    digest = kernel_sources_digest(kernel)
     with open(TRAFFIC_FILE) as fh:
         for line in fh:
             f = line.split()
