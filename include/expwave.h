@@ -262,9 +262,16 @@ int32_t expw_batch_table_bytes(int32_t n_ops, const expw_grid* g, size_t* bytes)
 int32_t expw_batch_create(expw_op* const* ops, int32_t n_ops, const int32_t* m, const double* dt,
                           void* const* states_dev, void* const* traces_dev, void* table_dev,
                           size_t table_bytes, void* stream, expw_batch** out);
-/* nsteps steps of every shot; shot i's step s runs from t0 + s dt[i]. The
- * traces of step s go to row trace_step0 + s. */
-int32_t expw_batch_step_faber(expw_batch* b, double t0, int64_t nsteps, int64_t trace_step0);
+/* nsteps steps of every shot, numbered step0, step0 + 1, ...: shot i's step
+ * n runs from t0 + n dt[i] and its traces go to row n. */
+int32_t expw_batch_step_faber(expw_batch* b, double t0, int64_t nsteps, int64_t step0);
+/* Captures the launches of nsteps steps into a HIP graph (stream capture on
+ * the batch's stream, which must not be the default stream); later step
+ * calls replay it for every whole group of nsteps steps (the step time and
+ * trace row come from a clock in the table, set by a small kernel before
+ * each replay). nsteps = 0 drops the graph. The graph holds no memset or
+ * memcpy nodes. */
+int32_t expw_batch_capture(expw_batch* b, int64_t nsteps);
 int32_t expw_batch_destroy(expw_batch* b);
 
 /* Krylov steps (Arnoldi with modified Gram-Schmidt on the augmented matrix,

@@ -20,6 +20,31 @@ namespace expw {
 
 constexpr int kBatchMaxM = 64;
 
+// Time base of the batch's kernels in device memory: step st of a sequence
+// runs at t0 + (step0 + st) dt of each shot and records into trace row
+// trace0 + st. Kept in memory (set by k_batch_set_clock before a sequence)
+// so that a captured sequence of launches can be replayed at other times.
+struct BatchClock {
+  double t0;
+  int64_t step0, trace0;
+};
+
+__global__ void k_batch_set_clock(BatchClock* clk, double t0, int64_t step0, int64_t trace0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    clk->t0 = t0;
+    clk->step0 = step0;
+    clk->trace0 = trace0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_batch_copy(T* __restrict__ dst, const T* __restrict__ src,
+                                                       int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    dst[i] = src[i];
+}
+
 template <typename T, int K, int DIM>
 struct BatchShot {
   Geo<T, K, DIM> g;
@@ -78,7 +103,8 @@ __device__ __forceinline__ int batch_shot(const int64_t* prefix, int n_part) {
 template <typename T, int K, int BC, int DIM>
 __global__ __launch_bounds__(kBlock) void k_faber_batch_term(const BatchShot<T, K, DIM>* shots,
                                                              const int64_t* prefix, int n_part,
-                                                             int j, double t0, int64_t step) {
+                                                             int j, const BatchClock* clk,
+                                                             int64_t st) {
   const int s = batch_shot(prefix, n_part);
   const BatchShot<T, K, DIM>& sh = shots[s];
   const Geo<T, K, DIM>& g = sh.g;
@@ -113,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_faber_batch_term(const BatchShot<T, 
       if (sh.src_idx[k] == idx) am += sh.src_amp[k];
     if (am != T(0)) {
       double der[EXPW_MAX_TAYLOR];
-      ricker_derivatives_dev(t0 + step * sh.dt, sh.f_peak, sh.t_delay, sh.p, der);
+      ricker_derivatives_dev(clk->t0 + (clk->step0 + st) * sh.dt, sh.f_peak, sh.t_delay, sh.p, der);
       double q = 0.0;
       for (int c = 0; c < sh.p; ++c) q += der[sh.p - 1 - c] * sh.qtab[j - 1][c];
       src = static_cast<T>(q) * am;
@@ -136,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_faber_batch_term(const BatchShot<T, 
 template <typename T, int K, int DIM>
 __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchShot<T, K, DIM>* shots,
                                                          const int64_t* prefix_rec, int n_shots,
-                                                         int64_t step) {
+                                                         const BatchClock* clk, int64_t st) {
   const int64_t it = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   if (it >= prefix_rec[n_shots]) return;
   int lo = 0, hi = n_shots - 1;
@@ -147,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchShot<T, K, D
   }
   const BatchShot<T, K, DIM>& sh = shots[lo];
   const int64_t r = it - prefix_rec[lo];
-  if (sh.traces && r < sh.n_rec) sh.traces[step * sh.n_rec + r] = sh.S[sh.rec[r]];
+  if (sh.traces && r < sh.n_rec) sh.traces[(clk->trace0 + st) * sh.n_rec + r] = sh.S[sh.rec[r]];
 }
 
 // Fused passes for batches of 2D order-4 zero-ghost shots: pass p of every
@@ -175,8 +201,8 @@ struct FusedShot {
 
 template <typename T, int S>
 __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d_batch(
-    const FusedShot<T>* shots, const int64_t* prefix, int n_part, int pass, double t0,
-    int64_t step) {
+    const FusedShot<T>* shots, const int64_t* prefix, int n_part, int pass,
+    const BatchClock* clk, int64_t st) {
   const int s = batch_shot(prefix, n_part);
   const FusedShot<T>& sh = shots[s];
   const int t = static_cast<int>(static_cast<int64_t>(blockIdx.x) - prefix[s]);
@@ -200,7 +226,7 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
   if (sh.n_src > 0) {
     const double pi = 3.14159265358979323846264338327950;
     const double a = (pi * sh.f_peak) * (pi * sh.f_peak);
-    const double tau = t0 + step * sh.dt - sh.t_delay;
+    const double tau = clk->t0 + (clk->step0 + st) * sh.dt - sh.t_delay;
     const double sa = sqrt(a);
     const double xs = sa * tau;
     const double e = exp(-a * tau * tau);

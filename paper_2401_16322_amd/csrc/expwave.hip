@@ -71,7 +71,12 @@ struct expw_batch {
   std::vector<int> count_pass;      // count_pass[p] = shots with more than p passes
   std::vector<int64_t> fprefix;     // host copy of the tile prefix
   std::vector<void*> copy_dst, copy_src;  // one-pass shots: sum C -> state
-  std::vector<size_t> copy_bytes;
+  std::vector<int64_t> copy_elems;
+  size_t off_clock;
+  // a captured sequence of graph_steps steps (nullptr: none)
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+  int64_t graph_steps;
 };
 
 namespace expw {
@@ -666,7 +671,7 @@ size_t batch_table_bytes(int n) {
   size_t b = align_up(n * sizeof(BatchShot<T, K, DIM>)) + 2 * align_up((n + 1) * sizeof(int64_t));
   if (K == 2 && DIM == 2)
     b += align_up(n * sizeof(FusedShot<T>)) + align_up((n + 1) * sizeof(int64_t));
-  return b;
+  return b + align_up(sizeof(BatchClock));
 }
 
 template <typename T, int K, int BC, int DIM>
@@ -752,7 +757,7 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
       std::vector<int64_t> fprefix(n + 1, 0);
       b->copy_dst.clear();
       b->copy_src.clear();
-      b->copy_bytes.clear();
+      b->copy_elems.clear();
       b->max_passes = 0;
       for (int r = 0; r < n; ++r) {
         const Shot& h = host[r];
@@ -789,7 +794,7 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
         if (passes == 1) {
           b->copy_dst.push_back(h.S);
           b->copy_src.push_back(h.C);
-          b->copy_bytes.push_back(ns * sizeof(T));
+          b->copy_elems.push_back(ns);
         }
       }
       b->count_pass.assign(b->max_passes, 0);
@@ -806,31 +811,37 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
       b->fused = true;
     }
   }
+  b->off_clock = batch_table_bytes<T, K, DIM>(n) - align_up(sizeof(BatchClock));
   return EXPW_OK;
 }
 
+// Enqueues steps st = 0..count-1 of the batch (times and trace rows from the
+// clock in the table).
 template <typename T, int K, int BC, int DIM>
-int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t trace_step0) {
+int32_t batch_enqueue(expw_batch* b, int64_t count) {
   using Shot = BatchShot<T, K, DIM>;
-  const Shot* shots = static_cast<const Shot*>(b->table);
-  const int64_t* prefix = reinterpret_cast<const int64_t*>(static_cast<char*>(b->table) + b->off_prefix);
-  const int64_t* prefix_rec = reinterpret_cast<const int64_t*>(static_cast<char*>(b->table) + b->off_prefix_rec);
-  for (int64_t st = 0; st < nsteps; ++st) {
+  char* t = static_cast<char*>(b->table);
+  const Shot* shots = reinterpret_cast<const Shot*>(t);
+  const int64_t* prefix = reinterpret_cast<const int64_t*>(t + b->off_prefix);
+  const int64_t* prefix_rec = reinterpret_cast<const int64_t*>(t + b->off_prefix_rec);
+  const BatchClock* clk = reinterpret_cast<const BatchClock*>(t + b->off_clock);
+  for (int64_t st = 0; st < count; ++st) {
     bool done = false;
     if constexpr (K == 2 && BC == 0 && DIM == 2) {
       if (b->fused) {
-        char* t = static_cast<char*>(b->table);
         const auto* fshots = reinterpret_cast<const FusedShot<T>*>(t + b->off_fshots);
         const auto* fprefix = reinterpret_cast<const int64_t*>(t + b->off_fprefix);
         for (int p = 0; p < b->max_passes; ++p) {
           const int np = b->count_pass[p];
           const unsigned grid = static_cast<unsigned>(b->fprefix[np]);
-          k_faber_fused2d_batch<T, kBatchFuse><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, t0, st);
+          k_faber_fused2d_batch<T, kBatchFuse><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, clk, st);
           if (int32_t rc = check_launch("batch fused pass")) return rc;
         }
-        for (size_t i = 0; i < b->copy_dst.size(); ++i)
-          if (hipMemcpyAsync(b->copy_dst[i], b->copy_src[i], b->copy_bytes[i], hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
-            return fail(EXPW_EDEVICE, "batch: copy failed");
+        for (size_t i = 0; i < b->copy_dst.size(); ++i) {
+          const unsigned g = static_cast<unsigned>(std::min<int64_t>(4096, (b->copy_elems[i] + kBlock - 1) / kBlock));
+          k_batch_copy<T><<<g, kBlock, 0, b->stream>>>(static_cast<T*>(b->copy_dst[i]), static_cast<const T*>(b->copy_src[i]), b->copy_elems[i]);
+          if (int32_t rc = check_launch("batch copy")) return rc;
+        }
         done = true;
       }
     }
@@ -838,16 +849,43 @@ int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t trace_
       for (int j = 1; j <= b->max_m; ++j) {
         const int np = b->count_ge[j];
         const unsigned grid = static_cast<unsigned>(b->prefix[np]);
-        k_faber_batch_term<T, K, BC, DIM><<<grid, kBlock, 0, b->stream>>>(shots, prefix, np, j, t0, st);
+        k_faber_batch_term<T, K, BC, DIM><<<grid, kBlock, 0, b->stream>>>(shots, prefix, np, j, clk, st);
         if (int32_t rc = check_launch("batch term")) return rc;
       }
     }
     if (b->rec_items > 0) {
-      k_batch_gather<T, K, DIM><<<grid_for(b->rec_items), kBlock, 0, b->stream>>>(shots, prefix_rec, b->n, trace_step0 + st);
+      k_batch_gather<T, K, DIM><<<grid_for(b->rec_items), kBlock, 0, b->stream>>>(shots, prefix_rec, b->n, clk, st);
       if (int32_t rc = check_launch("batch gather")) return rc;
     }
   }
   return EXPW_OK;
+}
+
+template <typename T, int K, int BC, int DIM>
+int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t step0) {
+  BatchClock* clk = reinterpret_cast<BatchClock*>(static_cast<char*>(b->table) + b->off_clock);
+  int64_t done = 0;
+  while (done < nsteps) {
+    const bool use_graph = b->gexec && nsteps - done >= b->graph_steps;
+    const int64_t count = use_graph ? b->graph_steps : nsteps - done;
+    k_batch_set_clock<<<1, 1, 0, b->stream>>>(clk, t0, step0 + done, step0 + done);
+    if (int32_t rc = check_launch("batch clock")) return rc;
+    if (use_graph) {
+      if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return fail(EXPW_EDEVICE, "batch graph launch failed");
+    } else if (int32_t rc = batch_enqueue<T, K, BC, DIM>(b, count)) {
+      return rc;
+    }
+    done += count;
+  }
+  return EXPW_OK;
+}
+
+void batch_drop_graph(expw_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->graph_steps = 0;
 }
 
 template <class Fn>
@@ -1124,16 +1162,46 @@ int32_t expw_batch_create(expw_op* const* ops, int32_t n_ops, const int32_t* m, 
   return EXPW_OK;
 }
 
-int32_t expw_batch_step_faber(expw_batch* b, double t0, int64_t nsteps, int64_t trace_step0) {
+int32_t expw_batch_step_faber(expw_batch* b, double t0, int64_t nsteps, int64_t step0) {
   if (!b) return fail(EXPW_EINVAL, "batch is NULL");
-  if (nsteps < 0 || trace_step0 < 0) return fail(EXPW_EINVAL, "nsteps and trace_step0 must be >= 0");
+  if (nsteps < 0 || step0 < 0) return fail(EXPW_EINVAL, "nsteps and step0 must be >= 0");
   return dispatch_batch(b, [&](auto cfg) {
     using C = decltype(cfg);
-    return batch_step_impl<typename C::type, C::k, C::bc, C::dim>(b, t0, nsteps, trace_step0);
+    return batch_step_impl<typename C::type, C::k, C::bc, C::dim>(b, t0, nsteps, step0);
   });
 }
 
+int32_t expw_batch_capture(expw_batch* b, int64_t nsteps) {
+  if (!b) return fail(EXPW_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(EXPW_EINVAL, "nsteps must be >= 0");
+  batch_drop_graph(b);
+  if (nsteps == 0) return EXPW_OK;
+  if (!b->stream) return fail(EXPW_EINVAL, "capture needs a non-default stream (expw_batch_create)");
+  if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(EXPW_EDEVICE, "batch: stream capture could not start");
+  int32_t rc = dispatch_batch(b, [&](auto cfg) {
+    using C = decltype(cfg);
+    return batch_enqueue<typename C::type, C::k, C::bc, C::dim>(b, nsteps);
+  });
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc != EXPW_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != EXPW_OK ? rc : fail(EXPW_EDEVICE, "batch: stream capture failed");
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(EXPW_EDEVICE, "batch: graph instantiation failed");
+  }
+  b->graph = g;
+  b->gexec = x;
+  b->graph_steps = nsteps;
+  return EXPW_OK;
+}
+
 int32_t expw_batch_destroy(expw_batch* b) {
+  if (b) batch_drop_graph(b);
   delete b;
   return EXPW_OK;
 }

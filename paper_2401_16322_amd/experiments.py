@@ -242,16 +242,24 @@ def shots(dtype="f32", nshots=64, steps=20, seed0=4000):
     b.step(0.0, 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.step(0.0, steps)
+    b.step(0.0, steps, step0=2)
     torch.cuda.synchronize()
     t_bat = time.perf_counter() - t0
+    b.capture(steps)
+    b.step(0.0, steps, step0=2 + steps)   # first replay (warm-up)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(0.0, steps, step0=2 + 2 * steps)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
     for S in states:
         if not torch.isfinite(S).all():
             raise RuntimeError("non-finite state")
     b.close()
     return {"experiment": "uneven shots", "dtype": dtype, "shots": nshots, "steps": steps,
             "points": int(sum(npts)), "degrees": [min(ms), max(ms), float(np.mean(ms))],
-            "sequential_s": t_seq, "batched_s": t_bat,
+            "sequential_s": t_seq, "batched_s": t_bat, "batched_graph_s": t_graph,
+            "batched_graph_grid_pt_matvecs_per_s": work / t_graph,
             "sequential_grid_pt_matvecs_per_s": work / t_seq,
             "batched_grid_pt_matvecs_per_s": work / t_bat,
             "launches_per_step": {"sequential": int(sum(math.ceil(m / 4) for m in ms)),

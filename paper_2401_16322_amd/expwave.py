@@ -76,6 +76,7 @@ SIGNATURES = {
     "expw_batch_create": (_i32, [ctypes.POINTER(_vp), _i32, _pi32, _pd, ctypes.POINTER(_vp),
                                  ctypes.POINTER(_vp), _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     "expw_batch_step_faber": (_i32, [_vp, _dbl, _i64, _i64]),
+    "expw_batch_capture": (_i32, [_vp, _i64]),
     "expw_batch_destroy": (_i32, [_vp]),
     "expw_step_krylov": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_rk4": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
@@ -309,8 +310,12 @@ def expw_batch_create(ops, m, dt, state_ptrs, trace_ptrs, table_ptr, table_bytes
     return h.value
 
 
-def expw_batch_step_faber(batch, t0, nsteps, trace_step0=0):
-    _check(load().expw_batch_step_faber(batch, t0, nsteps, trace_step0))
+def expw_batch_step_faber(batch, t0, nsteps, step0=0):
+    _check(load().expw_batch_step_faber(batch, t0, nsteps, step0))
+
+
+def expw_batch_capture(batch, nsteps):
+    _check(load().expw_batch_capture(batch, nsteps))
 
 
 def expw_batch_destroy(batch):
@@ -645,12 +650,24 @@ class Batch:
         tptr = None
         if traces is not None:
             tptr = [t.data_ptr() if t is not None else None for t in traces]
-        stream = torch.cuda.current_stream(ops[0].device).cuda_stream
+        # the batch's own stream (default priority), ordered against the caller's
+        self.stream = torch.cuda.Stream(device=ops[0].device)
+        self.stream.wait_stream(torch.cuda.current_stream(ops[0].device))
         self.handle = expw_batch_create([o.op for o in ops], m, dt, [s.data_ptr() for s in states],
-                                        tptr, self.table.data_ptr(), nbytes, stream)
+                                        tptr, self.table.data_ptr(), nbytes, self.stream.cuda_stream)
 
-    def step(self, t0, nsteps=1, trace_step0=0):
-        expw_batch_step_faber(self.handle, t0, nsteps, trace_step0)
+    def step(self, t0, nsteps=1, step0=0):
+        """Steps step0 .. step0 + nsteps - 1: shot i's step n runs from
+        t0 + n dt[i] and records its traces in row n."""
+        cur = self._torch.cuda.current_stream(self.ops[0].device)
+        self.stream.wait_stream(cur)
+        expw_batch_step_faber(self.handle, t0, nsteps, step0)
+        cur.wait_stream(self.stream)
+
+    def capture(self, nsteps):
+        """Capture nsteps steps into a HIP graph replayed by step() (0 drops it)."""
+        self.stream.synchronize()
+        expw_batch_capture(self.handle, nsteps)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -57,10 +57,11 @@ def test_batch_3d_and_trace_offset():
     states = [to_dev(c, c.U0) for c, _ in cases]
     traces = [torch.zeros(4 * r.size, dtype=torch.float64, device="cuda") for c, r in cases]
     b = Batch([c.op for c, _ in cases], [5, 8], [2e-3, 1e-3], states, [traces[0], None])
-    b.step(0.03, 2, trace_step0=2)
+    b.step(0.03, 2, step0=2)          # steps 2 and 3: from 0.03 + 2 dt
     torch.cuda.synchronize()
     for (c, rec), S, m, dt in zip(cases, states, [5, 8], [2e-3, 1e-3]):
-        Uref, _, _ = run(c.prob, "faber", c.U0, 0.03, dt, 2, m=m, p=c.p, ellipse=c.op.ellipse)
+        Uref, _, _ = run(c.prob, "faber", c.U0, 0.03 + 2 * dt, dt, 2, m=m, p=c.p,
+                         ellipse=c.op.ellipse)
         assert rel_l2(S.cpu().numpy(), Uref) <= 1e-11
     t = traces[0].cpu().numpy().reshape(4, -1)
     assert not np.any(t[:2]) and np.all(np.isfinite(t[2:])) and np.any(t[2:])
@@ -96,3 +97,48 @@ def test_autotune_fuse_picks_a_depth_with_the_same_results():
     V = to_dev(case, case.U0)
     case.op.step_faber(V, 0.0, 2e-3, 16, 2)
     assert rel_l2(U.cpu().numpy(), V.cpu().numpy()) <= 2e-6
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_graph_replays_match_eager(dtype):
+    """A captured 2-step graph replayed three times (eager work and
+    synchronisations between the replays) gives the same states and traces
+    as the same steps launched eagerly, bit for bit, after every replay; a
+    remainder step after the replays runs eagerly."""
+    import torch
+    from paper_2401_16322_amd.expwave import Batch
+    dims = [(90, 40), (64, 33), (120, 50)]
+    ms, dts = [3, 9, 16], [1e-3, 2e-3, 2e-3]
+    A = _shots(dtype, dims)
+    B = _shots(dtype, dims)
+    sa = [to_dev(c, c.U0) for c, _ in A]
+    sb = [to_dev(c, c.U0) for c, _ in B]
+    ta = [torch.zeros(7 * r.size, dtype=c.torch_dtype, device="cuda") for c, r in A]
+    tb = [torch.zeros(7 * r.size, dtype=c.torch_dtype, device="cuda") for c, r in B]
+    ga = Batch([c.op for c, _ in A], ms, dts, sa, ta)
+    eb = Batch([c.op for c, _ in B], ms, dts, sb, tb)
+    ga.capture(2)
+    for rep in range(3):
+        ga.step(0.02, 2, step0=2 * rep)          # one graph replay
+        eb.step(0.02, 1, step0=2 * rep)          # the same two steps, eagerly
+        eb.step(0.02, 1, step0=2 * rep + 1)
+        torch.cuda.synchronize()
+        x = torch.randn(4096, device="cuda")     # eager work between replays
+        float((x * x).sum())
+        torch.cuda.synchronize()
+        for u, v in zip(sa + ta, sb + tb):
+            assert torch.equal(u, v)
+    ga.step(0.02, 1, step0=6)                    # shorter than the graph: eager
+    eb.step(0.02, 1, step0=6)
+    torch.cuda.synchronize()
+    for u, v in zip(sa + ta, sb + tb):
+        assert torch.equal(u, v)
+    # and the eager batch itself matches one-shot stepping after 7 steps
+    tight = 1e-13 if dtype == "float64" else 2e-6
+    for (c, rec), S, m, dt in zip(B, sb, ms, dts):
+        U = to_dev(c, c.U0)
+        c.op.set_tuning(1)
+        c.op.step_faber(U, 0.02, dt, m, 7)
+        assert rel_l2(S.cpu().numpy(), U.cpu().numpy()) <= tight
+    ga.close()
+    eb.close()
