@@ -1,0 +1,94 @@
+"""Parity at the full sizes of the 3D workload (256^3) and of the 8192x4096
+shape, in the bench's launch configuration, through the domain of dependence:
+a Faber step of degree m moves information at most m K cells (K = 2 for the
+order-4 stencil), so from a state of compact support in the interior the GPU
+result on the whole grid must equal the oracle's result on a sub-box that
+holds the support plus that reach, and be exactly zero outside it. The
+sub-box lies where the damping profile is zero, so the oracle's own grid for
+it (no layer) has the same operator there."""
+import numpy as np
+import pytest
+
+from gpu_cases import TOL, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _pulse(n, centre, radius):
+    """Pressure pulse of compact support (zero beyond `radius` cells)."""
+    shape = tuple(reversed(n))
+    idx = np.meshgrid(*[np.arange(s, dtype=np.float64) for s in shape], indexing="ij")
+    c = tuple(reversed(centre))
+    r2 = sum((idx[a] - c[a]) ** 2 for a in range(len(shape)))
+    p = np.exp(-r2 / (2.0 * (radius / 3.0) ** 2))
+    p[r2 > radius * radius] = 0.0
+    return p
+
+
+def _subbox(field, lo, hi):
+    sl = tuple(slice(a, b) for a, b in zip(reversed(lo), reversed(hi)))
+    return field[sl]
+
+
+def _check(workload, dtype, nsteps, radius, with_source):
+    import torch
+    from oracle.operator import Grid
+    from oracle.source import PointSources
+    from oracle.steppers import Problem, run
+    from paper_2401_16322_amd.expwave import Operator
+    from synthetic import get_workload
+    w = get_workload(workload)
+    n, d = w.n, len(w.n)
+    centre = tuple(v // 2 for v in n)
+    reach = radius + nsteps * w.faber_m * 2 + 2
+    lo = tuple(c - reach for c in centre)
+    hi = tuple(c + reach for c in centre)
+    assert all(a >= w.abc_cells + 1 for a in lo) and all(b <= nn - w.abc_cells - 1 for b, nn in zip(hi, n))
+    c2 = (w.velocity() ** 2).reshape(tuple(reversed(n)))
+    p0 = _pulse(n, centre, radius)
+    npts = int(np.prod(n))
+    U0 = np.zeros((d + 1) * npts)
+    U0[:npts] = p0.ravel()
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    op = Operator(n, w.h, torch.tensor(c2, dtype=tdt, device="cuda"), abc_cells=w.abc_cells,
+                  sigma_max=w.sigma_max, max_taylor_p=w.taylor_p)
+    src_node = sum(v * int(np.prod(n[:a])) for a, v in enumerate(centre))
+    if with_source:
+        op.set_source_ricker([src_node], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+    ell = op.ellipse
+    U = torch.tensor(U0, dtype=tdt, device="cuda")
+    t0 = 0.1
+    op.step_faber(U, t0, w.dt, w.faber_m, nsteps)
+    Ug = U.cpu().numpy().astype(np.float64)
+    # oracle on the sub-box (no damping layer there), with the GPU's ellipse
+    bn = tuple(b - a for a, b in zip(lo, hi))
+    gb = Grid(bn, w.h, 4, abc_cells=0, sigma_max=0.0)
+    c2b = np.ascontiguousarray(_subbox(c2, lo, hi))
+    bsrc = None
+    if with_source:
+        local = sum((c - a) * int(np.prod(bn[:k])) for k, (c, a) in enumerate(zip(centre, lo)))
+        bsrc = PointSources((local,), (1.0,), w.f_peak, w.t_delay)
+    prob = Problem(gb, c2b, bsrc)
+    Ub0 = np.concatenate([np.ascontiguousarray(_subbox(U0[f * npts:(f + 1) * npts].reshape(c2.shape), lo, hi)).ravel()
+                          for f in range(d + 1)])
+    ref, _, _ = run(prob, "faber", Ub0, t0, w.dt, nsteps, m=w.faber_m, p=w.taylor_p, ellipse=ell)
+    inside = np.concatenate([np.ascontiguousarray(_subbox(Ug[f * npts:(f + 1) * npts].reshape(c2.shape), lo, hi)).ravel()
+                             for f in range(d + 1)])
+    assert rel_l2(inside, ref) <= TOL[dtype]
+    # exact zeros outside the sub-box
+    total = float(np.sum(Ug * Ug))
+    assert abs(total - float(np.sum(inside * inside))) <= 1e-12 * total
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_layered3d_256_full_size_faber_step(dtype):
+    """256^3, Faber degree 24, dt = 2.5 ms, one step (one term per sweep), a
+    pulse and the Ricker source at the centre."""
+    _check("layered3d_256", dtype, 1, 6, True)
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_layered2d_8192x4096_full_size_fused_steps(dtype):
+    """8192 x 4096, Faber degree 16 in fused passes of 4 terms, dt = 2 ms, two
+    steps, a pulse and a source at the centre."""
+    _check("layered2d_8192x4096", dtype, 2, 8, True)
