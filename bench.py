@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--faber-m", type=int, default=0, help="0 = the workload's degree")
     ap.add_argument("--krylov-k", type=int, default=16)
     ap.add_argument("--fuse", type=int, default=0)
+    ap.add_argument("--order", type=int, default=4, choices=[4, 8],
+                    help="stencil order (4: the workloads' stencil; 8: the paper's)")
     ap.add_argument("--methods", default="faber,krylov,rk4,leapfrog")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
@@ -111,8 +113,9 @@ def main():
     dev = torch.device("cuda:0")
     c2_np = w.velocity() ** 2
     c2 = torch.tensor(c2_np, dtype=tdt, device=dev)
-    op = xw.Operator(w.n, w.h, c2, abc_cells=w.abc_cells, sigma_max=w.sigma_max,
-                     max_krylov_k=max(args.krylov_k, 1), max_taylor_p=w.taylor_p)
+    op = xw.Operator(w.n, w.h, c2, order=args.order, abc_cells=w.abc_cells,
+                     sigma_max=w.sigma_max, max_krylov_k=max(args.krylov_k, 1),
+                     max_taylor_p=w.taylor_p)
     op.set_tuning(args.fuse)
     src = w.source_node()
     op.set_source_ricker([src], [1.0], w.f_peak, w.t_delay, w.taylor_p)
@@ -210,6 +213,7 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.n), "h_m": w.h, "abc_cells": w.abc_cells,
+                   "order": args.order,
                    "methods": {m: {"dt_ms": dts[m] * 1e3, "mvo": mvos[m]} for m in methods},
                    "receivers": int(rec.size), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
@@ -358,7 +362,7 @@ def cpu_baseline(w, methods, mvos, dts, args, c2_np, rec):
     from oracle.operator import Grid
     from oracle.source import PointSources
     from oracle.steppers import Problem, step
-    g = Grid(w.n, w.h, 4, abc_cells=w.abc_cells, sigma_max=w.sigma_max)
+    g = Grid(w.n, w.h, args.order, abc_cells=w.abc_cells, sigma_max=w.sigma_max)
     prob = Problem(g, c2_np, PointSources((w.source_node(),), (1.0,), w.f_peak, w.t_delay))
     ell = prob.ellipse()
     states = {m: np.zeros(g.nstate) for m in methods}

@@ -331,10 +331,10 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
     };
     const Src<T> src0 = make_src<T>(op, 0.0);
     if (fuse > 1 && !term_out) {
-      if constexpr (K == 2 && BC == 0 && DIM == 2) {
+      if constexpr (BC == 0 && DIM == 2) {
         rc = faber_fused_passes<T>(op->stream, ns, S, Abuf, Bbuf, Cbuf, Dbuf, Ebuf, m, fuse, final_term,
             [&](int n, const T* vp, const T* vpp, const T* acc_in, T* ol, T* opv, T* acc_out, int j, bool first) {
-              return launch_pass<T>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, j, first, a.data(), q.data(), el.gamma, el.c0, el.c1);
+              return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, j, first, a.data(), q.data(), el.gamma, el.c0, el.c1);
             });
       } else if constexpr (K == 2 && BC == 0 && DIM == 3) {
         rc = faber_fused_passes<T>(op->stream, ns, S, Abuf, Bbuf, Cbuf, Dbuf, Ebuf, m, 2, final_term,

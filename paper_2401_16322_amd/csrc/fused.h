@@ -33,11 +33,11 @@ constexpr int kMaxFuse = 8;
 constexpr int kFusedNT = 1024;             // 16 waves
 constexpr int kFusedRX = 64, kFusedRY = 48;  // largest region of a pass
 
-// Output tile of a pass of S terms (stencil half-width K = 2).
-template <int S>
+// Output tile of a pass of S terms (stencil half-width K: 2 for order 4, 4 for order 8).
+template <int S, int K = 2>
 struct FusedTile {
-  static constexpr int TX = kFusedRX - 4 * (S - 1);
-  static constexpr int TY = kFusedRY - 4 * (S - 1);
+  static constexpr int TX = kFusedRX - 2 * K * (S - 1);
+  static constexpr int TY = kFusedRY - 2 * K * (S - 1);
 };
 
 template <typename T, int S>
@@ -51,15 +51,14 @@ struct FusedArgs {
 // One pass over tile (tx_, ty_) of the recurrence terms r0..S-1 of an S-term
 // pass (r0 > 0 runs the last S - r0 terms only: a shorter pass on the same
 // tile). 2D grids with 3 * points < 2^31.
-template <typename T, int S>
-__device__ __forceinline__ void fused2d_pass(const Geo<T, 2, 2>& g, const T* __restrict__ vp,
+template <typename T, int S, int K = 2>
+__device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __restrict__ vp,
                                              const T* __restrict__ vpp, const T* acc_in,
                                              T* __restrict__ out_last, T* __restrict__ out_prev,
                                              T* acc_out, const FusedArgs<T, S>& c,
                                              const Src<T>& src, int tx_, int ty_, int r0) {
-  constexpr int K = 2;
   constexpr int H = K * S;
-  constexpr int TX = FusedTile<S>::TX, TY = FusedTile<S>::TY;
+  constexpr int TX = FusedTile<S, K>::TX, TY = FusedTile<S, K>::TY;
   constexpr int EX = TX + 2 * H, EY = TY + 2 * H, E = EX * EY;
   constexpr int X0 = H - K * (S - 1);  // first column/row of the largest region (= K)
   constexpr int NSL = kFusedRY / 16;   // rows per wave
@@ -141,7 +140,6 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, 2, 2>& g, const T* __r
     }
   }
 
-  const T w0 = g.w[0], w1 = g.w[1];
   const T* cp = cur;
   const T* cvx = cur + E;
   const T* cvz = cur + 2 * E;
@@ -155,10 +153,15 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, 2, 2>& g, const T* __r
       if (r <= last[i]) {
         const int l = (X0 + wave + 16 * i) * EX + lx;
         const T pc = cp[l], vxc = cvx[l], vzc = cvz[l];
-        const T dvx = w0 * (vxc - cvx[l - 1]) + w1 * (cvx[l + 1] - cvx[l - 2]);
-        const T dvz = w0 * (vzc - cvz[l - EX]) + w1 * (cvz[l + EX] - cvz[l - 2 * EX]);
-        const T dpx = w0 * (cp[l + 1] - pc) + w1 * (cp[l + 2] - cp[l - 1]);
-        const T dpz = w0 * (cp[l + EX] - pc) + w1 * (cp[l + 2 * EX] - cp[l - EX]);
+        T dvx = T(0), dvz = T(0), dpx = T(0), dpz = T(0);
+#pragma unroll
+        for (int q = 1; q <= K; ++q) {
+          const T wq = g.w[q - 1];
+          dvx += wq * (cvx[l + q - 1] - cvx[l - q]);
+          dvz += wq * (cvz[l + (q - 1) * EX] - cvz[l - q * EX]);
+          dpx += wq * (cp[l + q] - cp[l + 1 - q]);
+          dpz += wq * (cp[l + q * EX] - cp[l + (1 - q) * EX]);
+        }
         const T hp = -cc2[i] * (dvx + dvz) - sp[i] * pc;
         const T hvx = -dpx - sxh * vxc;
         const T hvz = -dpz - szh[i] * vzc;
@@ -223,37 +226,38 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, 2, 2>& g, const T* __r
 // band_w tile columns and walks it row by row (k = b / 8), so the tiles above
 // and below a tile run on the same XCD at about the same time and their
 // shared halo rows are read from its L2.
-template <typename T, int S>
+template <typename T, int S, int K>
 __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d(
-    Geo<T, 2, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp, const T* acc_in,
+    Geo<T, K, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp, const T* acc_in,
     T* __restrict__ out_last, T* __restrict__ out_prev, T* acc_out, FusedArgs<T, S> c, Src<T> src) {
   const int b = blockIdx.x;
   const int kk = b >> 3;
   const int ty_ = kk / c.band_w;
   const int tx_ = (b & 7) * c.band_w + (kk - ty_ * c.band_w);
   if (tx_ >= c.tiles_x || ty_ >= c.tiles_y) return;
-  fused2d_pass<T, S>(g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src, tx_, ty_, 0);
+  fused2d_pass<T, S, K>(g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src, tx_, ty_, 0);
 }
 
 // Fusion depth actually used for a request (1 = unfused kernels): 2D order 4
-// with zero ghosts up to 8 (FP32) or 4 (FP64) terms, default 4; 3D FP32 order
-// 4 with zero ghosts 2 terms when asked for (fuse >= 2), one term by default
-// (the one-term sweep already runs at the streaming limit in 3D and the
-// two-term pass gains little; in FP64 it spills registers).
+// with zero ghosts up to 8 (FP32) or 4 (FP64) terms, default 4; 2D order 8
+// with zero ghosts up to 4 terms, default 3; 3D FP32 order 4 with zero ghosts
+// 2 terms when asked for (fuse >= 2), one term by default (the one-term sweep
+// already runs at the streaming limit in 3D and the two-term pass gains
+// little; in FP64 it spills registers).
 template <typename T, int K, int BC, int DIM>
 int fused_depth(int requested, int m, int64_t npts) {
-  if (K != 2 || BC != 0) return 1;
-  if (DIM == 3) return (sizeof(T) == 4 && requested >= 2 && m >= 2) ? 2 : 1;
+  if (BC != 0) return 1;
+  if (DIM == 3) return (K == 2 && sizeof(T) == 4 && requested >= 2 && m >= 2) ? 2 : 1;
   if (3 * npts >= (int64_t(1) << 31)) return 1;
-  const int smax = sizeof(T) == 4 ? 8 : 4;
-  int s = requested == 0 ? 4 : requested;  // default depth
+  const int smax = (K == 2 && sizeof(T) == 4) ? 8 : 4;
+  int s = requested == 0 ? (K == 2 ? 4 : 3) : requested;  // default depth
   if (s > smax) s = smax;
   if (s > m) s = m;
   return s < 2 ? 1 : s;
 }
 
-template <typename T, int S>
-int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<T> src,
+template <typename T, int S, int K>
+int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                      const T* vp, const T* vpp, const T* acc_in, T* out_last, T* out_prev,
                      T* acc_out, int j, bool first, const double* a, const double* q,
                      double gamma, double c0, double c1) {
@@ -268,7 +272,7 @@ int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<
     c.cpp[r] = static_cast<T>(jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1));
     c.q[r] = static_cast<T>(q[jj - 1]);
   }
-  constexpr int TX = FusedTile<S>::TX, TY = FusedTile<S>::TY;
+  constexpr int TX = FusedTile<S, K>::TX, TY = FusedTile<S, K>::TY;
   const int tx = static_cast<int>((g.n[0] + TX - 1) / TX);
   const int ty = static_cast<int>((g.n[1] + TY - 1) / TY);
   c.tiles_x = tx;
@@ -278,23 +282,23 @@ int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<
   // algorithmic words per point: v_{j-1} (3), c^2 (1), and unless first v_{j-2}
   // and the partial sum (3 + 3); writes: the sum (3), and unless last the pair (3 + 3)
   const double words = 3 + 1 + (first ? 0 : 6) + 3 + (out_last ? 6 : 0);
-  launch_timed(prof, st, EXPW_KERNEL_FABER, words * g.N * sizeof(T), k_faber_fused2d<T, S>,
+  launch_timed(prof, st, EXPW_KERNEL_FABER, words * g.N * sizeof(T), k_faber_fused2d<T, S, K>,
                dim3(blocks), dim3(kFusedNT), g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "fused Faber pass: %s", hipGetErrorString(e));
   return EXPW_OK;
 }
 
-template <typename T>
-int32_t launch_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<T> src,
+template <typename T, int K>
+int32_t launch_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                     const T* vp, const T* vpp, const T* acc_in, T* out_last, T* out_prev,
                     T* acc_out, int j, bool first, const double* a, const double* q,
                     double gamma, double c0, double c1) {
 #define EXPW_PASS(S_)                                                                          \
   case S_:                                                                                     \
-    return launch_fused<T, S_>(st, prof, g, src, vp, vpp, acc_in, out_last, out_prev, acc_out, \
-                               j, first, a, q, gamma, c0, c1);
-  if constexpr (sizeof(T) == 4) {
+    return launch_fused<T, S_, K>(st, prof, g, src, vp, vpp, acc_in, out_last, out_prev,      \
+                                  acc_out, j, first, a, q, gamma, c0, c1);
+  if constexpr (sizeof(T) == 4 && K == 2) {
     switch (n) {
       EXPW_PASS(2) EXPW_PASS(3) EXPW_PASS(4) EXPW_PASS(5) EXPW_PASS(6) EXPW_PASS(7) EXPW_PASS(8)
       default: break;

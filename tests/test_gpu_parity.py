@@ -384,3 +384,24 @@ def test_faber_3d_fused_matches_oracle_and_unfused(dtype, m):
     Uref, _, _ = run(prob, "faber", case.U0, 0.04, dt, nst, m=m, p=case.p, ellipse=case.op.ellipse)
     assert rel_l2(U.cpu().numpy(), Uref) <= TOL[dtype]
     assert rel_l2(U.cpu().numpy(), U1.cpu().numpy()) <= (1e-13 if dtype == "float64" else 2e-6)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,fuse", [(2, 2), (3, 3), (7, 3), (8, 4), (16, 0), (13, 4)])
+def test_faber_order8_fused_matches_oracle_and_unfused(dtype, m, fuse):
+    """The paper's 8th-order stencil in fused passes (tiles of 64 - 8(S - 1)
+    columns) over several tiles with ragged edges and sources, against the
+    oracle and the one-term path."""
+    case = make_case((150, 90), dtype, order=8, seed=81, n_src=2)
+    dt, nst = 2e-3, 2
+    U = to_dev(case, case.U0)
+    case.op.set_tuning(fuse)
+    case.op.step_faber(U, 0.04, dt, m, nst)
+    U1 = to_dev(case, case.U0)
+    case.op.set_tuning(1)
+    case.op.step_faber(U1, 0.04, dt, m, nst)
+    ref, _, _ = run(case.prob, "faber", case.U0, 0.04, dt, nst, m=m, p=case.p,
+                    ellipse=case.op.ellipse)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+    assert rel_l2(U.cpu().numpy(), U1.cpu().numpy()) <= (1e-13 if dtype == "float64" else 2e-6)
