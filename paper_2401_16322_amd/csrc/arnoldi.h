@@ -1,39 +1,55 @@
-// Persistent Arnoldi (modified Gram-Schmidt) for one Krylov step, for
-// augmented vectors small enough to live in registers across the grid.
+// Persistent Arnoldi for one Krylov step, for augmented vectors small
+// enough to live in registers across the grid (Sec. 3.2, Krylov subspace
+// projection).
 //
 // One cooperative launch runs the whole basis construction: each thread owns
 // UN elements of the flat augmented vector (element e = tid + u * threads),
-// and keeps its slice of w, q_0 and the current q_i in registers. An MGS step
-// then costs one grid barrier (to reduce the dot) and one read of the next
-// basis vector, instead of a kernel launch that streams w, q_i, q_{i+1} and w
-// again. Columns are written unnormalized with their scale s_j = 1/h_{j,j-1}
+// and keeps its slices of w, q_0 and the newest basis vector in registers.
+// Columns are written unnormalized with their scale s_j = 1/h_{j+1,j}
 // (s_0 = 1), as in the launch-per-step path.
 //
-// Data that crosses workgroups inside the launch (reduction partials and the
-// basis vectors Q_j) is read and written with device-coherent accesses
+// Gram-Schmidt with two grid-wide reductions per column. Modified
+// Gram-Schmidt takes h_{i,j} = <w - sum_{l<i} h_{l,j} q_l, q_i>, which equals
+// r_i - sum_{l<i} h_{l,j} <q_l, q_i> with r_i = <w, q_i>, for any basis, not
+// only an exactly orthonormal one. So one reduction gives all r_i together
+// with the new Gram row <q_j, q_l> (l < j), a forward substitution over the
+// Gram entries then gives MGS's projections, and a second sweep applies
+// them in MGS's order (w -= h_{i,j} q_i, i = 0..j, rounded after each) and
+// reduces |w|^2. The price is a second read of q_1..q_{j-1} per column; the
+// gain is 2 grid-wide reductions per column instead of j + 2.
+//
+// Reduction partials cross workgroups through device-coherent accesses
 // (agent-scope relaxed atomics, i.e. sc1 loads and stores that do not stop in
-// an XCD's L2), so no cache-wide writeback or invalidation is needed. A
-// grid-wide reduction is also the barrier, and uses no read-modify-write:
+// an XCD's L2). Basis vectors are written the same way, but read with plain,
+// cached loads: each column Q_j is written once per launch, before any
+// workgroup reads one of its cache lines (columns start on 256-byte
+// boundaries), and the launch starts with no lines of Q in any cache, so a
+// read after the grid-wide reduction that follows the write can only miss
+// and fetch the written value. The stencil's neighbour reads then hit in L1
+// and L2 instead of crossing the fabric each time. A grid-wide reduction is also the barrier, and uses no read-modify-write:
 // each block's partial is its own arrival word. Slots start out holding a
 // signalling-NaN pattern that no arithmetic produces; block b stores its
-// partial (after waiting for its earlier stores, s_waitcnt 0) into slot b of
-// the barrier's buffer, and every block waits, one thread per slot, until the
-// slot no longer holds that pattern, taking the value it finds. Three
-// buffers rotate: when barrier s completes, every block has read the values
-// of barrier s-1, so each block then restores the pattern in its slot of that
-// buffer, which is next written at barrier s+2. One store and one successful
-// load per block and barrier, against two of each with separate flags. Every
-// wait is bounded: a wait longer than spin_limit polls sets *err and gives up,
-// and once *err is set no wait lasts more than 1024 polls, so every wave
-// always reaches the end of the kernel.
+// partial of value v (after waiting for its earlier stores, s_waitcnt 0) into
+// slot (v, b) of the barrier's buffer, and every block waits until each slot
+// no longer holds that pattern, taking the value it finds. Three buffers
+// rotate: when barrier s completes, every block has read the values of
+// barrier s-1, so each block then restores the pattern in its slots of that
+// buffer, which is next written at barrier s+2. Every wait is bounded: a wait
+// longer than spin_limit polls sets *err and gives up, and once *err is set
+// no wait lasts more than 1024 polls, so every wave always reaches the end of
+// the kernel.
 #pragma once
 
 #include "device_common.h"
+#include "expwave.h"
 #include "kernels.h"
 
 namespace expw {
 
-constexpr int kArnNT = 1024;  // threads per block of the persistent kernel
+constexpr int kArnNT = 1024;        // threads per block of the persistent kernel
+constexpr int kArnMaxBlocks = 256;  // grid cap of the persistent kernel
+constexpr int kArnMaxVals = 2 * EXPW_MAX_KRYLOV - 1;  // values of one grid-wide reduction
+constexpr int kArnHessLd = EXPW_MAX_KRYLOV;           // leading dimension of the Hessenberg matrix
 
 template <typename T>
 __device__ __forceinline__ T ld_coherent(const T* p) {
@@ -45,92 +61,121 @@ __device__ __forceinline__ void st_coherent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// base[e] for a byte offset that fits 32 bits (a uniform base plus a 32-bit
+// per-lane offset, so the address needs no 64-bit vector arithmetic)
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, uint32_t byte_off, T v) {
+  st_coherent(reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off), v);
+}
+
 // Contents of an empty slot of the grid-wide reduction (a signalling NaN;
 // a NaN partial is stored as the default quiet NaN instead).
 constexpr unsigned long long kSlotEmpty = 0x7FF4DEADBEEF0001ull;
 constexpr int kSlotBuffers = 3;
 
-// Grid-wide sum of v (blocks of NT threads, at most 1024 blocks): returns the
-// sum of the per-block partials, added in a fixed order, to every thread. slots holds
-// kSlotBuffers buffers of kRedMaxBlocks words, all kSlotEmpty at launch; seq
-// numbers the barriers of the launch (1, 2, ...). after() runs in every
-// thread once this block has arrived: loads it issues overlap the wait (the
-// s_waitcnt before the arrival waits for every outstanding memory operation,
-// so loads issued earlier would be waited for there).
+// Grid-wide sums of nv values (1 <= nv <= nvmax, at most kArnMaxBlocks
+// blocks of NT threads). Before the call, lane 0 of wave w has put its wave's
+// partial of value v in wpart[v][w]. On return every thread sees the totals
+// in tot[0..nv). Each total is added in a fixed order, the same in every
+// block: a block's partial is the sum of its waves in order; block b's partial
+// goes to lane b % 64 of the wave that collects the value, each lane adds its
+// blocks in increasing order, and the lanes are added by a fixed DPP tree.
+// slots holds kSlotBuffers buffers of nvmax x gridDim.x words (row v = value
+// v), all kSlotEmpty at launch; seq numbers the barriers of the launch
+// (1, 2, ...). after() runs in every thread once this block has arrived:
+// loads it issues overlap the wait (the s_waitcnt before the arrival waits
+// for every outstanding memory operation, so loads issued earlier would be
+// waited for there).
 template <int NT, typename F>
-__device__ __forceinline__ double grid_sum(double v, unsigned long long* slots, unsigned seq,
-                                           unsigned spin_limit, int* err, F&& after) {
+__device__ __forceinline__ void grid_sum_vec(int nv, int nvmax, const double (*wpart)[NT / 64],
+                                             double* tot, unsigned long long* slots, unsigned seq,
+                                             unsigned spin_limit, int* err, F&& after) {
   static_assert(NT % 64 == 0 && NT <= 1024, "block of whole waves");
-  __shared__ double s_part[NT / 64];
-  __shared__ double s_poll[2][kRedMaxBlocks / 64];
-  unsigned long long* cur = slots + (seq % kSlotBuffers) * kRedMaxBlocks;
-  unsigned long long* prev = slots + ((seq + kSlotBuffers - 1) % kSlotBuffers) * kRedMaxBlocks;
+  constexpr int NW = NT / 64;
+  constexpr int PER = kArnMaxBlocks / 64;
+  const int nb = static_cast<int>(gridDim.x);
+  const size_t buf = static_cast<size_t>(nvmax) * nb;
+  unsigned long long* cur = slots + (seq % kSlotBuffers) * buf;
+  unsigned long long* prev = slots + ((seq + kSlotBuffers - 1) % kSlotBuffers) * buf;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // the block's partial: wave sums, then wave 0 sums them
-  v = wave_sum_fixed(v);
-  if (lane == 0) s_part[wid] = v;
   __builtin_amdgcn_s_waitcnt(0);  // this thread's coherent stores have completed
-  __syncthreads();
-  if (wid == 0) {
-    double b = lane < NT / 64 ? s_part[lane] : 0.0;
-    b = wave_sum_fixed(b);
-    if (lane == 0) {
-      const unsigned long long bits = (b != b) ? 0x7FF8000000000000ull : __double_as_longlong(b);
-      st_coherent(cur + blockIdx.x, bits);
-    }
+  __syncthreads();                // ... and so have the block's; wave partials are in LDS
+  if (static_cast<int>(threadIdx.x) < nv) {
+    double b = 0.0;
+    for (int w = 0; w < NW; ++w) b += wpart[threadIdx.x][w];
+    const unsigned long long bits = (b != b) ? 0x7FF8000000000000ull : __double_as_longlong(b);
+    st_coherent(cur + static_cast<size_t>(threadIdx.x) * nb + blockIdx.x, bits);
   }
   after();
-  // every block's partial, one thread per slot
-  double pv = 0.0;
-  if (threadIdx.x < gridDim.x) {
-    unsigned polls = 0;
-    unsigned long long x;
-    while ((x = ld_coherent(cur + threadIdx.x)) == kSlotEmpty) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++polls > spin_limit ||
-          ((polls & 1023u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
+  for (int v = wid; v < nv; v += NW) {
+    const unsigned long long* row = cur + static_cast<size_t>(v) * nb;
+    unsigned long long x[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int b = lane + 64 * r;
+      x[r] = b < nb ? ld_coherent(row + b) : 0ull;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int b = lane + 64 * r;
+      if (b < nb) {
+        unsigned polls = 0;
+        while (x[r] == kSlotEmpty) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++polls > spin_limit ||
+              ((polls & 1023u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          x[r] = ld_coherent(row + b);
+        }
+        s += __longlong_as_double(x[r]);
       }
     }
-    pv = __longlong_as_double(x);
-  }
-  // sum in block order: per wave of slots, then the waves in order (every
-  // thread adds the same values in the same order)
-  const int nw = (static_cast<int>(gridDim.x) + 63) / 64;
-  double* sp = s_poll[seq & 1u];
-  if (wid < nw) {
-    pv = wave_sum_fixed(pv);
-    if (lane == 0) sp[wid] = pv;
+    s = wave_sum_fixed(s);
+    if (lane == 0) tot[v] = s;
   }
   __syncthreads();
-  double tot = 0.0;
-  for (int w = 0; w < nw; ++w) tot += sp[w];
-  if (threadIdx.x == 0) {
-    // all blocks arrived at this barrier, so all have read barrier seq-1's
-    // values; the store completes before this block's next arrival (s_waitcnt)
-    st_coherent(prev + blockIdx.x, kSlotEmpty);
-  }
-  return tot;
+  // all blocks arrived at this barrier, so all have read barrier seq-1's
+  // values; the stores complete before this block's next arrival (s_waitcnt)
+  if (static_cast<int>(threadIdx.x) < nvmax)
+    st_coherent(prev + static_cast<size_t>(threadIdx.x) * nb + blockIdx.x, kSlotEmpty);
 }
 
-// x at the point shifted by s along one axis (zero outside or wrapped), read
-// with a device-coherent load.
+// Extents and strides of the grid in 32 bits: the persistent kernel's
+// vectors have fewer than 2^31 elements, so point indices, coordinates and
+// byte offsets fit, and the stencil needs no 64-bit index arithmetic.
+struct Geo32 {
+  uint32_t n[3], st[3], N;
+};
+
+// x at the point shifted by s along one axis (zero outside or wrapped); x is
+// a uniform field base, idx the point, i its coordinate on the axis.
 template <typename T, int BC>
-__device__ __forceinline__ T ldn_coherent(const T* f, int64_t idx, int64_t i, int64_t n, int64_t st,
-                                          int s) {
-  const int64_t j = i + s;
-  if (BC == 0) return (j >= 0 && j < n) ? ld_coherent(f + idx + s * st) : T(0);
-  int64_t jj = j % n;
-  if (jj < 0) jj += n;
-  return ld_coherent(f + idx + (jj - i) * st);
+__device__ __forceinline__ T ldn32(const T* x, uint32_t idx, uint32_t i, uint32_t n, uint32_t st,
+                                   int s) {
+  const int j = static_cast<int>(i) + s;
+  if (BC == 0)
+    return (j >= 0 && j < static_cast<int>(n))
+               ? ld_at(x, (idx + static_cast<uint32_t>(s) * st) * static_cast<uint32_t>(sizeof(T)))
+               : T(0);
+  int jj = j % static_cast<int>(n);
+  if (jj < 0) jj += static_cast<int>(n);
+  return ld_at(x, (idx + static_cast<uint32_t>(jj - static_cast<int>(i)) * st) *
+                      static_cast<uint32_t>(sizeof(T)));
 }
 
-// (H x)_f at one point: field f = 0 (pressure) or 1 + a (velocity along a),
-// with x read coherently (c^2 and the damping profiles are read-only).
+// (H x)_f at one point: field f = 0 (pressure) or 1 + a (velocity along a).
 template <typename T, int K, int BC, int DIM>
-__device__ __forceinline__ T apply_field(const Geo<T, K, DIM>& g, const T* x, int f, int64_t idx,
-                                         const int64_t* ic) {
+__device__ __forceinline__ T apply_field(const Geo<T, K, DIM>& g, const Geo32& g32, const T* x,
+                                         uint32_t f, uint32_t idx, const uint32_t* ic) {
+  constexpr uint32_t es = sizeof(T);
   if (f == 0) {
     T div = T(0), sp = T(0);
 #pragma unroll
@@ -138,166 +183,275 @@ __device__ __forceinline__ T apply_field(const Geo<T, K, DIM>& g, const T* x, in
       const T* v = x + (1 + a) * g.N;
 #pragma unroll
       for (int l = 1; l <= K; ++l)
-        div += g.w[l - 1] * (ldn_coherent<T, BC>(v, idx, ic[a], g.n[a], g.st[a], l - 1) -
-                             ldn_coherent<T, BC>(v, idx, ic[a], g.n[a], g.st[a], -l));
-      sp += g.sint[a][ic[a]];
+        div += g.w[l - 1] * (ldn32<T, BC>(v, idx, ic[a], g32.n[a], g32.st[a], l - 1) -
+                             ldn32<T, BC>(v, idx, ic[a], g32.n[a], g32.st[a], -l));
+      sp += ld_at(g.sint[a], ic[a] * es);
     }
-    return -g.c2[idx] * div - sp * ld_coherent(x + idx);
+    return -ld_at(g.c2, idx * es) * div - sp * ld_at(x, idx * es);
   }
-  const int a = f - 1;
-  T dp = T(0);
+  // velocity along axis f - 1, unrolled over the axes so that every array
+  // index is a compile-time constant
+  T res = T(0);
 #pragma unroll
-  for (int l = 1; l <= K; ++l)
-    dp += g.w[l - 1] * (ldn_coherent<T, BC>(x, idx, ic[a], g.n[a], g.st[a], l) -
-                        ldn_coherent<T, BC>(x, idx, ic[a], g.n[a], g.st[a], 1 - l));
-  return -dp - g.shalf[a][ic[a]] * ld_coherent(x + f * g.N + idx);
+  for (int a = 0; a < DIM; ++a)
+    if (f == static_cast<uint32_t>(1 + a)) {
+      T dp = T(0);
+#pragma unroll
+      for (int l = 1; l <= K; ++l)
+        dp += g.w[l - 1] * (ldn32<T, BC>(x, idx, ic[a], g32.n[a], g32.st[a], l) -
+                            ldn32<T, BC>(x, idx, ic[a], g32.n[a], g32.st[a], 1 - l));
+      res = -dp - ld_at(g.shalf[a], ic[a] * es) * ld_at(x + (1 + a) * g.N, idx * es);
+    }
+  return res;
 }
 
 struct ArnArgs {
   int64_t ns, naug, ld;
   int k;
+  int nvmax;     // values of the largest grid-wide reduction: 2k - 1
   double tail2;  // |e_p|^2: 1 with a source, else 0
   double tol;
   unsigned spin_limit;
 };
 
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
 template <typename T, int K, int BC, int DIM, int UN>
 __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     Geo<T, K, DIM> g, const T* __restrict__ S, T* Q, KrySrc src, const T* __restrict__ amp,
     ArnArgs a, unsigned long long* slots, int* err, double* hess, double* sc, double* beta_out) {
-  __shared__ double s_scale[65];
+  constexpr int NW = kArnNT / 64;
+  __shared__ double s_scale[EXPW_MAX_KRYLOV + 1];
+  __shared__ double s_gt[EXPW_MAX_KRYLOV][EXPW_MAX_KRYLOV];  // s_gt[l][i] = <q_i, q_l>, l < i
+  __shared__ double s_wpart[kArnMaxVals][NW];
+  __shared__ double s_tot[kArnMaxVals];
+  __shared__ double s_h[EXPW_MAX_KRYLOV];
+  __shared__ T s_qj[UN][kArnNT];  // this block's slice of Q_j, the newest stored column
   const unsigned nb = gridDim.x;
   const int64_t nthreads = static_cast<int64_t>(nb) * kArnNT;
   const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kArnNT + threadIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   unsigned seq = 0;
+  // element e = gtid + u * nthreads < naug <= UN * nthreads < 2^31 (host
+  // check), so element indices and byte offsets are 32-bit
+  const uint32_t e0 = static_cast<uint32_t>(gtid), estep = static_cast<uint32_t>(nthreads);
+  const uint32_t naug32 = static_cast<uint32_t>(a.naug), ns32 = static_cast<uint32_t>(a.ns);
+  const uint32_t npts32 = static_cast<uint32_t>(g.N);
+  constexpr uint32_t kEs = sizeof(T);
+  Geo32 g32;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    g32.n[d] = static_cast<uint32_t>(g.n[d]);
+    g32.st[d] = static_cast<uint32_t>(g.st[d]);
+  }
+  g32.N = npts32;
+  // per-thread partial sums and the update w -= h q run in T (FP32 partials
+  // cover UN <= 8 products); every sum across threads is in FP64
 
-  // grid-wide sums double as the barriers between Gram-Schmidt steps
-  auto publish = [&](double v) {
-    return grid_sum<kArnNT>(v, slots, ++seq, a.spin_limit, err, [] {});
+  auto put = [&](int v, double x) {
+    x = wave_sum_fixed(x);
+    if (lane == 0) s_wpart[v][wid] = x;
   };
+  auto reduce = [&](int nv, auto&& after) {
+    grid_sum_vec<kArnNT>(nv, a.nvmax, s_wpart, s_tot, slots, ++seq, a.spin_limit, err, after);
+  };
+  auto nothing = [] {};
 
   // q_0 = [S; e_p] / beta
   double acc = 0.0;
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
-    const int64_t e = gtid + u * nthreads;
-    if (e < a.ns) {
+    const uint32_t e = e0 + u * estep;
+    if (e < ns32) {
       const double v = static_cast<double>(S[e]);
       acc += v * v;
     }
   }
-  const double beta = sqrt(publish(acc) + a.tail2);
+  put(0, acc);
+  reduce(1, nothing);
+  const double beta = sqrt(s_tot[0] + a.tail2);
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
   if (lead) {
     *beta_out = beta;
     sc[0] = 1.0;
   }
   if (threadIdx.x == 0) s_scale[0] = 1.0;
-  T q0[UN];
+  // q0: q_0; w: the vector being orthogonalized; qa, qb: streamed columns
+  // Q_1..Q_{j-1}
+  T q0[UN], w[UN], qa[UN], qb[UN];
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
-    const int64_t e = gtid + u * nthreads;
+    const uint32_t e = e0 + u * estep;
     double v = 0.0;
-    if (e < a.ns)
+    if (e < ns32)
       v = static_cast<double>(S[e]) * inv;
-    else if (e == a.naug - 1 && a.tail2 > 0.0)
+    else if (e + 1 == naug32 && a.tail2 > 0.0)
       v = inv;
     q0[u] = static_cast<T>(v);
-    if (e < a.naug) st_coherent(Q + e, q0[u]);
+    s_qj[u][threadIdx.x] = q0[u];
+    if (e < naug32) st_at(Q, e * kEs, q0[u]);
   }
-  (void)publish(0.0);  // Q_0 complete everywhere
+  put(0, 0.0);
+  reduce(1, nothing);  // Q_0 complete everywhere
 
-  // qa holds q_i's stored column Q_i, qb the next one Q_{i+1}; the next
-  // column is loaded as soon as this block has arrived at a grid-wide sum, so
-  // the load overlaps the wait for the other blocks
-  T w[UN], qa[UN], qb[UN];
+  // the thread's first element, made opaque once per column (an empty asm):
+  // otherwise the per-element index math of all UN elements is hoisted out
+  // of the column loop and held in registers for the whole kernel
+  uint32_t ecur = e0;
   auto load_col = [&](T* dst, int col) {
     const T* qc = Q + col * a.ld;
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      const int64_t e = gtid + u * nthreads;
-      dst[u] = (e < a.naug) ? ld_coherent(qc + e) : T(0);
+      const uint32_t e = ecur + u * estep;
+      dst[u] = (e < naug32) ? ld_at(qc, e * kEs) : T(0);
     }
   };
+  // fn(i, column) for the n stored columns first, first + step, ..., two
+  // buffers in turn; qa already holds (or is loading) Q_first
+  auto stream = [&](int first, int n, int step, auto&& fn) {
+    for (int t = 0; t < n; t += 2) {
+      const int i = first + t * step;
+      if (t + 1 < n) load_col(qb, i + step);
+      fn(i, qa);
+      if (t + 1 < n) {
+        if (t + 2 < n) load_col(qa, i + 2 * step);
+        fn(i + step, qb);
+      }
+    }
+  };
+
+  T sj = T(1);
   for (int j = 0; j < a.k; ++j) {
-    const T* qj = Q + j * a.ld;
+    const T* qcol = Q + j * a.ld;
     T* wout = Q + (j + 1) * a.ld;
-    const T sj = static_cast<T>(s_scale[j]);
-    // w = s_j H~ Q_j, and the first dot w . q_0
-    acc = 0.0;
+    ecur = e0;
+    asm volatile("" : "+v"(ecur));
+    // w = s_j H~ Q_j
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      const int64_t e = gtid + u * nthreads;
+      const uint32_t e = ecur + u * estep;
       T v = T(0);
-      if (e < a.ns) {
-        const int f = static_cast<int>(e / g.N);
-        const int64_t idx = e - f * g.N;
-        int64_t ic[3];
-        decompose<DIM>(g.n, idx, ic);
-        v = apply_field<T, K, BC, DIM>(g, qj, f, idx, ic);
-        if (f == 0 && src.n > 0 && idx >= src.lo && idx <= src.hi) {
+      if (e < ns32) {
+        const uint32_t f = e / npts32;
+        const uint32_t idx = e - f * npts32;
+        uint32_t ic[3];
+        ic[0] = idx % g32.n[0];
+        const uint32_t rest = idx / g32.n[0];
+        if (DIM == 2) {
+          ic[1] = rest;
+          ic[2] = 0;
+        } else {
+          ic[1] = rest % g32.n[1];
+          ic[2] = rest / g32.n[1];
+        }
+        v = apply_field<T, K, BC, DIM>(g, g32, qcol, f, idx, ic);
+        if (f == 0 && src.n > 0 && static_cast<int64_t>(idx) >= src.lo && static_cast<int64_t>(idx) <= src.hi) {
           for (int s = 0; s < src.n; ++s)
-            if (src.idx[s] == idx) {
+            if (src.idx[s] == static_cast<int64_t>(idx)) {
               double gt = 0.0;
               for (int cc = 0; cc < src.p; ++cc)
-                gt += src.G[cc] * static_cast<double>(ld_coherent(qj + a.ns + cc));
+                gt += src.G[cc] * static_cast<double>(qcol[a.ns + cc]);
               v += static_cast<T>(gt * static_cast<double>(amp[s]));
             }
         }
         v *= sj;
-      } else if (e < a.naug) {
-        const int cc = static_cast<int>(e - a.ns);
-        v = (cc + 1 < src.p) ? ld_coherent(qj + a.ns + cc + 1) * sj : T(0);  // J q_tail
+      } else if (e < naug32) {
+        const int cc = static_cast<int>(e - ns32);
+        v = (cc + 1 < src.p) ? qcol[a.ns + cc + 1] * sj : T(0);  // J q_tail
       }
       w[u] = v;
-      qa[u] = q0[u];
-      acc += static_cast<double>(v) * static_cast<double>(q0[u]);
     }
-    double h = grid_sum<kArnNT>(acc, slots, ++seq, a.spin_limit, err, [&] {
-      if (j >= 1) load_col(qb, 1);
-    });
-    if (lead) hess[0 * 64 + j] = h;
-    double sa = 1.0;
-    for (int i = 0; i <= j; ++i) {
-      const bool lastc = (i == j);
-      const double hs = h * sa;
-      const double sb = lastc ? 1.0 : s_scale[i + 1];
-      acc = 0.0;
+    // first sweep: value i <= j is <w, Q_i>, value j + 1 + l (l < j) is
+    // <Q_j, Q_l>; columns j-1 down to 1, so that the second sweep starts on
+    // the columns read last
+    {
+      T r = T(0), gq = T(0);
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
-        const int64_t e = gtid + u * nthreads;
-        const T wt = static_cast<T>(static_cast<double>(w[u]) - hs * static_cast<double>(qa[u]));
-        w[u] = wt;
-        if (!lastc) {
-          acc += static_cast<double>(wt) * sb * static_cast<double>(qb[u]);
-        } else {
-          if (e < a.naug) st_coherent(wout + e, wt);
-          acc += static_cast<double>(wt) * static_cast<double>(wt);
-        }
+        r += w[u] * q0[u];
+        gq += s_qj[u][threadIdx.x] * q0[u];
       }
-      if (!lastc) {
+      put(0, static_cast<double>(r));
+      if (j >= 1) put(j + 1, static_cast<double>(gq));
+    }
+    stream(j - 1, j - 1, -1, [&](int i, const T* q) {
+      T r = T(0), gq = T(0);
 #pragma unroll
-        for (int u = 0; u < UN; ++u) qa[u] = qb[u];
+      for (int u = 0; u < UN; ++u) {
+        r += w[u] * q[u];
+        gq += s_qj[u][threadIdx.x] * q[u];
       }
-      const double r = grid_sum<kArnNT>(acc, slots, ++seq, a.spin_limit, err, [&] {
-        if (!lastc && i + 2 <= j) load_col(qb, i + 2);
-      });
-      if (!lastc) {
-        h = r;
-        if (lead) hess[(i + 1) * 64 + j] = h;
-        sa = sb;
-      } else {
-        const double hn = sqrt(r);
-        const double s = (hn > a.tol * beta) ? 1.0 / hn : 0.0;
-        if (lead) {
-          hess[(j + 1) * 64 + j] = hn;
-          sc[j + 1] = s;
-        }
-        if (threadIdx.x == 0) s_scale[j + 1] = s;
-        __syncthreads();
+      put(i, static_cast<double>(r));
+      put(j + 1 + i, static_cast<double>(gq));
+    });
+    if (j >= 1) {
+      T r = T(0);
+#pragma unroll
+      for (int u = 0; u < UN; ++u) r += w[u] * s_qj[u][threadIdx.x];
+      put(j, static_cast<double>(r));
+    }
+    reduce(2 * j + 1, [&] {
+      if (j >= 2) load_col(qa, 1);
+    });
+    // MGS's projections: h_i = r_i - sum_{l<i} h_l <q_l, q_i>, lane i of wave 0
+    if (wid == 0) {
+      const double sl = lane <= j ? s_scale[lane] : 0.0;
+      double r = lane <= j ? s_tot[lane] * sl : 0.0;
+      const double grow = lane < j ? s_tot[j + 1 + lane] * s_scale[j] * sl : 0.0;  // <q_j, q_lane>
+      for (int l = 0; l < j; ++l) {
+        const double hl = readlane_f64(r, l);  // final: lanes below l+1 are done
+        const double gil = (lane == j) ? readlane_f64(grow, l) : s_gt[l][lane];
+        if (lane > l && lane <= j) r -= hl * gil;
+      }
+      if (lane < j) s_gt[lane][j] = grow;
+      if (lane <= j) {
+        s_h[lane] = r * sl;  // applied to the stored column Q_i = q_i / s_i
+        if (blockIdx.x == 0) hess[lane * kArnHessLd + j] = r;
       }
     }
+    __syncthreads();
+    // second sweep: w -= h_i q_i in order i = 0..j, then |w|^2
+    {
+      const T h0 = static_cast<T>(s_h[0]);
+#pragma unroll
+      for (int u = 0; u < UN; ++u) w[u] -= h0 * q0[u];
+    }
+    stream(1, j - 1, 1, [&](int i, const T* q) {
+      const T hi = static_cast<T>(s_h[i]);
+#pragma unroll
+      for (int u = 0; u < UN; ++u) w[u] -= hi * q[u];
+    });
+    if (j >= 1) {
+      const T hj = static_cast<T>(s_h[j]);
+#pragma unroll
+      for (int u = 0; u < UN; ++u) w[u] -= hj * s_qj[u][threadIdx.x];
+    }
+    T nrm = T(0);
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const uint32_t e = ecur + u * estep;
+      if (e < naug32) st_at(wout, e * kEs, w[u]);
+      nrm += w[u] * w[u];
+      s_qj[u][threadIdx.x] = w[u];
+    }
+    put(0, static_cast<double>(nrm));
+    reduce(1, [&] {
+      if (j >= 1 && j + 1 < a.k) load_col(qa, j);  // the next first sweep starts on Q_j
+    });
+    const double hn = sqrt(s_tot[0]);
+    const double s = (hn > a.tol * beta) ? 1.0 / hn : 0.0;
+    if (lead) {
+      hess[(j + 1) * kArnHessLd + j] = hn;
+      sc[j + 1] = s;
+    }
+    if (threadIdx.x == 0) s_scale[j + 1] = s;  // read after the next reduction's barriers
+    sj = static_cast<T>(s);
   }
 }
 

@@ -128,7 +128,7 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
   L.scal = off; off = align_up(off + 64 * sizeof(double));
   L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
   L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
-  L.bar = off; off = align_up(off + kSlotBuffers * kRedMaxBlocks * sizeof(unsigned long long));  // grid reduction slots
+  L.bar = off; off = align_up(off + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks * sizeof(unsigned long long));  // grid reduction slots
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -432,7 +432,7 @@ int persistent_un(expw_op* op, int64_t naug) {
         !coop || per_cu < 1) {
       op->coop_blocks = -1;
     } else {
-      op->coop_blocks = std::min(256, cus * per_cu);
+      op->coop_blocks = std::min(kArnMaxBlocks, cus * per_cu);
     }
   }
   if (op->coop_blocks <= 0) return 0;
@@ -454,8 +454,9 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   aa.k = k;
   aa.tail2 = tail2;
   aa.tol = tol;
+  aa.nvmax = std::max(1, 2 * k - 1);
   aa.spin_limit = 1u << 20;  // about a second of polling
-  constexpr int nslots = kSlotBuffers * kRedMaxBlocks;
+  const int nslots = kSlotBuffers * aa.nvmax * op->coop_blocks;
   k_fill_u64<<<(nslots + 255) / 256, 256, 0, op->stream>>>(slots, nslots, kSlotEmpty);
   Geo<T, K, DIM> gg = g;
   const T* Sp = S;
