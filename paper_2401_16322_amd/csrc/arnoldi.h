@@ -78,6 +78,55 @@ __device__ __forceinline__ void st_at(T* base, uint32_t byte_off, T v) {
 constexpr unsigned long long kSlotEmpty = 0x7FF4DEADBEEF0001ull;
 constexpr int kSlotBuffers = 3;
 
+// Sums of the slots of row0 (and of row1 when two) over the nb blocks, each
+// lane adding blocks lane, lane + 64, ... in order and the lanes by a fixed
+// DPP tree. All loads of the rows are issued together and the empty slots are
+// polled again together, so each poll costs one round trip. Bounded: after
+// spin_limit polls (1024 once *err is set) it sets *err and gives up.
+template <int PER>
+__device__ __forceinline__ void collect_rows(const unsigned long long* row0,
+                                             const unsigned long long* row1, bool two, int nb,
+                                             int lane, unsigned spin_limit, int* err, double& s0,
+                                             double& s1) {
+  unsigned long long x0[PER], x1[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int b = lane + 64 * r;
+    x0[r] = b < nb ? ld_coherent(row0 + b) : 0ull;
+    x1[r] = (two && b < nb) ? ld_coherent(row1 + b) : 0ull;
+  }
+  unsigned polls = 0;
+  for (;;) {
+    bool empty = false;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) empty = empty || x0[r] == kSlotEmpty || x1[r] == kSlotEmpty;
+    if (!empty) break;
+    __builtin_amdgcn_s_sleep(1);
+    if (++polls > spin_limit ||
+        ((polls & 1023u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int b = lane + 64 * r;
+      if (x0[r] == kSlotEmpty) x0[r] = ld_coherent(row0 + b);
+      if (x1[r] == kSlotEmpty) x1[r] = ld_coherent(row1 + b);
+    }
+  }
+  s0 = 0.0;
+  s1 = 0.0;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    if (lane + 64 * r < nb) {
+      s0 += __longlong_as_double(x0[r]);
+      s1 += __longlong_as_double(x1[r]);
+    }
+  }
+  s0 = wave_sum_fixed(s0);
+  s1 = wave_sum_fixed(s1);
+}
+
 // Grid-wide sums of nv values (1 <= nv <= nvmax, at most kArnMaxBlocks
 // blocks of NT threads). Before the call, lane 0 of wave w has put its wave's
 // partial of value v in wpart[v][w]. On return every thread sees the totals
@@ -112,34 +161,29 @@ __device__ __forceinline__ void grid_sum_vec(int nv, int nvmax, const double (*w
     st_coherent(cur + static_cast<size_t>(threadIdx.x) * nb + blockIdx.x, bits);
   }
   after();
-  for (int v = wid; v < nv; v += NW) {
-    const unsigned long long* row = cur + static_cast<size_t>(v) * nb;
-    unsigned long long x[PER];
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int b = lane + 64 * r;
-      x[r] = b < nb ? ld_coherent(row + b) : 0ull;
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int b = lane + 64 * r;
-      if (b < nb) {
-        unsigned polls = 0;
-        while (x[r] == kSlotEmpty) {
-          __builtin_amdgcn_s_sleep(1);
-          if (++polls > spin_limit ||
-              ((polls & 1023u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-          x[r] = ld_coherent(row + b);
-        }
-        s += __longlong_as_double(x[r]);
+  // wave 0 alone waits for value 0 of every block (a block stores all its
+  // values at once, so the other rows are then complete or nearly so); one
+  // polling wave per block keeps the waiting traffic small
+  if (wid == 0) {
+    double s0, s1;
+    collect_rows<PER>(cur, cur, false, nb, lane, spin_limit, err, s0, s1);
+    if (lane == 0) tot[0] = s0;
+  }
+  if (nv > 1) {
+    __syncthreads();
+    // values 1..nv-1: wave w takes values 1 + w and 1 + w + NW, then the
+    // next 2 NW
+    for (int v0 = 1 + wid; v0 < nv; v0 += 2 * NW) {
+      const int v1 = v0 + NW;
+      const bool two = v1 < nv;
+      double s0, s1;
+      collect_rows<PER>(cur + static_cast<size_t>(v0) * nb, cur + static_cast<size_t>(two ? v1 : v0) * nb,
+                        two, nb, lane, spin_limit, err, s0, s1);
+      if (lane == 0) {
+        tot[v0] = s0;
+        if (two) tot[v1] = s1;
       }
     }
-    s = wave_sum_fixed(s);
-    if (lane == 0) tot[v] = s;
   }
   __syncthreads();
   // all blocks arrived at this barrier, so all have read barrier seq-1's
@@ -404,10 +448,20 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       const double sl = lane <= j ? s_scale[lane] : 0.0;
       double r = lane <= j ? s_tot[lane] * sl : 0.0;
       const double grow = lane < j ? s_tot[j + 1 + lane] * s_scale[j] * sl : 0.0;  // <q_j, q_lane>
-      for (int l = 0; l < j; ++l) {
-        const double hl = readlane_f64(r, l);  // final: lanes below l+1 are done
-        const double gil = (lane == j) ? readlane_f64(grow, l) : s_gt[l][lane];
-        if (lane > l && lane <= j) r -= hl * gil;
+      // Gram entries are read from LDS eight steps ahead of the dependent chain
+      for (int l0 = 0; l0 < j; l0 += 8) {
+        double gb[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) gb[t] = (l0 + t < j) ? s_gt[l0 + t][lane] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int l = l0 + t;
+          if (l < j) {
+            const double hl = readlane_f64(r, l);  // final: lanes below l+1 are done
+            const double gil = (lane == j) ? readlane_f64(grow, l) : gb[t];
+            if (lane > l && lane <= j) r -= hl * gil;
+          }
+        }
       }
       if (lane < j) s_gt[lane][j] = grow;
       if (lane <= j) {
