@@ -50,6 +50,7 @@ constexpr int kArnNT = 1024;        // threads per block of the persistent kerne
 constexpr int kArnMaxBlocks = 256;  // grid cap of the persistent kernel
 constexpr int kArnMaxVals = 2 * EXPW_MAX_KRYLOV - 1;  // values of one grid-wide reduction
 constexpr int kArnHessLd = EXPW_MAX_KRYLOV;           // leading dimension of the Hessenberg matrix
+constexpr int kArnLdsBudget = 160 * 1024 - 1024;      // LDS of one block of the persistent kernel
 
 template <typename T>
 __device__ __forceinline__ T ld_coherent(const T* p) {
@@ -276,6 +277,13 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   __shared__ double s_tot[kArnMaxVals];
   __shared__ double s_h[EXPW_MAX_KRYLOV];
   __shared__ T s_qj[UN][kArnNT];  // this block's slice of Q_j, the newest stored column
+  // the first NC stored columns Q_1..Q_NC also stay in LDS, as far as the
+  // block's LDS allows: every later column reads them in both sweeps
+  constexpr int kColLds = UN * kArnNT * static_cast<int>(sizeof(T));
+  constexpr int kFixedLds = (3 * EXPW_MAX_KRYLOV + 1 + EXPW_MAX_KRYLOV * EXPW_MAX_KRYLOV + kArnMaxVals * (NW + 1)) * 8;
+  constexpr int kFree = kArnLdsBudget - kFixedLds - kColLds;
+  constexpr int NC = kFree / kColLds < 4 ? kFree / kColLds : 4;
+  __shared__ T s_cache[NC > 0 ? NC : 1][NC > 0 ? UN : 1][NC > 0 ? kArnNT : 1];
   const unsigned nb = gridDim.x;
   const int64_t nthreads = static_cast<int64_t>(nb) * kArnNT;
   const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kArnNT + threadIdx.x;
@@ -358,6 +366,13 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   };
   // fn(i, column) for the n stored columns first, first + step, ..., two
   // buffers in turn; qa already holds (or is loading) Q_first
+  // fn(i, column) for the cached column Q_i (1 <= i <= NC)
+  auto from_lds = [&](int i, auto&& fn) {
+    T qt[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) qt[u] = s_cache[i - 1][u][threadIdx.x];
+    fn(i, qt);
+  };
   auto stream = [&](int first, int n, int step, auto&& fn) {
     for (int t = 0; t < n; t += 2) {
       const int i = first + t * step;
@@ -424,7 +439,7 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       put(0, static_cast<double>(r));
       if (j >= 1) put(j + 1, static_cast<double>(gq));
     }
-    stream(j - 1, j - 1, -1, [&](int i, const T* q) {
+    auto dot1 = [&](int i, const T* q) {
       T r = T(0), gq = T(0);
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
@@ -433,7 +448,12 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       }
       put(i, static_cast<double>(r));
       put(j + 1 + i, static_cast<double>(gq));
-    });
+    };
+    // columns 1..j-1: the first nc in LDS, the other ns streamed from memory
+    const int nc = j - 1 < NC ? (j - 1 > 0 ? j - 1 : 0) : NC;
+    const int ns = j - 1 > nc ? j - 1 - nc : 0;
+    stream(j - 1, ns, -1, dot1);
+    for (int i = nc; i >= 1; --i) from_lds(i, dot1);
     if (j >= 1) {
       T r = T(0);
 #pragma unroll
@@ -441,7 +461,7 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       put(j, static_cast<double>(r));
     }
     reduce(2 * j + 1, [&] {
-      if (j >= 2) load_col(qa, 1);
+      if (ns > 0) load_col(qa, nc + 1);
     });
     // MGS's projections: h_i = r_i - sum_{l<i} h_l <q_l, q_i>, lane i of wave 0
     if (wid == 0) {
@@ -476,11 +496,13 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
 #pragma unroll
       for (int u = 0; u < UN; ++u) w[u] -= h0 * q0[u];
     }
-    stream(1, j - 1, 1, [&](int i, const T* q) {
+    auto upd = [&](int i, const T* q) {
       const T hi = static_cast<T>(s_h[i]);
 #pragma unroll
       for (int u = 0; u < UN; ++u) w[u] -= hi * q[u];
-    });
+    };
+    for (int i = 1; i <= nc; ++i) from_lds(i, upd);
+    stream(nc + 1, ns, 1, upd);
     if (j >= 1) {
       const T hj = static_cast<T>(s_h[j]);
 #pragma unroll
@@ -493,10 +515,11 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       if (e < naug32) st_at(wout, e * kEs, w[u]);
       nrm += w[u] * w[u];
       s_qj[u][threadIdx.x] = w[u];
+      if (j < NC) s_cache[j < NC ? j : 0][u][threadIdx.x] = w[u];
     }
     put(0, static_cast<double>(nrm));
     reduce(1, [&] {
-      if (j >= 1 && j + 1 < a.k) load_col(qa, j);  // the next first sweep starts on Q_j
+      if (j > NC && j + 1 < a.k) load_col(qa, j);  // the next first sweep starts on Q_j
     });
     const double hn = sqrt(s_tot[0]);
     const double s = (hn > a.tol * beta) ? 1.0 / hn : 0.0;
