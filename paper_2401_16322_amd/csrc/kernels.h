@@ -411,13 +411,30 @@ __global__ __launch_bounds__(kBlock) void k_kry_combine_dev(T* __restrict__ S,
 
 // C = A B for keff x keff matrices in LDS (leading dimension LD), one
 // workgroup; ends with a barrier.
+// (A B)_{rc} for matrices in LDS (leading dimension LD): operands are read
+// eight at a time ahead of the multiply-adds
+template <int LD>
+__device__ __forceinline__ double lds_dot(const double* A, const double* B, int r, int c, int n) {
+  double acc = 0.0;
+  for (int l0 = 0; l0 < n; l0 += 8) {
+    double a[8], b[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const bool in = l0 + t < n;
+      a[t] = in ? A[r * LD + l0 + t] : 0.0;
+      b[t] = in ? B[(l0 + t) * LD + c] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc += a[t] * b[t];
+  }
+  return acc;
+}
+
 template <int LD>
 __device__ __forceinline__ void lds_matmul(const double* A, const double* B, double* C, int n) {
   for (int e = threadIdx.x; e < n * n; e += kBlock) {
     const int r = e / n, c = e - r * n;
-    double acc = 0.0;
-    for (int l = 0; l < n; ++l) acc += A[r * LD + l] * B[l * LD + c];
-    C[r * LD + c] = acc;
+    C[r * LD + c] = lds_dot<LD>(A, B, r, c, n);
   }
   __syncthreads();
 }
@@ -438,17 +455,20 @@ __global__ __launch_bounds__(kBlock) void k_kry_expm(const double* __restrict__ 
                                                      int* __restrict__ keff_out) {
   constexpr int LD = 65;
   __shared__ double A[64 * LD], T[64 * LD], W[64 * LD];
-  __shared__ double cs[64];
+  __shared__ double cs[64], sub[64];
   __shared__ int s_keff, s_sq;
   const int tid = threadIdx.x;
+  // the subdiagonal is loaded in parallel, then scanned in LDS
+  if (tid < k) sub[tid] = hess[(tid + 1) * 64 + tid];
+  const double beta = *beta_p;
+  __syncthreads();
   if (tid == 0) {
-    const double beta = *beta_p;
     int ke = k;
     if (!(beta > 0.0)) {
       ke = 0;
     } else {
       for (int j = 0; j < k; ++j)
-        if (!(hess[(j + 1) * 64 + j] > tol * beta)) {
+        if (!(sub[j] > tol * beta)) {
           ke = j + 1;
           break;
         }
@@ -495,19 +515,21 @@ __global__ __launch_bounds__(kBlock) void k_kry_expm(const double* __restrict__ 
     T[r * LD + c] = (r == c ? 1.0 : 0.0) + A[r * LD + c] / 16.0;
   }
   __syncthreads();
-  // Horner: T <- I + A T / j for j = 15 .. 1
+  // Horner: P <- I + A P / j for j = 15 .. 1, alternating between T and W
+  double* cur = T;
+  double* nxt = W;
   for (int j = 15; j >= 1; --j) {
-    lds_matmul<LD>(A, T, W, n);
     const double inv = 1.0 / j;
     for (int e = tid; e < n * n; e += kBlock) {
       const int r = e / n, c = e - r * n;
-      T[r * LD + c] = (r == c ? 1.0 : 0.0) + W[r * LD + c] * inv;
+      nxt[r * LD + c] = (r == c ? 1.0 : 0.0) + lds_dot<LD>(A, cur, r, c, n) * inv;
     }
     __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
   }
-  // squarings, alternating between T and W
-  double* cur = T;
-  double* nxt = W;
+  // squarings
   for (int i = 0; i < sq; ++i) {
     lds_matmul<LD>(cur, cur, nxt, n);
     double* t = cur;
