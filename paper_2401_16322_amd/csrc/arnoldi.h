@@ -253,7 +253,7 @@ __device__ __forceinline__ T apply_field(const Geo<T, K, DIM>& g, const Geo32& g
 struct ArnArgs {
   int64_t ns, naug, ld;
   int k;
-  int nvmax;     // values of the largest grid-wide reduction: 2k - 1
+  int nvmax;     // values of the largest grid-wide reduction: max(2, 2k - 1)
   double tail2;  // |e_p|^2: 1 with a source, else 0
   double tol;
   unsigned spin_limit;
@@ -313,44 +313,29 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   auto reduce = [&](int nv, auto&& after) {
     grid_sum_vec<kArnNT>(nv, a.nvmax, s_wpart, s_tot, slots, ++seq, a.spin_limit, err, after);
   };
-  auto nothing = [] {};
 
-  // q_0 = [S; e_p] / beta
-  double acc = 0.0;
-#pragma unroll
-  for (int u = 0; u < UN; ++u) {
-    const uint32_t e = e0 + u * estep;
-    if (e < ns32) {
-      const double v = static_cast<double>(S[e]);
-      acc += v * v;
-    }
-  }
-  put(0, acc);
-  reduce(1, nothing);
-  const double beta = sqrt(s_tot[0] + a.tail2);
-  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-  if (lead) {
-    *beta_out = beta;
-    sc[0] = 1.0;
-  }
+  // x = [S; e_p]. q0 holds x until its norm beta is known: the first
+  // grid-wide reduction of column 0 brings |x|^2 together with <H~ x, x>.
+  // Column 0's matvec reads S, an input complete before the launch, so no
+  // barrier precedes it; Q_0 is stored after that reduction (the kernel never
+  // reads it back).
   if (threadIdx.x == 0) s_scale[0] = 1.0;
   // q0: q_0; w: the vector being orthogonalized; qa, qb: streamed columns
   // Q_1..Q_{j-1}
   T q0[UN], w[UN], qa[UN], qb[UN];
+  double xx = 0.0;
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
     const uint32_t e = e0 + u * estep;
-    double v = 0.0;
+    T v = T(0);
     if (e < ns32)
-      v = static_cast<double>(S[e]) * inv;
+      v = S[e];
     else if (e + 1 == naug32 && a.tail2 > 0.0)
-      v = inv;
-    q0[u] = static_cast<T>(v);
-    s_qj[u][threadIdx.x] = q0[u];
-    if (e < naug32) st_at(Q, e * kEs, q0[u]);
+      v = T(1);
+    q0[u] = v;
+    xx += static_cast<double>(v) * static_cast<double>(v);
   }
-  put(0, 0.0);
-  reduce(1, nothing);  // Q_0 complete everywhere
+  double beta = 0.0, inv = 0.0;
 
   // the thread's first element, made opaque once per column (an empty asm):
   // otherwise the per-element index math of all UN elements is hoisted out
@@ -391,7 +376,11 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     T* wout = Q + (j + 1) * a.ld;
     ecur = e0;
     asm volatile("" : "+v"(ecur));
-    // w = s_j H~ Q_j
+    // w = s_j H~ Q_j (column 0: H~ x, scaled once beta is known)
+    const T* xcol = j == 0 ? S : qcol;
+    auto tailv = [&](int cc) -> T {
+      return j == 0 ? (cc == src.p - 1 ? T(1) : T(0)) : qcol[a.ns + cc];
+    };
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
       const uint32_t e = ecur + u * estep;
@@ -409,20 +398,20 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
           ic[1] = rest % g32.n[1];
           ic[2] = rest / g32.n[1];
         }
-        v = apply_field<T, K, BC, DIM>(g, g32, qcol, f, idx, ic);
+        v = apply_field<T, K, BC, DIM>(g, g32, xcol, f, idx, ic);
         if (f == 0 && src.n > 0 && static_cast<int64_t>(idx) >= src.lo && static_cast<int64_t>(idx) <= src.hi) {
           for (int s = 0; s < src.n; ++s)
             if (src.idx[s] == static_cast<int64_t>(idx)) {
               double gt = 0.0;
               for (int cc = 0; cc < src.p; ++cc)
-                gt += src.G[cc] * static_cast<double>(qcol[a.ns + cc]);
+                gt += src.G[cc] * static_cast<double>(tailv(cc));
               v += static_cast<T>(gt * static_cast<double>(amp[s]));
             }
         }
         v *= sj;
       } else if (e < naug32) {
         const int cc = static_cast<int>(e - ns32);
-        v = (cc + 1 < src.p) ? qcol[a.ns + cc + 1] * sj : T(0);  // J q_tail
+        v = (cc + 1 < src.p) ? tailv(cc + 1) * sj : T(0);  // J q_tail
       }
       w[u] = v;
     }
@@ -438,6 +427,7 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       }
       put(0, static_cast<double>(r));
       if (j >= 1) put(j + 1, static_cast<double>(gq));
+      if (j == 0) put(1, xx);
     }
     auto dot1 = [&](int i, const T* q) {
       T r = T(0), gq = T(0);
@@ -460,13 +450,31 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       for (int u = 0; u < UN; ++u) r += w[u] * s_qj[u][threadIdx.x];
       put(j, static_cast<double>(r));
     }
-    reduce(2 * j + 1, [&] {
+    reduce(j == 0 ? 2 : 2 * j + 1, [&] {
       if (ns > 0) load_col(qa, nc + 1);
     });
+    if (j == 0) {
+      // q_0 = x / beta, and w = H~ q_0
+      beta = sqrt(s_tot[1]);
+      inv = beta > 0.0 ? 1.0 / beta : 0.0;
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const uint32_t e = ecur + u * estep;
+        q0[u] = static_cast<T>(static_cast<double>(q0[u]) * inv);
+        w[u] = static_cast<T>(static_cast<double>(w[u]) * inv);
+        s_qj[u][threadIdx.x] = q0[u];
+        if (e < naug32) st_at(Q, e * kEs, q0[u]);
+      }
+      if (lead) {
+        *beta_out = beta;
+        sc[0] = 1.0;
+      }
+    }
     // MGS's projections: h_i = r_i - sum_{l<i} h_l <q_l, q_i>, lane i of wave 0
     if (wid == 0) {
       const double sl = lane <= j ? s_scale[lane] : 0.0;
       double r = lane <= j ? s_tot[lane] * sl : 0.0;
+      if (j == 0) r *= inv * inv;  // <H~ x, x> / beta^2
       const double grow = lane < j ? s_tot[j + 1 + lane] * s_scale[j] * sl : 0.0;  // <q_j, q_lane>
       // Gram entries are read from LDS eight steps ahead of the dependent chain
       for (int l0 = 0; l0 < j; l0 += 8) {

@@ -454,7 +454,7 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   aa.k = k;
   aa.tail2 = tail2;
   aa.tol = tol;
-  aa.nvmax = std::max(1, 2 * k - 1);
+  aa.nvmax = std::max(2, 2 * k - 1);
   aa.spin_limit = 1u << 20;  // about a second of polling
   const int nslots = kSlotBuffers * aa.nvmax * op->coop_blocks;
   k_fill_u64<<<(nslots + 255) / 256, 256, 0, op->stream>>>(slots, nslots, kSlotEmpty);
