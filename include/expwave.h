@@ -337,6 +337,85 @@ int32_t expw_set_timing(expw_op* op, int32_t class_mask);
  * launch, halos not counted) since timing was enabled. */
 int32_t expw_get_timing(expw_op* op, double* ms, int64_t* launches, double* bytes);
 
+/* ---------------------------------------------- the paper's PML operator
+ *
+ * Sec. 2, 2.1, 2.2 and the appendix on the free surface: the 2D acoustic
+ * system with perfectly matched layers in (u, v, w_x, w_y), displacement u,
+ * its rate v = u_t and the auxiliaries w_x, w_y:
+ *   u_t = v
+ *   v_t = (-b_x b_y + c^2 (d_xx + d_yy)) u - (b_x + b_y) v + c^2 (d_x w_x + d_y w_y) + f
+ *   w_x,t = (b_y - b_x) d_x u - b_x w_x,   w_y,t = (b_x - b_y) d_y u - b_y w_y
+ * on nx x ny nodes, row 0 the free surface and y pointing up (y = -j h).
+ * Layout of a state (dtype of the grid, device memory): four fields of
+ * nx * ny values, x fastest, [u | v | w_x | w_y]; u, v and c^2 at nodes
+ * (i, j), w_x at (i + 1/2, j), w_y at (i, j + 1/2). Stencils: 8th-order
+ * staggered first and centred second derivatives with zero values outside
+ * the sides and the bottom; at the top, the appendix's one-sided stencils for
+ * d_yy u (rows 0..3) and d_y u (half rows 0..2), and Fornberg weights on the
+ * surface point (w_y = 0 there) and w_y's eight nearest half rows for d_y w_y
+ * (rows 0..3). The damping b_z = beta0 (1 - d/delta)^2 grows towards the two
+ * sides (b_x) and the bottom (b_y); there is no layer at the top. Sources
+ * enter the v equation with strength amp / h^2; receivers record u. */
+typedef struct {
+  int64_t nx, ny;    /* nodes along x and depth; nx >= 1, ny >= 9 */
+  double h;          /* grid spacing (m), > 0 */
+  int32_t dtype;     /* expw_dtype of every device array */
+  int32_t abc_cells; /* layer thickness delta = abc_cells h, >= 0 */
+  double beta0;      /* beta_0 of the profile (1/s), >= 0 */
+} expw_pml_grid;
+
+typedef struct expw_pml expw_pml;
+
+/* Host only: validates a grid (EXPW_EINVAL with a message). */
+int32_t expw_pml_check_grid(const expw_pml_grid* grid);
+
+/* Host only: the rectangle [x_lo, 0] x i[-B, B] around the spectrum (the
+ * paper gives no formula; the reading): B = 1.25 c_max sqrt(2 s), s the
+ * largest symbol (205/72 + 2 sum |b_l|) / h^2 of the centred second derivative
+ * along one axis and 1.25 a margin for the one-sided surface rows;
+ * x_lo = -(max b_x + max b_y). */
+int32_t expw_pml_spectrum_rectangle(const expw_pml_grid* grid, double c2_max, double* x_lo, double* B);
+
+/* Host only: the one-sided tables the kernels use, row-major in FP64:
+ * d2[4][9] (d_yy u at rows 0..3 from u_0..u_8, times 1/h^2), d1[3][8] (d_y u
+ * at half rows 0..2 from u_0..u_7, times 1/h), dw[4][8] (d_y w_y at rows
+ * 0..3 from w_y's half rows 0..7, times 1/h). */
+int32_t expw_pml_surface_weights(double* d2, double* d1, double* dw);
+
+/* Bytes of device workspace expw_pml_create needs (max_taylor_p <= EXPW_MAX_TAYLOR). */
+int32_t expw_pml_workspace_size(const expw_pml_grid* grid, int32_t max_taylor_p, size_t* bytes);
+
+/* Binds a grid, c^2 at the nodes (nx * ny values, > 0, read until destroy)
+ * and a caller-owned, 256-byte aligned workspace; computes the spectrum
+ * rectangle and the Faber ellipse. stream: hipStream_t (NULL = default). */
+int32_t expw_pml_create(const expw_pml_grid* grid, const void* c2_dev, int32_t max_taylor_p,
+                        void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                        expw_pml** out);
+int32_t expw_pml_destroy(expw_pml* op);
+int32_t expw_pml_get_ellipse(const expw_pml* op, double* gamma, double* c0, double* c1);
+
+/* y = H x (device arrays of 4 nx ny values; y must not alias x). */
+int32_t expw_pml_apply(expw_pml* op, const void* x_dev, void* y_dev);
+
+/* Point sources on the v equation at nodes node_idx_host[s] (j nx + i), one
+ * Ricker wavelet, Taylor order taylor_p <= max_taylor_p (Sec. 3.2, augmented
+ * matrix). n_src = 0 removes them. */
+int32_t expw_pml_set_source_ricker(expw_pml* op, int32_t n_src, const int64_t* node_idx_host,
+                                   const double* amp_host, double f_peak, double t_delay,
+                                   int32_t taylor_p);
+
+/* Receivers: u at node_idx_dev[r] (device array, kept until replaced). */
+int32_t expw_pml_set_receivers(expw_pml* op, int32_t n_rec, const int64_t* node_idx_dev);
+
+/* nsteps Faber steps of degree m (Sec. 3.2) in place on state_dev, step n
+ * from t0 + n dt, one term per sweep; traces_dev (nullable) receives u at the
+ * receivers after every step (nsteps x n_rec). Asynchronous on the stream. */
+int32_t expw_pml_step_faber(expw_pml* op, void* state_dev, double t0, double dt, int32_t m,
+                            int64_t nsteps, void* traces_dev);
+
+/* Synchronizes the stream and reports device errors. */
+int32_t expw_pml_sync_status(expw_pml* op);
+
 #ifdef __cplusplus
 }
 #endif

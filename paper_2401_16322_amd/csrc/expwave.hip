@@ -15,6 +15,7 @@
 #include "fused3d.h"
 #include "internal.h"
 #include "kernels.h"
+#include "pml.h"
 #include "profiler.h"
 
 struct expw_op {
@@ -1402,6 +1403,346 @@ int32_t expw_set_krylov_expm(expw_op* op, int32_t mode) {
   if (mode != EXPW_EXPM_DEVICE && mode != EXPW_EXPM_HOST)
     return fail(EXPW_EINVAL, "mode must be EXPW_EXPM_DEVICE or EXPW_EXPM_HOST");
   op->kry_mode = mode;
+  return EXPW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- PML operator
+
+struct expw_pml {
+  expw_pml_grid g;
+  const void* c2;
+  char* ws;
+  size_t ws_bytes;
+  hipStream_t stream;
+  int pmax;
+  size_t off_bx, off_bxh, off_by, off_byh, off_src_idx, off_src_amp, off_big;
+  double c2max, x_lo, B, gamma, c0, c1;
+  double d2[4][9], d1[3][8], dw[4][8];
+  int n_src;
+  int64_t src_lo, src_hi;
+  double f_peak, t_delay;
+  int taylor_p;
+  int n_rec;
+  const int64_t* rec_dev;
+};
+
+namespace expw {
+namespace {
+
+struct PmlLayout {
+  size_t bx, bxh, by, byh, src_idx, src_amp, big, total;
+};
+
+PmlLayout pml_layout(const expw_pml_grid& g) {
+  const size_t es = g.dtype == EXPW_F32 ? 4 : 8;
+  PmlLayout L{};
+  size_t off = 0;
+  L.bx = off; off = align_up(off + g.nx * es);
+  L.bxh = off; off = align_up(off + g.nx * es);
+  L.by = off; off = align_up(off + g.ny * es);
+  L.byh = off; off = align_up(off + g.ny * es);
+  L.src_idx = off; off = align_up(off + EXPW_MAX_SOURCES * sizeof(int64_t));
+  L.src_amp = off; off = align_up(off + EXPW_MAX_SOURCES * es);
+  L.big = off;
+  // Faber: two previous terms and the partial sum, 4 fields each
+  L.total = align_up(off + 3 * 4 * static_cast<size_t>(g.nx * g.ny) * es);
+  return L;
+}
+
+template <typename T>
+PmlGeo<T> make_pml_geo(const expw_pml* op) {
+  PmlGeo<T> g{};
+  g.nx = static_cast<int32_t>(op->g.nx);
+  g.ny = static_cast<int32_t>(op->g.ny);
+  g.N = op->g.nx * op->g.ny;
+  g.ih = static_cast<T>(1.0 / op->g.h);
+  g.ih2 = static_cast<T>(1.0 / (op->g.h * op->g.h));
+  double alpha[4];
+  int K = 0;
+  stagger_weights(8, alpha, &K);
+  for (int l = 0; l < 4; ++l) g.a[l] = static_cast<T>(alpha[l]);
+  // Sec. 2.1, centred second derivative (read with sums)
+  g.d2c = static_cast<T>(-205.0 / 72.0);
+  const double b[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+  for (int l = 0; l < 4; ++l) g.d2[l] = static_cast<T>(b[l]);
+  for (int r = 0; r < 4; ++r)
+    for (int k = 0; k < 9; ++k) g.s2[r][k] = static_cast<T>(op->d2[r][k]);
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 8; ++k) g.s1[r][k] = static_cast<T>(op->d1[r][k]);
+  for (int r = 0; r < 4; ++r)
+    for (int k = 0; k < 8; ++k) g.sw[r][k] = static_cast<T>(op->dw[r][k]);
+  g.c2 = static_cast<const T*>(op->c2);
+  g.bx = reinterpret_cast<const T*>(op->ws + op->off_bx);
+  g.bxh = reinterpret_cast<const T*>(op->ws + op->off_bxh);
+  g.by = reinterpret_cast<const T*>(op->ws + op->off_by);
+  g.byh = reinterpret_cast<const T*>(op->ws + op->off_byh);
+  return g;
+}
+
+template <typename T>
+Src<T> make_pml_src(const expw_pml* op, double q) {
+  Src<T> s{};
+  s.n = op->n_src;
+  s.lo = op->src_lo;
+  s.hi = op->src_hi;
+  s.idx = reinterpret_cast<const int64_t*>(op->ws + op->off_src_idx);
+  s.amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
+  s.q = static_cast<T>(q);
+  return s;
+}
+
+// Faber steps (Sec. 3.2) on the PML operator, one term per sweep; the ellipse
+// is the step ellipse of precision T, as for the p/v operator.
+template <typename T>
+int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t nsteps, T* traces) {
+  const PmlGeo<T> g = make_pml_geo<T>(op);
+  const int64_t ns = 4 * g.N;
+  T* A = reinterpret_cast<T*>(op->ws + op->off_big);
+  T* B = A + ns;
+  T* C = B + ns;
+  double gs, c0s, c1s;
+  step_ellipse(sizeof(T) == 4 ? EXPW_F32 : EXPW_F64, op->gamma, op->c0, op->c1, &gs, &c0s, &c1s);
+  std::vector<double> a(m + 1), q(m, 0.0), der(EXPW_MAX_TAYLOR), G(EXPW_MAX_TAYLOR);
+  faber_coefficients(gs, c0s, c1s, dt, m, a.data());
+  const int p = op->taylor_p;
+  const double sc = 1.0 / (op->g.h * op->g.h);
+  const unsigned grid = grid_for(g.N);
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const double t = t0 + st * dt;
+    if (op->n_src > 0) {
+      ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
+      for (int c = 0; c < p; ++c) G[c] = der[p - 1 - c];
+      faber_source_scalars(gs, c0s, c1s, m, p, G.data(), q.data());
+      for (int j = 0; j < m; ++j) q[j] *= sc;
+    }
+    FaberTerm<T> c{};
+    c.inv_gamma = static_cast<T>(1.0 / gs);
+    c.c0 = static_cast<T>(c0s);
+    // j = 1: v1 = F1 v0 into A, sum a0 v0 + a1 v1 into C
+    c.first = 1;
+    split_weight(a[0], &c.a_first, &c.a_first_lo);
+    split_weight(a[1], &c.a_j, &c.a_j_lo);
+    // (S is read with a halo here, so the sum of a one-term step goes to C first)
+    k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, S, nullptr, m == 1 ? nullptr : A, nullptr, C, c,
+                                                         make_pml_src<T>(op, q[0]));
+    if (int32_t rc = check_launch("pml faber j=1")) return rc;
+    if (m == 1) {
+      if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
+        return fail(EXPW_EDEVICE, "pml faber: copy failed");
+    } else {
+      // j = 2: v2 = F1 v1 - 2 c1 v0 into B
+      c.first = 0;
+      c.a_first = c.a_first_lo = T(0);
+      c.cpp = static_cast<T>(2.0 * c1s);
+      split_weight(a[2], &c.a_j, &c.a_j_lo);
+      k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, A, S, m == 2 ? nullptr : B, C, m == 2 ? S : C,
+                                                           c, make_pml_src<T>(op, q[1]));
+      if (int32_t rc = check_launch("pml faber j=2")) return rc;
+      T* last = B;
+      T* older = A;
+      c.cpp = static_cast<T>(c1s);
+      for (int j = 3; j <= m; ++j) {
+        split_weight(a[j], &c.a_j, &c.a_j_lo);
+        const bool fin = j == m;
+        k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, last, older, fin ? nullptr : older, C,
+                                                             fin ? S : C, c, make_pml_src<T>(op, q[j - 1]));
+        if (int32_t rc = check_launch("pml faber term")) return rc;
+        std::swap(last, older);
+      }
+    }
+    if (traces && op->n_rec > 0) {
+      k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec, traces + st * op->n_rec);
+      if (int32_t rc = check_launch("pml gather")) return rc;
+    }
+  }
+  return EXPW_OK;
+}
+
+int32_t check_pml(const expw_pml* op) {
+  if (!op) return fail(EXPW_EINVAL, "op is NULL");
+  return EXPW_OK;
+}
+
+}  // namespace
+}  // namespace expw
+
+extern "C" {
+
+int32_t expw_pml_workspace_size(const expw_pml_grid* g, int32_t max_p, size_t* bytes) {
+  clear_error();
+  if (int32_t rc = expw_pml_check_grid(g)) return rc;
+  if (max_p < 0 || max_p > EXPW_MAX_TAYLOR) return fail(EXPW_EINVAL, "max_taylor_p must be in [0, %d]", EXPW_MAX_TAYLOR);
+  if (!bytes) return fail(EXPW_EINVAL, "bytes is NULL");
+  *bytes = pml_layout(*g).total;
+  return EXPW_OK;
+}
+
+int32_t expw_pml_create(const expw_pml_grid* g, const void* c2_dev, int32_t max_p, void* ws,
+                        size_t ws_bytes, void* stream, expw_pml** out) {
+  clear_error();
+  size_t need = 0;
+  if (int32_t rc = expw_pml_workspace_size(g, max_p, &need)) return rc;
+  if (!out) return fail(EXPW_EINVAL, "out is NULL");
+  if (!c2_dev) return fail(EXPW_EINVAL, "c2_dev is NULL");
+  if (!ws) return fail(EXPW_EINVAL, "workspace_dev is NULL");
+  if (ws_bytes < need) return fail(EXPW_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return fail(EXPW_EINVAL, "workspace must be 256-byte aligned");
+  expw_pml* op = new expw_pml();
+  op->g = *g;
+  op->c2 = c2_dev;
+  op->ws = static_cast<char*>(ws);
+  op->ws_bytes = ws_bytes;
+  op->stream = static_cast<hipStream_t>(stream);
+  op->pmax = max_p;
+  const PmlLayout L = pml_layout(*g);
+  op->off_bx = L.bx;
+  op->off_bxh = L.bxh;
+  op->off_by = L.by;
+  op->off_byh = L.byh;
+  op->off_src_idx = L.src_idx;
+  op->off_src_amp = L.src_amp;
+  op->off_big = L.big;
+  op->n_src = 0;
+  op->n_rec = 0;
+  op->rec_dev = nullptr;
+  op->taylor_p = std::max(1, std::min(8, max_p));
+  pml_surface_tables(op->d2, op->d1, op->dw);
+  // damping profiles (FP64 on the host, stored in the grid dtype)
+  const size_t es = g->dtype == EXPW_F32 ? 4 : 8;
+  std::vector<std::vector<char>> staging;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t n = k < 2 ? g->nx : g->ny;
+    std::vector<double> prof(n);
+    if (k < 2) damping_profile(n, g->h, g->abc_cells, g->beta0, k == 1, prof.data());
+    else bottom_profile(n, g->h, g->abc_cells, g->beta0, k == 3, prof.data());
+    std::vector<char> buf(n * es);
+    for (int64_t i = 0; i < n; ++i) {
+      if (g->dtype == EXPW_F32) reinterpret_cast<float*>(buf.data())[i] = static_cast<float>(prof[i]);
+      else reinterpret_cast<double*>(buf.data())[i] = prof[i];
+    }
+    const size_t off = k == 0 ? L.bx : k == 1 ? L.bxh : k == 2 ? L.by : L.byh;
+    if (hipMemcpyAsync(op->ws + off, buf.data(), buf.size(), hipMemcpyHostToDevice, op->stream) != hipSuccess) {
+      delete op;
+      return fail(EXPW_EDEVICE, "expw_pml_create: profile upload failed");
+    }
+    staging.push_back(std::move(buf));
+  }
+  // largest c^2 (partials in the Faber buffer, which is free until a step)
+  double* part = reinterpret_cast<double*>(op->ws + L.big);
+  const int64_t N = g->nx * g->ny;
+  const unsigned nb = red_grid_for(N);
+  if (g->dtype == EXPW_F32)
+    k_c2_max<float><<<nb, kBlock, 0, op->stream>>>(static_cast<const float*>(c2_dev), N, part);
+  else
+    k_c2_max<double><<<nb, kBlock, 0, op->stream>>>(static_cast<const double*>(c2_dev), N, part);
+  std::vector<double> parts(nb);
+  hipError_t e = hipMemcpyAsync(parts.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, op->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
+  if (e != hipSuccess || hipGetLastError() != hipSuccess) {
+    delete op;
+    return fail(EXPW_EDEVICE, "expw_pml_create: device error: %s", hipGetErrorString(e));
+  }
+  double c2max = -INFINITY;
+  for (double v : parts) c2max = std::fmax(c2max, v);
+  if (!std::isfinite(c2max)) {
+    delete op;
+    return fail(EXPW_ENONFINITE, "c2 holds a non-finite or non-positive value");
+  }
+  op->c2max = c2max;
+  expw_pml_spectrum_rectangle(g, c2max, &op->x_lo, &op->B);
+  expw_ellipse(op->x_lo, op->B, &op->gamma, &op->c0, &op->c1);
+  *out = op;
+  return EXPW_OK;
+}
+
+int32_t expw_pml_destroy(expw_pml* op) {
+  delete op;
+  return EXPW_OK;
+}
+
+int32_t expw_pml_get_ellipse(const expw_pml* op, double* gamma, double* c0, double* c1) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (gamma) *gamma = op->gamma;
+  if (c0) *c0 = op->c0;
+  if (c1) *c1 = op->c1;
+  return EXPW_OK;
+}
+
+int32_t expw_pml_apply(expw_pml* op, const void* x, void* y) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (!x || !y) return fail(EXPW_EINVAL, "NULL state");
+  if (x == y) return fail(EXPW_EINVAL, "y must not alias x");
+  const int64_t N = op->g.nx * op->g.ny;
+  if (op->g.dtype == EXPW_F32)
+    k_pml_apply<float><<<grid_for(N), kBlock, 0, op->stream>>>(make_pml_geo<float>(op), static_cast<const float*>(x), static_cast<float*>(y));
+  else
+    k_pml_apply<double><<<grid_for(N), kBlock, 0, op->stream>>>(make_pml_geo<double>(op), static_cast<const double*>(x), static_cast<double*>(y));
+  return check_launch("pml apply");
+}
+
+int32_t expw_pml_set_source_ricker(expw_pml* op, int32_t n_src, const int64_t* idx, const double* amp,
+                                   double f_peak, double t_delay, int32_t taylor_p) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (n_src < 0 || n_src > EXPW_MAX_SOURCES) return fail(EXPW_EINVAL, "n_src must be in [0, %d]", EXPW_MAX_SOURCES);
+  if (n_src == 0) {
+    op->n_src = 0;
+    return EXPW_OK;
+  }
+  if (!idx || !amp) return fail(EXPW_EINVAL, "NULL source arrays");
+  if (!(f_peak > 0.0) || !std::isfinite(f_peak) || !std::isfinite(t_delay)) return fail(EXPW_EINVAL, "f_peak must be > 0");
+  if (taylor_p < 1 || taylor_p > op->pmax) return fail(EXPW_EINVAL, "taylor_p must be in [1, %d] (max_taylor_p at create)", op->pmax);
+  const int64_t N = op->g.nx * op->g.ny;
+  for (int s = 0; s < n_src; ++s) {
+    if (idx[s] < 0 || idx[s] >= N) return fail(EXPW_EINVAL, "source %d index %lld out of range", s, (long long)idx[s]);
+    if (!std::isfinite(amp[s])) return fail(EXPW_EINVAL, "source %d amplitude not finite", s);
+  }
+  std::vector<char> ampbuf(n_src * (op->g.dtype == EXPW_F32 ? 4 : 8));
+  for (int s = 0; s < n_src; ++s) {
+    if (op->g.dtype == EXPW_F32) reinterpret_cast<float*>(ampbuf.data())[s] = static_cast<float>(amp[s]);
+    else reinterpret_cast<double*>(ampbuf.data())[s] = amp[s];
+  }
+  if (hipMemcpyAsync(op->ws + op->off_src_idx, idx, n_src * sizeof(int64_t), hipMemcpyHostToDevice, op->stream) != hipSuccess ||
+      hipMemcpyAsync(op->ws + op->off_src_amp, ampbuf.data(), ampbuf.size(), hipMemcpyHostToDevice, op->stream) != hipSuccess ||
+      hipStreamSynchronize(op->stream) != hipSuccess)
+    return fail(EXPW_EDEVICE, "source upload failed");
+  op->n_src = n_src;
+  op->src_lo = *std::min_element(idx, idx + n_src);
+  op->src_hi = *std::max_element(idx, idx + n_src);
+  op->f_peak = f_peak;
+  op->t_delay = t_delay;
+  op->taylor_p = taylor_p;
+  return EXPW_OK;
+}
+
+int32_t expw_pml_set_receivers(expw_pml* op, int32_t n_rec, const int64_t* idx_dev) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (n_rec < 0) return fail(EXPW_EINVAL, "n_rec must be >= 0");
+  if (n_rec > 0 && !idx_dev) return fail(EXPW_EINVAL, "NULL receiver indices");
+  op->n_rec = n_rec;
+  op->rec_dev = n_rec > 0 ? idx_dev : nullptr;
+  return EXPW_OK;
+}
+
+int32_t expw_pml_step_faber(expw_pml* op, void* state, double t0, double dt, int32_t m, int64_t nsteps,
+                            void* traces) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (!state) return fail(EXPW_EINVAL, "state is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t0)) return fail(EXPW_EINVAL, "dt must be > 0");
+  if (nsteps < 0) return fail(EXPW_EINVAL, "nsteps must be >= 0");
+  if (m < 1 || m > 1024) return fail(EXPW_EINVAL, "Faber degree m must be in [1, 1024]");
+  if (op->g.dtype == EXPW_F32)
+    return pml_faber_impl<float>(op, static_cast<float*>(state), t0, dt, m, nsteps, static_cast<float*>(traces));
+  return pml_faber_impl<double>(op, static_cast<double*>(state), t0, dt, m, nsteps, static_cast<double*>(traces));
+}
+
+int32_t expw_pml_sync_status(expw_pml* op) {
+  if (int32_t rc = check_pml(op)) return rc;
+  const hipError_t e = hipStreamSynchronize(op->stream);
+  if (e != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGetLastError();
+  if (e2 != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e2));
   return EXPW_OK;
 }
 

@@ -28,5 +28,10 @@ bool expm(int k, const double* A, double* E);
 // and c1 rounded to that precision, gamma taken back from the rounded 1/gamma.
 void step_ellipse(int dtype, double gamma, double c0, double c1, double* gs, double* c0s,
                   double* c1s);
+// PML operator: Fornberg weights (c[k * n + i], derivative orders 0..m), the
+// free-surface tables, and beta_y (layer at the bottom only).
+void fd_weights(double z0, const double* nodes, int n, int m, double* c);
+void pml_surface_tables(double d2[4][9], double d1[3][8], double dw[4][8]);
+void bottom_profile(int64_t n, double h, int cells, double beta0, bool half, double* out);
 
 }  // namespace expw

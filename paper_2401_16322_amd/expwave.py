@@ -42,6 +42,14 @@ _pi64 = ctypes.POINTER(ctypes.c_int64)
 _pi32 = ctypes.POINTER(ctypes.c_int32)
 _pgrid = ctypes.POINTER(ExpwGrid)
 
+
+class ExpwPmlGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("h", ctypes.c_double),
+                ("dtype", ctypes.c_int32), ("abc_cells", ctypes.c_int32), ("beta0", ctypes.c_double)]
+
+
+_ppml = ctypes.POINTER(ExpwPmlGrid)
+
 # name -> (restype, argtypes); the list is the full C ABI of include/expwave.h
 SIGNATURES = {
     "expw_version": (_i32, []),
@@ -87,6 +95,18 @@ SIGNATURES = {
     "expw_set_krylov_persistent": (_i32, [_vp, _i32]),
     "expw_set_timing": (_i32, [_vp, _i32]),
     "expw_get_timing": (_i32, [_vp, _pd, _pi64, _pd]),
+    "expw_pml_check_grid": (_i32, [_ppml]),
+    "expw_pml_spectrum_rectangle": (_i32, [_ppml, _dbl, _pd, _pd]),
+    "expw_pml_surface_weights": (_i32, [_pd, _pd, _pd]),
+    "expw_pml_workspace_size": (_i32, [_ppml, _i32, ctypes.POINTER(_sz)]),
+    "expw_pml_create": (_i32, [_ppml, _vp, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "expw_pml_destroy": (_i32, [_vp]),
+    "expw_pml_get_ellipse": (_i32, [_vp, _pd, _pd, _pd]),
+    "expw_pml_apply": (_i32, [_vp, _vp, _vp]),
+    "expw_pml_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
+    "expw_pml_set_receivers": (_i32, [_vp, _i32, _vp]),
+    "expw_pml_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
+    "expw_pml_sync_status": (_i32, [_vp]),
 }
 
 KERNEL_CLASSES = ("faber", "krylov_matvec", "krylov_mgs", "krylov_aux", "rk4",
@@ -626,6 +646,111 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def make_pml_grid(nx, ny, h, dtype=EXPW_F32, abc_cells=0, beta0=0.0):
+    g = ExpwPmlGrid()
+    g.nx, g.ny, g.h, g.dtype, g.abc_cells, g.beta0 = int(nx), int(ny), float(h), int(dtype), int(abc_cells), float(beta0)
+    return g
+
+
+def expw_pml_spectrum_rectangle(grid, c2_max):
+    x_lo, B = _dbl(), _dbl()
+    _check(load().expw_pml_spectrum_rectangle(ctypes.byref(grid), c2_max, ctypes.byref(x_lo), ctypes.byref(B)))
+    return x_lo.value, B.value
+
+
+def expw_pml_surface_weights():
+    d2, d1, dw = np.zeros((4, 9)), np.zeros((3, 8)), np.zeros((4, 8))
+    _check(load().expw_pml_surface_weights(_dptr(d2), _dptr(d1), _dptr(dw)))
+    return d2, d1, dw
+
+
+def expw_pml_workspace_size(grid, max_taylor_p):
+    out = _sz(0)
+    _check(load().expw_pml_workspace_size(ctypes.byref(grid), max_taylor_p, ctypes.byref(out)))
+    return out.value
+
+
+class PMLOperator:
+    """The paper's own operator (the 2D acoustic PML system with a free surface)
+    on one grid. c2: GPU tensor (float32 or float64) of numpy shape (ny, nx),
+    row 0 the free surface. States are flat tensors of 4 * nx * ny values
+    [u | v | w_x | w_y]; only Faber steps run on this operator."""
+
+    def __init__(self, nx, ny, h, c2, abc_cells=0, beta0=0.0, max_taylor_p=8):
+        import torch
+        self._torch = torch
+        if not c2.is_cuda or c2.dtype not in (torch.float32, torch.float64):
+            raise ValueError("c2 must be a float32 or float64 GPU tensor")
+        self.dtype = c2.dtype
+        self.device = c2.device
+        self.nx, self.ny = int(nx), int(ny)
+        self.npts = self.nx * self.ny
+        self.nstate = 4 * self.npts
+        self.grid = make_pml_grid(nx, ny, h, EXPW_F32 if c2.dtype == torch.float32 else EXPW_F64,
+                                  abc_cells, beta0)
+        self.c2 = c2.contiguous()
+        if self.c2.numel() != self.npts:
+            raise ValueError("c2 has the wrong number of points")
+        nbytes = expw_pml_workspace_size(self.grid, max_taylor_p)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._rec = None
+        h_ = _vp()
+        _check(load().expw_pml_create(ctypes.byref(self.grid), self.c2.data_ptr(), max_taylor_p,
+                                      self.workspace.data_ptr(), nbytes,
+                                      torch.cuda.current_stream(self.device).cuda_stream, ctypes.byref(h_)))
+        self.op = h_.value
+
+    def __del__(self):
+        op = getattr(self, "op", None)
+        if op:
+            load().expw_pml_destroy(op)
+            self.op = None
+
+    def _check_state(self, state):
+        if state.dtype != self.dtype or not state.is_cuda or state.numel() != self.nstate \
+                or not state.is_contiguous():
+            raise ValueError("state must be a contiguous GPU tensor of the grid dtype and size")
+
+    @property
+    def ellipse(self):
+        g, c0, c1 = _dbl(), _dbl(), _dbl()
+        _check(load().expw_pml_get_ellipse(self.op, ctypes.byref(g), ctypes.byref(c0), ctypes.byref(c1)))
+        return g.value, c0.value, c1.value
+
+    def apply(self, x, y):
+        self._check_state(x)
+        self._check_state(y)
+        _check(load().expw_pml_apply(self.op, x.data_ptr(), y.data_ptr()))
+
+    def set_source_ricker(self, nodes, amps, f_peak, t_delay, taylor_p):
+        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+        amps = np.ascontiguousarray(amps, dtype=np.float64)
+        if nodes.size != amps.size:
+            raise ValueError("nodes and amps differ in length")
+        _check(load().expw_pml_set_source_ricker(self.op, nodes.size, nodes.ctypes.data_as(_pi64),
+                                                 _dptr(amps), f_peak, t_delay, taylor_p))
+
+    def set_receivers(self, nodes):
+        t = self._torch.as_tensor(np.asarray(nodes, dtype=np.int64), device=self.device).contiguous()
+        self._rec = t
+        _check(load().expw_pml_set_receivers(self.op, t.numel(), t.data_ptr()))
+
+    def step_faber(self, state, t0, dt, m, nsteps, traces=None):
+        self._check_state(state)
+        tp = None
+        if traces is not None:
+            if self._rec is None:
+                raise ValueError("no receivers set")
+            if traces.dtype != self.dtype or traces.numel() < nsteps * self._rec.numel() \
+                    or not traces.is_contiguous():
+                raise ValueError("traces must hold nsteps * n_rec values of the grid dtype")
+            tp = traces.data_ptr()
+        _check(load().expw_pml_step_faber(self.op, state.data_ptr(), t0, dt, m, nsteps, tp))
+
+    def sync(self):
+        _check(load().expw_pml_sync_status(self.op))
 
 
 class Batch:

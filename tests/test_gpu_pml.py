@@ -1,0 +1,110 @@
+"""GPU parity of the paper's own operator (the 2D acoustic PML system with a
+free surface) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import pml
+from oracle.steppers import run
+from gpu_cases import TOL, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+APPLY_TOL = {"float64": 1e-13, "float32": 2e-6}
+
+
+def _case(nx, ny, dtype, seed, cells=6, beta0=150.0, src=True):
+    import torch
+    from paper_2401_16322_amd.expwave import PMLOperator
+    g = pml.PMLGrid(nx, ny, 10.0, abc_cells=cells, beta0=beta0)
+    rng = np.random.default_rng(seed)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    x = np.ones((ny, 1)) * np.arange(nx)[None, :]
+    c = 1800.0 + 40.0 * y + 100.0 * np.sin(x / 7.0)
+    c2 = c ** 2
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    op = PMLOperator(nx, ny, 10.0, torch.tensor(c2, dtype=tdt, device="cuda"), abc_cells=cells,
+                     beta0=beta0, max_taylor_p=8)
+    U0 = rng.standard_normal(g.nstate) * 1e-3
+    s = None
+    if src:
+        pt = (ny // 3) * nx + nx // 2
+        s = pml.PMLSources((pt,), (1.5,), 20.0, 0.05)
+        op.set_source_ricker([pt], [1.5], 20.0, 0.05, 8)
+    # the oracle runs on the ellipse the library chose
+    prob = pml.PMLProblem(g, c2, s, rect=None)
+    return op, prob, U0, tdt
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("nx,ny", [(37, 29), (9, 9), (1, 12), (300, 40), (70, 300)])
+def test_apply_matches_oracle(dtype, nx, ny):
+    import torch
+    op, prob, U0, tdt = _case(nx, ny, dtype, seed=1, src=False)
+    x = torch.tensor(U0, dtype=tdt, device="cuda")
+    y = torch.empty_like(x)
+    op.apply(x, y)
+    op.sync()
+    ref = prob.H(U0)
+    got = y.cpu().numpy()
+    for f in range(4):
+        sl = slice(f * prob.grid.npts, (f + 1) * prob.grid.npts)
+        assert np.max(np.abs(got[sl] - ref[sl])) <= APPLY_TOL[dtype] * max(np.max(np.abs(ref[sl])), 1e-300), f
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("m", [1, 2, 3, 12, 20])
+def test_faber_steps_with_source_and_receivers_match_oracle(dtype, m):
+    import torch
+    op, prob, U0, tdt = _case(45, 33, dtype, seed=2)
+    g = prob.grid
+    rec = np.array([0 * g.nx + i for i in range(0, g.nx, 4)] + [10 * g.nx + 5], dtype=np.int64)
+    op.set_receivers(rec)
+    nst, dt, t0 = 3, 1e-3, 0.02
+    U = torch.tensor(U0, dtype=tdt, device="cuda")
+    tr = torch.zeros(nst * rec.size, dtype=tdt, device="cuda")
+    op.step_faber(U, t0, dt, m, nst, traces=tr)
+    op.sync()
+    ref, traces, _ = run(prob, "faber", U0, t0, dt, nst, receivers=rec, m=m, p=8,
+                         ellipse=_step_ellipse(op, dtype))
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+    assert rel_l2(tr.cpu().numpy().reshape(nst, -1), traces) <= TOL[dtype]
+
+
+def _step_ellipse(op, dtype):
+    from paper_2401_16322_amd import expwave as ew
+    gam, c0, c1 = op.ellipse
+    return ew.expw_step_ellipse(ew.EXPW_F32 if dtype == "float32" else ew.EXPW_F64, gam, c0, c1)
+
+
+def test_library_ellipse_matches_the_oracle_reading():
+    op, prob, U0, tdt = _case(45, 33, "float64", seed=3)
+    assert np.allclose(op.ellipse, prob.ellipse(), rtol=1e-13, atol=0.0)
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_faber_at_a_larger_grid_without_layer(dtype):
+    """512 x 256 without a layer: free surface and zero values only."""
+    import torch
+    op, prob, U0, tdt = _case(512, 256, dtype, seed=4, cells=0, beta0=0.0)
+    U = torch.tensor(U0, dtype=tdt, device="cuda")
+    op.step_faber(U, 0.0, 2e-3, 16, 1)
+    op.sync()
+    ref, _, _ = run(prob, "faber", U0, 0.0, 2e-3, 1, m=16, p=8, ellipse=_step_ellipse(op, dtype))
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+
+
+def test_invalid_arguments_are_rejected():
+    import torch
+    from paper_2401_16322_amd import expwave as ew
+    op, prob, U0, tdt = _case(20, 12, "float64", seed=5)
+    U = torch.zeros(prob.grid.nstate, dtype=tdt, device="cuda")
+    with pytest.raises(ew.ExpwError):
+        op.step_faber(U, 0.0, -1.0, 4, 1)
+    with pytest.raises(ew.ExpwError):
+        op.step_faber(U, 0.0, 1e-3, 0, 1)
+    with pytest.raises(ew.ExpwError):
+        op.set_source_ricker([prob.grid.npts], [1.0], 20.0, 0.05, 8)
+    with pytest.raises(ew.ExpwError):
+        op.apply(U, U)
+    with pytest.raises(ew.ExpwError):  # the free-surface stencils need 9 rows
+        type(op)(8, 8, 10.0, torch.ones(64, dtype=tdt, device="cuda"))
