@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--order", type=int, default=4, choices=[4, 8],
                     help="stencil order (4: the workloads' stencil; 8: the paper's)")
     ap.add_argument("--methods", default="faber,krylov,rk4,leapfrog")
+    ap.add_argument("--operator", default="pv", choices=["pv", "pml"],
+                    help="pv: the first-order p/v operator (the composite step); pml: "
+                         "Faber steps on the paper's PML system with a free surface")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--cpu-steps", type=int, default=4,
@@ -90,6 +93,58 @@ def parse():
     ap.add_argument("--tts-dtypes", default="f32,f64")
     ap.add_argument("--tts-repeats", type=int, default=3)
     return ap.parse_args()
+
+
+def bench_pml(args, w):
+    """Faber steps on the paper's own operator (2D PML system, free surface at
+    row 0): the workload's grid, medium, layer (delta = abc_cells h, beta_0 =
+    sigma_max), source (on v) and receivers (u); state starts at rest."""
+    import torch
+    from paper_2401_16322_amd import expwave as xw
+    if len(w.n) != 2:
+        raise SystemExit("the PML operator is 2D")
+    tdt = torch.float32 if args.dtype == "f32" else torch.float64
+    dev = torch.device("cuda:0")
+    nx, ny = w.n
+    c2 = torch.tensor(w.velocity() ** 2, dtype=tdt, device=dev)
+    op = xw.PMLOperator(nx, ny, w.h, c2, abc_cells=w.abc_cells, beta0=w.sigma_max,
+                        max_taylor_p=w.taylor_p)
+    op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+    rec = w.receiver_nodes()
+    op.set_receivers(rec)
+    m, dt = args.faber_m, w.dt
+    U = torch.zeros(4 * nx * ny, dtype=tdt, device=dev)
+    tr = torch.zeros(max(args.steps, args.warmup, 1) * len(rec), dtype=tdt, device=dev)
+    op.step_faber(U, 0.0, dt, m, args.warmup, traces=tr)
+    op.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    op.step_faber(U, args.warmup * dt, dt, m, args.steps, traces=tr)
+    e1.record()
+    op.sync()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    if not bool(torch.isfinite(U).all()):
+        raise RuntimeError("pml: non-finite wavefield")
+    npts = nx * ny
+    es = 4 if args.dtype == "f32" else 8
+    # words per point per step: first term 13, middle terms 21, last term 17
+    # (four fields: reads of v_{j-1}, v_{j-2}, the sum and c^2; writes of v_j and the sum)
+    words = 13 + 21 * (m - 2) + 17 if m >= 2 else 13
+    gbps = words * npts * es * args.steps / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "grid-pt matvecs/s", "value": npts * m * args.steps / (ms * 1e-3),
+        "unit": "grid-pt matvecs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": args.workload, "operator": "pml", "grid": [nx, ny], "faber_m": m,
+                   "dt_ms": dt * 1e3, "abc_cells": w.abc_cells, "beta0": w.sigma_max},
+        "roofline": {"bound": "hbm", "kernel": "pml_faber_term", "achieved": round(gbps, 1),
+                     "peak": 8000.0, "unit": "GB/s", "frac": round(gbps / 8000.0, 4),
+                     "traffic": None, "avg_term_us": round(ms * 1e3 / (args.steps * m), 3)},
+    }
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 def main():
@@ -108,6 +163,8 @@ def main():
     w = get_workload(args.workload)
     if args.faber_m == 0:
         args.faber_m = w.faber_m
+    if args.operator == "pml":
+        return bench_pml(args, w)
     methods = [m for m in args.methods.split(",") if m]
     tdt = torch.float32 if args.dtype == "f32" else torch.float64
     dev = torch.device("cuda:0")
