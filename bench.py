@@ -113,6 +113,14 @@ def bench_pml(args, w):
     rec = w.receiver_nodes()
     op.set_receivers(rec)
     m, dt = args.faber_m, w.dt
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 4
+        a_ = torch.ones(nel, dtype=torch.float32, device=dev)
+        b_ = torch.empty_like(a_)
+        for _ in range(3):
+            b_.copy_(a_)
+        torch.cuda.synchronize()
+        del a_, b_
     U = torch.zeros(4 * nx * ny, dtype=tdt, device=dev)
     tr = torch.zeros(max(args.steps, args.warmup, 1) * len(rec), dtype=tdt, device=dev)
     op.step_faber(U, 0.0, dt, m, args.warmup, traces=tr)

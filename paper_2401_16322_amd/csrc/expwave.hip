@@ -1426,10 +1426,15 @@ struct expw_pml {
   int taylor_p;
   int n_rec;
   const int64_t* rec_dev;
+  int path;  // 0 automatic, 1 one thread per node, 2 LDS tiles
 };
 
 namespace expw {
 namespace {
+
+// tiles (64 x 16 nodes) from which the LDS path is taken automatically: with
+// fewer, its 256-thread blocks leave the CUs short of waves
+constexpr int64_t kPmlLdsMinTiles = 2048;
 
 struct PmlLayout {
   size_t bx, bxh, by, byh, src_idx, src_amp, big, total;
@@ -1508,7 +1513,20 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   faber_coefficients(gs, c0s, c1s, dt, m, a.data());
   const int p = op->taylor_p;
   const double sc = 1.0 / (op->g.h * op->g.h);
-  const unsigned grid = grid_for(g.N);
+  const int tiles_x = static_cast<int>((op->g.nx + kPmlTX - 1) / kPmlTX);
+  const int64_t tiles = tiles_x * ((op->g.ny + kPmlTY - 1) / kPmlTY);
+  const bool lds = op->path == 2 || (op->path == 0 && tiles >= kPmlLdsMinTiles);
+  const unsigned grid = lds ? static_cast<unsigned>(tiles) : grid_for(g.N);
+  // one term: the LDS kernel on tiles or one thread per node
+  auto term = [&](const T* vp, const T* vpp, T* vout, const T* acc_in, T* acc_out, const FaberTerm<T>& c,
+                  double qj) {
+    if (lds)
+      k_pml_faber_term_lds<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, c,
+                                                               make_pml_src<T>(op, qj), tiles_x);
+    else
+      k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, c,
+                                                           make_pml_src<T>(op, qj));
+  };
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     if (op->n_src > 0) {
@@ -1525,8 +1543,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
     split_weight(a[0], &c.a_first, &c.a_first_lo);
     split_weight(a[1], &c.a_j, &c.a_j_lo);
     // (S is read with a halo here, so the sum of a one-term step goes to C first)
-    k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, S, nullptr, m == 1 ? nullptr : A, nullptr, C, c,
-                                                         make_pml_src<T>(op, q[0]));
+    term(S, nullptr, m == 1 ? nullptr : A, nullptr, C, c, q[0]);
     if (int32_t rc = check_launch("pml faber j=1")) return rc;
     if (m == 1) {
       if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
@@ -1537,8 +1554,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
       c.a_first = c.a_first_lo = T(0);
       c.cpp = static_cast<T>(2.0 * c1s);
       split_weight(a[2], &c.a_j, &c.a_j_lo);
-      k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, A, S, m == 2 ? nullptr : B, C, m == 2 ? S : C,
-                                                           c, make_pml_src<T>(op, q[1]));
+      term(A, S, m == 2 ? nullptr : B, C, m == 2 ? S : C, c, q[1]);
       if (int32_t rc = check_launch("pml faber j=2")) return rc;
       T* last = B;
       T* older = A;
@@ -1546,8 +1562,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
       for (int j = 3; j <= m; ++j) {
         split_weight(a[j], &c.a_j, &c.a_j_lo);
         const bool fin = j == m;
-        k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, last, older, fin ? nullptr : older, C,
-                                                             fin ? S : C, c, make_pml_src<T>(op, q[j - 1]));
+        term(last, older, fin ? nullptr : older, C, fin ? S : C, c, q[j - 1]);
         if (int32_t rc = check_launch("pml faber term")) return rc;
         std::swap(last, older);
       }
@@ -1608,6 +1623,7 @@ int32_t expw_pml_create(const expw_pml_grid* g, const void* c2_dev, int32_t max_
   op->n_rec = 0;
   op->rec_dev = nullptr;
   op->taylor_p = std::max(1, std::min(8, max_p));
+  op->path = 0;
   pml_surface_tables(op->d2, op->d1, op->dw);
   // damping profiles (FP64 on the host, stored in the grid dtype)
   const size_t es = g->dtype == EXPW_F32 ? 4 : 8;
@@ -1735,6 +1751,13 @@ int32_t expw_pml_step_faber(expw_pml* op, void* state, double t0, double dt, int
   if (op->g.dtype == EXPW_F32)
     return pml_faber_impl<float>(op, static_cast<float*>(state), t0, dt, m, nsteps, static_cast<float*>(traces));
   return pml_faber_impl<double>(op, static_cast<double*>(state), t0, dt, m, nsteps, static_cast<double*>(traces));
+}
+
+int32_t expw_pml_set_path(expw_pml* op, int32_t path) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (path < 0 || path > 2) return fail(EXPW_EINVAL, "path must be 0 (automatic), 1 (per node) or 2 (LDS tiles)");
+  op->path = path;
+  return EXPW_OK;
 }
 
 int32_t expw_pml_sync_status(expw_pml* op) {

@@ -40,48 +40,47 @@ __device__ __forceinline__ T pml_at(const PmlGeo<T>& g, const T* f, int i, int j
   return (i >= 0 && i < g.nx && j >= 0 && j < g.ny) ? f[static_cast<int64_t>(j) * g.nx + i] : T(0);
 }
 
-// The four components of H x at node (i, j), and x itself there.
-template <typename T>
-__device__ __forceinline__ void pml_point(const PmlGeo<T>& g, const T* x, int i, int j, T o[4],
-                                          T s[4]) {
-  const int64_t n = static_cast<int64_t>(j) * g.nx + i;
-  const T* u = x;
-  const T* v = x + g.N;
-  const T* wx = x + 2 * g.N;
-  const T* wy = x + 3 * g.N;
-  s[0] = u[n];
-  s[1] = v[n];
-  s[2] = wx[n];
-  s[3] = wy[n];
+// The four components o of H x at node (i, j), and x itself there (s), with
+// the neighbours read through accessors relative to the node, each zero
+// outside the grid: U(di, dj) = u(i + di, j + dj) for |di|, |dj| <= 4 and, at
+// the four top rows, dj up to 8 - j; WX(di) = w_x(i + di, j) for -4 <= di <= 3;
+// WY(dj) = w_y(i, j + dj) for -4 <= dj <= 3 and, at the top rows, up to 7 - j.
+template <typename T, typename FU, typename FX, typename FY>
+__device__ __forceinline__ void pml_point_acc(const PmlGeo<T>& g, int i, int j, T vc, FU&& U, FX&& WX,
+                                              FY&& WY, T o[4], T s[4]) {
+  s[0] = U(0, 0);
+  s[1] = vc;
+  s[2] = WX(0);
+  s[3] = WY(0);
   T dxx = g.d2c * s[0], dwx = T(0), dxu = T(0);
 #pragma unroll
   for (int l = 1; l <= 4; ++l) {
-    dxx += g.d2[l - 1] * (pml_at(g, u, i + l, j) + pml_at(g, u, i - l, j));
-    dwx += g.a[l - 1] * (pml_at(g, wx, i + l - 1, j) - pml_at(g, wx, i - l, j));
-    dxu += g.a[l - 1] * (pml_at(g, u, i + l, j) - pml_at(g, u, i + 1 - l, j));
+    dxx += g.d2[l - 1] * (U(l, 0) + U(-l, 0));
+    dwx += g.a[l - 1] * (WX(l - 1) - WX(-l));
+    dxu += g.a[l - 1] * (U(l, 0) - U(1 - l, 0));
   }
   T dyy = T(0), dwy = T(0), dyu = T(0);
   if (j < 4) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) dyy += g.s2[j][k] * u[static_cast<int64_t>(k) * g.nx + i];
+    for (int k = 0; k < 9; ++k) dyy += g.s2[j][k] * U(0, k - j);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) dwy += g.sw[j][k] * wy[static_cast<int64_t>(k) * g.nx + i];
+    for (int k = 0; k < 8; ++k) dwy += g.sw[j][k] * WY(k - j);
   } else {
     dyy = g.d2c * s[0];
 #pragma unroll
     for (int l = 1; l <= 4; ++l) {
-      dyy += g.d2[l - 1] * (pml_at(g, u, i, j + l) + u[n - static_cast<int64_t>(l) * g.nx]);
-      dwy += g.a[l - 1] * (wy[n - static_cast<int64_t>(l) * g.nx] - pml_at(g, wy, i, j + l - 1));
+      dyy += g.d2[l - 1] * (U(0, l) + U(0, -l));
+      dwy += g.a[l - 1] * (WY(-l) - WY(l - 1));
     }
   }
   if (j < 3) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) dyu += g.s1[j][k] * u[static_cast<int64_t>(k) * g.nx + i];
+    for (int k = 0; k < 8; ++k) dyu += g.s1[j][k] * U(0, k - j);
   } else {
 #pragma unroll
-    for (int l = 1; l <= 4; ++l)
-      dyu += g.a[l - 1] * (u[n + static_cast<int64_t>(1 - l) * g.nx] - pml_at(g, u, i, j + l));
+    for (int l = 1; l <= 4; ++l) dyu += g.a[l - 1] * (U(0, 1 - l) - U(0, l));
   }
+  const int64_t n = static_cast<int64_t>(j) * g.nx + i;
   const T bx = g.bx[i], bxh = g.bxh[i], by = g.by[j], byh = g.byh[j];
   const T c2 = g.c2[n];
   o[0] = s[1];
@@ -89,6 +88,24 @@ __device__ __forceinline__ void pml_point(const PmlGeo<T>& g, const T* x, int i,
   o[2] = (by - bxh) * (dxu * g.ih) - bxh * s[2];
   o[3] = (bx - byh) * (dyu * g.ih) - byh * s[3];
 }
+
+// The same with every read from global memory.
+template <typename T>
+__device__ __forceinline__ void pml_point(const PmlGeo<T>& g, const T* x, int i, int j, T o[4],
+                                          T s[4]) {
+  const T* u = x;
+  const T* wx = x + 2 * g.N;
+  const T* wy = x + 3 * g.N;
+  pml_point_acc(
+      g, i, j, x[g.N + static_cast<int64_t>(j) * g.nx + i],
+      [&](int di, int dj) { return pml_at(g, u, i + di, j + dj); },
+      [&](int di) { return pml_at(g, wx, i + di, j); },
+      [&](int dj) { return pml_at(g, wy, i, j + dj); }, o, s);
+}
+
+// Tiles of the LDS kernel: 64 x 16 nodes per 256-thread block (4 rows per
+// thread), with 4-cell halos of u (both axes), w_x (along x) and w_y (along y).
+constexpr int kPmlTX = 64, kPmlTY = 16, kPmlHalo = 4;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pml_apply(PmlGeo<T> g, const T* __restrict__ x,
@@ -102,10 +119,11 @@ __global__ __launch_bounds__(kBlock) void k_pml_apply(PmlGeo<T> g, const T* __re
   for (int f = 0; f < 4; ++f) y[f * g.N + n] = o[f];
 }
 
-// One Faber term (Sec. 3.2) on the PML operator, as k_faber_term: the source
-// enters the v equation. vout may alias vpp and acc_out may alias acc_in or
-// vpp; vp is read with a halo and must not alias an output; vout == nullptr
-// skips storing v_j.
+// One Faber term (Sec. 3.2) on the PML operator, as k_faber_term, one thread
+// per node with every read from global memory (the path for grids with few
+// tiles). The source enters the v equation. vout may alias vpp and acc_out may
+// alias acc_in or vpp; vp is read with a halo and must not alias an output;
+// vout == nullptr skips storing v_j.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pml_faber_term(PmlGeo<T> g, const T* vp, const T* vpp,
                                                            T* vout, const T* acc_in, T* acc_out,
@@ -124,6 +142,66 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term(PmlGeo<T> g, const T*
     if (vout) vout[e] = v;
     T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, s[f]) : acc_in[e];
     acc_out[e] = add_weighted(acc, c.a_j, c.a_j_lo, v);
+  }
+}
+
+// The same term with the stencil operands staged in LDS (the path for grids
+// with many tiles).
+// tiles_x = ceil(nx / 64); one block per 64 x 16 tile, blocks in row-major
+// tile order. vout may alias vpp and acc_out may alias acc_in or vpp; vp is
+// read with a halo and must not alias an output; vout == nullptr skips v_j.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, const T* vp, const T* vpp,
+                                                               T* vout, const T* acc_in, T* acc_out,
+                                                               FaberTerm<T> c, Src<T> src,
+                                                               int tiles_x) {
+  static_assert(kBlock == 256 && kPmlTX == 64, "4 waves, one tile column per lane");
+  constexpr int TX = kPmlTX, TY = kPmlTY, HL = kPmlHalo;
+  constexpr int UX = TX + 2 * HL, UY = TY + 2 * HL;
+  __shared__ T su[UY][UX];  // u at rows j0 - 4 .. j0 + 19, columns i0 - 4 .. i0 + 67
+  __shared__ T sx[TY][UX];  // w_x at rows j0 .. j0 + 15, columns i0 - 4 .. i0 + 67
+  __shared__ T sy[UY][TX];  // w_y at rows j0 - 4 .. j0 + 19, columns i0 .. i0 + 63
+  const int ty0 = static_cast<int>(blockIdx.x) / tiles_x;
+  const int i0 = (static_cast<int>(blockIdx.x) - ty0 * tiles_x) * TX, j0 = ty0 * TY;
+  const T* u = vp;
+  const T* wx = vp + 2 * g.N;
+  const T* wy = vp + 3 * g.N;
+  for (int e = threadIdx.x; e < UY * UX; e += kBlock) {
+    const int r = e / UX, q = e - r * UX;
+    su[r][q] = pml_at(g, u, i0 - HL + q, j0 - HL + r);
+  }
+  for (int e = threadIdx.x; e < TY * UX; e += kBlock) {
+    const int r = e / UX, q = e - r * UX;
+    sx[r][q] = pml_at(g, wx, i0 - HL + q, j0 + r);
+  }
+  for (int e = threadIdx.x; e < UY * TX; e += kBlock) {
+    const int r = e / TX, q = e - r * TX;
+    sy[r][q] = pml_at(g, wy, i0 + q, j0 - HL + r);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, tyb = threadIdx.x >> 6;
+  const int i = i0 + tx;
+#pragma unroll
+  for (int k = 0; k < TY / 4; ++k) {
+    const int ly = tyb + 4 * k, j = j0 + ly;
+    if (i >= g.nx || j >= g.ny) continue;
+    const int64_t n = static_cast<int64_t>(j) * g.nx + i;
+    T o[4], s[4];
+    pml_point_acc(
+        g, i, j, vp[g.N + n],
+        [&](int di, int dj) { return su[ly + HL + dj][tx + HL + di]; },
+        [&](int di) { return sx[ly][tx + HL + di]; },
+        [&](int dj) { return sy[ly + HL + dj][tx]; }, o, s);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int64_t e = f * g.N + n;
+      T v = o[f] * c.inv_gamma - c.c0 * s[f];
+      if (vpp) v -= c.cpp * vpp[e];
+      if (f == 1) v += src_value(src, n);
+      if (vout) vout[e] = v;
+      T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, s[f]) : acc_in[e];
+      acc_out[e] = add_weighted(acc, c.a_j, c.a_j_lo, v);
+    }
   }
 }
 

@@ -106,6 +106,7 @@ SIGNATURES = {
     "expw_pml_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
     "expw_pml_set_receivers": (_i32, [_vp, _i32, _vp]),
     "expw_pml_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
+    "expw_pml_set_path": (_i32, [_vp, _i32]),
     "expw_pml_sync_status": (_i32, [_vp]),
 }
 
@@ -748,6 +749,10 @@ class PMLOperator:
                 raise ValueError("traces must hold nsteps * n_rec values of the grid dtype")
             tp = traces.data_ptr()
         _check(load().expw_pml_step_faber(self.op, state.data_ptr(), t0, dt, m, nsteps, tp))
+
+    def set_path(self, path):
+        """0 automatic, 1 one thread per node, 2 LDS tiles."""
+        _check(load().expw_pml_set_path(self.op, int(path)))
 
     def sync(self):
         _check(load().expw_pml_sync_status(self.op))

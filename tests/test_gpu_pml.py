@@ -51,11 +51,15 @@ def test_apply_matches_oracle(dtype, nx, ny):
         assert np.max(np.abs(got[sl] - ref[sl])) <= APPLY_TOL[dtype] * max(np.max(np.abs(ref[sl])), 1e-300), f
 
 
+@pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 @pytest.mark.parametrize("m", [1, 2, 3, 12, 20])
-def test_faber_steps_with_source_and_receivers_match_oracle(dtype, m):
+def test_faber_steps_with_source_and_receivers_match_oracle(dtype, m, path):
+    """Both term kernels (one thread per node; LDS tiles, here with a ragged
+    last tile column and row and the surface rows inside the first tile row)."""
     import torch
-    op, prob, U0, tdt = _case(45, 33, dtype, seed=2)
+    op, prob, U0, tdt = _case(45 if path == 1 else 141, 33 if path == 1 else 37, dtype, seed=2)
+    op.set_path(path)
     g = prob.grid
     rec = np.array([0 * g.nx + i for i in range(0, g.nx, 4)] + [10 * g.nx + 5], dtype=np.int64)
     op.set_receivers(rec)
@@ -93,6 +97,20 @@ def test_faber_at_a_larger_grid_without_layer(dtype):
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("nx,ny", [(9, 9), (64, 16), (65, 17), (1, 40)])
+def test_lds_and_per_node_kernels_agree_to_rounding(nx, ny):
+    import torch
+    op, prob, U0, tdt = _case(nx, ny, "float64", seed=6)
+    outs = []
+    for path in (1, 2):
+        op.set_path(path)
+        U = torch.tensor(U0, dtype=tdt, device="cuda")
+        op.step_faber(U, 0.01, 1e-3, 6, 2)
+        op.sync()
+        outs.append(U.cpu().numpy())
+    assert rel_l2(outs[1], outs[0]) <= 1e-14
+
+
 def test_invalid_arguments_are_rejected():
     import torch
     from paper_2401_16322_amd import expwave as ew
@@ -106,5 +124,7 @@ def test_invalid_arguments_are_rejected():
         op.set_source_ricker([prob.grid.npts], [1.0], 20.0, 0.05, 8)
     with pytest.raises(ew.ExpwError):
         op.apply(U, U)
+    with pytest.raises(ew.ExpwError):
+        op.set_path(3)
     with pytest.raises(ew.ExpwError):  # the free-surface stencils need 9 rows
         type(op)(8, 8, 10.0, torch.ones(64, dtype=tdt, device="cuda"))
