@@ -92,3 +92,58 @@ def test_layered2d_8192x4096_full_size_fused_steps(dtype):
     """8192 x 4096, Faber degree 16 in fused passes of 4 terms, dt = 2 ms, two
     steps, a pulse and a source at the centre."""
     _check("layered2d_8192x4096", dtype, 2, 8, True)
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_pml_faber_at_8192x4096_through_the_domain_of_dependence(dtype):
+    """The PML operator at the 8192x4096 size in the bench's launch
+    configuration (LDS tiles): a term moves information at most 4 cells, so a
+    step of degree m from a displacement pulse of compact support (plus a
+    source at its centre, on v) must equal the oracle on a sub-box that holds
+    the support plus 4 m cells and keeps 10 untouched rows above it (the
+    oracle's own row 0 is a free surface, whose stencils reach 8 rows down),
+    and be exactly zero elsewhere. The sub-box lies where both layers are zero."""
+    import torch
+    from oracle import pml
+    from oracle.steppers import run
+    from paper_2401_16322_amd.expwave import PMLOperator
+    from synthetic import get_workload
+    w = get_workload("layered2d_8192x4096")
+    nx, ny = w.n
+    m, radius = w.faber_m, 20
+    cx, cy = nx // 2, ny // 2
+    reach = radius + 4 * m + 2
+    x0, x1 = cx - reach, cx + reach + 1
+    y0, y1 = cy - reach - 10, cy + reach + 1
+    assert x0 > w.abc_cells and x1 < nx - w.abc_cells and y1 < ny - w.abc_cells
+    c2 = w.velocity() ** 2
+    u0 = _pulse((nx, ny), (cx, cy), radius)
+    npts = nx * ny
+    U0 = np.zeros(4 * npts)
+    U0[:npts] = u0.ravel()
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    op = PMLOperator(nx, ny, w.h, torch.tensor(c2, dtype=tdt, device="cuda"), abc_cells=w.abc_cells,
+                     beta0=w.sigma_max, max_taylor_p=w.taylor_p)
+    op.set_source_ricker([cy * nx + cx], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+    gam, c0, c1 = op.ellipse
+    U = torch.tensor(U0, dtype=tdt, device="cuda")
+    t0 = 0.1
+    op.step_faber(U, t0, w.dt, m, 1)
+    op.sync()
+    Ug = U.cpu().numpy().astype(np.float64)
+    del U
+    gb = pml.PMLGrid(x1 - x0, y1 - y0, w.h, abc_cells=0, beta0=0.0)
+    c2b = np.ascontiguousarray(c2[y0:y1, x0:x1])
+    src = pml.PMLSources(((cy - y0) * gb.nx + (cx - x0),), (1.0,), w.f_peak, w.t_delay)
+    prob = pml.PMLProblem(gb, c2b, src)
+    sub = lambda U: np.concatenate([U[f * npts:(f + 1) * npts].reshape(ny, nx)[y0:y1, x0:x1].ravel()
+                                    for f in range(4)])
+    from paper_2401_16322_amd import expwave as ew
+    ell = ew.expw_step_ellipse(ew.EXPW_F32 if dtype == "float32" else ew.EXPW_F64, gam, c0, c1)
+    ref, _, _ = run(prob, "faber", sub(U0), t0, w.dt, 1, m=m, p=w.taylor_p, ellipse=ell)
+    inside = sub(Ug)
+    assert rel_l2(inside, ref) <= TOL[dtype]
+    # the untouched top rows of the sub-box and everything outside it are zero
+    assert np.all(inside.reshape(4, gb.ny, gb.nx)[:, :10, :] == 0.0)
+    total = float(np.sum(Ug * Ug))
+    assert abs(total - float(np.sum(inside * inside))) <= 1e-12 * total
