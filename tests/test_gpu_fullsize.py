@@ -89,8 +89,9 @@ def test_layered3d_256_full_size_faber_step(dtype):
 
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
 def test_layered2d_8192x4096_full_size_fused_steps(dtype):
-    """8192 x 4096, Faber degree 16 in fused passes of 4 terms, dt = 2 ms, two
-    steps, a pulse and a source at the centre."""
+    """8192 x 4096, Faber degree 16 in fused passes at the default depth (6
+    terms at FP32: passes of 6, 6 and 4; 4 terms at FP64), dt = 2 ms, two steps,
+    a pulse and a source at the centre."""
     _check("layered2d_8192x4096", dtype, 2, 8, True)
 
 
