@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--order", type=int, default=4, choices=[4, 8],
                     help="stencil order (4: the workloads' stencil; 8: the paper's)")
     ap.add_argument("--methods", default="faber,krylov,rk4,leapfrog")
+    ap.add_argument("--pml-path", type=int, default=0,
+                    help="PML term kernel: 0 automatic, 1 per node, 2 LDS tiles, 3 two terms per pass")
     ap.add_argument("--operator", default="pv", choices=["pv", "pml"],
                     help="pv: the first-order p/v operator (the composite step); pml: "
                          "Faber steps on the paper's PML system with a free surface")
@@ -110,6 +112,7 @@ def bench_pml(args, w):
     op = xw.PMLOperator(nx, ny, w.h, c2, abc_cells=w.abc_cells, beta0=w.sigma_max,
                         max_taylor_p=w.taylor_p)
     op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+    op.set_path(args.pml_path)
     rec = w.receiver_nodes()
     op.set_receivers(rec)
     m, dt = args.faber_m, w.dt

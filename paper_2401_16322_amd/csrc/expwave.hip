@@ -1426,7 +1426,7 @@ struct expw_pml {
   int taylor_p;
   int n_rec;
   const int64_t* rec_dev;
-  int path;  // 0 automatic, 1 one thread per node, 2 LDS tiles
+  int path;  // 0 automatic, 1 one thread per node, 2 LDS tiles, 3 pairs of terms in LDS tiles
 };
 
 namespace expw {
@@ -1451,8 +1451,8 @@ PmlLayout pml_layout(const expw_pml_grid& g) {
   L.src_idx = off; off = align_up(off + EXPW_MAX_SOURCES * sizeof(int64_t));
   L.src_amp = off; off = align_up(off + EXPW_MAX_SOURCES * es);
   L.big = off;
-  // Faber: two previous terms and the partial sum, 4 fields each
-  L.total = align_up(off + 3 * 4 * static_cast<size_t>(g.nx * g.ny) * es);
+  // Faber: two pairs of terms and the partial sum, 4 fields each
+  L.total = align_up(off + 5 * 4 * static_cast<size_t>(g.nx * g.ny) * es);
   return L;
 }
 
@@ -1498,6 +1498,60 @@ Src<T> make_pml_src(const expw_pml* op, double q) {
   return s;
 }
 
+// One Faber step of degree m >= 2 in passes of two terms (k_pml_faber_pair_lds)
+// and, for odd m, a last single term. Pass buffers: v_0 = S, then the pairs
+// (A, B) and (D, E) in turn; C holds the sum. A pass reads v_{j-1} and v_{j-2}
+// with halos, so it never writes them; a first pass that is also the last
+// (m = 2) sums into C and copies to S.
+template <typename T, typename Term>
+int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D, T* E, const double* a,
+                  const double* q, int m, double gs, double c0s, double c1s, int tiles_x, unsigned grid,
+                  Term&& term) {
+  const int64_t ns = 4 * g.N;
+  const T* vp = S;
+  const T* vpp = nullptr;
+  T* pair_out[2][2] = {{A, B}, {D, E}};
+  int which = 0;
+  int j = 1;
+  for (; j + 1 <= m; j += 2) {
+    const bool last = (j + 1 == m);
+    FaberTerm<T> t0{}, t1{};
+    t0.inv_gamma = t1.inv_gamma = static_cast<T>(1.0 / gs);
+    t0.c0 = t1.c0 = static_cast<T>(c0s);
+    t0.first = j == 1 ? 1 : 0;
+    if (j == 1) split_weight(a[0], &t0.a_first, &t0.a_first_lo);
+    t0.cpp = j == 1 ? T(0) : static_cast<T>(c1s);
+    t1.cpp = static_cast<T>(j + 1 == 2 ? 2.0 * c1s : c1s);
+    split_weight(a[j], &t0.a_j, &t0.a_j_lo);
+    split_weight(a[j + 1], &t1.a_j, &t1.a_j_lo);
+    T* o0 = (last && j + 1 == m) ? nullptr : pair_out[which][0];
+    T* o1 = (last && j + 1 == m) ? nullptr : pair_out[which][1];
+    T* acc_out = (last && vp != S) ? S : C;
+    k_pml_faber_pair_lds<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, o0, o1, j == 1 ? nullptr : C, acc_out,
+                                                             t0, t1, make_pml_src<T>(op, q[j - 1]),
+                                                             make_pml_src<T>(op, q[j]), tiles_x);
+    if (int32_t rc = check_launch("pml faber pair")) return rc;
+    if (last && acc_out == C) {
+      if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
+        return fail(EXPW_EDEVICE, "pml faber: copy failed");
+    }
+    vpp = pair_out[which][0];
+    vp = pair_out[which][1];
+    which ^= 1;
+  }
+  if (j == m) {
+    // odd m: the last term alone (v_{m-1} = vp, v_{m-2} = vpp, neither is S)
+    FaberTerm<T> c{};
+    c.inv_gamma = static_cast<T>(1.0 / gs);
+    c.c0 = static_cast<T>(c0s);
+    c.cpp = static_cast<T>(c1s);
+    split_weight(a[m], &c.a_j, &c.a_j_lo);
+    term(vp, vpp, nullptr, C, S, c, q[m - 1]);
+    if (int32_t rc = check_launch("pml faber last term")) return rc;
+  }
+  return EXPW_OK;
+}
+
 // Faber steps (Sec. 3.2) on the PML operator, one term per sweep; the ellipse
 // is the step ellipse of precision T, as for the p/v operator.
 template <typename T>
@@ -1515,8 +1569,11 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   const double sc = 1.0 / (op->g.h * op->g.h);
   const int tiles_x = static_cast<int>((op->g.nx + kPmlTX - 1) / kPmlTX);
   const int64_t tiles = tiles_x * ((op->g.ny + kPmlTY - 1) / kPmlTY);
-  const bool lds = op->path == 2 || (op->path == 0 && tiles >= kPmlLdsMinTiles);
+  const bool pairs = op->path == 3;
+  const bool lds = pairs || op->path == 2 || (op->path == 0 && tiles >= kPmlLdsMinTiles);
   const unsigned grid = lds ? static_cast<unsigned>(tiles) : grid_for(g.N);
+  T* D = C + ns;
+  T* E = D + ns;
   // one term: the LDS kernel on tiles or one thread per node
   auto term = [&](const T* vp, const T* vpp, T* vout, const T* acc_in, T* acc_out, const FaberTerm<T>& c,
                   double qj) {
@@ -1534,6 +1591,16 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
       for (int c = 0; c < p; ++c) G[c] = der[p - 1 - c];
       faber_source_scalars(gs, c0s, c1s, m, p, G.data(), q.data());
       for (int j = 0; j < m; ++j) q[j] *= sc;
+    }
+    if (pairs && m >= 2) {
+      if (int32_t rc = pml_pairs<T>(op, g, S, A, B, C, D, E, a.data(), q.data(), m, gs, c0s, c1s, tiles_x, grid,
+                                    term))
+        return rc;
+      if (traces && op->n_rec > 0) {
+        k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec, traces + st * op->n_rec);
+        if (int32_t rc = check_launch("pml gather")) return rc;
+      }
+      continue;
     }
     FaberTerm<T> c{};
     c.inv_gamma = static_cast<T>(1.0 / gs);
@@ -1755,7 +1822,8 @@ int32_t expw_pml_step_faber(expw_pml* op, void* state, double t0, double dt, int
 
 int32_t expw_pml_set_path(expw_pml* op, int32_t path) {
   if (int32_t rc = check_pml(op)) return rc;
-  if (path < 0 || path > 2) return fail(EXPW_EINVAL, "path must be 0 (automatic), 1 (per node) or 2 (LDS tiles)");
+  if (path < 0 || path > 3)
+    return fail(EXPW_EINVAL, "path must be 0 (automatic), 1 (per node), 2 (LDS tiles) or 3 (pairs of terms)");
   op->path = path;
   return EXPW_OK;
 }

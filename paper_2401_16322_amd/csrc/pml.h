@@ -205,4 +205,107 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, cons
   }
 }
 
+// Two Faber terms j and j + 1 per pass on the PML operator (temporal
+// blocking). A 256-thread block owns a 64 x 16 tile. It stages v_{j-1} on the
+// tile grown by 8 cells (u on both axes, w_x along x, w_y along y; v on the
+// tile grown by 4), computes term j on the tile grown by 4 (R1) into LDS (zero
+// outside the grid, so the next stencils see the zero values there), then term
+// j + 1 on the tile from LDS. Per tile point it writes v_j, v_{j+1} (each
+// skipped when its pointer is null) and the sum acc_in + a_j v_j + a_{j+1}
+// v_{j+1} (for c0.first: a_0 v_{j-1} + ...). vpp (v_{j-2}, null for j = 1)
+// is read on R1, so no output may alias vp or vpp; acc_out may alias acc_in.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pml_faber_pair_lds(PmlGeo<T> g, const T* vp, const T* vpp,
+                                                               T* out0, T* out1, const T* acc_in,
+                                                               T* acc_out, FaberTerm<T> c0,
+                                                               FaberTerm<T> c1, Src<T> s0, Src<T> s1,
+                                                               int tiles_x) {
+  static_assert(kBlock == 256 && kPmlTX == 64, "4 waves, one tile column per lane");
+  constexpr int TX = kPmlTX, TY = kPmlTY;
+  constexpr int AX = TX + 16, AY = TY + 16;  // tile grown by 8
+  constexpr int BX = TX + 8, BY = TY + 8;    // tile grown by 4 (R1)
+  __shared__ T au[AY][AX];   // v_{j-1}: u on the tile grown by 8
+  __shared__ T av[BY][BX];   //          v on R1
+  __shared__ T ax[BY][AX];   //          w_x on R1's rows, columns grown by 8
+  __shared__ T ay[AY][BX];   //          w_y on R1's columns, rows grown by 8
+  __shared__ T bu[BY][BX], bv[BY][BX], bx[BY][BX], by[BY][BX];  // v_j on R1
+  const int ty0 = static_cast<int>(blockIdx.x) / tiles_x;
+  const int i0 = (static_cast<int>(blockIdx.x) - ty0 * tiles_x) * TX, j0 = ty0 * TY;
+  const T* u = vp;
+  const T* v = vp + g.N;
+  const T* wx = vp + 2 * g.N;
+  const T* wy = vp + 3 * g.N;
+  for (int e = threadIdx.x; e < AY * AX; e += kBlock) {
+    const int r = e / AX, q = e - r * AX;
+    au[r][q] = pml_at(g, u, i0 - 8 + q, j0 - 8 + r);
+  }
+  for (int e = threadIdx.x; e < BY * BX; e += kBlock) {
+    const int r = e / BX, q = e - r * BX;
+    av[r][q] = pml_at(g, v, i0 - 4 + q, j0 - 4 + r);
+  }
+  for (int e = threadIdx.x; e < BY * AX; e += kBlock) {
+    const int r = e / AX, q = e - r * AX;
+    ax[r][q] = pml_at(g, wx, i0 - 8 + q, j0 - 4 + r);
+  }
+  for (int e = threadIdx.x; e < AY * BX; e += kBlock) {
+    const int r = e / BX, q = e - r * BX;
+    ay[r][q] = pml_at(g, wy, i0 - 4 + q, j0 - 8 + r);
+  }
+  __syncthreads();
+  // term j on R1: point (r, q) is node (i0 - 4 + q, j0 - 4 + r)
+  for (int e = threadIdx.x; e < BY * BX; e += kBlock) {
+    const int r = e / BX, q = e - r * BX;
+    const int i = i0 - 4 + q, j = j0 - 4 + r;
+    T f[4] = {T(0), T(0), T(0), T(0)};
+    if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+      const int64_t n = static_cast<int64_t>(j) * g.nx + i;
+      T o[4], sc[4];
+      pml_point_acc(
+          g, i, j, av[r][q],
+          [&](int di, int dj) { return au[r + 4 + dj][q + 4 + di]; },
+          [&](int di) { return ax[r][q + 4 + di]; },
+          [&](int dj) { return ay[r + 4 + dj][q]; }, o, sc);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        T val = o[k] * c0.inv_gamma - c0.c0 * sc[k];
+        if (vpp) val -= c0.cpp * vpp[k * g.N + n];
+        if (k == 1) val += src_value(s0, n);
+        f[k] = val;
+      }
+    }
+    bu[r][q] = f[0];
+    bv[r][q] = f[1];
+    bx[r][q] = f[2];
+    by[r][q] = f[3];
+  }
+  __syncthreads();
+  // term j + 1 on the tile; v_{j-1} there is the older term
+  const int tx = threadIdx.x & 63, tyb = threadIdx.x >> 6;
+  const int i = i0 + tx;
+#pragma unroll
+  for (int k4 = 0; k4 < TY / 4; ++k4) {
+    const int ly = tyb + 4 * k4, j = j0 + ly;
+    if (i >= g.nx || j >= g.ny) continue;
+    const int64_t n = static_cast<int64_t>(j) * g.nx + i;
+    T o[4], sc[4];
+    pml_point_acc(
+        g, i, j, bv[ly + 4][tx + 4],
+        [&](int di, int dj) { return bu[ly + 4 + dj][tx + 4 + di]; },
+        [&](int di) { return bx[ly + 4][tx + 4 + di]; },
+        [&](int dj) { return by[ly + 4 + dj][tx + 4]; }, o, sc);
+    const T old[4] = {au[ly + 8][tx + 8], av[ly + 4][tx + 4], ax[ly + 4][tx + 8], ay[ly + 8][tx + 4]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t e = k * g.N + n;
+      T val = o[k] * c1.inv_gamma - c1.c0 * sc[k] - c1.cpp * old[k];
+      if (k == 1) val += src_value(s1, n);
+      if (out0) out0[e] = sc[k];
+      if (out1) out1[e] = val;
+      T acc = c0.first ? add_weighted(T(0), c0.a_first, c0.a_first_lo, old[k]) : acc_in[e];
+      acc = add_weighted(acc, c0.a_j, c0.a_j_lo, sc[k]);
+      acc_out[e] = add_weighted(acc, c1.a_j, c1.a_j_lo, val);
+    }
+  }
+}
+
 }  // namespace expw

@@ -51,12 +51,14 @@ def test_apply_matches_oracle(dtype, nx, ny):
         assert np.max(np.abs(got[sl] - ref[sl])) <= APPLY_TOL[dtype] * max(np.max(np.abs(ref[sl])), 1e-300), f
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 @pytest.mark.parametrize("m", [1, 2, 3, 12, 20])
 def test_faber_steps_with_source_and_receivers_match_oracle(dtype, m, path):
-    """Both term kernels (one thread per node; LDS tiles, here with a ragged
-    last tile column and row and the surface rows inside the first tile row)."""
+    """Every term kernel: one thread per node; LDS tiles; pairs of terms per
+    pass (m = 2: one pass that is first and last; odd m: a last single term),
+    the tiled ones here with a ragged last tile column and row and the surface
+    rows inside the first tile row."""
     import torch
     op, prob, U0, tdt = _case(45 if path == 1 else 141, 33 if path == 1 else 37, dtype, seed=2)
     op.set_path(path)
@@ -102,13 +104,15 @@ def test_lds_and_per_node_kernels_agree_to_rounding(nx, ny):
     import torch
     op, prob, U0, tdt = _case(nx, ny, "float64", seed=6)
     outs = []
-    for path in (1, 2):
+    for path in (1, 2, 3):
         op.set_path(path)
-        U = torch.tensor(U0, dtype=tdt, device="cuda")
-        op.step_faber(U, 0.01, 1e-3, 6, 2)
-        op.sync()
-        outs.append(U.cpu().numpy())
-    assert rel_l2(outs[1], outs[0]) <= 1e-14
+        for m in (6, 7):
+            U = torch.tensor(U0, dtype=tdt, device="cuda")
+            op.step_faber(U, 0.01, 1e-3, m, 2)
+            op.sync()
+            outs.append(U.cpu().numpy())
+    for k in range(2, 6):
+        assert rel_l2(outs[k], outs[k % 2]) <= 1e-14
 
 
 def test_invalid_arguments_are_rejected():
@@ -125,6 +129,6 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(ew.ExpwError):
         op.apply(U, U)
     with pytest.raises(ew.ExpwError):
-        op.set_path(3)
+        op.set_path(4)
     with pytest.raises(ew.ExpwError):  # the free-surface stencils need 9 rows
         type(op)(8, 8, 10.0, torch.ones(64, dtype=tdt, device="cuda"))
