@@ -188,6 +188,20 @@ int32_t expw_set_source_ricker(expw_op* op, int32_t n_src, const int64_t* node_i
                                const double* amp_host, double f_peak, double t_delay,
                                int32_t taylor_p);
 
+/* A tabulated source time function (Sec. 3.2, augmented matrix: the source
+ * over a step is its Taylor polynomial): point sources at node_idx_host with
+ * amplitudes amp_host, as for expw_set_source_ricker, and gder_host
+ * (nsteps x taylor_p, row-major, host) holding g^(k)(t_n), k = 0..taylor_p-1,
+ * for step n = 0..nsteps-1 of each following step call (step n of a call uses
+ * row n; a call with more steps than rows fails with EXPW_EINVAL; an adjoint
+ * step uses row 0). Faber and Krylov use a row as the columns of W; RK4 and
+ * leap-frog evaluate its Taylor polynomial at their stage times. The table is
+ * copied; it stays until the next source call. Batches reject it
+ * (EXPW_EUNSUPPORTED). n_src = 0 removes the sources. */
+int32_t expw_set_source_taylor(expw_op* op, int32_t n_src, const int64_t* node_idx_host,
+                               const double* amp_host, int32_t taylor_p, int64_t nsteps,
+                               const double* gder_host);
+
 /* Receivers: n_rec flat pressure-node indices in a caller-owned device int64
  * array (validated once, synchronizes). After every step the pressure at the
  * receivers is written to traces[step * n_rec + r] when a step call is given

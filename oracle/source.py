@@ -21,6 +21,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
+from math import factorial
+
 import numpy as np
 
 
@@ -77,6 +79,41 @@ class PointSources:
     def w_columns(self, t, p):
         """Row vector G with W = e_src G: [g^(p-1)(t), ..., g(t)]."""
         return ricker_derivatives(t, self.f_peak, self.t_delay, p)[::-1].copy()
+
+
+class TaylorTableSource:
+    """Point sources with a tabulated time function: row n of table holds
+    g^(k)(t_n), k = 0..p-1 (Sec. 3.2, augmented matrix: over a step the source
+    is its Taylor polynomial). bind(n, t_n) selects the step; forcing evaluates
+    the row's polynomial at t - t_n, and w_columns returns the row in the
+    column order of W (highest derivative first)."""
+
+    def __init__(self, nodes, amps, table):
+        self.nodes = tuple(int(v) for v in nodes)
+        self.amps = tuple(float(a) for a in amps)
+        self.table = np.asarray(table, dtype=np.float64)
+        self.step, self.t_n = 0, 0.0
+
+    def bind(self, n, t_n):
+        self.step, self.t_n = int(n), float(t_n)
+
+    def strengths(self, grid):
+        return np.asarray(self.amps, dtype=np.float64) / grid.h ** grid.ndim
+
+    def value(self, t):
+        tau = t - self.t_n
+        row = self.table[self.step]
+        return float(sum(row[k] * tau ** k / factorial(k) for k in range(row.size)))
+
+    def forcing(self, grid, t):
+        s = np.zeros(grid.nstate)
+        g = self.value(t)
+        for node, st in zip(self.nodes, self.strengths(grid)):
+            s[node] += st * g
+        return s
+
+    def w_columns(self, t, p):
+        return self.table[self.step, :p][::-1].copy()
 
 
 def apply_W(grid, src, G, tau):

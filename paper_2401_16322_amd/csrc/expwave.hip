@@ -40,6 +40,11 @@ struct expw_op {
   int64_t src_lo, src_hi;
   double f_peak, t_delay;
   int taylor_p;
+  // a tabulated source (expw_set_source_taylor): row n holds g^(k)(t_n),
+  // k = 0..taylor_p-1, for step n of the next step call
+  int src_table;
+  std::vector<double> src_rows;
+  int64_t src_nrows;
   // receivers
   int n_rec;
   const int64_t* rec_dev;
@@ -209,6 +214,42 @@ unsigned red_grid_for(int64_t n) {
 
 double src_scale(const expw_op* op) { return 1.0 / std::pow(op->g.h, op->g.ndim); }
 
+// g^(k)(t_n), k = 0..p-1, for step st of a call (time t_n = t): the Ricker
+// wavelet, or row st of the table
+void source_derivs(const expw_op* op, int64_t st, double t, int p, double* der) {
+  if (op->src_table) {
+    const double* row = op->src_rows.data() + st * op->taylor_p;
+    for (int k = 0; k < p; ++k) der[k] = row[k];
+  } else {
+    ricker_derivatives(t, op->f_peak, op->t_delay, p, der);
+  }
+}
+
+// g(t_n + tau) for step st: the Ricker wavelet, or the table row's Taylor
+// polynomial (Sec. 3.2: the source over a step is its Taylor polynomial)
+double source_value(const expw_op* op, int64_t st, double t, double tau) {
+  if (!op->src_table) {
+    double g0;
+    ricker_derivatives(t + tau, op->f_peak, op->t_delay, 1, &g0);
+    return g0;
+  }
+  const double* row = op->src_rows.data() + st * op->taylor_p;
+  double acc = 0.0, term = 1.0;
+  for (int k = 0; k < op->taylor_p; ++k) {
+    acc += row[k] * term;
+    term *= tau / (k + 1);
+  }
+  return acc;
+}
+
+// a step call of nsteps steps needs as many table rows
+int32_t check_source_rows(const expw_op* op, int64_t nsteps) {
+  if (op->n_src > 0 && op->src_table && nsteps > op->src_nrows)
+    return fail(EXPW_EINVAL, "the source table has %lld rows, the call needs %lld", (long long)op->src_nrows,
+                (long long)nsteps);
+  return EXPW_OK;
+}
+
 
 template <typename T>
 int32_t gather(expw_op* op, const T* S, T* traces, int64_t step) {
@@ -312,7 +353,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     if (op->n_src > 0) {
-      ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
+      source_derivs(op, st, t, p, der.data());
       for (int c = 0; c < p; ++c) G[c] = der[p - 1 - c];
       faber_source_scalars(el.gamma, el.c0, el.c1, m, p, G.data(), q.data());
       const double sc = src_scale(op);
@@ -367,16 +408,18 @@ int32_t rk4_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T* tra
   const unsigned grid = grid_for(g.N);
   const double sc = src_scale(op);
   const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
-  double der[1];
+  int64_t cur = 0;  // the step being taken
+  double tn = t0;
   auto srcq = [&](double t) {
     if (op->n_src == 0) return make_src<T>(op, 0.0);
-    ricker_derivatives(t, op->f_peak, op->t_delay, 1, der);
-    return make_src<T>(op, der[0] * sc);
+    return make_src<T>(op, source_value(op, cur, tn, t - tn) * sc);
   };
   const T h2 = static_cast<T>(0.5 * dt), h1 = static_cast<T>(dt), s6 = static_cast<T>(dt / 6.0),
           s3 = static_cast<T>(dt / 3.0);
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
+    cur = st;
+    tn = t;
     // words per point: stage 1 reads u (nf) + c^2, writes y, sum (2 nf); stages 2-3 read
     // y, u, sum (3 nf) + c^2, write y, sum (2 nf); stage 4 reads y, sum + c^2, writes u
     launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, S, nullptr, Abuf, Cbuf, h2, s6, srcq(t));
@@ -396,16 +439,12 @@ int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T
   const unsigned grid = grid_for(g.N);
   const double sc = src_scale(op);
   const double pb = static_cast<double>(g.N) * sizeof(T);
-  double der[1];
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     // velocity: reads p and v (1 + d), writes v (d); pressure: reads p, v, c^2 (d + 2), writes p
     launch_timed(&op->prof, op->stream, EXPW_KERNEL_LEAPFROG_V, (1 + 2 * DIM) * pb, k_lf_v<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, static_cast<T>(dt));
     double q = 0.0;
-    if (op->n_src > 0) {
-      ricker_derivatives(t + 0.5 * dt, op->f_peak, op->t_delay, 1, der);
-      q = dt * der[0] * sc;
-    }
+    if (op->n_src > 0) q = dt * source_value(op, st, t, 0.5 * dt) * sc;
     launch_timed(&op->prof, op->stream, EXPW_KERNEL_LEAPFROG_P, (DIM + 3) * pb, k_lf_p<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, static_cast<T>(dt), make_src<T>(op, q));
     int32_t rc = check_launch("leapfrog");
     if (rc != EXPW_OK) return rc;
@@ -518,7 +557,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     if (p > 0) {
-      ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
+      source_derivs(op, st, t, p, der.data());
       const double sc = src_scale(op);
       for (int c = 0; c < p; ++c) ks.G[c] = der[p - 1 - c] * sc;
     }
@@ -623,7 +662,7 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
   faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a.data());
   const int p = op->taylor_p;
   if (op->n_src > 0) {
-    ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
+    source_derivs(op, 0, t, p, der.data());  // a table's row 0: one step per call
     for (int c = 0; c < p; ++c) G[c] = der[p - 1 - c];
     faber_source_scalars(el.gamma, el.c0, el.c1, m, p, G.data(), q.data());
     const double sc = src_scale(op);
@@ -908,7 +947,7 @@ int32_t check_step_args(const expw_op* op, const void* state, double dt, int64_t
   if (!state) return fail(EXPW_EINVAL, "state is NULL");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(EXPW_EINVAL, "dt must be positive and finite");
   if (nsteps < 0) return fail(EXPW_EINVAL, "nsteps must be >= 0");
-  return EXPW_OK;
+  return check_source_rows(op, nsteps);
 }
 
 }  // namespace
@@ -958,6 +997,8 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->off_big = L.big;
   op->naug_pad = L.naug_pad;
   op->n_src = 0;
+  op->src_table = 0;
+  op->src_nrows = 0;
   op->n_rec = 0;
   op->rec_dev = nullptr;
   op->taylor_p = std::max(1, std::min(8, max_p));
@@ -1136,6 +1177,8 @@ int32_t expw_batch_create(expw_op* const* ops, int32_t n_ops, const int32_t* m, 
     if (gi.dtype != g0.dtype || gi.ndim != g0.ndim || gi.order != g0.order || gi.bc != g0.bc)
       return fail(EXPW_EINVAL, "shot %d: dtype, ndim, order and bc must match shot 0", i);
     if (m[i] < 2 || m[i] > kBatchMaxM) return fail(EXPW_EINVAL, "shot %d: degree must be in [2, %d]", i, kBatchMaxM);
+    if (ops[i]->n_src > 0 && ops[i]->src_table)
+      return fail(EXPW_EUNSUPPORTED, "shot %d: batches form the Ricker wavelet on the device; a tabulated source is not supported", i);
     if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(EXPW_EINVAL, "shot %d: dt must be positive", i);
     for (int k = 0; k < i; ++k)
       if (ops[k] == ops[i] || states_dev[k] == states_dev[i])
@@ -1243,6 +1286,27 @@ int32_t expw_set_source_ricker(expw_op* op, int32_t n_src, const int64_t* idx, c
   op->f_peak = f_peak;
   op->t_delay = t_delay;
   op->taylor_p = taylor_p;
+  op->src_table = 0;
+  return EXPW_OK;
+}
+
+int32_t expw_set_source_taylor(expw_op* op, int32_t n_src, const int64_t* idx, const double* amp,
+                               int32_t taylor_p, int64_t nsteps, const double* gder) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (n_src > 0) {
+    if (nsteps < 1) return fail(EXPW_EINVAL, "nsteps must be >= 1");
+    if (!gder) return fail(EXPW_EINVAL, "gder is NULL");
+    if (taylor_p < 1 || taylor_p > op->pmax)
+      return fail(EXPW_EINVAL, "taylor_p must be in [1, %d] (max_taylor_p at create)", op->pmax);
+    for (int64_t i = 0; i < nsteps * taylor_p; ++i)
+      if (!std::isfinite(gder[i])) return fail(EXPW_EINVAL, "gder[%lld] is not finite", (long long)i);
+  }
+  // the points and amplitudes as for the Ricker source (its checks and upload)
+  if (int32_t rc = expw_set_source_ricker(op, n_src, idx, amp, 1.0, 0.0, n_src > 0 ? taylor_p : 1)) return rc;
+  if (n_src == 0) return EXPW_OK;
+  op->src_rows.assign(gder, gder + nsteps * taylor_p);
+  op->src_nrows = nsteps;
+  op->src_table = 1;
   return EXPW_OK;
 }
 

@@ -76,6 +76,7 @@ SIGNATURES = {
     "expw_faber_adjoint_step": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
     "expw_inject_receivers": (_i32, [_vp, _vp, _dbl, _vp]),
     "expw_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
+    "expw_set_source_taylor": (_i32, [_vp, _i32, _pi64, _pd, _i32, _i64, _pd]),
     "expw_set_receivers": (_i32, [_vp, _i32, _vp]),
     "expw_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_faber_dense": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp, _vp]),
@@ -293,6 +294,19 @@ def expw_set_source_ricker(op, nodes, amps, f_peak, t_delay, taylor_p):
         raise ValueError("nodes and amps differ in length")
     _check(load().expw_set_source_ricker(op, nodes.size, nodes.ctypes.data_as(_pi64), _dptr(amps),
                                          f_peak, t_delay, taylor_p))
+
+
+def expw_set_source_taylor(op, nodes, amps, gder):
+    """gder: (nsteps, taylor_p) array of g^(k)(t_n) for step n of each following call."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    amps = np.ascontiguousarray(amps, dtype=np.float64)
+    gder = np.ascontiguousarray(gder, dtype=np.float64)
+    if nodes.size != amps.size:
+        raise ValueError("nodes and amps differ in length")
+    if gder.ndim != 2:
+        raise ValueError("gder must be (nsteps, taylor_p)")
+    _check(load().expw_set_source_taylor(op, nodes.size, nodes.ctypes.data_as(_pi64), _dptr(amps),
+                                         gder.shape[1], gder.shape[0], _dptr(gder)))
 
 
 def expw_set_receivers(op, n_rec, idx_ptr):
@@ -538,6 +552,11 @@ class Operator:
     def set_source_ricker(self, nodes, amps, f_peak, t_delay, taylor_p=8):
         self._sync_stream()
         expw_set_source_ricker(self.op, nodes, amps, f_peak, t_delay, taylor_p)
+
+    def set_source_taylor(self, nodes, amps, gder):
+        """A tabulated source: gder[n, k] = g^(k)(t_n) for step n of each following call."""
+        self._sync_stream()
+        expw_set_source_taylor(self.op, nodes, amps, gder)
 
     def set_receivers(self, nodes):
         torch = self._torch
