@@ -59,7 +59,7 @@ typedef enum {
   EXPW_EINVAL = -1,       /* invalid argument (message says which) */
   EXPW_ENOMEM = -2,       /* caller-supplied workspace too small */
   EXPW_EDEVICE = -3,      /* HIP runtime or launch failure */
-  EXPW_ENONFINITE = -4,   /* NaN/Inf in c^2 */
+  EXPW_ENONFINITE = -4,   /* NaN/Inf in c^2, or in a state (guard) */
   EXPW_EUNSUPPORTED = -5  /* valid but not supported combination */
 } expw_status;
 
@@ -300,8 +300,14 @@ int32_t expw_step_leapfrog(expw_op* op, void* state_dev, double t0, double dt, i
 
 /* Synchronizes the stream and reports a pending device error (including a
  * grid barrier of the persistent Arnoldi kernel that exceeded its bounded
- * wait). */
+ * wait), then a state the non-finite guard caught (EXPW_ENONFINITE, reported
+ * once). */
 int32_t expw_sync_status(expw_op* op);
+
+/* Optional non-finite guard: on != 0 checks the state for NaN and infinite
+ * values after every step of every step call (one extra read of the state per
+ * step); a hit surfaces as EXPW_ENONFINITE at the next expw_sync_status. */
+int32_t expw_set_guard(expw_op* op, int32_t on);
 
 /* Effective dimension and beta of the last Krylov step (host values;
  * synchronizes when the step ran its small exponential on the device). */

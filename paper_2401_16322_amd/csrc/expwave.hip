@@ -48,6 +48,8 @@ struct expw_op {
   // receivers
   int n_rec;
   const int64_t* rec_dev;
+  // non-finite guard after every step (expw_set_guard)
+  int guard;
   // tuning
   int fuse;
   // Krylov: small exponential on the device (0) or the host (1); last step info
@@ -251,6 +253,19 @@ int32_t check_source_rows(const expw_op* op, int64_t nsteps) {
 }
 
 
+// the non-finite flag of the guard (an int of the Krylov scalar area, zeroed at create)
+int* guard_flag(const expw_op* op) {
+  return reinterpret_cast<int*>(op->ws + op->off_kry + 136 * sizeof(double)) + 9;
+}
+
+// the optional non-finite guard on a state of ns values, after a step
+template <typename T>
+int32_t guard_state(expw_op* op, const T* S, int64_t ns) {
+  if (!op->guard) return EXPW_OK;
+  k_guard<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, ns, guard_flag(op));
+  return check_launch("guard");
+}
+
 template <typename T>
 int32_t gather(expw_op* op, const T* S, T* traces, int64_t step) {
   if (!traces || op->n_rec == 0) return EXPW_OK;
@@ -392,6 +407,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
     }
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+    if ((rc = guard_state<T>(op, S, (DIM + 1) * g.N)) != EXPW_OK) return rc;
   }
   return EXPW_OK;
 }
@@ -429,6 +445,7 @@ int32_t rk4_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T* tra
     int32_t rc = check_launch("rk4 stage");
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+    if ((rc = guard_state<T>(op, S, (DIM + 1) * g.N)) != EXPW_OK) return rc;
   }
   return EXPW_OK;
 }
@@ -449,6 +466,7 @@ int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T
     int32_t rc = check_launch("leapfrog");
     if (rc != EXPW_OK) return rc;
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+    if ((rc = guard_state<T>(op, S, (DIM + 1) * g.N)) != EXPW_OK) return rc;
   }
   return EXPW_OK;
 }
@@ -629,6 +647,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
       }
     }
     if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+    if ((rc = guard_state<T>(op, S, (DIM + 1) * g.N)) != EXPW_OK) return rc;
   }
   return EXPW_OK;
 }
@@ -999,6 +1018,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->n_src = 0;
   op->src_table = 0;
   op->src_nrows = 0;
+  op->guard = 0;
   op->n_rec = 0;
   op->rec_dev = nullptr;
   op->taylor_p = std::max(1, std::min(8, max_p));
@@ -1290,6 +1310,12 @@ int32_t expw_set_source_ricker(expw_op* op, int32_t n_src, const int64_t* idx, c
   return EXPW_OK;
 }
 
+int32_t expw_set_guard(expw_op* op, int32_t on) {
+  if (int32_t rc = check_op(op)) return rc;
+  op->guard = on != 0;
+  return EXPW_OK;
+}
+
 int32_t expw_set_source_taylor(expw_op* op, int32_t n_src, const int64_t* idx, const double* amp,
                                int32_t taylor_p, int64_t nsteps, const double* gder) {
   if (int32_t rc = check_op(op)) return rc;
@@ -1409,11 +1435,17 @@ int32_t expw_sync_status(expw_op* op) {
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e));
   const hipError_t e2 = hipGetLastError();
   if (e2 != hipSuccess) return fail(EXPW_EDEVICE, "device error: %s", hipGetErrorString(e2));
-  int err = 0;
+  int flags[2] = {0, 0};  // Arnoldi barrier time-out, non-finite guard
   const char* flag = op->ws + op->off_kry + 136 * sizeof(double) + 8 * sizeof(int);
-  if (hipMemcpy(&err, flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(flags, flag, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(EXPW_EDEVICE, "status read failed");
-  if (err) return fail(EXPW_EDEVICE, "a grid barrier of the persistent Arnoldi kernel timed out");
+  if (flags[0]) return fail(EXPW_EDEVICE, "a grid barrier of the persistent Arnoldi kernel timed out");
+  if (flags[1]) {
+    // reported once: the flag is cleared for the next steps
+    k_zero_u32<<<1, 64, 0, op->stream>>>(reinterpret_cast<unsigned*>(guard_flag(op)), 1);
+    if (hipStreamSynchronize(op->stream) != hipSuccess) return fail(EXPW_EDEVICE, "guard reset failed");
+    return fail(EXPW_ENONFINITE, "a state held a NaN or infinite value after a step (guard)");
+  }
   return EXPW_OK;
 }
 

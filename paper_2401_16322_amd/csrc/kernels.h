@@ -540,4 +540,15 @@ __global__ __launch_bounds__(kBlock) void k_kry_expm(const double* __restrict__ 
   if (tid == 0) *keff_out = n;
 }
 
+// Non-finite guard: sets *flag when any of the n values is NaN or infinite
+// (vector atomic store; the flag is only ever set here).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_guard(const T* __restrict__ x, int64_t n, int* flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    bad = bad || !isfinite(x[i]);
+  if (bad) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace expw

@@ -77,6 +77,7 @@ SIGNATURES = {
     "expw_inject_receivers": (_i32, [_vp, _vp, _dbl, _vp]),
     "expw_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
     "expw_set_source_taylor": (_i32, [_vp, _i32, _pi64, _pd, _i32, _i64, _pd]),
+    "expw_set_guard": (_i32, [_vp, _i32]),
     "expw_set_receivers": (_i32, [_vp, _i32, _vp]),
     "expw_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_faber_dense": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp, _vp]),
@@ -552,6 +553,10 @@ class Operator:
     def set_source_ricker(self, nodes, amps, f_peak, t_delay, taylor_p=8):
         self._sync_stream()
         expw_set_source_ricker(self.op, nodes, amps, f_peak, t_delay, taylor_p)
+
+    def set_guard(self, on=True):
+        """Check every state for NaN/Inf after each step; sync() then raises."""
+        _check(load().expw_set_guard(self.op, int(bool(on))))
 
     def set_source_taylor(self, nodes, amps, gder):
         """A tabulated source: gder[n, k] = g^(k)(t_n) for step n of each following call."""

@@ -66,3 +66,34 @@ def test_a_call_longer_than_the_table_is_rejected():
     assert e.value.status == ew.EXPW_EINVAL
     case.op.step_faber(U, 0.0, 1e-3, 6, 2)
     case.op.sync()
+
+
+@pytest.mark.parametrize("method", ["faber", "krylov", "rk4", "leapfrog"])
+def test_non_finite_guard_reports_at_the_next_sync(method):
+    """One NaN entry in the state: with the guard on, the next sync reports
+    EXPW_ENONFINITE once; with it off, steps run and sync reports nothing."""
+    import math
+    from paper_2401_16322_amd import expwave as ew
+    case = make_case((24, 18), "float64", src=True, seed=25, max_k=8)
+    run = {"faber": lambda U: case.op.step_faber(U, 0.0, 1e-3, 6, 2),
+           "krylov": lambda U: case.op.step_krylov(U, 0.0, 1e-3, 6, 2),
+           "rk4": lambda U: case.op.step_rk4(U, 0.0, 1e-3, 2),
+           "leapfrog": lambda U: case.op.step_leapfrog(U, 0.0, 1e-3, 2)}[method]
+    U0 = np.array(case.U0)
+    U0[37] = math.nan
+    case.op.set_guard(True)
+    U = to_dev(case, U0)
+    run(U)
+    with pytest.raises(ew.ExpwError) as e:
+        case.op.sync()
+    assert e.value.status == ew.EXPW_ENONFINITE
+    case.op.sync()  # reported once
+    # a finite state passes the guard
+    U = to_dev(case, case.U0)
+    run(U)
+    case.op.sync()
+    # guard off: the NaN goes through unreported
+    case.op.set_guard(False)
+    U = to_dev(case, U0)
+    run(U)
+    case.op.sync()
