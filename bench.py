@@ -140,18 +140,32 @@ def bench_pml(args, w):
         raise RuntimeError("pml: non-finite wavefield")
     npts = nx * ny
     es = 4 if args.dtype == "f32" else 8
-    # words per point per step: first term 13, middle terms 21, last term 17
-    # (four fields: reads of v_{j-1}, v_{j-2}, the sum and c^2; writes of v_j and the sum)
-    words = 13 + 21 * (m - 2) + 17 if m >= 2 else 13
+    # algorithmic words per point per step (four fields: reads of v_{j-1}, v_{j-2}
+    # and the sum, and c^2; writes of the new terms and the sum), by term kernel
+    path = op.path_for(m)
+    if path == 3:
+        # passes of two terms: first pass reads v_0 and c^2 and writes v_1, v_2 and
+        # the sum (17; 9 if it is also the last); middle passes 13 + 12 = 25; a
+        # last pass 13 + 4 = 17; for odd m a last single term 13 + 4 = 17
+        npair, odd = m // 2, m % 2
+        if npair == 1 and not odd:
+            words = 9
+        else:
+            words = 17 + 25 * (npair - 2 + odd) + 17
+    else:
+        # one term per sweep: first term 13, middle terms 21, last term 17
+        words = 13 + 21 * (m - 2) + 17 if m >= 2 else 13
     gbps = words * npts * es * args.steps / (ms * 1e-3) / 1e9
     out = {
         "metric": "grid-pt matvecs/s", "value": npts * m * args.steps / (ms * 1e-3),
         "unit": "grid-pt matvecs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": args.workload, "operator": "pml", "grid": [nx, ny], "faber_m": m,
+        "config": {"workload": args.workload, "operator": "pml", "term_kernel": path,
+                   "grid": [nx, ny], "faber_m": m,
                    "dt_ms": dt * 1e3, "abc_cells": w.abc_cells, "beta0": w.sigma_max},
-        "roofline": {"bound": "hbm", "kernel": "pml_faber_term", "achieved": round(gbps, 1),
+        "roofline": {"bound": "hbm", "kernel": "pml_faber_pair" if path == 3 else "pml_faber_term",
+                     "achieved": round(gbps, 1),
                      "peak": 8000.0, "unit": "GB/s", "frac": round(gbps / 8000.0, 4),
                      "traffic": None, "avg_term_us": round(ms * 1e3 / (args.steps * m), 3)},
     }

@@ -433,11 +433,15 @@ int32_t expw_pml_set_receivers(expw_pml* op, int32_t n_rec, const int64_t* node_
 int32_t expw_pml_step_faber(expw_pml* op, void* state_dev, double t0, double dt, int32_t m,
                             int64_t nsteps, void* traces_dev);
 
-/* Kernel of the Faber terms: 0 = automatic (LDS tiles of 64 x 16 nodes once the
- * grid has at least 2048 of them, else one thread per node), 1 = one thread
- * per node, 2 = LDS tiles, 3 = two terms per pass on LDS tiles (temporal
- * blocking; an odd last term alone). Results agree to rounding. */
+/* Kernel of the Faber terms: 0 = automatic (FP32: two terms per pass; FP64:
+ * LDS tiles of 64 x 16 nodes once the grid has at least 2048 of them, else one
+ * thread per node), 1 = one thread per node, 2 = LDS tiles, 3 = two terms per
+ * pass on LDS tiles (temporal blocking; an odd last term alone). Results agree
+ * to rounding. */
 int32_t expw_pml_set_path(expw_pml* op, int32_t path);
+
+/* The path (1, 2 or 3) a step of degree m takes under the current setting. */
+int32_t expw_pml_path_for(const expw_pml* op, int32_t m, int32_t* path);
 
 /* Synchronizes the stream and reports device errors. */
 int32_t expw_pml_sync_status(expw_pml* op);

@@ -1532,6 +1532,16 @@ namespace {
 // fewer, its 256-thread blocks leave the CUs short of waves
 constexpr int64_t kPmlLdsMinTiles = 2048;
 
+// The term kernel a step of degree m takes: the forced one, else pairs of
+// terms at FP32 (fastest at 1001x501 and 8192x4096), and at FP64 LDS tiles from
+// kPmlLdsMinTiles tiles up, one thread per node below.
+int pml_path_for(const expw_pml* op, int m) {
+  if (op->path != 0) return op->path;
+  if (op->g.dtype == EXPW_F32 && m >= 2) return 3;
+  const int64_t tiles = ((op->g.nx + kPmlTX - 1) / kPmlTX) * ((op->g.ny + kPmlTY - 1) / kPmlTY);
+  return tiles >= kPmlLdsMinTiles ? 2 : 1;
+}
+
 struct PmlLayout {
   size_t bx, bxh, by, byh, src_idx, src_amp, big, total;
 };
@@ -1620,12 +1630,16 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
     t1.cpp = static_cast<T>(j + 1 == 2 ? 2.0 * c1s : c1s);
     split_weight(a[j], &t0.a_j, &t0.a_j_lo);
     split_weight(a[j + 1], &t1.a_j, &t1.a_j_lo);
-    T* o0 = (last && j + 1 == m) ? nullptr : pair_out[which][0];
-    T* o1 = (last && j + 1 == m) ? nullptr : pair_out[which][1];
+    T* o0 = last ? nullptr : pair_out[which][0];
+    T* o1 = last ? nullptr : pair_out[which][1];
     T* acc_out = (last && vp != S) ? S : C;
-    k_pml_faber_pair_lds<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, o0, o1, j == 1 ? nullptr : C, acc_out,
-                                                             t0, t1, make_pml_src<T>(op, q[j - 1]),
-                                                             make_pml_src<T>(op, q[j]), tiles_x);
+    // FP32: 1024-thread blocks on 64 x 32 tiles; FP64 (more registers): 256 on 64 x 16
+    constexpr int NT = sizeof(T) == 4 ? 1024 : 256, TY = sizeof(T) == 4 ? 32 : 16;
+    const int ptx = static_cast<int>((g.nx + kPmlTX - 1) / kPmlTX);
+    const unsigned pgrid = static_cast<unsigned>(ptx * ((g.ny + TY - 1) / TY));
+    k_pml_faber_pair_lds<T, NT, TY><<<pgrid, NT, 0, op->stream>>>(g, vp, vpp, o0, o1, j == 1 ? nullptr : C, acc_out,
+                                                                  t0, t1, make_pml_src<T>(op, q[j - 1]),
+                                                                  make_pml_src<T>(op, q[j]), ptx);
     if (int32_t rc = check_launch("pml faber pair")) return rc;
     if (last && acc_out == C) {
       if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
@@ -1665,8 +1679,9 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   const double sc = 1.0 / (op->g.h * op->g.h);
   const int tiles_x = static_cast<int>((op->g.nx + kPmlTX - 1) / kPmlTX);
   const int64_t tiles = tiles_x * ((op->g.ny + kPmlTY - 1) / kPmlTY);
-  const bool pairs = op->path == 3;
-  const bool lds = pairs || op->path == 2 || (op->path == 0 && tiles >= kPmlLdsMinTiles);
+  const int path = pml_path_for(op, m);
+  const bool pairs = path == 3;
+  const bool lds = path >= 2;
   const unsigned grid = lds ? static_cast<unsigned>(tiles) : grid_for(g.N);
   T* D = C + ns;
   T* E = D + ns;
@@ -1921,6 +1936,13 @@ int32_t expw_pml_set_path(expw_pml* op, int32_t path) {
   if (path < 0 || path > 3)
     return fail(EXPW_EINVAL, "path must be 0 (automatic), 1 (per node), 2 (LDS tiles) or 3 (pairs of terms)");
   op->path = path;
+  return EXPW_OK;
+}
+
+int32_t expw_pml_path_for(const expw_pml* op, int32_t m, int32_t* path) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (!path || m < 1) return fail(EXPW_EINVAL, "invalid argument");
+  *path = pml_path_for(op, m);
   return EXPW_OK;
 }
 

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, cons
 }
 
 // Two Faber terms j and j + 1 per pass on the PML operator (temporal
-// blocking). A 256-thread block owns a 64 x 16 tile. It stages v_{j-1} on the
+// blocking). A block of NT threads owns a 64 x TY tile. It stages v_{j-1} on the
 // tile grown by 8 cells (u on both axes, w_x along x, w_y along y; v on the
 // tile grown by 4), computes term j on the tile grown by 4 (R1) into LDS (zero
 // outside the grid, so the next stencils see the zero values there), then term
@@ -214,14 +214,14 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, cons
 // skipped when its pointer is null) and the sum acc_in + a_j v_j + a_{j+1}
 // v_{j+1} (for c0.first: a_0 v_{j-1} + ...). vpp (v_{j-2}, null for j = 1)
 // is read on R1, so no output may alias vp or vpp; acc_out may alias acc_in.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pml_faber_pair_lds(PmlGeo<T> g, const T* vp, const T* vpp,
-                                                               T* out0, T* out1, const T* acc_in,
-                                                               T* acc_out, FaberTerm<T> c0,
-                                                               FaberTerm<T> c1, Src<T> s0, Src<T> s1,
-                                                               int tiles_x) {
-  static_assert(kBlock == 256 && kPmlTX == 64, "4 waves, one tile column per lane");
-  constexpr int TX = kPmlTX, TY = kPmlTY;
+template <typename T, int NT, int TY>
+__global__ __launch_bounds__(NT) void k_pml_faber_pair_lds(PmlGeo<T> g, const T* vp, const T* vpp,
+                                                           T* out0, T* out1, const T* acc_in,
+                                                           T* acc_out, FaberTerm<T> c0,
+                                                           FaberTerm<T> c1, Src<T> s0, Src<T> s1,
+                                                           int tiles_x) {
+  constexpr int TX = kPmlTX, NW = NT / 64;
+  static_assert(NT % 64 == 0 && TY % NW == 0, "whole waves, each wave a set of tile rows");
   constexpr int AX = TX + 16, AY = TY + 16;  // tile grown by 8
   constexpr int BX = TX + 8, BY = TY + 8;    // tile grown by 4 (R1)
   __shared__ T au[AY][AX];   // v_{j-1}: u on the tile grown by 8
@@ -235,25 +235,25 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_pair_lds(PmlGeo<T> g, cons
   const T* v = vp + g.N;
   const T* wx = vp + 2 * g.N;
   const T* wy = vp + 3 * g.N;
-  for (int e = threadIdx.x; e < AY * AX; e += kBlock) {
+  for (int e = threadIdx.x; e < AY * AX; e += NT) {
     const int r = e / AX, q = e - r * AX;
     au[r][q] = pml_at(g, u, i0 - 8 + q, j0 - 8 + r);
   }
-  for (int e = threadIdx.x; e < BY * BX; e += kBlock) {
+  for (int e = threadIdx.x; e < BY * BX; e += NT) {
     const int r = e / BX, q = e - r * BX;
     av[r][q] = pml_at(g, v, i0 - 4 + q, j0 - 4 + r);
   }
-  for (int e = threadIdx.x; e < BY * AX; e += kBlock) {
+  for (int e = threadIdx.x; e < BY * AX; e += NT) {
     const int r = e / AX, q = e - r * AX;
     ax[r][q] = pml_at(g, wx, i0 - 8 + q, j0 - 4 + r);
   }
-  for (int e = threadIdx.x; e < AY * BX; e += kBlock) {
+  for (int e = threadIdx.x; e < AY * BX; e += NT) {
     const int r = e / BX, q = e - r * BX;
     ay[r][q] = pml_at(g, wy, i0 - 4 + q, j0 - 8 + r);
   }
   __syncthreads();
   // term j on R1: point (r, q) is node (i0 - 4 + q, j0 - 4 + r)
-  for (int e = threadIdx.x; e < BY * BX; e += kBlock) {
+  for (int e = threadIdx.x; e < BY * BX; e += NT) {
     const int r = e / BX, q = e - r * BX;
     const int i = i0 - 4 + q, j = j0 - 4 + r;
     T f[4] = {T(0), T(0), T(0), T(0)};
@@ -283,8 +283,8 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_pair_lds(PmlGeo<T> g, cons
   const int tx = threadIdx.x & 63, tyb = threadIdx.x >> 6;
   const int i = i0 + tx;
 #pragma unroll
-  for (int k4 = 0; k4 < TY / 4; ++k4) {
-    const int ly = tyb + 4 * k4, j = j0 + ly;
+  for (int k4 = 0; k4 < TY / NW; ++k4) {
+    const int ly = tyb + NW * k4, j = j0 + ly;
     if (i >= g.nx || j >= g.ny) continue;
     const int64_t n = static_cast<int64_t>(j) * g.nx + i;
     T o[4], sc[4];

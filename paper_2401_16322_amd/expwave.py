@@ -109,6 +109,7 @@ SIGNATURES = {
     "expw_pml_set_receivers": (_i32, [_vp, _i32, _vp]),
     "expw_pml_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_pml_set_path": (_i32, [_vp, _i32]),
+    "expw_pml_path_for": (_i32, [_vp, _i32, _pi32]),
     "expw_pml_sync_status": (_i32, [_vp]),
 }
 
@@ -777,6 +778,12 @@ class PMLOperator:
     def set_path(self, path):
         """0 automatic, 1 one thread per node, 2 LDS tiles, 3 two terms per pass."""
         _check(load().expw_pml_set_path(self.op, int(path)))
+
+    def path_for(self, m):
+        """The term kernel (1, 2 or 3) a step of degree m takes."""
+        out = _i32(0)
+        _check(load().expw_pml_path_for(self.op, int(m), ctypes.byref(out)))
+        return out.value
 
     def sync(self):
         _check(load().expw_pml_sync_status(self.op))
