@@ -324,10 +324,11 @@ enum { EXPW_EXPM_DEVICE = 0, EXPW_EXPM_HOST = 1 };
 int32_t expw_set_krylov_expm(expw_op* op, int32_t mode);
 
 /* allow = 1 (default): when the augmented vectors fit in registers across one
- * cooperative grid, the Arnoldi process runs as one persistent launch (grid
- * barriers between Gram-Schmidt steps); otherwise, and with allow = 0, one
- * launch per matrix-vector product and per Gram-Schmidt step. Results agree
- * to rounding. */
+ * cooperative grid, the Arnoldi process runs as one persistent launch with two
+ * grid-wide reductions per column (modified Gram-Schmidt's projections from
+ * one batched reduction of the dots and the basis Gram entries, by forward
+ * substitution); otherwise, and with allow = 0, one launch per matrix-vector
+ * product and per Gram-Schmidt step. Results agree to rounding. */
 int32_t expw_set_krylov_persistent(expw_op* op, int32_t allow);
 
 /* ------------------------------------------------------------------ timing */

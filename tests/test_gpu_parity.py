@@ -218,7 +218,7 @@ def test_homogeneous_101_full_run(dtype):
 
 def test_layered_1001x501_steps_at_full_size():
     """The 1001x501 layered medium at full size in the bench's launch
-    configuration (FP32, Faber degree 16, fused passes of 4 terms), three
+    configuration (FP32, Faber degree 16, fused passes of 6, 6 and 4 terms), three
     steps of 2 ms from a seeded smooth state, with the surface receiver line."""
     import torch
     from oracle.operator import Grid
