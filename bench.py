@@ -169,7 +169,99 @@ def bench_pml(args, w):
                      "peak": 8000.0, "unit": "GB/s", "frac": round(gbps / 8000.0, 4),
                      "traffic": None, "avg_term_us": round(ms * 1e3 / (args.steps * m), 3)},
     }
+    if args.tts:
+        out["time_to_solution"] = pml_time_to_solution(w, args)
     print(json.dumps(out, allow_nan=False), flush=True)
+
+
+PML_TTS_ORDERS = (8, 16, 24, 32, 40)
+
+
+def pml_time_to_solution(w, args):
+    """Time to solution of Faber steps on the PML operator: the largest dt of the
+    ladder whose displacement snapshots every 0.5 s up to the final time stay
+    within tol (relative L2 of u over the physical domain: the layers on the
+    sides and the bottom excluded, the free-surface rows included) of an FP64
+    reference (Faber degree 40, dt = 0.5 ms, checked against dt = 1 ms), and the
+    wall time of that run (receiver recording included)."""
+    import torch
+    from paper_2401_16322_amd import expwave as xw
+    dev = torch.device("cuda:0")
+    nx, ny = w.n
+    L, T, snap_every = w.abc_cells, w.T, 0.5
+    nsnap = int(round(T / snap_every))
+    rec = w.receiver_nodes()
+    c2_np = w.velocity() ** 2
+
+    def make_op(tdt):
+        op = xw.PMLOperator(nx, ny, w.h, torch.tensor(c2_np, dtype=tdt, device=dev),
+                            abc_cells=w.abc_cells, beta0=w.sigma_max, max_taylor_p=w.taylor_p)
+        op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)
+        op.set_receivers(rec)
+        return op
+
+    def interior(state):
+        return state[:nx * ny].view(ny, nx)[: ny - L, L: nx - L].double()
+
+    def run(op, tdt, m, dt, ref=None, tol=None):
+        state = torch.zeros(4 * nx * ny, dtype=tdt, device=dev)
+        nper = int(round(snap_every / dt))
+        traces = torch.zeros(nper * max(rec.size, 1), dtype=tdt, device=dev)
+        snaps, err = [], 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(nsnap):
+            op.step_faber(state, s_ * snap_every, dt, m, nper, traces=traces if rec.size else None)
+            if ref is None:
+                snaps.append(interior(state).clone())
+            else:
+                torch.cuda.synchronize()
+                t_pause = time.perf_counter()
+                r = ref[s_]
+                e = (torch.linalg.vector_norm(interior(state) - r) / torch.linalg.vector_norm(r)).item()
+                err = max(err, e if np.isfinite(e) else float("inf"))
+                t0 += time.perf_counter() - t_pause
+                if err > tol:
+                    break
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        op.sync()
+        return err, wall, snaps
+
+    op64 = make_op(torch.float64)
+    _, _, ref = run(op64, torch.float64, 40, 0.5e-3)
+    _, _, ref2 = run(op64, torch.float64, 40, 1.0e-3)
+    ref_check = max((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a)).item()
+                    for a, b in zip(ref, ref2))
+    del op64
+    out = {"tol": args.tts_tol, "T_s": T, "snapshots_s": [snap_every * (i + 1) for i in range(nsnap)],
+           "error": "relative L2 of u over the physical domain (free-surface rows included), max over snapshots",
+           "reference": {"method": "faber", "order": 40, "dt_ms": 0.5, "dtype": "f64", "vs_dt_1ms": ref_check},
+           "dt_ladder_ms": list(TTS_DTS_MS)}
+    for dname in [d for d in args.tts_dtypes.split(",") if d]:
+        tdt = {"f32": torch.float32, "f64": torch.float64}[dname]
+        op = make_op(tdt)
+        results = []
+        for m in PML_TTS_ORDERS:
+            best, tried = None, []
+            for dt_ms in TTS_DTS_MS:
+                dt = dt_ms * 1e-3
+                err, _, _ = run(op, tdt, m, dt, ref=ref, tol=args.tts_tol)
+                tried.append([dt_ms, float(f"{err:.3g}") if np.isfinite(err) else None])
+                if err <= args.tts_tol:
+                    walls = [run(op, tdt, m, dt, ref=ref, tol=args.tts_tol)[1] for _ in range(args.tts_repeats)]
+                    nsteps = int(round(T / dt))
+                    best = {"method": "faber", "order": m, "dt_ms": dt_ms, "max_rel_l2": err,
+                            "wall_s": float(np.median(walls)), "n_steps": nsteps, "n_op": nsteps * m,
+                            "n_mem": nsteps}
+                    break
+            r = best if best else {"method": "faber", "order": m, "dt_ms": None}
+            r["tried"] = tried
+            results.append(r)
+        del op
+        ok = [r for r in results if r.get("dt_ms")]
+        out[dname] = {"runs": results, "fastest": min(ok, key=lambda r: r["wall_s"]) if ok else None}
+    return out
 
 
 def main():
