@@ -495,7 +495,7 @@ int persistent_un(expw_op* op, int64_t naug) {
   }
   if (op->coop_blocks <= 0) return 0;
   const int64_t threads = static_cast<int64_t>(op->coop_blocks) * kArnNT;
-  for (int un : {2, 4, 8})
+  for (int un : {2, 4, 6, 8})
     if (naug <= un * threads) return un;
   return 0;
 }
@@ -525,6 +525,7 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   const void* fn = nullptr;
   if (un == 2) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2>);
   else if (un == 4) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 4>);
+  else if (un == 6) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 6>);
   else fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 8>);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int slot = op->prof.acquire(EXPW_KERNEL_KRYLOV_ARNOLDI, &e0, &e1);
