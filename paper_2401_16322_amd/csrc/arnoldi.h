@@ -272,7 +272,8 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     ArnArgs a, unsigned long long* slots, int* err, double* hess, double* sc, double* beta_out) {
   constexpr int NW = kArnNT / 64;
   __shared__ double s_scale[EXPW_MAX_KRYLOV + 1];
-  __shared__ double s_gt[EXPW_MAX_KRYLOV][EXPW_MAX_KRYLOV];  // s_gt[l][i] = <q_i, q_l>, l < i
+  // <q_i, q_l> for l < i < EXPW_MAX_KRYLOV, packed: entry i (i - 1) / 2 + l
+  __shared__ double s_gt[EXPW_MAX_KRYLOV * (EXPW_MAX_KRYLOV - 1) / 2];
   __shared__ double s_wpart[kArnMaxVals][NW];
   __shared__ double s_tot[kArnMaxVals];
   __shared__ double s_h[EXPW_MAX_KRYLOV];
@@ -280,7 +281,8 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   // the first NC stored columns Q_1..Q_NC also stay in LDS, as far as the
   // block's LDS allows: every later column reads them in both sweeps
   constexpr int kColLds = UN * kArnNT * static_cast<int>(sizeof(T));
-  constexpr int kFixedLds = (3 * EXPW_MAX_KRYLOV + 1 + EXPW_MAX_KRYLOV * EXPW_MAX_KRYLOV + kArnMaxVals * (NW + 1)) * 8;
+  constexpr int kFixedLds =
+      (3 * EXPW_MAX_KRYLOV + 1 + EXPW_MAX_KRYLOV * (EXPW_MAX_KRYLOV - 1) / 2 + kArnMaxVals * (NW + 1)) * 8;
   constexpr int kFree = kArnLdsBudget - kFixedLds - kColLds;
   constexpr int NC = kFree / kColLds < 4 ? kFree / kColLds : 4;
   __shared__ T s_cache[NC > 0 ? NC : 1][NC > 0 ? UN : 1][NC > 0 ? kArnNT : 1];
@@ -480,7 +482,8 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       for (int l0 = 0; l0 < j; l0 += 8) {
         double gb[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) gb[t] = (l0 + t < j) ? s_gt[l0 + t][lane] : 0.0;
+        for (int t = 0; t < 8; ++t)
+          gb[t] = (l0 + t < j && lane > l0 + t && lane < j) ? s_gt[lane * (lane - 1) / 2 + l0 + t] : 0.0;
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           const int l = l0 + t;
@@ -491,7 +494,7 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
           }
         }
       }
-      if (lane < j) s_gt[lane][j] = grow;
+      if (lane < j) s_gt[j * (j - 1) / 2 + lane] = grow;
       if (lane <= j) {
         s_h[lane] = r * sl;  // applied to the stored column Q_i = q_i / s_i
         if (blockIdx.x == 0) hess[lane * kArnHessLd + j] = r;
