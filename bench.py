@@ -174,11 +174,12 @@ def bench_pml(args, w):
     print(json.dumps(out, allow_nan=False), flush=True)
 
 
-PML_TTS_ORDERS = (8, 16, 24, 32, 40)
+PML_TTS_CANDIDATES = (("faber", 8), ("faber", 16), ("faber", 24), ("faber", 32), ("faber", 40),
+                      ("krylov", 10), ("krylov", 20), ("krylov", 30), ("krylov", 40), ("rk4", 4))
 
 
 def pml_time_to_solution(w, args):
-    """Time to solution of Faber steps on the PML operator: the largest dt of the
+    """Time to solution on the PML operator (Faber, Krylov, RK4): the largest dt of the
     ladder whose displacement snapshots every 0.5 s up to the final time stay
     within tol (relative L2 of u over the physical domain: the layers on the
     sides and the bottom excluded, the free-surface rows included) of an FP64
@@ -193,9 +194,12 @@ def pml_time_to_solution(w, args):
     rec = w.receiver_nodes()
     c2_np = w.velocity() ** 2
 
+    kmax = max(k for m_, k in PML_TTS_CANDIDATES if m_ == "krylov")
+
     def make_op(tdt):
         op = xw.PMLOperator(nx, ny, w.h, torch.tensor(c2_np, dtype=tdt, device=dev),
-                            abc_cells=w.abc_cells, beta0=w.sigma_max, max_taylor_p=w.taylor_p)
+                            abc_cells=w.abc_cells, beta0=w.sigma_max, max_taylor_p=w.taylor_p,
+                            max_krylov_k=kmax)
         op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)
         op.set_receivers(rec)
         return op
@@ -203,7 +207,7 @@ def pml_time_to_solution(w, args):
     def interior(state):
         return state[:nx * ny].view(ny, nx)[: ny - L, L: nx - L].double()
 
-    def run(op, tdt, m, dt, ref=None, tol=None):
+    def run(op, tdt, method, m, dt, ref=None, tol=None):
         state = torch.zeros(4 * nx * ny, dtype=tdt, device=dev)
         nper = int(round(snap_every / dt))
         traces = torch.zeros(nper * max(rec.size, 1), dtype=tdt, device=dev)
@@ -211,7 +215,13 @@ def pml_time_to_solution(w, args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s_ in range(nsnap):
-            op.step_faber(state, s_ * snap_every, dt, m, nper, traces=traces if rec.size else None)
+            tr = traces if rec.size else None
+            if method == "faber":
+                op.step_faber(state, s_ * snap_every, dt, m, nper, traces=tr)
+            elif method == "krylov":
+                op.step_krylov(state, s_ * snap_every, dt, m, nper, traces=tr)
+            else:
+                op.step_rk4(state, s_ * snap_every, dt, nper, traces=tr)
             if ref is None:
                 snaps.append(interior(state).clone())
             else:
@@ -229,8 +239,8 @@ def pml_time_to_solution(w, args):
         return err, wall, snaps
 
     op64 = make_op(torch.float64)
-    _, _, ref = run(op64, torch.float64, 40, 0.5e-3)
-    _, _, ref2 = run(op64, torch.float64, 40, 1.0e-3)
+    _, _, ref = run(op64, torch.float64, "faber", 40, 0.5e-3)
+    _, _, ref2 = run(op64, torch.float64, "faber", 40, 1.0e-3)
     ref_check = max((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a)).item()
                     for a, b in zip(ref, ref2))
     del op64
@@ -242,20 +252,21 @@ def pml_time_to_solution(w, args):
         tdt = {"f32": torch.float32, "f64": torch.float64}[dname]
         op = make_op(tdt)
         results = []
-        for m in PML_TTS_ORDERS:
+        for method, m in PML_TTS_CANDIDATES:
             best, tried = None, []
             for dt_ms in TTS_DTS_MS:
                 dt = dt_ms * 1e-3
-                err, _, _ = run(op, tdt, m, dt, ref=ref, tol=args.tts_tol)
+                err, _, _ = run(op, tdt, method, m, dt, ref=ref, tol=args.tts_tol)
                 tried.append([dt_ms, float(f"{err:.3g}") if np.isfinite(err) else None])
                 if err <= args.tts_tol:
-                    walls = [run(op, tdt, m, dt, ref=ref, tol=args.tts_tol)[1] for _ in range(args.tts_repeats)]
+                    walls = [run(op, tdt, method, m, dt, ref=ref, tol=args.tts_tol)[1]
+                             for _ in range(args.tts_repeats)]
                     nsteps = int(round(T / dt))
-                    best = {"method": "faber", "order": m, "dt_ms": dt_ms, "max_rel_l2": err,
+                    best = {"method": method, "order": m, "dt_ms": dt_ms, "max_rel_l2": err,
                             "wall_s": float(np.median(walls)), "n_steps": nsteps, "n_op": nsteps * m,
                             "n_mem": nsteps}
                     break
-            r = best if best else {"method": "faber", "order": m, "dt_ms": None}
+            r = best if best else {"method": method, "order": m, "dt_ms": None}
             r["tried"] = tried
             results.append(r)
         del op

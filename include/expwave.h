@@ -403,15 +403,18 @@ int32_t expw_pml_spectrum_rectangle(const expw_pml_grid* grid, double c2_max, do
  * 0..3 from w_y's half rows 0..7, times 1/h). */
 int32_t expw_pml_surface_weights(double* d2, double* d1, double* dw);
 
-/* Bytes of device workspace expw_pml_create needs (max_taylor_p <= EXPW_MAX_TAYLOR). */
-int32_t expw_pml_workspace_size(const expw_pml_grid* grid, int32_t max_taylor_p, size_t* bytes);
+/* Bytes of device workspace expw_pml_create needs for a largest Krylov
+ * dimension max_krylov_k (0 = Krylov unused, <= EXPW_MAX_KRYLOV) and a largest
+ * source Taylor order max_taylor_p (<= EXPW_MAX_TAYLOR). */
+int32_t expw_pml_workspace_size(const expw_pml_grid* grid, int32_t max_krylov_k, int32_t max_taylor_p,
+                                size_t* bytes);
 
 /* Binds a grid, c^2 at the nodes (nx * ny values, > 0, read until destroy)
  * and a caller-owned, 256-byte aligned workspace; computes the spectrum
  * rectangle and the Faber ellipse. stream: hipStream_t (NULL = default). */
-int32_t expw_pml_create(const expw_pml_grid* grid, const void* c2_dev, int32_t max_taylor_p,
-                        void* workspace_dev, size_t workspace_bytes, void* hip_stream,
-                        expw_pml** out);
+int32_t expw_pml_create(const expw_pml_grid* grid, const void* c2_dev, int32_t max_krylov_k,
+                        int32_t max_taylor_p, void* workspace_dev, size_t workspace_bytes,
+                        void* hip_stream, expw_pml** out);
 int32_t expw_pml_destroy(expw_pml* op);
 int32_t expw_pml_get_ellipse(const expw_pml* op, double* gamma, double* c0, double* c1);
 
@@ -433,6 +436,17 @@ int32_t expw_pml_set_receivers(expw_pml* op, int32_t n_rec, const int64_t* node_
  * receivers after every step (nsteps x n_rec). Asynchronous on the stream. */
 int32_t expw_pml_step_faber(expw_pml* op, void* state_dev, double t0, double dt, int32_t m,
                             int64_t nsteps, void* traces_dev);
+
+/* nsteps Krylov steps of dimension k <= max_krylov_k (Sec. 3.2, Arnoldi with
+ * modified Gram-Schmidt on the augmented matrix, exp(dt H_k) e_1 on the device)
+ * in place; traces as for expw_pml_step_faber. */
+int32_t expw_pml_step_krylov(expw_pml* op, void* state_dev, double t0, double dt, int32_t k,
+                             int64_t nsteps, void* traces_dev);
+
+/* nsteps classical RK4 steps (Sec. 3.1) in place, the source at the stage
+ * times; traces as for expw_pml_step_faber. */
+int32_t expw_pml_step_rk4(expw_pml* op, void* state_dev, double t0, double dt, int64_t nsteps,
+                          void* traces_dev);
 
 /* Kernel of the Faber terms: 0 = automatic (FP32: two terms per pass; FP64:
  * LDS tiles of 64 x 16 nodes once the grid has at least 2048 of them, else one

@@ -1524,6 +1524,10 @@ struct expw_pml {
   int n_rec;
   const int64_t* rec_dev;
   int path;  // 0 automatic, 1 one thread per node, 2 LDS tiles, 3 pairs of terms in LDS tiles
+  // Krylov (launch per step): largest dimension, workspace offsets, stride of a basis vector
+  int kmax;
+  size_t off_part, off_scal, off_hess, off_kry;
+  int64_t naug_pad;
 };
 
 namespace expw {
@@ -1544,10 +1548,11 @@ int pml_path_for(const expw_pml* op, int m) {
 }
 
 struct PmlLayout {
-  size_t bx, bxh, by, byh, src_idx, src_amp, big, total;
+  size_t bx, bxh, by, byh, src_idx, src_amp, part, scal, hess, kry, big, total;
+  int64_t naug_pad;
 };
 
-PmlLayout pml_layout(const expw_pml_grid& g) {
+PmlLayout pml_layout(const expw_pml_grid& g, int kmax, int pmax) {
   const size_t es = g.dtype == EXPW_F32 ? 4 : 8;
   PmlLayout L{};
   size_t off = 0;
@@ -1557,9 +1562,17 @@ PmlLayout pml_layout(const expw_pml_grid& g) {
   L.byh = off; off = align_up(off + g.ny * es);
   L.src_idx = off; off = align_up(off + EXPW_MAX_SOURCES * sizeof(int64_t));
   L.src_amp = off; off = align_up(off + EXPW_MAX_SOURCES * es);
+  L.part = off; off = align_up(off + 2 * kRedMaxBlocks * sizeof(double));  // two partial sets
+  L.scal = off; off = align_up(off + 64 * sizeof(double));
+  L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
+  L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
   L.big = off;
-  // Faber: two pairs of terms and the partial sum, 4 fields each
-  L.total = align_up(off + 5 * 4 * static_cast<size_t>(g.nx * g.ny) * es);
+  const int64_t ns = 4 * g.nx * g.ny;
+  L.naug_pad = (ns + pmax + 63) / 64 * 64;
+  // Faber: two pairs of terms and the partial sum; Krylov: kmax + 1 basis vectors
+  size_t big = 5 * static_cast<size_t>(ns) * es;
+  if (kmax > 0) big = std::max(big, static_cast<size_t>(kmax + 1) * L.naug_pad * es);
+  L.total = align_up(off + big);
   return L;
 }
 
@@ -1754,6 +1767,107 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   return EXPW_OK;
 }
 
+// RK4 steps (Sec. 3.1) on the PML operator; the source enters at the stage times.
+template <typename T>
+int32_t pml_rk4_impl(expw_pml* op, T* S, double t0, double dt, int64_t nsteps, T* traces) {
+  const PmlGeo<T> g = make_pml_geo<T>(op);
+  const int64_t ns = 4 * g.N;
+  T* A = reinterpret_cast<T*>(op->ws + op->off_big);
+  T* B = A + ns;
+  T* C = B + ns;
+  const unsigned grid = grid_for(g.N);
+  const double sc = 1.0 / (op->g.h * op->g.h);
+  auto srcq = [&](double t) {
+    double gv = 0.0;
+    if (op->n_src > 0) ricker_derivatives(t, op->f_peak, op->t_delay, 1, &gv);
+    return make_pml_src<T>(op, gv * sc);
+  };
+  const T h2 = static_cast<T>(0.5 * dt), h1 = static_cast<T>(dt), s6 = static_cast<T>(dt / 6.0),
+          s3 = static_cast<T>(dt / 3.0);
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const double t = t0 + st * dt;
+    k_pml_rk4_stage<T><<<grid, kBlock, 0, op->stream>>>(g, S, S, nullptr, A, C, h2, s6, srcq(t));
+    k_pml_rk4_stage<T><<<grid, kBlock, 0, op->stream>>>(g, A, S, C, B, C, h2, s3, srcq(t + 0.5 * dt));
+    k_pml_rk4_stage<T><<<grid, kBlock, 0, op->stream>>>(g, B, S, C, A, C, h1, s3, srcq(t + 0.5 * dt));
+    k_pml_rk4_stage<T><<<grid, kBlock, 0, op->stream>>>(g, A, nullptr, C, nullptr, S, T(0), s6, srcq(t + dt));
+    if (int32_t rc = check_launch("pml rk4 stage")) return rc;
+    if (traces && op->n_rec > 0) {
+      k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec, traces + st * op->n_rec);
+      if (int32_t rc = check_launch("pml gather")) return rc;
+    }
+  }
+  return EXPW_OK;
+}
+
+// Krylov steps (Sec. 3.2) on the PML operator: the launch-per-step Arnoldi
+// process (modified Gram-Schmidt, one projection per reduction) and the small
+// exponential on the device.
+template <typename T>
+int32_t pml_krylov_impl(expw_pml* op, T* S, double t0, double dt, int k, int64_t nsteps, T* traces) {
+  const PmlGeo<T> g = make_pml_geo<T>(op);
+  const int64_t ns = 4 * g.N;
+  const int p = op->n_src > 0 ? op->taylor_p : 0;
+  const int64_t naug = ns + p;
+  const int64_t ld = op->naug_pad;
+  T* Q = reinterpret_cast<T*>(op->ws + op->off_big);
+  double* part = reinterpret_cast<double*>(op->ws + op->off_part);
+  double* scal = reinterpret_cast<double*>(op->ws + op->off_scal);
+  double* hess = reinterpret_cast<double*>(op->ws + op->off_hess);
+  const T* amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
+  double* kry_y = reinterpret_cast<double*>(op->ws + op->off_kry);
+  double* kry_sc = kry_y + 64;
+  int* kry_keff = reinterpret_cast<int*>(op->ws + op->off_kry + 136 * sizeof(double));
+  const unsigned rg_vec = red_grid_for(naug);
+  const unsigned rg_pts = red_grid_for(g.N + p);
+  const double tol = 1e-14;
+  std::vector<double> der(EXPW_MAX_TAYLOR);
+  KrySrc ks{};
+  ks.n = op->n_src;
+  ks.p = p;
+  ks.lo = op->src_lo;
+  ks.hi = op->src_hi;
+  ks.idx = reinterpret_cast<const int64_t*>(op->ws + op->off_src_idx);
+  const double sc = 1.0 / (op->g.h * op->g.h);
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const double t = t0 + st * dt;
+    if (p > 0) {
+      ricker_derivatives(t, op->f_peak, op->t_delay, p, der.data());
+      for (int c = 0; c < p; ++c) ks.G[c] = der[p - 1 - c] * sc;
+    }
+    double* P[2] = {part, part + kRedMaxBlocks};
+    const unsigned nb_ns = red_grid_for(ns);
+    k_norm2<T><<<nb_ns, kBlock, 0, op->stream>>>(S, ns, P[0]);
+    k_kry_init<T><<<rg_vec, kBlock, 0, op->stream>>>(S, ns, Q, naug, P[0], nb_ns, p > 0 ? 1.0 : 0.0, scal + 1,
+                                                     kry_sc);
+    int c = 0, nin = 0;
+    for (int j = 0; j < k; ++j) {
+      T* w = Q + (j + 1) * ld;
+      k_pml_kry_matvec<T><<<rg_pts, kBlock, 0, op->stream>>>(g, Q + j * ld, w, Q, ks, amp, j == 0 ? nullptr : P[c],
+                                                             nin, tol, scal + 1,
+                                                             j == 0 ? nullptr : hess + j * kHessLd + (j - 1),
+                                                             kry_sc + j, P[c ^ 1]);
+      c ^= 1;
+      nin = static_cast<int>(rg_pts);
+      for (int i = 0; i <= j; ++i) {
+        const bool lastc = (i == j);
+        k_kry_mgs<T><<<rg_vec, kBlock, 0, op->stream>>>(w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld, naug,
+                                                        P[c], nin, hess + i * kHessLd + j, kry_sc, i, P[c ^ 1]);
+        c ^= 1;
+        nin = static_cast<int>(rg_vec);
+      }
+    }
+    k_kry_finish<<<1, kBlock, 0, op->stream>>>(P[c], nin, tol, scal + 1, hess + k * kHessLd + (k - 1), kry_sc + k);
+    k_kry_expm<<<1, kBlock, 0, op->stream>>>(hess, k, dt, tol, scal + 1, kry_y, kry_keff);
+    k_kry_combine_dev<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc);
+    if (int32_t rc = check_launch("pml krylov")) return rc;
+    if (traces && op->n_rec > 0) {
+      k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec, traces + st * op->n_rec);
+      if (int32_t rc = check_launch("pml gather")) return rc;
+    }
+  }
+  return EXPW_OK;
+}
+
 int32_t check_pml(const expw_pml* op) {
   if (!op) return fail(EXPW_EINVAL, "op is NULL");
   return EXPW_OK;
@@ -1764,20 +1878,21 @@ int32_t check_pml(const expw_pml* op) {
 
 extern "C" {
 
-int32_t expw_pml_workspace_size(const expw_pml_grid* g, int32_t max_p, size_t* bytes) {
+int32_t expw_pml_workspace_size(const expw_pml_grid* g, int32_t max_k, int32_t max_p, size_t* bytes) {
   clear_error();
   if (int32_t rc = expw_pml_check_grid(g)) return rc;
+  if (max_k < 0 || max_k > EXPW_MAX_KRYLOV) return fail(EXPW_EINVAL, "max_krylov_k must be in [0, %d]", EXPW_MAX_KRYLOV);
   if (max_p < 0 || max_p > EXPW_MAX_TAYLOR) return fail(EXPW_EINVAL, "max_taylor_p must be in [0, %d]", EXPW_MAX_TAYLOR);
   if (!bytes) return fail(EXPW_EINVAL, "bytes is NULL");
-  *bytes = pml_layout(*g).total;
+  *bytes = pml_layout(*g, max_k, max_p).total;
   return EXPW_OK;
 }
 
-int32_t expw_pml_create(const expw_pml_grid* g, const void* c2_dev, int32_t max_p, void* ws,
+int32_t expw_pml_create(const expw_pml_grid* g, const void* c2_dev, int32_t max_k, int32_t max_p, void* ws,
                         size_t ws_bytes, void* stream, expw_pml** out) {
   clear_error();
   size_t need = 0;
-  if (int32_t rc = expw_pml_workspace_size(g, max_p, &need)) return rc;
+  if (int32_t rc = expw_pml_workspace_size(g, max_k, max_p, &need)) return rc;
   if (!out) return fail(EXPW_EINVAL, "out is NULL");
   if (!c2_dev) return fail(EXPW_EINVAL, "c2_dev is NULL");
   if (!ws) return fail(EXPW_EINVAL, "workspace_dev is NULL");
@@ -1790,7 +1905,13 @@ int32_t expw_pml_create(const expw_pml_grid* g, const void* c2_dev, int32_t max_
   op->ws_bytes = ws_bytes;
   op->stream = static_cast<hipStream_t>(stream);
   op->pmax = max_p;
-  const PmlLayout L = pml_layout(*g);
+  op->kmax = max_k;
+  const PmlLayout L = pml_layout(*g, max_k, max_p);
+  op->off_part = L.part;
+  op->off_scal = L.scal;
+  op->off_hess = L.hess;
+  op->off_kry = L.kry;
+  op->naug_pad = L.naug_pad;
   op->off_bx = L.bx;
   op->off_bxh = L.bxh;
   op->off_by = L.by;
@@ -1930,6 +2051,28 @@ int32_t expw_pml_step_faber(expw_pml* op, void* state, double t0, double dt, int
   if (op->g.dtype == EXPW_F32)
     return pml_faber_impl<float>(op, static_cast<float*>(state), t0, dt, m, nsteps, static_cast<float*>(traces));
   return pml_faber_impl<double>(op, static_cast<double*>(state), t0, dt, m, nsteps, static_cast<double*>(traces));
+}
+
+int32_t expw_pml_step_krylov(expw_pml* op, void* state, double t0, double dt, int32_t k, int64_t nsteps,
+                             void* traces) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (!state) return fail(EXPW_EINVAL, "state is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t0)) return fail(EXPW_EINVAL, "dt must be > 0");
+  if (nsteps < 0) return fail(EXPW_EINVAL, "nsteps must be >= 0");
+  if (k < 1 || k > op->kmax) return fail(EXPW_EINVAL, "Krylov dimension k must be in [1, %d] (max_krylov_k at create)", op->kmax);
+  if (op->g.dtype == EXPW_F32)
+    return pml_krylov_impl<float>(op, static_cast<float*>(state), t0, dt, k, nsteps, static_cast<float*>(traces));
+  return pml_krylov_impl<double>(op, static_cast<double*>(state), t0, dt, k, nsteps, static_cast<double*>(traces));
+}
+
+int32_t expw_pml_step_rk4(expw_pml* op, void* state, double t0, double dt, int64_t nsteps, void* traces) {
+  if (int32_t rc = check_pml(op)) return rc;
+  if (!state) return fail(EXPW_EINVAL, "state is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t0)) return fail(EXPW_EINVAL, "dt must be > 0");
+  if (nsteps < 0) return fail(EXPW_EINVAL, "nsteps must be >= 0");
+  if (op->g.dtype == EXPW_F32)
+    return pml_rk4_impl<float>(op, static_cast<float*>(state), t0, dt, nsteps, static_cast<float*>(traces));
+  return pml_rk4_impl<double>(op, static_cast<double*>(state), t0, dt, nsteps, static_cast<double*>(traces));
 }
 
 int32_t expw_pml_set_path(expw_pml* op, int32_t path) {

@@ -308,4 +308,76 @@ __global__ __launch_bounds__(NT) void k_pml_faber_pair_lds(PmlGeo<T> g, const T*
   }
 }
 
+// One classical RK4 stage on the PML operator (Sec. 3.1), as k_rk4_stage:
+// k = H y + s(t_stage) (source on the v equation); ynext = u + cy k (if
+// ynext), acc_out = (acc_in ? acc_in : u) + ca k. y is read with a halo and
+// must not alias an output.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pml_rk4_stage(PmlGeo<T> g, const T* y, const T* u,
+                                                          const T* acc_in, T* ynext, T* acc_out,
+                                                          T cy, T ca, Src<T> src) {
+  const int64_t n = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  if (n >= g.N) return;
+  const int j = static_cast<int>(n / g.nx), i = static_cast<int>(n - static_cast<int64_t>(j) * g.nx);
+  T o[4], s[4];
+  pml_point(g, y, i, j, o, s);
+  o[1] += src_value(src, n);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int64_t e = f * g.N + n;
+    const T ue = u ? u[e] : T(0);
+    if (ynext) ynext[e] = ue + cy * o[f];
+    const T base = acc_in ? acc_in[e] : ue;
+    acc_out[e] = base + ca * o[f];
+  }
+}
+
+// Arnoldi on the PML operator (Sec. 3.2, Krylov listing), launch per step:
+// w = s_j H~ q for the augmented vector q = [state; tail] (the source tail
+// enters the v equation: W tail, and J shifts the tail), with the first dot
+// w . q_0 into per-block partials, as k_kry_matvec for the p/v operator.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pml_kry_matvec(PmlGeo<T> g, const T* __restrict__ q,
+                                                           T* __restrict__ w, const T* __restrict__ q0,
+                                                           KrySrc src, const T* __restrict__ amp,
+                                                           const double* pin, int nin, double tol,
+                                                           const double* beta, double* h_store,
+                                                           double* sc_store, double* __restrict__ pout) {
+  const int64_t ns = 4 * g.N;
+  const int64_t items = g.N + src.p;
+  const double sj = pin ? column_scale(pin, nin, tol, beta, h_store, sc_store) : 1.0;
+  const T st = static_cast<T>(sj);
+  double acc = 0.0;
+  for (int64_t it = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; it < items;
+       it += static_cast<int64_t>(gridDim.x) * kBlock) {
+    if (it < g.N) {
+      const int64_t n = it;
+      const int j = static_cast<int>(n / g.nx), i = static_cast<int>(n - static_cast<int64_t>(j) * g.nx);
+      T o[4], s[4];
+      pml_point(g, q, i, j, o, s);
+      if (src.n > 0 && n >= src.lo && n <= src.hi) {
+        for (int k = 0; k < src.n; ++k)
+          if (src.idx[k] == n) {
+            double gt = 0.0;
+            for (int c = 0; c < src.p; ++c) gt += src.G[c] * static_cast<double>(q[ns + c]);
+            o[1] += static_cast<T>(gt * static_cast<double>(amp[k]));
+          }
+      }
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const int64_t e = f * g.N + n;
+        const T v = o[f] * st;
+        w[e] = v;
+        acc += static_cast<double>(v) * static_cast<double>(q0[e]);
+      }
+    } else {
+      const int c = static_cast<int>(it - g.N);
+      const T val = (c + 1 < src.p) ? q[ns + c + 1] * st : T(0);  // J q_tail
+      w[ns + c] = val;
+      acc += static_cast<double>(val) * static_cast<double>(q0[ns + c]);
+    }
+  }
+  store_partial<false>(acc, pout);
+}
+
 }  // namespace expw

@@ -100,14 +100,16 @@ SIGNATURES = {
     "expw_pml_check_grid": (_i32, [_ppml]),
     "expw_pml_spectrum_rectangle": (_i32, [_ppml, _dbl, _pd, _pd]),
     "expw_pml_surface_weights": (_i32, [_pd, _pd, _pd]),
-    "expw_pml_workspace_size": (_i32, [_ppml, _i32, ctypes.POINTER(_sz)]),
-    "expw_pml_create": (_i32, [_ppml, _vp, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "expw_pml_workspace_size": (_i32, [_ppml, _i32, _i32, ctypes.POINTER(_sz)]),
+    "expw_pml_create": (_i32, [_ppml, _vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     "expw_pml_destroy": (_i32, [_vp]),
     "expw_pml_get_ellipse": (_i32, [_vp, _pd, _pd, _pd]),
     "expw_pml_apply": (_i32, [_vp, _vp, _vp]),
     "expw_pml_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
     "expw_pml_set_receivers": (_i32, [_vp, _i32, _vp]),
     "expw_pml_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
+    "expw_pml_step_rk4": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
+    "expw_pml_step_krylov": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_pml_set_path": (_i32, [_vp, _i32]),
     "expw_pml_path_for": (_i32, [_vp, _i32, _pi32]),
     "expw_pml_sync_status": (_i32, [_vp]),
@@ -692,9 +694,9 @@ def expw_pml_surface_weights():
     return d2, d1, dw
 
 
-def expw_pml_workspace_size(grid, max_taylor_p):
+def expw_pml_workspace_size(grid, max_taylor_p, max_krylov_k=0):
     out = _sz(0)
-    _check(load().expw_pml_workspace_size(ctypes.byref(grid), max_taylor_p, ctypes.byref(out)))
+    _check(load().expw_pml_workspace_size(ctypes.byref(grid), max_krylov_k, max_taylor_p, ctypes.byref(out)))
     return out.value
 
 
@@ -704,7 +706,7 @@ class PMLOperator:
     row 0 the free surface. States are flat tensors of 4 * nx * ny values
     [u | v | w_x | w_y]; only Faber steps run on this operator."""
 
-    def __init__(self, nx, ny, h, c2, abc_cells=0, beta0=0.0, max_taylor_p=8):
+    def __init__(self, nx, ny, h, c2, abc_cells=0, beta0=0.0, max_taylor_p=8, max_krylov_k=0):
         import torch
         self._torch = torch
         if not c2.is_cuda or c2.dtype not in (torch.float32, torch.float64):
@@ -719,11 +721,11 @@ class PMLOperator:
         self.c2 = c2.contiguous()
         if self.c2.numel() != self.npts:
             raise ValueError("c2 has the wrong number of points")
-        nbytes = expw_pml_workspace_size(self.grid, max_taylor_p)
+        nbytes = expw_pml_workspace_size(self.grid, max_taylor_p, max_krylov_k)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._rec = None
         h_ = _vp()
-        _check(load().expw_pml_create(ctypes.byref(self.grid), self.c2.data_ptr(), max_taylor_p,
+        _check(load().expw_pml_create(ctypes.byref(self.grid), self.c2.data_ptr(), max_krylov_k, max_taylor_p,
                                       self.workspace.data_ptr(), nbytes,
                                       torch.cuda.current_stream(self.device).cuda_stream, ctypes.byref(h_)))
         self.op = h_.value
@@ -784,6 +786,25 @@ class PMLOperator:
         out = _i32(0)
         _check(load().expw_pml_path_for(self.op, int(m), ctypes.byref(out)))
         return out.value
+
+    def _traces(self, traces, nsteps):
+        if traces is None:
+            return None
+        if self._rec is None:
+            raise ValueError("no receivers set")
+        if traces.dtype != self.dtype or traces.numel() < nsteps * self._rec.numel() \
+                or not traces.is_contiguous():
+            raise ValueError("traces must hold nsteps * n_rec values of the grid dtype")
+        return traces.data_ptr()
+
+    def step_krylov(self, state, t0, dt, k, nsteps, traces=None):
+        self._check_state(state)
+        _check(load().expw_pml_step_krylov(self.op, state.data_ptr(), t0, dt, k, nsteps,
+                                           self._traces(traces, nsteps)))
+
+    def step_rk4(self, state, t0, dt, nsteps, traces=None):
+        self._check_state(state)
+        _check(load().expw_pml_step_rk4(self.op, state.data_ptr(), t0, dt, nsteps, self._traces(traces, nsteps)))
 
     def sync(self):
         _check(load().expw_pml_sync_status(self.op))

@@ -23,7 +23,7 @@ def _case(nx, ny, dtype, seed, cells=6, beta0=150.0, src=True):
     c2 = c ** 2
     tdt = torch.float64 if dtype == "float64" else torch.float32
     op = PMLOperator(nx, ny, 10.0, torch.tensor(c2, dtype=tdt, device="cuda"), abc_cells=cells,
-                     beta0=beta0, max_taylor_p=8)
+                     beta0=beta0, max_taylor_p=8, max_krylov_k=20)
     U0 = rng.standard_normal(g.nstate) * 1e-3
     s = None
     if src:
@@ -80,6 +80,36 @@ def _step_ellipse(op, dtype):
     from paper_2401_16322_amd import expwave as ew
     gam, c0, c1 = op.ellipse
     return ew.expw_step_ellipse(ew.EXPW_F32 if dtype == "float32" else ew.EXPW_F64, gam, c0, c1)
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_rk4_steps_with_source_and_receivers_match_oracle(dtype):
+    import torch
+    op, prob, U0, tdt = _case(45, 33, dtype, seed=7)
+    g = prob.grid
+    rec = np.array([3 * g.nx + i for i in range(0, g.nx, 5)], dtype=np.int64)
+    op.set_receivers(rec)
+    nst, dt, t0 = 4, 2e-4, 0.02
+    U = torch.tensor(U0, dtype=tdt, device="cuda")
+    tr = torch.zeros(nst * rec.size, dtype=tdt, device="cuda")
+    op.step_rk4(U, t0, dt, nst, traces=tr)
+    op.sync()
+    ref, traces, _ = run(prob, "rk4", U0, t0, dt, nst, receivers=rec)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+    assert rel_l2(tr.cpu().numpy().reshape(nst, -1), traces) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("k,src", [(1, True), (8, True), (20, True), (12, False)])
+def test_krylov_steps_match_oracle(dtype, k, src):
+    import torch
+    op, prob, U0, tdt = _case(37, 29, dtype, seed=8, src=src)
+    nst, dt, t0 = 2, 1e-3, 0.03
+    U = torch.tensor(U0, dtype=tdt, device="cuda")
+    op.step_krylov(U, t0, dt, k, nst)
+    op.sync()
+    ref, _, _ = run(prob, "krylov", U0, t0, dt, nst, k=k, p=8)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
 
 
 def test_library_ellipse_matches_the_oracle_reading():
