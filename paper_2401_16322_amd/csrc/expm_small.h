@@ -1,0 +1,127 @@
+// y = exp(dt H_keff) e_1 for Krylov dimensions k <= 16 (Sec. 3.2, the
+// exponential of the small projected matrix), one workgroup of 256 threads.
+//
+// The same arithmetic as k_kry_expm (breakdown test, 1-norm scaling to
+// |A|_1 <= 1/2, degree-16 Taylor polynomial by Horner's rule, s squarings,
+// each product summed over l = 0, 1, ... in order), laid out for the small
+// case: thread t owns entry (t / 16, t % 16) of every 16 x 16 matrix, the
+// keff x keff matrices sit in the leading block of zero-padded 16 x 16 tiles,
+// and every product is one unrolled 16-term dot product with all of its LDS
+// operands loaded at once. The padding leaves the leading block unchanged
+// (A is zero outside it, so the Horner iterate and its squares stay
+// block-diagonal with an identity trailing block), and a product against a
+// zero operand adds an exact zero, so the leading block holds the values that
+// k_kry_expm computes.
+#pragma once
+
+#include "device_common.h"
+
+namespace expw {
+
+constexpr int kExpmSmallK = 16;
+
+// 1 / j for the Horner steps j = 1..15 (correctly rounded at compile time,
+// the value a run-time division gives)
+__device__ constexpr double kInvJ[16] = {0.0,        1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
+                                         1.0 / 6,    1.0 / 7,  1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
+                                         1.0 / 12,   1.0 / 13, 1.0 / 14, 1.0 / 15};
+
+// (X Y)_{rc} over the 16 x 16 tiles in LDS (row-major, ld 16)
+__device__ __forceinline__ double tile_dot16(const double* X, const double* Y, int r, int c) {
+  double x[16], y[16];
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    x[l] = X[r * 16 + l];
+    y[l] = Y[l * 16 + c];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int l = 0; l < 16; ++l) acc += x[l] * y[l];
+  return acc;
+}
+
+// hess: (k + 1) x k upper Hessenberg matrix, leading dimension 64; requires
+// 1 <= k <= 16 and blockDim.x == 256. Outputs as k_kry_expm: y_out[0..63]
+// (zero beyond keff, NaN if dt H is not finite) and *keff_out.
+__global__ __launch_bounds__(kBlock) void k_kry_expm_small(const double* __restrict__ hess, int k,
+                                                           double dt, double tol,
+                                                           const double* __restrict__ beta_p,
+                                                           double* __restrict__ y_out,
+                                                           int* __restrict__ keff_out) {
+  static_assert(kBlock == 256, "one thread per entry of a 16 x 16 tile");
+  __shared__ double A[256], P0[256], P1[256];
+  __shared__ int s_keff, s_sq;
+  const int tid = threadIdx.x;
+  const int r = tid >> 4, c = tid & 15;
+  const int lane = tid & 63;
+  // the entry this thread owns, loaded while wave 0 finds keff
+  const double hrc = (r < k && c < k && r <= c + 1) ? hess[r * 64 + c] : 0.0;
+  if (tid < 64) {
+    // keff: one more than the first column whose subdiagonal entry fails the
+    // breakdown test, else k (0 when beta is not positive)
+    const double beta = *beta_p;
+    const bool brk = lane < k && !(hess[(lane + 1) * 64 + lane] > tol * beta);
+    const unsigned long long m = __ballot(brk);
+    int ke = m ? __ffsll(static_cast<long long>(m)) : k;
+    if (!(beta > 0.0)) ke = 0;
+    if (lane == 0) s_keff = ke;
+  }
+  __syncthreads();
+  const int n = s_keff;
+  const double a = (r < n && c < n) ? dt * hrc : 0.0;
+  A[tid] = a;
+  __syncthreads();
+  if (tid < 64) {
+    // 1-norm: largest column sum of |A| (columns summed over r in order)
+    double cs = 0.0;
+    if (lane < 16) {
+      for (int i = 0; i < 16; ++i) cs += fabs(A[i * 16 + lane]);
+    }
+    double nm = cs;
+    for (int off = 32; off >= 1; off >>= 1) nm = fmax(nm, __shfl_xor(nm, off));
+    if (lane == 0) {
+      int sq = -1;  // -1: non-finite
+      if (isfinite(nm)) {
+        sq = 0;
+        while (nm > 0.5 && sq < 1100) {
+          nm *= 0.5;
+          ++sq;
+        }
+      }
+      s_sq = sq;
+    }
+  }
+  __syncthreads();
+  const int sq = s_sq;
+  if (sq < 0) {
+    if (tid < 64) y_out[tid] = NAN;
+    if (tid == 0) *keff_out = n;
+    return;
+  }
+  const double id = (r == c) ? 1.0 : 0.0;
+  const double as = a * ldexp(1.0, -sq);
+  A[tid] = as;
+  P0[tid] = id + as / 16.0;
+  __syncthreads();
+  // Horner: P <- I + A P / j for j = 15 .. 1
+  double* cur = P0;
+  double* nxt = P1;
+  for (int j = 15; j >= 1; --j) {
+    nxt[tid] = id + tile_dot16(A, cur, r, c) * kInvJ[j];
+    __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  for (int i = 0; i < sq; ++i) {
+    nxt[tid] = tile_dot16(cur, cur, r, c);
+    __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  if (tid < 64) y_out[tid] = (tid < n) ? cur[tid * 16] : 0.0;
+  if (tid == 0) *keff_out = n;
+}
+
+}  // namespace expw

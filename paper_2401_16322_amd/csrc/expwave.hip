@@ -11,6 +11,7 @@
 #include "adjoint.h"
 #include "arnoldi.h"
 #include "batch.h"
+#include "expm_small.h"
 #include "fused.h"
 #include "fused3d.h"
 #include "internal.h"
@@ -614,7 +615,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
     if (rc != EXPW_OK) return rc;
     if (op->kry_mode == EXPW_EXPM_DEVICE) {
       // y = exp(dt H_k) e_1 and the combination without leaving the device
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, k_kry_expm, dim3(1), dim3(kBlock), hess, k, dt, tol, scal + 1, kry_y, kry_keff);
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, k <= kExpmSmallK ? k_kry_expm_small : k_kry_expm, dim3(1), dim3(kBlock), hess, k, dt, tol, scal + 1, kry_y, kry_keff);
       launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (k + 1.0) * ns * es, k_kry_combine_dev<T>, dim3(red_grid_for(ns)), dim3(kBlock), S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc);
       op->last_keff = -1;  // on the device; read by expw_krylov_info
       if ((rc = check_launch("krylov exponential")) != EXPW_OK) return rc;
@@ -1857,7 +1858,7 @@ int32_t pml_krylov_impl(expw_pml* op, T* S, double t0, double dt, int k, int64_t
       }
     }
     k_kry_finish<<<1, kBlock, 0, op->stream>>>(P[c], nin, tol, scal + 1, hess + k * kHessLd + (k - 1), kry_sc + k);
-    k_kry_expm<<<1, kBlock, 0, op->stream>>>(hess, k, dt, tol, scal + 1, kry_y, kry_keff);
+    (k <= kExpmSmallK ? k_kry_expm_small : k_kry_expm)<<<1, kBlock, 0, op->stream>>>(hess, k, dt, tol, scal + 1, kry_y, kry_keff);
     k_kry_combine_dev<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc);
     if (int32_t rc = check_launch("pml krylov")) return rc;
     if (traces && op->n_rec > 0) {
