@@ -87,7 +87,7 @@ def parse():
                          "Faber steps on the paper's PML system with a free surface")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
-    ap.add_argument("--cpu-steps", type=int, default=16,
+    ap.add_argument("--cpu-steps", type=int, default=24,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--tts", type=int, default=1,
                     help="1 = also measure time-to-solution at --tts-tol over the full simulated time")

@@ -1,13 +1,14 @@
-// y = exp(dt H_keff) e_1 for Krylov dimensions k <= 16 (Sec. 3.2, the
-// exponential of the small projected matrix), one workgroup of 256 threads.
+// y = exp(dt H_keff) e_1 for Krylov dimensions k <= 32 (Sec. 3.2, the
+// exponential of the small projected matrix), one workgroup of TS x TS
+// threads for tiles of TS = 16 or 32.
 //
 // The same arithmetic as k_kry_expm (breakdown test, 1-norm scaling to
 // |A|_1 <= 1/2, degree-16 Taylor polynomial by Horner's rule, s squarings,
 // each product summed over l = 0, 1, ... in order), laid out for the small
-// case: thread t owns entry (t / 16, t % 16) of every 16 x 16 matrix, the
-// keff x keff matrices sit in the leading block of zero-padded 16 x 16 tiles,
-// and every product is one unrolled 16-term dot product with all of its LDS
-// operands loaded at once. The padding leaves the leading block unchanged
+// case: thread t owns entry (t / TS, t % TS) of every TS x TS matrix, the
+// keff x keff matrices sit in the leading block of zero-padded TS x TS tiles,
+// and every product is an unrolled TS-term dot product whose LDS operands are
+// loaded 16 at a time. The padding leaves the leading block unchanged
 // (A is zero outside it, so the Horner iterate and its squares stay
 // block-diagonal with an identity trailing block), and a product against a
 // zero operand adds an exact zero, so the leading block holds the values that
@@ -18,7 +19,7 @@
 
 namespace expw {
 
-constexpr int kExpmSmallK = 16;
+constexpr int kExpmSmallK = 32;  // largest k of the tiled kernels
 
 // 1 / j for the Horner steps j = 1..15 (correctly rounded at compile time,
 // the value a run-time division gives)
@@ -26,33 +27,39 @@ __device__ constexpr double kInvJ[16] = {0.0,        1.0 / 1,  1.0 / 2,  1.0 / 3
                                          1.0 / 6,    1.0 / 7,  1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
                                          1.0 / 12,   1.0 / 13, 1.0 / 14, 1.0 / 15};
 
-// (X Y)_{rc} over the 16 x 16 tiles in LDS (row-major, ld 16)
-__device__ __forceinline__ double tile_dot16(const double* X, const double* Y, int r, int c) {
-  double x[16], y[16];
-#pragma unroll
-  for (int l = 0; l < 16; ++l) {
-    x[l] = X[r * 16 + l];
-    y[l] = Y[l * 16 + c];
-  }
+// (X Y)_{rc} over TS x TS tiles in LDS (row-major, ld TS), summed over
+// l = 0 .. TS-1 in order
+template <int TS>
+__device__ __forceinline__ double tile_dot(const double* X, const double* Y, int r, int c) {
   double acc = 0.0;
 #pragma unroll
-  for (int l = 0; l < 16; ++l) acc += x[l] * y[l];
+  for (int l0 = 0; l0 < TS; l0 += 16) {
+    double x[16], y[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) {
+      x[l] = X[r * TS + l0 + l];
+      y[l] = Y[(l0 + l) * TS + c];
+    }
+#pragma unroll
+    for (int l = 0; l < 16; ++l) acc += x[l] * y[l];
+  }
   return acc;
 }
 
 // hess: (k + 1) x k upper Hessenberg matrix, leading dimension 64; requires
-// 1 <= k <= 16 and blockDim.x == 256. Outputs as k_kry_expm: y_out[0..63]
+// 1 <= k <= TS and blockDim.x == TS * TS. Outputs as k_kry_expm: y_out[0..63]
 // (zero beyond keff, NaN if dt H is not finite) and *keff_out.
-__global__ __launch_bounds__(kBlock) void k_kry_expm_small(const double* __restrict__ hess, int k,
-                                                           double dt, double tol,
-                                                           const double* __restrict__ beta_p,
-                                                           double* __restrict__ y_out,
-                                                           int* __restrict__ keff_out) {
-  static_assert(kBlock == 256, "one thread per entry of a 16 x 16 tile");
-  __shared__ double A[256], P0[256], P1[256];
+template <int TS>
+__global__ __launch_bounds__(TS * TS) void k_kry_expm_tile(const double* __restrict__ hess, int k,
+                                                          double dt, double tol,
+                                                          const double* __restrict__ beta_p,
+                                                          double* __restrict__ y_out,
+                                                          int* __restrict__ keff_out) {
+  static_assert(TS == 16 || TS == 32, "tiles of 16 x 16 or 32 x 32");
+  __shared__ double A[TS * TS], P0[TS * TS], P1[TS * TS];
   __shared__ int s_keff, s_sq;
   const int tid = threadIdx.x;
-  const int r = tid >> 4, c = tid & 15;
+  const int r = tid / TS, c = tid % TS;
   const int lane = tid & 63;
   // the entry this thread owns, loaded while wave 0 finds keff
   const double hrc = (r < k && c < k && r <= c + 1) ? hess[r * 64 + c] : 0.0;
@@ -74,8 +81,8 @@ __global__ __launch_bounds__(kBlock) void k_kry_expm_small(const double* __restr
   if (tid < 64) {
     // 1-norm: largest column sum of |A| (columns summed over r in order)
     double cs = 0.0;
-    if (lane < 16) {
-      for (int i = 0; i < 16; ++i) cs += fabs(A[i * 16 + lane]);
+    if (lane < TS) {
+      for (int i = 0; i < TS; ++i) cs += fabs(A[i * TS + lane]);
     }
     double nm = cs;
     for (int off = 32; off >= 1; off >>= 1) nm = fmax(nm, __shfl_xor(nm, off));
@@ -107,20 +114,20 @@ __global__ __launch_bounds__(kBlock) void k_kry_expm_small(const double* __restr
   double* cur = P0;
   double* nxt = P1;
   for (int j = 15; j >= 1; --j) {
-    nxt[tid] = id + tile_dot16(A, cur, r, c) * kInvJ[j];
+    nxt[tid] = id + tile_dot<TS>(A, cur, r, c) * kInvJ[j];
     __syncthreads();
     double* t = cur;
     cur = nxt;
     nxt = t;
   }
   for (int i = 0; i < sq; ++i) {
-    nxt[tid] = tile_dot16(cur, cur, r, c);
+    nxt[tid] = tile_dot<TS>(cur, cur, r, c);
     __syncthreads();
     double* t = cur;
     cur = nxt;
     nxt = t;
   }
-  if (tid < 64) y_out[tid] = (tid < n) ? cur[tid * 16] : 0.0;
+  if (tid < 64) y_out[tid] = (tid < n) ? cur[tid * TS] : 0.0;
   if (tid == 0) *keff_out = n;
 }
 

@@ -74,7 +74,7 @@ def test_faber_tiny_and_degenerate_grids(dtype, n):
 @pytest.mark.parametrize("mode", ["device", "host"])
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("k,src", [(1, True), (5, True), (16, True), (17, True), (20, True),
-                                   (12, False), (40, True)])
+                                   (12, False), (32, True), (40, True)])
 def test_krylov_steps_match_oracle(dtype, k, src, mode, path):
     case = make_case((45, 33), dtype, src=src, seed=5, max_k=40)
     case.op.set_krylov_expm(mode)
