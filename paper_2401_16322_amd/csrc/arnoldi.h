@@ -266,6 +266,30 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
+// Sums of two values over the 64 lanes of a wave (all lanes active), a into
+// sa and b into sb. One exchange of 32-lane halves (v_permlane32_swap, which
+// trades lanes 32-63 of its first operand for lanes 0-31 of its second)
+// leaves a_l + a_{l+32} in lanes l < 32 and b_{l-32} + b_l in lanes l >= 32;
+// then every 16-lane row is summed by DPP (quad permutations, row rotations
+// by 4 and 8) and rows 0+1 and 2+3 are added (row broadcast of lane 15), so
+// that lane 31 holds the sum of a and lane 63 that of b. Half the DPP
+// additions of two separate wave sums; the order of the additions is fixed.
+__device__ __forceinline__ void wave_sum_pair(double a, double b, double& sa, double& sb) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(__double2loint(a)),
+                                                   static_cast<unsigned>(__double2loint(b)), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(__double2hiint(a)),
+                                                   static_cast<unsigned>(__double2hiint(b)), false, false);
+  double v = __hiloint2double(static_cast<int>(hi[0]), static_cast<int>(lo[0])) +
+             __hiloint2double(static_cast<int>(hi[1]), static_cast<int>(lo[1]));
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124, 0xF>(v);  // row_ror:4
+  v += dpp_move<0x128, 0xF>(v);  // row_ror:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  sa = readlane_f64(v, 31);
+  sb = readlane_f64(v, 63);
+}
+
 template <typename T, int K, int BC, int DIM, int UN>
 __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     Geo<T, K, DIM> g, const T* __restrict__ S, T* Q, KrySrc src, const T* __restrict__ amp,
@@ -311,6 +335,14 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   auto put = [&](int v, double x) {
     x = wave_sum_fixed(x);
     if (lane == 0) s_wpart[v][wid] = x;
+  };
+  auto put2 = [&](int va, double xa, int vb, double xb) {
+    double sa, sb;
+    wave_sum_pair(xa, xb, sa, sb);
+    if (lane == 0) {
+      s_wpart[va][wid] = sa;
+      s_wpart[vb][wid] = sb;
+    }
   };
   auto reduce = [&](int nv, auto&& after) {
     grid_sum_vec<kArnNT>(nv, a.nvmax, s_wpart, s_tot, slots, ++seq, a.spin_limit, err, after);
@@ -427,9 +459,8 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
         r += w[u] * q0[u];
         gq += s_qj[u][threadIdx.x] * q0[u];
       }
-      put(0, static_cast<double>(r));
-      if (j >= 1) put(j + 1, static_cast<double>(gq));
-      if (j == 0) put(1, xx);
+      // value 1 of column 0 is |x|^2
+      put2(0, static_cast<double>(r), j >= 1 ? j + 1 : 1, j >= 1 ? static_cast<double>(gq) : xx);
     }
     auto dot1 = [&](int i, const T* q) {
       T r = T(0), gq = T(0);
@@ -438,8 +469,7 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
         r += w[u] * q[u];
         gq += s_qj[u][threadIdx.x] * q[u];
       }
-      put(i, static_cast<double>(r));
-      put(j + 1 + i, static_cast<double>(gq));
+      put2(i, static_cast<double>(r), j + 1 + i, static_cast<double>(gq));
     };
     // columns 1..j-1: the first nc in LDS, the other ns streamed from memory
     const int nc = j - 1 < NC ? (j - 1 > 0 ? j - 1 : 0) : NC;
