@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+# the CPU baseline (the FP64 oracle) runs on grids of at most this many points;
+# a step of a larger grid takes the oracle minutes and many GB, so none is given
+CPU_BASELINE_MAX_PTS = 2_000_000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_2401_16322_amd", "csrc")
 
@@ -37,6 +40,8 @@ CSRC = os.path.join(ROOT, "paper_2401_16322_amd", "csrc")
 KERNEL_SOURCES = {
     "krylov_arnoldi": ("arnoldi.h", "device_common.h", "kernels.h"),
     "faber": ("fused.h", "device_common.h", "kernels.h"),
+    "pml_faber_pair": ("pml.h", "device_common.h"),
+    "pml_faber_term": ("pml.h", "device_common.h"),
 }
 
 
@@ -156,6 +161,7 @@ def bench_pml(args, w):
         # one term per sweep: first term 13, middle terms 21, last term 17
         words = 13 + 21 * (m - 2) + 17 if m >= 2 else 13
     gbps = words * npts * es * args.steps / (ms * 1e-3) / 1e9
+    kclass = "pml_faber_pair" if path == 3 else "pml_faber_term"
     out = {
         "metric": "grid-pt matvecs/s", "value": npts * m * args.steps / (ms * 1e-3),
         "unit": "grid-pt matvecs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -164,14 +170,45 @@ def bench_pml(args, w):
         "config": {"workload": args.workload, "operator": "pml", "term_kernel": path,
                    "grid": [nx, ny], "faber_m": m,
                    "dt_ms": dt * 1e3, "abc_cells": w.abc_cells, "beta0": w.sigma_max},
-        "roofline": {"bound": "hbm", "kernel": "pml_faber_pair" if path == 3 else "pml_faber_term",
+        "roofline": {"bound": "hbm", "kernel": kclass,
                      "achieved": round(gbps, 1),
                      "peak": 8000.0, "unit": "GB/s", "frac": round(gbps / 8000.0, 4),
-                     "traffic": None, "avg_term_us": round(ms * 1e3 / (args.steps * m), 3)},
+                     "traffic": measured_traffic(kclass, w.name, args.dtype),
+                     "traffic_unit": "HBM bytes per launch, mean over the passes of a step "
+                                     "(rocprofv3 counters, copy-calibrated)",
+                     "avg_term_us": round(ms * 1e3 / (args.steps * m), 3)},
     }
+    if args.cpu_steps > 0 and w.npts <= CPU_BASELINE_MAX_PTS:
+        out["cpu_baseline"] = cpu_baseline_pml(w, args, c2.double().cpu().numpy())
     if args.tts:
         out["time_to_solution"] = pml_time_to_solution(w, args)
     print(json.dumps(out, allow_nan=False), flush=True)
+
+
+def cpu_baseline_pml(w, args, c2_np):
+    """The FP64 oracle's Faber steps on the PML operator (same grid, medium,
+    layer, source, degree and dt), single-threaded, on a bounded number of
+    steps (a quarter of --cpu-steps, at least 1)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import pml as opml
+    from oracle.steppers import faber_step
+    nx, ny = w.n
+    g = opml.PMLGrid(nx, ny, w.h, abc_cells=w.abc_cells, beta0=w.sigma_max)
+    prob = opml.PMLProblem(g, c2_np, opml.PMLSources((w.source_node(),), (1.0,), w.f_peak, w.t_delay))
+    ell = prob.ellipse()
+    nsteps = max(1, args.cpu_steps // 4)
+    U = np.zeros(g.nstate)
+    rec = np.asarray(w.receiver_nodes())
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for s in range(nsteps):
+            U = faber_step(prob, U, s * w.dt, w.dt, args.faber_m, p=w.taylor_p, ellipse=ell)
+            _ = U[rec]
+        el = time.perf_counter() - t0
+    total = nx * ny * args.faber_m * nsteps
+    return {"value": total / el, "unit": "grid-pt matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} Faber steps (m = {args.faber_m}) of the PML operator on {w.name}, "
+                      f"FP64 numpy, {el:.1f} s"}
 
 
 PML_TTS_CANDIDATES = (("faber", 8), ("faber", 16), ("faber", 24), ("faber", 32), ("faber", 40),
@@ -278,7 +315,7 @@ def pml_time_to_solution(w, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
     import torch
@@ -414,7 +451,7 @@ def main():
         del states, traces
         op.close()
         out["time_to_solution"] = time_to_solution(w, c2_np, args)
-    if args.cpu_steps > 0:
+    if args.cpu_steps > 0 and w.npts <= CPU_BASELINE_MAX_PTS:
         out["cpu_baseline"] = cpu_baseline(w, methods, mvos, dts, args, c2_np, rec)
     print(json.dumps(out, allow_nan=False), flush=True)
 
