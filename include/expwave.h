@@ -205,7 +205,13 @@ int32_t expw_set_source_taylor(expw_op* op, int32_t n_src, const int64_t* node_i
 /* Receivers: n_rec flat pressure-node indices in a caller-owned device int64
  * array (validated once, synchronizes). After every step the pressure at the
  * receivers is written to traces[step * n_rec + r] when a step call is given
- * a non-NULL traces_dev. n_rec = 0 removes the receivers. */
+ * a non-NULL traces_dev. n_rec = 0 removes the receivers. When the indices
+ * are consecutive (first, first + 1, ...: a receiver line along x) the kernel
+ * that writes a step's final pressure also writes the traces (2D fused Faber
+ * passes, the Krylov combination on the device, the last RK4 stage, the
+ * leap-frog pressure update); otherwise one gather kernel runs per step. The
+ * indices are read at this call: a later change of the array needs a new
+ * call. */
 int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* node_idx_dev);
 
 /* Advance the state nsteps steps of size dt starting at time t0 (step s runs

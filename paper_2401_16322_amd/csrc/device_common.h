@@ -81,6 +81,23 @@ __device__ __forceinline__ void apply_point(const Geo<T, K, DIM>& g, const T* __
   out[0] = -g.c2[idx] * div - sp * pc;
 }
 
+// Receivers on a run of consecutive pressure nodes first .. first + n - 1,
+// recorded by the kernel that writes a step's final pressure: out is the
+// step's row of the traces (nullptr: not recorded in the kernel).
+template <typename T>
+struct RecRun {
+  T* out;
+  int64_t first, n;
+};
+
+template <typename T>
+__device__ __forceinline__ void rec_run_put(const RecRun<T>& r, int64_t idx, T v) {
+  if (r.out) {
+    const int64_t d = idx - r.first;
+    if (d >= 0 && d < r.n) r.out[d] = v;
+  }
+}
+
 // Point sources: flat pressure indices idx[s] with amplitudes amp[s];
 // [lo, hi] bounds the indices so that other threads skip the search.
 template <typename T>

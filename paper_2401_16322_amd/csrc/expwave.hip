@@ -46,9 +46,12 @@ struct expw_op {
   int src_table;
   std::vector<double> src_rows;
   int64_t src_nrows;
-  // receivers
+  // receivers; rec_run_first >= 0 when they are the consecutive pressure
+  // nodes rec_run_first .. rec_run_first + n_rec - 1 (then the kernel that
+  // writes a step's final pressure records them, instead of a gather)
   int n_rec;
   const int64_t* rec_dev;
+  int64_t rec_run_first;
   // non-finite guard after every step (expw_set_guard)
   int guard;
   // tuning
@@ -286,6 +289,15 @@ int32_t gather(expw_op* op, const T* S, T* traces, int64_t step) {
   return check_launch("gather");
 }
 
+// The receivers of step `step` as a run recorded by the step's last kernel,
+// or none (out = nullptr: no traces, no receivers, or not a run; then
+// gather() records them after the step).
+template <typename T>
+RecRun<T> rec_run(const expw_op* op, T* traces, int64_t step) {
+  if (!traces || op->n_rec == 0 || op->rec_run_first < 0) return RecRun<T>{nullptr, 0, 0};
+  return RecRun<T>{traces + step * op->n_rec, op->rec_run_first, op->n_rec};
+}
+
 // ---------------------------------------------------------------- Faber step
 
 // The ellipse a Faber step in precision T runs with: 1/gamma, c0 and c1 are
@@ -400,11 +412,15 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
       return check_launch("faber final term");
     };
     const Src<T> src0 = make_src<T>(op, 0.0);
+    bool recorded = false;  // by the last fused pass
     if (fuse > 1 && !term_out) {
       if constexpr (BC == 0 && DIM == 2) {
         rc = faber_fused_passes<T>(op->stream, ns, S, Abuf, Bbuf, Cbuf, Dbuf, Ebuf, m, fuse, final_term,
             [&](int n, const T* vp, const T* vpp, const T* acc_in, T* ol, T* opv, T* acc_out, int j, bool first) {
-              return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, j, first, a.data(), q.data(), el.gamma, el.c0, el.c1);
+              // the last pass (no terms kept) writes the step's sum
+              const RecRun<T> rr = ol == nullptr ? rec_run(op, traces, st) : RecRun<T>{nullptr, 0, 0};
+              recorded = recorded || rr.out != nullptr;
+              return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, j, first, a.data(), q.data(), el.gamma, el.c0, el.c1, rr);
             });
       } else if constexpr (K == 2 && BC == 0 && DIM == 3) {
         rc = faber_fused_passes<T>(op->stream, ns, S, Abuf, Bbuf, Cbuf, Dbuf, Ebuf, m, 2, final_term,
@@ -419,7 +435,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
       rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m, term_out);
     }
     if (rc != EXPW_OK) return rc;
-    if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+    if (!recorded && (rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
     if ((rc = guard_state<T>(op, S, (DIM + 1) * g.N)) != EXPW_OK) return rc;
   }
   return EXPW_OK;
@@ -451,13 +467,14 @@ int32_t rk4_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T* tra
     tn = t;
     // words per point: stage 1 reads u (nf) + c^2, writes y, sum (2 nf); stages 2-3 read
     // y, u, sum (3 nf) + c^2, write y, sum (2 nf); stage 4 reads y, sum + c^2, writes u
-    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, S, nullptr, Abuf, Cbuf, h2, s6, srcq(t));
-    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, S, Cbuf, Bbuf, Cbuf, h2, s3, srcq(t + 0.5 * dt));
-    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Bbuf, S, Cbuf, Abuf, Cbuf, h1, s3, srcq(t + 0.5 * dt));
-    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, nullptr, Cbuf, nullptr, S, T(0), s6, srcq(t + dt));
+    const RecRun<T> none{nullptr, 0, 0}, rr = rec_run(op, traces, st);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, S, nullptr, Abuf, Cbuf, h2, s6, srcq(t), none);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, S, Cbuf, Bbuf, Cbuf, h2, s3, srcq(t + 0.5 * dt), none);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (5 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Bbuf, S, Cbuf, Abuf, Cbuf, h1, s3, srcq(t + 0.5 * dt), none);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_RK4, (3 * nf + 1) * pb, k_rk4_stage<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, nullptr, Cbuf, nullptr, S, T(0), s6, srcq(t + dt), rr);
     int32_t rc = check_launch("rk4 stage");
     if (rc != EXPW_OK) return rc;
-    if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+    if (!rr.out && (rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
     if ((rc = guard_state<T>(op, S, (DIM + 1) * g.N)) != EXPW_OK) return rc;
   }
   return EXPW_OK;
@@ -475,10 +492,11 @@ int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T
     launch_timed(&op->prof, op->stream, EXPW_KERNEL_LEAPFROG_V, (1 + 2 * DIM) * pb, k_lf_v<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, static_cast<T>(dt));
     double q = 0.0;
     if (op->n_src > 0) q = dt * source_value(op, st, t, 0.5 * dt) * sc;
-    launch_timed(&op->prof, op->stream, EXPW_KERNEL_LEAPFROG_P, (DIM + 3) * pb, k_lf_p<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, static_cast<T>(dt), make_src<T>(op, q));
+    const RecRun<T> rr = rec_run(op, traces, st);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_LEAPFROG_P, (DIM + 3) * pb, k_lf_p<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, static_cast<T>(dt), make_src<T>(op, q), rr);
     int32_t rc = check_launch("leapfrog");
     if (rc != EXPW_OK) return rc;
-    if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+    if (!rr.out && (rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
     if ((rc = guard_state<T>(op, S, (DIM + 1) * g.N)) != EXPW_OK) return rc;
   }
   return EXPW_OK;
@@ -625,10 +643,12 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
     }
     int32_t rc = check_launch("arnoldi");
     if (rc != EXPW_OK) return rc;
+    RecRun<T> rr{nullptr, 0, 0};  // set when the combination records the receivers
     if (op->kry_mode == EXPW_EXPM_DEVICE) {
       // y = exp(dt H_k) e_1 and the combination without leaving the device
       launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, expm_kernel(k), dim3(1), dim3(expm_threads(k)), hess, k, dt, tol, scal + 1, kry_y, kry_keff);
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (k + 1.0) * ns * es, k_kry_combine_dev<T>, dim3(red_grid_for(ns)), dim3(kBlock), S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc);
+      rr = rec_run(op, traces, st);
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (k + 1.0) * ns * es, k_kry_combine_dev<T>, dim3(red_grid_for(ns)), dim3(kBlock), S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc, rr);
       op->last_keff = -1;  // on the device; read by expw_krylov_info
       if ((rc = check_launch("krylov exponential")) != EXPW_OK) return rc;
     } else {
@@ -660,7 +680,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
         if ((rc = check_launch("krylov combine")) != EXPW_OK) return rc;
       }
     }
-    if ((rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
+    if (!rr.out && (rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
     if ((rc = guard_state<T>(op, S, (DIM + 1) * g.N)) != EXPW_OK) return rc;
   }
   return EXPW_OK;
@@ -1035,6 +1055,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->guard = 0;
   op->n_rec = 0;
   op->rec_dev = nullptr;
+  op->rec_run_first = -1;
   op->taylor_p = std::max(1, std::min(8, max_p));
   op->fuse = 0;
   op->kry_mode = EXPW_EXPM_DEVICE;
@@ -1356,6 +1377,7 @@ int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* idx_dev) {
   if (n_rec == 0) {
     op->n_rec = 0;
     op->rec_dev = nullptr;
+    op->rec_run_first = -1;
     return EXPW_OK;
   }
   if (!idx_dev) return fail(EXPW_EINVAL, "NULL receiver array");
@@ -1364,10 +1386,14 @@ int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* idx_dev) {
       hipStreamSynchronize(op->stream) != hipSuccess)
     return fail(EXPW_EDEVICE, "receiver index read failed");
   const int64_t N = npts(op->g);
-  for (int r = 0; r < n_rec; ++r)
+  bool run = true;
+  for (int r = 0; r < n_rec; ++r) {
     if (h[r] < 0 || h[r] >= N) return fail(EXPW_EINVAL, "receiver %d index %lld out of range", r, (long long)h[r]);
+    run = run && h[r] == h[0] + r;
+  }
   op->n_rec = n_rec;
   op->rec_dev = idx_dev;
+  op->rec_run_first = run ? h[0] : -1;
   return EXPW_OK;
 }
 
@@ -1871,7 +1897,8 @@ int32_t pml_krylov_impl(expw_pml* op, T* S, double t0, double dt, int k, int64_t
     }
     k_kry_finish<<<1, kBlock, 0, op->stream>>>(P[c], nin, tol, scal + 1, hess + k * kHessLd + (k - 1), kry_sc + k);
     expm_kernel(k)<<<1, expm_threads(k), 0, op->stream>>>(hess, k, dt, tol, scal + 1, kry_y, kry_keff);
-    k_kry_combine_dev<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc);
+    k_kry_combine_dev<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc,
+                                                                      RecRun<T>{nullptr, 0, 0});
     if (int32_t rc = check_launch("pml krylov")) return rc;
     if (traces && op->n_rec > 0) {
       k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec, traces + st * op->n_rec);

@@ -46,6 +46,7 @@ struct FusedArgs {
   int32_t first;  // first pass of a step: acc = a_first * v0, no v_{j-2}
   int32_t tiles_x, tiles_y, band_w;
   T a[S], a_lo[S], cpp[S], q[S];
+  RecRun<T> rec;  // receivers recorded from the sum (last pass of a step only)
 };
 
 // One pass over tile (tx_, ty_) of the recurrence terms r0..S-1 of an S-term
@@ -216,6 +217,7 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
     if (gxx >= nx || gz >= nz) continue;
     const int gi = gz * nx + gxx;
     acc_out[gi] = sacc[t];
+    rec_run_put(c.rec, gi, sacc[t]);
     acc_out[N + gi] = sacc[TX * TY + t];
     acc_out[2 * N + gi] = sacc[2 * TX * TY + t];
   }
@@ -262,8 +264,9 @@ template <typename T, int S, int K>
 int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                      const T* vp, const T* vpp, const T* acc_in, T* out_last, T* out_prev,
                      T* acc_out, int j, bool first, const double* a, const double* q,
-                     double gamma, double c0, double c1) {
+                     double gamma, double c0, double c1, RecRun<T> rec) {
   FusedArgs<T, S> c{};
+  c.rec = rec;
   c.inv_gamma = static_cast<T>(1.0 / gamma);
   c.c0 = static_cast<T>(c0);
   c.first = first ? 1 : 0;
@@ -295,11 +298,11 @@ template <typename T, int K>
 int32_t launch_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                     const T* vp, const T* vpp, const T* acc_in, T* out_last, T* out_prev,
                     T* acc_out, int j, bool first, const double* a, const double* q,
-                    double gamma, double c0, double c1) {
+                    double gamma, double c0, double c1, RecRun<T> rec) {
 #define EXPW_PASS(S_)                                                                          \
   case S_:                                                                                     \
     return launch_fused<T, S_, K>(st, prof, g, src, vp, vpp, acc_in, out_last, out_prev,      \
-                                  acc_out, j, first, a, q, gamma, c0, c1);
+                                  acc_out, j, first, a, q, gamma, c0, c1, rec);
   if constexpr (sizeof(T) == 4 && K == 2) {
     switch (n) {
       EXPW_PASS(2) EXPW_PASS(3) EXPW_PASS(4) EXPW_PASS(5) EXPW_PASS(6) EXPW_PASS(7) EXPW_PASS(8)

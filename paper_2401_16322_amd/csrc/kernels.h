@@ -79,9 +79,10 @@ __global__ __launch_bounds__(kBlock) void k_faber_term(Geo<T, K, DIM> g, const T
 // One classical RK4 stage: k = H y + s(t_stage);
 //   ynext = u + cy k (if ynext), acc_out = (acc_in ? acc_in : u) + ca k.
 template <typename T, int K, int BC, int DIM>
+// (rec: receivers recorded from the pressure written to acc_out, in the last stage)
 __global__ __launch_bounds__(kBlock) void k_rk4_stage(Geo<T, K, DIM> g, const T* y, const T* u,
                                                       const T* acc_in, T* ynext, T* acc_out,
-                                                      T cy, T ca, Src<T> src) {
+                                                      T cy, T ca, Src<T> src, RecRun<T> rec) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   if (idx >= g.N) return;
   int64_t ic[3];
@@ -95,7 +96,9 @@ __global__ __launch_bounds__(kBlock) void k_rk4_stage(Geo<T, K, DIM> g, const T*
     const T ue = u ? u[e] : T(0);
     if (ynext) ynext[e] = ue + cy * o[f];
     const T base = acc_in ? acc_in[e] : ue;
-    acc_out[e] = base + ca * o[f];
+    const T r = base + ca * o[f];
+    acc_out[e] = r;
+    if (f == 0) rec_run_put(rec, idx, r);
   }
 }
 
@@ -125,7 +128,8 @@ __global__ __launch_bounds__(kBlock) void k_lf_v(Geo<T, K, DIM> g, T* x, T dt) {
 //   p <- ((1 - s_p dt/2) p - dt c2 sum_a D-_a v_a + dt s(t + dt/2)) / (1 + s_p dt/2)
 // (src.q carries dt g(t + dt/2) / h^d).
 template <typename T, int K, int BC, int DIM>
-__global__ __launch_bounds__(kBlock) void k_lf_p(Geo<T, K, DIM> g, T* x, T dt, Src<T> src) {
+__global__ __launch_bounds__(kBlock) void k_lf_p(Geo<T, K, DIM> g, T* x, T dt, Src<T> src,
+                                                 RecRun<T> rec) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   if (idx >= g.N) return;
   int64_t ic[3];
@@ -142,8 +146,10 @@ __global__ __launch_bounds__(kBlock) void k_lf_p(Geo<T, K, DIM> g, T* x, T dt, S
   }
   const T half = T(0.5) * dt;
   const T pc = x[idx];
-  x[idx] = ((T(1) - half * sp) * pc - dt * g.c2[idx] * div + src_value(src, idx)) /
-           (T(1) + half * sp);
+  const T pn = ((T(1) - half * sp) * pc - dt * g.c2[idx] * div + src_value(src, idx)) /
+               (T(1) + half * sp);
+  x[idx] = pn;
+  rec_run_put(rec, idx, pn);
 }
 
 // traces_row[r] = p[rec[r]]
@@ -395,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_kry_combine_dev(T* __restrict__ S,
                                                             int64_t ns, const double* y_dev,
                                                             const int* keff_dev,
                                                             const double* beta_dev,
-                                                            const double* sc) {
+                                                            const double* sc, RecRun<T> rec) {
   __shared__ double y[64];
   const int keff = *keff_dev;
   const double beta = *beta_dev;
@@ -405,7 +411,9 @@ __global__ __launch_bounds__(kBlock) void k_kry_combine_dev(T* __restrict__ S,
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     double acc = 0.0;
     for (int c = 0; c < keff; ++c) acc += y[c] * static_cast<double>(Q[c * ldq + i]);
-    S[i] = static_cast<T>(beta * acc);
+    const T v = static_cast<T>(beta * acc);
+    S[i] = v;
+    rec_run_put(rec, i, v);  // only pressure nodes (i < N) are on the run
   }
 }
 

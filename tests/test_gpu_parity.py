@@ -166,15 +166,23 @@ def test_leapfrog_matches_oracle(dtype, n):
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
 
 
-@pytest.mark.parametrize("method", ["faber", "krylov", "rk4", "leapfrog"])
-def test_receiver_traces_match_oracle(method):
+@pytest.mark.parametrize("layout", ["scattered", "run", "surface_row"])
+@pytest.mark.parametrize("method", ["faber", "faber13", "krylov", "rk4", "leapfrog"])
+def test_receiver_traces_match_oracle(method, layout):
+    """Scattered receivers are gathered after each step; consecutive ones (a run
+    that crosses a row end, or the whole surface row) are written by the step's
+    last kernel. faber13: passes of 4, 4, 4 terms and an unfused last term."""
     import torch
     case = make_case((80, 50), "float64", seed=10, max_k=10, n_src=2)
     g = case.prob.grid
-    rec = np.array([0, g.npts - 1, 5 * 80 + 7, 25 * 80 + 40, 49 * 80 + 79], dtype=np.int64)
+    rec = {"scattered": np.array([0, g.npts - 1, 5 * 80 + 7, 25 * 80 + 40, 49 * 80 + 79]),
+           "run": np.arange(5 * 80 + 70, 5 * 80 + 95),
+           "surface_row": np.arange(80)}[layout].astype(np.int64)
     case.op.set_receivers(rec)
     nst = 5
-    kw = {"faber": dict(m=12, p=case.p), "krylov": dict(k=10, p=case.p)}.get(method, {})
+    m = 13 if method == "faber13" else 12
+    method = "faber" if method == "faber13" else method
+    kw = {"faber": dict(m=m, p=case.p), "krylov": dict(k=10, p=case.p)}.get(method, {})
     dt = 1e-3 if method in ("faber", "krylov") else 3e-4
     U = to_dev(case, case.U0)
     tr = torch.zeros(nst * rec.size, dtype=torch.float64, device="cuda")
@@ -183,6 +191,35 @@ def test_receiver_traces_match_oracle(method):
                                        nsteps=nst, traces=tr)
     _, traces, _ = run(case.prob, method, case.U0, 0.02, dt, nst, receivers=rec, **kw)
     assert rel_l2(tr.cpu().numpy().reshape(nst, rec.size), traces) <= 1e-11
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("method", ["faber", "krylov", "krylov_host", "rk4", "leapfrog"])
+def test_receivers_on_a_run_equal_the_gathered_state(method, dtype):
+    """Receivers written by the step's last kernel hold exactly the values a
+    gather of the state gives: the same nodes as a run and in reverse order
+    (not a run, so gathered) give the same traces bit for bit, and the last
+    row equals the final state at the nodes."""
+    import torch
+    rec = np.arange(3 * 61 + 50, 3 * 61 + 90, dtype=np.int64)   # crosses a row end
+    outs = []
+    for order in (rec, rec[::-1].copy()):
+        case = make_case((61, 47), dtype, seed=12, max_k=12, n_src=1)
+        if method == "krylov_host":
+            case.op.set_krylov_expm("host")
+        case.op.set_receivers(order)
+        U = to_dev(case, case.U0)
+        nst = 4
+        tr = torch.zeros(nst * order.size, dtype=U.dtype, device="cuda")
+        name = "krylov" if method == "krylov_host" else method
+        args = [14] if name == "faber" else [12] if name == "krylov" else []
+        dt = 1e-3 if name in ("faber", "krylov") else 3e-4
+        getattr(case.op, "step_" + name)(U, 0.01, dt, *args, nsteps=nst, traces=tr)
+        case.op.sync()
+        t = tr.cpu().numpy().reshape(nst, order.size)
+        assert np.array_equal(t[-1], U.cpu().numpy()[order])
+        outs.append(t)
+    assert np.array_equal(outs[0], outs[1][:, ::-1])
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
