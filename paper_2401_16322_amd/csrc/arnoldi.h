@@ -3,8 +3,10 @@
 // projection).
 //
 // One cooperative launch runs the whole basis construction: each thread owns
-// UN elements of the flat augmented vector (element e = tid + u * threads),
-// and keeps its slices of w, q_0 and the newest basis vector in registers.
+// UN / (DIM + 1) grid points with all their fields (UN elements of the
+// augmented vector, the tail elements in pressure slots of points beyond the
+// grid), and keeps its slices of w, q_0 and the newest basis vector in
+// registers. A thread's matvec loads all operands of a point at once.
 // Columns are written unnormalized with their scale s_j = 1/h_{j+1,j}
 // (s_0 = 1), as in the launch-per-step path.
 //
@@ -216,38 +218,33 @@ __device__ __forceinline__ T ldn32(const T* x, uint32_t idx, uint32_t i, uint32_
                       static_cast<uint32_t>(sizeof(T)));
 }
 
-// (H x)_f at one point: field f = 0 (pressure) or 1 + a (velocity along a).
+// (H x) at one grid point for every field: out[0] the pressure, out[1 + a]
+// the velocity along a. No load depends on another or on a branch, so all of
+// the point's operands are in flight at once.
 template <typename T, int K, int BC, int DIM>
-__device__ __forceinline__ T apply_field(const Geo<T, K, DIM>& g, const Geo32& g32, const T* x,
-                                         uint32_t f, uint32_t idx, const uint32_t* ic) {
+__device__ __forceinline__ void apply_point_all(const Geo<T, K, DIM>& g, const Geo32& g32, const T* x,
+                                                uint32_t idx, const uint32_t* ic, T* out) {
   constexpr uint32_t es = sizeof(T);
-  if (f == 0) {
-    T div = T(0), sp = T(0);
+  T div = T(0), sp = T(0);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const T* v = x + (1 + a) * g.N;
+  for (int a = 0; a < DIM; ++a) {
+    const T* v = x + (1 + a) * g.N;
 #pragma unroll
-      for (int l = 1; l <= K; ++l)
-        div += g.w[l - 1] * (ldn32<T, BC>(v, idx, ic[a], g32.n[a], g32.st[a], l - 1) -
-                             ldn32<T, BC>(v, idx, ic[a], g32.n[a], g32.st[a], -l));
-      sp += ld_at(g.sint[a], ic[a] * es);
-    }
-    return -ld_at(g.c2, idx * es) * div - sp * ld_at(x, idx * es);
+    for (int l = 1; l <= K; ++l)
+      div += g.w[l - 1] * (ldn32<T, BC>(v, idx, ic[a], g32.n[a], g32.st[a], l - 1) -
+                           ldn32<T, BC>(v, idx, ic[a], g32.n[a], g32.st[a], -l));
+    sp += ld_at(g.sint[a], ic[a] * es);
   }
-  // velocity along axis f - 1, unrolled over the axes so that every array
-  // index is a compile-time constant
-  T res = T(0);
+  out[0] = -ld_at(g.c2, idx * es) * div - sp * ld_at(x, idx * es);
 #pragma unroll
-  for (int a = 0; a < DIM; ++a)
-    if (f == static_cast<uint32_t>(1 + a)) {
-      T dp = T(0);
+  for (int a = 0; a < DIM; ++a) {
+    T dp = T(0);
 #pragma unroll
-      for (int l = 1; l <= K; ++l)
-        dp += g.w[l - 1] * (ldn32<T, BC>(x, idx, ic[a], g32.n[a], g32.st[a], l) -
-                            ldn32<T, BC>(x, idx, ic[a], g32.n[a], g32.st[a], 1 - l));
-      res = -dp - ld_at(g.shalf[a], ic[a] * es) * ld_at(x + (1 + a) * g.N, idx * es);
-    }
-  return res;
+    for (int l = 1; l <= K; ++l)
+      dp += g.w[l - 1] * (ldn32<T, BC>(x, idx, ic[a], g32.n[a], g32.st[a], l) -
+                          ldn32<T, BC>(x, idx, ic[a], g32.n[a], g32.st[a], 1 - l));
+    out[1 + a] = -dp - ld_at(g.shalf[a], ic[a] * es) * ld_at(x + (1 + a) * g.N, idx * es);
+  }
 }
 
 struct ArnArgs {
@@ -295,6 +292,8 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     Geo<T, K, DIM> g, const T* __restrict__ S, T* Q, KrySrc src, const T* __restrict__ amp,
     ArnArgs a, unsigned long long* slots, int* err, double* hess, double* sc, double* beta_out) {
   constexpr int NW = kArnNT / 64;
+  static_assert(UN % (DIM + 1) == 0, "whole grid points per thread");
+  constexpr int UP = UN / (DIM + 1);  // grid points per thread
   __shared__ double s_scale[EXPW_MAX_KRYLOV + 1];
   // <q_i, q_l> for l < i < EXPW_MAX_KRYLOV, packed: entry i (i - 1) / 2 + l
   __shared__ double s_gt[EXPW_MAX_KRYLOV * (EXPW_MAX_KRYLOV - 1) / 2];
@@ -316,11 +315,23 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   unsigned seq = 0;
-  // element e = gtid + u * nthreads < naug <= UN * nthreads < 2^31 (host
-  // check), so element indices and byte offsets are 32-bit
+  // Thread gtid owns the grid points P_v = gtid + v * nthreads (v < UP) with
+  // all their fields: slot u = f * UP + v holds element f * N + P_v. The
+  // pressure slot of a point beyond the grid, P_v = N + t, holds tail element
+  // ns + t of the augmented vector (t < p). Every element has one slot
+  // (N + p <= UP * nthreads, host check), and naug < 2^31, so element indices
+  // and byte offsets are 32-bit.
   const uint32_t e0 = static_cast<uint32_t>(gtid), estep = static_cast<uint32_t>(nthreads);
   const uint32_t naug32 = static_cast<uint32_t>(a.naug), ns32 = static_cast<uint32_t>(a.ns);
   const uint32_t npts32 = static_cast<uint32_t>(g.N);
+  const uint32_t ntail32 = naug32 - ns32;
+  // element of slot u for the thread's first point p0, or ok = false
+  auto elem = [&](int u, uint32_t p0, bool& ok) -> uint32_t {
+    const uint32_t f = static_cast<uint32_t>(u / UP);
+    const uint32_t P = p0 + static_cast<uint32_t>(u % UP) * estep;
+    ok = P < npts32 || (f == 0 && P - npts32 < ntail32);
+    return P < npts32 ? f * npts32 + P : ns32 + (P - npts32);
+  };
   constexpr uint32_t kEs = sizeof(T);
   Geo32 g32;
 #pragma unroll
@@ -360,18 +371,19 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   double xx = 0.0;
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
-    const uint32_t e = e0 + u * estep;
+    bool ok;
+    const uint32_t e = elem(u, e0, ok);
     T v = T(0);
-    if (e < ns32)
+    if (ok && e < ns32)
       v = S[e];
-    else if (e + 1 == naug32 && a.tail2 > 0.0)
+    else if (ok && e + 1 == naug32 && a.tail2 > 0.0)
       v = T(1);
     q0[u] = v;
     xx += static_cast<double>(v) * static_cast<double>(v);
   }
   double beta = 0.0, inv = 0.0;
 
-  // the thread's first element, made opaque once per column (an empty asm):
+  // the thread's first point, made opaque once per column (an empty asm):
   // otherwise the per-element index math of all UN elements is hoisted out
   // of the column loop and held in registers for the whole kernel
   uint32_t ecur = e0;
@@ -379,8 +391,9 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     const T* qc = Q + col * a.ld;
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      const uint32_t e = ecur + u * estep;
-      dst[u] = (e < naug32) ? ld_at(qc, e * kEs) : T(0);
+      bool ok;
+      const uint32_t e = elem(u, ecur, ok);
+      dst[u] = ok ? ld_at(qc, e * kEs) : T(0);
     }
   };
   // fn(i, column) for the n stored columns first, first + step, ..., two
@@ -416,15 +429,12 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       return j == 0 ? (cc == src.p - 1 ? T(1) : T(0)) : qcol[a.ns + cc];
     };
 #pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const uint32_t e = ecur + u * estep;
-      T v = T(0);
-      if (e < ns32) {
-        const uint32_t f = e / npts32;
-        const uint32_t idx = e - f * npts32;
+    for (int v = 0; v < UP; ++v) {
+      const uint32_t P = ecur + static_cast<uint32_t>(v) * estep;
+      if (P < npts32) {
         uint32_t ic[3];
-        ic[0] = idx % g32.n[0];
-        const uint32_t rest = idx / g32.n[0];
+        ic[0] = P % g32.n[0];
+        const uint32_t rest = P / g32.n[0];
         if (DIM == 2) {
           ic[1] = rest;
           ic[2] = 0;
@@ -432,22 +442,29 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
           ic[1] = rest % g32.n[1];
           ic[2] = rest / g32.n[1];
         }
-        v = apply_field<T, K, BC, DIM>(g, g32, xcol, f, idx, ic);
-        if (f == 0 && src.n > 0 && static_cast<int64_t>(idx) >= src.lo && static_cast<int64_t>(idx) <= src.hi) {
+        T out[DIM + 1];
+        apply_point_all<T, K, BC, DIM>(g, g32, xcol, P, ic, out);
+        if (src.n > 0 && static_cast<int64_t>(P) >= src.lo && static_cast<int64_t>(P) <= src.hi) {
           for (int s = 0; s < src.n; ++s)
-            if (src.idx[s] == static_cast<int64_t>(idx)) {
+            if (src.idx[s] == static_cast<int64_t>(P)) {
               double gt = 0.0;
               for (int cc = 0; cc < src.p; ++cc)
                 gt += src.G[cc] * static_cast<double>(tailv(cc));
-              v += static_cast<T>(gt * static_cast<double>(amp[s]));
+              out[0] += static_cast<T>(gt * static_cast<double>(amp[s]));
             }
         }
-        v *= sj;
-      } else if (e < naug32) {
-        const int cc = static_cast<int>(e - ns32);
-        v = (cc + 1 < src.p) ? tailv(cc + 1) * sj : T(0);  // J q_tail
+#pragma unroll
+        for (int f = 0; f <= DIM; ++f) w[f * UP + v] = out[f] * sj;
+      } else {
+        // beyond the grid: the pressure slot may hold tail element t, J q_tail
+        const uint32_t t = P - npts32;
+#pragma unroll
+        for (int f = 0; f <= DIM; ++f) w[f * UP + v] = T(0);
+        if (t < ntail32) {
+          const int cc = static_cast<int>(t);
+          w[v] = (cc + 1 < src.p) ? tailv(cc + 1) * sj : T(0);
+        }
       }
-      w[u] = v;
     }
     // first sweep: value i <= j is <w, Q_i>, value j + 1 + l (l < j) is
     // <Q_j, Q_l>; columns j-1 down to 1, so that the second sweep starts on
@@ -491,11 +508,12 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       inv = beta > 0.0 ? 1.0 / beta : 0.0;
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
-        const uint32_t e = ecur + u * estep;
+        bool ok;
+        const uint32_t e = elem(u, ecur, ok);
         q0[u] = static_cast<T>(static_cast<double>(q0[u]) * inv);
         w[u] = static_cast<T>(static_cast<double>(w[u]) * inv);
         s_qj[u][threadIdx.x] = q0[u];
-        if (e < naug32) st_at(Q, e * kEs, q0[u]);
+        if (ok) st_at(Q, e * kEs, q0[u]);
       }
       if (lead) {
         *beta_out = beta;
@@ -552,8 +570,9 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     T nrm = T(0);
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      const uint32_t e = ecur + u * estep;
-      if (e < naug32) st_at(wout, e * kEs, w[u]);
+      bool ok;
+      const uint32_t e = elem(u, ecur, ok);
+      if (ok) st_at(wout, e * kEs, w[u]);
       nrm += w[u] * w[u];
       s_qj[u][threadIdx.x] = w[u];
       if (j < NC) s_cache[j < NC ? j : 0][u][threadIdx.x] = w[u];

@@ -505,8 +505,9 @@ int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T
 // ---------------------------------------------------------------- Krylov step
 
 // Elements per thread of the persistent Arnoldi kernel for this problem (0 =
-// use the launch-per-step path): the augmented vector must fit in UN
-// registers per thread over all co-resident blocks.
+// use the launch-per-step path): every thread holds one or two grid points
+// with all their fields, so the grid points and the tail of the augmented
+// vector must fit in two points per thread over all co-resident blocks.
 template <typename T, int K, int BC, int DIM>
 int persistent_un(expw_op* op, int64_t naug) {
   if (!op->kry_persistent) return 0;
@@ -516,7 +517,7 @@ int persistent_un(expw_op* op, int64_t naug) {
         hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 8>), kArnNT, 0) !=
+            &per_cu, reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2 * (DIM + 1)>), kArnNT, 0) !=
             hipSuccess ||
         !coop || per_cu < 1) {
       op->coop_blocks = -1;
@@ -525,9 +526,14 @@ int persistent_un(expw_op* op, int64_t naug) {
     }
   }
   if (op->coop_blocks <= 0) return 0;
+  // one or two grid points per thread, with all their fields; the tail of
+  // the augmented vector sits in pressure slots beyond the grid
   const int64_t threads = static_cast<int64_t>(op->coop_blocks) * kArnNT;
-  for (int un : {2, 4, 6, 8})
-    if (naug <= un * threads) return un;
+  const int64_t npt = npts(op->g);
+  const int64_t ns = (DIM + 1) * npt;
+  if (naug >= (int64_t(1) << 31)) return 0;
+  for (int up : {1, 2})
+    if (npt + (naug - ns) <= up * threads) return up * (DIM + 1);
   return 0;
 }
 
@@ -554,10 +560,8 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   const T* ap = amp;
   void* args[] = {&gg, &Sp, &Qp, &kk, &ap, &aa, &slots, &err, &hess, &sc, &beta_out};
   const void* fn = nullptr;
-  if (un == 2) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2>);
-  else if (un == 4) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 4>);
-  else if (un == 6) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 6>);
-  else fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 8>);
+  if (un == DIM + 1) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, DIM + 1>);
+  else fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2 * (DIM + 1)>);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int slot = op->prof.acquire(EXPW_KERNEL_KRYLOV_ARNOLDI, &e0, &e1);
   if (slot >= 0) (void)hipEventRecord(e0, op->stream);
