@@ -506,8 +506,9 @@ int32_t leapfrog_impl(expw_op* op, T* S, double t0, double dt, int64_t nsteps, T
 
 // Elements per thread of the persistent Arnoldi kernel for this problem (0 =
 // use the launch-per-step path): every thread holds one or two grid points
-// with all their fields, so the grid points and the tail of the augmented
-// vector must fit in two points per thread over all co-resident blocks.
+// (three in 2D) with all their fields, so the grid points and the tail of the
+// augmented vector must fit in that many points per thread over all
+// co-resident blocks.
 template <typename T, int K, int BC, int DIM>
 int persistent_un(expw_op* op, int64_t naug) {
   if (!op->kry_persistent) return 0;
@@ -532,8 +533,8 @@ int persistent_un(expw_op* op, int64_t naug) {
   const int64_t npt = npts(op->g);
   const int64_t ns = (DIM + 1) * npt;
   if (naug >= (int64_t(1) << 31)) return 0;
-  for (int up : {1, 2})
-    if (npt + (naug - ns) <= up * threads) return up * (DIM + 1);
+  for (int up : {1, 2, 3})
+    if ((up < 3 || DIM == 2) && npt + (naug - ns) <= up * threads) return up * (DIM + 1);
   return 0;
 }
 
@@ -561,7 +562,8 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   void* args[] = {&gg, &Sp, &Qp, &kk, &ap, &aa, &slots, &err, &hess, &sc, &beta_out};
   const void* fn = nullptr;
   if (un == DIM + 1) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, DIM + 1>);
-  else fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2 * (DIM + 1)>);
+  else if (un == 2 * (DIM + 1)) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2 * (DIM + 1)>);
+  else if constexpr (DIM == 2) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 9>);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int slot = op->prof.acquire(EXPW_KERNEL_KRYLOV_ARNOLDI, &e0, &e1);
   if (slot >= 0) (void)hipEventRecord(e0, op->stream);

@@ -144,6 +144,41 @@ def test_krylov_persistent_at_full_1001x501_size(dtype):
     assert rel_l2(outs[0], ref) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("path", ["persistent", "launches"])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,order,bc", [((17, 13, 11), 4, "zero"), ((40, 31), 8, "zero"),
+                                        ((14, 12, 10), 4, "periodic"), ((36, 28), 8, "periodic"),
+                                        ((9, 8, 7), 8, "zero")])
+def test_krylov_3d_order8_periodic_match_oracle(n, order, bc, dtype, path):
+    """Both Krylov paths in 3D (four fields per grid point in the persistent
+    kernel), at order 8 and with periodic ghosts."""
+    case = make_case(n, dtype, order=order, bc=bc, src=(bc == "zero"), seed=21, max_k=12)
+    case.op.set_krylov_persistent(path == "persistent")
+    U = to_dev(case, case.U0)
+    case.op.step_krylov(U, 0.02, 1e-3, 12, 2)
+    ref, _, _ = run(case.prob, "krylov", case.U0, 0.02, 1e-3, 2, k=12, p=case.p)
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_krylov_persistent_three_points_per_thread(dtype):
+    """1001 x 650 points: more than two grid points per thread of the
+    persistent kernel (three in 2D), against the launch-per-step path and the
+    oracle."""
+    import torch
+    case = make_case((1001, 650), dtype, seed=31, max_k=16)
+    outs = []
+    for persistent in (True, False):
+        case.op.set_krylov_persistent(persistent)
+        U = to_dev(case, case.U0)
+        case.op.step_krylov(U, 0.02, 2e-3, 16, 2)
+        case.op.sync()
+        outs.append(U.cpu().numpy())
+    assert rel_l2(outs[0], outs[1]) <= (1e-13 if dtype == "float64" else 1e-6)
+    ref, _, _ = run(case.prob, "krylov", case.U0, 0.02, 2e-3, 2, k=16, p=case.p)
+    assert rel_l2(outs[0], ref) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n", [(60, 41), (17, 13, 11)])
 def test_rk4_matches_oracle(dtype, n):
