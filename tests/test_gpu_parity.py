@@ -160,6 +160,27 @@ def test_krylov_3d_order8_periodic_match_oracle(n, order, bc, dtype, path):
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("n,src", [((509, 515), True), ((512, 512), True), ((512, 512), False),
+                                   ((511, 513), True)])
+def test_krylov_persistent_slot_boundaries(n, src):
+    """Grids at the edges of the persistent kernel's layout (with 256 workgroups
+    of 1024 threads: 262,144 threads): 509 x 515 + 8 tail elements fill one
+    point per thread up to the last threads; 512 x 512 needs a second point
+    per thread and puts the tail in the second slot of the first threads;
+    511 x 513 + 8 just overflows one point per thread. Against the
+    launch-per-step path."""
+    import torch
+    case = make_case(n, "float64", seed=41, max_k=8, src=src)
+    outs = []
+    for persistent in (True, False):
+        case.op.set_krylov_persistent(persistent)
+        U = to_dev(case, case.U0)
+        case.op.step_krylov(U, 0.02, 2e-3, 8, 2)
+        case.op.sync()
+        outs.append(U.cpu().numpy())
+    assert rel_l2(outs[0], outs[1]) <= 1e-13
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_krylov_persistent_three_points_per_thread(dtype):
     """1001 x 650 points: more than two grid points per thread of the
