@@ -329,8 +329,9 @@ int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta);
 enum { EXPW_EXPM_DEVICE = 0, EXPW_EXPM_HOST = 1 };
 int32_t expw_set_krylov_expm(expw_op* op, int32_t mode);
 
-/* allow = 1 (default): when the augmented vectors fit in registers across one
- * cooperative grid, the Arnoldi process runs as one persistent launch with two
+/* allow = 1 (default): when the grid fits in registers across one cooperative
+ * grid (every thread holding up to two grid points with all their fields,
+ * three in 2D), the Arnoldi process runs as one persistent launch with two
  * grid-wide reductions per column (modified Gram-Schmidt's projections from
  * one batched reduction of the dots and the basis Gram entries, by forward
  * substitution); otherwise, and with allow = 0, one launch per matrix-vector
