@@ -130,30 +130,51 @@ __device__ __forceinline__ void collect_rows(const unsigned long long* row0,
   s1 = wave_sum_fixed(s1);
 }
 
+// Leader blocks of the grid-wide sums and the length of a leader's record.
+constexpr int kArnLeaders = 8;
+constexpr int kArnRecLen = 128;
+// words of the reduction area: kSlotBuffers records per leader, then
+// kSlotBuffers slot buffers of up to kArnMaxVals x kArnMaxBlocks words
+constexpr size_t kArnRecWords = static_cast<size_t>(kSlotBuffers) * kArnLeaders * kArnRecLen;
+static_assert(kArnMaxVals <= kArnRecLen, "a record holds every value of a reduction");
+
 // Grid-wide sums of nv values (1 <= nv <= nvmax, at most kArnMaxBlocks
-// blocks of NT threads). Before the call, lane 0 of wave w has put its wave's
-// partial of value v in wpart[v][w]. On return every thread sees the totals
-// in tot[0..nv). Each total is added in a fixed order, the same in every
-// block: a block's partial is the sum of its waves in order; block b's partial
-// goes to lane b % 64 of the wave that collects the value, each lane adds its
-// blocks in increasing order, and the lanes are added by a fixed DPP tree.
-// slots holds kSlotBuffers buffers of nvmax x gridDim.x words (row v = value
-// v), all kSlotEmpty at launch; seq numbers the barriers of the launch
-// (1, 2, ...). after() runs in every thread once this block has arrived:
-// loads it issues overlap the wait (the s_waitcnt before the arrival waits
-// for every outstanding memory operation, so loads issued earlier would be
-// waited for there).
+// blocks of NT threads), in two levels. Before the call, lane 0 of wave w has
+// put its wave's partial of value v in wpart[v][w]. Every block stores its
+// partials into its slots; leader blocks 0..kArnLeaders-1 collect every
+// block's partials and store the totals into their record; every other block
+// b waits for the record of leader b % kArnLeaders. So only the leaders poll
+// the slots (fewer polls of the same lines than when every block collects
+// everything) and the others poll one short record. On return every thread
+// sees the totals in tot[0..nv). Each total is added in a fixed order: a
+// block's partial is the sum of its waves in order; block b's partial goes to
+// lane b % 64 of the wave that collects the value, each lane adds its blocks
+// in increasing order, and the lanes are added by a fixed DPP tree; the
+// followers take the leaders' bits.
+// area holds the kSlotBuffers x kArnLeaders records of kArnRecLen words, then
+// kSlotBuffers buffers of nvmax x gridDim.x words (row v = value v), all
+// kSlotEmpty at launch; seq numbers the barriers of the launch (1, 2, ...).
+// after() runs in every thread once this block has arrived: loads it issues
+// overlap the wait (the s_waitcnt before the arrival waits for every
+// outstanding memory operation, so loads issued earlier would be waited for
+// there).
 template <int NT, typename F>
 __device__ __forceinline__ void grid_sum_vec(int nv, int nvmax, const double (*wpart)[NT / 64],
-                                             double* tot, unsigned long long* slots, unsigned seq,
+                                             double* tot, unsigned long long* area, unsigned seq,
                                              unsigned spin_limit, int* err, F&& after) {
   static_assert(NT % 64 == 0 && NT <= 1024, "block of whole waves");
   constexpr int NW = NT / 64;
   constexpr int PER = kArnMaxBlocks / 64;
   const int nb = static_cast<int>(gridDim.x);
   const size_t buf = static_cast<size_t>(nvmax) * nb;
+  unsigned long long* slots = area + kArnRecWords;
   unsigned long long* cur = slots + (seq % kSlotBuffers) * buf;
   unsigned long long* prev = slots + ((seq + kSlotBuffers - 1) % kSlotBuffers) * buf;
+  const int leader = static_cast<int>(blockIdx.x) % kArnLeaders;
+  const bool is_leader = static_cast<int>(blockIdx.x) < kArnLeaders;
+  unsigned long long* rcur = area + ((seq % kSlotBuffers) * kArnLeaders + leader) * kArnRecLen;
+  unsigned long long* rprev =
+      area + (((seq + kSlotBuffers - 1) % kSlotBuffers) * kArnLeaders + leader) * kArnRecLen;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __builtin_amdgcn_s_waitcnt(0);  // this thread's coherent stores have completed
   __syncthreads();                // ... and so have the block's; wave partials are in LDS
@@ -164,33 +185,61 @@ __device__ __forceinline__ void grid_sum_vec(int nv, int nvmax, const double (*w
     st_coherent(cur + static_cast<size_t>(threadIdx.x) * nb + blockIdx.x, bits);
   }
   after();
-  // wave 0 alone waits for value 0 of every block (a block stores all its
-  // values at once, so the other rows are then complete or nearly so); one
-  // polling wave per block keeps the waiting traffic small
-  if (wid == 0) {
-    double s0, s1;
-    collect_rows<PER>(cur, cur, false, nb, lane, spin_limit, err, s0, s1);
-    if (lane == 0) tot[0] = s0;
-  }
-  if (nv > 1) {
-    __syncthreads();
-    // values 1..nv-1: wave w takes values 1 + w and 1 + w + NW, then the
-    // next 2 NW
-    for (int v0 = 1 + wid; v0 < nv; v0 += 2 * NW) {
-      const int v1 = v0 + NW;
-      const bool two = v1 < nv;
+  if (is_leader) {
+    // wave 0 alone waits for value 0 of every block (a block stores all its
+    // values at once, so the other rows are then complete or nearly so)
+    if (wid == 0) {
       double s0, s1;
-      collect_rows<PER>(cur + static_cast<size_t>(v0) * nb, cur + static_cast<size_t>(two ? v1 : v0) * nb,
-                        two, nb, lane, spin_limit, err, s0, s1);
-      if (lane == 0) {
-        tot[v0] = s0;
-        if (two) tot[v1] = s1;
+      collect_rows<PER>(cur, cur, false, nb, lane, spin_limit, err, s0, s1);
+      if (lane == 0) tot[0] = s0;
+    }
+    if (nv > 1) {
+      __syncthreads();
+      // values 1..nv-1: wave w takes values 1 + w and 1 + w + NW, then the
+      // next 2 NW
+      for (int v0 = 1 + wid; v0 < nv; v0 += 2 * NW) {
+        const int v1 = v0 + NW;
+        const bool two = v1 < nv;
+        double s0, s1;
+        collect_rows<PER>(cur + static_cast<size_t>(v0) * nb, cur + static_cast<size_t>(two ? v1 : v0) * nb,
+                          two, nb, lane, spin_limit, err, s0, s1);
+        if (lane == 0) {
+          tot[v0] = s0;
+          if (two) tot[v1] = s1;
+        }
       }
     }
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < nv) {
+      const double t = tot[threadIdx.x];
+      st_coherent(rcur + threadIdx.x, (t != t) ? 0x7FF8000000000000ull : __double_as_longlong(t));
+    }
+    // every follower has stored its slot of this barrier, so it has read this
+    // leader's record of the previous one
+    if (static_cast<int>(threadIdx.x) < nvmax) st_coherent(rprev + threadIdx.x, kSlotEmpty);
+  } else if (wid == 0) {
+    // the leader's record: lane v polls value v (nv <= kArnMaxVals < 2 * 64)
+    unsigned long long x0 = lane < nv ? ld_coherent(rcur + lane) : 0ull;
+    unsigned long long x1 = lane + 64 < nv ? ld_coherent(rcur + lane + 64) : 0ull;
+    unsigned polls = 0;
+    for (;;) {
+      if (!__any((lane < nv && x0 == kSlotEmpty) || (lane + 64 < nv && x1 == kSlotEmpty))) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++polls > spin_limit ||
+          ((polls & 1023u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      if (lane < nv && x0 == kSlotEmpty) x0 = ld_coherent(rcur + lane);
+      if (lane + 64 < nv && x1 == kSlotEmpty) x1 = ld_coherent(rcur + lane + 64);
+    }
+    if (lane < nv) tot[lane] = __longlong_as_double(x0);
+    if (lane + 64 < nv) tot[lane + 64] = __longlong_as_double(x1);
   }
   __syncthreads();
-  // all blocks arrived at this barrier, so all have read barrier seq-1's
-  // values; the stores complete before this block's next arrival (s_waitcnt)
+  // all blocks arrived at this barrier, so the leaders have read every
+  // block's values of barrier seq-1; the stores complete before this block's
+  // next arrival (s_waitcnt)
   if (static_cast<int>(threadIdx.x) < nvmax)
     st_coherent(prev + static_cast<size_t>(threadIdx.x) * nb + blockIdx.x, kSlotEmpty);
 }

@@ -140,7 +140,7 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
   L.scal = off; off = align_up(off + 64 * sizeof(double));
   L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
   L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
-  L.bar = off; off = align_up(off + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks * sizeof(unsigned long long));  // grid reduction slots
+  L.bar = off; off = align_up(off + (kArnRecWords + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks) * sizeof(unsigned long long));  // grid reduction records and slots
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -552,7 +552,7 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   aa.tol = tol;
   aa.nvmax = std::max(2, 2 * k - 1);
   aa.spin_limit = 1u << 20;  // about a second of polling
-  const int nslots = kSlotBuffers * aa.nvmax * op->coop_blocks;
+  const int nslots = static_cast<int>(kArnRecWords) + kSlotBuffers * aa.nvmax * op->coop_blocks;
   k_fill_u64<<<(nslots + 255) / 256, 256, 0, op->stream>>>(slots, nslots, kSlotEmpty);
   Geo<T, K, DIM> gg = g;
   const T* Sp = S;
