@@ -131,7 +131,7 @@ __device__ __forceinline__ void collect_rows(const unsigned long long* row0,
 }
 
 // Leader blocks of the grid-wide sums and the length of a leader's record.
-constexpr int kArnLeaders = 8;
+constexpr int kArnLeaders = 4;  // per launch at 1001x501, k = 16, FP32: 4 leaders 326-330 us, 2: 333-335, 8: 336, 16: 336-340
 constexpr int kArnRecLen = 128;
 // words of the reduction area: kSlotBuffers records per leader, then
 // kSlotBuffers slot buffers of up to kArnMaxVals x kArnMaxBlocks words
