@@ -32,11 +32,13 @@
 // each block's partial is its own arrival word. Slots start out holding a
 // signalling-NaN pattern that no arithmetic produces; block b stores its
 // partial of value v (after waiting for its earlier stores, s_waitcnt 0) into
-// slot (v, b) of the barrier's buffer, and every block waits until each slot
-// no longer holds that pattern, taking the value it finds. Three buffers
-// rotate: when barrier s completes, every block has read the values of
-// barrier s-1, so each block then restores the pattern in its slots of that
-// buffer, which is next written at barrier s+2. Every wait is bounded: a wait
+// slot (v, b) of the barrier's buffer; a few leader blocks wait until each
+// slot no longer holds that pattern, take the values they find, and store
+// the totals into their records (the same convention), which the other
+// blocks poll. Three buffers rotate: when barrier s completes, the leaders
+// have read every value of barrier s-1, so each block then restores the
+// pattern in its slots of that buffer, which is next written at barrier s+2
+// (and each leader its record of barrier s-1). Every wait is bounded: a wait
 // longer than spin_limit polls sets *err and gives up, and once *err is set
 // no wait lasts more than 1024 polls, so every wave always reaches the end of
 // the kernel.
