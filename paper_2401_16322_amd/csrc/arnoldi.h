@@ -188,18 +188,10 @@ __device__ __forceinline__ void grid_sum_vec(int nv, int nvmax, const double (*w
   }
   after();
   if (is_leader) {
-    // wave 0 alone waits for value 0 of every block (a block stores all its
-    // values at once, so the other rows are then complete or nearly so)
-    if (wid == 0) {
-      double s0, s1;
-      collect_rows<PER>(cur, cur, false, nb, lane, spin_limit, err, s0, s1);
-      if (lane == 0) tot[0] = s0;
-    }
-    if (nv > 1) {
-      __syncthreads();
-      // values 1..nv-1: wave w takes values 1 + w and 1 + w + NW, then the
-      // next 2 NW
-      for (int v0 = 1 + wid; v0 < nv; v0 += 2 * NW) {
+    // every wave polls its rows at once (only the few leaders poll the
+    // slots): wave w takes values w and w + NW, then the next 2 NW
+    {
+      for (int v0 = wid; v0 < nv; v0 += 2 * NW) {
         const int v1 = v0 + NW;
         const bool two = v1 < nv;
         double s0, s1;
