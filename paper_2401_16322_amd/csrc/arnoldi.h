@@ -333,7 +333,8 @@ __device__ __forceinline__ void wave_sum_pair(double a, double b, double& sa, do
 template <typename T, int K, int BC, int DIM, int UN>
 __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     Geo<T, K, DIM> g, const T* __restrict__ S, T* Q, KrySrc src, const T* __restrict__ amp,
-    ArnArgs a, unsigned long long* slots, int* err, double* hess, double* sc, double* beta_out) {
+    ArnArgs a, unsigned long long* slots, int* err, unsigned* seq_io, double* hess, double* sc,
+    double* beta_out) {
   constexpr int NW = kArnNT / 64;
   static_assert(UN % (DIM + 1) == 0, "whole grid points per thread");
   constexpr int UP = UN / (DIM + 1);  // grid points per thread
@@ -357,7 +358,10 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kArnNT + threadIdx.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-  unsigned seq = 0;
+  // barriers continue the numbering of the previous launch (mod 3): its last
+  // slot buffer and records are restored by this launch's first barrier, so
+  // the area needs no fill between launches
+  unsigned seq = __hip_atomic_load(seq_io, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // Thread gtid owns the grid points P_v = gtid + v * nthreads (v < UP) with
   // all their fields: slot u = f * UP + v holds element f * N + P_v. The
   // pressure slot of a point beyond the grid, P_v = N + t, holds tail element
@@ -633,6 +637,8 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     if (threadIdx.x == 0) s_scale[j + 1] = s;  // read after the next reduction's barriers
     sj = static_cast<T>(s);
   }
+  // every block has read seq_io: they all passed the barriers since
+  if (lead) st_coherent(seq_io, seq % static_cast<unsigned>(kSlotBuffers));
 }
 
 __global__ void k_zero_u32(unsigned* p, int n) {

@@ -60,6 +60,7 @@ struct expw_op {
   int kry_mode;
   int kry_persistent;  // 1: allow the persistent Arnoldi kernel
   int coop_blocks;     // co-resident blocks of the persistent kernel (0 = unknown)
+  int arn_nvmax_clean;  // reduction area consistent for this nvmax (0: fill before the next launch)
   int last_keff;
   double last_beta;
   expw::Profiler prof;
@@ -552,14 +553,21 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   aa.tol = tol;
   aa.nvmax = std::max(2, 2 * k - 1);
   aa.spin_limit = 1u << 20;  // about a second of polling
-  const int nslots = static_cast<int>(kArnRecWords) + kSlotBuffers * aa.nvmax * op->coop_blocks;
-  k_fill_u64<<<(nslots + 255) / 256, 256, 0, op->stream>>>(slots, nslots, kSlotEmpty);
+  // the kernel leaves the area consistent for the next launch with the same
+  // layout (nvmax); it is filled on first use and when the layout changes
+  unsigned* seq_io = reinterpret_cast<unsigned*>(err) + 2;
+  if (op->arn_nvmax_clean != aa.nvmax) {
+    const int nslots = static_cast<int>(kArnRecWords) + kSlotBuffers * aa.nvmax * op->coop_blocks;
+    k_fill_u64<<<(nslots + 255) / 256, 256, 0, op->stream>>>(slots, nslots, kSlotEmpty);
+    k_zero_u32<<<1, 64, 0, op->stream>>>(seq_io, 1);
+    op->arn_nvmax_clean = aa.nvmax;
+  }
   Geo<T, K, DIM> gg = g;
   const T* Sp = S;
   T* Qp = Q;
   KrySrc kk = ks;
   const T* ap = amp;
-  void* args[] = {&gg, &Sp, &Qp, &kk, &ap, &aa, &slots, &err, &hess, &sc, &beta_out};
+  void* args[] = {&gg, &Sp, &Qp, &kk, &ap, &aa, &slots, &err, &seq_io, &hess, &sc, &beta_out};
   const void* fn = nullptr;
   if (un == DIM + 1) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, DIM + 1>);
   else if (un == 2 * (DIM + 1)) fn = reinterpret_cast<const void*>(k_arnoldi_persistent<T, K, BC, DIM, 2 * (DIM + 1)>);
@@ -1067,6 +1075,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   op->kry_mode = EXPW_EXPM_DEVICE;
   op->kry_persistent = 1;
   op->coop_blocks = 0;
+  op->arn_nvmax_clean = 0;
   op->last_keff = 0;
   op->last_beta = 0.0;
 
@@ -1485,7 +1494,10 @@ int32_t expw_sync_status(expw_op* op) {
   const char* flag = op->ws + op->off_kry + 136 * sizeof(double) + 8 * sizeof(int);
   if (hipMemcpy(flags, flag, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(EXPW_EDEVICE, "status read failed");
-  if (flags[0]) return fail(EXPW_EDEVICE, "a grid barrier of the persistent Arnoldi kernel timed out");
+  if (flags[0]) {
+    op->arn_nvmax_clean = 0;  // the reduction area is filled again before the next launch
+    return fail(EXPW_EDEVICE, "a grid barrier of the persistent Arnoldi kernel timed out");
+  }
   if (flags[1]) {
     // reported once: the flag is cleared for the next steps
     k_zero_u32<<<1, 64, 0, op->stream>>>(reinterpret_cast<unsigned*>(guard_flag(op)), 1);

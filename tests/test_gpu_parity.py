@@ -182,6 +182,26 @@ def test_krylov_persistent_slot_boundaries(n, src):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+def test_krylov_persistent_consecutive_launches(dtype):
+    """One operator, many persistent launches: the reduction area is carried
+    from launch to launch (barrier numbering continued) and filled again only
+    when the Krylov dimension changes its layout. Against the launch-per-step
+    path over the same sequence of calls."""
+    outs = []
+    for persistent in (True, False):
+        case = make_case((70, 52), dtype, seed=51, max_k=12, n_src=2)
+        case.op.set_krylov_persistent(persistent)
+        U = to_dev(case, case.U0)
+        t = 0.01
+        for k, nst in ((12, 4), (5, 3), (12, 2), (12, 1), (7, 5)):
+            case.op.step_krylov(U, t, 1e-3, k, nst)
+            t += nst * 1e-3
+        case.op.sync()
+        outs.append(U.cpu().numpy())
+    assert rel_l2(outs[0], outs[1]) <= (1e-13 if dtype == "float64" else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_krylov_persistent_three_points_per_thread(dtype):
     """1001 x 650 points: more than two grid points per thread of the
     persistent kernel (three in 2D), against the launch-per-step path and the
