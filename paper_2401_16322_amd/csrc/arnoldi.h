@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   }
   g32.N = npts32;
   // per-thread partial sums and the update w -= h q run in T (FP32 partials
-  // cover UN <= 8 products); every sum across threads is in FP64
+  // cover UN <= 9 products); every sum across threads is in FP64
 
   auto put = [&](int v, double x) {
     x = wave_sum_fixed(x);
