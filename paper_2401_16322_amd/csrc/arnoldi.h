@@ -596,6 +596,10 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       }
     }
     __syncthreads();
+    // the last column's orthogonalized vector would only give h_{k,k-1} and
+    // Q_k, which neither the exponential of the k x k matrix H_k nor the
+    // combination of Q_0..Q_{k-1} uses
+    if (j + 1 == a.k) break;
     // second sweep: w -= h_i q_i in order i = 0..j, then |w|^2
     {
       const T h0 = static_cast<T>(s_h[0]);

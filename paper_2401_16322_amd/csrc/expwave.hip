@@ -579,9 +579,10 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
                                                   op->stream);
   if (slot >= 0) {
     (void)hipEventRecord(e1, op->stream);
-    // reads S; per column: Q_j with its stencil and c^2, Q_1..Q_j; writes Q_0..Q_k
+    // reads S; per column: Q_j with its stencil and c^2, Q_1..Q_j; writes
+    // Q_0..Q_{k-1} (the last column's vector is not orthogonalized or stored)
     const double es = sizeof(T);
-    const double words = ns + naug + k * (2.0 * naug + g.N) + naug * (k * (k - 1) / 2.0);
+    const double words = ns + naug + k * (naug + g.N) + (k - 1.0) * naug + naug * (k * (k - 1) / 2.0);
     op->prof.commit(slot, EXPW_KERNEL_KRYLOV_ARNOLDI, words * es);
   }
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "persistent Arnoldi launch: %s", hipGetErrorString(e));
