@@ -28,9 +28,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-# the CPU baseline (the FP64 oracle) runs on grids of at most this many points;
-# a step of a larger grid takes the oracle minutes and many GB, so none is given
-CPU_BASELINE_MAX_PTS = 2_000_000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_2401_16322_amd", "csrc")
 
@@ -77,14 +74,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="layered2d_1001x501")
+    ap.add_argument("--workload", default="layered3d_256")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--faber-m", type=int, default=0, help="0 = the workload's degree")
     ap.add_argument("--krylov-k", type=int, default=16)
     ap.add_argument("--fuse", type=int, default=0)
     ap.add_argument("--order", type=int, default=4, choices=[4, 8],
                     help="stencil order (4: the workloads' stencil; 8: the paper's)")
-    ap.add_argument("--methods", default="faber,krylov,rk4,leapfrog")
+    ap.add_argument("--methods", default="",
+                    help="comma list of faber,krylov,rk4,leapfrog (default: faber in 3D, all in 2D)")
     ap.add_argument("--pml-path", type=int, default=0,
                     help="PML term kernel: 0 automatic, 1 per node, 2 LDS tiles, 3 two terms per pass")
     ap.add_argument("--operator", default="pv", choices=["pv", "pml"],
@@ -97,6 +95,8 @@ def parse():
     ap.add_argument("--tts", type=int, default=1,
                     help="1 = also measure time-to-solution at --tts-tol over the full simulated time")
     ap.add_argument("--tts-tol", type=float, default=1e-5)
+    ap.add_argument("--tts-workload", default="layered2d_1001x501",
+                    help="workload of the time-to-solution measurement (its oracle reference is stored)")
     ap.add_argument("--tts-dtypes", default="f32,f64")
     ap.add_argument("--tts-repeats", type=int, default=3)
     return ap.parse_args()
@@ -113,7 +113,7 @@ def bench_pml(args, w):
     tdt = torch.float32 if args.dtype == "f32" else torch.float64
     dev = torch.device("cuda:0")
     nx, ny = w.n
-    c2 = torch.tensor(w.velocity() ** 2, dtype=tdt, device=dev)
+    c2 = torch.tensor(w.c2(), dtype=tdt, device=dev)
     op = xw.PMLOperator(nx, ny, w.h, c2, abc_cells=w.abc_cells, beta0=w.sigma_max,
                         max_taylor_p=w.taylor_p)
     op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)
@@ -178,7 +178,7 @@ def bench_pml(args, w):
                                      "(rocprofv3 counters, copy-calibrated)",
                      "avg_term_us": round(ms * 1e3 / (args.steps * m), 3)},
     }
-    if args.cpu_steps > 0 and w.npts <= CPU_BASELINE_MAX_PTS:
+    if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline_pml(w, args, c2.double().cpu().numpy())
     if args.tts:
         out["time_to_solution"] = pml_time_to_solution(w, args)
@@ -207,6 +207,7 @@ def cpu_baseline_pml(w, args, c2_np):
         el = time.perf_counter() - t0
     total = nx * ny * args.faber_m * nsteps
     return {"value": total / el, "unit": "grid-pt matvecs/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu(),
             "sample": f"{nsteps} Faber steps (m = {args.faber_m}) of the PML operator on {w.name}, "
                       f"FP64 numpy, {el:.1f} s"}
 
@@ -229,7 +230,7 @@ def pml_time_to_solution(w, args):
     L, T, snap_every = w.abc_cells, w.T, 0.5
     nsnap = int(round(T / snap_every))
     rec = w.receiver_nodes()
-    c2_np = w.velocity() ** 2
+    c2_np = w.c2()
 
     kmax = max(k for m_, k in PML_TTS_CANDIDATES if m_ == "krylov")
 
@@ -312,6 +313,27 @@ def pml_time_to_solution(w, args):
     return out
 
 
+def host_cpu():
+    """CPU model name and the host's logical CPU count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "os_cpu_count": os.cpu_count()}
+
+
+def ceiling(nbytes=1 << 30, reps=10):
+    """Measured HBM ceiling: the library's plain stream kernels (read, copy,
+    triad) over 1 GiB arrays, plain and non-temporal, in GB/s."""
+    from paper_2401_16322_amd import expwave as xw
+    return {k: round(v, 1) for k, v in xw.stream_ceiling(nbytes, reps).items()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -330,19 +352,45 @@ def main():
         args.faber_m = w.faber_m
     if args.operator == "pml":
         return bench_pml(args, w)
+    if not args.methods:
+        # the 3D workload is stated for Faber; the 2D ones step every method
+        args.methods = "faber" if w.ndim == 3 else "faber,krylov,rk4,leapfrog"
     methods = [m for m in args.methods.split(",") if m]
     tdt = torch.float32 if args.dtype == "f32" else torch.float64
     dev = torch.device("cuda:0")
-    c2_np = w.velocity() ** 2
+    c2_np = w.c2()
     c2 = torch.tensor(c2_np, dtype=tdt, device=dev)
+    kmax = max(args.krylov_k, 1) if "krylov" in methods else 0
     op = xw.Operator(w.n, w.h, c2, order=args.order, abc_cells=w.abc_cells,
-                     sigma_max=w.sigma_max, max_krylov_k=max(args.krylov_k, 1),
-                     max_taylor_p=w.taylor_p)
+                     sigma_max=w.sigma_max, max_krylov_k=kmax, max_taylor_p=w.taylor_p)
+    try:
+        out = bench_steps(args, w, methods, op, c2_np, tdt, dev)
+    finally:
+        op.close()
+    ceil = ceiling()
+    out["roofline"]["ceiling_GBps"] = ceil
+    best = max(ceil.get("copy", 0.0), ceil.get("copy_nt", 0.0))
+    out["roofline"]["frac_of_copy_ceiling"] = round(out["roofline"]["achieved"] / best, 4) if best else None
+    if args.tts:
+        out["time_to_solution"] = time_to_solution(get_workload(args.tts_workload), args)
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(w, methods, out["_mvos"], out["_dts"], args, c2_np,
+                                           w.receiver_nodes())
+    out.pop("_mvos")
+    out.pop("_dts")
+    print(json.dumps(out, allow_nan=False), flush=True)
+
+
+def bench_steps(args, w, methods, op, c2_np, tdt, dev):
+    """The timed steps of every method on one operator; the bench line
+    without the ceiling, time-to-solution and CPU baseline."""
+    import torch
     op.set_tuning(args.fuse)
     src = w.source_node()
     op.set_source_ricker([src], [1.0], w.f_peak, w.t_delay, w.taylor_p)
     rec = w.receiver_nodes()
-    op.set_receivers(rec)
+    if rec.size:
+        op.set_receivers(rec)
     npts = w.npts
     if args.calib_copy_mb > 0:
         nel = args.calib_copy_mb * (1 << 20) // 4
@@ -358,7 +406,8 @@ def main():
     mvos = {"faber": args.faber_m, "krylov": args.krylov_k, "rk4": 4, "leapfrog": 1}
     states = {m: torch.zeros(nstate, dtype=tdt, device=dev) for m in methods}
     total_steps = args.warmup + args.steps
-    traces = {m: torch.zeros(total_steps * max(rec.size, 1), dtype=tdt, device=dev) for m in methods}
+    traces = {m: (torch.zeros(total_steps * rec.size, dtype=tdt, device=dev) if rec.size else None)
+              for m in methods}
     tcur = {m: 0.0 for m in methods}
     counter = {m: 0 for m in methods}
 
@@ -388,7 +437,7 @@ def main():
     torch.cuda.synchronize()
     kt_warm = op.timing()
     dom = max(kt_warm, key=lambda k: kt_warm[k][0])
-    # timed region: HIP events only around launches of the dominant kernel class
+    # timed region: HIP events attached to the launches of the dominant kernel class
     op.set_timing([dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -397,6 +446,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt = op.timing()
+    op.sync()
     for m in methods:
         if not torch.isfinite(states[m]).all():
             raise RuntimeError(f"{m}: non-finite wavefield")
@@ -420,8 +470,7 @@ def main():
                          "kernel_ms_per_step": round(kms, 4),
                          "kernel_grid_pt_matvecs_per_s":
                              (npts * mvos[m] / (kms * 1e-3)) if kms > 0 else None}
-
-    out = {
+    return {
         "metric": METRIC,
         "value": value,
         "unit": "grid-pt matvecs/s",
@@ -442,18 +491,14 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom, w.name, args.dtype),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
-                     "avg_launch_us": round(1e3 * ms / launches, 3),
+                     "algorithmic_bytes_per_launch": round(nbytes / launches) if launches else None,
+                     "avg_launch_us": round(1e3 * ms / launches, 3) if launches else None,
                      "launches": launches},
         "methods": per_method,
         "kernels": kernels,
+        "_mvos": mvos,
+        "_dts": dts,
     }
-    if args.tts:
-        del states, traces
-        op.close()
-        out["time_to_solution"] = time_to_solution(w, c2_np, args)
-    if args.cpu_steps > 0 and w.npts <= CPU_BASELINE_MAX_PTS:
-        out["cpu_baseline"] = cpu_baseline(w, methods, mvos, dts, args, c2_np, rec)
-    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 # dt ladder (ms): every value divides the 0.5 s snapshot spacing
@@ -463,25 +508,51 @@ TTS_CANDIDATES = (("faber", 8), ("faber", 16), ("faber", 24), ("faber", 32), ("f
                   ("rk4", 4), ("leapfrog", 1))
 
 
-def time_to_solution(w, c2_np, args):
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def load_oracle_run(name):
+    """Snapshots and parameters of a stored oracle run (tests/golden, written
+    by tests/golden/make_oracle_runs.py), or None when it is not there."""
+    path = os.path.join(GOLDEN, f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(str(z["meta"]))
+        snaps = [z[f"p{k}"] for k in range(1, meta["snapshots_done"] + 1)]
+    return meta, snaps
+
+
+def time_to_solution(w, args):
     """Largest dt per method and order whose pressure snapshots every 0.5 s
     up to the final time stay within tol (relative L2 over the physical
-    domain, damping layer excluded) of a converged FP64 reference; the wall
-    time of that whole run (receiver recording included) is the time to
-    solution. The reference is the library's FP64 Faber path at degree 40
-    and dt = 0.5 ms, checked against dt = 1 ms; that path is itself held to
-    the FP64 oracle by the parity tests (a CPU oracle run at this size would
-    take about an hour)."""
+    domain, damping layer excluded) of the FP64 oracle's converged solution
+    (Faber degree 40, dt = 1 ms, stored; checked against the oracle at
+    dt = 0.5 ms); the wall time of that whole run (receiver recording
+    included) is the time to solution. The library's own FP64 run of the
+    reference configuration is reported beside it as a cross-check."""
     import torch
     from paper_2401_16322_amd import expwave as xw
+    ref_run = load_oracle_run("layered1001_ref_faber40_dt1")
+    if ref_run is None or ref_run[0]["workload"] != w.name:
+        return {"skipped": "no stored oracle reference for " + w.name}
+    meta, ref_np = ref_run
+    if meta["snapshots_done"] * meta["snapshot_every"] < meta["T"] - 1e-9:
+        return {"skipped": "stored oracle reference incomplete"}
     dev = torch.device("cuda:0")
     L = w.abc_cells
     T = w.T
-    snap_every = 0.5
+    snap_every = meta["snapshot_every"]
     nsnap = int(round(T / snap_every))
     rec = w.receiver_nodes()
     src = w.source_node()
     npts = w.npts
+    c2_np = w.c2()
+    ref = [torch.tensor(r, dtype=torch.float64, device=dev) for r in ref_np]
+    check = load_oracle_run("layered1001_ref_faber40_dt0.5")
+    ref_check = None
+    if check is not None and check[0]["snapshots_done"] == meta["snapshots_done"]:
+        ref_check = max(float(np.linalg.norm(a - b) / np.linalg.norm(a)) for a, b in zip(ref_np, check[1]))
 
     def make_op(tdt, kmax):
         op = xw.Operator(w.n, w.h, torch.tensor(c2_np, dtype=tdt, device=dev),
@@ -496,12 +567,12 @@ def time_to_solution(w, c2_np, args):
         sl = tuple(slice(L, n - L) for n in reversed(w.n))
         return p[sl].double()
 
-    def run(op, tdt, method, order, dt, ref=None, tol=None):
-        """Full run; returns (max snapshot error, wall seconds, snapshots)."""
+    def run(op, tdt, method, order, dt, tol):
+        """Full run; returns (max snapshot error, wall seconds)."""
         state = torch.zeros((w.ndim + 1) * npts, dtype=tdt, device=dev)
         nper = int(round(snap_every / dt))
         traces = torch.zeros(nper * max(rec.size, 1), dtype=tdt, device=dev)
-        snaps, err = [], 0.0
+        err = 0.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(nsnap):
@@ -515,63 +586,63 @@ def time_to_solution(w, c2_np, args):
                 op.step_rk4(state, t, dt, nper, traces=tr)
             else:
                 op.step_leapfrog(state, t, dt, nper, traces=tr)
-            if ref is None:
-                snaps.append(interior(state).clone())
-            else:
-                # the error check is outside the method; it stops a failing run early
-                torch.cuda.synchronize()
-                t_pause = time.perf_counter()
-                r = ref[s]
-                e = (torch.linalg.vector_norm(interior(state) - r) / torch.linalg.vector_norm(r)).item()
-                if not np.isfinite(e):
-                    e = float("inf")
-                err = max(err, e)
-                t0 += time.perf_counter() - t_pause
-                if err > tol:
-                    break
+            # the error check is outside the method; it stops a failing run early
+            torch.cuda.synchronize()
+            t_pause = time.perf_counter()
+            r = ref[s]
+            e = (torch.linalg.vector_norm(interior(state) - r) / torch.linalg.vector_norm(r)).item()
+            if not np.isfinite(e):
+                e = float("inf")
+            err = max(err, e)
+            t0 += time.perf_counter() - t_pause
+            if err > tol:
+                break
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         op.sync()
-        return err, wall, snaps
+        return err, wall
 
-    # converged FP64 reference
+    # the library's FP64 run of the reference configuration, against the oracle's
     op64 = make_op(torch.float64, 0)
-    _, _, ref = run(op64, torch.float64, "faber", 40, 0.5e-3)
-    _, _, ref2 = run(op64, torch.float64, "faber", 40, 1.0e-3)
-    ref_check = max((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a)).item()
-                    for a, b in zip(ref, ref2))
-    op64.close()
+    try:
+        gpu_ref_err, _ = run(op64, torch.float64, "faber", meta["order"], meta["dt"], float("inf"))
+    finally:
+        op64.close()
 
     kmax = max(k for m, k in TTS_CANDIDATES if m == "krylov")
     mvo_step = {"rk4": 4, "leapfrog": 1}
-    out = {"tol": args.tts_tol, "T_s": T,
+    out = {"workload": w.name, "tol": args.tts_tol, "T_s": T,
            "snapshots_s": [snap_every * (i + 1) for i in range(nsnap)],
            "error": "relative L2 of pressure over the physical domain, max over snapshots",
-           "reference": {"method": "faber", "order": 40, "dt_ms": 0.5, "dtype": "f64",
-                         "vs_dt_1ms": ref_check},
+           "reference": {"source": "FP64 oracle (tests/golden/oracle_layered1001_ref_faber40_dt1.npz)",
+                         "method": "faber", "order": meta["order"], "dt_ms": meta["dt"] * 1e3,
+                         "vs_oracle_dt_0.5ms": ref_check,
+                         "library_f64_same_config_vs_oracle": gpu_ref_err},
            "dt_ladder_ms": list(TTS_DTS_MS)}
     for dname in [d for d in args.tts_dtypes.split(",") if d]:
         tdt = {"f32": torch.float32, "f64": torch.float64}[dname]
         op = make_op(tdt, kmax)
         results = []
-        for method, order in TTS_CANDIDATES:
-            best, tried = None, []
-            for dt_ms in TTS_DTS_MS:
-                dt = dt_ms * 1e-3
-                err, _, _ = run(op, tdt, method, order, dt, ref=ref, tol=args.tts_tol)
-                tried.append([dt_ms, float(f"{err:.3g}") if np.isfinite(err) else None])
-                if err <= args.tts_tol:
-                    walls = [run(op, tdt, method, order, dt, ref=ref, tol=args.tts_tol)[1]
-                             for _ in range(args.tts_repeats)]
-                    nsteps = int(round(T / dt))
-                    best = {"method": method, "order": order, "dt_ms": dt_ms, "max_rel_l2": err,
-                            "wall_s": float(np.median(walls)), "n_steps": nsteps,
-                            "n_op": nsteps * mvo_step.get(method, order), "n_mem": nsteps}
-                    break
-            r = best if best else {"method": method, "order": order, "dt_ms": None}
-            r["tried"] = tried  # [dt_ms, error at the first snapshot that failed, or the max]
-            results.append(r)
-        op.close()
+        try:
+            for method, order in TTS_CANDIDATES:
+                best, tried = None, []
+                for dt_ms in TTS_DTS_MS:
+                    dt = dt_ms * 1e-3
+                    err, _ = run(op, tdt, method, order, dt, args.tts_tol)
+                    tried.append([dt_ms, float(f"{err:.3g}") if np.isfinite(err) else None])
+                    if err <= args.tts_tol:
+                        walls = [run(op, tdt, method, order, dt, args.tts_tol)[1]
+                                 for _ in range(args.tts_repeats)]
+                        nsteps = int(round(T / dt))
+                        best = {"method": method, "order": order, "dt_ms": dt_ms, "max_rel_l2": err,
+                                "wall_s": float(np.median(walls)), "n_steps": nsteps,
+                                "n_op": nsteps * mvo_step.get(method, order), "n_mem": nsteps}
+                        break
+                r = best if best else {"method": method, "order": order, "dt_ms": None}
+                r["tried"] = tried  # [dt_ms, error at the first snapshot that failed, or the max]
+                results.append(r)
+        finally:
+            op.close()
         ok = [r for r in results if r.get("dt_ms")]
         out[dname] = {"runs": results,
                       "fastest": min(ok, key=lambda r: r["wall_s"]) if ok else None}
@@ -579,7 +650,8 @@ def time_to_solution(w, c2_np, args):
 
 
 def cpu_baseline(w, methods, mvos, dts, args, c2_np, rec):
-    """The FP64 oracle on the same composite step, single-threaded."""
+    """The FP64 oracle on the same step, single-threaded: --cpu-steps steps,
+    stopping after the first step that ends past about 30 s of CPU time."""
     from threadpoolctl import threadpool_limits
     from oracle.operator import Grid
     from oracle.source import PointSources
@@ -590,17 +662,23 @@ def cpu_baseline(w, methods, mvos, dts, args, c2_np, rec):
     states = {m: np.zeros(g.nstate) for m in methods}
     kw = {"faber": dict(m=args.faber_m, p=w.taylor_p, ellipse=ell),
           "krylov": dict(k=args.krylov_k, p=w.taylor_p)}
+    done = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         for s in range(args.cpu_steps):
             for m in methods:
                 states[m] = step(prob, m, states[m], s * dts[m], dts[m], **kw.get(m, {}))
-                _ = states[m][rec]
+                if rec.size:
+                    _ = states[m][rec]
+            done += 1
+            if time.perf_counter() - t0 > 30.0:
+                break
         el = time.perf_counter() - t0
-    total = w.npts * sum(mvos[m] for m in methods) * args.cpu_steps
+    total = w.npts * sum(mvos[m] for m in methods) * done
     return {"value": total / el, "unit": "grid-pt matvecs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{args.cpu_steps} composite steps ({'+'.join(methods)}) of {w.name}, "
-                      f"FP64 numpy, {el:.1f} s"}
+            "host_cpu": host_cpu(),
+            "sample": f"{done} step(s) ({'+'.join(methods)}) of {w.name} from rest, "
+                      f"FP64 numpy on one thread, {el:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -365,6 +365,17 @@ int32_t expw_set_timing(expw_op* op, int32_t class_mask);
  * launch, halos not counted) since timing was enabled. */
 int32_t expw_get_timing(expw_op* op, double* ms, int64_t* launches, double* bytes);
 
+/* Bandwidth ceiling (not part of the method): times reps launches of a plain
+ * stream kernel over arrays of `bytes` bytes (a positive multiple of 16;
+ * device pointers, 16-byte aligned) on `stream`, after one warm-up launch,
+ * with HIP events, and returns the mean time per launch in ms (synchronizes).
+ * kind 0: read a (one partial sum per 4096 vectors of 16 bytes written to c,
+ * which must hold bytes / 4096 floats); 1: copy c = a; 2: triad c = a + 2 b.
+ * nontemporal != 0 marks loads and stores as streaming (no reuse). HBM bytes
+ * per launch: bytes (read), 2 bytes (copy), 3 bytes (triad). */
+int32_t expw_stream_bench(int32_t kind, int32_t nontemporal, const void* a, const void* b, void* c,
+                          size_t bytes, int32_t reps, void* stream, double* ms_per_launch);
+
 /* ---------------------------------------------- the paper's PML operator
  *
  * Sec. 2, 2.1, 2.2 and the appendix on the free surface: the 2D acoustic

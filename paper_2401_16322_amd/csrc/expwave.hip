@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -18,6 +20,7 @@
 #include "kernels.h"
 #include "pml.h"
 #include "profiler.h"
+#include "stream.h"
 
 struct expw_op {
   expw_grid g;
@@ -989,7 +992,28 @@ int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t step0)
   return EXPW_OK;
 }
 
+// Set by an atexit handler registered at the first handle creation. Handles
+// destroyed after exit() has begun (by a later atexit handler or a static
+// destructor) skip their HIP calls: the runtime may already be gone, and the
+// process is about to release every device resource anyway.
+std::atomic<bool> g_exiting{false};
+
+void note_exit() { g_exiting.store(true); }
+
+void watch_exit() {
+  static const bool registered = (std::atexit(note_exit), true);
+  (void)registered;
+}
+
+bool runtime_usable() { return !g_exiting.load(); }
+
 void batch_drop_graph(expw_batch* b) {
+  if (!runtime_usable()) {
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_steps = 0;
+    return;
+  }
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->gexec = nullptr;
@@ -1044,6 +1068,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   if (!ws) return fail(EXPW_EINVAL, "workspace_dev is NULL");
   if (ws_bytes < need) return fail(EXPW_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return fail(EXPW_EINVAL, "workspace must be 256-byte aligned");
+  watch_exit();
   expw_op* op = new expw_op();
   op->g = *g;
   stagger_weights(g->order, op->alpha, &op->K);
@@ -1128,6 +1153,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
 }
 
 int32_t expw_op_destroy(expw_op* op) {
+  if (op && runtime_usable()) op->prof.release();
   delete op;
   return EXPW_OK;
 }
@@ -1259,6 +1285,7 @@ int32_t expw_batch_create(expw_op* const* ops, int32_t n_ops, const int32_t* m, 
   if (int32_t rc = expw_batch_table_bytes(n_ops, &ops[0]->g, &need)) return rc;
   if (table_bytes < need) return fail(EXPW_EINVAL, "batch table too small (%zu < %zu bytes)", table_bytes, need);
   if (reinterpret_cast<uintptr_t>(table_dev) % kAlign) return fail(EXPW_EINVAL, "batch table must be 256-byte aligned");
+  watch_exit();
   auto* b = new (std::nothrow) expw_batch();
   if (!b) return fail(EXPW_ENOMEM, "out of host memory");
   b->n = n_ops;
@@ -1505,6 +1532,49 @@ int32_t expw_sync_status(expw_op* op) {
     if (hipStreamSynchronize(op->stream) != hipSuccess) return fail(EXPW_EDEVICE, "guard reset failed");
     return fail(EXPW_ENONFINITE, "a state held a NaN or infinite value after a step (guard)");
   }
+  return EXPW_OK;
+}
+
+int32_t expw_stream_bench(int32_t kind, int32_t nontemporal, const void* a, const void* b, void* c,
+                          size_t bytes, int32_t reps, void* stream, double* ms_per_launch) {
+  if (kind < 0 || kind > 2) return fail(EXPW_EINVAL, "kind must be 0 (read), 1 (copy) or 2 (triad)");
+  if (!a || !c || (kind == 2 && !b) || !ms_per_launch) return fail(EXPW_EINVAL, "NULL argument");
+  if (bytes == 0 || bytes % 16 != 0) return fail(EXPW_EINVAL, "bytes must be a positive multiple of 16");
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c)) % 16)
+    return fail(EXPW_EINVAL, "arrays must be 16-byte aligned");
+  if (reps < 1) return fail(EXPW_EINVAL, "reps must be >= 1");
+  const int64_t n4 = static_cast<int64_t>(bytes / 16);
+  const unsigned blocks = stream_blocks(n4);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto launch = [&]() {
+    const float4* A = static_cast<const float4*>(a);
+    const float4* B = static_cast<const float4*>(b);
+    float4* C = static_cast<float4*>(c);
+#define EXPW_STREAM(K_, NT_) hipLaunchKernelGGL((k_stream<K_, NT_>), dim3(blocks), dim3(kStreamNT), 0, st, A, B, C, n4, 2.0f)
+    if (nontemporal) {
+      if (kind == 0) EXPW_STREAM(0, true); else if (kind == 1) EXPW_STREAM(1, true); else EXPW_STREAM(2, true);
+    } else {
+      if (kind == 0) EXPW_STREAM(0, false); else if (kind == 1) EXPW_STREAM(1, false); else EXPW_STREAM(2, false);
+    }
+#undef EXPW_STREAM
+  };
+  launch();  // warm-up
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(EXPW_EDEVICE, "stream bench: event creation failed");
+  }
+  (void)hipEventRecord(e0, st);
+  for (int r = 0; r < reps; ++r) launch();
+  (void)hipEventRecord(e1, st);
+  hipError_t e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(EXPW_EDEVICE, "stream bench: %s", hipGetErrorString(e));
+  if (int32_t rc = check_launch("stream bench")) return rc;
+  *ms_per_launch = static_cast<double>(ms) / reps;
   return EXPW_OK;
 }
 

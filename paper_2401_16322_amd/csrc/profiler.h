@@ -15,8 +15,14 @@ namespace expw {
 
 class Profiler {
  public:
-  ~Profiler() {
+  // The destructor makes no HIP call (a handle may be destroyed while the
+  // process exits, after the runtime has shut down); release() frees the
+  // events while the runtime is alive.
+  void release() {
     for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+    pool_.clear();
+    recs_.clear();
+    used_ = 0;
   }
 
   // mask: bit k enables timing of kernel class k (0 = off)

@@ -41,7 +41,7 @@ def _operator(w, dtype, kmax):
     import torch
     from paper_2401_16322_amd.expwave import Operator
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    c2 = torch.tensor(w.velocity() ** 2, dtype=tdt, device="cuda")
+    c2 = torch.tensor(w.c2(), dtype=tdt, device="cuda")
     op = Operator(w.n, w.h, c2, abc_cells=w.abc_cells, sigma_max=w.sigma_max,
                   max_krylov_k=kmax, max_taylor_p=w.taylor_p)
     op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, w.taylor_p)

@@ -96,6 +96,7 @@ SIGNATURES = {
     "expw_set_krylov_expm": (_i32, [_vp, _i32]),
     "expw_set_krylov_persistent": (_i32, [_vp, _i32]),
     "expw_set_timing": (_i32, [_vp, _i32]),
+    "expw_stream_bench": (_i32, [_i32, _i32, _vp, _vp, _vp, _sz, _i32, _vp, _pd]),
     "expw_get_timing": (_i32, [_vp, _pd, _pi64, _pd]),
     "expw_pml_check_grid": (_i32, [_ppml]),
     "expw_pml_spectrum_rectangle": (_i32, [_ppml, _dbl, _pd, _pd]),
@@ -389,6 +390,30 @@ def expw_set_krylov_expm(op, mode):
 
 def expw_set_krylov_persistent(op, allow):
     _check(load().expw_set_krylov_persistent(op, int(bool(allow))))
+
+
+def expw_stream_bench(kind, nontemporal, a_ptr, b_ptr, c_ptr, nbytes, reps, stream):
+    ms = ctypes.c_double()
+    _check(load().expw_stream_bench(int(kind), int(nontemporal), a_ptr, b_ptr, c_ptr, int(nbytes),
+                                    int(reps), stream, ctypes.byref(ms)))
+    return ms.value
+
+
+def stream_ceiling(nbytes=1 << 30, reps=10):
+    """HBM GB/s of the plain read, copy and triad streams over arrays of
+    nbytes bytes (torch device memory), plain and non-temporal."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    st = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for kind, name, traffic in ((0, "read", 1), (1, "copy", 2), (2, "triad", 3)):
+        for nt in (0, 1):
+            ms = expw_stream_bench(kind, nt, a.data_ptr(), b.data_ptr(), c.data_ptr(), nbytes, reps, st)
+            out[name + ("_nt" if nt else "")] = traffic * nbytes / (ms * 1e-3) / 1e9
+    del a, b, c
+    return out
 
 
 def expw_set_timing(op, class_mask):

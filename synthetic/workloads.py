@@ -47,6 +47,11 @@ class Workload:
             return homogeneous_velocity(self.n, self.c_homog)
         return layered_velocity(self.n, self.h, self.seed)
 
+    def c2(self):
+        """c^2 (float64 array) with values representable in FP32: the FP32
+        and FP64 runs of a workload then see exactly the same medium."""
+        return (self.velocity() ** 2).astype(np.float32).astype(np.float64)
+
     def flat_index(self, node):
         idx = 0
         stride = 1
@@ -85,6 +90,13 @@ WORKLOADS = {
         name="layered2d_1001x501", n=(1001, 501), h=10.0, abc_cells=40, sigma_max=300.0,
         f_peak=15.0, t_delay=0.18, T=2.0, src=(500, 42), medium="layered",
         seed=2000, faber_m=16, dt=2e-3, taylor_p=8, receivers="surface_row"),
+    # 241x161 layered box without an absorbing layer (zero ghost values on
+    # every side, so the wavefield keeps its energy): a grid small enough for
+    # whole oracle runs of 1000 and more steps (long-run parity)
+    "layered2d_241x161": Workload(
+        name="layered2d_241x161", n=(241, 161), h=10.0, abc_cells=0, sigma_max=0.0,
+        f_peak=15.0, t_delay=0.18, T=2.0, src=(120, 42), medium="layered",
+        seed=2400, faber_m=16, dt=2e-3, taylor_p=8, receivers="surface_row"),
     # 8192x4096 layered: an added HBM-bound 2D shape (working set far above the
     # 256 MB Infinity Cache), same generator and layer as the 1001x501 medium
     "layered2d_8192x4096": Workload(

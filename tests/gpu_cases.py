@@ -34,6 +34,9 @@ def make_case(n, dtype="float64", order=4, bc="zero", abc=4, smax=300.0, src=Tru
     else:
         c = layered_velocity(n, 10.0, seed=seed + 100)
     c2 = c ** 2
+    if dtype == "float32":
+        # the values of the FP32 device array are the input both sides see
+        c2 = c2.astype(np.float32).astype(np.float64)
     rng = np.random.default_rng(seed)
     nodes = tuple(int(v) for v in rng.choice(g.npts, size=n_src, replace=False)) if src else ()
     amps = tuple(amp * float(a) for a in rng.uniform(0.5, 1.5, len(nodes)))

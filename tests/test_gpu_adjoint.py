@@ -27,7 +27,7 @@ def test_faber_adjoint_step_matches_oracle(dtype, m):
     import torch
     case = make_case((70, 45), dtype, seed=32, n_src=2)
     g = case.prob.grid
-    ell = case.op.ellipse
+    ell = case.prob.ellipse()
     lam0 = np.random.default_rng(3).normal(size=g.nstate)
     u = case.U0
     lam = to_dev(case, lam0)
@@ -69,7 +69,7 @@ def test_checkpointed_misfit_gradient_matches_oracle(dtype):
     nst, dt, m, t0 = 12, 2e-3, 8, 0.04
     d_obs = rng.normal(size=(nst, rec.size)) * 1e-4
     U0 = 1e-3 * case.U0
-    ell = case.op.ellipse
+    ell = case.prob.ellipse()
     L, grad, lam, traces = gpu_misfit_gradient(case.op, to_dev(case, U0), t0, dt, nst, m,
                                                torch.tensor(d_obs), checkpoint_every=5)
     Lr, gr, lr = misfit_gradient(case.prob, U0, t0, dt, nst, m, rec, d_obs, p=case.p, ellipse=ell)

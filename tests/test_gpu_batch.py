@@ -44,7 +44,7 @@ def test_batch_matches_single_shots_and_oracle(dtype):
         assert rel_l2(tr.cpu().numpy(), tr1.cpu().numpy()) <= tight
     c, rec = cases[2]
     Uref, trref, _ = run(c.prob, "faber", c.U0, t0, dts[2], nst, receivers=rec, m=ms[2], p=c.p,
-                         ellipse=c.op.ellipse)
+                         ellipse=c.prob.ellipse())
     assert rel_l2(states[2].cpu().numpy(), Uref) <= TOL[dtype]
     assert rel_l2(traces[2].cpu().numpy().reshape(nst, -1), trref) <= TOL[dtype]
     b.close()
@@ -61,7 +61,7 @@ def test_batch_3d_and_trace_offset():
     torch.cuda.synchronize()
     for (c, rec), S, m, dt in zip(cases, states, [5, 8], [2e-3, 1e-3]):
         Uref, _, _ = run(c.prob, "faber", c.U0, 0.03 + 2 * dt, dt, 2, m=m, p=c.p,
-                         ellipse=c.op.ellipse)
+                         ellipse=c.prob.ellipse())
         assert rel_l2(S.cpu().numpy(), Uref) <= 1e-11
     t = traces[0].cpu().numpy().reshape(4, -1)
     assert not np.any(t[:2]) and np.all(np.isfinite(t[2:])) and np.any(t[2:])

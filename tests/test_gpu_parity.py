@@ -125,7 +125,7 @@ def test_krylov_persistent_at_full_1001x501_size(dtype):
     from synthetic import get_workload, smooth_state
     w = get_workload("layered2d_1001x501")
     g = Grid(w.n, w.h, 4, abc_cells=w.abc_cells, sigma_max=w.sigma_max)
-    c2 = w.velocity() ** 2
+    c2 = w.c2()
     prob = Problem(g, c2, PointSources((w.source_node(),), (1.0,), w.f_peak, w.t_delay))
     U0 = smooth_state(w.n, seed=2002, width_cells=12.0)
     tdt = torch.float64 if dtype == "float64" else torch.float32
@@ -311,7 +311,7 @@ def test_homogeneous_101_full_run(dtype):
     from synthetic import get_workload
     w = get_workload("homog2d_101")
     g = Grid(w.n, w.h, 4, abc_cells=w.abc_cells, sigma_max=w.sigma_max)
-    c2 = w.velocity() ** 2
+    c2 = w.c2()
     prob = Problem(g, c2, PointSources((w.source_node(),), (1.0,), w.f_peak, w.t_delay))
     tdt = torch.float64 if dtype == "float64" else torch.float32
     op = Operator(w.n, w.h, torch.tensor(c2, dtype=tdt, device="cuda"), abc_cells=w.abc_cells,
@@ -342,7 +342,7 @@ def test_layered_1001x501_steps_at_full_size():
     from synthetic import get_workload, smooth_state
     w = get_workload("layered2d_1001x501")
     g = Grid(w.n, w.h, 4, abc_cells=w.abc_cells, sigma_max=w.sigma_max)
-    c2 = w.velocity() ** 2
+    c2 = w.c2()
     prob = Problem(g, c2, PointSources((w.source_node(),), (1.0,), w.f_peak, w.t_delay))
     U0 = smooth_state(w.n, seed=2001, width_cells=12.0)
     rec = w.receiver_nodes()
@@ -495,7 +495,7 @@ def test_faber_3d_fused_matches_oracle_and_unfused(dtype, m):
     U1 = to_dev(case, case.U0)
     case.op.set_tuning(1)
     case.op.step_faber(U1, 0.04, dt, m, nst)
-    Uref, _, _ = run(prob, "faber", case.U0, 0.04, dt, nst, m=m, p=case.p, ellipse=case.op.ellipse)
+    Uref, _, _ = run(prob, "faber", case.U0, 0.04, dt, nst, m=m, p=case.p, ellipse=prob.ellipse())
     assert rel_l2(U.cpu().numpy(), Uref) <= TOL[dtype]
     assert rel_l2(U.cpu().numpy(), U1.cpu().numpy()) <= (1e-13 if dtype == "float64" else 2e-6)
 
@@ -516,6 +516,6 @@ def test_faber_order8_fused_matches_oracle_and_unfused(dtype, m, fuse):
     case.op.set_tuning(1)
     case.op.step_faber(U1, 0.04, dt, m, nst)
     ref, _, _ = run(case.prob, "faber", case.U0, 0.04, dt, nst, m=m, p=case.p,
-                    ellipse=case.op.ellipse)
+                    ellipse=case.prob.ellipse())
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
     assert rel_l2(U.cpu().numpy(), U1.cpu().numpy()) <= (1e-13 if dtype == "float64" else 2e-6)

@@ -30,7 +30,6 @@ def _case(nx, ny, dtype, seed, cells=6, beta0=150.0, src=True):
         pt = (ny // 3) * nx + nx // 2
         s = pml.PMLSources((pt,), (1.5,), 20.0, 0.05)
         op.set_source_ricker([pt], [1.5], 20.0, 0.05, 8)
-    # the oracle runs on the ellipse the library chose
     prob = pml.PMLProblem(g, c2, s, rect=None)
     return op, prob, U0, tdt
 
@@ -71,15 +70,9 @@ def test_faber_steps_with_source_and_receivers_match_oracle(dtype, m, path):
     op.step_faber(U, t0, dt, m, nst, traces=tr)
     op.sync()
     ref, traces, _ = run(prob, "faber", U0, t0, dt, nst, receivers=rec, m=m, p=8,
-                         ellipse=_step_ellipse(op, dtype))
+                         ellipse=prob.ellipse())
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
     assert rel_l2(tr.cpu().numpy().reshape(nst, -1), traces) <= TOL[dtype]
-
-
-def _step_ellipse(op, dtype):
-    from paper_2401_16322_amd import expwave as ew
-    gam, c0, c1 = op.ellipse
-    return ew.expw_step_ellipse(ew.EXPW_F32 if dtype == "float32" else ew.EXPW_F64, gam, c0, c1)
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
@@ -125,7 +118,7 @@ def test_faber_at_a_larger_grid_without_layer(dtype):
     U = torch.tensor(U0, dtype=tdt, device="cuda")
     op.step_faber(U, 0.0, 2e-3, 16, 1)
     op.sync()
-    ref, _, _ = run(prob, "faber", U0, 0.0, 2e-3, 1, m=16, p=8, ellipse=_step_ellipse(op, dtype))
+    ref, _, _ = run(prob, "faber", U0, 0.0, 2e-3, 1, m=16, p=8, ellipse=prob.ellipse())
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
 
 
