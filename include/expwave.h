@@ -108,6 +108,13 @@ int32_t expw_damping_profile(int64_t n, double h, int32_t cells, double sigma_ma
  * c^2 is c2_max: B = sqrt(c2_max) sqrt(ndim) (2/h) sum |alpha_l|, x_lo = -max damping. */
 int32_t expw_spectrum_rectangle(const expw_grid* grid, double c2_max, double* x_lo, double* B);
 
+/* The rectangle for caller-given damping profiles (layout of
+ * expw_op_create_profiles; NULL = the grid's quadratic layer): B as above,
+ * x_lo = -max(sum_a max_i sigma_a(x_i), max_a max_i sigma_a(x_i + h/2)). */
+int32_t expw_spectrum_rectangle_profiles(const expw_grid* grid, double c2_max,
+                                         const double* const* sigma_host, double* x_lo,
+                                         double* B);
+
 /* Faber ellipse (gamma, c0, c1) of the minimum-area ellipse around the
  * rectangle (Sec. 3.2: the parameters of F_1 = H/gamma - c0 I). */
 int32_t expw_ellipse(double x_lo, double B, double* gamma, double* c0, double* c1);
@@ -116,9 +123,11 @@ int32_t expw_ellipse(double x_lo, double B, double* gamma, double* c0, double* c
  * coefficients of exp(dt gamma (w + c0 + c1/w)). a has m+1 entries. */
 int32_t expw_faber_coefficients(double gamma, double c0, double c1, double dt, int32_t m, double* a);
 
-/* The ellipse a Faber step with state dtype runs with (see expw_step_faber):
- * 1/gamma, c0 and c1 rounded to that precision, gamma = 1/(rounded 1/gamma).
- * The identity for EXPW_F64. */
+/* The ellipse a Faber step on the PML operator with state dtype runs with
+ * (see expw_pml_step_faber): 1/gamma, c0 and c1 rounded to that precision,
+ * gamma = 1/(rounded 1/gamma); the identity for EXPW_F64. (Faber steps on the
+ * pressure/velocity operator compute every term in FP64 for both dtypes and
+ * run on the operator's ellipse as it is.) */
 int32_t expw_step_ellipse(int32_t dtype, double gamma, double c0, double c1, double* gamma_step,
                           double* c0_step, double* c1_step);
 
@@ -156,6 +165,21 @@ int32_t expw_expm(int32_t k, const double* A, double* E);
 int32_t expw_op_create(const expw_grid* grid, const void* c2_dev, int32_t max_krylov_k,
                        int32_t max_taylor_p, void* workspace_dev, size_t workspace_bytes,
                        void* hip_stream, expw_op** out);
+/* As expw_op_create, with caller-given damping profiles (Sec. 2: the
+ * absorbing term is a function of position on each axis; the reading here
+ * keeps it separable and on the diagonal): sigma_host holds 2 * ndim host
+ * pointers, entry 2a the values of axis a at the integer points x_i = i h and
+ * entry 2a + 1 at the half points (i + 1/2) h, each n[a] finite values >= 0
+ * (1/s), copied at this call. sigma_p = sum_a sigma_a(x_a) damps p and
+ * axis a's half-point values damp v_a. grid->abc_cells and sigma_max are not
+ * used for the profiles; sigma_host == NULL takes the quadratic layer of
+ * expw_op_create. The spectrum rectangle's x_lo is minus the largest damping
+ * these profiles give. Periodic ghosts require all-zero profiles
+ * (EXPW_EINVAL otherwise). */
+int32_t expw_op_create_profiles(const expw_grid* grid, const void* c2_dev,
+                                const double* const* sigma_host, int32_t max_krylov_k,
+                                int32_t max_taylor_p, void* workspace_dev, size_t workspace_bytes,
+                                void* hip_stream, expw_op** out);
 int32_t expw_op_destroy(expw_op* op);
 
 /* Stream for subsequent launches (hipStream_t as void*). */
@@ -217,10 +241,12 @@ int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* node_idx_d
 /* Advance the state nsteps steps of size dt starting at time t0 (step s runs
  * from t0 + s dt). traces_dev: NULL or an array of nsteps * n_rec elements.
  * Faber steps (Sec. 3.2, Faber recurrence and sum, degree m = m products with
- * the augmented matrix): the recurrence runs with 1/gamma, c0 and c1 of the
- * ellipse rounded to the state precision, and the coefficients are computed
- * in FP64 for that rounded ellipse (in FP32 this keeps the coefficients
- * consistent with the recurrence; expw_get_ellipse reports the unrounded one). */
+ * the augmented matrix): every term v_j is computed in FP64 from the stored
+ * values and stored in the state dtype, the partial sum is kept in FP64 (in
+ * the workspace between sweeps) and the step's result is rounded to the state
+ * dtype once. With FP32 states this keeps the rounding of a step to that of
+ * its stored terms: FP32 arithmetic inside a term, repeated on nearly the same
+ * data every step, would round coherently and accumulate over long runs. */
 int32_t expw_step_faber(expw_op* op, void* state_dev, double t0, double dt, int32_t m,
                         int64_t nsteps, void* traces_dev);
 /* Faber steps that also record every term at the receivers: the pressure of

@@ -54,6 +54,11 @@ class Grid:
     bc: str = "zero"         # "zero" ghost values, or "periodic" (closed-form tests)
     abc_cells: int = 0       # damping-layer thickness L in cells (delta = L h)
     sigma_max: float = 0.0   # beta_0 of the paper's profile (1/s)
+    # optional caller-given 1D damping profiles (1/s), 2 * ndim arrays: axis a
+    # at the integer points x_i = i h (entry 2a) and at the half points
+    # (i + 1/2) h (entry 2a + 1), each of n[a] values >= 0; when given they
+    # replace the quadratic profile of (abc_cells, sigma_max)
+    profiles: tuple = None
 
     @property
     def ndim(self):
@@ -104,13 +109,21 @@ def _broadcast_axis(grid, a, vec):
     return vec.reshape(shp)
 
 
+def axis_profiles(grid, a):
+    """(integer-point, half-point) damping values along axis a."""
+    if grid.profiles is not None:
+        return (np.asarray(grid.profiles[2 * a], dtype=np.float64),
+                np.asarray(grid.profiles[2 * a + 1], dtype=np.float64))
+    return (damping_profile(grid.n[a], grid.h, grid.abc_cells, grid.sigma_max, False),
+            damping_profile(grid.n[a], grid.h, grid.abc_cells, grid.sigma_max, True))
+
+
 def damping_fields(grid):
     """sigma_p on nodes (sum over axes) and sigma_a at the v_a points."""
     sig_p = np.zeros(grid.shape)
     sig_v = []
     for a in range(grid.ndim):
-        s_int = damping_profile(grid.n[a], grid.h, grid.abc_cells, grid.sigma_max, False)
-        s_half = damping_profile(grid.n[a], grid.h, grid.abc_cells, grid.sigma_max, True)
+        s_int, s_half = axis_profiles(grid, a)
         sig_p = sig_p + _broadcast_axis(grid, a, s_int)
         sig_v.append(np.broadcast_to(_broadcast_axis(grid, a, s_half), grid.shape))
     return sig_p, sig_v

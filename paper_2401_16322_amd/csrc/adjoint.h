@@ -8,6 +8,8 @@
 //   mu_j = a_j lam + A^T mu_{j+1} - c_{j+2} mu_{j+2},
 // with d<lam, u'>/du = mu_0 and
 //   d<lam, u'>/dc^2 = -(1/gamma) sum_{j>=1} mu_{j,p} (sum_a D-_a v_{j-1,a}).
+// As in the forward step, every reverse term is computed in FP64 from the
+// stored values and stored in T (see FaberTerm).
 #pragma once
 
 #include "device_common.h"
@@ -46,6 +48,56 @@ __device__ __forceinline__ void apply_point_adjoint(const Geo<T, K, DIM>& g,
   out[0] = div - sp * pc;
 }
 
+// (H^T y) at one point in FP64 from stored values of precision T.
+template <typename T, int K, int BC, int DIM>
+__device__ __forceinline__ void apply_point_adjoint_d(const Geo<T, K, DIM>& g,
+                                                      const T* __restrict__ y, int64_t idx,
+                                                      const int64_t* ic, double* out,
+                                                      double* self) {
+  const T* __restrict__ p = y;
+  const double pc = static_cast<double>(p[idx]);
+  self[0] = pc;
+  double div = 0.0, sp = 0.0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* __restrict__ v = y + (1 + a) * g.N;
+    double dv = 0.0, dcp = 0.0;
+#pragma unroll
+    for (int l = 1; l <= K; ++l) {
+      dv += g.wd[l - 1] * (static_cast<double>(ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], l - 1)) -
+                           static_cast<double>(ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], -l)));
+      dcp += g.wd[l - 1] *
+             (static_cast<double>(ldn<T, BC>(g.c2, idx, ic[a], g.n[a], g.st[a], l)) *
+                  static_cast<double>(ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], l)) -
+              static_cast<double>(ldn<T, BC>(g.c2, idx, ic[a], g.n[a], g.st[a], 1 - l)) *
+                  static_cast<double>(ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], 1 - l)));
+    }
+    div += dv;
+    sp += static_cast<double>(g.sint[a][ic[a]]);
+    const double vc = static_cast<double>(v[idx]);
+    self[1 + a] = vc;
+    out[1 + a] = dcp - static_cast<double>(g.shalf[a][ic[a]]) * vc;
+  }
+  out[0] = div - sp * pc;
+}
+
+// sum_a D-_a v_a at one point in FP64 (the factor of c^2 in the pressure row of H).
+template <typename T, int K, int BC, int DIM>
+__device__ __forceinline__ double velocity_divergence_d(const Geo<T, K, DIM>& g,
+                                                        const T* __restrict__ x, int64_t idx,
+                                                        const int64_t* ic) {
+  double div = 0.0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* __restrict__ v = x + (1 + a) * g.N;
+#pragma unroll
+    for (int l = 1; l <= K; ++l)
+      div += g.wd[l - 1] * (static_cast<double>(ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], l - 1)) -
+                            static_cast<double>(ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], -l)));
+  }
+  return div;
+}
+
 // sum_a D-_a v_a at one point (the factor of c^2 in the pressure row of H).
 template <typename T, int K, int BC, int DIM>
 __device__ __forceinline__ T velocity_divergence(const Geo<T, K, DIM>& g, const T* __restrict__ x,
@@ -77,10 +129,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_adjoint(Geo<T, K, DIM> g, cons
 }
 
 // Coefficients of one reverse term j: mu_j = a_j lam + (H^T mu1)/gamma
-// - c0 mu1 - cnext mu2 (cnext = c_{j+2}; a_j as hi + lo, see FaberTerm).
-template <typename T>
+// - c0 mu1 - cnext mu2 (cnext = c_{j+2}).
 struct AdjointTerm {
-  T inv_gamma, c0, cnext, a_j, a_j_lo;
+  double inv_gamma, c0, cnext, a_j;
 };
 
 // One reverse term. mu1 (read with a halo) and mu2 may be NULL (zero);
@@ -90,29 +141,32 @@ template <typename T, int K, int BC, int DIM>
 __global__ __launch_bounds__(kBlock) void k_faber_adjoint_term(Geo<T, K, DIM> g, const T* mu1,
                                                                const T* mu2, const T* lam,
                                                                const T* vprev, T* mu_out, T* grad,
-                                                               AdjointTerm<T> c) {
+                                                               AdjointTerm c) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   if (idx >= g.N) return;
   int64_t ic[3];
   decompose<DIM>(g.n, idx, ic);
-  T o[DIM + 1], s[DIM + 1];
+  double o[DIM + 1], s[DIM + 1];
   if (mu1) {
-    apply_point_adjoint<T, K, BC, DIM>(g, mu1, idx, ic, o, s);
+    apply_point_adjoint_d<T, K, BC, DIM>(g, mu1, idx, ic, o, s);
   } else {
 #pragma unroll
-    for (int f = 0; f <= DIM; ++f) o[f] = s[f] = T(0);
+    for (int f = 0; f <= DIM; ++f) o[f] = s[f] = 0.0;
   }
-  T mp = T(0);
+  double mp = 0.0;
 #pragma unroll
   for (int f = 0; f <= DIM; ++f) {
     const int64_t e = f * g.N + idx;
-    T mu = add_weighted(T(0), c.a_j, c.a_j_lo, lam[e]);
+    double mu = c.a_j * static_cast<double>(lam[e]);
     mu += o[f] * c.inv_gamma - c.c0 * s[f];
-    if (mu2) mu -= c.cnext * mu2[e];
-    mu_out[e] = mu;
-    if (f == 0) mp = mu;
+    if (mu2) mu -= c.cnext * static_cast<double>(mu2[e]);
+    const T mt = static_cast<T>(mu);
+    mu_out[e] = mt;
+    if (f == 0) mp = static_cast<double>(mt);
   }
-  if (grad) grad[idx] -= c.inv_gamma * mp * velocity_divergence<T, K, BC, DIM>(g, vprev, idx, ic);
+  if (grad)
+    grad[idx] = static_cast<T>(static_cast<double>(grad[idx]) -
+                               c.inv_gamma * mp * velocity_divergence_d<T, K, BC, DIM>(g, vprev, idx, ic));
 }
 
 // state_p[rec[r]] += scale * vals[r] (adjoint sources at the receivers;

@@ -48,7 +48,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_copy(T* __restrict__ dst, cons
 template <typename T, int K, int DIM>
 struct BatchShot {
   Geo<T, K, DIM> g;
-  T *S, *A, *B, *C;  // state and three workspace vectors of the shot
+  T *S, *A, *B;  // state and two term vectors of the shot
+  double* C;     // the shot's FP64 partial sum
   int32_t m, n_src, p, n_rec;
   int64_t src_lo, src_hi;
   const int64_t* src_idx;
@@ -56,8 +57,8 @@ struct BatchShot {
   const int64_t* rec;
   T* traces;  // NULL: not recorded
   double f_peak, t_delay, dt;
-  T inv_gamma, c0, c1;
-  T a_hi[kBatchMaxM + 1], a_lo[kBatchMaxM + 1];
+  double inv_gamma, c0, c1;
+  double a[kBatchMaxM + 1];
   double qtab[kBatchMaxM][EXPW_MAX_TAYLOR];  // source scalar of term j: sum_c G_c(t) qtab[j-1][c]
 };
 
@@ -98,8 +99,9 @@ __device__ __forceinline__ int batch_shot(const int64_t* prefix, int n_part) {
 }
 
 // Term j of every shot with m >= j. Buffers per shot as in the one-shot
-// unfused step: v1 -> A, v2 -> B, then v_j overwrites v_{j-2}; the sum in C,
-// the last term writes it into S (degree >= 2).
+// unfused step: v1 -> A, v2 -> B, then v_j overwrites v_{j-2}; the FP64 sum
+// in C, the last term rounds it into S (degree >= 2). Terms are computed in
+// FP64 and stored in T (see FaberTerm).
 template <typename T, int K, int BC, int DIM>
 __global__ __launch_bounds__(kBlock) void k_faber_batch_term(const BatchShot<T, K, DIM>* shots,
                                                              const int64_t* prefix, int n_part,
@@ -112,49 +114,50 @@ __global__ __launch_bounds__(kBlock) void k_faber_batch_term(const BatchShot<T, 
   if (idx >= g.N) return;
   const bool fin = (j == sh.m);
   const T *vp, *vpp;
-  T *vout, *acc_out;
-  const T* acc_in = sh.C;
-  T cpp;
+  T* vout;
+  T* state_out = fin ? sh.S : nullptr;
+  double cpp;
   if (j == 1) {
-    vp = sh.S, vpp = nullptr, vout = sh.A, acc_in = nullptr, acc_out = sh.C, cpp = T(0);
+    vp = sh.S, vpp = nullptr, vout = sh.A, cpp = 0.0;
   } else if (j == 2) {
-    vp = sh.A, vpp = sh.S, vout = fin ? nullptr : sh.B, acc_out = fin ? sh.S : sh.C;
-    cpp = T(2) * sh.c1;
+    vp = sh.A, vpp = sh.S, vout = fin ? nullptr : sh.B;
+    cpp = 2.0 * sh.c1;
   } else {
     vp = (j & 1) ? sh.B : sh.A;
     vpp = (j & 1) ? sh.A : sh.B;
     vout = fin ? nullptr : const_cast<T*>(vpp);
-    acc_out = fin ? sh.S : sh.C;
     cpp = sh.c1;
   }
   int64_t ic[3];
   decompose<DIM>(g.n, idx, ic);
-  T o[DIM + 1], sv[DIM + 1];
-  apply_point<T, K, BC, DIM>(g, vp, idx, ic, o, sv);
+  double o[DIM + 1], sv[DIM + 1];
+  apply_point_d<T, K, BC, DIM>(g, vp, idx, ic, o, sv);
   // source at this point (rare): scalar of term j at the step time
-  T src = T(0);
+  double src = 0.0;
   if (sh.n_src > 0 && idx >= sh.src_lo && idx <= sh.src_hi) {
-    T am = T(0);
+    double am = 0.0;
     for (int k = 0; k < sh.n_src; ++k)
-      if (sh.src_idx[k] == idx) am += sh.src_amp[k];
-    if (am != T(0)) {
+      if (sh.src_idx[k] == idx) am += static_cast<double>(sh.src_amp[k]);
+    if (am != 0.0) {
       double der[EXPW_MAX_TAYLOR];
       ricker_derivatives_dev(clk->t0 + (clk->step0 + st) * sh.dt, sh.f_peak, sh.t_delay, sh.p, der);
       double q = 0.0;
       for (int c = 0; c < sh.p; ++c) q += der[sh.p - 1 - c] * sh.qtab[j - 1][c];
-      src = static_cast<T>(q) * am;
+      src = q * am;
     }
   }
 #pragma unroll
   for (int f = 0; f <= DIM; ++f) {
     const int64_t e = f * g.N + idx;
-    T v = o[f] * sh.inv_gamma - sh.c0 * sv[f];
-    if (vpp) v -= cpp * vpp[e];
+    double v = o[f] * sh.inv_gamma - sh.c0 * sv[f];
+    if (vpp) v -= cpp * static_cast<double>(vpp[e]);
     if (f == 0) v += src;
-    T acc = (j == 1) ? add_weighted(T(0), sh.a_hi[0], sh.a_lo[0], sv[f]) : acc_in[e];
-    acc = add_weighted(acc, sh.a_hi[j], sh.a_lo[j], v);
-    if (vout) vout[e] = v;
-    acc_out[e] = acc;
+    const T vt = static_cast<T>(v);
+    double acc = (j == 1) ? sh.a[0] * sv[f] : sh.C[e];
+    acc = fma(sh.a[j], static_cast<double>(vt), acc);
+    if (vout) vout[e] = vt;
+    if (state_out) state_out[e] = static_cast<T>(acc);
+    else sh.C[e] = acc;
   }
 }
 
@@ -181,21 +184,22 @@ __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchShot<T, K, D
 // shot's tiles in one launch (a last pass with n < S terms runs the last n
 // terms of the S-term tile schedule). Buffers per shot as in the one-shot
 // fused step: (A, B) and (D, E) alternate as (v_last, v_prev), C holds the
-// sum, the last pass writes it into S (a shot of one pass writes C, copied
-// afterwards).
+// FP64 sum, the last pass rounds it into S (a shot of one pass writes A,
+// copied afterwards).
 constexpr int kBatchFuse = 4;
 
 template <typename T>
 struct FusedShot {
   Geo<T, 2, 2> g;
-  T *S, *A, *B, *C, *D, *E;
+  T *S, *A, *B, *D, *E;
+  double* C;
   int32_t m, tiles_x, tiles_y, n_src, p, pad_;
   int64_t src_lo, src_hi;
   const int64_t* src_idx;
   const T* src_amp;
   double f_peak, t_delay, dt;
-  T inv_gamma, c0, c1;
-  T a_hi[kBatchMaxM + 1], a_lo[kBatchMaxM + 1];
+  double inv_gamma, c0, c1;
+  double a[kBatchMaxM + 1];
   double qtab[kBatchMaxM][EXPW_MAX_TAYLOR];
 };
 
@@ -216,8 +220,7 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
   c.inv_gamma = sh.inv_gamma;
   c.c0 = sh.c0;
   c.first = first ? 1 : 0;
-  c.a_first = sh.a_hi[0];
-  c.a_first_lo = sh.a_lo[0];
+  c.a_first = sh.a[0];
   // source scalars of the pass's terms: q_r = sum_c g^(p-1-c)(t) qtab[j_r - 1][c],
   // accumulated while the Ricker derivatives are generated (no arrays)
   double q[S];
@@ -248,24 +251,25 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
   for (int r = 0; r < S; ++r) {
     const int j = j0 + (r - r0);
     const bool on = r >= r0;
-    c.a[r] = on ? sh.a_hi[j] : T(0);
-    c.a_lo[r] = on ? sh.a_lo[j] : T(0);
-    c.cpp[r] = (!on || j == 1) ? T(0) : (j == 2 ? T(2) * sh.c1 : sh.c1);
-    c.q[r] = static_cast<T>(q[r]);
+    c.a[r] = on ? sh.a[j] : 0.0;
+    c.cpp[r] = (!on || j == 1) ? 0.0 : (j == 2 ? 2.0 * sh.c1 : sh.c1);
+    c.q[r] = q[r];
   }
   const bool odd_in = ((pass - 1) & 1) != 0, odd_out = (pass & 1) != 0;
   const T* vp = first ? sh.S : (odd_in ? sh.D : sh.A);
   const T* vpp = first ? nullptr : (odd_in ? sh.E : sh.B);
   T* ol = last ? nullptr : (odd_out ? sh.D : sh.A);
   T* opv = last ? nullptr : (odd_out ? sh.E : sh.B);
-  T* acc_out = (last && !first) ? sh.S : sh.C;
+  double* acc_out = last ? nullptr : sh.C;
+  T* state_out = last ? (first ? sh.A : sh.S) : nullptr;
   Src<T> src{};
   src.n = sh.n_src;
   src.lo = sh.src_lo;
   src.hi = sh.src_hi;
   src.idx = sh.src_idx;
   src.amp = sh.src_amp;
-  fused2d_pass<T, S>(sh.g, vp, vpp, first ? nullptr : sh.C, ol, opv, acc_out, c, src, tx_, ty_, r0);
+  fused2d_pass<T, S>(sh.g, vp, vpp, first ? nullptr : sh.C, ol, opv, acc_out, state_out, c, src,
+                     tx_, ty_, r0);
 }
 
 }  // namespace expw

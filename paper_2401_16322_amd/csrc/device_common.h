@@ -13,13 +13,16 @@ constexpr int kRedMaxBlocks = 1024;  // grid cap (and partials length) of reduct
 
 // Geometry and coefficients of H on one grid, passed to kernels by value.
 // Axis a has extent n[a] and flat stride st[a] (axis 0 fastest); w[l-1] =
-// alpha_l / h; sint/shalf are the damping profiles at integer / half points.
+// alpha_l / h in the state precision and wd[l-1] in FP64 (for the kernels that
+// compute in FP64 from stored values of precision T); sint/shalf are the
+// damping profiles at integer / half points.
 template <typename T, int K, int DIM>
 struct Geo {
   int64_t n[3];
   int64_t st[3];
   int64_t N;  // points per field
   T w[K];
+  double wd[K];
   const T* __restrict__ c2;
   const T* __restrict__ sint[3];
   const T* __restrict__ shalf[3];
@@ -81,6 +84,38 @@ __device__ __forceinline__ void apply_point(const Geo<T, K, DIM>& g, const T* __
   out[0] = -g.c2[idx] * div - sp * pc;
 }
 
+// out = H x at one point in FP64 from stored values of precision T (all DIM+1
+// fields), self = x at that point. The differences of stored neighbours are
+// exact in FP64, and so is every product with the FP64 weights up to one
+// rounding: the operator applied is H itself, not H with weights rounded to T.
+template <typename T, int K, int BC, int DIM>
+__device__ __forceinline__ void apply_point_d(const Geo<T, K, DIM>& g, const T* __restrict__ x,
+                                              int64_t idx, const int64_t* ic, double* out,
+                                              double* self) {
+  const T* __restrict__ p = x;
+  const double pc = static_cast<double>(p[idx]);
+  self[0] = pc;
+  double div = 0.0, sp = 0.0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* __restrict__ v = x + (1 + a) * g.N;
+    double dv = 0.0, dp = 0.0;
+#pragma unroll
+    for (int l = 1; l <= K; ++l) {
+      dv += g.wd[l - 1] * (static_cast<double>(ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], l - 1)) -
+                           static_cast<double>(ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], -l)));
+      dp += g.wd[l - 1] * (static_cast<double>(ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], l)) -
+                           static_cast<double>(ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], 1 - l)));
+    }
+    div += dv;
+    sp += static_cast<double>(g.sint[a][ic[a]]);
+    const double vc = static_cast<double>(v[idx]);
+    self[1 + a] = vc;
+    out[1 + a] = -dp - static_cast<double>(g.shalf[a][ic[a]]) * vc;
+  }
+  out[0] = -static_cast<double>(g.c2[idx]) * div - sp * pc;
+}
+
 // Receivers on a run of consecutive pressure nodes first .. first + n - 1,
 // recorded by the kernel that writes a step's final pressure: out is the
 // step's row of the traces (nullptr: not recorded in the kernel).
@@ -106,7 +141,7 @@ struct Src {
   int64_t lo, hi;
   const int64_t* __restrict__ idx;
   const T* __restrict__ amp;
-  T q;  // scalar multiplying every amplitude for this launch
+  double q;  // scalar multiplying every amplitude for this launch
 };
 
 template <typename T>
@@ -114,7 +149,17 @@ __device__ __forceinline__ T src_value(const Src<T>& s, int64_t idx) {
   T r = T(0);
   if (s.n > 0 && idx >= s.lo && idx <= s.hi)
     for (int i = 0; i < s.n; ++i)
-      if (s.idx[i] == idx) r += s.q * s.amp[i];
+      if (s.idx[i] == idx) r += static_cast<T>(s.q) * s.amp[i];
+  return r;
+}
+
+// The source term at a pressure node in FP64 (the kernels that compute in FP64).
+template <typename T>
+__device__ __forceinline__ double src_value_d(const Src<T>& s, int64_t idx) {
+  double r = 0.0;
+  if (s.n > 0 && idx >= s.lo && idx <= s.hi)
+    for (int i = 0; i < s.n; ++i)
+      if (s.idx[i] == idx) r += s.q * static_cast<double>(s.amp[i]);
   return r;
 }
 

@@ -129,6 +129,23 @@ struct Layout {
   int64_t naug_pad;
 };
 
+// The buffers of a Faber step (FaberBufs) in one region: the FP64 partial
+// sum first, then the two (v_last, v_prev) pairs of T.
+template <typename T>
+FaberBufs<T> faber_bufs(char* big, int64_t ns) {
+  FaberBufs<T> b;
+  b.C = reinterpret_cast<double*>(big);
+  b.A = reinterpret_cast<T*>(big + align_up(static_cast<size_t>(ns) * sizeof(double)));
+  b.B = b.A + ns;
+  b.D = b.B + ns;
+  b.E = b.D + ns;
+  return b;
+}
+
+size_t faber_big_bytes(int64_t ns, size_t es) {
+  return align_up(static_cast<size_t>(ns) * sizeof(double)) + 4 * static_cast<size_t>(ns) * es;
+}
+
 Layout layout(const expw_grid& g, int kmax, int pmax) {
   Layout L{};
   const size_t es = elem_size(g);
@@ -148,7 +165,7 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
-  size_t big = 5 * static_cast<size_t>(ns) * es;  // Faber: v pairs (2 x 2) + partial sum
+  size_t big = faber_big_bytes(ns, es);  // Faber: FP64 partial sum + v pairs (2 x 2)
   if (kmax > 0) big = std::max(big, static_cast<size_t>(kmax + 1) * L.naug_pad * es);
   L.total = align_up(off + big);
   return L;
@@ -188,7 +205,10 @@ Geo<T, K, DIM> make_geo(const expw_op* op) {
   g.st[1] = g.n[0];
   g.st[2] = g.n[0] * g.n[1];
   g.N = g.n[0] * g.n[1] * g.n[2];
-  for (int l = 0; l < K; ++l) g.w[l] = static_cast<T>(op->alpha[l] / op->g.h);
+  for (int l = 0; l < K; ++l) {
+    g.wd[l] = op->alpha[l] / op->g.h;
+    g.w[l] = static_cast<T>(g.wd[l]);
+  }
   g.c2 = static_cast<const T*>(op->c2);
   for (int a = 0; a < 3; ++a) {
     g.sint[a] = reinterpret_cast<const T*>(op->ws + op->off_sig[a][0]);
@@ -205,7 +225,7 @@ Src<T> make_src(const expw_op* op, double q) {
   s.hi = op->src_hi;
   s.idx = reinterpret_cast<const int64_t*>(op->ws + op->off_src_idx);
   s.amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
-  s.q = static_cast<T>(q);
+  s.q = q;
   return s;
 }
 
@@ -304,27 +324,18 @@ RecRun<T> rec_run(const expw_op* op, T* traces, int64_t step) {
 
 // ---------------------------------------------------------------- Faber step
 
-// The ellipse a Faber step in precision T runs with: 1/gamma, c0 and c1 are
-// rounded to T first (gamma taken back from the rounded 1/gamma) and the
-// coefficients are computed in FP64 for that ellipse. The recurrence then
-// uses exactly the scalars its coefficients assume; rounding them after the
-// fact would perturb every step the same way, and in FP32 that systematic
-// error grows linearly with the number of steps. The change of the ellipse
-// itself is a relative 1e-7 at most, well inside the slack of the bound.
-template <typename T>
+// The ellipse of a Faber step: the operator's, in FP64 for both storage
+// precisions (every term is computed in FP64).
 struct WorkEllipse {
   double gamma, c0, c1;
-  explicit WorkEllipse(const expw_op* op) {
-    step_ellipse(sizeof(T) == 4 ? EXPW_F32 : EXPW_F64, op->gamma, op->c0, op->c1, &gamma, &c0,
-                 &c1);
-  }
+  explicit WorkEllipse(const expw_op* op) : gamma(op->gamma), c0(op->c0), c1(op->c1) {}
 };
 
 // One Faber step, one term per sweep. term_out (nullable): receives the
 // pressure of every term v_0..v_m at the receivers ((m + 1) * n_rec values).
 template <typename T, int K, int BC, int DIM>
-int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse<T>& el, T* S,
-                      T* Abuf, T* Bbuf, T* Cbuf, const double* a, const double* q, int m,
+int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse& el, T* S,
+                      const FaberBufs<T>& b, const double* a, const double* q, int m,
                       T* term_out) {
   const int64_t ns = (DIM + 1) * g.N;
   const unsigned grid = grid_for(g.N);
@@ -333,43 +344,45 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse<T>
     return keep ? gather<T>(op, v, term_out + static_cast<int64_t>(j) * op->n_rec, 0) : EXPW_OK;
   };
   if (int32_t rc = record(S, 0)) return rc;
-  FaberTerm<T> c{};
-  c.inv_gamma = static_cast<T>(1.0 / el.gamma);
-  c.c0 = static_cast<T>(el.c0);
-  // j = 1: v1 = F1 v0 into A; acc = a0 v0 + a1 v1 into C
-  c.cpp = T(0);
+  FaberTerm c{};
+  c.inv_gamma = 1.0 / el.gamma;
+  c.c0 = el.c0;
+  // j = 1: v1 = F1 v0 into A; sum = a0 v0 + a1 v1 into C (m = 1: the result
+  // into B and then S, which this sweep reads with its halo)
+  c.cpp = 0.0;
   c.first = 1;
-  split_weight(a[0], &c.a_first, &c.a_first_lo);
-  split_weight(a[1], &c.a_j, &c.a_j_lo);
-  const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
-  // words per point: reads v_{j-1} (nf) + c^2 (1) [+ v_{j-2} (nf) + sum (nf)],
-  // writes the sum (nf) [+ v_j (nf)]
-  T* v1 = (m == 1 && !keep) ? nullptr : Abuf;
-  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1 + nf + (v1 ? nf : 0)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, nullptr, v1, nullptr, Cbuf, c, make_src<T>(op, q[0]));
+  c.a_first = a[0];
+  c.a_j = a[1];
+  const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T), pd = static_cast<double>(g.N) * sizeof(double);
+  // bytes: reads v_{j-1} (nf T) + c^2 [+ v_{j-2} (nf T) + sum (nf FP64)];
+  // writes [v_j (nf T)] + the sum (nf FP64, or nf T for the step's result)
+  T* v1 = (m == 1 && !keep) ? nullptr : b.A;
+  T* out1 = m == 1 ? b.B : nullptr;
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1) * pb + (v1 ? nf * pb : 0.0) + (m == 1 ? nf * pb : nf * pd), k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, nullptr, v1, nullptr, m == 1 ? nullptr : b.C, out1, c, make_src<T>(op, q[0]));
   if (int32_t rc = check_launch("faber j=1")) return rc;
-  if (int32_t rc = record(Abuf, 1)) return rc;
+  if (int32_t rc = record(b.A, 1)) return rc;
   if (m == 1) {
-    if (hipMemcpyAsync(S, Cbuf, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
+    if (hipMemcpyAsync(S, b.B, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
       return fail(EXPW_EDEVICE, "faber: copy failed");
     return EXPW_OK;
   }
   // j = 2: v2 = F1 v1 - 2 c1 v0 into B (v0 = S read pointwise)
   c.first = 0;
-  c.a_first = c.a_first_lo = T(0);
-  c.cpp = static_cast<T>(2.0 * el.c1);
-  split_weight(a[2], &c.a_j, &c.a_j_lo);
-  T* v2 = (m == 2 && !keep) ? nullptr : Bbuf;
-  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (v2 ? nf : 0)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, Abuf, S, v2, Cbuf, m == 2 ? S : Cbuf, c, make_src<T>(op, q[1]));
+  c.a_first = 0.0;
+  c.cpp = 2.0 * el.c1;
+  c.a_j = a[2];
+  T* v2 = (m == 2 && !keep) ? nullptr : b.B;
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (2 * nf + 1) * pb + nf * pd + (v2 ? nf * pb : 0.0) + (m == 2 ? nf * pb : nf * pd), k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, b.A, S, v2, b.C, m == 2 ? nullptr : b.C, m == 2 ? S : nullptr, c, make_src<T>(op, q[1]));
   if (int32_t rc = check_launch("faber j=2")) return rc;
-  if (int32_t rc = record(Bbuf, 2)) return rc;
-  T* last = Bbuf;   // v_{j-1}
-  T* older = Abuf;  // v_{j-2}
-  c.cpp = static_cast<T>(el.c1);
+  if (int32_t rc = record(b.B, 2)) return rc;
+  T* last = b.B;   // v_{j-1}
+  T* older = b.A;  // v_{j-2}
+  c.cpp = el.c1;
   for (int j = 3; j <= m; ++j) {
-    split_weight(a[j], &c.a_j, &c.a_j_lo);
+    c.a_j = a[j];
     const bool fin = (j == m);
     T* vj = (fin && !keep) ? nullptr : older;
-    launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (4 * nf + 1 + (vj ? nf : 0)) * pb, k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, last, older, vj, Cbuf, fin ? S : Cbuf, c, make_src<T>(op, q[j - 1]));
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (2 * nf + 1) * pb + nf * pd + (vj ? nf * pb : 0.0) + (fin ? nf * pb : nf * pd), k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, last, older, vj, b.C, fin ? nullptr : b.C, fin ? S : nullptr, c, make_src<T>(op, q[j - 1]));
     if (int32_t rc = check_launch("faber term")) return rc;
     if (int32_t rc = record(older, j)) return rc;
     std::swap(last, older);
@@ -378,65 +391,63 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse<T>
 }
 
 // Faber steps; term_traces (nullable) records every term at the receivers
-// and then runs the terms one per sweep.
+// and then runs the terms one per sweep. big: the step's buffers
+// (faber_big_bytes); a, q: host scratch of m + 1 and m doubles.
 template <typename T, int K, int BC, int DIM>
 int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nsteps, T* traces,
-                   T* term_traces) {
+                   T* term_traces, char* big, double* a, double* q) {
   const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
   const int64_t ns = (DIM + 1) * g.N;
-  T* Abuf = reinterpret_cast<T*>(op->ws + op->off_big);
-  T* Bbuf = Abuf + ns;
-  T* Cbuf = Bbuf + ns;
-  std::vector<double> a(m + 1), q(m, 0.0), der(EXPW_MAX_TAYLOR), G(EXPW_MAX_TAYLOR);
-  const WorkEllipse<T> el(op);
-  faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a.data());
+  const FaberBufs<T> b = faber_bufs<T>(big, ns);
+  double der[EXPW_MAX_TAYLOR], G[EXPW_MAX_TAYLOR];
+  const WorkEllipse el(op);
+  faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a);
+  for (int j = 0; j < m; ++j) q[j] = 0.0;
   const int p = op->taylor_p;
-  T* Dbuf = Cbuf + ns;
-  T* Ebuf = Dbuf + ns;
   const int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m, g.N);
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     if (op->n_src > 0) {
-      source_derivs(op, st, t, p, der.data());
+      source_derivs(op, st, t, p, der);
       for (int c = 0; c < p; ++c) G[c] = der[p - 1 - c];
-      faber_source_scalars(el.gamma, el.c0, el.c1, m, p, G.data(), q.data());
+      faber_source_scalars(el.gamma, el.c0, el.c1, m, p, G, q);
       const double sc = src_scale(op);
       for (int j = 0; j < m; ++j) q[j] *= sc;
     }
     int32_t rc = EXPW_OK;
     T* term_out = term_traces ? term_traces + st * (m + 1) * op->n_rec : nullptr;
     // a remainder of one term after the fused passes: unfused final term
-    auto final_term = [&](const T* vl, const T* vpv, T* acc, T* out, int j) -> int32_t {
-      FaberTerm<T> c{};
-      c.inv_gamma = static_cast<T>(1.0 / el.gamma);
-      c.c0 = static_cast<T>(el.c0);
-      c.cpp = static_cast<T>(el.c1);
-      split_weight(a[j], &c.a_j, &c.a_j_lo);
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (3.0 * (DIM + 1) + 1) * g.N * sizeof(T), k_faber_term<T, K, BC, DIM>, dim3(grid_for(g.N)), dim3(kBlock), g, vl, vpv, nullptr, acc, out, c, make_src<T>(op, q[j - 1]));
+    auto final_term = [&](const T* vl, const T* vpv, const double* acc, T* out, int j) -> int32_t {
+      FaberTerm c{};
+      c.inv_gamma = 1.0 / el.gamma;
+      c.c0 = el.c0;
+      c.cpp = el.c1;
+      c.a_j = a[j];
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, ((3.0 * (DIM + 1) + 1) * sizeof(T) + (DIM + 1) * sizeof(double)) * g.N, k_faber_term<T, K, BC, DIM>, dim3(grid_for(g.N)), dim3(kBlock), g, vl, vpv, nullptr, acc, nullptr, out, c, make_src<T>(op, q[j - 1]));
       return check_launch("faber final term");
     };
     const Src<T> src0 = make_src<T>(op, 0.0);
     bool recorded = false;  // by the last fused pass
     if (fuse > 1 && !term_out) {
       if constexpr (BC == 0 && DIM == 2) {
-        rc = faber_fused_passes<T>(op->stream, ns, S, Abuf, Bbuf, Cbuf, Dbuf, Ebuf, m, fuse, final_term,
-            [&](int n, const T* vp, const T* vpp, const T* acc_in, T* ol, T* opv, T* acc_out, int j, bool first) {
-              // the last pass (no terms kept) writes the step's sum
-              const RecRun<T> rr = ol == nullptr ? rec_run(op, traces, st) : RecRun<T>{nullptr, 0, 0};
+        rc = faber_fused_passes<T>(op->stream, ns, S, b, m, fuse, final_term,
+            [&](int n, const T* vp, const T* vpp, const double* acc_in, T* ol, T* opv, double* acc_out, T* state_out, int j, bool first) {
+              // the last pass (no terms kept) writes the step's result
+              const RecRun<T> rr = state_out ? rec_run(op, traces, st) : RecRun<T>{nullptr, 0, 0};
               recorded = recorded || rr.out != nullptr;
-              return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, j, first, a.data(), q.data(), el.gamma, el.c0, el.c1, rr);
+              return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1, rr);
             });
       } else if constexpr (K == 2 && BC == 0 && DIM == 3) {
-        rc = faber_fused_passes<T>(op->stream, ns, S, Abuf, Bbuf, Cbuf, Dbuf, Ebuf, m, 2, final_term,
-            [&](int n, const T* vp, const T* vpp, const T* acc_in, T* ol, T* opv, T* acc_out, int j, bool first) {
+        rc = faber_fused_passes<T>(op->stream, ns, S, b, m, 2, final_term,
+            [&](int n, const T* vp, const T* vpp, const double* acc_in, T* ol, T* opv, double* acc_out, T* state_out, int j, bool first) {
               (void)n;
-              return launch_fused3d<T>(op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, j, first, a.data(), q.data(), el.gamma, el.c0, el.c1);
+              return launch_fused3d<T>(op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1);
             });
       } else {
-        rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m, term_out);
+        rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, b, a, q, m, term_out);
       }
     } else {
-      rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, Abuf, Bbuf, Cbuf, a.data(), q.data(), m, term_out);
+      rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, b, a, q, m, term_out);
     }
     if (rc != EXPW_OK) return rc;
     if (!recorded && (rc = gather<T>(op, S, traces, st)) != EXPW_OK) return rc;
@@ -728,7 +739,7 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
   const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
   const int64_t ns = (DIM + 1) * g.N;
   const unsigned grid = grid_for(g.N);
-  const WorkEllipse<T> el(op);
+  const WorkEllipse el(op);
   std::vector<double> a(m + 1), q(m, 0.0), der(EXPW_MAX_TAYLOR), G(EXPW_MAX_TAYLOR);
   faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a.data());
   const int p = op->taylor_p;
@@ -741,15 +752,15 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
   }
   auto v = [&](int j) -> const T* { return j == 0 ? U : terms + (j - 1) * ns; };
   // forward: v_j = F1 v_{j-1} - c_j v_{j-2} + source, j = 1..m-1
-  FaberTerm<T> f{};
-  f.inv_gamma = static_cast<T>(1.0 / el.gamma);
-  f.c0 = static_cast<T>(el.c0);
+  FaberTerm f{};
+  f.inv_gamma = 1.0 / el.gamma;
+  f.c0 = el.c0;
   const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
   for (int j = 1; j < m; ++j) {
-    f.cpp = static_cast<T>(j == 1 ? 0.0 : (j == 2 ? 2.0 * el.c1 : el.c1));
+    f.cpp = j == 1 ? 0.0 : (j == 2 ? 2.0 * el.c1 : el.c1);
     launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1 + (j > 1 ? nf : 0) + nf) * pb,
                  k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, v(j - 1),
-                 j > 1 ? v(j - 2) : nullptr, terms + (j - 1) * ns, nullptr, nullptr, f,
+                 j > 1 ? v(j - 2) : nullptr, terms + (j - 1) * ns, nullptr, nullptr, nullptr, f,
                  make_src<T>(op, q[j - 1]));
     if (int32_t rc = check_launch("adjoint: forward terms")) return rc;
   }
@@ -758,12 +769,12 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
   mbuf[1] = mbuf[0] + ns;
   mbuf[2] = mbuf[1] + ns;
   auto cc = [&](int j) { return j < 2 ? 0.0 : (j == 2 ? 2.0 * el.c1 : el.c1); };
-  AdjointTerm<T> c{};
+  AdjointTerm c{};
   c.inv_gamma = f.inv_gamma;
   c.c0 = f.c0;
   for (int j = m; j >= 0; --j) {
-    split_weight(a[j], &c.a_j, &c.a_j_lo);
-    c.cnext = static_cast<T>(cc(j + 2));
+    c.a_j = a[j];
+    c.cnext = cc(j + 2);
     const T* mu1 = j + 1 <= m ? mbuf[(j + 1) % 3] : nullptr;
     const T* mu2 = j + 2 <= m ? mbuf[(j + 2) % 3] : nullptr;
     T* out = j == 0 ? lam : mbuf[j % 3];
@@ -805,18 +816,17 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
     std::memcpy(static_cast<void*>(&sh.g), &geo, sizeof(geo));
     const int64_t ns = (DIM + 1) * sh.g.N;
     sh.S = static_cast<T*>(states[i]);
-    sh.A = reinterpret_cast<T*>(op->ws + op->off_big);
-    sh.B = sh.A + ns;
-    sh.C = sh.B + ns;
+    const FaberBufs<T> fb = faber_bufs<T>(op->ws + op->off_big, ns);
+    sh.A = fb.A;
+    sh.B = fb.B;
+    sh.C = fb.C;
     sh.m = m[i];
     sh.dt = dt[i];
-    const WorkEllipse<T> el(op);
-    sh.inv_gamma = static_cast<T>(1.0 / el.gamma);
-    sh.c0 = static_cast<T>(el.c0);
-    sh.c1 = static_cast<T>(el.c1);
-    std::vector<double> a(m[i] + 1);
-    faber_coefficients(el.gamma, el.c0, el.c1, dt[i], m[i], a.data());
-    for (int j = 0; j <= m[i]; ++j) split_weight(a[j], &sh.a_hi[j], &sh.a_lo[j]);
+    const WorkEllipse el(op);
+    sh.inv_gamma = 1.0 / el.gamma;
+    sh.c0 = el.c0;
+    sh.c1 = el.c1;
+    faber_coefficients(el.gamma, el.c0, el.c1, dt[i], m[i], sh.a);
     if (op->n_src > 0) {
       sh.n_src = op->n_src;
       sh.p = op->taylor_p;
@@ -880,7 +890,7 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
         f.A = h.A;
         f.B = h.B;
         f.C = h.C;
-        f.D = h.C + ns;
+        f.D = h.B + ns;
         f.E = f.D + ns;
         f.m = h.m;
         f.tiles_x = static_cast<int32_t>((h.g.n[0] + TX - 1) / TX);
@@ -897,15 +907,14 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
         f.inv_gamma = h.inv_gamma;
         f.c0 = h.c0;
         f.c1 = h.c1;
-        std::memcpy(f.a_hi, h.a_hi, sizeof(h.a_hi));
-        std::memcpy(f.a_lo, h.a_lo, sizeof(h.a_lo));
+        std::memcpy(f.a, h.a, sizeof(h.a));
         std::memcpy(f.qtab, h.qtab, sizeof(h.qtab));
         fprefix[r + 1] = fprefix[r] + static_cast<int64_t>(f.tiles_x) * f.tiles_y;
         const int passes = (h.m + S - 1) / S;
         b->max_passes = std::max(b->max_passes, passes);
         if (passes == 1) {
           b->copy_dst.push_back(h.S);
-          b->copy_src.push_back(h.C);
+          b->copy_src.push_back(h.A);
           b->copy_elems.push_back(ns);
         }
       }
@@ -1060,6 +1069,12 @@ int32_t expw_workspace_size(const expw_grid* g, int32_t max_k, int32_t max_p, si
 
 int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, int32_t max_p,
                        void* ws, size_t ws_bytes, void* stream, expw_op** out) {
+  return expw_op_create_profiles(g, c2_dev, nullptr, max_k, max_p, ws, ws_bytes, stream, out);
+}
+
+int32_t expw_op_create_profiles(const expw_grid* g, const void* c2_dev,
+                                const double* const* sigma_host, int32_t max_k, int32_t max_p,
+                                void* ws, size_t ws_bytes, void* stream, expw_op** out) {
   clear_error();
   size_t need = 0;
   if (int32_t rc = expw_workspace_size(g, max_k, max_p, &need)) return rc;
@@ -1068,6 +1083,27 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   if (!ws) return fail(EXPW_EINVAL, "workspace_dev is NULL");
   if (ws_bytes < need) return fail(EXPW_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return fail(EXPW_EINVAL, "workspace must be 256-byte aligned");
+  // the damping profiles: the caller's, or the quadratic layer of the grid
+  std::vector<double> profiles[3][2];
+  for (int a = 0; a < g->ndim; ++a)
+    for (int hf = 0; hf < 2; ++hf) {
+      std::vector<double>& prof = profiles[a][hf];
+      prof.resize(g->n[a]);
+      if (sigma_host) {
+        const double* src = sigma_host[2 * a + hf];
+        if (!src) return fail(EXPW_EINVAL, "sigma_host[%d] is NULL", 2 * a + hf);
+        for (int64_t i = 0; i < g->n[a]; ++i) {
+          if (!(src[i] >= 0.0) || !std::isfinite(src[i]))
+            return fail(EXPW_EINVAL, "sigma_host[%d][%lld] must be finite and >= 0", 2 * a + hf,
+                        static_cast<long long>(i));
+          if (g->bc == EXPW_BC_PERIODIC && src[i] != 0.0)
+            return fail(EXPW_EINVAL, "damping profiles must be zero with periodic ghosts");
+          prof[i] = src[i];
+        }
+      } else {
+        damping_profile(g->n[a], g->h, g->abc_cells, g->sigma_max, hf == 1, prof.data());
+      }
+    }
   watch_exit();
   expw_op* op = new expw_op();
   op->g = *g;
@@ -1110,8 +1146,7 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
   const size_t es = elem_size(*g);
   for (int a = 0; a < g->ndim; ++a)
     for (int hf = 0; hf < 2; ++hf) {
-      std::vector<double> prof(g->n[a]);
-      damping_profile(g->n[a], g->h, g->abc_cells, g->sigma_max, hf == 1, prof.data());
+      const std::vector<double>& prof = profiles[a][hf];
       std::vector<char> buf(g->n[a] * es);
       for (int64_t i = 0; i < g->n[a]; ++i) {
         if (g->dtype == EXPW_F32) reinterpret_cast<float*>(buf.data())[i] = static_cast<float>(prof[i]);
@@ -1146,7 +1181,10 @@ int32_t expw_op_create(const expw_grid* g, const void* c2_dev, int32_t max_k, in
     return fail(EXPW_ENONFINITE, "c2 holds a non-finite or non-positive value");
   }
   op->c2max = c2max;
-  expw_spectrum_rectangle(g, c2max, &op->x_lo, &op->B);
+  const double* prof_ptrs[6] = {};
+  for (int a = 0; a < g->ndim; ++a)
+    for (int hf = 0; hf < 2; ++hf) prof_ptrs[2 * a + hf] = profiles[a][hf].data();
+  expw_spectrum_rectangle_profiles(g, c2max, prof_ptrs, &op->x_lo, &op->B);
   expw_ellipse(op->x_lo, op->B, &op->gamma, &op->c0, &op->c1);
   *out = op;
   return EXPW_OK;
@@ -1447,7 +1485,8 @@ int32_t expw_step_faber(expw_op* op, void* state, double t0, double dt, int32_t 
   return dispatch(op, [&](auto cfg) {
     using C = decltype(cfg);
     using T = typename C::type;
-    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), nullptr);
+    std::vector<double> a(m + 1), q(m);
+    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), nullptr, op->ws + op->off_big, a.data(), q.data());
   });
 }
 
@@ -1460,7 +1499,8 @@ int32_t expw_step_faber_dense(expw_op* op, void* state, double t0, double dt, in
   return dispatch(op, [&](auto cfg) {
     using C = decltype(cfg);
     using T = typename C::type;
-    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), static_cast<T*>(term_traces));
+    std::vector<double> a(m + 1), q(m);
+    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), static_cast<T*>(term_traces), op->ws + op->off_big, a.data(), q.data());
   });
 }
 
@@ -1742,7 +1782,7 @@ Src<T> make_pml_src(const expw_pml* op, double q) {
   s.hi = op->src_hi;
   s.idx = reinterpret_cast<const int64_t*>(op->ws + op->off_src_idx);
   s.amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
-  s.q = static_cast<T>(q);
+  s.q = q;
   return s;
 }
 
@@ -1763,7 +1803,7 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
   int j = 1;
   for (; j + 1 <= m; j += 2) {
     const bool last = (j + 1 == m);
-    FaberTerm<T> t0{}, t1{};
+    PmlTerm<T> t0{}, t1{};
     t0.inv_gamma = t1.inv_gamma = static_cast<T>(1.0 / gs);
     t0.c0 = t1.c0 = static_cast<T>(c0s);
     t0.first = j == 1 ? 1 : 0;
@@ -1793,7 +1833,7 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
   }
   if (j == m) {
     // odd m: the last term alone (v_{m-1} = vp, v_{m-2} = vpp, neither is S)
-    FaberTerm<T> c{};
+    PmlTerm<T> c{};
     c.inv_gamma = static_cast<T>(1.0 / gs);
     c.c0 = static_cast<T>(c0s);
     c.cpp = static_cast<T>(c1s);
@@ -1828,7 +1868,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   T* D = C + ns;
   T* E = D + ns;
   // one term: the LDS kernel on tiles or one thread per node
-  auto term = [&](const T* vp, const T* vpp, T* vout, const T* acc_in, T* acc_out, const FaberTerm<T>& c,
+  auto term = [&](const T* vp, const T* vpp, T* vout, const T* acc_in, T* acc_out, const PmlTerm<T>& c,
                   double qj) {
     if (lds)
       k_pml_faber_term_lds<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, c,
@@ -1855,7 +1895,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
       }
       continue;
     }
-    FaberTerm<T> c{};
+    PmlTerm<T> c{};
     c.inv_gamma = static_cast<T>(1.0 / gs);
     c.c0 = static_cast<T>(c0s);
     // j = 1: v1 = F1 v0 into A, sum a0 v0 + a1 v1 into C

@@ -18,6 +18,10 @@
 // partial sum, i.e. 19 words per point per pass instead of 16 per term for
 // one-term sweeps.
 //
+// Every term is computed in FP64 from the stored values and kept in LDS in
+// the storage precision T; the partial sum is FP64 (in LDS and between
+// passes), and the last pass rounds it to T once (see FaberTerm).
+//
 // Tiles are mapped to workgroups so that each XCD (block id mod 8) owns a
 // band of tile columns walked row by row: halo rows shared by neighbouring
 // tiles then hit in that XCD's L2.
@@ -42,22 +46,27 @@ struct FusedTile {
 
 template <typename T, int S>
 struct FusedArgs {
-  T inv_gamma, c0, a_first, a_first_lo;  // weights as hi + lo (see FaberTerm)
+  double inv_gamma, c0, a_first;
   int32_t first;  // first pass of a step: acc = a_first * v0, no v_{j-2}
   int32_t tiles_x, tiles_y, band_w;
-  T a[S], a_lo[S], cpp[S], q[S];
+  double a[S], cpp[S], q[S];
   RecRun<T> rec;  // receivers recorded from the sum (last pass of a step only)
 };
 
 // One pass over tile (tx_, ty_) of the recurrence terms r0..S-1 of an S-term
 // pass (r0 > 0 runs the last S - r0 terms only: a shorter pass on the same
 // tile). 2D grids with 3 * points < 2^31.
+// acc_in: the FP64 sum of the previous passes (not read on the first); the
+// sum goes to acc_out (FP64) or, on a step's last pass, to state_out rounded
+// to T (state_out must not alias vp or vpp).
 template <typename T, int S, int K = 2>
 __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __restrict__ vp,
-                                             const T* __restrict__ vpp, const T* acc_in,
+                                             const T* __restrict__ vpp,
+                                             const double* __restrict__ acc_in,
                                              T* __restrict__ out_last, T* __restrict__ out_prev,
-                                             T* acc_out, const FusedArgs<T, S>& c,
-                                             const Src<T>& src, int tx_, int ty_, int r0) {
+                                             double* __restrict__ acc_out, T* __restrict__ state_out,
+                                             const FusedArgs<T, S>& c, const Src<T>& src, int tx_,
+                                             int ty_, int r0) {
   constexpr int H = K * S;
   constexpr int TX = FusedTile<S, K>::TX, TY = FusedTile<S, K>::TY;
   constexpr int EX = TX + 2 * H, EY = TY + 2 * H, E = EX * EY;
@@ -65,7 +74,7 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
   constexpr int NSL = kFusedRY / 16;   // rows per wave
   static_assert(TX + 2 * K * (S - 1) == 64, "largest region is one wave wide");
   __shared__ T cur[3 * E];
-  __shared__ T sacc[3 * TX * TY];
+  __shared__ double sacc[3 * TX * TY];
 
   const int nx = static_cast<int>(g.n[0]), nz = static_cast<int>(g.n[1]);
   const int N = static_cast<int>(g.N);
@@ -125,9 +134,9 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
       const int gxx = x0 + H + tx, gz = z0 + H + ty;
       const bool in = gxx < nx && gz < nz;
       const int gi = in ? gz * nx + gxx : 0;
-      sacc[t] = in ? acc_in[gi] : T(0);
-      sacc[TX * TY + t] = in ? acc_in[N + gi] : T(0);
-      sacc[2 * TX * TY + t] = in ? acc_in[2 * N + gi] : T(0);
+      sacc[t] = in ? acc_in[gi] : 0.0;
+      sacc[TX * TY + t] = in ? acc_in[N + gi] : 0.0;
+      sacc[2 * TX * TY + t] = in ? acc_in[2 * N + gi] : 0.0;
     }
   }
   __syncthreads();
@@ -135,9 +144,9 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
     for (int t = tid; t < TX * TY; t += kFusedNT) {
       const int ty = t / TX, tx = t - ty * TX;
       const int l = (ty + H) * EX + tx + H;
-      sacc[t] = add_weighted(T(0), c.a_first, c.a_first_lo, cur[l]);
-      sacc[TX * TY + t] = add_weighted(T(0), c.a_first, c.a_first_lo, cur[E + l]);
-      sacc[2 * TX * TY + t] = add_weighted(T(0), c.a_first, c.a_first_lo, cur[2 * E + l]);
+      sacc[t] = c.a_first * static_cast<double>(cur[l]);
+      sacc[TX * TY + t] = c.a_first * static_cast<double>(cur[E + l]);
+      sacc[2 * TX * TY + t] = c.a_first * static_cast<double>(cur[2 * E + l]);
     }
   }
 
@@ -147,28 +156,29 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
 #pragma unroll
   for (int r = 0; r < S; ++r) {
     if (r < r0) continue;  // block-uniform
-    const T cpp = c.cpp[r];
-    const T qr = c.q[r];
+    const double cpp = c.cpp[r];
+    const double qr = c.q[r];
 #pragma unroll
     for (int i = 0; i < NSL; ++i) {
       if (r <= last[i]) {
         const int l = (X0 + wave + 16 * i) * EX + lx;
         const T pc = cp[l], vxc = cvx[l], vzc = cvz[l];
-        T dvx = T(0), dvz = T(0), dpx = T(0), dpz = T(0);
+        double dvx = 0.0, dvz = 0.0, dpx = 0.0, dpz = 0.0;
 #pragma unroll
         for (int q = 1; q <= K; ++q) {
-          const T wq = g.w[q - 1];
-          dvx += wq * (cvx[l + q - 1] - cvx[l - q]);
-          dvz += wq * (cvz[l + (q - 1) * EX] - cvz[l - q * EX]);
-          dpx += wq * (cp[l + q] - cp[l + 1 - q]);
-          dpz += wq * (cp[l + q * EX] - cp[l + (1 - q) * EX]);
+          const double wq = g.wd[q - 1];
+          dvx += wq * (static_cast<double>(cvx[l + q - 1]) - static_cast<double>(cvx[l - q]));
+          dvz += wq * (static_cast<double>(cvz[l + (q - 1) * EX]) - static_cast<double>(cvz[l - q * EX]));
+          dpx += wq * (static_cast<double>(cp[l + q]) - static_cast<double>(cp[l + 1 - q]));
+          dpz += wq * (static_cast<double>(cp[l + q * EX]) - static_cast<double>(cp[l + (1 - q) * EX]));
         }
-        const T hp = -cc2[i] * (dvx + dvz) - sp[i] * pc;
-        const T hvx = -dpx - sxh * vxc;
-        const T hvz = -dpz - szh[i] * vzc;
-        nv[i][0] = hp * c.inv_gamma - c.c0 * pc - cpp * old[i][0] + qr * amp[i];
-        nv[i][1] = hvx * c.inv_gamma - c.c0 * vxc - cpp * old[i][1];
-        nv[i][2] = hvz * c.inv_gamma - c.c0 * vzc - cpp * old[i][2];
+        const double hp = -static_cast<double>(cc2[i]) * (dvx + dvz) - static_cast<double>(sp[i]) * pc;
+        const double hvx = -dpx - static_cast<double>(sxh) * vxc;
+        const double hvz = -dpz - static_cast<double>(szh[i]) * vzc;
+        nv[i][0] = static_cast<T>(hp * c.inv_gamma - c.c0 * pc - cpp * static_cast<double>(old[i][0]) +
+                                  qr * static_cast<double>(amp[i]));
+        nv[i][1] = static_cast<T>(hvx * c.inv_gamma - c.c0 * vxc - cpp * static_cast<double>(old[i][1]));
+        nv[i][2] = static_cast<T>(hvz * c.inv_gamma - c.c0 * vzc - cpp * static_cast<double>(old[i][2]));
         // v_{j-1} at the point becomes the next term's v_{j-2}
         old[i][0] = pc;
         old[i][1] = vxc;
@@ -176,7 +186,7 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
       }
     }
     __syncthreads();  // every read of v_{j-1} is done
-    const T aj = c.a[r], ajl = c.a_lo[r];
+    const double aj = c.a[r];
 #pragma unroll
     for (int i = 0; i < NSL; ++i) {
       if (r <= last[i]) {
@@ -187,9 +197,9 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
         cur[2 * E + l] = nv[i][2];
         if (last[i] == S - 1 && lx >= H && lx < H + TX && ly >= H && ly < H + TY) {
           const int t = (ly - H) * TX + (lx - H);
-          sacc[t] = add_weighted(sacc[t], aj, ajl, nv[i][0]);
-          sacc[TX * TY + t] = add_weighted(sacc[TX * TY + t], aj, ajl, nv[i][1]);
-          sacc[2 * TX * TY + t] = add_weighted(sacc[2 * TX * TY + t], aj, ajl, nv[i][2]);
+          sacc[t] = fma(aj, static_cast<double>(nv[i][0]), sacc[t]);
+          sacc[TX * TY + t] = fma(aj, static_cast<double>(nv[i][1]), sacc[TX * TY + t]);
+          sacc[2 * TX * TY + t] = fma(aj, static_cast<double>(nv[i][2]), sacc[2 * TX * TY + t]);
         }
       }
     }
@@ -216,10 +226,17 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
     const int gxx = x0 + H + tx, gz = z0 + H + ty;
     if (gxx >= nx || gz >= nz) continue;
     const int gi = gz * nx + gxx;
-    acc_out[gi] = sacc[t];
-    rec_run_put(c.rec, gi, sacc[t]);
-    acc_out[N + gi] = sacc[TX * TY + t];
-    acc_out[2 * N + gi] = sacc[2 * TX * TY + t];
+    if (state_out) {
+      const T pv = static_cast<T>(sacc[t]);
+      state_out[gi] = pv;
+      rec_run_put(c.rec, gi, pv);
+      state_out[N + gi] = static_cast<T>(sacc[TX * TY + t]);
+      state_out[2 * N + gi] = static_cast<T>(sacc[2 * TX * TY + t]);
+    } else {
+      acc_out[gi] = sacc[t];
+      acc_out[N + gi] = sacc[TX * TY + t];
+      acc_out[2 * N + gi] = sacc[2 * TX * TY + t];
+    }
   }
 }
 
@@ -230,14 +247,15 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
 // shared halo rows are read from its L2.
 template <typename T, int S, int K>
 __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d(
-    Geo<T, K, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp, const T* acc_in,
-    T* __restrict__ out_last, T* __restrict__ out_prev, T* acc_out, FusedArgs<T, S> c, Src<T> src) {
+    Geo<T, K, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp, const double* acc_in,
+    T* __restrict__ out_last, T* __restrict__ out_prev, double* acc_out, T* state_out,
+    FusedArgs<T, S> c, Src<T> src) {
   const int b = blockIdx.x;
   const int kk = b >> 3;
   const int ty_ = kk / c.band_w;
   const int tx_ = (b & 7) * c.band_w + (kk - ty_ * c.band_w);
   if (tx_ >= c.tiles_x || ty_ >= c.tiles_y) return;
-  fused2d_pass<T, S, K>(g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src, tx_, ty_, 0);
+  fused2d_pass<T, S, K>(g, vp, vpp, acc_in, out_last, out_prev, acc_out, state_out, c, src, tx_, ty_, 0);
 }
 
 // Fusion depth actually used for a request (1 = unfused kernels): 2D order 4
@@ -262,20 +280,20 @@ int fused_depth(int requested, int m, int64_t npts) {
 
 template <typename T, int S, int K>
 int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
-                     const T* vp, const T* vpp, const T* acc_in, T* out_last, T* out_prev,
-                     T* acc_out, int j, bool first, const double* a, const double* q,
-                     double gamma, double c0, double c1, RecRun<T> rec) {
+                     const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
+                     double* acc_out, T* state_out, int j, bool first, const double* a,
+                     const double* q, double gamma, double c0, double c1, RecRun<T> rec) {
   FusedArgs<T, S> c{};
   c.rec = rec;
-  c.inv_gamma = static_cast<T>(1.0 / gamma);
-  c.c0 = static_cast<T>(c0);
+  c.inv_gamma = 1.0 / gamma;
+  c.c0 = c0;
   c.first = first ? 1 : 0;
-  if (first) split_weight(a[0], &c.a_first, &c.a_first_lo);
+  if (first) c.a_first = a[0];
   for (int r = 0; r < S; ++r) {
     const int jj = j + r;
-    split_weight(a[jj], &c.a[r], &c.a_lo[r]);
-    c.cpp[r] = static_cast<T>(jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1));
-    c.q[r] = static_cast<T>(q[jj - 1]);
+    c.a[r] = a[jj];
+    c.cpp[r] = jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1);
+    c.q[r] = q[jj - 1];
   }
   constexpr int TX = FusedTile<S, K>::TX, TY = FusedTile<S, K>::TY;
   const int tx = static_cast<int>((g.n[0] + TX - 1) / TX);
@@ -284,11 +302,14 @@ int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<
   c.tiles_y = ty;
   c.band_w = (tx + 7) / 8;
   const unsigned blocks = 8u * static_cast<unsigned>(c.band_w) * static_cast<unsigned>(ty);
-  // algorithmic words per point: v_{j-1} (3), c^2 (1), and unless first v_{j-2}
-  // and the partial sum (3 + 3); writes: the sum (3), and unless last the pair (3 + 3)
-  const double words = 3 + 1 + (first ? 0 : 6) + 3 + (out_last ? 6 : 0);
-  launch_timed(prof, st, EXPW_KERNEL_FABER, words * g.N * sizeof(T), k_faber_fused2d<T, S, K>,
-               dim3(blocks), dim3(kFusedNT), g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src);
+  // algorithmic bytes per point: reads v_{j-1} (3 T), c^2 (1 T), and unless
+  // first v_{j-2} (3 T) and the FP64 sum (3 doubles); writes the sum (3
+  // doubles, or the step's result: 3 T), and unless last the pair (6 T)
+  const double bytes = (3 + 1 + (first ? 0 : 3) + (out_last ? 6 : 0) + (state_out ? 3 : 0)) * sizeof(T) +
+                       ((first ? 0 : 3) + (state_out ? 0 : 3)) * sizeof(double);
+  launch_timed(prof, st, EXPW_KERNEL_FABER, bytes * g.N, k_faber_fused2d<T, S, K>,
+               dim3(blocks), dim3(kFusedNT), g, vp, vpp, acc_in, out_last, out_prev, acc_out,
+               state_out, c, src);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "fused Faber pass: %s", hipGetErrorString(e));
   return EXPW_OK;
@@ -296,13 +317,13 @@ int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<
 
 template <typename T, int K>
 int32_t launch_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
-                    const T* vp, const T* vpp, const T* acc_in, T* out_last, T* out_prev,
-                    T* acc_out, int j, bool first, const double* a, const double* q,
-                    double gamma, double c0, double c1, RecRun<T> rec) {
+                    const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
+                    double* acc_out, T* state_out, int j, bool first, const double* a,
+                    const double* q, double gamma, double c0, double c1, RecRun<T> rec) {
 #define EXPW_PASS(S_)                                                                          \
   case S_:                                                                                     \
     return launch_fused<T, S_, K>(st, prof, g, src, vp, vpp, acc_in, out_last, out_prev,      \
-                                  acc_out, j, first, a, q, gamma, c0, c1, rec);
+                                  acc_out, state_out, j, first, a, q, gamma, c0, c1, rec);
   if constexpr (sizeof(T) == 4 && K == 2) {
     switch (n) {
       EXPW_PASS(2) EXPW_PASS(3) EXPW_PASS(4) EXPW_PASS(5) EXPW_PASS(6) EXPW_PASS(7) EXPW_PASS(8)
@@ -318,36 +339,48 @@ int32_t launch_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g
   return fail(EXPW_EUNSUPPORTED, "no fused pass of %d terms", n);
 }
 
+// The buffers of a Faber step: the FP64 partial sum C and two (v_last,
+// v_prev) pairs of the storage precision.
+template <typename T>
+struct FaberBufs {
+  double* C;
+  T *A, *B, *D, *E;
+};
+
 // One Faber step of degree m in passes of s terms (the last pass takes the
 // remainder; a remainder of one term runs as an unfused final term).
-// Buffers: S0 = state (v0), A/B and D/E alternate as (v_last, v_prev), C holds
-// the partial sum; the last pass writes the sum into S0 unless it also read S0.
-// pass(n, vp, vpp, acc_in, out_last, out_prev, acc_out, j, first) launches
-// one pass of n terms starting at term j.
+// S0 = state (v0); A/B and D/E alternate as (v_last, v_prev); C holds the
+// FP64 partial sum between passes. The last pass rounds the sum into S0,
+// except when it is also the first (it reads S0 with its halo): then into A,
+// copied to S0 afterwards.
+// pass(n, vp, vpp, acc_in, out_last, out_prev, acc_out, state_out, j, first)
+// launches one pass of n terms starting at term j; final_term(vp, vpp,
+// acc_in, state_out, j) the unfused last term.
 template <typename T, class Term, class Pass>
-int32_t faber_fused_passes(hipStream_t st, int64_t ns, T* S0, T* A, T* B, T* C, T* D, T* E, int m,
-                           int s, Term&& final_term, Pass&& pass) {
+int32_t faber_fused_passes(hipStream_t st, int64_t ns, T* S0, const FaberBufs<T>& b, int m, int s,
+                           Term&& final_term, Pass&& pass) {
   const T* in_last = S0;
   const T* in_prev = nullptr;
-  T* pair[2][2] = {{A, B}, {D, E}};
+  T* pair[2][2] = {{b.A, b.B}, {b.D, b.E}};
   int which = 0;
   int j = 1;
   while (j <= m) {
     int n = std::min(s, m - j + 1);
     const bool first = (j == 1);
-    if (n == 1) {  // a single final term: v_m from (in_last, in_prev), sum into S0
-      int32_t rc = final_term(in_last, in_prev, C, S0, j);
+    if (n == 1) {  // a single final term: v_m from (in_last, in_prev), result into S0
+      int32_t rc = final_term(in_last, in_prev, b.C, S0, j);
       if (rc != EXPW_OK) return rc;
       break;
     }
     const bool last = (j + n - 1 == m);
-    T* acc_out = (last && !first) ? S0 : C;
     T* ol = last ? nullptr : pair[which][0];
     T* opv = last ? nullptr : pair[which][1];
-    int32_t rc = pass(n, in_last, in_prev, first ? nullptr : C, ol, opv, acc_out, j, first);
+    double* acc_out = last ? nullptr : b.C;
+    T* state_out = last ? (first ? b.A : S0) : nullptr;
+    int32_t rc = pass(n, in_last, in_prev, first ? nullptr : b.C, ol, opv, acc_out, state_out, j, first);
     if (rc != EXPW_OK) return rc;
     if (last && first)
-      if (hipMemcpyAsync(S0, C, ns * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      if (hipMemcpyAsync(S0, b.A, ns * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
         return fail(EXPW_EDEVICE, "fused Faber: copy failed");
     in_last = ol;
     in_prev = opv;

@@ -13,7 +13,9 @@
 // per iteration separates all of them. Every global load of an iteration is
 // issued one iteration ahead. Per point and pass: reads u, v_{j-2}, the sum (4 words each)
 // and c^2, writes v_{j+1}, v_j and the sum: 25 words for two terms against 42
-// for two one-term sweeps.
+// for two one-term sweeps (the sum in FP64: two words more each way). The
+// terms are computed in FP64 from the stored values and kept in T (see
+// FaberTerm).
 #pragma once
 
 #include "device_common.h"
@@ -27,12 +29,11 @@ constexpr int k3X = 64, k3Y = 16, k3NT = k3X * k3Y;  // threads: columns of the 
 constexpr int k3TX = k3X - 8, k3TY = k3Y - 8;        // output tile
 constexpr int k3ZC = 64;                             // output planes per workgroup
 
-template <typename T>
 struct Fused3Args {
-  T inv_gamma, c0, a_first, a_first_lo;  // weights as hi + lo (see FaberTerm)
-  int32_t first;                         // first pass: acc = a_first u, no v_{j-2}
+  double inv_gamma, c0, a_first;
+  int32_t first;  // first pass: acc = a_first u, no v_{j-2}
   int32_t tiles_x, tiles_y;
-  T a[2], a_lo[2], cpp[2], q[2];
+  double a[2], cpp[2], q[2];
 };
 
 template <typename T>
@@ -53,8 +54,9 @@ __device__ __forceinline__ T source_amp(const Src<T>& src, int64_t gi) {
 
 template <typename T>
 __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
-    Geo<T, 2, 3> g, const T* __restrict__ vp, const T* __restrict__ vpp, const T* acc_in,
-    T* __restrict__ out_last, T* __restrict__ out_prev, T* acc_out, Fused3Args<T> c, Src<T> src) {
+    Geo<T, 2, 3> g, const T* __restrict__ vp, const T* __restrict__ vpp,
+    const double* __restrict__ acc_in, T* __restrict__ out_last, T* __restrict__ out_prev,
+    double* __restrict__ acc_out, T* __restrict__ state_out, Fused3Args c, Src<T> src) {
   __shared__ T su[3][3][k3NT];  // u planes: ring slot, field (p, v_x, v_y), column
   __shared__ T sa[3][3][k3NT];  // a planes
   const int b = blockIdx.x;
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
   const T sxh = inxy ? g.shalf[0][x] : T(0), syh = inxy ? g.shalf[1][y] : T(0);
   const int zc0 = zci * k3ZC;
   const int zc1 = min(zc0 + k3ZC, nz);
-  const T w0 = g.w[0], w1 = g.w[1];
+  const double w0 = g.wd[0], w1 = g.wd[1];
   constexpr int R = k3X;  // LDS row stride
 
   T qp[5], qvx[5], qvy[5], qvz[5];  // u at planes k-4..k (index 0 oldest)
@@ -89,7 +91,8 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
   // iteration k - 1 (u at plane k; v_{j-2} and c^2 at plane k - 2; c^2 and
   // the sum at plane k - 4), so the loads overlap a whole iteration.
   struct Ahead {
-    T u[4], w[4], acc[4], c2a, c2b;
+    T u[4], w[4], c2a, c2b;
+    double acc[4];
   };
   auto load_ahead = [&](int k, Ahead& o) {
     const bool in = inxy && k >= 0 && k < nz;
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
     const bool t1 = in_tile && z1 >= zc0 && z1 < zc1;
     const int64_t g1 = col + static_cast<int64_t>(t1 ? z1 : 0) * sxy;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) o.acc[f] = (t1 && !c.first) ? acc_in[f * N + g1] : T(0);
+    for (int f = 0; f < 4; ++f) o.acc[f] = (t1 && !c.first) ? acc_in[f * N + g1] : 0.0;
     o.c2b = t1 ? g.c2[g1] : T(0);
   };
   Ahead nxt;
@@ -133,25 +136,27 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
       const T* VX = su[s0][1];
       const T* VY = su[s0][2];
       const int l = tid;
-      const T pc = qp[2], vxc = qvx[2], vyc = qvy[2], vzc = qvz[2];
-      const T dvx = w0 * (vxc - VX[l - 1]) + w1 * (VX[l + 1] - VX[l - 2]);
-      const T dvy = w0 * (vyc - VY[l - R]) + w1 * (VY[l + R] - VY[l - 2 * R]);
-      const T dvz = w0 * (qvz[2] - qvz[1]) + w1 * (qvz[3] - qvz[0]);
-      const T dpx = w0 * (P[l + 1] - pc) + w1 * (P[l + 2] - P[l - 1]);
-      const T dpy = w0 * (P[l + R] - pc) + w1 * (P[l + 2 * R] - P[l - R]);
-      const T dpz = w0 * (qp[3] - qp[2]) + w1 * (qp[4] - qp[1]);
+#define D_(x) static_cast<double>(x)
+      const double pc = D_(qp[2]), vxc = D_(qvx[2]), vyc = D_(qvy[2]), vzc = D_(qvz[2]);
+      const double dvx = w0 * (vxc - D_(VX[l - 1])) + w1 * (D_(VX[l + 1]) - D_(VX[l - 2]));
+      const double dvy = w0 * (vyc - D_(VY[l - R])) + w1 * (D_(VY[l + R]) - D_(VY[l - 2 * R]));
+      const double dvz = w0 * (D_(qvz[2]) - D_(qvz[1])) + w1 * (D_(qvz[3]) - D_(qvz[0]));
+      const double dpx = w0 * (D_(P[l + 1]) - pc) + w1 * (D_(P[l + 2]) - D_(P[l - 1]));
+      const double dpy = w0 * (D_(P[l + R]) - pc) + w1 * (D_(P[l + 2 * R]) - D_(P[l - R]));
+      const double dpz = w0 * (D_(qp[3]) - D_(qp[2])) + w1 * (D_(qp[4]) - D_(qp[1]));
       const int64_t gi = col + static_cast<int64_t>(z0) * sxy;
-      const T hp = -cu.c2a * (dvx + dvy + dvz) - (sxy_int + g.sint[2][z0]) * pc;
-      const T hvx = -dpx - sxh * vxc;
-      const T hvy = -dpy - syh * vyc;
-      const T hvz = -dpz - g.shalf[2][z0] * vzc;
-      const T self[4] = {pc, vxc, vyc, vzc};
-      const T h[4] = {hp, hvx, hvy, hvz};
+      const double hp = -D_(cu.c2a) * (dvx + dvy + dvz) - (D_(sxy_int) + D_(g.sint[2][z0])) * pc;
+      const double hvx = -dpx - D_(sxh) * vxc;
+      const double hvy = -dpy - D_(syh) * vyc;
+      const double hvz = -dpz - D_(g.shalf[2][z0]) * vzc;
+      const double self[4] = {pc, vxc, vyc, vzc};
+      const double h[4] = {hp, hvx, hvy, hvz};
+      double src0 = 0.0;
+      if (src.n > 0) src0 = c.q[0] * D_(source_amp(src, gi));
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        a0[f] = h[f] * c.inv_gamma - c.c0 * self[f] - c.cpp[0] * cu.w[f];
-      }
-      a0[0] += c.q[0] * source_amp(src, gi);
+      for (int f = 0; f < 4; ++f)
+        a0[f] = static_cast<T>(h[f] * c.inv_gamma - c.c0 * self[f] - c.cpp[0] * D_(cu.w[f]) +
+                               (f == 0 ? src0 : 0.0));
     }
     const int sz0 = (z0 + 6) % 3;
     sa[sz0][0][tid] = a0[0];
@@ -170,35 +175,38 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
       const T* VX = sa[s1][1];
       const T* VY = sa[s1][2];
       const int l = tid;
-      const T pc = ap[2], vxc = avx[0], vyc = avy[0], vzc = avz[2];
-      const T dvx = w0 * (vxc - VX[l - 1]) + w1 * (VX[l + 1] - VX[l - 2]);
-      const T dvy = w0 * (vyc - VY[l - R]) + w1 * (VY[l + R] - VY[l - 2 * R]);
-      const T dvz = w0 * (avz[2] - avz[1]) + w1 * (avz[3] - avz[0]);
-      const T dpx = w0 * (P[l + 1] - pc) + w1 * (P[l + 2] - P[l - 1]);
-      const T dpy = w0 * (P[l + R] - pc) + w1 * (P[l + 2 * R] - P[l - R]);
-      const T dpz = w0 * (ap[3] - ap[2]) + w1 * (ap[4] - ap[1]);
+      const double pc = D_(ap[2]), vxc = D_(avx[0]), vyc = D_(avy[0]), vzc = D_(avz[2]);
+      const double dvx = w0 * (vxc - D_(VX[l - 1])) + w1 * (D_(VX[l + 1]) - D_(VX[l - 2]));
+      const double dvy = w0 * (vyc - D_(VY[l - R])) + w1 * (D_(VY[l + R]) - D_(VY[l - 2 * R]));
+      const double dvz = w0 * (D_(avz[2]) - D_(avz[1])) + w1 * (D_(avz[3]) - D_(avz[0]));
+      const double dpx = w0 * (D_(P[l + 1]) - pc) + w1 * (D_(P[l + 2]) - D_(P[l - 1]));
+      const double dpy = w0 * (D_(P[l + R]) - pc) + w1 * (D_(P[l + 2 * R]) - D_(P[l - R]));
+      const double dpz = w0 * (D_(ap[3]) - D_(ap[2])) + w1 * (D_(ap[4]) - D_(ap[1]));
       const int64_t gi = col + static_cast<int64_t>(z1) * sxy;
-      const T hp = -cu.c2b * (dvx + dvy + dvz) - (sxy_int + g.sint[2][z1]) * pc;
-      const T hvx = -dpx - sxh * vxc;
-      const T hvy = -dpy - syh * vyc;
-      const T hvz = -dpz - g.shalf[2][z1] * vzc;
-      const T self[4] = {pc, vxc, vyc, vzc};
-      const T h[4] = {hp, hvx, hvy, hvz};
+      const double hp = -D_(cu.c2b) * (dvx + dvy + dvz) - (D_(sxy_int) + D_(g.sint[2][z1])) * pc;
+      const double hvx = -dpx - D_(sxh) * vxc;
+      const double hvy = -dpy - D_(syh) * vyc;
+      const double hvz = -dpz - D_(g.shalf[2][z1]) * vzc;
+      const double self[4] = {pc, vxc, vyc, vzc};
+      const double h[4] = {hp, hvx, hvy, hvz};
       const T uz[4] = {qp[0], qvx[0], qvy[0], qvz[0]};
-      const T am = source_amp(src, gi);
+      const double am = src.n > 0 ? D_(source_amp(src, gi)) : 0.0;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        T v = h[f] * c.inv_gamma - c.c0 * self[f] - c.cpp[1] * uz[f];
+        double v = h[f] * c.inv_gamma - c.c0 * self[f] - c.cpp[1] * D_(uz[f]);
         if (f == 0) v += c.q[1] * am;
-        T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, uz[f]) : cu.acc[f];
-        acc = add_weighted(acc, c.a[0], c.a_lo[0], self[f]);
-        acc = add_weighted(acc, c.a[1], c.a_lo[1], v);
+        const T vt = static_cast<T>(v);
+        double acc = c.first ? c.a_first * D_(uz[f]) : cu.acc[f];
+        acc = fma(c.a[0], self[f], acc);
+        acc = fma(c.a[1], D_(vt), acc);
         if (out_last) {
-          out_last[f * N + gi] = v;
-          out_prev[f * N + gi] = self[f];
+          out_last[f * N + gi] = vt;
+          out_prev[f * N + gi] = static_cast<T>(self[f]);
         }
-        acc_out[f * N + gi] = acc;
+        if (state_out) state_out[f * N + gi] = static_cast<T>(acc);
+        else acc_out[f * N + gi] = acc;
       }
+#undef D_
     }
     __syncthreads();
   }
@@ -206,31 +214,33 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
 
 template <typename T>
 int32_t launch_fused3d(hipStream_t st, Profiler* prof, const Geo<T, 2, 3>& g, Src<T> src,
-                       const T* vp, const T* vpp, const T* acc_in, T* out_last, T* out_prev,
-                       T* acc_out, int j, bool first, const double* a, const double* q,
-                       double gamma, double c0, double c1) {
-  Fused3Args<T> c{};
-  c.inv_gamma = static_cast<T>(1.0 / gamma);
-  c.c0 = static_cast<T>(c0);
+                       const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
+                       double* acc_out, T* state_out, int j, bool first, const double* a,
+                       const double* q, double gamma, double c0, double c1) {
+  Fused3Args c{};
+  c.inv_gamma = 1.0 / gamma;
+  c.c0 = c0;
   c.first = first ? 1 : 0;
-  if (first) split_weight(a[0], &c.a_first, &c.a_first_lo);
+  if (first) c.a_first = a[0];
   for (int r = 0; r < 2; ++r) {
     const int jj = j + r;
-    split_weight(a[jj], &c.a[r], &c.a_lo[r]);
-    c.cpp[r] = static_cast<T>(jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1));
-    c.q[r] = static_cast<T>(q[jj - 1]);
+    c.a[r] = a[jj];
+    c.cpp[r] = jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1);
+    c.q[r] = q[jj - 1];
   }
   c.tiles_x = static_cast<int>((g.n[0] + k3TX - 1) / k3TX);
   c.tiles_y = static_cast<int>((g.n[1] + k3TY - 1) / k3TY);
   const int64_t chunks = (g.n[2] + k3ZC - 1) / k3ZC;
   const int64_t blocks = static_cast<int64_t>(c.tiles_x) * c.tiles_y * chunks;
   if (blocks > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "3D fused pass: grid too large");
-  // algorithmic words per point: u (4), c^2 (1), unless first v_{j-2} and the
-  // sum (4 + 4); writes: the sum (4), unless last the pair (4 + 4)
-  const double words = 4 + 1 + (first ? 0 : 8) + 4 + (out_last ? 8 : 0);
-  launch_timed(prof, st, EXPW_KERNEL_FABER, words * g.N * sizeof(T), k_faber_fused3d<T>,
+  // algorithmic bytes per point: u (4 T), c^2 (1 T), unless first v_{j-2}
+  // (4 T) and the sum (4 FP64); writes the sum (4 FP64, or the step's result:
+  // 4 T), unless last the pair (8 T)
+  const double bytes = (4 + 1 + (first ? 0 : 4) + (out_last ? 8 : 0) + (state_out ? 4 : 0)) * sizeof(T) +
+                       ((first ? 0 : 4) + (state_out ? 0 : 4)) * sizeof(double);
+  launch_timed(prof, st, EXPW_KERNEL_FABER, bytes * g.N, k_faber_fused3d<T>,
                dim3(static_cast<unsigned>(blocks)), dim3(k3NT), g, vp, vpp, acc_in, out_last,
-               out_prev, acc_out, c, src);
+               out_prev, acc_out, state_out, c, src);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "3D fused Faber pass: %s", hipGetErrorString(e));
   return EXPW_OK;

@@ -399,6 +399,32 @@ int32_t expw_spectrum_rectangle(const expw_grid* g, double c2_max, double* x_lo,
   return EXPW_OK;
 }
 
+int32_t expw_spectrum_rectangle_profiles(const expw_grid* g, double c2_max,
+                                         const double* const* sigma_host, double* x_lo,
+                                         double* B) {
+  if (!sigma_host) return expw_spectrum_rectangle(g, c2_max, x_lo, B);
+  if (int32_t rc = expw_spectrum_rectangle(g, c2_max, x_lo, B)) return rc;
+  // x_lo = -(largest damping): sigma_p sums the axes' integer-point values (its
+  // maximum is the sum of their maxima), v_a takes axis a's half-point values
+  double smax_p = 0.0, smax_v = 0.0;
+  for (int a = 0; a < g->ndim; ++a) {
+    const double* si = sigma_host[2 * a];
+    const double* sh = sigma_host[2 * a + 1];
+    if (!si || !sh) return expw::fail(EXPW_EINVAL, "expw_spectrum_rectangle_profiles: NULL profile");
+    double mi = 0.0, mh = 0.0;
+    for (int64_t i = 0; i < g->n[a]; ++i) {
+      if (!(si[i] >= 0.0) || !(sh[i] >= 0.0) || !std::isfinite(si[i]) || !std::isfinite(sh[i]))
+        return expw::fail(EXPW_EINVAL, "expw_spectrum_rectangle_profiles: profile values must be finite and >= 0");
+      mi = std::fmax(mi, si[i]);
+      mh = std::fmax(mh, sh[i]);
+    }
+    smax_p += mi;
+    smax_v = std::fmax(smax_v, mh);
+  }
+  *x_lo = -std::fmax(smax_p, smax_v);
+  return EXPW_OK;
+}
+
 int32_t expw_faber_coefficients(double gamma, double c0, double c1, double dt, int32_t m,
                                 double* a) {
   if (!(gamma > 0.0) || !(dt > 0.0) || m < 0 || !a || !(std::fabs(c1) <= 1.0) ||

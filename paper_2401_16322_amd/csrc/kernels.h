@@ -22,16 +22,28 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo<T, K, DIM> g, const T* __r
 
 // Coefficients of one Faber term j (Sec. 3.2, Faber recurrence):
 //   v_j = (H~ v_{j-1}) / gamma - c0 v_{j-1} - cpp v_{j-2}
-//   acc = (first ? a_first v_{j-1} : acc) + a_j v_j
+//   sum = (first ? a_first v_{j-1} : sum) + a_j v_j
 // cpp is 0 for j = 1, 2 c1 for j = 2 and c1 beyond; the source adds
-// src.q * amp_s to the pressure of v_j at each source node. Each weight a is
-// given as hi + lo in T (lo = a - hi, zero in FP64): the same rounding of a
-// weight would otherwise repeat in every step and accumulate.
-template <typename T>
+// src.q * amp_s to the pressure of v_j at each source node.
+//
+// Precision: every term is computed in FP64 from the stored values of
+// precision T and stored back in T; the partial sum is FP64 in memory and
+// the step's result is rounded to T once. With FP32 storage the rounding of
+// intermediate arithmetic (not of the stored terms) is what would otherwise
+// accumulate over many steps: a term's FP32 operations on nearly the same
+// data in consecutive steps round nearly the same way, so their errors add up
+// coherently, and so do those of a partial sum whose terms cancel.
 struct FaberTerm {
-  T inv_gamma, c0, cpp, a_first, a_j, a_first_lo, a_j_lo;
+  double inv_gamma, c0, cpp, a_first, a_j;
   int32_t first;
 };
+
+// The two parts of a weight in T.
+template <typename T>
+inline void split_weight(double a, T* hi, T* lo) {
+  *hi = static_cast<T>(a);
+  *lo = static_cast<T>(a - static_cast<double>(*hi));
+}
 
 // acc + (hi + lo) x, hi and lo the two parts of one weight.
 template <typename T>
@@ -41,37 +53,36 @@ __device__ __forceinline__ T add_weighted(T acc, T hi, T lo, T x) {
   return acc;
 }
 
-// The two parts of a weight in T.
-template <typename T>
-inline void split_weight(double a, T* hi, T* lo) {
-  *hi = static_cast<T>(a);
-  *lo = static_cast<T>(a - static_cast<double>(*hi));
-}
-
-// vout may alias vpp and acc_out may alias acc_in or vpp (pointwise reuse);
-// vp is read with a halo and must not alias any output. vout == nullptr skips
-// storing v_j (last term of a step); acc_out == nullptr skips the sum (terms
-// recomputed for the adjoint).
+// vout may alias vpp (pointwise reuse); vp is read with a halo and must not
+// alias any output. vout == nullptr skips storing v_j (last term of a step).
+// The sum goes to state_out (rounded to T: the step's result) when it is
+// given, else to acc_out (FP64; may alias acc_in); both null skips the sum
+// (terms recomputed for the adjoint).
 template <typename T, int K, int BC, int DIM>
 __global__ __launch_bounds__(kBlock) void k_faber_term(Geo<T, K, DIM> g, const T* vp,
-                                                       const T* vpp, T* vout, const T* acc_in,
-                                                       T* acc_out, FaberTerm<T> c, Src<T> src) {
+                                                       const T* vpp, T* vout,
+                                                       const double* acc_in, double* acc_out,
+                                                       T* state_out, FaberTerm c, Src<T> src) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   if (idx >= g.N) return;
   int64_t ic[3];
   decompose<DIM>(g.n, idx, ic);
-  T o[DIM + 1], s[DIM + 1];
-  apply_point<T, K, BC, DIM>(g, vp, idx, ic, o, s);
+  double o[DIM + 1], s[DIM + 1];
+  apply_point_d<T, K, BC, DIM>(g, vp, idx, ic, o, s);
 #pragma unroll
   for (int f = 0; f <= DIM; ++f) {
     const int64_t e = f * g.N + idx;
-    T v = o[f] * c.inv_gamma - c.c0 * s[f];
-    if (vpp) v -= c.cpp * vpp[e];
-    if (f == 0) v += src_value(src, idx);
-    if (vout) vout[e] = v;
-    if (acc_out) {
-      T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, s[f]) : acc_in[e];
-      acc_out[e] = add_weighted(acc, c.a_j, c.a_j_lo, v);
+    double v = o[f] * c.inv_gamma - c.c0 * s[f];
+    if (vpp) v -= c.cpp * static_cast<double>(vpp[e]);
+    if (f == 0) v += src_value_d(src, idx);
+    const T vt = static_cast<T>(v);
+    if (vout) vout[e] = vt;
+    if (acc_out || state_out) {
+      // the sum takes the stored term, the one the recurrence continues from
+      double acc = c.first ? c.a_first * s[f] : acc_in[e];
+      acc = fma(c.a_j, static_cast<double>(vt), acc);
+      if (state_out) state_out[e] = static_cast<T>(acc);
+      else acc_out[e] = acc;
     }
   }
 }

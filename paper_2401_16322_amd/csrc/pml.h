@@ -17,6 +17,16 @@
 
 namespace expw {
 
+// Coefficients of one Faber term on the PML operator (Sec. 3.2, Faber
+// recurrence): as FaberTerm, computed in the storage precision with each
+// weight a as hi + lo in T (lo = a - hi, zero in FP64), so that the rounding
+// of a weight does not repeat in every step.
+template <typename T>
+struct PmlTerm {
+  T inv_gamma, c0, cpp, a_first, a_j, a_first_lo, a_j_lo;
+  int32_t first;
+};
+
 template <typename T>
 struct PmlGeo {
   int32_t nx, ny;
@@ -127,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_pml_apply(PmlGeo<T> g, const T* __re
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pml_faber_term(PmlGeo<T> g, const T* vp, const T* vpp,
                                                            T* vout, const T* acc_in, T* acc_out,
-                                                           FaberTerm<T> c, Src<T> src) {
+                                                           PmlTerm<T> c, Src<T> src) {
   const int64_t n = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   if (n >= g.N) return;
   const int j = static_cast<int>(n / g.nx), i = static_cast<int>(n - static_cast<int64_t>(j) * g.nx);
@@ -153,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term(PmlGeo<T> g, const T*
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, const T* vp, const T* vpp,
                                                                T* vout, const T* acc_in, T* acc_out,
-                                                               FaberTerm<T> c, Src<T> src,
+                                                               PmlTerm<T> c, Src<T> src,
                                                                int tiles_x) {
   static_assert(kBlock == 256 && kPmlTX == 64, "4 waves, one tile column per lane");
   constexpr int TX = kPmlTX, TY = kPmlTY, HL = kPmlHalo;
@@ -217,8 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, cons
 template <typename T, int NT, int TY>
 __global__ __launch_bounds__(NT) void k_pml_faber_pair_lds(PmlGeo<T> g, const T* vp, const T* vpp,
                                                            T* out0, T* out1, const T* acc_in,
-                                                           T* acc_out, FaberTerm<T> c0,
-                                                           FaberTerm<T> c1, Src<T> s0, Src<T> s1,
+                                                           T* acc_out, PmlTerm<T> c0,
+                                                           PmlTerm<T> c1, Src<T> s0, Src<T> s1,
                                                            int tiles_x) {
   constexpr int TX = kPmlTX, NW = NT / 64;
   static_assert(NT % 64 == 0 && TY % NW == 0, "whole waves, each wave a set of tile rows");

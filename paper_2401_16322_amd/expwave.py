@@ -65,6 +65,9 @@ SIGNATURES = {
     "expw_faber_source_scalars": (_i32, [_dbl, _dbl, _dbl, _i32, _i32, _pd, _pd]),
     "expw_expm": (_i32, [_i32, _pd, _pd]),
     "expw_op_create": (_i32, [_pgrid, _vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "expw_op_create_profiles": (_i32, [_pgrid, _vp, ctypes.POINTER(_pd), _i32, _i32, _vp, _sz, _vp,
+                                       ctypes.POINTER(_vp)]),
+    "expw_spectrum_rectangle_profiles": (_i32, [_pgrid, _dbl, ctypes.POINTER(_pd), _pd, _pd]),
     "expw_op_destroy": (_i32, [_vp]),
     "expw_set_stream": (_i32, [_vp, _vp]),
     "expw_get_spectrum": (_i32, [_vp, _pd, _pd]),
@@ -193,6 +196,22 @@ def expw_spectrum_rectangle(grid, c2_max):
     return x_lo.value, B.value
 
 
+def _profile_ptrs(profiles):
+    """(keep-alive arrays, C array of double*) for 2 * ndim 1D damping profiles."""
+    arrs = [np.ascontiguousarray(p, dtype=np.float64) for p in profiles]
+    ptrs = (_pd * len(arrs))(*[_dptr(a) for a in arrs])
+    return arrs, ptrs
+
+
+def expw_spectrum_rectangle_profiles(grid, c2_max, profiles):
+    x_lo, B = _dbl(), _dbl()
+    arrs, ptrs = _profile_ptrs(profiles)
+    _check(load().expw_spectrum_rectangle_profiles(ctypes.byref(grid), c2_max, ptrs,
+                                                   ctypes.byref(x_lo), ctypes.byref(B)))
+    del arrs
+    return x_lo.value, B.value
+
+
 def expw_ellipse(x_lo, B):
     g, c0, c1 = _dbl(), _dbl(), _dbl()
     _check(load().expw_ellipse(x_lo, B, ctypes.byref(g), ctypes.byref(c0), ctypes.byref(c1)))
@@ -245,6 +264,16 @@ def expw_op_create(grid, c2_ptr, max_krylov_k, max_taylor_p, ws_ptr, ws_bytes, s
     h = _vp()
     _check(load().expw_op_create(ctypes.byref(grid), c2_ptr, max_krylov_k, max_taylor_p, ws_ptr,
                                  ws_bytes, stream, ctypes.byref(h)))
+    return h.value
+
+
+def expw_op_create_profiles(grid, c2_ptr, profiles, max_krylov_k, max_taylor_p, ws_ptr, ws_bytes,
+                            stream):
+    h = _vp()
+    arrs, ptrs = _profile_ptrs(profiles)
+    _check(load().expw_op_create_profiles(ctypes.byref(grid), c2_ptr, ptrs, max_krylov_k,
+                                          max_taylor_p, ws_ptr, ws_bytes, stream, ctypes.byref(h)))
+    del arrs
     return h.value
 
 
@@ -438,10 +467,12 @@ class Operator:
     c2: torch tensor on the GPU (float32 or float64) of numpy shape
     (nz, nx) or (nz, ny, nx). States are flat tensors of (ndim+1) * points
     values in the canonical layout [p | v_0 | ... | v_{d-1}].
+    sigma_profiles: None (the quadratic layer of abc_cells and sigma_max) or
+    2 * ndim 1D arrays: axis a at the integer points, then at the half points.
     """
 
     def __init__(self, n, h, c2, order=4, bc="zero", abc_cells=0, sigma_max=0.0,
-                 max_krylov_k=0, max_taylor_p=8):
+                 max_krylov_k=0, max_taylor_p=8, sigma_profiles=None):
         import torch
         self._torch = torch
         if not c2.is_cuda:
@@ -466,8 +497,16 @@ class Operator:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._rec = None
         self.fuse = 0
-        self.op = expw_op_create(self.grid, self.c2.data_ptr(), max_krylov_k, max_taylor_p,
-                                 self.workspace.data_ptr(), nbytes, self._stream())
+        if sigma_profiles is None:
+            self.op = expw_op_create(self.grid, self.c2.data_ptr(), max_krylov_k, max_taylor_p,
+                                     self.workspace.data_ptr(), nbytes, self._stream())
+        else:
+            if len(sigma_profiles) != 2 * self.ndim or any(
+                    len(sigma_profiles[2 * a + hf]) != self.n[a] for a in range(self.ndim) for hf in (0, 1)):
+                raise ValueError("sigma_profiles: 2 * ndim arrays of n[a] values each")
+            self.op = expw_op_create_profiles(self.grid, self.c2.data_ptr(), sigma_profiles,
+                                              max_krylov_k, max_taylor_p, self.workspace.data_ptr(),
+                                              nbytes, self._stream())
 
     def _stream(self):
         return self._torch.cuda.current_stream(self.device).cuda_stream

@@ -35,7 +35,7 @@ RUNS = {
     # long runs on the small box (no layer): 2000, 1000 and 500 steps
     "box241_faber16_dt1": ("layered2d_241x161", "faber", 16, 1e-3, 2.0, 0.25, "interior"),
     "box241_faber16_dt2": ("layered2d_241x161", "faber", 16, 2e-3, 2.0, 0.25, "interior"),
-    "box241_faber24_dt4": ("layered2d_241x161", "faber", 24, 4e-3, 2.0, 0.25, "interior"),
+    "box241_faber24_dt4": ("layered2d_241x161", "faber", 24, 4e-3, 2.0, 0.2, "interior"),
     "box241_krylov10_dt2.5": ("layered2d_241x161", "krylov", 10, 2.5e-3, 2.0, 0.25, "interior"),
     # the 1001 x 501 workload: the bench's Faber configuration over T = 2 s
     "layered1001_faber16_dt2": ("layered2d_1001x501", "faber", 16, 2e-3, 2.0, 0.5, "interior"),

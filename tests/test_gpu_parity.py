@@ -519,3 +519,49 @@ def test_faber_order8_fused_matches_oracle_and_unfused(dtype, m, fuse):
                     ellipse=case.prob.ellipse())
     assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
     assert rel_l2(U.cpu().numpy(), U1.cpu().numpy()) <= (1e-13 if dtype == "float64" else 2e-6)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [(57, 41), (19, 14, 23)])
+def test_caller_damping_profiles_match_oracle(dtype, n):
+    """Caller-given, non-quadratic damping profiles (Sec. 2) through
+    expw_op_create_profiles: H x, Faber steps (default fusion) and Krylov steps
+    with a source against the oracle on the same profiles and its own ellipse."""
+    import torch
+    from oracle.operator import Grid, apply_H
+    from oracle.source import PointSources
+    from oracle.steppers import Problem
+    from paper_2401_16322_amd.expwave import Operator
+    from synthetic import layered_velocity, smooth_state
+    rng = np.random.default_rng(91)
+    profs = []
+    for na in n:
+        for half in (0.0, 0.5):
+            x = (np.arange(na) + half) / (na - 1)
+            profs.append(250.0 * rng.uniform(0.5, 1.0) * np.clip(1.0 - 3.0 * x, 0.0, None) ** 3
+                         + 60.0 * np.exp(-((x - rng.uniform()) / 0.1) ** 2))
+    c2 = layered_velocity(n, 10.0, seed=92) ** 2
+    if dtype == "float32":
+        c2 = c2.astype(np.float32).astype(np.float64)
+    g = Grid(n, 10.0, 4, profiles=tuple(profs))
+    node = int(rng.integers(0, g.npts))
+    prob = Problem(g, c2, PointSources((node,), (1.0,), 15.0, 0.05))
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    op = Operator(n, 10.0, torch.tensor(c2, dtype=tdt, device="cuda"), max_krylov_k=12,
+                  max_taylor_p=8, sigma_profiles=profs)
+    assert np.allclose(op.ellipse, prob.ellipse(), rtol=1e-12, atol=0.0)
+    U0 = smooth_state(n, seed=93, width_cells=max(1.0, min(n) / 8))
+    y = op.apply(torch.tensor(U0, dtype=tdt, device="cuda")).cpu().numpy()
+    ref = apply_H(g, c2, U0)
+    assert np.max(np.abs(y - ref)) <= (1e-13 if dtype == "float64" else 2e-6) * np.max(np.abs(ref))
+    op.set_source_ricker([node], [1.0], 15.0, 0.05, 8)
+    for method, kw in (("faber", dict(m=12, p=8, ellipse=prob.ellipse())), ("krylov", dict(k=12, p=8))):
+        U = torch.tensor(U0, dtype=tdt, device="cuda")
+        if method == "faber":
+            op.step_faber(U, 0.04, 2e-3, 12, 3)
+        else:
+            op.step_krylov(U, 0.04, 2e-3, 12, 3)
+        Uref, _, _ = run(prob, method, U0, 0.04, 2e-3, 3, **kw)
+        assert rel_l2(U.cpu().numpy(), Uref) <= TOL[dtype], method
+    op.close()

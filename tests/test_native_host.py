@@ -178,3 +178,30 @@ def test_dense_coefficients_match_oracle_and_identity_at_zero():
         assert np.max(np.abs(C[i] - ref)) <= 1e-13 * np.max(np.abs(ref))
     with pytest.raises(xw.ExpwError):
         xw.expw_faber_dense_coefficients(g, c0, c1, 8, [-1e-3])
+
+
+def test_spectrum_rectangle_with_caller_profiles_matches_oracle():
+    """Caller-given, non-quadratic damping profiles (Sec. 2): the library's
+    host rectangle equals the oracle's for the same profiles, in 2D and 3D;
+    without profiles it is the quadratic layer's."""
+    from oracle.operator import Grid
+    from oracle.spectrum import spectrum_rectangle
+    from synthetic import layered_velocity
+    rng = np.random.default_rng(21)
+    for n in ((23, 17), (9, 8, 11)):
+        profs = []
+        for na in n:
+            for half in (0.0, 0.5):
+                x = (np.arange(na) + half) / (na - 1)
+                profs.append(150.0 * rng.uniform(0.5, 1.0) * np.clip(1.0 - 2.5 * x, 0.0, None) ** 3
+                             + 40.0 * np.exp(-((x - rng.uniform()) / 0.15) ** 2))
+        c2 = layered_velocity(n, 10.0, seed=22) ** 2
+        g = Grid(n, 10.0, 4, profiles=tuple(profs))
+        xr, Br = spectrum_rectangle(g, c2)
+        grid = xw.make_grid(n, 10.0, 4, xw.EXPW_F64)
+        x_lo, B = xw.expw_spectrum_rectangle_profiles(grid, float(np.max(c2)), profs)
+        assert x_lo == pytest.approx(xr, rel=1e-15) and B == pytest.approx(Br, rel=1e-15)
+    bad = [p.copy() for p in profs]
+    bad[1][3] = -1.0
+    with pytest.raises(xw.ExpwError):
+        xw.expw_spectrum_rectangle_profiles(grid, 1e7, bad)

@@ -13,7 +13,7 @@ import pytest
 from scipy.linalg import expm
 from scipy.sparse.linalg import expm_multiply
 
-from oracle.operator import (Grid, apply_H, assemble_H, d_minus, d_plus, damping_profile,
+from oracle.operator import (Grid, apply_H, assemble_H, d_minus, d_plus, damping_fields, damping_profile,
                              energy, split_state, staggered_weights)
 from oracle.exact import plane_wave, staggered_symbol
 from oracle.spectrum import ellipse_from_rectangle, spectrum_rectangle
@@ -218,3 +218,61 @@ def test_interior_mask_and_relative_error_metric():
     V = U.copy()
     V[: g.npts] *= 1.0 + 1e-6
     assert np.isclose(rel_l2_pressure(g, V, U, interior=False), 1e-6)
+
+
+def _custom_profiles(n, seed):
+    """Non-quadratic, non-symmetric damping profiles: a random non-negative
+    ramp on one side of each axis plus a bump, different at the half points."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for na in n:
+        for half in (0.0, 0.5):
+            x = (np.arange(na) + half) / max(na - 1, 1)
+            prof = 200.0 * rng.uniform(0.5, 1.0) * np.clip(1.0 - 3.0 * x, 0.0, None) ** 3
+            prof += 50.0 * rng.uniform() * np.exp(-((x - rng.uniform()) / 0.1) ** 2)
+            out.append(prof)
+    return tuple(out)
+
+
+@pytest.mark.parametrize("n", [(9, 7), (6, 5, 7)])
+def test_custom_profiles_slicing_equals_assembled_matrix(n):
+    """Caller-given profiles enter the slicing H and the independently
+    assembled sparse H the same way; with the quadratic profile passed
+    explicitly H is unchanged."""
+    rng = np.random.default_rng(12)
+    c2 = layered_velocity(n, 10.0, seed=13) ** 2
+    g = Grid(n, 10.0, 4, profiles=_custom_profiles(n, 14))
+    U = rng.standard_normal(g.nstate)
+    y1 = apply_H(g, c2, U)
+    assert np.max(np.abs(y1 - assemble_H(g, c2) @ U)) <= 1e-13 * np.max(np.abs(y1))
+    gq = Grid(n, 10.0, 4, abc_cells=3, sigma_max=300.0)
+    quad = tuple(damping_profile(n[a], 10.0, 3, 300.0, half) for a in range(len(n))
+                 for half in (False, True))
+    ge = Grid(n, 10.0, 4, profiles=quad)
+    assert np.array_equal(apply_H(gq, c2, U), apply_H(ge, c2, U))
+    # the profile values sit where the reading puts them: sigma_p sums the
+    # axes' integer-point values, v_a takes axis a's half-point values
+    sig_p, sig_v = damping_fields(g)
+    prof = g.profiles
+    node = tuple(rng.integers(0, v) for v in n)          # (i_x, i_y/z, ...)
+    npi = tuple(reversed(node))
+    assert np.isclose(sig_p[npi], sum(prof[2 * a][node[a]] for a in range(len(n))))
+    for a in range(len(n)):
+        assert sig_v[a][npi] == prof[2 * a + 1][node[a]]
+
+
+def test_custom_profiles_energy_decays_and_spectrum_inside_ellipse():
+    n = (12, 10)
+    c2 = layered_velocity(n, 10.0, seed=15) ** 2
+    g = Grid(n, 10.0, 4, profiles=_custom_profiles(n, 16))
+    A = assemble_H(g, c2)
+    U = np.random.default_rng(17).standard_normal(g.nstate)
+    Es = [energy(g, c2, expm_multiply(t * A, U)) for t in (0.0, 0.005, 0.01, 0.02)]
+    assert all(Es[i + 1] < Es[i] for i in range(3))
+    lam = np.linalg.eigvals(A.toarray())
+    x_lo, B = spectrum_rectangle(g, c2)
+    assert x_lo < 0.0
+    assert np.all(lam.real <= 1e-9) and np.all(lam.real >= x_lo - 1e-9)
+    gamma, c0, c1 = ellipse_from_rectangle(x_lo, B)
+    xc, ar, bi = gamma * c0, gamma * (1 + c1), gamma * (1 - c1)
+    assert np.all(((lam.real - xc) / ar) ** 2 + (lam.imag / bi) ** 2 <= 1 + 1e-9)
