@@ -249,6 +249,23 @@ int32_t expw_set_receivers(expw_op* op, int32_t n_rec, const int64_t* node_idx_d
  * data every step, would round coherently and accumulate over long runs. */
 int32_t expw_step_faber(expw_op* op, void* state_dev, double t0, double dt, int32_t m,
                         int64_t nsteps, void* traces_dev);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): expw_step_faber
+ * with the step's buffers (the term vectors and the FP64 partial sum) in a
+ * static device array of the library (EXPW_NOALLOC_SCRATCH_BYTES, one per
+ * GPU, resolved when an operator is created on that GPU) instead of the
+ * operator's workspace. It allocates nothing and calls no allocating
+ * routine; results are those of expw_step_faber bit for bit. Limits: the grid
+ * must need at most EXPW_NOALLOC_SCRATCH_BYTES (8 (ndim + 1) points bytes for
+ * the sum + 4 state vectors of the dtype; EXPW_ENOMEM otherwise), m <=
+ * EXPW_NOALLOC_MAX_M, and kernel timing off (EXPW_EINVAL). Every call on a GPU
+ * uses the same array and leaves it holding its last contents (nothing in it
+ * needs to start at zero): calls that overlap on one GPU (other streams,
+ * other threads, other operators) race. */
+enum { EXPW_NOALLOC_SCRATCH_BYTES = 64 << 20, EXPW_NOALLOC_MAX_M = 128 };
+int32_t expw_step_faber_noalloc(expw_op* op, void* state_dev, double t0, double dt, int32_t m,
+                                int64_t nsteps, void* traces_dev);
+
 /* Faber steps that also record every term at the receivers: the pressure of
  * v_j = F_j(H~) [u_n; e_p], j = 0..m, at receiver r goes to
  * term_traces_dev[(s * (m + 1) + j) * n_rec + r] for step s (device array of

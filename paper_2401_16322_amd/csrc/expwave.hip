@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -66,6 +67,7 @@ struct expw_op {
   int arn_nvmax_clean;  // reduction area consistent for this nvmax (0: fill before the next launch)
   int last_keff;
   double last_beta;
+  char* noalloc_scratch;  // device address of the static scratch on the creating device
   expw::Profiler prof;
 };
 
@@ -1001,6 +1003,34 @@ int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t step0)
   return EXPW_OK;
 }
 
+// The Faber buffers of expw_step_faber_noalloc: one static device array per
+// GPU (every code object load gets its own), shared by all calls on that GPU.
+// Host code must not use the array's name as a device address; its address
+// on each device is taken once with hipGetSymbolAddress while that device is
+// current (noalloc_scratch_on) and used from then on.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+static_assert(kNoallocScratchBytes == static_cast<size_t>(EXPW_NOALLOC_SCRATCH_BYTES),
+              "the header states the scratch size");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// The static scratch's device address on the current device (nullptr and a
+// message on failure).
+char* noalloc_scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
 // Set by an atexit handler registered at the first handle creation. Handles
 // destroyed after exit() has begun (by a later atexit handler or a static
 // destructor) skip their HIP calls: the runtime may already be gone, and the
@@ -1140,6 +1170,9 @@ int32_t expw_op_create_profiles(const expw_grid* g, const void* c2_dev,
   op->arn_nvmax_clean = 0;
   op->last_keff = 0;
   op->last_beta = 0.0;
+  // the allocation-free Faber entry point's buffers on this device (resolved
+  // here, once per device, with the device current)
+  op->noalloc_scratch = noalloc_scratch_on_current_device();
 
   // damping profiles (FP64 on the host, stored in the grid dtype)
   std::vector<std::vector<char>> staging;
@@ -1487,6 +1520,26 @@ int32_t expw_step_faber(expw_op* op, void* state, double t0, double dt, int32_t 
     using T = typename C::type;
     std::vector<double> a(m + 1), q(m);
     return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), nullptr, op->ws + op->off_big, a.data(), q.data());
+  });
+}
+
+int32_t expw_step_faber_noalloc(expw_op* op, void* state, double t0, double dt, int32_t m,
+                                int64_t nsteps, void* traces) {
+  if (int32_t rc = check_step_args(op, state, dt, nsteps)) return rc;
+  if (m < 1 || m > EXPW_NOALLOC_MAX_M)
+    return fail(EXPW_EINVAL, "Faber degree m must be in [1, %d] here", EXPW_NOALLOC_MAX_M);
+  if (op->prof.active()) return fail(EXPW_EINVAL, "expw_step_faber_noalloc: kernel timing must be off");
+  if (!op->noalloc_scratch)
+    return fail(EXPW_EDEVICE, "expw_step_faber_noalloc: the static scratch has no device address");
+  const size_t need = faber_big_bytes((op->g.ndim + 1) * npts(op->g), elem_size(op->g));
+  if (need > kNoallocScratchBytes)
+    return fail(EXPW_ENOMEM, "expw_step_faber_noalloc: the grid needs %zu bytes of scratch, the static scratch holds %zu",
+                need, kNoallocScratchBytes);
+  double a[EXPW_NOALLOC_MAX_M + 1], q[EXPW_NOALLOC_MAX_M];
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), nullptr, op->noalloc_scratch, a, q);
   });
 }
 

@@ -25,6 +25,8 @@ class Profiler {
     used_ = 0;
   }
 
+  bool active() const { return mask_ != 0; }
+
   // mask: bit k enables timing of kernel class k (0 = off)
   void enable(uint32_t mask) {
     mask_ = mask;

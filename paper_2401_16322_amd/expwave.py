@@ -83,6 +83,7 @@ SIGNATURES = {
     "expw_set_guard": (_i32, [_vp, _i32]),
     "expw_set_receivers": (_i32, [_vp, _i32, _vp]),
     "expw_step_faber": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
+    "expw_step_faber_noalloc": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_faber_dense": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp, _vp]),
     "expw_faber_dense_output": (_i32, [_vp, _i32, _i64, _vp, _vp, _vp, _i64, _vp]),
     "expw_batch_table_bytes": (_i32, [_i32, _pgrid, ctypes.POINTER(_sz)]),
@@ -349,6 +350,10 @@ def expw_set_receivers(op, n_rec, idx_ptr):
 
 def expw_step_faber(op, state_ptr, t0, dt, m, nsteps, traces_ptr=None):
     _check(load().expw_step_faber(op, state_ptr, t0, dt, m, nsteps, traces_ptr))
+
+
+def expw_step_faber_noalloc(op, state_ptr, t0, dt, m, nsteps, traces_ptr=None):
+    _check(load().expw_step_faber_noalloc(op, state_ptr, t0, dt, m, nsteps, traces_ptr))
 
 
 def expw_step_faber_dense(op, state_ptr, t0, dt, m, nsteps, traces_ptr, term_traces_ptr):
@@ -646,6 +651,14 @@ class Operator:
         self._check_state(state)
         self._sync_stream()
         expw_step_faber(self.op, state.data_ptr(), t0, dt, m, nsteps, self._traces_ptr(traces, nsteps))
+
+    def step_faber_noalloc(self, state, t0, dt, m, nsteps=1, traces=None):
+        """step_faber with the step's buffers in the library's static device
+        scratch (no device allocation; see expw_step_faber_noalloc)."""
+        self._check_state(state)
+        self._sync_stream()
+        expw_step_faber_noalloc(self.op, state.data_ptr(), t0, dt, m, nsteps,
+                                self._traces_ptr(traces, nsteps))
 
     def step_faber_dense(self, state, t0, dt, m, nsteps, term_traces, traces=None):
         """Faber steps that record every term v_0..v_m at the receivers into
