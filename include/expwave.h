@@ -157,7 +157,10 @@ int32_t expw_expm(int32_t k, const double* A, double* E);
 /* ------------------------------------------------------------------ device */
 
 /* Create an operator from c^2 (device array, one field of the grid dtype) and
- * the damping layer in *grid. Synchronizes: computes max c^2 on the device
+ * the damping layer in *grid: the semi-discrete operator H of U' = H U + f
+ * (Sec. 3) on the staggered grid of Sec. 2.1, with the quadratic absorbing
+ * profile of Sec. 2 (the paper's PML coupling terms dropped: damping on the
+ * diagonal only) and zero values outside the grid. Synchronizes: computes max c^2 on the device
  * (EXPW_ENONFINITE on NaN/Inf or c^2 <= 0), then the spectrum rectangle and
  * the Faber ellipse on the host in FP64, and uploads the 1D damping profiles
  * into the workspace. c2_dev and workspace_dev must stay valid and unmodified
@@ -200,7 +203,9 @@ int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
  * beyond rounding order. */
 int32_t expw_set_tuning(expw_op* op, int32_t fuse);
 
-/* y = H x (no source), x and y device state arrays (must not alias). */
+/* y = H x (no source; Sec. 3, the semi-discrete operator with the staggered
+ * differences of Sec. 2.1), x and y device state arrays in the state layout
+ * (must not alias). */
 int32_t expw_apply(expw_op* op, const void* x_dev, void* y_dev);
 
 /* Point sources sharing one Ricker wavelet (f_peak, t_delay) entering the
@@ -226,8 +231,9 @@ int32_t expw_set_source_taylor(expw_op* op, int32_t n_src, const int64_t* node_i
                                const double* amp_host, int32_t taylor_p, int64_t nsteps,
                                const double* gder_host);
 
-/* Receivers: n_rec flat pressure-node indices in a caller-owned device int64
- * array (validated once, synchronizes). After every step the pressure at the
+/* Receivers (Sec. 5: seismograms recorded at points of the grid): n_rec flat
+ * pressure-node indices in a caller-owned device int64 array (validated once,
+ * synchronizes). After every step the pressure at the
  * receivers is written to traces[step * n_rec + r] when a step call is given
  * a non-NULL traces_dev. n_rec = 0 removes the receivers. When the indices
  * are consecutive (first, first + 1, ...: a receiver line along x) the kernel
@@ -342,8 +348,16 @@ int32_t expw_batch_destroy(expw_batch* b);
  * k <= max_krylov_k. */
 int32_t expw_step_krylov(expw_op* op, void* state_dev, double t0, double dt, int32_t k,
                          int64_t nsteps, void* traces_dev);
+/* Classical four-stage RK4 steps (Sec. 3.1, low-order methods) of
+ * U' = H U + f(t), the source sampled at the stage times t, t + dt/2 (twice)
+ * and t + dt; state, traces and errors as for expw_step_faber. */
 int32_t expw_step_rk4(expw_op* op, void* state_dev, double t0, double dt, int64_t nsteps,
                       void* traces_dev);
+/* Leap-frog steps (Sec. 3.1; the reading for the first-order system): the
+ * staggered-time update v^{n+1/2} = [(1 - sigma dt/2) v^{n-1/2} - dt D+ p^n] /
+ * (1 + sigma dt/2), then p^{n+1} from D- v^{n+1/2} and the source at
+ * t + dt/2, damping averaged the same way. The velocity slots of the state
+ * hold v at t - dt/2 (start from zero velocities at rest). */
 int32_t expw_step_leapfrog(expw_op* op, void* state_dev, double t0, double dt, int64_t nsteps,
                            void* traces_dev);
 
@@ -359,7 +373,11 @@ int32_t expw_sync_status(expw_op* op);
 int32_t expw_set_guard(expw_op* op, int32_t on);
 
 /* Effective dimension and beta of the last Krylov step (host values;
- * synchronizes when the step ran its small exponential on the device). */
+ * synchronizes when the step ran its small exponential on the device).
+ * k_eff is one more than the first column j <= k - 2 with h_{j+1,j} <=
+ * 1e-14 beta, else k; h_{k,k-1} itself is not formed by the persistent
+ * Arnoldi kernel (neither the k x k exponential nor the combination uses it)
+ * and is not read. */
 int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta);
 
 /* Where the Krylov step evaluates y = exp(dt H_k) e_1 (Sec. 3.2: the small

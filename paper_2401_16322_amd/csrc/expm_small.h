@@ -65,9 +65,11 @@ __global__ __launch_bounds__(TS * TS) void k_kry_expm_tile(const double* __restr
   const double hrc = (r < k && c < k && r <= c + 1) ? hess[r * 64 + c] : 0.0;
   if (tid < 64) {
     // keff: one more than the first column whose subdiagonal entry fails the
-    // breakdown test, else k (0 when beta is not positive)
+    // breakdown test, else k (0 when beta is not positive). Columns 0..k-2
+    // only: a breakdown in the last column gives keff = k anyway, and the
+    // persistent Arnoldi kernel does not produce h_{k,k-1}
     const double beta = *beta_p;
-    const bool brk = lane < k && !(hess[(lane + 1) * 64 + lane] > tol * beta);
+    const bool brk = lane + 1 < k && !(hess[(lane + 1) * 64 + lane] > tol * beta);
     const unsigned long long m = __ballot(brk);
     int ke = m ? __ffsll(static_cast<long long>(m)) : k;
     if (!(beta > 0.0)) ke = 0;

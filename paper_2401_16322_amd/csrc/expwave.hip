@@ -22,6 +22,7 @@
 #include "pml.h"
 #include "profiler.h"
 #include "stream.h"
+#include "term_o4.h"
 
 struct expw_op {
   expw_grid g;
@@ -333,6 +334,27 @@ struct WorkEllipse {
   explicit WorkEllipse(const expw_op* op) : gamma(op->gamma), c0(op->c0), c1(op->c1) {}
 };
 
+// Stencil arithmetic of the one-term order-4 kernel (see k_faber_term_o4).
+using TermSC = double;
+
+// One Faber term per sweep: the order-4 zero-ghost kernel where it applies,
+// else the generic one (same arguments and outputs).
+template <typename T, int K, int BC, int DIM>
+void launch_term(expw_op* op, const Geo<T, K, DIM>& g, double bytes, const T* vp, const T* vpp,
+                 T* vout, const double* acc_in, double* acc_out, T* state_out, const FaberTerm& c,
+                 const Src<T>& src) {
+  if constexpr (K == 2 && BC == 0) {
+    if ((DIM + 1) * g.N < (int64_t(1) << 31)) {
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, bytes, k_faber_term_o4<T, DIM, TermSC>,
+                   o4_grid<DIM>(g.n), dim3(kO4X * kO4Y), g, vp, vpp, vout, acc_in, acc_out, state_out,
+                   c, src);
+      return;
+    }
+  }
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, bytes, k_faber_term<T, K, BC, DIM>,
+               dim3(grid_for(g.N)), dim3(kBlock), g, vp, vpp, vout, acc_in, acc_out, state_out, c, src);
+}
+
 // One Faber step, one term per sweep. term_out (nullable): receives the
 // pressure of every term v_0..v_m at the receivers ((m + 1) * n_rec values).
 template <typename T, int K, int BC, int DIM>
@@ -340,7 +362,6 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse& e
                       const FaberBufs<T>& b, const double* a, const double* q, int m,
                       T* term_out) {
   const int64_t ns = (DIM + 1) * g.N;
-  const unsigned grid = grid_for(g.N);
   const bool keep = term_out != nullptr && op->n_rec > 0;
   auto record = [&](const T* v, int j) -> int32_t {
     return keep ? gather<T>(op, v, term_out + static_cast<int64_t>(j) * op->n_rec, 0) : EXPW_OK;
@@ -360,7 +381,7 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse& e
   // writes [v_j (nf T)] + the sum (nf FP64, or nf T for the step's result)
   T* v1 = (m == 1 && !keep) ? nullptr : b.A;
   T* out1 = m == 1 ? b.B : nullptr;
-  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1) * pb + (v1 ? nf * pb : 0.0) + (m == 1 ? nf * pb : nf * pd), k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, S, nullptr, v1, nullptr, m == 1 ? nullptr : b.C, out1, c, make_src<T>(op, q[0]));
+  launch_term<T, K, BC, DIM>(op, g, (nf + 1) * pb + (v1 ? nf * pb : 0.0) + (m == 1 ? nf * pb : nf * pd), S, nullptr, v1, nullptr, m == 1 ? nullptr : b.C, out1, c, make_src<T>(op, q[0]));
   if (int32_t rc = check_launch("faber j=1")) return rc;
   if (int32_t rc = record(b.A, 1)) return rc;
   if (m == 1) {
@@ -374,7 +395,7 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse& e
   c.cpp = 2.0 * el.c1;
   c.a_j = a[2];
   T* v2 = (m == 2 && !keep) ? nullptr : b.B;
-  launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (2 * nf + 1) * pb + nf * pd + (v2 ? nf * pb : 0.0) + (m == 2 ? nf * pb : nf * pd), k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, b.A, S, v2, b.C, m == 2 ? nullptr : b.C, m == 2 ? S : nullptr, c, make_src<T>(op, q[1]));
+  launch_term<T, K, BC, DIM>(op, g, (2 * nf + 1) * pb + nf * pd + (v2 ? nf * pb : 0.0) + (m == 2 ? nf * pb : nf * pd), b.A, S, v2, b.C, m == 2 ? nullptr : b.C, m == 2 ? S : nullptr, c, make_src<T>(op, q[1]));
   if (int32_t rc = check_launch("faber j=2")) return rc;
   if (int32_t rc = record(b.B, 2)) return rc;
   T* last = b.B;   // v_{j-1}
@@ -384,7 +405,7 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse& e
     c.a_j = a[j];
     const bool fin = (j == m);
     T* vj = (fin && !keep) ? nullptr : older;
-    launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (2 * nf + 1) * pb + nf * pd + (vj ? nf * pb : 0.0) + (fin ? nf * pb : nf * pd), k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, last, older, vj, b.C, fin ? nullptr : b.C, fin ? S : nullptr, c, make_src<T>(op, q[j - 1]));
+    launch_term<T, K, BC, DIM>(op, g, (2 * nf + 1) * pb + nf * pd + (vj ? nf * pb : 0.0) + (fin ? nf * pb : nf * pd), last, older, vj, b.C, fin ? nullptr : b.C, fin ? S : nullptr, c, make_src<T>(op, q[j - 1]));
     if (int32_t rc = check_launch("faber term")) return rc;
     if (int32_t rc = record(older, j)) return rc;
     std::swap(last, older);
@@ -425,7 +446,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
       c.c0 = el.c0;
       c.cpp = el.c1;
       c.a_j = a[j];
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, ((3.0 * (DIM + 1) + 1) * sizeof(T) + (DIM + 1) * sizeof(double)) * g.N, k_faber_term<T, K, BC, DIM>, dim3(grid_for(g.N)), dim3(kBlock), g, vl, vpv, nullptr, acc, nullptr, out, c, make_src<T>(op, q[j - 1]));
+      launch_term<T, K, BC, DIM>(op, g, ((3.0 * (DIM + 1) + 1) * sizeof(T) + (DIM + 1) * sizeof(double)) * g.N, vl, vpv, nullptr, acc, nullptr, out, c, make_src<T>(op, q[j - 1]));
       return check_launch("faber final term");
     };
     const Src<T> src0 = make_src<T>(op, 0.0);
@@ -690,7 +711,9 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
         return fail(EXPW_EDEVICE, "krylov: device to host copy failed: %s", hipGetErrorString(hipGetLastError()));
       const double beta = scal_h[1];
       int keff = k;
-      for (int j = 0; j < k; ++j)
+      // columns 0..k-2: a breakdown in the last column gives keff = k anyway,
+      // and the persistent Arnoldi kernel does not produce h_{k,k-1}
+      for (int j = 0; j + 1 < k; ++j)
         if (!(hh[(j + 1) * kHessLd + j] > tol * beta)) {
           keff = j + 1;
           break;

@@ -477,8 +477,11 @@ __global__ __launch_bounds__(kBlock) void k_kry_expm(const double* __restrict__ 
   __shared__ double cs[64], sub[64];
   __shared__ int s_keff, s_sq;
   const int tid = threadIdx.x;
-  // the subdiagonal is loaded in parallel, then scanned in LDS
-  if (tid < k) sub[tid] = hess[(tid + 1) * 64 + tid];
+  // the subdiagonal is loaded in parallel, then scanned in LDS. Only the
+  // columns 0..k-2 are read: a breakdown in the last column would give
+  // k_eff = k anyway, and the persistent Arnoldi kernel does not produce
+  // h_{k,k-1} (its entry holds an older value)
+  if (tid < k - 1) sub[tid] = hess[(tid + 1) * 64 + tid];
   const double beta = *beta_p;
   __syncthreads();
   if (tid == 0) {
@@ -486,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_kry_expm(const double* __restrict__ 
     if (!(beta > 0.0)) {
       ke = 0;
     } else {
-      for (int j = 0; j < k; ++j)
+      for (int j = 0; j + 1 < k; ++j)
         if (!(sub[j] > tol * beta)) {
           ke = j + 1;
           break;

@@ -1,0 +1,124 @@
+// One Faber term per sweep for the order-4 staggered stencil with zero ghost
+// values (Sec. 2.1), in 2D and 3D: the one-term path of the Faber step (3D
+// steps, a single final term after fused passes, depth 1).
+//
+// A 64 x 4 workgroup covers 64 consecutive x-points of 4 consecutive rows
+// (one plane z in 3D), so every wave reads 64 consecutive values of a row.
+// Each point's 4 (3D: 4 fields) neighbour values along each axis are loaded
+// with 32-bit offsets that are clamped to the point itself when the
+// neighbour lies outside the grid (the loaded value is then replaced by
+// zero), so no load sits behind a branch and the compiler issues all of a
+// point's loads together; x-neighbours hit in L1, y- and z-neighbours in
+// L1/L2 (the planes a workgroup reads are read again by the workgroups of the
+// next planes). Arithmetic and precision as in k_faber_term: the stencil
+// sums in SC (FP64, or the storage precision where that is enough), the
+// recurrence combination and the partial sum in FP64.
+#pragma once
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace expw {
+
+constexpr int kO4X = 64, kO4Y = 4;
+
+template <typename T>
+__device__ __forceinline__ T ld_or0(const T* __restrict__ f, int base, int off, bool ok) {
+  const T v = f[base + (ok ? off : 0)];
+  return ok ? v : T(0);
+}
+
+template <typename SC, typename T>
+__device__ __forceinline__ SC to_sc(T v) {
+  return static_cast<SC>(v);
+}
+
+// grid: (ceil(nx / 64), ceil(n1 / 4), n2) for 3D (n1 = ny, n2 = nz), and
+// (ceil(nx / 64), ceil(nz / 4), 1) in 2D. Requires (DIM + 1) * points < 2^31.
+// Outputs as in k_faber_term (vout may alias vpp, acc_out may alias acc_in,
+// state_out may alias vpp; vp must not alias any output).
+template <typename T, int DIM, typename SC>
+__global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g, const T* __restrict__ vp,
+                                                              const T* vpp, T* vout,
+                                                              const double* acc_in, double* acc_out,
+                                                              T* state_out, FaberTerm c, Src<T> src) {
+  const int nx = static_cast<int>(g.n[0]), n1 = static_cast<int>(g.n[1]);
+  const int i = blockIdx.x * kO4X + (threadIdx.x & (kO4X - 1));
+  const int j = blockIdx.y * kO4Y + (threadIdx.x >> 6);
+  const int k = DIM == 3 ? static_cast<int>(blockIdx.z) : 0;
+  if (i >= nx || j >= n1) return;
+  const int n2 = DIM == 3 ? static_cast<int>(g.n[2]) : 1;
+  const int N = static_cast<int>(g.N);
+  const int sy = nx, sz = nx * n1;
+  const int idx = (k * n1 + j) * nx + i;
+  const int coord[3] = {i, j, k};
+  const int ext[3] = {nx, n1, n2};
+  const int str[3] = {1, sy, sz};
+  const T* p = vp;
+  // loads: p at the point and at -1, +1, +2 along each axis; v_a at the point
+  // and at -2, -1, +1 along axis a
+  T pm1[DIM], pp1[DIM], pp2[DIM], vm2[DIM], vm1[DIM], vp1[DIM], vc[DIM];
+  const T pc = p[idx];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* v = vp + (1 + a) * N;
+    const int x = coord[a], n = ext[a], s = str[a];
+    pm1[a] = ld_or0(p, idx, -s, x >= 1);
+    pp1[a] = ld_or0(p, idx, s, x + 1 < n);
+    pp2[a] = ld_or0(p, idx, 2 * s, x + 2 < n);
+    vm2[a] = ld_or0(v, idx, -2 * s, x >= 2);
+    vm1[a] = ld_or0(v, idx, -s, x >= 1);
+    vp1[a] = ld_or0(v, idx, s, x + 1 < n);
+    vc[a] = v[idx];
+  }
+  const T c2 = g.c2[idx];
+  T old[DIM + 1];
+#pragma unroll
+  for (int f = 0; f <= DIM; ++f) old[f] = vpp ? vpp[f * N + idx] : T(0);
+  double acc[DIM + 1];
+#pragma unroll
+  for (int f = 0; f <= DIM; ++f) acc[f] = c.first ? 0.0 : acc_in[f * N + idx];
+
+  // H v at the point: derivatives in SC, the rest in FP64
+  const SC w0 = static_cast<SC>(g.wd[0]), w1 = static_cast<SC>(g.wd[1]);
+  SC div = SC(0);
+  double o[DIM + 1], s[DIM + 1];
+  double sp = 0.0;
+  s[0] = static_cast<double>(pc);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const SC dv = w0 * (to_sc<SC>(vc[a]) - to_sc<SC>(vm1[a])) + w1 * (to_sc<SC>(vp1[a]) - to_sc<SC>(vm2[a]));
+    const SC dp = w0 * (to_sc<SC>(pp1[a]) - to_sc<SC>(pc)) + w1 * (to_sc<SC>(pp2[a]) - to_sc<SC>(pm1[a]));
+    div += dv;
+    sp += static_cast<double>(g.sint[a][coord[a]]);
+    s[1 + a] = static_cast<double>(vc[a]);
+    o[1 + a] = -static_cast<double>(dp) - static_cast<double>(g.shalf[a][coord[a]]) * s[1 + a];
+  }
+  o[0] = -static_cast<double>(c2) * static_cast<double>(div) - sp * s[0];
+  const double q = src.n > 0 ? src_value_d(src, idx) : 0.0;
+#pragma unroll
+  for (int f = 0; f <= DIM; ++f) {
+    const int e = f * N + idx;
+    double v = o[f] * c.inv_gamma - c.c0 * s[f];
+    if (vpp) v -= c.cpp * static_cast<double>(old[f]);
+    if (f == 0) v += q;
+    const T vt = static_cast<T>(v);
+    if (vout) vout[e] = vt;
+    if (acc_out || state_out) {
+      double a_ = c.first ? c.a_first * s[f] : acc[f];
+      a_ = fma(c.a_j, static_cast<double>(vt), a_);
+      if (state_out) state_out[e] = static_cast<T>(a_);
+      else acc_out[e] = a_;
+    }
+  }
+}
+
+template <int DIM>
+inline dim3 o4_grid(const int64_t* n) {
+  return DIM == 3 ? dim3(static_cast<unsigned>((n[0] + kO4X - 1) / kO4X),
+                         static_cast<unsigned>((n[1] + kO4Y - 1) / kO4Y), static_cast<unsigned>(n[2]))
+                  : dim3(static_cast<unsigned>((n[0] + kO4X - 1) / kO4X),
+                         static_cast<unsigned>((n[1] + kO4Y - 1) / kO4Y), 1u);
+}
+
+}  // namespace expw
