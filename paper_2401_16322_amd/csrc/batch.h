@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_faber_batch_term(const BatchShot<T, 
   int64_t ic[3];
   decompose<DIM>(g.n, idx, ic);
   double o[DIM + 1], sv[DIM + 1];
-  apply_point_d<T, K, BC, DIM>(g, vp, idx, ic, o, sv);
+  apply_point_m<T, K, BC, DIM>(g, vp, idx, ic, o, sv);
   // source at this point (rare): scalar of term j at the step time
   double src = 0.0;
   if (sh.n_src > 0 && idx >= sh.src_lo && idx <= sh.src_hi) {

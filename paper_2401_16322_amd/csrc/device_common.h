@@ -23,6 +23,10 @@ struct Geo {
   int64_t N;  // points per field
   T w[K];
   double wd[K];
+  // the weights as small integers (exact in T) times one FP64 factor:
+  // alpha_l / h = wscale * wi[l-1]
+  T wi[K];
+  double wscale;
   const T* __restrict__ c2;
   const T* __restrict__ sint[3];
   const T* __restrict__ shalf[3];
@@ -114,6 +118,40 @@ __device__ __forceinline__ void apply_point_d(const Geo<T, K, DIM>& g, const T* 
     out[1 + a] = -dp - static_cast<double>(g.shalf[a][ic[a]]) * vc;
   }
   out[0] = -static_cast<double>(g.c2[idx]) * div - sp * pc;
+}
+
+// out = H x at one point in mixed precision (the Faber kernels): each
+// staggered difference sum_l wi_l (f_{+} - f_{-}) with the integer weights is
+// formed in T, and everything after it in FP64: the factor wscale (so the
+// operator applied is H itself, not H with weights rounded to T; a rounded
+// weight would change the wave speed slightly and, repeated every term of
+// every step, shift the phase coherently), c^2, the damping and the sums.
+template <typename T, int K, int BC, int DIM>
+__device__ __forceinline__ void apply_point_m(const Geo<T, K, DIM>& g, const T* __restrict__ x,
+                                              int64_t idx, const int64_t* ic, double* out,
+                                              double* self) {
+  const T* __restrict__ p = x;
+  const double pc = static_cast<double>(p[idx]);
+  self[0] = pc;
+  double div = 0.0, sp = 0.0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* __restrict__ v = x + (1 + a) * g.N;
+    T dv = T(0), dp = T(0);
+#pragma unroll
+    for (int l = 1; l <= K; ++l) {
+      dv += g.wi[l - 1] * (ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], l - 1) -
+                           ldn<T, BC>(v, idx, ic[a], g.n[a], g.st[a], -l));
+      dp += g.wi[l - 1] * (ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], l) -
+                           ldn<T, BC>(p, idx, ic[a], g.n[a], g.st[a], 1 - l));
+    }
+    div += static_cast<double>(dv);
+    sp += static_cast<double>(g.sint[a][ic[a]]);
+    const double vc = static_cast<double>(v[idx]);
+    self[1 + a] = vc;
+    out[1 + a] = -static_cast<double>(dp) * g.wscale - static_cast<double>(g.shalf[a][ic[a]]) * vc;
+  }
+  out[0] = -static_cast<double>(g.c2[idx]) * (div * g.wscale) - sp * pc;
 }
 
 // Receivers on a run of consecutive pressure nodes first .. first + n - 1,

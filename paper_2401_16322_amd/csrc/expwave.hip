@@ -212,6 +212,13 @@ Geo<T, K, DIM> make_geo(const expw_op* op) {
     g.wd[l] = op->alpha[l] / op->g.h;
     g.w[l] = static_cast<T>(g.wd[l]);
   }
+  {
+    double wi[4], beta = 0.0;
+    int kk = 0;
+    stagger_weights_int(op->g.order, wi, &beta, &kk);
+    for (int l = 0; l < K; ++l) g.wi[l] = static_cast<T>(wi[l]);
+    g.wscale = beta / op->g.h;
+  }
   g.c2 = static_cast<const T*>(op->c2);
   for (int a = 0; a < 3; ++a) {
     g.sint[a] = reinterpret_cast<const T*>(op->ws + op->off_sig[a][0]);
@@ -334,8 +341,10 @@ struct WorkEllipse {
   explicit WorkEllipse(const expw_op* op) : gamma(op->gamma), c0(op->c0), c1(op->c1) {}
 };
 
-// Stencil arithmetic of the one-term order-4 kernel (see k_faber_term_o4).
-using TermSC = double;
+// Stencil arithmetic of the one-term order-4 kernel (see k_faber_term_o4):
+// difference sums in the storage precision over integer weights.
+template <typename T>
+using TermSC = T;
 
 // One Faber term per sweep: the order-4 zero-ghost kernel where it applies,
 // else the generic one (same arguments and outputs).
@@ -345,7 +354,7 @@ void launch_term(expw_op* op, const Geo<T, K, DIM>& g, double bytes, const T* vp
                  const Src<T>& src) {
   if constexpr (K == 2 && BC == 0) {
     if ((DIM + 1) * g.N < (int64_t(1) << 31)) {
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, bytes, k_faber_term_o4<T, DIM, TermSC>,
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, bytes, k_faber_term_o4<T, DIM, TermSC<T>>,
                    o4_grid<DIM>(g.n), dim3(kO4X * kO4Y), g, vp, vpp, vout, acc_in, acc_out, state_out,
                    c, src);
       return;

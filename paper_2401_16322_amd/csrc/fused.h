@@ -18,9 +18,10 @@
 // partial sum, i.e. 19 words per point per pass instead of 16 per term for
 // one-term sweeps.
 //
-// Every term is computed in FP64 from the stored values and kept in LDS in
-// the storage precision T; the partial sum is FP64 (in LDS and between
-// passes), and the last pass rounds it to T once (see FaberTerm).
+// Every term is computed from the stored values with the difference sums in
+// T (integer weights) and the rest in FP64 (see apply_point_m), and kept in
+// LDS in the storage precision T; the partial sum is FP64 (in LDS and
+// between passes), and the last pass rounds it to T once (see FaberTerm).
 //
 // Tiles are mapped to workgroups so that each XCD (block id mod 8) owns a
 // band of tile columns walked row by row: halo rows shared by neighbouring
@@ -163,18 +164,22 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
       if (r <= last[i]) {
         const int l = (X0 + wave + 16 * i) * EX + lx;
         const T pc = cp[l], vxc = cvx[l], vzc = cvz[l];
-        double dvx = 0.0, dvz = 0.0, dpx = 0.0, dpz = 0.0;
+        // difference sums with the integer weights in T, the rest in FP64
+        // (see apply_point_m)
+        T dvx = T(0), dvz = T(0), dpx = T(0), dpz = T(0);
 #pragma unroll
         for (int q = 1; q <= K; ++q) {
-          const double wq = g.wd[q - 1];
-          dvx += wq * (static_cast<double>(cvx[l + q - 1]) - static_cast<double>(cvx[l - q]));
-          dvz += wq * (static_cast<double>(cvz[l + (q - 1) * EX]) - static_cast<double>(cvz[l - q * EX]));
-          dpx += wq * (static_cast<double>(cp[l + q]) - static_cast<double>(cp[l + 1 - q]));
-          dpz += wq * (static_cast<double>(cp[l + q * EX]) - static_cast<double>(cp[l + (1 - q) * EX]));
+          const T wq = g.wi[q - 1];
+          dvx += wq * (cvx[l + q - 1] - cvx[l - q]);
+          dvz += wq * (cvz[l + (q - 1) * EX] - cvz[l - q * EX]);
+          dpx += wq * (cp[l + q] - cp[l + 1 - q]);
+          dpz += wq * (cp[l + q * EX] - cp[l + (1 - q) * EX]);
         }
-        const double hp = -static_cast<double>(cc2[i]) * (dvx + dvz) - static_cast<double>(sp[i]) * pc;
-        const double hvx = -dpx - static_cast<double>(sxh) * vxc;
-        const double hvz = -dpz - static_cast<double>(szh[i]) * vzc;
+        const double ws = g.wscale;
+        const double hp = -static_cast<double>(cc2[i]) * (static_cast<double>(dvx + dvz) * ws) -
+                          static_cast<double>(sp[i]) * pc;
+        const double hvx = -static_cast<double>(dpx) * ws - static_cast<double>(sxh) * vxc;
+        const double hvz = -static_cast<double>(dpz) * ws - static_cast<double>(szh[i]) * vzc;
         nv[i][0] = static_cast<T>(hp * c.inv_gamma - c.c0 * pc - cpp * static_cast<double>(old[i][0]) +
                                   qr * static_cast<double>(amp[i]));
         nv[i][1] = static_cast<T>(hvx * c.inv_gamma - c.c0 * vxc - cpp * static_cast<double>(old[i][1]));

@@ -14,8 +14,8 @@
 // issued one iteration ahead. Per point and pass: reads u, v_{j-2}, the sum (4 words each)
 // and c^2, writes v_{j+1}, v_j and the sum: 25 words for two terms against 42
 // for two one-term sweeps (the sum in FP64: two words more each way). The
-// terms are computed in FP64 from the stored values and kept in T (see
-// FaberTerm).
+// terms' difference sums are formed in T over integer weights and the rest
+// in FP64, and the terms are kept in T (see apply_point_m and FaberTerm).
 #pragma once
 
 #include "device_common.h"
@@ -77,7 +77,9 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
   const T sxh = inxy ? g.shalf[0][x] : T(0), syh = inxy ? g.shalf[1][y] : T(0);
   const int zc0 = zci * k3ZC;
   const int zc1 = min(zc0 + k3ZC, nz);
-  const double w0 = g.wd[0], w1 = g.wd[1];
+  // difference sums with the integer weights in T, the rest in FP64 (see apply_point_m)
+  const T w0 = g.wi[0], w1 = g.wi[1];
+  const double ws = g.wscale;
   constexpr int R = k3X;  // LDS row stride
 
   T qp[5], qvx[5], qvy[5], qvz[5];  // u at planes k-4..k (index 0 oldest)
@@ -138,17 +140,17 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
       const int l = tid;
 #define D_(x) static_cast<double>(x)
       const double pc = D_(qp[2]), vxc = D_(qvx[2]), vyc = D_(qvy[2]), vzc = D_(qvz[2]);
-      const double dvx = w0 * (vxc - D_(VX[l - 1])) + w1 * (D_(VX[l + 1]) - D_(VX[l - 2]));
-      const double dvy = w0 * (vyc - D_(VY[l - R])) + w1 * (D_(VY[l + R]) - D_(VY[l - 2 * R]));
-      const double dvz = w0 * (D_(qvz[2]) - D_(qvz[1])) + w1 * (D_(qvz[3]) - D_(qvz[0]));
-      const double dpx = w0 * (D_(P[l + 1]) - pc) + w1 * (D_(P[l + 2]) - D_(P[l - 1]));
-      const double dpy = w0 * (D_(P[l + R]) - pc) + w1 * (D_(P[l + 2 * R]) - D_(P[l - R]));
-      const double dpz = w0 * (D_(qp[3]) - D_(qp[2])) + w1 * (D_(qp[4]) - D_(qp[1]));
+      const T dvx = w0 * (qvx[2] - VX[l - 1]) + w1 * (VX[l + 1] - VX[l - 2]);
+      const T dvy = w0 * (qvy[2] - VY[l - R]) + w1 * (VY[l + R] - VY[l - 2 * R]);
+      const T dvz = w0 * (qvz[2] - qvz[1]) + w1 * (qvz[3] - qvz[0]);
+      const T dpx = w0 * (P[l + 1] - qp[2]) + w1 * (P[l + 2] - P[l - 1]);
+      const T dpy = w0 * (P[l + R] - qp[2]) + w1 * (P[l + 2 * R] - P[l - R]);
+      const T dpz = w0 * (qp[3] - qp[2]) + w1 * (qp[4] - qp[1]);
       const int64_t gi = col + static_cast<int64_t>(z0) * sxy;
-      const double hp = -D_(cu.c2a) * (dvx + dvy + dvz) - (D_(sxy_int) + D_(g.sint[2][z0])) * pc;
-      const double hvx = -dpx - D_(sxh) * vxc;
-      const double hvy = -dpy - D_(syh) * vyc;
-      const double hvz = -dpz - D_(g.shalf[2][z0]) * vzc;
+      const double hp = -D_(cu.c2a) * (D_(dvx + dvy + dvz) * ws) - (D_(sxy_int) + D_(g.sint[2][z0])) * pc;
+      const double hvx = -D_(dpx) * ws - D_(sxh) * vxc;
+      const double hvy = -D_(dpy) * ws - D_(syh) * vyc;
+      const double hvz = -D_(dpz) * ws - D_(g.shalf[2][z0]) * vzc;
       const double self[4] = {pc, vxc, vyc, vzc};
       const double h[4] = {hp, hvx, hvy, hvz};
       double src0 = 0.0;
@@ -176,17 +178,17 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
       const T* VY = sa[s1][2];
       const int l = tid;
       const double pc = D_(ap[2]), vxc = D_(avx[0]), vyc = D_(avy[0]), vzc = D_(avz[2]);
-      const double dvx = w0 * (vxc - D_(VX[l - 1])) + w1 * (D_(VX[l + 1]) - D_(VX[l - 2]));
-      const double dvy = w0 * (vyc - D_(VY[l - R])) + w1 * (D_(VY[l + R]) - D_(VY[l - 2 * R]));
-      const double dvz = w0 * (D_(avz[2]) - D_(avz[1])) + w1 * (D_(avz[3]) - D_(avz[0]));
-      const double dpx = w0 * (D_(P[l + 1]) - pc) + w1 * (D_(P[l + 2]) - D_(P[l - 1]));
-      const double dpy = w0 * (D_(P[l + R]) - pc) + w1 * (D_(P[l + 2 * R]) - D_(P[l - R]));
-      const double dpz = w0 * (D_(ap[3]) - D_(ap[2])) + w1 * (D_(ap[4]) - D_(ap[1]));
+      const T dvx = w0 * (avx[0] - VX[l - 1]) + w1 * (VX[l + 1] - VX[l - 2]);
+      const T dvy = w0 * (avy[0] - VY[l - R]) + w1 * (VY[l + R] - VY[l - 2 * R]);
+      const T dvz = w0 * (avz[2] - avz[1]) + w1 * (avz[3] - avz[0]);
+      const T dpx = w0 * (P[l + 1] - ap[2]) + w1 * (P[l + 2] - P[l - 1]);
+      const T dpy = w0 * (P[l + R] - ap[2]) + w1 * (P[l + 2 * R] - P[l - R]);
+      const T dpz = w0 * (ap[3] - ap[2]) + w1 * (ap[4] - ap[1]);
       const int64_t gi = col + static_cast<int64_t>(z1) * sxy;
-      const double hp = -D_(cu.c2b) * (dvx + dvy + dvz) - (D_(sxy_int) + D_(g.sint[2][z1])) * pc;
-      const double hvx = -dpx - D_(sxh) * vxc;
-      const double hvy = -dpy - D_(syh) * vyc;
-      const double hvz = -dpz - D_(g.shalf[2][z1]) * vzc;
+      const double hp = -D_(cu.c2b) * (D_(dvx + dvy + dvz) * ws) - (D_(sxy_int) + D_(g.sint[2][z1])) * pc;
+      const double hvx = -D_(dpx) * ws - D_(sxh) * vxc;
+      const double hvy = -D_(dpy) * ws - D_(syh) * vyc;
+      const double hvz = -D_(dpz) * ws - D_(g.shalf[2][z1]) * vzc;
       const double self[4] = {pc, vxc, vyc, vzc};
       const double h[4] = {hp, hvx, hvy, hvz};
       const T uz[4] = {qp[0], qvx[0], qvy[0], qvz[0]};

@@ -52,6 +52,29 @@ bool stagger_weights(int order, double* alpha, int* K) {
   return false;
 }
 
+bool stagger_weights_int(int order, double* w, double* beta, int* K) {
+  // the same weights as integer multiples of one factor: alpha_l = beta w_l
+  // (order 4: (27, -1) / 24; order 8: 1225 / (1024 * 128625) times
+  // 128625 (1, -1/15, 1/125, -1/1715) = (128625, -8575, 1029, -75))
+  if (order == 4) {
+    w[0] = 27.0;
+    w[1] = -1.0;
+    *beta = 1.0 / 24.0;
+    *K = 2;
+    return true;
+  }
+  if (order == 8) {
+    w[0] = 128625.0;
+    w[1] = -8575.0;
+    w[2] = 1029.0;
+    w[3] = -75.0;
+    *beta = 1225.0 / (1024.0 * 128625.0);
+    *K = 4;
+    return true;
+  }
+  return false;
+}
+
 void damping_profile(int64_t n, double h, int cells, double sigma_max, bool half, double* out) {
   // Sec. 2: sigma(d) = sigma_max (1 - d/delta)^2 for d < delta, 0 otherwise,
   // d = distance to the nearest outer node, clamped at 0 beyond the last node.

@@ -16,6 +16,9 @@ void clear_error();
 
 // Staggered first-derivative weights alpha_1..alpha_K (Sec. 2.1); K = order/2.
 bool stagger_weights(int order, double* alpha /* >= 4 entries */, int* K);
+// The staggered weights as alpha_l = beta * w_l with small integers w_l
+// (exact in FP32).
+bool stagger_weights_int(int order, double* w /* >= 4 entries */, double* beta, int* K);
 
 // Host math (FP64).
 void damping_profile(int64_t n, double h, int cells, double sigma_max, bool half, double* out);

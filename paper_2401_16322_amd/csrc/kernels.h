@@ -26,13 +26,15 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo<T, K, DIM> g, const T* __r
 // cpp is 0 for j = 1, 2 c1 for j = 2 and c1 beyond; the source adds
 // src.q * amp_s to the pressure of v_j at each source node.
 //
-// Precision: every term is computed in FP64 from the stored values of
-// precision T and stored back in T; the partial sum is FP64 in memory and
-// the step's result is rounded to T once. With FP32 storage the rounding of
-// intermediate arithmetic (not of the stored terms) is what would otherwise
-// accumulate over many steps: a term's FP32 operations on nearly the same
-// data in consecutive steps round nearly the same way, so their errors add up
-// coherently, and so do those of a partial sum whose terms cancel.
+// Precision: every term is computed from the stored values of precision T
+// with the stencil's difference sums in T over integer weights and
+// everything after them in FP64 (apply_point_m), and stored back in T; the
+// partial sum is FP64 in memory and the step's result is rounded to T once.
+// With FP32 storage two things would otherwise accumulate over many steps:
+// weights rounded to FP32 (a slightly different wave speed, the same in
+// every term of every step) and the rounding of a partial sum whose terms
+// cancel (nearly the same data in consecutive steps rounds nearly the same
+// way, so those errors add up coherently).
 struct FaberTerm {
   double inv_gamma, c0, cpp, a_first, a_j;
   int32_t first;
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_faber_term(Geo<T, K, DIM> g, const T
   int64_t ic[3];
   decompose<DIM>(g.n, idx, ic);
   double o[DIM + 1], s[DIM + 1];
-  apply_point_d<T, K, BC, DIM>(g, vp, idx, ic, o, s);
+  apply_point_m<T, K, BC, DIM>(g, vp, idx, ic, o, s);
 #pragma unroll
   for (int f = 0; f <= DIM; ++f) {
     const int64_t e = f * g.N + idx;

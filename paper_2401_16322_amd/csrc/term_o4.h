@@ -10,9 +10,10 @@
 // zero), so no load sits behind a branch and the compiler issues all of a
 // point's loads together; x-neighbours hit in L1, y- and z-neighbours in
 // L1/L2 (the planes a workgroup reads are read again by the workgroups of the
-// next planes). Arithmetic and precision as in k_faber_term: the stencil
-// sums in SC (FP64, or the storage precision where that is enough), the
-// recurrence combination and the partial sum in FP64.
+// next planes). Arithmetic and precision as in k_faber_term: with SC = T the
+// difference sums use the integer weights in T and everything after them
+// (the weight factor, c^2, damping, recurrence and sum) is FP64
+// (apply_point_m); with SC = double the whole stencil is FP64.
 #pragma once
 
 #include "device_common.h"
@@ -79,8 +80,12 @@ __global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g,
 #pragma unroll
   for (int f = 0; f <= DIM; ++f) acc[f] = c.first ? 0.0 : acc_in[f * N + idx];
 
-  // H v at the point: derivatives in SC, the rest in FP64
-  const SC w0 = static_cast<SC>(g.wd[0]), w1 = static_cast<SC>(g.wd[1]);
+  // H v at the point: difference sums in SC (integer weights unless SC is
+  // FP64), the weight factor and the rest in FP64
+  constexpr bool kInt = !(sizeof(SC) == 8 && sizeof(T) == 4);
+  const SC w0 = kInt ? static_cast<SC>(g.wi[0]) : static_cast<SC>(g.wd[0]);
+  const SC w1 = kInt ? static_cast<SC>(g.wi[1]) : static_cast<SC>(g.wd[1]);
+  const double wsc = kInt ? g.wscale : 1.0;
   SC div = SC(0);
   double o[DIM + 1], s[DIM + 1];
   double sp = 0.0;
@@ -92,9 +97,9 @@ __global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g,
     div += dv;
     sp += static_cast<double>(g.sint[a][coord[a]]);
     s[1 + a] = static_cast<double>(vc[a]);
-    o[1 + a] = -static_cast<double>(dp) - static_cast<double>(g.shalf[a][coord[a]]) * s[1 + a];
+    o[1 + a] = -static_cast<double>(dp) * wsc - static_cast<double>(g.shalf[a][coord[a]]) * s[1 + a];
   }
-  o[0] = -static_cast<double>(c2) * static_cast<double>(div) - sp * s[0];
+  o[0] = -static_cast<double>(c2) * (static_cast<double>(div) * wsc) - sp * s[0];
   const double q = src.n > 0 ? src_value_d(src, idx) : 0.0;
 #pragma unroll
   for (int f = 0; f <= DIM; ++f) {
