@@ -203,6 +203,16 @@ int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
  * beyond rounding order. */
 int32_t expw_set_tuning(expw_op* op, int32_t fuse);
 
+/* Kernel of the fused Faber passes on 2D order-4 grids with zero ghosts:
+ *   EXPW_PASS_AUTO (default): streamed when the grid gives the chip at least
+ *     512 workgroups with row segments of 64 rows or more, else tiled;
+ *   EXPW_PASS_TILED: each workgroup recomputes the halo of a 2D tile;
+ *   EXPW_PASS_STREAMED: each workgroup walks a column band down the grid,
+ *     every term two rows behind the previous one (no recomputation in z).
+ * Results agree to rounding (the same polynomial on the same ellipse). */
+enum { EXPW_PASS_AUTO = 0, EXPW_PASS_TILED = 1, EXPW_PASS_STREAMED = 2 };
+int32_t expw_set_pass_kernel(expw_op* op, int32_t kind);
+
 /* y = H x (no source; Sec. 3, the semi-discrete operator with the staggered
  * differences of Sec. 2.1), x and y device state arrays in the state layout
  * (must not alias). */

@@ -22,6 +22,7 @@
 #include "pml.h"
 #include "profiler.h"
 #include "stream.h"
+#include "stream2d.h"
 #include "term_o4.h"
 
 struct expw_op {
@@ -61,6 +62,7 @@ struct expw_op {
   int guard;
   // tuning
   int fuse;
+  int pass_kernel;  // 2D order-4 fused passes: 0 by grid size, 1 tiled, 2 streamed
   // Krylov: small exponential on the device (0) or the host (1); last step info
   int kry_mode;
   int kry_persistent;  // 1: allow the persistent Arnoldi kernel
@@ -336,9 +338,33 @@ RecRun<T> rec_run(const expw_op* op, T* traces, int64_t step) {
 
 // The ellipse of a Faber step: the operator's, in FP64 for both storage
 // precisions (every term is computed in FP64).
+// For FP32 states the ellipse is moved (by a relative 1e-7 at most, well
+// inside the slack of the spectral bound) so that the kernels that compute a
+// term entirely in FP32 apply H / gamma exactly up to rounding: kappa =
+// wscale / gamma is rounded to FP32 and gamma taken back from it, and c0, c1
+// are rounded to FP32. The FP64 kernels run on the same (gamma, c0, c1), and
+// the coefficients and source scalars are computed in FP64 for it, so every
+// kernel of a step evaluates the same polynomial. FP64 states: the
+// operator's ellipse as it is.
 struct WorkEllipse {
   double gamma, c0, c1;
-  explicit WorkEllipse(const expw_op* op) : gamma(op->gamma), c0(op->c0), c1(op->c1) {}
+  double kappa;   // wscale / gamma (an FP32 value for FP32 states)
+  double inv_ws;  // 1 / wscale rounded like kappa (damping in units of the stencil factor)
+  explicit WorkEllipse(const expw_op* op) : gamma(op->gamma), c0(op->c0), c1(op->c1) {
+    double wi[4], beta = 0.0;
+    int kk = 0;
+    stagger_weights_int(op->g.order, wi, &beta, &kk);
+    const double ws = beta / op->g.h;
+    kappa = ws / gamma;
+    inv_ws = 1.0 / ws;
+    if (op->g.dtype == EXPW_F32) {
+      kappa = static_cast<double>(static_cast<float>(kappa));
+      gamma = ws / kappa;
+      c0 = static_cast<double>(static_cast<float>(c0));
+      c1 = static_cast<double>(static_cast<float>(c1));
+      inv_ws = static_cast<double>(static_cast<float>(inv_ws));
+    }
+  }
 };
 
 // Stencil arithmetic of the one-term order-4 kernel (see k_faber_term_o4):
@@ -467,7 +493,13 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
               // the last pass (no terms kept) writes the step's result
               const RecRun<T> rr = state_out ? rec_run(op, traces, st) : RecRun<T>{nullptr, 0, 0};
               recorded = recorded || rr.out != nullptr;
-              return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1, rr);
+              if constexpr (K == 2) {
+                if (op->pass_kernel == EXPW_PASS_STREAMED ||
+                    (op->pass_kernel == EXPW_PASS_AUTO && stream2d_fits(g.n[0], g.n[1], n)))
+                  return launch_stream_pass<T>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1, rr);
+                return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1, rr);
+              } else
+                return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1, rr);
             });
       } else if constexpr (K == 2 && BC == 0 && DIM == 3) {
         rc = faber_fused_passes<T>(op->stream, ns, S, b, m, 2, final_term,
@@ -1196,6 +1228,7 @@ int32_t expw_op_create_profiles(const expw_grid* g, const void* c2_dev,
   op->rec_run_first = -1;
   op->taylor_p = std::max(1, std::min(8, max_p));
   op->fuse = 0;
+  op->pass_kernel = EXPW_PASS_AUTO;
   op->kry_mode = EXPW_EXPM_DEVICE;
   op->kry_persistent = 1;
   op->coop_blocks = 0;
@@ -1298,6 +1331,14 @@ int32_t expw_set_tuning(expw_op* op, int32_t fuse) {
   if (int32_t rc = check_op(op)) return rc;
   if (fuse < 0 || fuse > kMaxFuse) return fail(EXPW_EINVAL, "fuse must be in [0, %d]", kMaxFuse);
   op->fuse = fuse;
+  return EXPW_OK;
+}
+
+int32_t expw_set_pass_kernel(expw_op* op, int32_t kind) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (kind < EXPW_PASS_AUTO || kind > EXPW_PASS_STREAMED)
+    return fail(EXPW_EINVAL, "pass kernel must be 0 (automatic), 1 (tiled) or 2 (streamed)");
+  op->pass_kernel = kind;
   return EXPW_OK;
 }
 

@@ -274,10 +274,10 @@ int fused_depth(int requested, int m, int64_t npts) {
   if (BC != 0) return 1;
   if (DIM == 3) return (K == 2 && sizeof(T) == 4 && requested >= 2 && m >= 2) ? 2 : 1;
   if (3 * npts >= (int64_t(1) << 31)) return 1;
-  const int smax = (K == 2 && sizeof(T) == 4) ? 8 : 4;
-  // default depth: 6 terms per pass at FP32 order 4 (fastest at 1001x501 and
-  // at 8192x4096 in depth sweeps), 4 at FP64 (its register limit), 3 at order 8
-  int s = requested == 0 ? (K == 2 ? (sizeof(T) == 4 ? 6 : 4) : 3) : requested;
+  // order 4: the row-streaming passes (stream2d.h), up to 6 terms at FP32 and
+  // 4 at FP64, default 4; order 8: the tiled passes, up to 4, default 3
+  const int smax = (K == 2 && sizeof(T) == 4) ? 6 : 4;
+  int s = requested == 0 ? (K == 2 ? 4 : 3) : requested;
   if (s > smax) s = smax;
   if (s > m) s = m;
   return s < 2 ? 1 : s;

@@ -74,6 +74,7 @@ SIGNATURES = {
     "expw_get_ellipse": (_i32, [_vp, _pd, _pd, _pd]),
     "expw_set_ellipse": (_i32, [_vp, _dbl, _dbl, _dbl]),
     "expw_set_tuning": (_i32, [_vp, _i32]),
+    "expw_set_pass_kernel": (_i32, [_vp, _i32]),
     "expw_apply": (_i32, [_vp, _vp, _vp]),
     "expw_apply_adjoint": (_i32, [_vp, _vp, _vp]),
     "expw_faber_adjoint_step": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
@@ -304,6 +305,13 @@ def expw_set_ellipse(op, gamma, c0, c1):
 
 def expw_set_tuning(op, fuse):
     _check(load().expw_set_tuning(op, fuse))
+
+
+EXPW_PASS_AUTO, EXPW_PASS_TILED, EXPW_PASS_STREAMED = 0, 1, 2
+
+
+def expw_set_pass_kernel(op, kind):
+    _check(load().expw_set_pass_kernel(op, int(kind)))
 
 
 def expw_apply(op, x_ptr, y_ptr):
@@ -549,6 +557,10 @@ class Operator:
     def set_tuning(self, fuse=0):
         expw_set_tuning(self.op, fuse)
         self.fuse = fuse
+
+    def set_pass_kernel(self, kind=EXPW_PASS_AUTO):
+        """Fused-pass kernel of 2D order-4 grids: auto, tiled or streamed."""
+        expw_set_pass_kernel(self.op, kind)
 
     def autotune_fuse(self, m, dt, candidates=None, steps=3, repeats=2):
         """Pick the Faber fusion depth (terms per sweep) that runs fastest

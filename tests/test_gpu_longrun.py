@@ -44,9 +44,10 @@ def _planes(w, p):
     return [f[nz // 2], f[:, ny // 2, :], f[:, :, nx // 2]]
 
 
-def _gpu_run(meta, dtype):
+def _gpu_run(meta, dtype, pass_kernel=0):
     """The GPU's snapshots of the stored run's configuration (numpy float64),
-    keyed like the stored ones."""
+    keyed like the stored ones; pass_kernel picks the fused-pass kernel of
+    2D Faber steps (0 automatic, 1 tiled, 2 streamed)."""
     import torch
     from paper_2401_16322_amd.expwave import Operator
     from synthetic import get_workload
@@ -56,6 +57,7 @@ def _gpu_run(meta, dtype):
                   sigma_max=w.sigma_max, max_krylov_k=meta["order"] if meta["method"] == "krylov" else 0,
                   max_taylor_p=meta["taylor_p"])
     op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, meta["taylor_p"])
+    op.set_pass_kernel(pass_kernel)
     U = torch.zeros((w.ndim + 1) * w.npts, dtype=tdt, device="cuda")
     dt, every = meta["dt"], meta["snapshot_every"]
     per = int(round(every / dt))
@@ -76,16 +78,17 @@ def _gpu_run(meta, dtype):
     return out
 
 
-def _check(name, dtype):
+def _check(name, dtype, pass_kernel=0):
     meta, ref = _load(name)
-    got = _gpu_run(meta, dtype)
+    got = _gpu_run(meta, dtype, pass_kernel)
     keys = sorted(ref, key=lambda s: (int(s[1:].split("_")[0]), s))
     norms = {k: float(np.linalg.norm(ref[k])) for k in keys}
     big = max(norms.values())
     errs = {}
     for k in keys:
         errs[k] = float(np.linalg.norm(got[k] - ref[k]) / norms[k]) if norms[k] > 0 else 0.0
-    print(f"{name} {dtype}: " + " ".join(f"{k}={e:.2e}" for k, e in errs.items()), flush=True)
+    print(f"{name} {dtype} pass kernel {pass_kernel}: " + " ".join(f"{k}={e:.2e}" for k, e in errs.items()),
+          flush=True)
     gated = [k for k in keys if norms[k] >= 1e-3 * big]
     assert gated, "no snapshot to gate"
     worst = max(errs[k] for k in gated)
@@ -94,22 +97,26 @@ def _check(name, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
-@pytest.mark.parametrize("name", ["box241_faber16_dt1", "box241_faber16_dt2", "box241_faber24_dt4",
-                                  "box241_krylov10_dt2.5"])
-def test_small_box_long_runs_match_stored_oracle(name, dtype):
+@pytest.mark.parametrize("name,pass_kernel", [
+    ("box241_faber16_dt1", 1), ("box241_faber16_dt1", 2), ("box241_faber16_dt2", 1),
+    ("box241_faber16_dt2", 2), ("box241_faber24_dt4", 1), ("box241_faber24_dt4", 2),
+    ("box241_krylov10_dt2.5", 0)])
+def test_small_box_long_runs_match_stored_oracle(name, pass_kernel, dtype):
     """241 x 161 layered box without a layer (its energy stays in the grid),
     T = 2 s: 2000 steps of Faber m = 16 at dt = 1 ms, 1000 at 2 ms, 500 of
-    m = 24 at 4 ms and 800 Krylov steps of k = 10 at 2.5 ms, snapshots every
-    0.25 s (0.2 s at 4 ms)."""
-    _check(name, dtype)
+    m = 24 at 4 ms (fused passes on the tiled and on the streamed kernel) and
+    800 Krylov steps of k = 10 at 2.5 ms, snapshots every 0.25 s (0.2 s at
+    4 ms)."""
+    _check(name, dtype, pass_kernel)
 
 
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
-def test_layered_1001x501_whole_run_matches_stored_oracle(dtype):
+@pytest.mark.parametrize("pass_kernel", [1, 2])
+def test_layered_1001x501_whole_run_matches_stored_oracle(dtype, pass_kernel):
     """The 1001 x 501 workload (40-cell layer, source and the bench's Faber
     configuration m = 16, dt = 2 ms) over T = 2 s: 1000 steps, snapshots of
-    the physical domain every 0.5 s."""
-    _check("layered1001_faber16_dt2", dtype)
+    the physical domain every 0.5 s, on both fused-pass kernels."""
+    _check("layered1001_faber16_dt2", dtype, pass_kernel)
 
 
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
