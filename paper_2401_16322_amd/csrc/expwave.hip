@@ -505,7 +505,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
         rc = faber_fused_passes<T>(op->stream, ns, S, b, m, 2, final_term,
             [&](int n, const T* vp, const T* vpp, const double* acc_in, T* ol, T* opv, double* acc_out, T* state_out, int j, bool first) {
               (void)n;
-              return launch_fused3d<T>(op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1);
+              return launch_fused3d<T>(op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1);
             });
       } else {
         rc = faber_unfused<T, K, BC, DIM>(op, g, el, S, b, a, q, m, term_out);

@@ -14,8 +14,9 @@
 // issued one iteration ahead. Per point and pass: reads u, v_{j-2}, the sum (4 words each)
 // and c^2, writes v_{j+1}, v_j and the sum: 25 words for two terms against 42
 // for two one-term sweeps (the sum in FP64: two words more each way). The
-// terms' difference sums are formed in T over integer weights and the rest
-// in FP64, and the terms are kept in T (see apply_point_m and FaberTerm).
+// terms are computed entirely in T with the integer weights and kappa =
+// wscale / gamma on an ellipse where kappa, c0 and c1 are exact in T (as in
+// the streamed 2D passes, stream2d.h); the partial sum is FP64.
 #pragma once
 
 #include "device_common.h"
@@ -30,7 +31,7 @@ constexpr int k3TX = k3X - 8, k3TY = k3Y - 8;        // output tile
 constexpr int k3ZC = 64;                             // output planes per workgroup
 
 struct Fused3Args {
-  double inv_gamma, c0, a_first;
+  double kappa, inv_ws, c0, a_first;
   int32_t first;  // first pass: acc = a_first u, no v_{j-2}
   int32_t tiles_x, tiles_y;
   double a[2], cpp[2], q[2];
@@ -77,9 +78,10 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
   const T sxh = inxy ? g.shalf[0][x] : T(0), syh = inxy ? g.shalf[1][y] : T(0);
   const int zc0 = zci * k3ZC;
   const int zc1 = min(zc0 + k3ZC, nz);
-  // difference sums with the integer weights in T, the rest in FP64 (see apply_point_m)
+  // every term in T (integer weights, kappa), the sum in FP64
   const T w0 = g.wi[0], w1 = g.wi[1];
-  const double ws = g.wscale;
+  const T kap = static_cast<T>(c.kappa), iws = static_cast<T>(c.inv_ws), cz = static_cast<T>(c.c0);
+  const T sxy_s = sxy_int * iws, sxh_s = sxh * iws, syh_s = syh * iws;
   constexpr int R = k3X;  // LDS row stride
 
   T qp[5], qvx[5], qvy[5], qvz[5];  // u at planes k-4..k (index 0 oldest)
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
       const T* VY = su[s0][2];
       const int l = tid;
 #define D_(x) static_cast<double>(x)
-      const double pc = D_(qp[2]), vxc = D_(qvx[2]), vyc = D_(qvy[2]), vzc = D_(qvz[2]);
+      const T pc = qp[2], vxc = qvx[2], vyc = qvy[2], vzc = qvz[2];
       const T dvx = w0 * (qvx[2] - VX[l - 1]) + w1 * (VX[l + 1] - VX[l - 2]);
       const T dvy = w0 * (qvy[2] - VY[l - R]) + w1 * (VY[l + R] - VY[l - 2 * R]);
       const T dvz = w0 * (qvz[2] - qvz[1]) + w1 * (qvz[3] - qvz[0]);
@@ -147,18 +149,18 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
       const T dpy = w0 * (P[l + R] - qp[2]) + w1 * (P[l + 2 * R] - P[l - R]);
       const T dpz = w0 * (qp[3] - qp[2]) + w1 * (qp[4] - qp[1]);
       const int64_t gi = col + static_cast<int64_t>(z0) * sxy;
-      const double hp = -D_(cu.c2a) * (D_(dvx + dvy + dvz) * ws) - (D_(sxy_int) + D_(g.sint[2][z0])) * pc;
-      const double hvx = -D_(dpx) * ws - D_(sxh) * vxc;
-      const double hvy = -D_(dpy) * ws - D_(syh) * vyc;
-      const double hvz = -D_(dpz) * ws - D_(g.shalf[2][z0]) * vzc;
-      const double self[4] = {pc, vxc, vyc, vzc};
-      const double h[4] = {hp, hvx, hvy, hvz};
-      double src0 = 0.0;
-      if (src.n > 0) src0 = c.q[0] * D_(source_amp(src, gi));
+      const T hp = -cu.c2a * (dvx + dvy + dvz) - (sxy_s + g.sint[2][z0] * iws) * pc;
+      const T hvx = -dpx - sxh_s * vxc;
+      const T hvy = -dpy - syh_s * vyc;
+      const T hvz = -dpz - g.shalf[2][z0] * iws * vzc;
+      const T self[4] = {pc, vxc, vyc, vzc};
+      const T h[4] = {hp, hvx, hvy, hvz};
+      const T cpp0 = static_cast<T>(c.cpp[0]);
+      T src0 = T(0);
+      if (src.n > 0) src0 = static_cast<T>(c.q[0]) * source_amp(src, gi);
 #pragma unroll
       for (int f = 0; f < 4; ++f)
-        a0[f] = static_cast<T>(h[f] * c.inv_gamma - c.c0 * self[f] - c.cpp[0] * D_(cu.w[f]) +
-                               (f == 0 ? src0 : 0.0));
+        a0[f] = kap * h[f] - cz * self[f] - cpp0 * cu.w[f] + (f == 0 ? src0 : T(0));
     }
     const int sz0 = (z0 + 6) % 3;
     sa[sz0][0][tid] = a0[0];
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
       const T* VX = sa[s1][1];
       const T* VY = sa[s1][2];
       const int l = tid;
-      const double pc = D_(ap[2]), vxc = D_(avx[0]), vyc = D_(avy[0]), vzc = D_(avz[2]);
+      const T pc = ap[2], vxc = avx[0], vyc = avy[0], vzc = avz[2];
       const T dvx = w0 * (avx[0] - VX[l - 1]) + w1 * (VX[l + 1] - VX[l - 2]);
       const T dvy = w0 * (avy[0] - VY[l - R]) + w1 * (VY[l + R] - VY[l - 2 * R]);
       const T dvz = w0 * (avz[2] - avz[1]) + w1 * (avz[3] - avz[0]);
@@ -185,25 +187,25 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
       const T dpy = w0 * (P[l + R] - ap[2]) + w1 * (P[l + 2 * R] - P[l - R]);
       const T dpz = w0 * (ap[3] - ap[2]) + w1 * (ap[4] - ap[1]);
       const int64_t gi = col + static_cast<int64_t>(z1) * sxy;
-      const double hp = -D_(cu.c2b) * (D_(dvx + dvy + dvz) * ws) - (D_(sxy_int) + D_(g.sint[2][z1])) * pc;
-      const double hvx = -D_(dpx) * ws - D_(sxh) * vxc;
-      const double hvy = -D_(dpy) * ws - D_(syh) * vyc;
-      const double hvz = -D_(dpz) * ws - D_(g.shalf[2][z1]) * vzc;
-      const double self[4] = {pc, vxc, vyc, vzc};
-      const double h[4] = {hp, hvx, hvy, hvz};
+      const T hp = -cu.c2b * (dvx + dvy + dvz) - (sxy_s + g.sint[2][z1] * iws) * pc;
+      const T hvx = -dpx - sxh_s * vxc;
+      const T hvy = -dpy - syh_s * vyc;
+      const T hvz = -dpz - g.shalf[2][z1] * iws * vzc;
+      const T self[4] = {pc, vxc, vyc, vzc};
+      const T h[4] = {hp, hvx, hvy, hvz};
       const T uz[4] = {qp[0], qvx[0], qvy[0], qvz[0]};
-      const double am = src.n > 0 ? D_(source_amp(src, gi)) : 0.0;
+      const T am = src.n > 0 ? source_amp(src, gi) : T(0);
+      const T cpp1 = static_cast<T>(c.cpp[1]);
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        double v = h[f] * c.inv_gamma - c.c0 * self[f] - c.cpp[1] * D_(uz[f]);
-        if (f == 0) v += c.q[1] * am;
-        const T vt = static_cast<T>(v);
+        T vt = kap * h[f] - cz * self[f] - cpp1 * uz[f];
+        if (f == 0) vt += static_cast<T>(c.q[1]) * am;
         double acc = c.first ? c.a_first * D_(uz[f]) : cu.acc[f];
-        acc = fma(c.a[0], self[f], acc);
+        acc = fma(c.a[0], D_(self[f]), acc);
         acc = fma(c.a[1], D_(vt), acc);
         if (out_last) {
           out_last[f * N + gi] = vt;
-          out_prev[f * N + gi] = static_cast<T>(self[f]);
+          out_prev[f * N + gi] = self[f];
         }
         if (state_out) state_out[f * N + gi] = static_cast<T>(acc);
         else acc_out[f * N + gi] = acc;
@@ -218,9 +220,10 @@ template <typename T>
 int32_t launch_fused3d(hipStream_t st, Profiler* prof, const Geo<T, 2, 3>& g, Src<T> src,
                        const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
                        double* acc_out, T* state_out, int j, bool first, const double* a,
-                       const double* q, double gamma, double c0, double c1) {
+                       const double* q, double kappa, double inv_ws, double c0, double c1) {
   Fused3Args c{};
-  c.inv_gamma = 1.0 / gamma;
+  c.kappa = kappa;
+  c.inv_ws = inv_ws;
   c.c0 = c0;
   c.first = first ? 1 : 0;
   if (first) c.a_first = a[0];
