@@ -196,11 +196,11 @@ int32_t expw_get_ellipse(const expw_op* op, double* gamma, double* c0, double* c
 int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
 
 /* Kernel tuning for the Faber step: fuse = recurrence terms per HBM sweep
- * (0 = automatic, 1 = one term per sweep, up to 8; 2D FP32 takes up to 8 and
- * 2D FP64 up to 4, automatic = 4; 3D FP32 takes 2 when asked for, automatic
- * = 1; 3D FP64 runs one term per sweep). Only order 4 with zero ghosts fuses.
- * The fused kernels' tiles follow the depth. Results do not depend on it
- * beyond rounding order. */
+ * (0 = automatic, 1 = one term per sweep, up to 8 accepted). 2D order 4:
+ * up to 6 terms at FP32 and 4 at FP64, automatic = 4; 2D order 8: up to 4,
+ * automatic = 3; 3D FP32 order 4: two terms unless fuse = 1; 3D FP64: one
+ * term per sweep. Only zero ghosts fuse. Results do not depend on it beyond
+ * rounding order. */
 int32_t expw_set_tuning(expw_op* op, int32_t fuse);
 
 /* Kernel of the fused Faber passes on 2D order-4 grids with zero ghosts:

@@ -264,15 +264,16 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
 }
 
 // Fusion depth actually used for a request (1 = unfused kernels): 2D order 4
-// with zero ghosts up to 8 (FP32) or 4 (FP64) terms, default 4; 2D order 8
+// with zero ghosts up to 6 (FP32) or 4 (FP64) terms, default 4; 2D order 8
 // with zero ghosts up to 4 terms, default 3; 3D FP32 order 4 with zero ghosts
-// 2 terms when asked for (fuse >= 2), one term by default (the one-term sweep
-// already runs at the streaming limit in 3D and the two-term pass gains
-// little; in FP64 it spills registers).
+// 2 terms unless fuse = 1 is asked for.
 template <typename T, int K, int BC, int DIM>
 int fused_depth(int requested, int m, int64_t npts) {
   if (BC != 0) return 1;
-  if (DIM == 3) return (K == 2 && sizeof(T) == 4 && requested >= 2 && m >= 2) ? 2 : 1;
+  // 3D FP32 order 4: passes of two terms by default (fused3d.h; 52 against 48
+  // G grid-pt matvecs/s for one term per sweep at 256^3), fuse = 1 forces one
+  // term per sweep; FP64 runs one term per sweep (the two-term pass spills)
+  if (DIM == 3) return (K == 2 && sizeof(T) == 4 && requested != 1 && m >= 2) ? 2 : 1;
   if (3 * npts >= (int64_t(1) << 31)) return 1;
   // order 4: the row-streaming passes (stream2d.h), up to 6 terms at FP32 and
   // 4 at FP64, default 4; order 8: the tiled passes, up to 4, default 3

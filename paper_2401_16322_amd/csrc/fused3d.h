@@ -107,13 +107,13 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
     const bool t0 = in_r0 && z0 >= 0 && z0 < nz && z0 >= zc0 - 2 && z0 <= zc1 + 1;
     const int64_t g0 = col + static_cast<int64_t>(t0 ? z0 : 0) * sxy;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) o.w[f] = (t0 && !c.first) ? vpp[f * N + g0] : T(0);
+    for (int f = 0; f < 4; ++f) o.w[f] = (t0 && !c.first) ? __builtin_nontemporal_load(vpp + f * N + g0) : T(0);
     o.c2a = t0 ? g.c2[g0] : T(0);
     const int z1 = k - 4;
     const bool t1 = in_tile && z1 >= zc0 && z1 < zc1;
     const int64_t g1 = col + static_cast<int64_t>(t1 ? z1 : 0) * sxy;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) o.acc[f] = (t1 && !c.first) ? acc_in[f * N + g1] : 0.0;
+    for (int f = 0; f < 4; ++f) o.acc[f] = (t1 && !c.first) ? __builtin_nontemporal_load(acc_in + f * N + g1) : 0.0;
     o.c2b = t1 ? g.c2[g1] : T(0);
   };
   Ahead nxt;
@@ -204,11 +204,11 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
         acc = fma(c.a[0], D_(self[f]), acc);
         acc = fma(c.a[1], D_(vt), acc);
         if (out_last) {
-          out_last[f * N + gi] = vt;
-          out_prev[f * N + gi] = self[f];
+          __builtin_nontemporal_store(vt, out_last + f * N + gi);
+          __builtin_nontemporal_store(self[f], out_prev + f * N + gi);
         }
-        if (state_out) state_out[f * N + gi] = static_cast<T>(acc);
-        else acc_out[f * N + gi] = acc;
+        if (state_out) __builtin_nontemporal_store(static_cast<T>(acc), state_out + f * N + gi);
+        else __builtin_nontemporal_store(acc, acc_out + f * N + gi);
       }
 #undef D_
     }

@@ -13,7 +13,11 @@
 // next planes). Arithmetic and precision as in k_faber_term: with SC = T the
 // difference sums use the integer weights in T and everything after them
 // (the weight factor, c^2, damping, recurrence and sum) is FP64
-// (apply_point_m); with SC = double the whole stencil is FP64.
+// (apply_point_m); with SC = double the whole stencil is FP64. The arrays
+// touched once per point (v_{j-2}, the sum, the outputs) are read and
+// written as streaming (non-temporal) accesses, so that v_{j-1}, whose
+// neighbour values are read again by other workgroups, and c^2 keep the
+// caches.
 #pragma once
 
 #include "device_common.h"
@@ -75,10 +79,10 @@ __global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g,
   const T c2 = g.c2[idx];
   T old[DIM + 1];
 #pragma unroll
-  for (int f = 0; f <= DIM; ++f) old[f] = vpp ? vpp[f * N + idx] : T(0);
+  for (int f = 0; f <= DIM; ++f) old[f] = vpp ? __builtin_nontemporal_load(vpp + f * N + idx) : T(0);
   double acc[DIM + 1];
 #pragma unroll
-  for (int f = 0; f <= DIM; ++f) acc[f] = c.first ? 0.0 : acc_in[f * N + idx];
+  for (int f = 0; f <= DIM; ++f) acc[f] = c.first ? 0.0 : __builtin_nontemporal_load(acc_in + f * N + idx);
 
   // H v at the point: difference sums in SC (integer weights unless SC is
   // FP64), the weight factor and the rest in FP64
@@ -108,12 +112,12 @@ __global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g,
     if (vpp) v -= c.cpp * static_cast<double>(old[f]);
     if (f == 0) v += q;
     const T vt = static_cast<T>(v);
-    if (vout) vout[e] = vt;
+    if (vout) __builtin_nontemporal_store(vt, vout + e);
     if (acc_out || state_out) {
       double a_ = c.first ? c.a_first * s[f] : acc[f];
       a_ = fma(c.a_j, static_cast<double>(vt), a_);
-      if (state_out) state_out[e] = static_cast<T>(a_);
-      else acc_out[e] = a_;
+      if (state_out) __builtin_nontemporal_store(static_cast<T>(a_), state_out + e);
+      else __builtin_nontemporal_store(a_, acc_out + e);
     }
   }
 }
