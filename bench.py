@@ -651,7 +651,7 @@ def time_to_solution(w, args):
 
 def cpu_baseline(w, methods, mvos, dts, args, c2_np, rec):
     """The FP64 oracle on the same step, single-threaded: --cpu-steps steps,
-    stopping after the first step that ends past about 30 s of CPU time."""
+    stopping after the first step that ends past 20 s of CPU time."""
     from threadpoolctl import threadpool_limits
     from oracle.operator import Grid
     from oracle.source import PointSources
@@ -671,7 +671,7 @@ def cpu_baseline(w, methods, mvos, dts, args, c2_np, rec):
                 if rec.size:
                     _ = states[m][rec]
             done += 1
-            if time.perf_counter() - t0 > 30.0:
+            if time.perf_counter() - t0 > 20.0:
                 break
         el = time.perf_counter() - t0
     total = w.npts * sum(mvos[m] for m in methods) * done

@@ -28,7 +28,7 @@ namespace expw {
 
 constexpr int k3X = 64, k3Y = 16, k3NT = k3X * k3Y;  // threads: columns of the loaded region
 constexpr int k3TX = k3X - 8, k3TY = k3Y - 8;        // output tile
-constexpr int k3ZC = 64;                             // output planes per workgroup
+constexpr int k3ZC = 32;                             // output planes per workgroup
 
 struct Fused3Args {
   double kappa, inv_ws, c0, a_first;
@@ -116,12 +116,15 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
     for (int f = 0; f < 4; ++f) o.acc[f] = (t1 && !c.first) ? __builtin_nontemporal_load(acc_in + f * N + g1) : 0.0;
     o.c2b = t1 ? g.c2[g1] : T(0);
   };
-  Ahead nxt;
+  // loads run two iterations ahead
+  Ahead nxt, nx2;
   load_ahead(zc0 - 4, nxt);
+  load_ahead(zc0 - 3, nx2);
   for (int k = zc0 - 4; k <= zc1 + 3; ++k) {
     const Ahead cu = nxt;
+    nxt = nx2;
     const T* cur = cu.u;
-    if (k < zc1 + 3) load_ahead(k + 1, nxt);
+    if (k + 1 < zc1 + 3) load_ahead(k + 2, nx2);
     shift_in(qp, 5, cur[0]);
     shift_in(qvx, 5, cur[1]);
     shift_in(qvy, 5, cur[2]);
