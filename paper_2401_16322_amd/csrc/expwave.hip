@@ -501,7 +501,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
               } else
                 return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1, rr);
             });
-      } else if constexpr (K == 2 && BC == 0 && DIM == 3) {
+      } else if constexpr (K == 2 && BC == 0 && DIM == 3 && sizeof(T) == 4) {
         rc = faber_fused_passes<T>(op->stream, ns, S, b, m, 2, final_term,
             [&](int n, const T* vp, const T* vpp, const double* acc_in, T* ol, T* opv, double* acc_out, T* state_out, int j, bool first) {
               (void)n;
