@@ -317,6 +317,25 @@ int32_t expw_apply_adjoint(expw_op* op, const void* x_dev, void* y_dev);
  * this is the exact transpose of that step's linear part. Uses the workspace. */
 int32_t expw_faber_adjoint_step(expw_op* op, const void* u_dev, void* lam_dev, double t, double dt,
                                 int32_t m, void* grad_c2_dev, void* terms_dev);
+/* Reverse of one Krylov step of dimension k from t (Sec. 3.2, Krylov
+ * subspace projection; its adjoint is not in the paper). The Krylov step's
+ * polynomial depends on its start vector, so the reverse step differentiates
+ * the exponential it approximates and approximates each factor in a Krylov
+ * space of dimension k: on return lam_dev holds the Krylov approximation of
+ * exp(dt H^T) lam (Arnoldi with modified Gram-Schmidt on H^T from lam, the
+ * forward step's breakdown rule), and grad_c2_dev (one value per point) is
+ * incremented by the c^2 derivative of <lam, exp(dt H~) [u; e_p]>,
+ *   dt int_0^1 <exp((1-s) dt H^T) lam, dH/dc^2[x] exp(s dt H~) [u; e_p]> ds,
+ * with both exponentials taken in their Krylov spaces (the forward one is the
+ * basis of the step from u_dev at t, with its source); the time integral is
+ * the upper right block of one block-triangular exponential (Van Loan). Both
+ * results converge to the exact exponential's derivatives as k grows.
+ * k in [1, max_krylov_k at create] (the forward basis uses the workspace);
+ * basis_dev: caller scratch of (k + 1) state vectors for the basis of H^T.
+ * lam_dev, grad_c2_dev and basis_dev must not alias each other or u_dev.
+ * Synchronizes the op's stream (two small host exponentials). */
+int32_t expw_krylov_adjoint_step(expw_op* op, const void* u_dev, void* lam_dev, double t, double dt,
+                                 int32_t k, void* grad_c2_dev, void* basis_dev);
 /* state_dev pressure at the receivers += scale * values_dev[r] (adjoint
  * sources; device atomics, so repeated receivers add up). */
 int32_t expw_inject_receivers(expw_op* op, const void* values_dev, double scale, void* state_dev);

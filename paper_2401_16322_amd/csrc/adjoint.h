@@ -13,6 +13,7 @@
 #pragma once
 
 #include "device_common.h"
+#include "expwave.h"
 #include "kernels.h"
 
 namespace expw {
@@ -167,6 +168,80 @@ __global__ __launch_bounds__(kBlock) void k_faber_adjoint_term(Geo<T, K, DIM> g,
   if (grad)
     grad[idx] = static_cast<T>(static_cast<double>(grad[idx]) -
                                c.inv_gamma * mp * velocity_divergence_d<T, K, BC, DIM>(g, vprev, idx, ic));
+}
+
+// Krylov adjoint (Sec. 3.2, Krylov subspace projection, differentiated): the
+// state adjoint is the Krylov approximation of exp(dt H^T) lam (Arnoldi on
+// H^T from lam, no augmentation), and the c^2 derivative of
+// <lam, exp(dt H~) [u; e_p]> is
+//   dt int_0^1 <exp((1-s) dt H^T) lam, dH/dc^2[x] exp(s dt H~) [u; e_p]> ds
+//   = -dt sum_{a,b} C_ab W_{a,p}[x] (sum_d D-_d V_{b,v_d})[x]
+// with V, W the two bases and C = beta beta' int_0^1 exp((1-s) dt G_k) e_1
+// e_1^T exp(s dt H_k^T) ds (formed on the host from one block exponential).
+
+// Column j of the Arnoldi process on H^T: w = s_j H^T Q_j (s_j from the norm
+// partials pin of the previous column, or 1 for j = 0 when pin == nullptr),
+// in FP64 from the stored values; stores the partials of w . q_0.
+template <typename T, int K, int BC, int DIM>
+__global__ __launch_bounds__(kBlock) void k_kry_matvec_adj(Geo<T, K, DIM> g, const T* __restrict__ q,
+                                                           T* __restrict__ w, const T* __restrict__ q0,
+                                                           const double* pin, int nin, double tol,
+                                                           const double* beta, double* h_store,
+                                                           double* sc_store, double* __restrict__ pout) {
+  const double sj = pin ? column_scale(pin, nin, tol, beta, h_store, sc_store) : 1.0;
+  double acc = 0.0;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; idx < g.N;
+       idx += static_cast<int64_t>(gridDim.x) * kBlock) {
+    int64_t ic[3];
+    decompose<DIM>(g.n, idx, ic);
+    double o[DIM + 1], s[DIM + 1];
+    apply_point_adjoint_d<T, K, BC, DIM>(g, q, idx, ic, o, s);
+#pragma unroll
+    for (int f = 0; f <= DIM; ++f) {
+      const int64_t e = f * g.N + idx;
+      const T v = static_cast<T>(o[f] * sj);
+      w[e] = v;
+      acc += static_cast<double>(v) * static_cast<double>(q0[e]);
+    }
+  }
+  store_partial<false>(acc, pout);
+}
+
+// grad[x] += scale * sum_{a < kw} W_a,p[x] sum_{b < kv} M[a kv + b]
+// (sum_d D-_d V_b,v_d)[x] for the unnormalized basis columns V_b (leading
+// dimension ldv) and W_a (ldw); M (kw x kv, row-major, FP64) carries the
+// column scales. The divergences are formed eight columns at a time.
+template <typename T, int K, int BC, int DIM>
+__global__ __launch_bounds__(kBlock) void k_kry_grad(Geo<T, K, DIM> g, const T* __restrict__ V,
+                                                     int64_t ldv, int32_t kv, const T* __restrict__ W,
+                                                     int64_t ldw, int32_t kw,
+                                                     const double* __restrict__ M, double scale,
+                                                     T* __restrict__ grad) {
+  __shared__ double sm[EXPW_MAX_KRYLOV * EXPW_MAX_KRYLOV];
+  for (int i = threadIdx.x; i < kw * kv; i += kBlock) sm[i] = M[i];
+  __syncthreads();
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  if (idx >= g.N) return;
+  int64_t ic[3];
+  decompose<DIM>(g.n, idx, ic);
+  constexpr int CB = 8;
+  double acc = 0.0;
+  for (int b0 = 0; b0 < kv; b0 += CB) {
+    double d[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      d[u] = (b0 + u < kv) ? velocity_divergence_d<T, K, BC, DIM>(g, V + (b0 + u) * ldv, idx, ic) : 0.0;
+    const int nb = min(CB, kv - b0);
+    for (int a = 0; a < kw; ++a) {
+      const double* row = sm + a * kv + b0;
+      double t = 0.0;
+#pragma unroll
+      for (int u = 0; u < CB; ++u)
+        if (u < nb) t += row[u] * d[u];
+      acc += static_cast<double>(W[a * ldw + idx]) * t;
+    }
+  }
+  grad[idx] = static_cast<T>(static_cast<double>(grad[idx]) + scale * acc);
 }
 
 // state_p[rec[r]] += scale * vals[r] (adjoint sources at the receivers;

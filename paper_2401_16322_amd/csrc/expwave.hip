@@ -667,6 +667,52 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   return EXPW_OK;
 }
 
+// The Arnoldi process by launches: q_0 = x / beta, then per column j one
+// matvec launch (fused with the first dot) and j + 1 fused MGS launches, and
+// the norm of the last column. Forward (ADJ = false): H~ on x = [S; e_p]
+// (naug entries, the source tail when ks.p > 0); ADJ: H^T on x = S (naug =
+// ns). Writes Q_0..Q_k (leading dimension ld), the Hessenberg entries into
+// hess (leading dimension kHessLd), beta into *beta_out and the column scales
+// into sc.
+template <typename T, int K, int BC, int DIM, bool ADJ>
+int32_t arnoldi_launches(expw_op* op, const Geo<T, K, DIM>& g, const T* S, T* Q, int64_t ld, int64_t ns,
+                         int64_t naug, const KrySrc& ks, const T* amp, int k, double tol, double* part,
+                         double* hess, double* beta_out, double* sc) {
+  const double es = sizeof(T);
+  const unsigned rg_vec = red_grid_for(naug);
+  const unsigned rg_pts = red_grid_for(ADJ ? g.N : g.N + ks.p);
+  const double tail2 = (!ADJ && ks.p > 0) ? 1.0 : 0.0;
+  double* P[2] = {part, part + kRedMaxBlocks};
+  const unsigned nb_ns = red_grid_for(ns);
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, ns * es, k_norm2<T>, dim3(nb_ns), dim3(kBlock), S, ns, P[0]);
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (ns + naug) * es, k_kry_init<T>, dim3(rg_vec), dim3(kBlock), S, ns, Q, naug, P[0], nb_ns, tail2, beta_out, sc);
+  // P[c] holds the partials of the latest reduction, produced by nin blocks
+  int c = 0, nin = 0;
+  for (int j = 0; j < k; ++j) {
+    T* w = Q + (j + 1) * ld;
+    const double* pin = j == 0 ? nullptr : P[c];
+    double* hst = j == 0 ? nullptr : hess + j * kHessLd + (j - 1);
+    if constexpr (ADJ) {
+      // reads Q_j (with the stencil), q_0 and c^2, writes w
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * ns + g.N) * es, k_kry_matvec_adj<T, K, BC, DIM>, dim3(rg_pts), dim3(kBlock), g, Q + j * ld, w, Q, pin, nin, tol, beta_out, hst, sc + j, P[c ^ 1]);
+    } else {
+      // reads Q_j (with tail), q_1 and c^2, writes w
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * naug + g.N) * es, k_kry_matvec<T, K, BC, DIM>, dim3(rg_pts), dim3(kBlock), g, Q + j * ld, w, Q, ks, amp, pin, nin, tol, beta_out, hst, sc + j, P[c ^ 1]);
+    }
+    c ^= 1;
+    nin = static_cast<int>(rg_pts);
+    for (int i = 0; i <= j; ++i) {
+      const bool lastc = (i == j);
+      // reads w, Q_i [, Q_{i+1}], writes w
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MGS, (lastc ? 3.0 : 4.0) * naug * es, k_kry_mgs<T>, dim3(rg_vec), dim3(kBlock), w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld, naug, P[c], nin, hess + i * kHessLd + j, sc, i, P[c ^ 1]);
+      c ^= 1;
+      nin = static_cast<int>(rg_vec);
+    }
+  }
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, k_kry_finish, dim3(1), dim3(kBlock), P[c], nin, tol, beta_out, hess + k * kHessLd + (k - 1), sc + k);
+  return check_launch(ADJ ? "adjoint arnoldi" : "arnoldi");
+}
+
 template <typename T, int K, int BC, int DIM>
 int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nsteps, T* traces) {
   const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
@@ -679,8 +725,6 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
   double* scal = reinterpret_cast<double*>(op->ws + op->off_scal);
   double* hess = reinterpret_cast<double*>(op->ws + op->off_hess);
   const T* amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
-  const unsigned rg_vec = red_grid_for(naug);
-  const unsigned rg_pts = red_grid_for(g.N + p);
   const double es = sizeof(T);
   double* kry_y = reinterpret_cast<double*>(op->ws + op->off_kry);
   double* kry_sc = kry_y + 64;
@@ -711,28 +755,8 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
                                                      hess, kry_sc, scal + 1);
       if (rc != EXPW_OK) return rc;
     } else {
-      // q_1 = [S; e_p] / beta
-      double* P[2] = {part, part + kRedMaxBlocks};
-      const unsigned nb_ns = red_grid_for(ns);
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, ns * es, k_norm2<T>, dim3(nb_ns), dim3(kBlock), S, ns, P[0]);
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (ns + naug) * es, k_kry_init<T>, dim3(red_grid_for(naug)), dim3(kBlock), S, ns, Q, naug, P[0], nb_ns, p > 0 ? 1.0 : 0.0, scal + 1, kry_sc);
-      // P[c] holds the partials of the latest reduction, produced by nin blocks
-      int c = 0, nin = 0;
-      for (int j = 0; j < k; ++j) {
-        T* w = Q + (j + 1) * ld;
-        // reads Q_j (with tail), q_1 and c^2, writes w
-        launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * naug + g.N) * es, k_kry_matvec<T, K, BC, DIM>, dim3(rg_pts), dim3(kBlock), g, Q + j * ld, w, Q, ks, amp, j == 0 ? nullptr : P[c], nin, tol, scal + 1, j == 0 ? nullptr : hess + j * kHessLd + (j - 1), kry_sc + j, P[c ^ 1]);
-        c ^= 1;
-        nin = static_cast<int>(rg_pts);
-        for (int i = 0; i <= j; ++i) {
-          const bool lastc = (i == j);
-          // reads w, Q_i [, Q_{i+1}], writes w
-          launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MGS, (lastc ? 3.0 : 4.0) * naug * es, k_kry_mgs<T>, dim3(rg_vec), dim3(kBlock), w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld, naug, P[c], nin, hess + i * kHessLd + j, kry_sc, i, P[c ^ 1]);
-          c ^= 1;
-          nin = static_cast<int>(rg_vec);
-        }
-      }
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, k_kry_finish, dim3(1), dim3(kBlock), P[c], nin, tol, scal + 1, hess + k * kHessLd + (k - 1), kry_sc + k);
+      int32_t rc = arnoldi_launches<T, K, BC, DIM, false>(op, g, S, Q, ld, ns, naug, ks, amp, k, tol, part, hess, scal + 1, kry_sc);
+      if (rc != EXPW_OK) return rc;
     }
     int32_t rc = check_launch("arnoldi");
     if (rc != EXPW_OK) return rc;
@@ -852,6 +876,107 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
                  j > 0 ? grad : nullptr, c);
     if (int32_t rc = check_launch("adjoint term")) return rc;
   }
+  return EXPW_OK;
+}
+
+// Reverse of one Krylov step of dimension k from t (see adjoint.h): the
+// forward basis V of the step (the op's Krylov workspace) and the basis W of
+// H^T from lam (caller scratch Wb of k + 1 state vectors); on the host, one
+// exponential of the block triangular matrix [[dt G_k, e_1 e_1^T], [0, dt
+// H_k^T]] gives exp(dt G_k) e_1 (its first column, upper left block) and the
+// coupling C (upper right block); then lam = beta' W exp(dt G_k) e_1 and the
+// gradient kernel.
+template <typename T, int K, int BC, int DIM>
+int32_t krylov_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt, int k, T* grad, T* Wb) {
+  const Geo<T, K, DIM> g = make_geo<T, K, DIM>(op);
+  const int64_t ns = (DIM + 1) * g.N;
+  const int p = op->n_src > 0 ? op->taylor_p : 0;
+  const int64_t naug = ns + p;
+  const int64_t ld = op->naug_pad;
+  T* Q = reinterpret_cast<T*>(op->ws + op->off_big);
+  double* part = reinterpret_cast<double*>(op->ws + op->off_part);
+  double* scal = reinterpret_cast<double*>(op->ws + op->off_scal);
+  double* hess = reinterpret_cast<double*>(op->ws + op->off_hess);
+  const T* amp = reinterpret_cast<const T*>(op->ws + op->off_src_amp);
+  double* kry_sc = reinterpret_cast<double*>(op->ws + op->off_kry) + 64;
+  const double tol = 1e-14;
+  KrySrc ks{};
+  ks.n = op->n_src;
+  ks.p = p;
+  ks.lo = op->src_lo;
+  ks.hi = op->src_hi;
+  ks.idx = reinterpret_cast<const int64_t*>(op->ws + op->off_src_idx);
+  if (p > 0) {
+    std::vector<double> der(EXPW_MAX_TAYLOR);
+    source_derivs(op, 0, t, p, der.data());  // a table's row 0: one step per call
+    const double sc = src_scale(op);
+    for (int c = 0; c < p; ++c) ks.G[c] = der[p - 1 - c] * sc;
+  }
+  struct Basis {
+    std::vector<double> h, s;
+    double beta = 0.0;
+    int keff = 0;
+  };
+  auto fetch = [&](Basis& b) -> int32_t {
+    b.h.resize((EXPW_MAX_KRYLOV + 1) * kHessLd);
+    b.s.resize(k + 1);
+    if (hipMemcpyAsync(b.h.data(), hess, b.h.size() * sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+        hipMemcpyAsync(b.s.data(), kry_sc, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+        hipMemcpyAsync(&b.beta, scal + 1, sizeof(double), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+        hipStreamSynchronize(op->stream) != hipSuccess)
+      return fail(EXPW_EDEVICE, "krylov adjoint: device to host copy failed: %s", hipGetErrorString(hipGetLastError()));
+    // the breakdown rule of the forward step
+    b.keff = b.beta == 0.0 ? 0 : k;
+    for (int j = 0; b.keff > 0 && j + 1 < k; ++j)
+      if (!(b.h[(j + 1) * kHessLd + j] > tol * b.beta)) {
+        b.keff = j + 1;
+        break;
+      }
+    return EXPW_OK;
+  };
+  Basis bv, bw;
+  int32_t rc = arnoldi_launches<T, K, BC, DIM, false>(op, g, U, Q, ld, ns, naug, ks, amp, k, tol, part, hess, scal + 1, kry_sc);
+  if (rc == EXPW_OK) rc = fetch(bv);
+  if (rc == EXPW_OK) rc = arnoldi_launches<T, K, BC, DIM, true>(op, g, lam, Wb, ns, ns, ns, ks, amp, k, tol, part, hess, scal + 1, kry_sc);
+  if (rc == EXPW_OK) rc = fetch(bw);
+  if (rc != EXPW_OK) return rc;
+  const int kv = bv.keff, kw = bw.keff;
+  if (kw == 0) return EXPW_OK;  // lam = 0 stays 0 and adds nothing
+  const int n = kw + kv;
+  std::vector<double> Z(static_cast<size_t>(n) * n, 0.0), E(static_cast<size_t>(n) * n);
+  for (int r = 0; r < kw; ++r)
+    for (int c = 0; c < kw; ++c) Z[r * n + c] = (r <= c + 1) ? dt * bw.h[r * kHessLd + c] : 0.0;
+  if (kv > 0) {
+    Z[0 * n + kw] = 1.0;
+    for (int r = 0; r < kv; ++r)
+      for (int c = 0; c < kv; ++c) Z[(kw + r) * n + kw + c] = (c <= r + 1) ? dt * bv.h[c * kHessLd + r] : 0.0;
+  }
+  if (!expm(n, Z.data(), E.data())) return fail(EXPW_ENONFINITE, "krylov adjoint: non-finite Hessenberg matrix");
+  const double es = sizeof(T);
+  if (kv > 0) {
+    // M_ab = beta beta' C_ab s^W_a s^V_b for the unnormalized columns
+    std::vector<double> M(static_cast<size_t>(kw) * kv);
+    for (int a = 0; a < kw; ++a)
+      for (int b = 0; b < kv; ++b)
+        M[a * kv + b] = bv.beta * bw.beta * E[a * n + kw + b] * bw.s[a] * bv.s[b];
+    if (hipMemcpyAsync(hess, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, op->stream) != hipSuccess)
+      return fail(EXPW_EDEVICE, "krylov adjoint: host to device copy failed");
+    // reads kv velocity columns (with the stencil), kw pressure columns, grad RMW
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (kv * DIM + kw + 2.0) * g.N * es,
+                 k_kry_grad<T, K, BC, DIM>, dim3(grid_for(g.N)), dim3(kBlock), g, static_cast<const T*>(Q), ld, kv,
+                 static_cast<const T*>(Wb), ns, kw, static_cast<const double*>(hess), -dt, grad);
+    if ((rc = check_launch("krylov adjoint gradient")) != EXPW_OK) return rc;
+  }
+  KryCoef y{};
+  for (int a = 0; a < kw; ++a) y.y[a] = E[a * n + 0];
+  // kry_sc holds the scales of W (the last Arnoldi process)
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (kw + 1.0) * ns * es, k_kry_combine<T>,
+               dim3(red_grid_for(ns)), dim3(kBlock), lam, static_cast<const T*>(Wb), ns, ns, kw, y, bw.beta,
+               static_cast<const double*>(kry_sc));
+  if ((rc = check_launch("krylov adjoint combine")) != EXPW_OK) return rc;
+  // M lives in host memory until the copy has run
+  if (hipStreamSynchronize(op->stream) != hipSuccess)
+    return fail(EXPW_EDEVICE, "krylov adjoint: %s", hipGetErrorString(hipGetLastError()));
   return EXPW_OK;
 }
 
@@ -1375,6 +1500,20 @@ int32_t expw_faber_adjoint_step(expw_op* op, const void* u, void* lam, double t,
     using C = decltype(cfg);
     using T = typename C::type;
     return faber_adjoint_impl<T, C::k, C::bc, C::dim>(op, static_cast<const T*>(u), static_cast<T*>(lam), t, dt, m, static_cast<T*>(grad), static_cast<T*>(terms));
+  });
+}
+
+int32_t expw_krylov_adjoint_step(expw_op* op, const void* u, void* lam, double t, double dt,
+                                 int32_t k, void* grad, void* basis) {
+  if (int32_t rc = check_step_args(op, u, dt, 1)) return rc;
+  if (k < 1 || k > op->kmax) return fail(EXPW_EINVAL, "Krylov dimension k must be in [1, %d] (max_krylov_k at create)", op->kmax);
+  if (!lam || !grad || !basis) return fail(EXPW_EINVAL, "NULL lam, grad or basis");
+  if (lam == u || lam == grad || basis == u || basis == lam || basis == grad)
+    return fail(EXPW_EINVAL, "lam, grad and basis must not alias each other or u");
+  return dispatch(op, [&](auto cfg) {
+    using C = decltype(cfg);
+    using T = typename C::type;
+    return krylov_adjoint_impl<T, C::k, C::bc, C::dim>(op, static_cast<const T*>(u), static_cast<T*>(lam), t, dt, k, static_cast<T*>(grad), static_cast<T*>(basis));
   });
 }
 

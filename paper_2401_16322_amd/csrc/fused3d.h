@@ -60,7 +60,7 @@ __global__ __launch_bounds__(k3NT) void k_faber_fused3d(
     double* __restrict__ acc_out, T* __restrict__ state_out, Fused3Args c, Src<T> src) {
   __shared__ T su[3][3][k3NT];  // u planes: ring slot, field (p, v_x, v_y), column
   __shared__ T sa[3][3][k3NT];  // a planes
-  const int b = blockIdx.x;
+  const int b = xcd_contiguous(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   const int txi = b % c.tiles_x;
   const int rr = b / c.tiles_x;
   const int tyi = rr % c.tiles_y;

@@ -78,6 +78,7 @@ SIGNATURES = {
     "expw_apply": (_i32, [_vp, _vp, _vp]),
     "expw_apply_adjoint": (_i32, [_vp, _vp, _vp]),
     "expw_faber_adjoint_step": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
+    "expw_krylov_adjoint_step": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
     "expw_inject_receivers": (_i32, [_vp, _vp, _dbl, _vp]),
     "expw_set_source_ricker": (_i32, [_vp, _i32, _pi64, _pd, _dbl, _dbl, _i32]),
     "expw_set_source_taylor": (_i32, [_vp, _i32, _pi64, _pd, _i32, _i64, _pd]),
@@ -324,6 +325,10 @@ def expw_apply_adjoint(op, x_ptr, y_ptr):
 
 def expw_faber_adjoint_step(op, u_ptr, lam_ptr, t, dt, m, grad_ptr, terms_ptr):
     _check(load().expw_faber_adjoint_step(op, u_ptr, lam_ptr, t, dt, m, grad_ptr, terms_ptr))
+
+
+def expw_krylov_adjoint_step(op, u_ptr, lam_ptr, t, dt, k, grad_ptr, basis_ptr):
+    _check(load().expw_krylov_adjoint_step(op, u_ptr, lam_ptr, t, dt, k, grad_ptr, basis_ptr))
 
 
 def expw_inject_receivers(op, values_ptr, scale, state_ptr):
@@ -622,6 +627,25 @@ class Operator:
         self._sync_stream()
         expw_faber_adjoint_step(self.op, u.data_ptr(), lam.data_ptr(), t, dt, m, grad.data_ptr(),
                                 terms.data_ptr() if m > 1 else None)
+        return lam
+
+    def krylov_adjoint_step(self, u, lam, t, dt, k, grad, basis=None):
+        """lam <- the Krylov approximation (dimension k) of exp(dt H^T) lam in
+        place; grad (one value per point) += the c^2 derivative of
+        <lam, exp(dt H~) [u; e_p]> with both exponentials in their Krylov
+        spaces (the forward one that of the step from u at t). basis: scratch
+        of (k + 1) * nstate values (allocated when None)."""
+        self._check_state(u)
+        self._check_state(lam)
+        if grad.dtype != self.dtype or grad.numel() != self.npts or not grad.is_contiguous():
+            raise ValueError("grad must hold one value per grid point of the grid dtype")
+        if basis is None:
+            basis = self._torch.empty((k + 1) * self.nstate, dtype=self.dtype, device=u.device)
+        if basis.dtype != self.dtype or basis.numel() < (k + 1) * self.nstate or not basis.is_contiguous():
+            raise ValueError("basis must hold (k + 1) * nstate values")
+        self._sync_stream()
+        expw_krylov_adjoint_step(self.op, u.data_ptr(), lam.data_ptr(), t, dt, k, grad.data_ptr(),
+                                 basis.data_ptr())
         return lam
 
     def inject_receivers(self, values, state, scale=1.0):

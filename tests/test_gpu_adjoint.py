@@ -1,10 +1,12 @@
-"""GPU parity of the adjoint path (H^T, the reverse Faber step, the
-checkpointed misfit gradient and the autograd wrapper) against the oracle."""
+"""GPU parity of the adjoint path (H^T, the reverse Faber and Krylov steps,
+the checkpointed misfit gradient and the autograd wrapper) against the
+oracle."""
 import numpy as np
 import pytest
 
 from gpu_cases import TOL, make_case, rel_l2, to_dev
-from oracle.adjoint import apply_HT, faber_adjoint_step, misfit_gradient
+from oracle.adjoint import (apply_HT, faber_adjoint_step, krylov_adjoint_step, krylov_misfit_gradient,
+                            misfit_gradient)
 
 DTYPES = ["float64", "float32"]
 pytestmark = pytest.mark.gpu
@@ -35,8 +37,10 @@ def test_faber_adjoint_step_matches_oracle(dtype, m):
     case.op.faber_adjoint_step(to_dev(case, u), lam, 0.05, 2e-3, m, grad)
     mu0, gref = faber_adjoint_step(case.prob, u, lam0, 0.05, 2e-3, m, p=case.p, ellipse=ell)
     tol = TOL[dtype]
-    assert rel_l2(lam.cpu().numpy(), mu0) <= tol
-    assert rel_l2(grad.cpu().numpy(), gref) <= tol * (1 if dtype == "float64" else 5)
+    el, eg = rel_l2(lam.cpu().numpy(), mu0), rel_l2(grad.cpu().numpy(), gref)
+    print(f"faber adjoint {dtype} m={m}: lam {el:.2e} grad {eg:.2e}")
+    assert el <= tol
+    assert eg <= tol
 
 
 def test_adjoint_step_dot_product_on_gpu():
@@ -73,10 +77,12 @@ def test_checkpointed_misfit_gradient_matches_oracle(dtype):
     L, grad, lam, traces = gpu_misfit_gradient(case.op, to_dev(case, U0), t0, dt, nst, m,
                                                torch.tensor(d_obs), checkpoint_every=5)
     Lr, gr, lr = misfit_gradient(case.prob, U0, t0, dt, nst, m, rec, d_obs, p=case.p, ellipse=ell)
-    tol = 1e-10 if dtype == "float64" else 5e-5
+    tol = TOL[dtype]
+    eg, el = rel_l2(grad.cpu().numpy(), gr), rel_l2(lam.cpu().numpy(), lr)
+    print(f"faber misfit {dtype}: L {abs(L / Lr - 1):.2e} grad {eg:.2e} lam {el:.2e}")
     assert L == pytest.approx(Lr, rel=tol)
-    assert rel_l2(grad.cpu().numpy(), gr) <= tol
-    assert rel_l2(lam.cpu().numpy(), lr) <= tol
+    assert eg <= tol
+    assert el <= tol
 
 
 def test_autograd_wrapper_gradients():
@@ -114,3 +120,91 @@ def test_inject_receivers_adds_at_receivers():
     out = s.cpu().numpy()
     assert out[3] == 0.5 and out[50] == 2.5 and out[199] == 2.0
     assert np.count_nonzero(out) == 3
+
+
+def _balanced_lam(case, seed):
+    """A smooth adjoint state whose velocity part is scaled by c (the scaling
+    under which H^T is balanced: (H^T y)_v ~ c^2 y_p / h, (H^T y)_p ~ y_v / h)."""
+    from synthetic import smooth_state
+    g = case.prob.grid
+    lam = smooth_state(g.n, seed=seed, width_cells=max(1.0, min(g.n) / 6))
+    c = np.sqrt(case.prob.c2.ravel())
+    for a in range(g.ndim):
+        lam[(1 + a) * g.npts:(2 + a) * g.npts] *= c
+    return lam
+
+
+@pytest.mark.parametrize("dtype,n,order,bc,k", [
+    (d, *c) for d in DTYPES for c in [((70, 45), 4, "zero", 1), ((70, 45), 4, "zero", 4),
+                                      ((70, 45), 4, "zero", 12), ((13, 11, 9), 4, "zero", 8),
+                                      ((33, 20), 8, "zero", 8)]] + [("float64", (24, 16), 4, "periodic", 8)])
+def test_krylov_adjoint_step_matches_oracle(dtype, n, order, bc, k):
+    """Single reverse steps on damped grids with a balanced adjoint state, and
+    one undamped periodic grid in FP64 only: without damping, H^T is far from
+    normal in the Euclidean inner product (h_jj reaches +-8e5 and h_{j+1,j}
+    alternates between ~1e6 and ~0.2), so modified Gram-Schmidt loses
+    orthogonality (|q_i . q_j| ~ 1e-2 by k = 8 when the basis is stored in
+    FP32, the same in the forward step), and FP32 results then differ from
+    the FP64 oracle by ~1e-3; in FP64 they agree to ~2e-11 (held to 1e-10)."""
+    import torch
+    src = bc == "zero"
+    case = make_case(n, dtype, order=order, bc=bc, seed=37, n_src=2, src=src, max_k=k)
+    g = case.prob.grid
+    lam0 = _balanced_lam(case, 7)
+    u = case.U0
+    lam = to_dev(case, lam0)
+    grad = torch.zeros(g.npts, dtype=case.torch_dtype, device="cuda")
+    case.op.krylov_adjoint_step(to_dev(case, u), lam, 0.05, 2e-3, k, grad)
+    lref, gref = krylov_adjoint_step(case.prob, u, lam0, 0.05, 2e-3, k, p=case.p)
+    el, eg = rel_l2(lam.cpu().numpy(), lref), rel_l2(grad.cpu().numpy(), gref)
+    print(f"krylov adjoint {dtype} {n} order {order} {bc} k={k}: lam {el:.2e} grad {eg:.2e}")
+    tol = 1e-10 if bc == "periodic" else TOL[dtype]
+    assert el <= tol
+    assert eg <= tol
+
+
+def test_krylov_adjoint_step_degenerate_inputs():
+    """lam = 0 gives lam' = 0 and no gradient; u = 0 without a source gives
+    no gradient and lam' = the Krylov exponential of H^T (FP64)."""
+    import torch
+    case = make_case((30, 20), "float64", seed=38, src=False, max_k=6)
+    g = case.prob.grid
+    grad = torch.zeros(g.npts, dtype=torch.float64, device="cuda")
+    lam = torch.zeros(g.nstate, dtype=torch.float64, device="cuda")
+    case.op.krylov_adjoint_step(to_dev(case, case.U0), lam, 0.0, 2e-3, 6, grad)
+    assert float(lam.abs().max()) == 0.0 and float(grad.abs().max()) == 0.0
+    lam0 = _balanced_lam(case, 8)
+    lam = to_dev(case, lam0)
+    case.op.krylov_adjoint_step(torch.zeros(g.nstate, dtype=torch.float64, device="cuda"), lam, 0.0,
+                                2e-3, 6, grad)
+    lref, gref = krylov_adjoint_step(case.prob, np.zeros(g.nstate), lam0, 0.0, 2e-3, 6)
+    assert float(grad.abs().max()) == 0.0 and not gref.any()
+    assert rel_l2(lam.cpu().numpy(), lref) <= 1e-11
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_checkpointed_krylov_misfit_gradient_matches_oracle(dtype):
+    """10 Krylov steps (k = 10) with a source, 4 receivers, checkpoints every
+    4 steps. The adjoint states here start as point values at the receivers
+    (pressure only): the Arnoldi process on H^T then sees Hessenberg entries
+    from c^2/h down to 1/h (dt |G_k| ~ 1e3), and FP64 results that agree to
+    about 1e-10 (rounding in the basis amplified by that spread), so FP64 is
+    held to 1e-9 here; the balanced single-step cases above hold 1e-11."""
+    import torch
+    from paper_2401_16322_amd.fwi import misfit_gradient as gpu_misfit_gradient
+    case = make_case((40, 30), dtype, seed=39, n_src=1, max_k=10)
+    rec = np.array([41, 377, 615, 1170], dtype=np.int64)
+    case.op.set_receivers(rec)
+    rng = np.random.default_rng(9)
+    nst, dt, k, t0 = 10, 2e-3, 10, 0.04
+    d_obs = rng.normal(size=(nst, rec.size)) * 1e-4
+    U0 = 1e-3 * case.U0
+    L, grad, lam, _ = gpu_misfit_gradient(case.op, to_dev(case, U0), t0, dt, nst, k,
+                                          torch.tensor(d_obs), checkpoint_every=4, method="krylov")
+    Lr, gr, lr = krylov_misfit_gradient(case.prob, U0, t0, dt, nst, k, rec, d_obs, p=case.p)
+    eg, el = rel_l2(grad.cpu().numpy(), gr), rel_l2(lam.cpu().numpy(), lr)
+    print(f"krylov misfit {dtype}: L {abs(L / Lr - 1):.2e} grad {eg:.2e} lam {el:.2e}")
+    tol = 1e-9 if dtype == "float64" else 1e-5
+    assert L == pytest.approx(Lr, rel=tol)
+    assert eg <= tol
+    assert el <= tol
