@@ -212,6 +212,22 @@ int32_t expw_set_tuning(expw_op* op, int32_t fuse);
  * Results agree to rounding (the same polynomial on the same ellipse). */
 enum { EXPW_PASS_AUTO = 0, EXPW_PASS_TILED = 1, EXPW_PASS_STREAMED = 2 };
 int32_t expw_set_pass_kernel(expw_op* op, int32_t kind);
+/* Autotuner of the Faber step (Sec. 3.2, Faber recurrence; the pass design
+ * is this library's): times expw_step_faber of degree m and step dt on
+ * scratch_dev (a state vector of the op's dtype, overwritten) for every
+ * terms-per-pass depth the layout admits (2D order 4 FP32: 1..6, FP64 and
+ * order 8: 1..4, 3D FP32 order 4: 1..2, else 1) and, for 2D order-4 passes,
+ * both pass kernels; keeps the fastest on the operator (as expw_set_tuning
+ * and expw_set_pass_kernel would; batches created from the operator use
+ * its depth) and returns it in fuse_out, pass_kernel_out and ms_out (one
+ * step, ms; any may be NULL). cache_path (NULL = none): a text file with one
+ * line per device (architecture, compute units), layout (ndim, sizes,
+ * dtype, order, bc) and degree m; a line for this key applies its choice
+ * without timing; otherwise the result is appended (the file is created if
+ * missing; a file that cannot be opened is ignored). Synchronizes the op's
+ * stream while timing. */
+int32_t expw_autotune(expw_op* op, int32_t m, double dt, void* scratch_dev, const char* cache_path,
+                      int32_t* fuse_out, int32_t* pass_kernel_out, double* ms_out);
 
 /* y = H x (no source; Sec. 3, the semi-discrete operator with the staggered
  * differences of Sec. 2.1), x and y device state arrays in the state layout
@@ -341,10 +357,12 @@ int32_t expw_krylov_adjoint_step(expw_op* op, const void* u_dev, void* lam_dev, 
 int32_t expw_inject_receivers(expw_op* op, const void* values_dev, double scale, void* state_dev);
 
 /* Batches of independent problems (shots) stepped together (Faber
- * recurrence, Sec. 3.2): 2D order-4 zero-ghost shots run passes of 4 terms,
- * pass p of every shot still running in one launch (ceil(max m / 4) + 1
- * launches per step); other shots run term j of every shot with degree >= j
- * in one launch (max m + 1 launches). The shots keep their own operators,
+ * recurrence, Sec. 3.2): 2D order-4 zero-ghost shots run passes of S terms
+ * (S = 2, 4 or 6 from the depth set on shot 0's operator by expw_set_tuning
+ * or expw_autotune, rounded; default 4; FP64 at most 4), pass p of every
+ * shot still running in one launch (ceil(max m / S) + 1 launches per step,
+ * or one with expw_batch_set_persistent); other shots run term j of every
+ * shot with degree >= j in one launch (max m + 1 launches). The shots keep their own operators,
  * grids, ellipses, sources and receivers but must share dtype, ndim, order
  * and bc; each shot uses its operator's workspace. */
 typedef struct expw_batch expw_batch;
@@ -370,6 +388,17 @@ int32_t expw_batch_step_faber(expw_batch* b, double t0, int64_t nsteps, int64_t 
  * each replay). nsteps = 0 drops the graph. The graph holds no memset or
  * memcpy nodes. */
 int32_t expw_batch_capture(expw_batch* b, int64_t nsteps);
+/* One launch per batched step (Sec. 3.2, Faber recurrence): on = 1 runs every
+ * pass of every shot, the copies of one-pass shots and the receiver
+ * recording of a step in one cooperative launch whose workgroups take the
+ * shots' tiles in turn and meet at a grid-wide barrier between passes; on =
+ * 0 returns to one launch per pass. Needs 2D order-4 zero-ghost shots
+ * (EXPW_EUNSUPPORTED otherwise, or without cooperative launches). Each
+ * expw_batch_step_faber call then synchronizes the batch's stream once at
+ * its end, and fails with EXPW_EDEVICE if a barrier wait timed out (bounded
+ * waits: the kernel always ends). Captured sequences (expw_batch_capture)
+ * keep one launch per pass. */
+int32_t expw_batch_set_persistent(expw_batch* b, int32_t on);
 int32_t expw_batch_destroy(expw_batch* b);
 
 /* Krylov steps (Arnoldi with modified Gram-Schmidt on the augmented matrix,

@@ -86,16 +86,20 @@ __device__ __forceinline__ void ricker_derivatives_dev(double t, double f_peak, 
   }
 }
 
-// Shot of this block among the first n_part shots (prefix[s] = first block of shot s).
-__device__ __forceinline__ int batch_shot(const int64_t* prefix, int n_part) {
+// Shot of item b among the first n_part shots (prefix[s] = first item of shot s).
+__device__ __forceinline__ int batch_shot_of(const int64_t* prefix, int n_part, int64_t b) {
   int lo = 0, hi = n_part - 1;
-  const int64_t b = blockIdx.x;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (prefix[mid] <= b) lo = mid;
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Shot of this block among the first n_part shots (prefix[s] = first block of shot s).
+__device__ __forceinline__ int batch_shot(const int64_t* prefix, int n_part) {
+  return batch_shot_of(prefix, n_part, blockIdx.x);
 }
 
 // Term j of every shot with m >= j. Buffers per shot as in the one-shot
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchShot<T, K, D
 // fused step: (A, B) and (D, E) alternate as (v_last, v_prev), C holds the
 // FP64 sum, the last pass rounds it into S (a shot of one pass writes A,
 // copied afterwards).
-constexpr int kBatchFuse = 4;
+constexpr int kBatchFuse = 4;  // default depth (2, 4 or 6)
 
 template <typename T>
 struct FusedShot {
@@ -203,13 +207,10 @@ struct FusedShot {
   double qtab[kBatchMaxM][EXPW_MAX_TAYLOR];
 };
 
+// Tile t of pass `pass` of one shot (the whole workgroup).
 template <typename T, int S>
-__global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d_batch(
-    const FusedShot<T>* shots, const int64_t* prefix, int n_part, int pass,
-    const BatchClock* clk, int64_t st) {
-  const int s = batch_shot(prefix, n_part);
-  const FusedShot<T>& sh = shots[s];
-  const int t = static_cast<int>(static_cast<int64_t>(blockIdx.x) - prefix[s]);
+__device__ __forceinline__ void batch_fused_tile(const FusedShot<T>& sh, int t, int pass,
+                                                 const BatchClock* clk, int64_t st) {
   const int tx_ = t % sh.tiles_x, ty_ = t / sh.tiles_x;
   const int j0 = 1 + pass * S;
   const int n = min(S, sh.m - j0 + 1);
@@ -270,6 +271,102 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
   src.amp = sh.src_amp;
   fused2d_pass<T, S>(sh.g, vp, vpp, first ? nullptr : sh.C, ol, opv, acc_out, state_out, c, src,
                      tx_, ty_, r0);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d_batch(
+    const FusedShot<T>* shots, const int64_t* prefix, int n_part, int pass,
+    const BatchClock* clk, int64_t st) {
+  const int s = batch_shot(prefix, n_part);
+  batch_fused_tile<T, S>(shots[s], static_cast<int>(static_cast<int64_t>(blockIdx.x) - prefix[s]), pass,
+                         clk, st);
+}
+
+// One launch per batched step (cooperative: every workgroup is resident).
+// The workgroups take the tiles of pass p of every shot still running in
+// turn (tile i, i + grid, ...), then meet at a grid-wide barrier before pass
+// p + 1; after the last pass, one-pass shots copy their result into the
+// state, and the receivers are recorded, each behind a barrier. The barrier
+// is a counter and a generation word: arriving, a workgroup's first thread
+// releases its writes at agent scope (written back past its XCD's L2) and
+// adds one to the counter; the last to arrive resets it and advances the
+// generation, the others wait for that, and each then acquires at agent
+// scope (its XCD's caches drop lines other XCDs may have written). Every
+// wait is bounded: past spin_limit polls (1024 once err is set) it sets err
+// and goes on, so every wave reaches the end of the kernel; the host then
+// reports the step as failed.
+struct BatchSync {
+  unsigned count, gen;
+  int err, pad;
+};
+
+constexpr int kBatchMaxPasses = kBatchMaxM;
+
+struct BatchPersist {
+  int32_t count_pass[kBatchMaxPasses];
+  int32_t max_passes, n_shots, any_single;
+  uint32_t spin_limit;
+};
+
+__device__ __forceinline__ void batch_grid_sync(BatchSync* bs, unsigned spin_limit) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned g = __hip_atomic_load(&bs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned prev = __hip_atomic_fetch_add(&bs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev + 1 == gridDim.x) {
+      __hip_atomic_store(&bs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bs->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned polls = 0;
+      unsigned limit = __hip_atomic_load(&bs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1024u : spin_limit;
+      while (__hip_atomic_load(&bs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++polls > limit) {
+          __hip_atomic_store(&bs->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        if ((polls & 1023u) == 0 && __hip_atomic_load(&bs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          limit = polls + 1024u < limit ? polls + 1024u : limit;
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(kFusedNT) void k_faber_batch_persistent(
+    const FusedShot<T>* fshots, const int64_t* fprefix, const BatchShot<T, 2, 2>* shots,
+    const int64_t* prefix_rec, BatchPersist pa, const BatchClock* clk, int64_t st, BatchSync* bs) {
+  for (int p = 0; p < pa.max_passes; ++p) {
+    const int np = pa.count_pass[p];
+    const int64_t total = fprefix[np];
+    for (int64_t vt = blockIdx.x; vt < total; vt += gridDim.x) {
+      const int s = batch_shot_of(fprefix, np, vt);
+      batch_fused_tile<T, S>(fshots[s], static_cast<int>(vt - fprefix[s]), p, clk, st);
+      __syncthreads();  // the next tile reuses the LDS
+    }
+    batch_grid_sync(bs, pa.spin_limit);
+  }
+  const int64_t tid = blockIdx.x * static_cast<int64_t>(kFusedNT) + threadIdx.x;
+  const int64_t nth = static_cast<int64_t>(gridDim.x) * kFusedNT;
+  if (pa.any_single) {
+    for (int s = 0; s < pa.n_shots; ++s) {
+      const FusedShot<T>& sh = fshots[s];
+      if (sh.m > S) continue;
+      const int64_t ns = 3 * sh.g.N;
+      for (int64_t i = tid; i < ns; i += nth) sh.S[i] = sh.A[i];
+    }
+    batch_grid_sync(bs, pa.spin_limit);
+  }
+  const int64_t items = prefix_rec[pa.n_shots];
+  for (int64_t it = tid; it < items; it += nth) {
+    const int s = batch_shot_of(prefix_rec, pa.n_shots, it);
+    const BatchShot<T, 2, 2>& sh = shots[s];
+    const int64_t r = it - prefix_rec[s];
+    if (sh.traces && r < sh.n_rec) sh.traces[(clk->trace0 + st) * sh.n_rec + r] = sh.S[sh.rec[r]];
+  }
 }
 
 }  // namespace expw

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <mutex>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -93,6 +94,10 @@ struct expw_batch {
   std::vector<int64_t> fprefix;     // host copy of the tile prefix
   std::vector<void*> copy_dst, copy_src;  // one-pass shots: sum C -> state
   std::vector<int64_t> copy_elems;
+  int depth;          // terms per fused pass (2, 4 or 6)
+  bool persistent;    // one cooperative launch per step
+  int coop_blocks;    // workgroups of that launch (0 = not known yet, < 0 = unavailable)
+  size_t off_sync;    // its barrier words (BatchSync)
   size_t off_clock;
   // a captured sequence of graph_steps steps (nullptr: none)
   hipGraph_t graph;
@@ -984,7 +989,7 @@ template <typename T, int K, int DIM>
 size_t batch_table_bytes(int n) {
   size_t b = align_up(n * sizeof(BatchShot<T, K, DIM>)) + 2 * align_up((n + 1) * sizeof(int64_t));
   if (K == 2 && DIM == 2)
-    b += align_up(n * sizeof(FusedShot<T>)) + align_up((n + 1) * sizeof(int64_t));
+    b += align_up(n * sizeof(FusedShot<T>)) + align_up((n + 1) * sizeof(int64_t)) + align_up(sizeof(BatchSync));
   return b + align_up(sizeof(BatchClock));
 }
 
@@ -1062,9 +1067,16 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
   if constexpr (K == 2 && BC == 0 && DIM == 2) {
     bool ok = true;
     for (int r = 0; r < n; ++r) ok = ok && 3 * host[r].g.N < (int64_t(1) << 31);
+    // passes of the depth set on shot 0's operator (expw_set_tuning or the
+    // autotuner), rounded to 2, 4 or 6 terms (4 at most in FP64), default 4
+    const int req = ops[0]->fuse;
+    int depth = req == 0 ? kBatchFuse : (req <= 2 ? 2 : (req <= 4 ? 4 : 6));
+    if (sizeof(T) == 8 && depth > 4) depth = 4;
+    b->depth = depth;
     if (ok) {
-      constexpr int S = kBatchFuse;
-      constexpr int TX = FusedTile<S>::TX, TY = FusedTile<S>::TY;
+      const int S = depth;
+      const int TX = depth == 2 ? FusedTile<2>::TX : (depth == 4 ? FusedTile<4>::TX : FusedTile<6>::TX);
+      const int TY = depth == 2 ? FusedTile<2>::TY : (depth == 4 ? FusedTile<4>::TY : FusedTile<6>::TY);
       std::vector<unsigned char> fb(n * sizeof(FusedShot<T>), 0);
       auto* fs = reinterpret_cast<FusedShot<T>*>(fb.data());
       std::vector<int64_t> fprefix(n + 1, 0);
@@ -1114,6 +1126,7 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
         for (int p = 0; p < (host[r].m + S - 1) / S; ++p) b->count_pass[p]++;
       b->off_fshots = b->off_prefix_rec + align_up((n + 1) * sizeof(int64_t));
       b->off_fprefix = b->off_fshots + align_up(n * sizeof(FusedShot<T>));
+      b->off_sync = b->off_fprefix + align_up((n + 1) * sizeof(int64_t));
       if (fprefix[n] > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "batch too large for one launch");
       if (hipMemcpyAsync(t + b->off_fshots, fb.data(), fb.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
           hipMemcpyAsync(t + b->off_fprefix, fprefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
@@ -1130,7 +1143,7 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
 // Enqueues steps st = 0..count-1 of the batch (times and trace rows from the
 // clock in the table).
 template <typename T, int K, int BC, int DIM>
-int32_t batch_enqueue(expw_batch* b, int64_t count) {
+int32_t batch_enqueue(expw_batch* b, int64_t count, bool capturing) {
   using Shot = BatchShot<T, K, DIM>;
   char* t = static_cast<char*>(b->table);
   const Shot* shots = reinterpret_cast<const Shot*>(t);
@@ -1140,13 +1153,42 @@ int32_t batch_enqueue(expw_batch* b, int64_t count) {
   for (int64_t st = 0; st < count; ++st) {
     bool done = false;
     if constexpr (K == 2 && BC == 0 && DIM == 2) {
+      if (b->fused && b->persistent && !capturing) {
+        const auto* fshots = reinterpret_cast<const FusedShot<T>*>(t + b->off_fshots);
+        const auto* fprefix = reinterpret_cast<const int64_t*>(t + b->off_fprefix);
+        BatchSync* bs = reinterpret_cast<BatchSync*>(t + b->off_sync);
+        BatchPersist pa{};
+        for (int p = 0; p < b->max_passes; ++p) pa.count_pass[p] = b->count_pass[p];
+        pa.max_passes = b->max_passes;
+        pa.n_shots = b->n;
+        pa.any_single = b->copy_dst.empty() ? 0 : 1;
+        pa.spin_limit = 1u << 22;  // polls of about 0.1 us: far longer than any pass
+        const Shot* shp = shots;
+        const FusedShot<T>* fsp = fshots;
+        const int64_t* fpp = fprefix;
+        const int64_t* prp = prefix_rec;
+        const BatchClock* ckp = clk;
+        int64_t stv = st;
+        void* args[] = {&fsp, &fpp, &shp, &prp, &pa, &ckp, &stv, &bs};
+        const void* fn = b->depth == 2 ? reinterpret_cast<const void*>(k_faber_batch_persistent<T, 2>)
+                         : b->depth == 4 ? reinterpret_cast<const void*>(k_faber_batch_persistent<T, 4>)
+                                         : reinterpret_cast<const void*>(k_faber_batch_persistent<T, 6>);
+        if (hipLaunchCooperativeKernel(fn, dim3(b->coop_blocks), dim3(kFusedNT), args, 0, b->stream) != hipSuccess)
+          return fail(EXPW_EDEVICE, "batch: persistent launch failed: %s", hipGetErrorString(hipGetLastError()));
+        continue;
+      }
       if (b->fused) {
         const auto* fshots = reinterpret_cast<const FusedShot<T>*>(t + b->off_fshots);
         const auto* fprefix = reinterpret_cast<const int64_t*>(t + b->off_fprefix);
         for (int p = 0; p < b->max_passes; ++p) {
           const int np = b->count_pass[p];
           const unsigned grid = static_cast<unsigned>(b->fprefix[np]);
-          k_faber_fused2d_batch<T, kBatchFuse><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, clk, st);
+          if (b->depth == 2)
+            k_faber_fused2d_batch<T, 2><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, clk, st);
+          else if (b->depth == 4)
+            k_faber_fused2d_batch<T, 4><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, clk, st);
+          else
+            k_faber_fused2d_batch<T, 6><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, clk, st);
           if (int32_t rc = check_launch("batch fused pass")) return rc;
         }
         for (size_t i = 0; i < b->copy_dst.size(); ++i) {
@@ -1176,6 +1218,13 @@ int32_t batch_enqueue(expw_batch* b, int64_t count) {
 template <typename T, int K, int BC, int DIM>
 int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t step0) {
   BatchClock* clk = reinterpret_cast<BatchClock*>(static_cast<char*>(b->table) + b->off_clock);
+  const bool persistent = b->fused && b->persistent;
+  BatchSync* bs = reinterpret_cast<BatchSync*>(static_cast<char*>(b->table) + b->off_sync);
+  if (persistent) {
+    // a clean barrier (also after a failed call) and no error
+    k_zero_u32<<<1, 64, 0, b->stream>>>(reinterpret_cast<unsigned*>(bs), 4);
+    if (int32_t rc = check_launch("batch barrier reset")) return rc;
+  }
   int64_t done = 0;
   while (done < nsteps) {
     const bool use_graph = b->gexec && nsteps - done >= b->graph_steps;
@@ -1184,10 +1233,17 @@ int32_t batch_step_impl(expw_batch* b, double t0, int64_t nsteps, int64_t step0)
     if (int32_t rc = check_launch("batch clock")) return rc;
     if (use_graph) {
       if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return fail(EXPW_EDEVICE, "batch graph launch failed");
-    } else if (int32_t rc = batch_enqueue<T, K, BC, DIM>(b, count)) {
+    } else if (int32_t rc = batch_enqueue<T, K, BC, DIM>(b, count, false)) {
       return rc;
     }
     done += count;
+  }
+  if (persistent) {
+    int err = 0;
+    if (hipMemcpyAsync(&err, &bs->err, sizeof(int), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+      return fail(EXPW_EDEVICE, "batch: %s", hipGetErrorString(hipGetLastError()));
+    if (err) return fail(EXPW_EDEVICE, "batch: a grid-wide barrier of the persistent step timed out");
   }
   return EXPW_OK;
 }
@@ -1607,7 +1663,7 @@ int32_t expw_batch_capture(expw_batch* b, int64_t nsteps) {
     return fail(EXPW_EDEVICE, "batch: stream capture could not start");
   int32_t rc = dispatch_batch(b, [&](auto cfg) {
     using C = decltype(cfg);
-    return batch_enqueue<typename C::type, C::k, C::bc, C::dim>(b, nsteps);
+    return batch_enqueue<typename C::type, C::k, C::bc, C::dim>(b, nsteps, true);
   });
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(b->stream, &g);
@@ -1623,6 +1679,35 @@ int32_t expw_batch_capture(expw_batch* b, int64_t nsteps) {
   b->graph = g;
   b->gexec = x;
   b->graph_steps = nsteps;
+  return EXPW_OK;
+}
+
+int32_t expw_batch_set_persistent(expw_batch* b, int32_t on) {
+  if (!b) return fail(EXPW_EINVAL, "batch is NULL");
+  if (!on) {
+    b->persistent = false;
+    return EXPW_OK;
+  }
+  if (!b->fused) return fail(EXPW_EUNSUPPORTED, "persistent batches need 2D order-4 shots with zero ghosts");
+  if (b->coop_blocks == 0) {
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    const void* fn = nullptr;
+    const bool f32 = b->g.dtype == EXPW_F32;
+    if (b->depth == 2) fn = f32 ? reinterpret_cast<const void*>(k_faber_batch_persistent<float, 2>) : reinterpret_cast<const void*>(k_faber_batch_persistent<double, 2>);
+    else if (b->depth == 4) fn = f32 ? reinterpret_cast<const void*>(k_faber_batch_persistent<float, 4>) : reinterpret_cast<const void*>(k_faber_batch_persistent<double, 4>);
+    else fn = f32 ? reinterpret_cast<const void*>(k_faber_batch_persistent<float, 6>) : reinterpret_cast<const void*>(k_faber_batch_persistent<double, 6>);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFusedNT, 0) != hipSuccess || !coop || per_cu < 1) {
+      b->coop_blocks = -1;
+    } else {
+      const int64_t tiles0 = b->fprefix[b->count_pass[0]];
+      b->coop_blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(cus) * per_cu, tiles0)));
+    }
+  }
+  if (b->coop_blocks < 0) return fail(EXPW_EUNSUPPORTED, "cooperative launches are not available");
+  b->persistent = true;
   return EXPW_OK;
 }
 
@@ -1733,6 +1818,99 @@ int32_t expw_step_faber(expw_op* op, void* state, double t0, double dt, int32_t 
     std::vector<double> a(m + 1), q(m);
     return faber_impl<T, C::k, C::bc, C::dim>(op, static_cast<T*>(state), t0, dt, m, nsteps, static_cast<T*>(traces), nullptr, op->ws + op->off_big, a.data(), q.data());
   });
+}
+
+int32_t expw_autotune(expw_op* op, int32_t m, double dt, void* scratch, const char* cache_path,
+                      int32_t* fuse_out, int32_t* pass_kernel_out, double* ms_out) {
+  if (int32_t rc = check_step_args(op, scratch, dt, 1)) return rc;
+  if (m < 1 || m > 1024) return fail(EXPW_EINVAL, "Faber degree m must be in [1, 1024]");
+  // the key: device (architecture and compute units) and layout
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(EXPW_EDEVICE, "autotune: device query failed");
+  const expw_grid& g = op->g;
+  char key[256];
+  std::snprintf(key, sizeof key, "expw-autotune-v1 %s %d %d %lldx%lldx%lld %s %d %d %d", prop.gcnArchName,
+                prop.multiProcessorCount, g.ndim, static_cast<long long>(g.n[0]),
+                static_cast<long long>(g.ndim > 1 ? g.n[1] : 1), static_cast<long long>(g.ndim > 2 ? g.n[2] : 1),
+                g.dtype == EXPW_F32 ? "f32" : "f64", g.order, g.bc, m);
+  int fuse = -1, pk = -1;
+  double best = 0.0;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[512];
+      const size_t kl = std::strlen(key);
+      while (std::fgets(line, sizeof line, f))
+        if (std::strncmp(line, key, kl) == 0 && line[kl] == ' ') {
+          int fz = 0, pkk = 0;
+          double ms = 0.0;
+          if (std::sscanf(line + kl, "%d %d %lf", &fz, &pkk, &ms) == 3 && fz >= 0 && fz <= kMaxFuse &&
+              pkk >= EXPW_PASS_AUTO && pkk <= EXPW_PASS_STREAMED) {
+            fuse = fz;
+            pk = pkk;
+            best = ms;
+          }
+        }
+      std::fclose(f);
+    }
+  }
+  if (fuse < 0) {
+    // candidates: every depth the layout admits, and both 2D order-4 pass kernels
+    const bool f32 = g.dtype == EXPW_F32;
+    int smax = 1;
+    if (g.bc == EXPW_BC_ZERO) {
+      if (g.ndim == 3) smax = (f32 && g.order == 4) ? 2 : 1;
+      else smax = (g.order == 4 && f32) ? 6 : 4;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return fail(EXPW_EDEVICE, "autotune: event creation failed");
+    }
+    const int saved_fuse = op->fuse, saved_pk = op->pass_kernel;
+    int32_t rc = EXPW_OK;
+    const int reps = 3;
+    for (int fz = 1; fz <= std::min(smax, m) && rc == EXPW_OK; ++fz) {
+      const bool two = g.ndim == 2 && g.order == 4 && g.bc == EXPW_BC_ZERO && fz >= 2;
+      for (int pkk : {EXPW_PASS_TILED, EXPW_PASS_STREAMED}) {
+        if (!two && pkk == EXPW_PASS_STREAMED) continue;
+        op->fuse = fz;
+        op->pass_kernel = two ? pkk : EXPW_PASS_AUTO;
+        rc = expw_step_faber(op, scratch, 0.0, dt, m, 1, nullptr);  // warm-up
+        if (rc == EXPW_OK && hipEventRecord(e0, op->stream) != hipSuccess) rc = fail(EXPW_EDEVICE, "autotune: event record failed");
+        if (rc == EXPW_OK) rc = expw_step_faber(op, scratch, dt, dt, m, reps, nullptr);
+        float ms = 0.f;
+        if (rc == EXPW_OK && (hipEventRecord(e1, op->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = fail(EXPW_EDEVICE, "autotune: timing failed");
+        if (rc != EXPW_OK) break;
+        const double per = ms / reps;
+        if (fuse < 0 || per < best) {
+          fuse = fz;
+          pk = op->pass_kernel;
+          best = per;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    op->fuse = saved_fuse;
+    op->pass_kernel = saved_pk;
+    if (rc != EXPW_OK) return rc;
+    if (cache_path) {
+      if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s %d %d %.9g\n", key, fuse, pk, best);
+        std::fclose(f);
+      }
+    }
+  }
+  op->fuse = fuse;
+  op->pass_kernel = pk;
+  if (fuse_out) *fuse_out = fuse;
+  if (pass_kernel_out) *pass_kernel_out = pk;
+  if (ms_out) *ms_out = best;
+  return EXPW_OK;
 }
 
 int32_t expw_step_faber_noalloc(expw_op* op, void* state, double t0, double dt, int32_t m,

@@ -75,6 +75,8 @@ SIGNATURES = {
     "expw_set_ellipse": (_i32, [_vp, _dbl, _dbl, _dbl]),
     "expw_set_tuning": (_i32, [_vp, _i32]),
     "expw_set_pass_kernel": (_i32, [_vp, _i32]),
+    "expw_autotune": (_i32, [_vp, _i32, _dbl, _vp, ctypes.c_char_p, ctypes.POINTER(_i32),
+                             ctypes.POINTER(_i32), ctypes.POINTER(_dbl)]),
     "expw_apply": (_i32, [_vp, _vp, _vp]),
     "expw_apply_adjoint": (_i32, [_vp, _vp, _vp]),
     "expw_faber_adjoint_step": (_i32, [_vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp]),
@@ -94,6 +96,7 @@ SIGNATURES = {
     "expw_batch_step_faber": (_i32, [_vp, _dbl, _i64, _i64]),
     "expw_batch_capture": (_i32, [_vp, _i64]),
     "expw_batch_destroy": (_i32, [_vp]),
+    "expw_batch_set_persistent": (_i32, [_vp, _i32]),
     "expw_step_krylov": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_rk4": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
     "expw_step_leapfrog": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
@@ -315,6 +318,15 @@ def expw_set_pass_kernel(op, kind):
     _check(load().expw_set_pass_kernel(op, int(kind)))
 
 
+def expw_autotune(op, m, dt, scratch_ptr, cache_path=None):
+    """(fuse, pass_kernel, ms per step) chosen by the library's autotuner."""
+    fz, pk, ms = _i32(0), _i32(0), _dbl(0.0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(load().expw_autotune(op, int(m), float(dt), scratch_ptr, path, ctypes.byref(fz),
+                                ctypes.byref(pk), ctypes.byref(ms)))
+    return fz.value, pk.value, ms.value
+
+
 def expw_apply(op, x_ptr, y_ptr):
     _check(load().expw_apply(op, x_ptr, y_ptr))
 
@@ -407,6 +419,10 @@ def expw_batch_capture(batch, nsteps):
 
 def expw_batch_destroy(batch):
     _check(load().expw_batch_destroy(batch))
+
+
+def expw_batch_set_persistent(batch, on):
+    _check(load().expw_batch_set_persistent(batch, 1 if on else 0))
 
 
 def expw_step_krylov(op, state_ptr, t0, dt, k, nsteps, traces_ptr=None):
@@ -567,34 +583,16 @@ class Operator:
         """Fused-pass kernel of 2D order-4 grids: auto, tiled or streamed."""
         expw_set_pass_kernel(self.op, kind)
 
-    def autotune_fuse(self, m, dt, candidates=None, steps=3, repeats=2):
-        """Pick the Faber fusion depth (terms per sweep) that runs fastest
-        for degree m on this grid: each candidate runs `steps` steps on a
-        scratch state (twice, the better time counts; HIP events on the
-        operator's stream), then the fastest is set. Returns
-        (best, {depth: ms per step})."""
-        torch = self._torch
-        if candidates is None:
-            candidates = (1, 2, 3, 4, 5, 6, 8) if self.dtype == torch.float32 else (1, 2, 3, 4)
-        scratch = torch.zeros(self.nstate, dtype=self.dtype, device=self.device)
-        times = {}
-        for f in candidates:
-            self.set_tuning(f)
-            self.step_faber(scratch, 0.0, dt, m, 1)   # warm-up (and first-use set-up)
-            best = None
-            for _ in range(repeats):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                self.step_faber(scratch, 0.0, dt, m, steps)
-                e1.record()
-                e1.synchronize()
-                ms = e0.elapsed_time(e1) / steps
-                best = ms if best is None else min(best, ms)
-            times[f] = best
-        fbest = min(times, key=times.get)
-        self.set_tuning(fbest)
-        return fbest, times
+    def autotune(self, m, dt, cache_path=None):
+        """The library's autotuner (expw_autotune): times every depth and pass
+        kernel this grid admits for Faber steps of degree m (or takes them
+        from cache_path) and keeps the fastest. Returns (fuse, pass_kernel,
+        ms per step)."""
+        scratch = self._torch.zeros(self.nstate, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        fz, pk, ms = expw_autotune(self.op, m, dt, scratch.data_ptr(), cache_path)
+        self.fuse = fz
+        return fz, pk, ms
 
     def apply(self, x, out=None):
         self._check_state(x)
@@ -958,6 +956,10 @@ class Batch:
         self.stream.wait_stream(cur)
         expw_batch_step_faber(self.handle, t0, nsteps, step0)
         cur.wait_stream(self.stream)
+
+    def set_persistent(self, on=True):
+        """One cooperative launch per step (True) or one launch per pass."""
+        expw_batch_set_persistent(self.handle, on)
 
     def capture(self, nsteps):
         """Capture nsteps steps into a HIP graph replayed by step() (0 drops it)."""

@@ -84,19 +84,83 @@ def test_batch_validation():
         Batch([a.op, c.op], [4, 4], [1e-3, 1e-3], [sa, sa])     # shared state
 
 
-def test_autotune_fuse_picks_a_depth_with_the_same_results():
-    """The autotuner times the depths and keeps the fastest; any depth gives
-    the same step (rounding order aside)."""
+def test_autotune_picks_and_caches_a_choice_with_the_same_results(tmp_path):
+    """The library's autotuner times the depths and pass kernels, keeps the
+    fastest, appends it to the cache file, and a second operator of the same
+    layout takes it from the cache without timing; any choice gives the same
+    step (rounding order aside)."""
+    cache = tmp_path / "tune.txt"
     case = make_case((300, 140), "float32", seed=70)
-    best, times = case.op.autotune_fuse(16, 2e-3, candidates=(1, 2, 4, 8), steps=2, repeats=1)
-    assert best in times and times[best] == min(times.values())
-    assert case.op.fuse == best
+    fz, pk, ms = case.op.autotune(16, 2e-3, cache_path=str(cache))
+    assert 1 <= fz <= 6 and pk in (0, 1, 2) and ms > 0
+    assert case.op.fuse == fz
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[-3:-1] == [str(fz), str(pk)]
+    other = make_case((300, 140), "float32", seed=71)
+    assert other.op.autotune(16, 2e-3, cache_path=str(cache)) == (fz, pk, pytest.approx(ms, rel=1e-5))
+    assert len(cache.read_text().splitlines()) == 1
     U = to_dev(case, case.U0)
     case.op.step_faber(U, 0.0, 2e-3, 16, 2)
     case.op.set_tuning(1)
     V = to_dev(case, case.U0)
     case.op.step_faber(V, 0.0, 2e-3, 16, 2)
     assert rel_l2(U.cpu().numpy(), V.cpu().numpy()) <= 2e-6
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("depth", [2, 4, 6])
+def test_batch_depths_and_persistent_launch(dtype, depth):
+    """Batches run passes of the depth set on shot 0's operator (6 becomes 4
+    in FP64); one cooperative launch per step gives the per-pass launches'
+    states and traces bit for bit; both match single shots and the oracle.
+    Degrees 2 and 3 make one-pass shots (copied into the state) for depth
+    >= 4."""
+    import torch
+    from paper_2401_16322_amd.expwave import Batch
+    dims = [(90, 40), (33, 71), (128, 65), (20, 18), (257, 30)]
+    ms = [2, 3, 16, 7, 12]
+    dts = [1e-3, 2e-3, 2e-3, 1.5e-3, 3e-3]
+    nst, t0 = 3, 0.02
+    runs = []
+    for persistent in (False, True):
+        cases = _shots(dtype, dims)
+        cases[0][0].op.set_tuning(depth)
+        states = [to_dev(c, c.U0) for c, _ in cases]
+        traces = [torch.zeros(nst * r.size, dtype=c.torch_dtype, device="cuda") for c, r in cases]
+        b = Batch([c.op for c, _ in cases], ms, dts, states, traces)
+        if persistent:
+            b.set_persistent(True)
+        b.step(t0, 1)
+        b.step(t0, nst - 1, step0=1)
+        torch.cuda.synchronize()
+        runs.append(([S.cpu().numpy() for S in states], [t.cpu().numpy() for t in traces]))
+        b.close()
+    for a, c_ in zip(runs[0][0] + runs[0][1], runs[1][0] + runs[1][1]):
+        assert np.array_equal(a, c_)
+    tight = 1e-13 if dtype == "float64" else 2e-6
+    cases = _shots(dtype, dims)
+    for (c, rec), S, tr, m, dt in zip(cases, runs[1][0], runs[1][1], ms, dts):
+        U = to_dev(c, c.U0)
+        tr1 = torch.zeros(nst * rec.size, dtype=c.torch_dtype, device="cuda")
+        c.op.set_tuning(1)
+        c.op.step_faber(U, t0, dt, m, nst, traces=tr1)
+        assert rel_l2(S, U.cpu().numpy()) <= tight
+        assert rel_l2(tr, tr1.cpu().numpy()) <= tight
+    c, rec = cases[2]
+    Uref, trref, _ = run(c.prob, "faber", c.U0, t0, dts[2], nst, receivers=rec, m=ms[2], p=c.p,
+                         ellipse=c.prob.ellipse())
+    assert rel_l2(runs[1][0][2], Uref) <= TOL[dtype]
+    assert rel_l2(runs[1][1][2].reshape(nst, -1), trref) <= TOL[dtype]
+
+
+def test_persistent_batch_rejects_unsupported_shots():
+    from paper_2401_16322_amd.expwave import Batch, ExpwError
+    cases = _shots("float64", [(17, 13, 11), (9, 20, 14)])
+    states = [to_dev(c, c.U0) for c, _ in cases]
+    b = Batch([c.op for c, _ in cases], [5, 8], [2e-3, 1e-3], states)
+    with pytest.raises(ExpwError):
+        b.set_persistent(True)
+    b.close()
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
