@@ -9,17 +9,6 @@
 namespace expw {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
-constexpr int kXcds = 8;           // accelerator complex dies, each with its own L2
-
-// The dispatcher deals the workgroups of a launch to the XCDs round-robin
-// (workgroup i runs on XCD i mod 8). This renumbering hands each XCD a
-// contiguous range of logical workgroups (a bijection on [0, nb)), so that
-// tiles which share halo data run on the same XCD and meet in its L2.
-__device__ __forceinline__ int xcd_contiguous(int i, int nb) {
-  const int q = nb / kXcds, r = nb % kXcds;
-  const int x = i % kXcds, l = i / kXcds;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
-}
 constexpr int kRedMaxBlocks = 1024;  // grid cap (and partials length) of reduction kernels
 
 // Geometry and coefficients of H on one grid, passed to kernels by value.

@@ -29,6 +29,17 @@ namespace expw {
 constexpr int k3X = 64, k3Y = 16, k3NT = k3X * k3Y;  // threads: columns of the loaded region
 constexpr int k3TX = k3X - 8, k3TY = k3Y - 8;        // output tile
 constexpr int k3ZC = 32;                             // output planes per workgroup
+constexpr int kXcds = 8;                             // accelerator complex dies, each with its own L2
+
+// The dispatcher deals the workgroups of a launch to the XCDs round-robin
+// (workgroup i runs on XCD i mod 8). This renumbering hands each XCD a
+// contiguous range of logical workgroups (a bijection on [0, nb)), so that
+// tiles which share halo data run on the same XCD and meet in its L2.
+__device__ __forceinline__ int xcd_contiguous(int i, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = i % kXcds, l = i / kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
 
 struct Fused3Args {
   double kappa, inv_ws, c0, a_first;
