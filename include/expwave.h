@@ -197,7 +197,8 @@ int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
 
 /* Kernel tuning for the Faber step: fuse = recurrence terms per HBM sweep
  * (0 = automatic, 1 = one term per sweep, up to 8 accepted). 2D order 4:
- * up to 6 terms at FP32 and 4 at FP64, automatic = 4; 2D order 8: up to 4,
+ * up to 6 terms at FP32 and 4 at FP64, automatic = 4 (6 at FP32 where the
+ * tiled passes run, see expw_set_pass_kernel); 2D order 8: up to 4,
  * automatic = 3; 3D FP32 order 4: two terms unless fuse = 1; 3D FP64: one
  * term per sweep. Only zero ghosts fuse. Results do not depend on it beyond
  * rounding order. */
@@ -359,7 +360,7 @@ int32_t expw_inject_receivers(expw_op* op, const void* values_dev, double scale,
 /* Batches of independent problems (shots) stepped together (Faber
  * recurrence, Sec. 3.2): 2D order-4 zero-ghost shots run passes of S terms
  * (S = 2, 4 or 6 from the depth set on shot 0's operator by expw_set_tuning
- * or expw_autotune, rounded; default 4; FP64 at most 4), pass p of every
+ * or expw_autotune, rounded; default 6 in FP32, 4 in FP64; FP64 at most 4), pass p of every
  * shot still running in one launch (ceil(max m / S) + 1 launches per step,
  * or one with expw_batch_set_persistent); other shots run term j of every
  * shot with degree >= j in one launch (max m + 1 launches). The shots keep their own operators,

@@ -58,6 +58,7 @@ struct BatchShot {
   T* traces;  // NULL: not recorded
   double f_peak, t_delay, dt;
   double inv_gamma, c0, c1;
+  double kappa, inv_ws;  // wscale / gamma and 1 / wscale (the fused passes' form)
   double a[kBatchMaxM + 1];
   double qtab[kBatchMaxM][EXPW_MAX_TAYLOR];  // source scalar of term j: sum_c G_c(t) qtab[j-1][c]
 };
@@ -202,15 +203,42 @@ struct FusedShot {
   const int64_t* src_idx;
   const T* src_amp;
   double f_peak, t_delay, dt;
-  double inv_gamma, c0, c1;
+  double kappa, inv_ws, c0, c1;
   double a[kBatchMaxM + 1];
+  T cpp[kBatchMaxM + 1];  // coefficient of v_{j-2} in term j (0, 2 c1, c1, ...), in T
   double qtab[kBatchMaxM][EXPW_MAX_TAYLOR];
 };
 
-// Tile t of pass `pass` of one shot (the whole workgroup).
+// The source scalars of every term of shot sh for step st (one thread):
+// q_j = sum_c g^(p-1-c)(t) qtab[j - 1][c], with the Ricker derivatives g^(k)
+// at the step time from the Hermite recurrence (the host's FP64 formula);
+// zero without a source.
+template <typename T>
+__device__ __forceinline__ void batch_shot_source_q(const FusedShot<T>& sh, const BatchClock* clk,
+                                                    int64_t st, T* q) {
+  double gk[EXPW_MAX_TAYLOR];
+  const int p = sh.n_src > 0 ? sh.p : 0;
+  if (p > 0) ricker_derivatives_dev(clk->t0 + (clk->step0 + st) * sh.dt, sh.f_peak, sh.t_delay, p, gk);
+  for (int j = 1; j <= sh.m; ++j) {
+    double v = 0.0;
+    for (int c = 0; c < p; ++c) v += gk[p - 1 - c] * sh.qtab[j - 1][c];
+    q[j - 1] = static_cast<T>(v);
+  }
+}
+
+// The per-step table of source scalars (kBatchMaxM per shot), one thread per shot.
+template <typename T>
+__global__ __launch_bounds__(64) void k_batch_source_q(const FusedShot<T>* shots, int n, const BatchClock* clk,
+                                                       int64_t st, T* qstep) {
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s < n) batch_shot_source_q(shots[s], clk, st, qstep + static_cast<int64_t>(s) * kBatchMaxM);
+}
+
+// Tile t of pass `pass` of one shot (the whole workgroup); qs: the shot's
+// source scalars of this step (k_batch_source_q).
 template <typename T, int S>
-__device__ __forceinline__ void batch_fused_tile(const FusedShot<T>& sh, int t, int pass,
-                                                 const BatchClock* clk, int64_t st) {
+__device__ __forceinline__ void batch_fused_tile(const FusedShot<T>& sh, const T* __restrict__ qs, int t,
+                                                 int pass) {
   const int tx_ = t % sh.tiles_x, ty_ = t / sh.tiles_x;
   const int j0 = 1 + pass * S;
   const int n = min(S, sh.m - j0 + 1);
@@ -218,43 +246,18 @@ __device__ __forceinline__ void batch_fused_tile(const FusedShot<T>& sh, int t, 
   const bool first = (pass == 0);
   const bool last = (j0 + n - 1 == sh.m);
   FusedArgs<T, S> c{};
-  c.inv_gamma = sh.inv_gamma;
-  c.c0 = sh.c0;
+  c.kappa = static_cast<T>(sh.kappa);
+  c.inv_ws = static_cast<T>(sh.inv_ws);
+  c.c0 = static_cast<T>(sh.c0);
   c.first = first ? 1 : 0;
   c.a_first = sh.a[0];
-  // source scalars of the pass's terms: q_r = sum_c g^(p-1-c)(t) qtab[j_r - 1][c],
-  // accumulated while the Ricker derivatives are generated (no arrays)
-  double q[S];
-#pragma unroll
-  for (int r = 0; r < S; ++r) q[r] = 0.0;
-  if (sh.n_src > 0) {
-    const double pi = 3.14159265358979323846264338327950;
-    const double a = (pi * sh.f_peak) * (pi * sh.f_peak);
-    const double tau = clk->t0 + (clk->step0 + st) * sh.dt - sh.t_delay;
-    const double sa = sqrt(a);
-    const double xs = sa * tau;
-    const double e = exp(-a * tau * tau);
-    double hm1 = 1.0, h0 = 2.0 * xs, apow = a;
-    for (int nn = 1; nn <= sh.p; ++nn) {
-      const double h1 = 2.0 * xs * h0 - 2.0 * nn * hm1;  // H_{nn+1}
-      hm1 = h0;
-      h0 = h1;
-      const int k = nn - 1;                             // g^(k) uses H_{k+2}
-      const double gk = -(1.0 / (2.0 * a)) * ((k % 2 == 0) ? 1.0 : -1.0) * apow * h0 * e;
-      apow *= sa;
-      const int cc = sh.p - 1 - k;
-#pragma unroll
-      for (int r = 0; r < S; ++r)
-        if (r >= r0) q[r] += gk * sh.qtab[j0 + (r - r0) - 1][cc];
-    }
-  }
 #pragma unroll
   for (int r = 0; r < S; ++r) {
     const int j = j0 + (r - r0);
     const bool on = r >= r0;
     c.a[r] = on ? sh.a[j] : 0.0;
-    c.cpp[r] = (!on || j == 1) ? 0.0 : (j == 2 ? 2.0 * sh.c1 : sh.c1);
-    c.q[r] = q[r];
+    c.cpp[r] = on ? sh.cpp[j] : T(0);
+    c.q[r] = on ? qs[j - 1] : T(0);
   }
   const bool odd_in = ((pass - 1) & 1) != 0, odd_out = (pass & 1) != 0;
   const T* vp = first ? sh.S : (odd_in ? sh.D : sh.A);
@@ -275,11 +278,11 @@ __device__ __forceinline__ void batch_fused_tile(const FusedShot<T>& sh, int t, 
 
 template <typename T, int S>
 __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fused2d_batch(
-    const FusedShot<T>* shots, const int64_t* prefix, int n_part, int pass,
-    const BatchClock* clk, int64_t st) {
+    const FusedShot<T>* __restrict__ shots, const int64_t* __restrict__ prefix, int n_part, int pass,
+    const T* __restrict__ qstep) {
   const int s = batch_shot(prefix, n_part);
-  batch_fused_tile<T, S>(shots[s], static_cast<int>(static_cast<int64_t>(blockIdx.x) - prefix[s]), pass,
-                         clk, st);
+  batch_fused_tile<T, S>(shots[s], qstep + static_cast<int64_t>(s) * kBatchMaxM,
+                         static_cast<int>(static_cast<int64_t>(blockIdx.x) - prefix[s]), pass);
 }
 
 // One launch per batched step (cooperative: every workgroup is resident).
@@ -338,13 +341,19 @@ __device__ __forceinline__ void batch_grid_sync(BatchSync* bs, unsigned spin_lim
 template <typename T, int S>
 __global__ __launch_bounds__(kFusedNT) void k_faber_batch_persistent(
     const FusedShot<T>* fshots, const int64_t* fprefix, const BatchShot<T, 2, 2>* shots,
-    const int64_t* prefix_rec, BatchPersist pa, const BatchClock* clk, int64_t st, BatchSync* bs) {
+    const int64_t* prefix_rec, BatchPersist pa, const BatchClock* clk, int64_t st, BatchSync* bs,
+    T* qstep) {
+  // the step's source scalars, one thread per shot, before the first pass
+  for (int s = blockIdx.x * kFusedNT + threadIdx.x; s < pa.n_shots; s += gridDim.x * kFusedNT)
+    batch_shot_source_q(fshots[s], clk, st, qstep + static_cast<int64_t>(s) * kBatchMaxM);
+  batch_grid_sync(bs, pa.spin_limit);
   for (int p = 0; p < pa.max_passes; ++p) {
     const int np = pa.count_pass[p];
     const int64_t total = fprefix[np];
     for (int64_t vt = blockIdx.x; vt < total; vt += gridDim.x) {
       const int s = batch_shot_of(fprefix, np, vt);
-      batch_fused_tile<T, S>(fshots[s], static_cast<int>(vt - fprefix[s]), p, clk, st);
+      batch_fused_tile<T, S>(fshots[s], qstep + static_cast<int64_t>(s) * kBatchMaxM,
+                             static_cast<int>(vt - fprefix[s]), p);
       __syncthreads();  // the next tile reuses the LDS
     }
     batch_grid_sync(bs, pa.spin_limit);

@@ -98,6 +98,7 @@ struct expw_batch {
   bool persistent;    // one cooperative launch per step
   int coop_blocks;    // workgroups of that launch (0 = not known yet, < 0 = unavailable)
   size_t off_sync;    // its barrier words (BatchSync)
+  size_t off_qstep;   // the step's source scalars (kBatchMaxM doubles per shot)
   size_t off_clock;
   // a captured sequence of graph_steps steps (nullptr: none)
   hipGraph_t graph;
@@ -467,7 +468,15 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
   faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a);
   for (int j = 0; j < m; ++j) q[j] = 0.0;
   const int p = op->taylor_p;
-  const int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m, g.N);
+  int req = op->fuse;
+  if constexpr (K == 2 && BC == 0 && DIM == 2 && sizeof(T) == 4) {
+    // the tiled passes keep the FP64 sum of the tile in LDS: from 5 terms on,
+    // two workgroups fit a CU, so where they run they default to 6 terms
+    const bool streamed = op->pass_kernel == EXPW_PASS_STREAMED ||
+                          (op->pass_kernel == EXPW_PASS_AUTO && stream2d_fits(g.n[0], g.n[1], 4));
+    if (req == 0 && !streamed) req = 6;
+  }
+  const int fuse = fused_depth<T, K, BC, DIM>(req, m, g.N);
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     if (op->n_src > 0) {
@@ -502,9 +511,9 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
                 if (op->pass_kernel == EXPW_PASS_STREAMED ||
                     (op->pass_kernel == EXPW_PASS_AUTO && stream2d_fits(g.n[0], g.n[1], n)))
                   return launch_stream_pass<T>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1, rr);
-                return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1, rr);
+                return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1, rr);
               } else
-                return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.gamma, el.c0, el.c1, rr);
+                return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1, rr);
             });
       } else if constexpr (K == 2 && BC == 0 && DIM == 3 && sizeof(T) == 4) {
         rc = faber_fused_passes<T>(op->stream, ns, S, b, m, 2, final_term,
@@ -989,7 +998,8 @@ template <typename T, int K, int DIM>
 size_t batch_table_bytes(int n) {
   size_t b = align_up(n * sizeof(BatchShot<T, K, DIM>)) + 2 * align_up((n + 1) * sizeof(int64_t));
   if (K == 2 && DIM == 2)
-    b += align_up(n * sizeof(FusedShot<T>)) + align_up((n + 1) * sizeof(int64_t)) + align_up(sizeof(BatchSync));
+    b += align_up(n * sizeof(FusedShot<T>)) + align_up((n + 1) * sizeof(int64_t)) + align_up(sizeof(BatchSync)) +
+         align_up(static_cast<size_t>(n) * kBatchMaxM * sizeof(double));
   return b + align_up(sizeof(BatchClock));
 }
 
@@ -1022,6 +1032,8 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
     sh.inv_gamma = 1.0 / el.gamma;
     sh.c0 = el.c0;
     sh.c1 = el.c1;
+    sh.kappa = el.kappa;
+    sh.inv_ws = el.inv_ws;
     faber_coefficients(el.gamma, el.c0, el.c1, dt[i], m[i], sh.a);
     if (op->n_src > 0) {
       sh.n_src = op->n_src;
@@ -1068,9 +1080,10 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
     bool ok = true;
     for (int r = 0; r < n; ++r) ok = ok && 3 * host[r].g.N < (int64_t(1) << 31);
     // passes of the depth set on shot 0's operator (expw_set_tuning or the
-    // autotuner), rounded to 2, 4 or 6 terms (4 at most in FP64), default 4
+    // autotuner), rounded to 2, 4 or 6 terms (4 at most in FP64); default 6
+    // in FP32 (two workgroups per CU fit the tiles' LDS), 4 in FP64
     const int req = ops[0]->fuse;
-    int depth = req == 0 ? kBatchFuse : (req <= 2 ? 2 : (req <= 4 ? 4 : 6));
+    int depth = req == 0 ? (sizeof(T) == 4 ? 6 : kBatchFuse) : (req <= 2 ? 2 : (req <= 4 ? 4 : 6));
     if (sizeof(T) == 8 && depth > 4) depth = 4;
     b->depth = depth;
     if (ok) {
@@ -1107,10 +1120,13 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
         f.f_peak = h.f_peak;
         f.t_delay = h.t_delay;
         f.dt = h.dt;
-        f.inv_gamma = h.inv_gamma;
+        f.kappa = h.kappa;
+        f.inv_ws = h.inv_ws;
         f.c0 = h.c0;
         f.c1 = h.c1;
         std::memcpy(f.a, h.a, sizeof(h.a));
+        for (int j = 0; j <= kBatchMaxM; ++j)
+          f.cpp[j] = static_cast<T>(j <= 1 ? 0.0 : (j == 2 ? 2.0 * h.c1 : h.c1));
         std::memcpy(f.qtab, h.qtab, sizeof(h.qtab));
         fprefix[r + 1] = fprefix[r] + static_cast<int64_t>(f.tiles_x) * f.tiles_y;
         const int passes = (h.m + S - 1) / S;
@@ -1127,6 +1143,7 @@ int32_t batch_create_impl(expw_op* const* ops, int n, const int32_t* m, const do
       b->off_fshots = b->off_prefix_rec + align_up((n + 1) * sizeof(int64_t));
       b->off_fprefix = b->off_fshots + align_up(n * sizeof(FusedShot<T>));
       b->off_sync = b->off_fprefix + align_up((n + 1) * sizeof(int64_t));
+      b->off_qstep = b->off_sync + align_up(sizeof(BatchSync));
       if (fprefix[n] > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "batch too large for one launch");
       if (hipMemcpyAsync(t + b->off_fshots, fb.data(), fb.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
           hipMemcpyAsync(t + b->off_fprefix, fprefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
@@ -1169,7 +1186,8 @@ int32_t batch_enqueue(expw_batch* b, int64_t count, bool capturing) {
         const int64_t* prp = prefix_rec;
         const BatchClock* ckp = clk;
         int64_t stv = st;
-        void* args[] = {&fsp, &fpp, &shp, &prp, &pa, &ckp, &stv, &bs};
+        T* qsp = reinterpret_cast<T*>(t + b->off_qstep);
+        void* args[] = {&fsp, &fpp, &shp, &prp, &pa, &ckp, &stv, &bs, &qsp};
         const void* fn = b->depth == 2 ? reinterpret_cast<const void*>(k_faber_batch_persistent<T, 2>)
                          : b->depth == 4 ? reinterpret_cast<const void*>(k_faber_batch_persistent<T, 4>)
                                          : reinterpret_cast<const void*>(k_faber_batch_persistent<T, 6>);
@@ -1180,15 +1198,18 @@ int32_t batch_enqueue(expw_batch* b, int64_t count, bool capturing) {
       if (b->fused) {
         const auto* fshots = reinterpret_cast<const FusedShot<T>*>(t + b->off_fshots);
         const auto* fprefix = reinterpret_cast<const int64_t*>(t + b->off_fprefix);
+        T* qstep = reinterpret_cast<T*>(t + b->off_qstep);
+        k_batch_source_q<T><<<(b->n + 63) / 64, 64, 0, b->stream>>>(fshots, b->n, clk, st, qstep);
+        if (int32_t rc = check_launch("batch source scalars")) return rc;
         for (int p = 0; p < b->max_passes; ++p) {
           const int np = b->count_pass[p];
           const unsigned grid = static_cast<unsigned>(b->fprefix[np]);
           if (b->depth == 2)
-            k_faber_fused2d_batch<T, 2><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, clk, st);
+            k_faber_fused2d_batch<T, 2><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, qstep);
           else if (b->depth == 4)
-            k_faber_fused2d_batch<T, 4><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, clk, st);
+            k_faber_fused2d_batch<T, 4><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, qstep);
           else
-            k_faber_fused2d_batch<T, 6><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, clk, st);
+            k_faber_fused2d_batch<T, 6><<<grid, kFusedNT, 0, b->stream>>>(fshots, fprefix, np, p, qstep);
           if (int32_t rc = check_launch("batch fused pass")) return rc;
         }
         for (size_t i = 0; i < b->copy_dst.size(); ++i) {

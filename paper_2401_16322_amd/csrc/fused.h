@@ -18,10 +18,11 @@
 // partial sum, i.e. 19 words per point per pass instead of 16 per term for
 // one-term sweeps.
 //
-// Every term is computed from the stored values with the difference sums in
-// T (integer weights) and the rest in FP64 (see apply_point_m), and kept in
-// LDS in the storage precision T; the partial sum is FP64 (in LDS and
-// between passes), and the last pass rounds it to T once (see FaberTerm).
+// Every term is computed entirely in T as in the row-streamed passes
+// (stream2d.h): the difference sums over the integer weights, kappa =
+// wscale / gamma, c0 and c1 exact in T on the step's ellipse, the damping
+// scaled by 1 / wscale; the partial sum is FP64 (in LDS and between passes),
+// and the last pass rounds it to T once.
 //
 // Tiles are mapped to workgroups so that each XCD (block id mod 8) owns a
 // band of tile columns walked row by row: halo rows shared by neighbouring
@@ -47,10 +48,12 @@ struct FusedTile {
 
 template <typename T, int S>
 struct FusedArgs {
-  double inv_gamma, c0, a_first;
+  T kappa, c0, inv_ws;  // wscale / gamma, c0, 1 / wscale
+  double a_first;
   int32_t first;  // first pass of a step: acc = a_first * v0, no v_{j-2}
   int32_t tiles_x, tiles_y, band_w;
-  double a[S], cpp[S], q[S];
+  double a[S];
+  T cpp[S], q[S];
   RecRun<T> rec;  // receivers recorded from the sum (last pass of a step only)
 };
 
@@ -99,10 +102,11 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
   const int lx = X0 + lane;
   const int gx = x0 + lx;
   const int dx = lx < H ? H - lx : (lx >= H + TX ? lx - (H + TX - 1) : 0);
+  const T iws = c.inv_ws;
   const T sxi = (gx >= 0 && gx < nx) ? g.sint[0][gx] : T(0);
-  const T sxh = (gx >= 0 && gx < nx) ? g.shalf[0][gx] : T(0);
+  const T sxh_s = ((gx >= 0 && gx < nx) ? g.shalf[0][gx] : T(0)) * iws;
   int last[NSL];  // last term that needs the point (-1: outside the domain)
-  T old[NSL][3], cc2[NSL], sp[NSL], szh[NSL], amp[NSL], nv[NSL][3];
+  T old[NSL][3], cc2[NSL], sp[NSL], szh[NSL], amp[NSL], nv[NSL][3];  // sp, szh: scaled by 1 / wscale
 #pragma unroll
   for (int i = 0; i < NSL; ++i) {
     const int ly = X0 + wave + 16 * i;
@@ -118,8 +122,8 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
     old[i][2] = rd ? vpp[2 * N + gi] : T(0);
     cc2[i] = in ? g.c2[gi] : T(0);
     const T szi = in ? g.sint[1][gz] : T(0);
-    szh[i] = in ? g.shalf[1][gz] : T(0);
-    sp[i] = sxi + szi;
+    szh[i] = (in ? g.shalf[1][gz] : T(0)) * iws;
+    sp[i] = sxi * iws + szi * iws;
     // sum of the source amplitudes at this point
     T am = T(0);
     if (in && src.n > 0 && gi >= src.lo && gi <= src.hi)
@@ -157,15 +161,15 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
 #pragma unroll
   for (int r = 0; r < S; ++r) {
     if (r < r0) continue;  // block-uniform
-    const double cpp = c.cpp[r];
-    const double qr = c.q[r];
+    const T cpp = c.cpp[r];
+    const T qr = c.q[r];
+    const T kap = c.kappa, cz = c.c0;
 #pragma unroll
     for (int i = 0; i < NSL; ++i) {
       if (r <= last[i]) {
         const int l = (X0 + wave + 16 * i) * EX + lx;
         const T pc = cp[l], vxc = cvx[l], vzc = cvz[l];
-        // difference sums with the integer weights in T, the rest in FP64
-        // (see apply_point_m)
+        // difference sums over the integer weights; the term in T
         T dvx = T(0), dvz = T(0), dpx = T(0), dpz = T(0);
 #pragma unroll
         for (int q = 1; q <= K; ++q) {
@@ -175,15 +179,12 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
           dpx += wq * (cp[l + q] - cp[l + 1 - q]);
           dpz += wq * (cp[l + q * EX] - cp[l + (1 - q) * EX]);
         }
-        const double ws = g.wscale;
-        const double hp = -static_cast<double>(cc2[i]) * (static_cast<double>(dvx + dvz) * ws) -
-                          static_cast<double>(sp[i]) * pc;
-        const double hvx = -static_cast<double>(dpx) * ws - static_cast<double>(sxh) * vxc;
-        const double hvz = -static_cast<double>(dpz) * ws - static_cast<double>(szh[i]) * vzc;
-        nv[i][0] = static_cast<T>(hp * c.inv_gamma - c.c0 * pc - cpp * static_cast<double>(old[i][0]) +
-                                  qr * static_cast<double>(amp[i]));
-        nv[i][1] = static_cast<T>(hvx * c.inv_gamma - c.c0 * vxc - cpp * static_cast<double>(old[i][1]));
-        nv[i][2] = static_cast<T>(hvz * c.inv_gamma - c.c0 * vzc - cpp * static_cast<double>(old[i][2]));
+        const T hp = -cc2[i] * (dvx + dvz) - sp[i] * pc;
+        const T hvx = -dpx - sxh_s * vxc;
+        const T hvz = -dpz - szh[i] * vzc;
+        nv[i][0] = kap * hp - cz * pc - cpp * old[i][0] + qr * amp[i];
+        nv[i][1] = kap * hvx - cz * vxc - cpp * old[i][1];
+        nv[i][2] = kap * hvz - cz * vzc - cpp * old[i][2];
         // v_{j-1} at the point becomes the next term's v_{j-2}
         old[i][0] = pc;
         old[i][1] = vxc;
@@ -288,18 +289,19 @@ template <typename T, int S, int K>
 int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                      const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
                      double* acc_out, T* state_out, int j, bool first, const double* a,
-                     const double* q, double gamma, double c0, double c1, RecRun<T> rec) {
+                     const double* q, double kappa, double inv_ws, double c0, double c1, RecRun<T> rec) {
   FusedArgs<T, S> c{};
   c.rec = rec;
-  c.inv_gamma = 1.0 / gamma;
-  c.c0 = c0;
+  c.kappa = static_cast<T>(kappa);
+  c.inv_ws = static_cast<T>(inv_ws);
+  c.c0 = static_cast<T>(c0);
   c.first = first ? 1 : 0;
   if (first) c.a_first = a[0];
   for (int r = 0; r < S; ++r) {
     const int jj = j + r;
     c.a[r] = a[jj];
-    c.cpp[r] = jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1);
-    c.q[r] = q[jj - 1];
+    c.cpp[r] = static_cast<T>(jj == 1 ? 0.0 : (jj == 2 ? 2.0 * c1 : c1));
+    c.q[r] = static_cast<T>(q[jj - 1]);
   }
   constexpr int TX = FusedTile<S, K>::TX, TY = FusedTile<S, K>::TY;
   const int tx = static_cast<int>((g.n[0] + TX - 1) / TX);
@@ -325,11 +327,11 @@ template <typename T, int K>
 int32_t launch_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                     const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
                     double* acc_out, T* state_out, int j, bool first, const double* a,
-                    const double* q, double gamma, double c0, double c1, RecRun<T> rec) {
+                    const double* q, double kappa, double inv_ws, double c0, double c1, RecRun<T> rec) {
 #define EXPW_PASS(S_)                                                                          \
   case S_:                                                                                     \
     return launch_fused<T, S_, K>(st, prof, g, src, vp, vpp, acc_in, out_last, out_prev,      \
-                                  acc_out, state_out, j, first, a, q, gamma, c0, c1, rec);
+                                  acc_out, state_out, j, first, a, q, kappa, inv_ws, c0, c1, rec);
   if constexpr (sizeof(T) == 4 && K == 2) {
     switch (n) {
       EXPW_PASS(2) EXPW_PASS(3) EXPW_PASS(4) EXPW_PASS(5) EXPW_PASS(6) EXPW_PASS(7) EXPW_PASS(8)
