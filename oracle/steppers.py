@@ -163,6 +163,36 @@ def krylov_step(prob, U, t, dt, k, p=8):
     return beta * out[: prob.grid.nstate]
 
 
+def krylov_step_estimate(prob, U, t, dt, k, p=8):
+    """(the Krylov step of dimension k, its a-posteriori error estimate).
+
+    With u_k(s) = beta V_k exp(s H_k) e_1, the Arnoldi relation gives the
+    residual of the projected flow r(s) = H~ u_k(s) - u_k'(s)
+    = beta h_{k+1,k} (e_k^T exp(s H_k) e_1) q_{k+1}; the step's error is
+    int_0^dt exp((dt - s) H~) r(s) ds, and the estimate is the norm of
+    int_0^dt r(s) ds = dt beta h_{k+1,k} |e_k^T phi_1(dt H_k) e_1| q_{k+1},
+    phi_1(z) = (e^z - 1)/z (Saad, 1992; the paper gives none). phi_1(A) e_1 is
+    the upper right column of exp([[A, e_1], [0, 0]]). Zero after a breakdown
+    (k_eff < k: the space is invariant)."""
+    G = prob.src.w_columns(t, p) if prob.src is not None else None
+    x = _augment(prob, U, p)
+    beta, Q, Hm, k_eff = arnoldi(prob, x, G, k)
+    if k_eff == 0:
+        return np.zeros(prob.grid.nstate), 0.0
+    y = expm(dt * Hm[:k_eff, :k_eff])[:, 0]
+    out = np.zeros_like(x)
+    for i in range(k_eff):
+        out += y[i] * Q[i]
+    est = 0.0
+    if k_eff == k:
+        Z = np.zeros((k + 1, k + 1))
+        Z[:k, :k] = dt * Hm[:k, :k]
+        Z[0, k] = 1.0
+        phi = expm(Z)[:k, k]
+        est = dt * beta * Hm[k, k - 1] * abs(phi[k - 1])
+    return beta * out[: prob.grid.nstate], float(est)
+
+
 def rk4_step(prob, U, t, dt):
     """Classical four-stage, fourth-order Runge-Kutta step of U' = H U + s(t)."""
     k1 = prob.H(U) + prob.forcing(t)

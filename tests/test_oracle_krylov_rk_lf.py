@@ -171,3 +171,56 @@ def test_leapfrog_second_order_with_damping_and_source():
         U, _, _ = run(prob, "leapfrog", U0, 0.0, T / ns, ns)
         errs.append(np.linalg.norm(split_state(prob.grid, U)[0] - split_state(prob.grid, Ue)[0]))
     assert abs(np.log2(errs[0] / errs[1]) - 2.0) < 0.3
+
+
+# ------------------------------------------------- Krylov error estimate
+
+def test_krylov_estimate_is_the_integrated_residual_of_the_projected_flow():
+    """The estimate equals |int_0^dt (H~ u_k(s) - u_k'(s)) ds| for
+    u_k(s) = beta V_k exp(s H_k) e_1, the integral by Gauss-Legendre
+    quadrature of residuals formed with the operator itself (augmented
+    vector, with a source)."""
+    from oracle.steppers import krylov_step_estimate
+    prob = _problem()
+    p, t, dt, k = 8, 0.04, 2e-3, 6
+    U0 = smooth_state(prob.grid.n, seed=8, width_cells=2.0)
+    G = prob.src.w_columns(t, p)
+    x = np.concatenate([U0, e_p(p)])
+    beta, Q, Hm, k_eff = arnoldi(prob, x, G, k)
+    assert k_eff == k
+    Vk = np.array(Q[:k]).T
+    xs, ws = np.polynomial.legendre.leggauss(20)
+    integral = np.zeros_like(x)
+    for xq, wq in zip(xs, ws):
+        s_ = 0.5 * dt * (xq + 1.0)
+        E = expm(s_ * Hm[:k, :k])[:, 0]
+        u = beta * Vk @ E
+        du = beta * Vk @ (Hm[:k, :k] @ E)
+        integral += 0.5 * dt * wq * (apply_Htilde(prob, u, G) - du)
+    U1, est = krylov_step_estimate(prob, U0, t, dt, k, p=p)
+    assert est == pytest.approx(np.linalg.norm(integral), rel=1e-8)
+    assert np.array_equal(U1, krylov_step(prob, U0, t, dt, k, p=p))
+
+
+def test_krylov_estimate_tracks_the_error_and_vanishes_on_breakdown():
+    """Against the dense exponential: the estimate falls with k and stays
+    within a factor 2 of the true error while that is above rounding; it is
+    at rounding level once the Krylov space is the whole space."""
+    from oracle.steppers import krylov_step_estimate
+    prob = _problem(with_source=False)
+    U0 = smooth_state(prob.grid.n, seed=9, width_cells=2.0)
+    for dt in (1e-3, 3e-3):
+        Ue = expm(dt * assemble_H(prob.grid, prob.c2).toarray()) @ U0
+        prev = np.inf
+        for k in (2, 4, 6, 8, 10, 12):
+            Uk, est = krylov_step_estimate(prob, U0, 0.0, dt, k)
+            err = np.linalg.norm(Uk - Ue)
+            assert est < prev
+            prev = est
+            if err > 1e-11 * np.linalg.norm(Ue):
+                assert err / 2 <= est <= err * 2, (dt, k, est, err)
+    g = Grid((3, 3), 10.0, 4, abc_cells=1, sigma_max=300.0)
+    small = Problem(g, layered_velocity(g.n, 10.0, seed=2) ** 2, None)
+    U0 = smooth_state(g.n, seed=7, width_cells=1.0)
+    _, est = krylov_step_estimate(small, U0, 0.0, 5e-3, g.nstate + 2)
+    assert est <= 1e-13 * np.linalg.norm(U0)
