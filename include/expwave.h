@@ -438,6 +438,19 @@ int32_t expw_set_guard(expw_op* op, int32_t on);
  * Arnoldi kernel (neither the k x k exponential nor the combination uses it)
  * and is not read. */
 int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta);
+/* A-posteriori error estimate of Krylov steps (Sec. 3.2, Krylov subspace
+ * projection; the estimate itself is not in the paper). With on != 0, every
+ * later expw_step_krylov step forms
+ *   est = dt beta h_{k+1,k} |e_k^T phi_1(dt H_k) e_1|, phi_1(z) = (e^z - 1)/z,
+ * the norm of the projected flow's residual integrated over the step (the
+ * step's error is that residual propagated by exp((dt - s) H~)); 0 after a
+ * breakdown (k_eff < k). It costs the last column's orthogonalization and
+ * norm, and the small exponential then runs on the host (one synchronization
+ * per step). expw_krylov_estimate returns the largest estimate over the steps
+ * of the last expw_step_krylov call, or EXPW_EINVAL if that call ran without
+ * the estimate. */
+int32_t expw_set_krylov_estimate(expw_op* op, int32_t on);
+int32_t expw_krylov_estimate(const expw_op* op, double* est);
 
 /* Where the Krylov step evaluates y = exp(dt H_k) e_1 (Sec. 3.2: the small
  * Hessenberg exponential), both in FP64:

@@ -297,6 +297,7 @@ struct ArnArgs {
   double tail2;  // |e_p|^2: 1 with a source, else 0
   double tol;
   unsigned spin_limit;
+  int32_t full_last;  // 1: orthogonalize and normalize the last column too (h_{k,k-1} for an estimate)
 };
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -596,10 +597,10 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       }
     }
     __syncthreads();
-    // the last column's orthogonalized vector would only give h_{k,k-1} and
-    // Q_k, which neither the exponential of the k x k matrix H_k nor the
-    // combination of Q_0..Q_{k-1} uses
-    if (j + 1 == a.k) break;
+    // the last column's orthogonalized vector only gives h_{k,k-1} and Q_k,
+    // which neither the exponential of the k x k matrix H_k nor the
+    // combination of Q_0..Q_{k-1} uses; only an error estimate needs h_{k,k-1}
+    if (j + 1 == a.k && !a.full_last) break;
     // second sweep: w -= h_i q_i in order i = 0..j, then |w|^2
     {
       const T h0 = static_cast<T>(s_h[0]);

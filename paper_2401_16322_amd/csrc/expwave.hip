@@ -71,6 +71,9 @@ struct expw_op {
   int arn_nvmax_clean;  // reduction area consistent for this nvmax (0: fill before the next launch)
   int last_keff;
   double last_beta;
+  bool kry_estimate;    // form the a-posteriori estimate of each Krylov step
+  bool last_est_valid;  // the last Krylov call formed it
+  double last_est;      // the largest estimate over that call's steps
   char* noalloc_scratch;  // device address of the static scratch on the creating device
   expw::Profiler prof;
 };
@@ -635,8 +638,9 @@ template <typename T, int K, int BC, int DIM>
 int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T* S, T* Q,
                            const KrySrc& ks, const T* amp, int64_t ns, int64_t naug, int64_t ld,
                            int k, double tail2, double tol, unsigned long long* slots, int* err,
-                           double* hess, double* sc, double* beta_out) {
+                           double* hess, double* sc, double* beta_out, bool full_last) {
   ArnArgs aa{};
+  aa.full_last = full_last ? 1 : 0;
   aa.ns = ns;
   aa.naug = naug;
   aa.ld = ld;
@@ -747,6 +751,11 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
   int* kry_err = kry_keff + 8;
   const int unp = persistent_un<T, K, BC, DIM>(op, naug);
   const double tol = 1e-14;
+  // the a-posteriori estimate needs h_{k,k-1} and phi_1(dt H_k) e_1: the last
+  // column is completed and the small exponential runs on the host
+  const bool est_on = op->kry_estimate;
+  op->last_est = 0.0;
+  op->last_est_valid = est_on;
   std::vector<double> hh((EXPW_MAX_KRYLOV + 1) * kHessLd), hk(k * k), E(k * k), der(EXPW_MAX_TAYLOR);
   std::vector<double> scal_h(2);
   KrySrc ks{};
@@ -766,7 +775,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
       // the whole Arnoldi process in one cooperative launch
       int32_t rc = arnoldi_persistent<T, K, BC, DIM>(op, unp, g, S, Q, ks, amp, ns, naug, ld, k,
                                                      p > 0 ? 1.0 : 0.0, tol, kry_slots, kry_err,
-                                                     hess, kry_sc, scal + 1);
+                                                     hess, kry_sc, scal + 1, est_on);
       if (rc != EXPW_OK) return rc;
     } else {
       int32_t rc = arnoldi_launches<T, K, BC, DIM, false>(op, g, S, Q, ld, ns, naug, ks, amp, k, tol, part, hess, scal + 1, kry_sc);
@@ -775,7 +784,7 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
     int32_t rc = check_launch("arnoldi");
     if (rc != EXPW_OK) return rc;
     RecRun<T> rr{nullptr, 0, 0};  // set when the combination records the receivers
-    if (op->kry_mode == EXPW_EXPM_DEVICE) {
+    if (op->kry_mode == EXPW_EXPM_DEVICE && !est_on) {
       // y = exp(dt H_k) e_1 and the combination without leaving the device
       launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, expm_kernel(k), dim3(1), dim3(expm_threads(k)), hess, k, dt, tol, scal + 1, kry_y, kry_keff);
       rr = rec_run(op, traces, st);
@@ -803,12 +812,21 @@ int32_t krylov_impl(expw_op* op, T* S, double t0, double dt, int k, int64_t nste
         // zero state and no source: the state stays zero
       } else {
         op->last_keff = keff;
-        // only the upper Hessenberg part is written by the kernels
+        // only the upper Hessenberg part is written by the kernels; with the
+        // estimate, exp([[dt H_k, e_1], [0, 0]]) gives exp(dt H_k) e_1 (first
+        // column) and phi_1(dt H_k) e_1 (last column)
+        const bool est_here = est_on && keff == k;
+        const int nz = est_here ? k + 1 : keff;
+        hk.assign(static_cast<size_t>(nz) * nz, 0.0);
+        E.resize(static_cast<size_t>(nz) * nz);
         for (int r = 0; r < keff; ++r)
-          for (int c = 0; c < keff; ++c) hk[r * keff + c] = (r <= c + 1) ? dt * hh[r * kHessLd + c] : 0.0;
-        if (!expm(keff, hk.data(), E.data())) return fail(EXPW_ENONFINITE, "krylov: non-finite Hessenberg matrix");
+          for (int c = 0; c < keff; ++c) hk[r * nz + c] = (r <= c + 1) ? dt * hh[r * kHessLd + c] : 0.0;
+        if (est_here) hk[0 * nz + k] = 1.0;
+        if (!expm(nz, hk.data(), E.data())) return fail(EXPW_ENONFINITE, "krylov: non-finite Hessenberg matrix");
         KryCoef y{};
-        for (int r = 0; r < keff; ++r) y.y[r] = E[r * keff + 0];
+        for (int r = 0; r < keff; ++r) y.y[r] = E[r * nz + 0];
+        if (est_here)
+          op->last_est = std::max(op->last_est, dt * beta * hh[k * kHessLd + (k - 1)] * std::fabs(E[(k - 1) * nz + k]));
         launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (keff + 1.0) * ns * es, k_kry_combine<T>, dim3(red_grid_for(ns)), dim3(kBlock), S, Q, ld, ns, keff, y, beta, kry_sc);
         if ((rc = check_launch("krylov combine")) != EXPW_OK) return rc;
       }
@@ -1437,6 +1455,9 @@ int32_t expw_op_create_profiles(const expw_grid* g, const void* c2_dev,
   op->arn_nvmax_clean = 0;
   op->last_keff = 0;
   op->last_beta = 0.0;
+  op->kry_estimate = false;
+  op->last_est_valid = false;
+  op->last_est = 0.0;
   // the allocation-free Faber entry point's buffers on this device (resolved
   // here, once per device, with the device current)
   op->noalloc_scratch = noalloc_scratch_on_current_device();
@@ -2118,6 +2139,21 @@ int32_t expw_krylov_info(const expw_op* op, int32_t* k_eff, double* beta) {
     return fail(EXPW_EDEVICE, "krylov info: copy failed");
   *k_eff = ke;
   *beta = b;
+  return EXPW_OK;
+}
+
+int32_t expw_set_krylov_estimate(expw_op* op, int32_t on) {
+  if (int32_t rc = check_op(op)) return rc;
+  op->kry_estimate = on != 0;
+  return EXPW_OK;
+}
+
+int32_t expw_krylov_estimate(const expw_op* op, double* est) {
+  if (int32_t rc = check_op(op)) return rc;
+  if (!est) return fail(EXPW_EINVAL, "NULL output");
+  if (!op->last_est_valid)
+    return fail(EXPW_EINVAL, "the last Krylov call ran without the estimate (expw_set_krylov_estimate)");
+  *est = op->last_est;
   return EXPW_OK;
 }
 

@@ -97,6 +97,8 @@ SIGNATURES = {
     "expw_batch_capture": (_i32, [_vp, _i64]),
     "expw_batch_destroy": (_i32, [_vp]),
     "expw_batch_set_persistent": (_i32, [_vp, _i32]),
+    "expw_set_krylov_estimate": (_i32, [_vp, _i32]),
+    "expw_krylov_estimate": (_i32, [_vp, ctypes.POINTER(_dbl)]),
     "expw_step_krylov": (_i32, [_vp, _vp, _dbl, _dbl, _i32, _i64, _vp]),
     "expw_step_rk4": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
     "expw_step_leapfrog": (_i32, [_vp, _vp, _dbl, _dbl, _i64, _vp]),
@@ -425,6 +427,16 @@ def expw_batch_set_persistent(batch, on):
     _check(load().expw_batch_set_persistent(batch, 1 if on else 0))
 
 
+def expw_set_krylov_estimate(op, on):
+    _check(load().expw_set_krylov_estimate(op, 1 if on else 0))
+
+
+def expw_krylov_estimate(op):
+    est = _dbl(0.0)
+    _check(load().expw_krylov_estimate(op, ctypes.byref(est)))
+    return est.value
+
+
 def expw_step_krylov(op, state_ptr, t0, dt, k, nsteps, traces_ptr=None):
     _check(load().expw_step_krylov(op, state_ptr, t0, dt, k, nsteps, traces_ptr))
 
@@ -626,6 +638,16 @@ class Operator:
         expw_faber_adjoint_step(self.op, u.data_ptr(), lam.data_ptr(), t, dt, m, grad.data_ptr(),
                                 terms.data_ptr() if m > 1 else None)
         return lam
+
+    def set_krylov_estimate(self, on=True):
+        """Form the a-posteriori error estimate of every later Krylov step."""
+        expw_set_krylov_estimate(self.op, on)
+
+    def krylov_estimate(self):
+        """Largest error estimate over the steps of the last step_krylov call
+        (dt beta h_{k+1,k} |e_k^T phi_1(dt H_k) e_1|)."""
+        self._sync_stream()
+        return expw_krylov_estimate(self.op)
 
     def krylov_adjoint_step(self, u, lam, t, dt, k, grad, basis=None):
         """lam <- the Krylov approximation (dimension k) of exp(dt H^T) lam in

@@ -592,3 +592,51 @@ def test_caller_damping_profiles_match_oracle(dtype, n):
         Uref, _, _ = run(prob, method, U0, 0.04, 2e-3, 3, **kw)
         assert rel_l2(U.cpu().numpy(), Uref) <= TOL[dtype], method
     op.close()
+
+
+@pytest.mark.parametrize("path", ["persistent", "launches"])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("k", [4, 8, 16])
+def test_krylov_error_estimate_matches_oracle(dtype, k, path):
+    """The a-posteriori estimate of one Krylov step (with a source) against
+    the oracle's: FP64 to 1e-8 relative; FP32 to 1e-2 where the estimate is
+    above the FP32 rounding of the basis (1e-5 of the state), else below
+    that level. The step itself still matches the oracle."""
+    from paper_2401_16322_amd.expwave import ExpwError
+    from oracle.steppers import krylov_step_estimate
+    case = make_case((70, 45), dtype, seed=81, n_src=1, max_k=k)
+    case.op.set_krylov_persistent(path == "persistent")
+    U = to_dev(case, case.U0)
+    case.op.step_krylov(U, 0.05, 2e-3, k, 1)
+    with pytest.raises(ExpwError):
+        case.op.krylov_estimate()
+    case.op.set_krylov_estimate(True)
+    U = to_dev(case, case.U0)
+    case.op.step_krylov(U, 0.05, 2e-3, k, 1)
+    est = case.op.krylov_estimate()
+    Uref, eref = krylov_step_estimate(case.prob, case.U0, 0.05, 2e-3, k, p=case.p)
+    assert rel_l2(U.cpu().numpy(), Uref) <= TOL[dtype]
+    print(f"krylov estimate {dtype} k={k} {path}: {est:.6e} oracle {eref:.6e}")
+    if dtype == "float64":
+        assert est == pytest.approx(eref, rel=1e-8)
+    elif eref >= 1e-5 * np.linalg.norm(Uref):
+        assert est == pytest.approx(eref, rel=1e-2)
+    else:
+        assert est <= 1e-4 * np.linalg.norm(Uref)
+
+
+def test_krylov_error_estimate_is_the_largest_over_the_steps():
+    """Three steps in one call: the reported estimate is the largest of the
+    oracle's three per-step estimates (FP64)."""
+    from oracle.steppers import krylov_step_estimate
+    case = make_case((60, 40), "float64", seed=82, n_src=1, max_k=8)
+    case.op.set_krylov_estimate(True)
+    U = to_dev(case, case.U0)
+    case.op.step_krylov(U, 0.04, 3e-3, 8, 3)
+    est = case.op.krylov_estimate()
+    Ur, ests = case.U0, []
+    for n in range(3):
+        Ur, e = krylov_step_estimate(case.prob, Ur, 0.04 + n * 3e-3, 3e-3, 8, p=case.p)
+        ests.append(e)
+    assert rel_l2(U.cpu().numpy(), Ur) <= 1e-11
+    assert est == pytest.approx(max(ests), rel=1e-8)
