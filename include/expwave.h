@@ -197,8 +197,8 @@ int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
 
 /* Kernel tuning for the Faber step: fuse = recurrence terms per HBM sweep
  * (0 = automatic, 1 = one term per sweep, up to 8 accepted). 2D order 4:
- * up to 6 terms at FP32 and 4 at FP64, automatic = 4 (6 at FP32 where the
- * tiled passes run, see expw_set_pass_kernel); 2D order 8: up to 4,
+ * up to 6 terms at FP32 and 4 at FP64, automatic = 6 at FP32 and 4 at FP64;
+ * 2D order 8: up to 4,
  * automatic = 3; 3D FP32 order 4: two terms unless fuse = 1; 3D FP64: one
  * term per sweep. Only zero ghosts fuse. Results do not depend on it beyond
  * rounding order. */

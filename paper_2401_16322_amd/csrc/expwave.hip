@@ -471,15 +471,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
   faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a);
   for (int j = 0; j < m; ++j) q[j] = 0.0;
   const int p = op->taylor_p;
-  int req = op->fuse;
-  if constexpr (K == 2 && BC == 0 && DIM == 2 && sizeof(T) == 4) {
-    // the tiled passes keep the FP64 sum of the tile in LDS: from 5 terms on,
-    // two workgroups fit a CU, so where they run they default to 6 terms
-    const bool streamed = op->pass_kernel == EXPW_PASS_STREAMED ||
-                          (op->pass_kernel == EXPW_PASS_AUTO && stream2d_fits(g.n[0], g.n[1], 4));
-    if (req == 0 && !streamed) req = 6;
-  }
-  const int fuse = fused_depth<T, K, BC, DIM>(req, m, g.N);
+  const int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m, g.N);
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     if (op->n_src > 0) {

@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kFusedNT, sizeof(T) == 4 ? 8 : 4) void k_faber_fuse
 }
 
 // Fusion depth actually used for a request (1 = unfused kernels): 2D order 4
-// with zero ghosts up to 6 (FP32) or 4 (FP64) terms, default 4; 2D order 8
+// with zero ghosts up to 6 (FP32) or 4 (FP64) terms, default 6 (FP32) or 4; 2D order 8
 // with zero ghosts up to 4 terms, default 3; 3D FP32 order 4 with zero ghosts
 // 2 terms unless fuse = 1 is asked for.
 template <typename T, int K, int BC, int DIM>
@@ -276,10 +276,11 @@ int fused_depth(int requested, int m, int64_t npts) {
   // term per sweep; FP64 runs one term per sweep (the two-term pass spills)
   if (DIM == 3) return (K == 2 && sizeof(T) == 4 && requested != 1 && m >= 2) ? 2 : 1;
   if (3 * npts >= (int64_t(1) << 31)) return 1;
-  // order 4: the row-streaming passes (stream2d.h), up to 6 terms at FP32 and
-  // 4 at FP64, default 4; order 8: the tiled passes, up to 4, default 3
+  // order 4: the row-streaming or tiled passes, up to 6 terms at FP32 and 4
+  // at FP64, default 6 (FP32) and 4 (FP64); order 8: the tiled passes, up to
+  // 4, default 3
   const int smax = (K == 2 && sizeof(T) == 4) ? 6 : 4;
-  int s = requested == 0 ? (K == 2 ? 4 : 3) : requested;
+  int s = requested == 0 ? (K == 2 ? (sizeof(T) == 4 ? 6 : 4) : 3) : requested;
   if (s > smax) s = smax;
   if (s > m) s = m;
   return s < 2 ? 1 : s;

@@ -312,12 +312,43 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
   }
 }
 
-// Rows per segment: enough workgroups to fill the chip (about 4 per CU),
-// at least 64 rows so the 4S-row warm-up stays small.
-inline int stream2d_zseg(int64_t nz, int bands) {
-  int zs = 256;
-  while (zs > 64 && static_cast<int64_t>(bands) * ((nz + zs - 1) / zs) < 1024) zs /= 2;
-  return zs;
+// Workgroups of a pass kernel resident on the device at once (CUs times the
+// occupancy of the kernel; 1024 when the runtime cannot say).
+template <typename T, int S, bool FIRST>
+int stream2d_capacity() {
+  static int cap = 0;  // per kernel, at first use
+  if (cap == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void*>(k_faber_stream2d<T, S, FIRST>), kStrNT, 0) == hipSuccess &&
+        cus > 0 && per > 0)
+      cap = cus * per;
+    else
+      cap = 1024;
+  }
+  return cap;
+}
+
+// Rows per segment. Every workgroup of a pass runs about as long (its rows
+// plus a warm-up of 2S rows), and the resident workgroups run in rounds, so
+// a pass takes about ceil(bands * segments / capacity) * (rows per segment +
+// 2S) row times: a second, nearly empty round costs as much as a full one.
+// The segment count (segments of 64 rows or more) minimizes that.
+inline int stream2d_zseg(int64_t nz, int bands, int capacity, int S) {
+  const int64_t smax = nz / 64 > 1 ? nz / 64 : 1;
+  int64_t best_segs = 1, best_cost = -1;
+  for (int64_t segs = 1; segs <= smax; ++segs) {
+    const int64_t zs = (nz + segs - 1) / segs;
+    const int64_t rounds = (static_cast<int64_t>(bands) * segs + capacity - 1) / capacity;
+    const int64_t cost = rounds * (zs + 2 * S);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best_segs = segs;
+    }
+  }
+  return static_cast<int>((nz + best_segs - 1) / best_segs);
 }
 
 template <typename T, int S>
@@ -340,7 +371,7 @@ int32_t launch_stream2d(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, S
     c.q[r] = static_cast<T>(qv[jj - 1]);
   }
   c.bands = static_cast<int>((g.n[0] + W - 1) / W);
-  c.zseg = stream2d_zseg(g.n[1], c.bands);
+  c.zseg = stream2d_zseg(g.n[1], c.bands, first ? stream2d_capacity<T, S, true>() : stream2d_capacity<T, S, false>(), S);
   const int64_t blocks = static_cast<int64_t>(c.bands) * ((g.n[1] + c.zseg - 1) / c.zseg);
   if (blocks > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "streamed Faber pass: grid too large");
   // the source term of a level is q_r amp: src.q is set to 1 so that
