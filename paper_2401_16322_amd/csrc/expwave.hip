@@ -2310,10 +2310,12 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
     // FP32: 1024-thread blocks on 64 x 32 tiles; FP64 (more registers): 256 on 64 x 16
     constexpr int NT = sizeof(T) == 4 ? 1024 : 256, TY = sizeof(T) == 4 ? 32 : 16;
     const int ptx = static_cast<int>((g.nx + kPmlTX - 1) / kPmlTX);
-    const unsigned pgrid = static_cast<unsigned>(ptx * ((g.ny + TY - 1) / TY));
+    const int pty = static_cast<int>((g.ny + TY - 1) / TY);
+    const int pbw = (ptx + 7) / 8;
+    const unsigned pgrid = 8u * static_cast<unsigned>(pbw) * static_cast<unsigned>(pty);
     k_pml_faber_pair_lds<T, NT, TY><<<pgrid, NT, 0, op->stream>>>(g, vp, vpp, o0, o1, j == 1 ? nullptr : C, acc_out,
                                                                   t0, t1, make_pml_src<T>(op, q[j - 1]),
-                                                                  make_pml_src<T>(op, q[j]), ptx);
+                                                                  make_pml_src<T>(op, q[j]), ptx, pty, pbw);
     if (int32_t rc = check_launch("pml faber pair")) return rc;
     if (last && acc_out == C) {
       if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
@@ -2352,11 +2354,12 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   const int p = op->taylor_p;
   const double sc = 1.0 / (op->g.h * op->g.h);
   const int tiles_x = static_cast<int>((op->g.nx + kPmlTX - 1) / kPmlTX);
-  const int64_t tiles = tiles_x * ((op->g.ny + kPmlTY - 1) / kPmlTY);
+  const int tiles_y = static_cast<int>((op->g.ny + kPmlTY - 1) / kPmlTY);
+  const int band_w = (tiles_x + 7) / 8;
   const int path = pml_path_for(op, m);
   const bool pairs = path == 3;
   const bool lds = path >= 2;
-  const unsigned grid = lds ? static_cast<unsigned>(tiles) : grid_for(g.N);
+  const unsigned grid = lds ? 8u * static_cast<unsigned>(band_w) * static_cast<unsigned>(tiles_y) : grid_for(g.N);
   T* D = C + ns;
   T* E = D + ns;
   // one term: the LDS kernel on tiles or one thread per node
@@ -2364,7 +2367,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
                   double qj) {
     if (lds)
       k_pml_faber_term_lds<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, c,
-                                                               make_pml_src<T>(op, qj), tiles_x);
+                                                               make_pml_src<T>(op, qj), tiles_x, tiles_y, band_w);
     else
       k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, c,
                                                            make_pml_src<T>(op, qj));

@@ -157,22 +157,35 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term(PmlGeo<T> g, const T*
 
 // The same term with the stencil operands staged in LDS (the path for grids
 // with many tiles).
-// tiles_x = ceil(nx / 64); one block per 64 x 16 tile, blocks in row-major
-// tile order. vout may alias vpp and acc_out may alias acc_in or vpp; vp is
+// XCD-aware tile order of the tiled PML kernels: workgroup b runs on XCD
+// b mod 8, which owns a band of band_w = ceil(tiles_x / 8) tile columns
+// walked row by row, so the tiles beside and below a tile run on the same
+// XCD at about the same time and their shared halo reaches its L2. The grid
+// is 8 band_w tiles_y workgroups; false for the workgroups past the last
+// column.
+__device__ __forceinline__ bool pml_band_tile(int tiles_x, int tiles_y, int band_w, int& tx0, int& ty0) {
+  const int b = static_cast<int>(blockIdx.x), kk = b >> 3;
+  ty0 = kk / band_w;
+  tx0 = (b & 7) * band_w + (kk - ty0 * band_w);
+  return tx0 < tiles_x && ty0 < tiles_y;
+}
+
+// tiles_x = ceil(nx / 64); one block per 64 x 16 tile, in the band order above. vout may alias vpp and acc_out may alias acc_in or vpp; vp is
 // read with a halo and must not alias an output; vout == nullptr skips v_j.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, const T* vp, const T* vpp,
                                                                T* vout, const T* acc_in, T* acc_out,
                                                                PmlTerm<T> c, Src<T> src,
-                                                               int tiles_x) {
+                                                               int tiles_x, int tiles_y, int band_w) {
   static_assert(kBlock == 256 && kPmlTX == 64, "4 waves, one tile column per lane");
   constexpr int TX = kPmlTX, TY = kPmlTY, HL = kPmlHalo;
   constexpr int UX = TX + 2 * HL, UY = TY + 2 * HL;
   __shared__ T su[UY][UX];  // u at rows j0 - 4 .. j0 + 19, columns i0 - 4 .. i0 + 67
   __shared__ T sx[TY][UX];  // w_x at rows j0 .. j0 + 15, columns i0 - 4 .. i0 + 67
   __shared__ T sy[UY][TX];  // w_y at rows j0 - 4 .. j0 + 19, columns i0 .. i0 + 63
-  const int ty0 = static_cast<int>(blockIdx.x) / tiles_x;
-  const int i0 = (static_cast<int>(blockIdx.x) - ty0 * tiles_x) * TX, j0 = ty0 * TY;
+  int tx0, ty0;
+  if (!pml_band_tile(tiles_x, tiles_y, band_w, tx0, ty0)) return;
+  const int i0 = tx0 * TX, j0 = ty0 * TY;
   const T* u = vp;
   const T* wx = vp + 2 * g.N;
   const T* wy = vp + 3 * g.N;
@@ -229,7 +242,7 @@ __global__ __launch_bounds__(NT) void k_pml_faber_pair_lds(PmlGeo<T> g, const T*
                                                            T* out0, T* out1, const T* acc_in,
                                                            T* acc_out, PmlTerm<T> c0,
                                                            PmlTerm<T> c1, Src<T> s0, Src<T> s1,
-                                                           int tiles_x) {
+                                                           int tiles_x, int tiles_y, int band_w) {
   constexpr int TX = kPmlTX, NW = NT / 64;
   static_assert(NT % 64 == 0 && TY % NW == 0, "whole waves, each wave a set of tile rows");
   constexpr int AX = TX + 16, AY = TY + 16;  // tile grown by 8
@@ -239,8 +252,9 @@ __global__ __launch_bounds__(NT) void k_pml_faber_pair_lds(PmlGeo<T> g, const T*
   __shared__ T ax[BY][AX];   //          w_x on R1's rows, columns grown by 8
   __shared__ T ay[AY][BX];   //          w_y on R1's columns, rows grown by 8
   __shared__ T bu[BY][BX], bv[BY][BX], bx[BY][BX], by[BY][BX];  // v_j on R1
-  const int ty0 = static_cast<int>(blockIdx.x) / tiles_x;
-  const int i0 = (static_cast<int>(blockIdx.x) - ty0 * tiles_x) * TX, j0 = ty0 * TY;
+  int tx0, ty0;
+  if (!pml_band_tile(tiles_x, tiles_y, band_w, tx0, ty0)) return;
+  const int i0 = tx0 * TX, j0 = ty0 * TY;
   const T* u = vp;
   const T* v = vp + g.N;
   const T* wx = vp + 2 * g.N;
