@@ -18,6 +18,7 @@
 #include "expm_small.h"
 #include "fused.h"
 #include "fused3d.h"
+#include "gram.h"
 #include "internal.h"
 #include "kernels.h"
 #include "pml.h"
@@ -175,7 +176,12 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
   L.scal = off; off = align_up(off + 64 * sizeof(double));
   L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
   L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
-  L.bar = off; off = align_up(off + (kArnRecWords + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks) * sizeof(unsigned long long));  // grid reduction records and slots
+  // grid reduction records and slots of the persistent Arnoldi kernel; the
+  // launch-per-column Gram-Schmidt's partials and Gram table share the area
+  static_assert(static_cast<size_t>(kGramPartials) + kGramTot + 2 * EXPW_MAX_KRYLOV <=
+                    kArnRecWords + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks,
+                "Gram-Schmidt partials fit the reduction area");
+  L.bar = off; off = align_up(off + (kArnRecWords + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks) * sizeof(unsigned long long));
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -696,30 +702,39 @@ int32_t arnoldi_launches(expw_op* op, const Geo<T, K, DIM>& g, const T* S, T* Q,
   const unsigned nb_ns = red_grid_for(ns);
   launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, ns * es, k_norm2<T>, dim3(nb_ns), dim3(kBlock), S, ns, P[0]);
   launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, (ns + naug) * es, k_kry_init<T>, dim3(rg_vec), dim3(kBlock), S, ns, Q, naug, P[0], nb_ns, tail2, beta_out, sc);
-  // P[c] holds the partials of the latest reduction, produced by nin blocks
-  int c = 0, nin = 0;
+  // Gram-Schmidt in three launches per column (gram.h): the block partials
+  // and the Gram table use the grid-reduction area of the persistent kernel,
+  // which is filled again before its next launch; the scaled projections go
+  // to the y area of the small exponential (unused until the basis is done)
+  double* gpart = reinterpret_cast<double*>(op->ws + op->off_bar);
+  double* gram = gpart + kGramPartials;
+  double* hs = reinterpret_cast<double*>(op->ws + op->off_kry);
+  op->arn_nvmax_clean = 0;
+  const unsigned gu = rg_vec;  // k_gram_update: its |w|^2 partials go to a reduction set (<= kRedMaxBlocks)
+  // P[0]: the partials of |w|^2 of the previous column (nin blocks); the
+  // matvec's partials of w . q_0 go to P[1] and are not used here
+  int nin = 0;
   for (int j = 0; j < k; ++j) {
     T* w = Q + (j + 1) * ld;
-    const double* pin = j == 0 ? nullptr : P[c];
+    const double* pin = j == 0 ? nullptr : P[0];
     double* hst = j == 0 ? nullptr : hess + j * kHessLd + (j - 1);
     if constexpr (ADJ) {
       // reads Q_j (with the stencil), q_0 and c^2, writes w
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * ns + g.N) * es, k_kry_matvec_adj<T, K, BC, DIM>, dim3(rg_pts), dim3(kBlock), g, Q + j * ld, w, Q, pin, nin, tol, beta_out, hst, sc + j, P[c ^ 1]);
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * ns + g.N) * es, k_kry_matvec_adj<T, K, BC, DIM>, dim3(rg_pts), dim3(kBlock), g, Q + j * ld, w, Q, pin, nin, tol, beta_out, hst, sc + j, P[1]);
     } else {
       // reads Q_j (with tail), q_1 and c^2, writes w
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * naug + g.N) * es, k_kry_matvec<T, K, BC, DIM>, dim3(rg_pts), dim3(kBlock), g, Q + j * ld, w, Q, ks, amp, pin, nin, tol, beta_out, hst, sc + j, P[c ^ 1]);
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MATVEC, (3.0 * naug + g.N) * es, k_kry_matvec<T, K, BC, DIM>, dim3(rg_pts), dim3(kBlock), g, Q + j * ld, w, Q, ks, amp, pin, nin, tol, beta_out, hst, sc + j, P[1]);
     }
-    c ^= 1;
-    nin = static_cast<int>(rg_pts);
-    for (int i = 0; i <= j; ++i) {
-      const bool lastc = (i == j);
-      // reads w, Q_i [, Q_{i+1}], writes w
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MGS, (lastc ? 3.0 : 4.0) * naug * es, k_kry_mgs<T>, dim3(rg_vec), dim3(kBlock), w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld, naug, P[c], nin, hess + i * kHessLd + j, sc, i, P[c ^ 1]);
-      c ^= 1;
-      nin = static_cast<int>(rg_vec);
-    }
+    // reads w and Q_0..Q_j
+    const unsigned gd = gram_dots_grid(naug, j);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MGS, (j + 2.0) * naug * es, k_gram_dots<T>, dim3(gd), dim3(kBlock), static_cast<const T*>(w), static_cast<const T*>(Q), ld, naug, j, gpart);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MGS, 0.0, k_gram_reduce, dim3(2 * j + 1), dim3(kBlock), static_cast<const double*>(gpart), static_cast<int>(gd), 2 * j + 1, gram + kGramTot);
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MGS, 0.0, k_gram_subst, dim3(1), dim3(64), static_cast<const double*>(gram + kGramTot), j, static_cast<const double*>(sc), gram, hess, kHessLd, hs);
+    // reads w and Q_0..Q_j, writes w (Q_{j+1})
+    launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_MGS, (j + 3.0) * naug * es, k_gram_update<T>, dim3(gu), dim3(kBlock), w, static_cast<const T*>(Q), ld, naug, j, static_cast<const double*>(hs), P[0]);
+    nin = static_cast<int>(gu);
   }
-  launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, k_kry_finish, dim3(1), dim3(kBlock), P[c], nin, tol, beta_out, hess + k * kHessLd + (k - 1), sc + k);
+  launch_timed(&op->prof, op->stream, EXPW_KERNEL_KRYLOV_AUX, 0.0, k_kry_finish, dim3(1), dim3(kBlock), P[0], nin, tol, beta_out, hess + k * kHessLd + (k - 1), sc + k);
   return check_launch(ADJ ? "adjoint arnoldi" : "arnoldi");
 }
 
@@ -2186,7 +2201,7 @@ struct expw_pml {
   int path;  // 0 automatic, 1 one thread per node, 2 LDS tiles, 3 pairs of terms in LDS tiles
   // Krylov (launch per step): largest dimension, workspace offsets, stride of a basis vector
   int kmax;
-  size_t off_part, off_scal, off_hess, off_kry;
+  size_t off_part, off_scal, off_hess, off_kry, off_gram;
   int64_t naug_pad;
 };
 
@@ -2208,7 +2223,7 @@ int pml_path_for(const expw_pml* op, int m) {
 }
 
 struct PmlLayout {
-  size_t bx, bxh, by, byh, src_idx, src_amp, part, scal, hess, kry, big, total;
+  size_t bx, bxh, by, byh, src_idx, src_amp, part, scal, hess, kry, gram, big, total;
   int64_t naug_pad;
 };
 
@@ -2226,6 +2241,7 @@ PmlLayout pml_layout(const expw_pml_grid& g, int kmax, int pmax) {
   L.scal = off; off = align_up(off + 64 * sizeof(double));
   L.hess = off; off = align_up(off + (EXPW_MAX_KRYLOV + 1) * kHessLd * sizeof(double));
   L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
+  if (kmax > 0) L.gram = off, off = align_up(off + (static_cast<size_t>(kGramPartials) + kGramTot + 2 * EXPW_MAX_KRYLOV) * sizeof(double));  // Gram-Schmidt partials, table and totals
   L.big = off;
   const int64_t ns = 4 * g.nx * g.ny;
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -2502,24 +2518,26 @@ int32_t pml_krylov_impl(expw_pml* op, T* S, double t0, double dt, int k, int64_t
     k_norm2<T><<<nb_ns, kBlock, 0, op->stream>>>(S, ns, P[0]);
     k_kry_init<T><<<rg_vec, kBlock, 0, op->stream>>>(S, ns, Q, naug, P[0], nb_ns, p > 0 ? 1.0 : 0.0, scal + 1,
                                                      kry_sc);
-    int c = 0, nin = 0;
+    // Gram-Schmidt in three launches per column (gram.h); P[0] carries the
+    // partials of |w|^2 to the next column's matvec, P[1] takes the matvec's
+    // unused partials of w . q_0
+    double* gpart = reinterpret_cast<double*>(op->ws + op->off_gram);
+    double* gram = gpart + kGramPartials;
+    int nin = 0;
     for (int j = 0; j < k; ++j) {
       T* w = Q + (j + 1) * ld;
-      k_pml_kry_matvec<T><<<rg_pts, kBlock, 0, op->stream>>>(g, Q + j * ld, w, Q, ks, amp, j == 0 ? nullptr : P[c],
+      k_pml_kry_matvec<T><<<rg_pts, kBlock, 0, op->stream>>>(g, Q + j * ld, w, Q, ks, amp, j == 0 ? nullptr : P[0],
                                                              nin, tol, scal + 1,
                                                              j == 0 ? nullptr : hess + j * kHessLd + (j - 1),
-                                                             kry_sc + j, P[c ^ 1]);
-      c ^= 1;
-      nin = static_cast<int>(rg_pts);
-      for (int i = 0; i <= j; ++i) {
-        const bool lastc = (i == j);
-        k_kry_mgs<T><<<rg_vec, kBlock, 0, op->stream>>>(w, Q + i * ld, lastc ? nullptr : Q + (i + 1) * ld, naug,
-                                                        P[c], nin, hess + i * kHessLd + j, kry_sc, i, P[c ^ 1]);
-        c ^= 1;
-        nin = static_cast<int>(rg_vec);
-      }
+                                                             kry_sc + j, P[1]);
+      const unsigned gd = gram_dots_grid(naug, j);
+      k_gram_dots<T><<<gd, kBlock, 0, op->stream>>>(w, Q, ld, naug, j, gpart);
+      k_gram_reduce<<<2 * j + 1, kBlock, 0, op->stream>>>(gpart, static_cast<int>(gd), 2 * j + 1, gram + kGramTot);
+      k_gram_subst<<<1, 64, 0, op->stream>>>(gram + kGramTot, j, kry_sc, gram, hess, kHessLd, kry_y);
+      k_gram_update<T><<<rg_vec, kBlock, 0, op->stream>>>(w, Q, ld, naug, j, kry_y, P[0]);
+      nin = static_cast<int>(rg_vec);
     }
-    k_kry_finish<<<1, kBlock, 0, op->stream>>>(P[c], nin, tol, scal + 1, hess + k * kHessLd + (k - 1), kry_sc + k);
+    k_kry_finish<<<1, kBlock, 0, op->stream>>>(P[0], nin, tol, scal + 1, hess + k * kHessLd + (k - 1), kry_sc + k);
     expm_kernel(k)<<<1, expm_threads(k), 0, op->stream>>>(hess, k, dt, tol, scal + 1, kry_y, kry_keff);
     k_kry_combine_dev<T><<<red_grid_for(ns), kBlock, 0, op->stream>>>(S, Q, ld, ns, kry_y, kry_keff, scal + 1, kry_sc,
                                                                       RecRun<T>{nullptr, 0, 0});
@@ -2571,6 +2589,7 @@ int32_t expw_pml_create(const expw_pml_grid* g, const void* c2_dev, int32_t max_
   op->pmax = max_p;
   op->kmax = max_k;
   const PmlLayout L = pml_layout(*g, max_k, max_p);
+  op->off_gram = L.gram;
   op->off_part = L.part;
   op->off_scal = L.scal;
   op->off_hess = L.hess;

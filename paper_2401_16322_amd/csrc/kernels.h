@@ -328,56 +328,6 @@ __global__ __launch_bounds__(kBlock) void k_kry_matvec(Geo<T, K, DIM> g, const T
   store_partial<false>(acc, pout);
 }
 
-// Modified Gram-Schmidt step i of a column, fused with the next dot:
-//   h = (reduced partials pin) = w . q_i, stored to *h_store by block 0;
-//   w -= h q_i (q_i = sc[i] Q_i);
-//   partials of w . q_{i+1} (q_{i+1} = sc[i+1] Q_{i+1}) into pout, or of
-//   w . w when qn == nullptr (last step of the column).
-// The first chunk of w, Q_i, Q_{i+1} is loaded before the reduction of pin so
-// that the loads overlap it.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_kry_mgs(T* __restrict__ w, const T* __restrict__ qi,
-                                                    const T* __restrict__ qn, int64_t n,
-                                                    const double* __restrict__ pin, int nin,
-                                                    double* h_store, const double* sc, int i_idx,
-                                                    double* __restrict__ pout) {
-  constexpr int UN = 8;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  int64_t base = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
-  T wv[UN], qv[UN], nv[UN];
-  auto load = [&](int64_t b0) {
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const int64_t idx = b0 + u * stride;
-      const bool ok = idx < n;
-      wv[u] = ok ? w[idx] : T(0);
-      qv[u] = ok ? qi[idx] : T(0);
-      nv[u] = (ok && qn) ? qn[idx] : T(0);
-    }
-  };
-  load(base);
-  const double h = load_reduced<false>(pin, nin);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *h_store = h;
-  const double hs = h * sc[i_idx];
-  const double sn = qn ? sc[i_idx + 1] : 1.0;
-  double acc = 0.0;
-  while (true) {
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const int64_t idx = base + u * stride;
-      if (idx < n) {
-        const T wt = static_cast<T>(static_cast<double>(wv[u]) - hs * static_cast<double>(qv[u]));
-        w[idx] = wt;
-        acc += static_cast<double>(wt) * (qn ? sn * static_cast<double>(nv[u]) : static_cast<double>(wt));
-      }
-    }
-    base += UN * stride;
-    if (base >= n) break;
-    load(base);
-  }
-  store_partial<false>(acc, pout);
-}
-
 // After the last column: h_{k,k-1} and s_k from the norm partials (one block).
 __global__ __launch_bounds__(kBlock) void k_kry_finish(const double* pin, int nin, double tol,
                                                        const double* beta, double* h_store,
