@@ -131,6 +131,7 @@ def test_time_to_solution_reference_configuration_matches_stored_oracle(dtype):
 def test_layered3d_256_whole_run_planes_match_stored_oracle(dtype):
     """The 256^3 workload (Faber m = 24, dt = 2.5 ms, source at the centre):
     the three central planes of the pressure every 0.25 s, as far as the
-    stored oracle run goes (an oracle step at this size takes about a minute
-    on one core)."""
+    stored oracle run goes (an oracle step at this size takes about three
+    minutes on one core, so the stored run holds the first snapshot,
+    t = 0.25 s after 100 steps)."""
     _check("layered3d256_faber24_dt2.5", dtype)
