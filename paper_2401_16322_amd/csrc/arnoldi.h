@@ -7,28 +7,44 @@
 // augmented vector, the tail elements in pressure slots of points beyond the
 // grid), and keeps its slices of w, q_0 and the newest basis vector in
 // registers. A thread's matvec loads all operands of a point at once.
-// Columns are written unnormalized with their scale s_j = 1/h_{j+1,j}
+// Columns are written unnormalized with their scale s_j = 1/h_{j,j-1}
 // (s_0 = 1), as in the launch-per-step path.
 //
-// Gram-Schmidt with two grid-wide reductions per column. Modified
+// Gram-Schmidt with one grid-wide reduction per column. Modified
 // Gram-Schmidt takes h_{i,j} = <w - sum_{l<i} h_{l,j} q_l, q_i>, which equals
 // r_i - sum_{l<i} h_{l,j} <q_l, q_i> with r_i = <w, q_i>, for any basis, not
-// only an exactly orthonormal one. So one reduction gives all r_i together
-// with the new Gram row <q_j, q_l> (l < j), a forward substitution over the
-// Gram entries then gives MGS's projections, and a second sweep applies
-// them in MGS's order (w -= h_{i,j} q_i, i = 0..j, rounded after each) and
-// reduces |w|^2. The price is a second read of q_1..q_{j-1} per column; the
-// gain is 2 grid-wide reductions per column instead of j + 2.
+// only an exactly orthonormal one. Column j's matvec runs on the stored,
+// unnormalized Q_j (H is linear, so w = s_j H Q_j is rescaled once s_j is
+// known), and |Q_j|^2 rides in the same reduction as the dots <H Q_j, Q_i>
+// and the new Gram row <Q_j, Q_l> (l < j), as in low-synchronization
+// Gram-Schmidt (Swirydowicz et al., 2020). After that one reduction, s_j,
+// a forward substitution over the Gram entries gives MGS's projections, and
+// a second sweep applies them in MGS's order (w -= h_{i,j} q_i, i = 0..j,
+// rounded after each), stores Q_{j+1} and takes this workgroup's part of
+// |Q_{j+1}|^2 into the next column's reduction. The price is a second read of
+// q_1..q_{j-1} per column; the gain is one grid-wide reduction per column
+// instead of j + 2.
+//
+// The stencil of column j + 1 still needs Q_{j+1} from the neighbouring
+// workgroups. Instead of a grid-wide barrier, each workgroup publishes a
+// flag (launch epoch + column) once its slice of Q_{j+1} is stored, and
+// waits only for the flags of the workgroups that own an element of a cache
+// line its matvec reads: the points within the stencil's reach along the
+// outermost axis plus a margin of a few cache lines, the lines that cross a
+// field boundary, and, where the source tail is read, the tail's owners.
+// (With periodic boundaries a workgroup waits for every other.)
 //
 // Reduction partials cross workgroups through device-coherent accesses
 // (agent-scope relaxed atomics, i.e. sc1 loads and stores that do not stop in
 // an XCD's L2). Basis vectors are written the same way, but read with plain,
-// cached loads: each column Q_j is written once per launch, before any
-// workgroup reads one of its cache lines (columns start on 256-byte
-// boundaries), and the launch starts with no lines of Q in any cache, so a
-// read after the grid-wide reduction that follows the write can only miss
-// and fetch the written value. The stencil's neighbour reads then hit in L1
-// and L2 instead of crossing the fabric each time. A grid-wide reduction is also the barrier, and uses no read-modify-write:
+// cached loads: each column Q_j is written once per launch, and no workgroup
+// reads a cache line of it before every workgroup owning an element of that
+// line has stored its slice (the grid-wide reductions, or the flags above,
+// order the two; columns start on 256-byte boundaries), and the launch starts
+// with no lines of Q in any cache, so such a read can only miss and fetch the
+// written value. The stencil's neighbour reads then hit in L1 and L2 instead
+// of crossing the fabric each time. A grid-wide reduction is also the
+// barrier, and uses no read-modify-write:
 // each block's partial is its own arrival word. Slots start out holding a
 // signalling-NaN pattern that no arithmetic produces; block b stores its
 // partial of value v (after waiting for its earlier stores, s_waitcnt 0) into
@@ -52,7 +68,7 @@ namespace expw {
 
 constexpr int kArnNT = 1024;        // threads per block of the persistent kernel
 constexpr int kArnMaxBlocks = 256;  // grid cap of the persistent kernel
-constexpr int kArnMaxVals = 2 * EXPW_MAX_KRYLOV - 1;  // values of one grid-wide reduction
+constexpr int kArnMaxVals = 2 * EXPW_MAX_KRYLOV;  // values of one grid-wide reduction
 constexpr int kArnHessLd = EXPW_MAX_KRYLOV;           // leading dimension of the Hessenberg matrix
 constexpr int kArnLdsBudget = 160 * 1024 - 1024;      // LDS of one block of the persistent kernel
 
@@ -139,6 +155,90 @@ constexpr int kArnRecLen = 128;
 // kSlotBuffers slot buffers of up to kArnMaxVals x kArnMaxBlocks words
 constexpr size_t kArnRecWords = static_cast<size_t>(kSlotBuffers) * kArnLeaders * kArnRecLen;
 static_assert(kArnMaxVals <= kArnRecLen, "a record holds every value of a reduction");
+// after the slot buffers: one column flag per workgroup, then the launch
+// epoch (all zero when the area is set up)
+constexpr size_t kArnFlagWord = kArnRecWords + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks;
+constexpr size_t kArnAreaWords = kArnFlagWord + kArnMaxBlocks + 8;
+// elements on either side of a read that may share a cache line with it
+// (four 128-byte lines of FP32 values)
+constexpr int64_t kArnLineMargin = 128;
+
+// The workgroups owning a point of [A, B] (points below N + tail; point P
+// belongs to workgroup (P mod nt) / kArnNT, nt the grid's threads), as bits r
+// of this lane for workgroup lane + 64 r.
+__device__ __forceinline__ uint32_t arn_owners(int64_t A, int64_t B, int64_t nt, int nb, int lane) {
+  if (A > B) return 0u;
+  const bool all = B - A + 1 >= nt;
+  const int64_t a = A % nt, b = B % nt;
+  uint32_t m = 0;
+#pragma unroll
+  for (int r = 0; r < kArnMaxBlocks / 64; ++r) {
+    const int c = lane + 64 * r;
+    const int64_t lo = static_cast<int64_t>(c) * kArnNT, hi = lo + kArnNT - 1;
+    const bool hit = all || (a <= b ? (lo <= b && hi >= a) : (hi >= a || lo <= b));
+    if (c < nb && hit) m |= 1u << r;
+  }
+  return m;
+}
+
+// The workgroups whose stored slices of a column workgroup blk's matvec
+// reads, with every element that shares a cache line with such a read
+// (wave 0; bits as in arn_owners). Points P_v = blk kArnNT + v nt + t
+// (t < kArnNT, v < up); reach = K times the outermost stride plus the line
+// margin. Grid points read their neighbours within reach, which near the
+// first or last point share lines with the neighbouring field (the last
+// field's with the tail); source points and tail slots read the tail.
+template <int BC>
+__device__ uint32_t arn_need_mask(int lane, int blk, int nb, int up, int64_t N, int64_t ntail, int64_t reach,
+                                  const KrySrc& src) {
+  const int64_t nt = static_cast<int64_t>(nb) * kArnNT;
+  if (BC != 0) return arn_owners(0, nt - 1, nt, nb, lane);
+  const int64_t tl = N > kArnLineMargin ? N - kArnLineMargin : 0, th = N + ntail - 1;
+  uint32_t m = 0;
+  for (int v = 0; v < up; ++v) {
+    const int64_t lo = static_cast<int64_t>(blk) * kArnNT + v * nt, hi = lo + kArnNT - 1;
+    if (lo < N) {
+      const int64_t gl = lo, gh = hi < N ? hi : N - 1;
+      const int64_t rl = gl - reach, rh = gh + reach;
+      m |= arn_owners(rl > 0 ? rl : 0, rh < N ? rh : N - 1, nt, nb, lane);
+      if (rl < 0) m |= arn_owners(N + rl > 0 ? N + rl : 0, N - 1, nt, nb, lane);
+      if (rh >= N) {
+        m |= arn_owners(0, rh - N < N ? rh - N : N - 1, nt, nb, lane);
+        if (ntail > 0) m |= arn_owners(tl, th, nt, nb, lane);
+      }
+      bool has_src = false;
+      for (int s = lane; s < src.n; s += 64) has_src = has_src || (src.idx[s] >= gl && src.idx[s] <= gh);
+      if (ntail > 0 && __any(has_src)) m |= arn_owners(tl, th, nt, nb, lane);
+    }
+    if (ntail > 0 && hi >= N && lo < N + ntail) m |= arn_owners(tl, th, nt, nb, lane);
+  }
+  return m;
+}
+
+// Wave 0: waits until every workgroup of need has stored a column flag of at
+// least target. Bounded like the reductions' waits.
+__device__ __forceinline__ void arn_wait_flags(const unsigned long long* flags, uint32_t need,
+                                               unsigned long long target, int lane, unsigned spin_limit,
+                                               int* err) {
+  constexpr int R = kArnMaxBlocks / 64;
+  uint32_t pend = need;
+  unsigned polls = 0;
+  for (;;) {
+    unsigned long long x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = (pend >> r & 1u) ? ld_coherent(flags + lane + 64 * r) : target;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (x[r] >= target) pend &= ~(1u << r);
+    if (!__any(pend != 0u)) break;
+    __builtin_amdgcn_s_sleep(1);
+    if (++polls > spin_limit ||
+        ((polls & 1023u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+}
 
 // Grid-wide sums of nv values (1 <= nv <= nvmax, at most kArnMaxBlocks
 // blocks of NT threads), in two levels. Before the call, lane 0 of wave w has
@@ -212,7 +312,7 @@ __device__ __forceinline__ void grid_sum_vec(int nv, int nvmax, const double (*w
     // leader's record of the previous one
     if (static_cast<int>(threadIdx.x) < nvmax) st_coherent(rprev + threadIdx.x, kSlotEmpty);
   } else if (wid == 0) {
-    // the leader's record: lane v polls value v (nv <= kArnMaxVals < 2 * 64)
+    // the leader's record: lane v polls values v and v + 64 (nv <= kArnMaxVals <= 2 * 64)
     unsigned long long x0 = lane < nv ? ld_coherent(rcur + lane) : 0ull;
     unsigned long long x1 = lane + 64 < nv ? ld_coherent(rcur + lane + 64) : 0ull;
     unsigned polls = 0;
@@ -293,7 +393,7 @@ __device__ __forceinline__ void apply_point_all(const Geo<T, K, DIM>& g, const G
 struct ArnArgs {
   int64_t ns, naug, ld;
   int k;
-  int nvmax;     // values of the largest grid-wide reduction: max(2, 2k - 1)
+  int nvmax;     // values of the largest grid-wide reduction: 2k
   double tail2;  // |e_p|^2: 1 with a source, else 0
   double tol;
   unsigned spin_limit;
@@ -363,6 +463,17 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
   // slot buffer and records are restored by this launch's first barrier, so
   // the area needs no fill between launches
   unsigned seq = __hip_atomic_load(seq_io, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // column flags: workgroup b stores ep + j into flags[b] once its slice of
+  // Q_j is stored; the epoch grows by k + 1 per launch, so no flag of an
+  // earlier launch reaches a target of this one
+  unsigned long long* flags = slots + kArnFlagWord;
+  unsigned long long ep = 0;
+  uint32_t need = 0;
+  if (wid == 0) {
+    ep = ld_coherent(flags + kArnMaxBlocks);
+    need = arn_need_mask<BC>(lane, static_cast<int>(blockIdx.x), static_cast<int>(nb), UP, g.N,
+                             a.naug - a.ns, static_cast<int64_t>(K) * g.st[DIM - 1] + kArnLineMargin, src);
+  }
   // Thread gtid owns the grid points P_v = gtid + v * nthreads (v < UP) with
   // all their fields: slot u = f * UP + v holds element f * N + P_v. The
   // pressure slot of a point beyond the grid, P_v = N + t, holds tail element
@@ -465,13 +576,18 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
     }
   };
 
-  T sj = T(1);
   for (int j = 0; j < a.k; ++j) {
     const T* qcol = Q + j * a.ld;
     T* wout = Q + (j + 1) * a.ld;
+    if (j >= 1) {
+      // the workgroups whose slices of Q_j this matvec reads have stored them
+      if (wid == 0) arn_wait_flags(flags, need, ep + static_cast<unsigned long long>(j), lane, a.spin_limit, err);
+      __syncthreads();
+    }
     ecur = e0;
     asm volatile("" : "+v"(ecur));
-    // w = s_j H~ Q_j (column 0: H~ x, scaled once beta is known)
+    // w = H~ Q_j, unscaled (column 0: H~ x); rescaled by s_j (1 / beta) once
+    // the column's reduction has brought |Q_j|^2 (|x|^2)
     const T* xcol = j == 0 ? S : qcol;
     auto tailv = [&](int cc) -> T {
       return j == 0 ? (cc == src.p - 1 ? T(1) : T(0)) : qcol[a.ns + cc];
@@ -502,7 +618,7 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
             }
         }
 #pragma unroll
-        for (int f = 0; f <= DIM; ++f) w[f * UP + v] = out[f] * sj;
+        for (int f = 0; f <= DIM; ++f) w[f * UP + v] = out[f];
       } else {
         // beyond the grid: the pressure slot may hold tail element t, J q_tail
         const uint32_t t = P - npts32;
@@ -510,13 +626,14 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
         for (int f = 0; f <= DIM; ++f) w[f * UP + v] = T(0);
         if (t < ntail32) {
           const int cc = static_cast<int>(t);
-          w[v] = (cc + 1 < src.p) ? tailv(cc + 1) * sj : T(0);
+          w[v] = (cc + 1 < src.p) ? tailv(cc + 1) : T(0);
         }
       }
     }
     // first sweep: value i <= j is <w, Q_i>, value j + 1 + l (l < j) is
-    // <Q_j, Q_l>; columns j-1 down to 1, so that the second sweep starts on
-    // the columns read last
+    // <Q_j, Q_l>, value 2j + 1 is |Q_j|^2 (stored by the previous column's
+    // second sweep; |x|^2 for column 0); columns j-1 down to 1, so that the
+    // second sweep starts on the columns read last
     {
       T r = T(0), gq = T(0);
 #pragma unroll
@@ -547,7 +664,7 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       for (int u = 0; u < UN; ++u) r += w[u] * s_qj[u][threadIdx.x];
       put(j, static_cast<double>(r));
     }
-    reduce(j == 0 ? 2 : 2 * j + 1, [&] {
+    reduce(2 * j + 2, [&] {
       if (ns > 0) load_col(qa, nc + 1);
     });
     if (j == 0) {
@@ -568,12 +685,26 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
         sc[0] = 1.0;
       }
     }
+    // s_j = 1 / h_{j,j-1} (0 at a breakdown), and w = s_j H~ Q_j
+    double sjd = 1.0;
+    if (j >= 1) {
+      const double hn = sqrt(s_tot[2 * j + 1]);
+      sjd = (hn > a.tol * beta) ? 1.0 / hn : 0.0;
+      if (lead) {
+        hess[j * kArnHessLd + j - 1] = hn;
+        sc[j] = sjd;
+      }
+      if (threadIdx.x == 0) s_scale[j] = sjd;  // read by later columns, after their reductions
+      const T sj = static_cast<T>(sjd);
+#pragma unroll
+      for (int u = 0; u < UN; ++u) w[u] *= sj;
+    }
     // MGS's projections: h_i = r_i - sum_{l<i} h_l <q_l, q_i>, lane i of wave 0
     if (wid == 0) {
-      const double sl = lane <= j ? s_scale[lane] : 0.0;
-      double r = lane <= j ? s_tot[lane] * sl : 0.0;
-      if (j == 0) r *= inv * inv;  // <H~ x, x> / beta^2
-      const double grow = lane < j ? s_tot[j + 1 + lane] * s_scale[j] * sl : 0.0;  // <q_j, q_lane>
+      const double sl = lane < j ? s_scale[lane] : (lane == j ? sjd : 0.0);
+      double r = lane <= j ? s_tot[lane] * sl * sjd : 0.0;  // <s_j H~ Q_j, q_lane>
+      if (j == 0) r *= inv * inv;                            // <H~ x, x> / beta^2
+      const double grow = lane < j ? s_tot[j + 1 + lane] * sjd * sl : 0.0;  // <q_j, q_lane>
       // Gram entries are read from LDS eight steps ahead of the dependent chain
       for (int l0 = 0; l0 < j; l0 += 8) {
         double gb[8];
@@ -629,21 +760,31 @@ __global__ __launch_bounds__(kArnNT) void k_arnoldi_persistent(
       s_qj[u][threadIdx.x] = w[u];
       if (j < NC) s_cache[j < NC ? j : 0][u][threadIdx.x] = w[u];
     }
-    put(0, static_cast<double>(nrm));
-    reduce(1, [&] {
-      if (j > NC && j + 1 < a.k) load_col(qa, j);  // the next first sweep starts on Q_j
-    });
-    const double hn = sqrt(s_tot[0]);
-    const double s = (hn > a.tol * beta) ? 1.0 / hn : 0.0;
-    if (lead) {
-      hess[(j + 1) * kArnHessLd + j] = hn;
-      sc[j + 1] = s;
+    // |Q_{j+1}|^2 goes with the next column's reduction (value 2j + 3)
+    put(j + 1 < a.k ? 2 * j + 3 : 0, static_cast<double>(nrm));
+    if (j + 1 < a.k) {
+      // this workgroup's slice of Q_{j+1} is stored (s_waitcnt 0 in every
+      // thread, then the block barrier): publish it
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0) st_coherent(flags + blockIdx.x, ep + static_cast<unsigned long long>(j + 1));
+      if (j > NC) load_col(qa, j);  // the next first sweep starts on Q_j
     }
-    if (threadIdx.x == 0) s_scale[j + 1] = s;  // read after the next reduction's barriers
-    sj = static_cast<T>(s);
   }
-  // every block has read seq_io: they all passed the barriers since
-  if (lead) st_coherent(seq_io, seq % static_cast<unsigned>(kSlotBuffers));
+  if (a.full_last) {
+    // h_{k,k-1} = |Q_k| for the error estimate
+    reduce(1, [] {});
+    const double hn = sqrt(s_tot[0]);
+    if (lead) {
+      hess[a.k * kArnHessLd + a.k - 1] = hn;
+      sc[a.k] = (hn > a.tol * beta) ? 1.0 / hn : 0.0;
+    }
+  }
+  // every block has read seq_io and the epoch: they all passed the barriers since
+  if (lead) {
+    st_coherent(seq_io, seq % static_cast<unsigned>(kSlotBuffers));
+    st_coherent(flags + kArnMaxBlocks, ep + static_cast<unsigned long long>(a.k + 1));
+  }
 }
 
 __global__ void k_zero_u32(unsigned* p, int n) {

@@ -178,10 +178,10 @@ Layout layout(const expw_grid& g, int kmax, int pmax) {
   L.kry = off; off = align_up(off + 64 * sizeof(double) + 72 * sizeof(double) + 64 * sizeof(int));  // y, scales, keff
   // grid reduction records and slots of the persistent Arnoldi kernel; the
   // launch-per-column Gram-Schmidt's partials and Gram table share the area
-  static_assert(static_cast<size_t>(kGramPartials) + kGramTot + 2 * EXPW_MAX_KRYLOV <=
-                    kArnRecWords + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks,
+  // (below the column flags, which only the persistent kernel uses)
+  static_assert(static_cast<size_t>(kGramPartials) + kGramTot + 2 * EXPW_MAX_KRYLOV <= kArnFlagWord,
                 "Gram-Schmidt partials fit the reduction area");
-  L.bar = off; off = align_up(off + (kArnRecWords + static_cast<size_t>(kSlotBuffers) * kArnMaxVals * kArnMaxBlocks) * sizeof(unsigned long long));
+  L.bar = off; off = align_up(off + kArnAreaWords * sizeof(unsigned long long));
   L.big = off;
   const int64_t ns = (g.ndim + 1) * npts(g);
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
@@ -645,7 +645,7 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   aa.k = k;
   aa.tail2 = tail2;
   aa.tol = tol;
-  aa.nvmax = std::max(2, 2 * k - 1);
+  aa.nvmax = 2 * k;
   aa.spin_limit = 1u << 20;  // about a second of polling
   // the kernel leaves the area consistent for the next launch with the same
   // layout (nvmax); it is filled on first use and when the layout changes
@@ -653,6 +653,8 @@ int32_t arnoldi_persistent(expw_op* op, int un, const Geo<T, K, DIM>& g, const T
   if (op->arn_nvmax_clean != aa.nvmax) {
     const int nslots = static_cast<int>(kArnRecWords) + kSlotBuffers * aa.nvmax * op->coop_blocks;
     k_fill_u64<<<(nslots + 255) / 256, 256, 0, op->stream>>>(slots, nslots, kSlotEmpty);
+    // column flags and the launch epoch
+    k_fill_u64<<<2, 256, 0, op->stream>>>(slots + kArnFlagWord, kArnMaxBlocks + 1, 0ull);
     k_zero_u32<<<1, 64, 0, op->stream>>>(seq_io, 1);
     op->arn_nvmax_clean = aa.nvmax;
   }
