@@ -38,6 +38,7 @@ KERNEL_SOURCES = {
     "krylov_arnoldi": ("arnoldi.h", "device_common.h", "kernels.h"),
     "faber": ("fused.h", "fused3d.h", "stream2d.h", "term_o4.h", "device_common.h", "kernels.h"),
     "pml_faber_pair": ("pml.h", "device_common.h"),
+    "pml_faber_stream": ("pml_stream.h", "pml.h", "device_common.h", "kernels.h"),
     "pml_faber_term": ("pml.h", "device_common.h"),
 }
 
@@ -84,7 +85,8 @@ def parse():
     ap.add_argument("--methods", default="",
                     help="comma list of faber,krylov,rk4,leapfrog (default: faber in 3D, all in 2D)")
     ap.add_argument("--pml-path", type=int, default=0,
-                    help="PML term kernel: 0 automatic, 1 per node, 2 LDS tiles, 3 two terms per pass")
+                    help="PML term kernel: 0 automatic, 1 per node, 2 LDS tiles, 3 two terms per pass, "
+                         "4 row-streamed passes")
     ap.add_argument("--operator", default="pv", choices=["pv", "pml"],
                     help="pv: the first-order p/v operator (the composite step); pml: "
                          "Faber steps on the paper's PML system with a free surface")
@@ -148,20 +150,21 @@ def bench_pml(args, w):
     # algorithmic words per point per step (four fields: reads of v_{j-1}, v_{j-2}
     # and the sum, and c^2; writes of the new terms and the sum), by term kernel
     path = op.path_for(m)
-    if path == 3:
-        # passes of two terms: first pass reads v_0 and c^2 and writes v_1, v_2 and
-        # the sum (17; 9 if it is also the last); middle passes 13 + 12 = 25; a
-        # last pass 13 + 4 = 17; for odd m a last single term 13 + 4 = 17
-        npair, odd = m // 2, m % 2
-        if npair == 1 and not odd:
-            words = 9
-        else:
-            words = 17 + 25 * (npair - 2 + odd) + 17
+    if path in (3, 4) and m >= 2:
+        # passes of several terms (pairs; row-streamed passes of up to 4 terms at
+        # FP32 and 2 at FP64, as evenly sized as their count allows): the first
+        # pass reads v_0 and c^2 and writes the last two terms and the sum (17; 9
+        # if it is also the last); middle passes 13 + 12 = 25; a last pass, or
+        # a last single term, 13 + 4 = 17
+        smax = 2 if path == 3 else (4 if args.dtype == "f32" else 2)
+        npass = -(-m // smax)
+        words = 9 if npass == 1 else 17 + 25 * (npass - 2) + 17
     else:
         # one term per sweep: first term 13, middle terms 21, last term 17
+        npass = m
         words = 13 + 21 * (m - 2) + 17 if m >= 2 else 13
     gbps = words * npts * es * args.steps / (ms * 1e-3) / 1e9
-    kclass = "pml_faber_pair" if path == 3 else "pml_faber_term"
+    kclass = {3: "pml_faber_pair", 4: "pml_faber_stream"}.get(path, "pml_faber_term")
     out = {
         "metric": "grid-pt matvecs/s", "value": npts * m * args.steps / (ms * 1e-3),
         "unit": "grid-pt matvecs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -176,7 +179,9 @@ def bench_pml(args, w):
                      "traffic": measured_traffic(kclass, w.name, args.dtype),
                      "traffic_unit": "HBM bytes per launch, mean over the passes of a step "
                                      "(rocprofv3 counters, copy-calibrated)",
-                     "avg_term_us": round(ms * 1e3 / (args.steps * m), 3)},
+                     "avg_term_us": round(ms * 1e3 / (args.steps * m), 3),
+                     "passes_per_step": npass,
+                     "avg_pass_us": round(ms * 1e3 / (args.steps * npass), 3)},
     }
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline_pml(w, args, c2.double().cpu().numpy())

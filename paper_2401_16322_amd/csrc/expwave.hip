@@ -22,6 +22,7 @@
 #include "internal.h"
 #include "kernels.h"
 #include "pml.h"
+#include "pml_stream.h"
 #include "profiler.h"
 #include "stream.h"
 #include "stream2d.h"
@@ -2200,7 +2201,7 @@ struct expw_pml {
   int taylor_p;
   int n_rec;
   const int64_t* rec_dev;
-  int path;  // 0 automatic, 1 one thread per node, 2 LDS tiles, 3 pairs of terms in LDS tiles
+  int path;  // 0 automatic, 1 one thread per node, 2 LDS tiles, 3 pairs of terms in LDS tiles, 4 row-streamed passes
   // Krylov (launch per step): largest dimension, workspace offsets, stride of a basis vector
   int kmax;
   size_t off_part, off_scal, off_hess, off_kry, off_gram;
@@ -2214,12 +2215,18 @@ namespace {
 // fewer, its 256-thread blocks leave the CUs short of waves
 constexpr int64_t kPmlLdsMinTiles = 2048;
 
-// The term kernel a step of degree m takes: the forced one, else pairs of
-// terms at FP32 (fastest at 1001x501 and 8192x4096), and at FP64 LDS tiles from
-// kPmlLdsMinTiles tiles up, one thread per node below.
+// Terms per streamed PML pass (pml_stream.h): FP32 up to kPmlStreamDepth,
+// FP64 two.
+constexpr int kPmlStreamDepth = 4;
+
+// The term kernel a step of degree m takes: the forced one, else at FP32 the
+// row-streamed passes where the grid gives them enough row segments and pairs
+// of terms on LDS tiles below, and at FP64 LDS tiles from kPmlLdsMinTiles
+// tiles up, one thread per node below.
 int pml_path_for(const expw_pml* op, int m) {
   if (op->path != 0) return op->path;
-  if (op->g.dtype == EXPW_F32 && m >= 2) return 3;
+  if (op->g.dtype == EXPW_F32 && m >= 2)
+    return pml_stream_fits(op->g.nx, op->g.ny, kPmlStreamDepth) ? 4 : 3;
   const int64_t tiles = ((op->g.nx + kPmlTX - 1) / kPmlTX) * ((op->g.ny + kPmlTY - 1) / kPmlTY);
   return tiles >= kPmlLdsMinTiles ? 2 : 1;
 }
@@ -2356,6 +2363,63 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
   return EXPW_OK;
 }
 
+// One Faber step of degree m >= 2 in row-streamed passes (pml_stream.h) of at
+// most kPmlStreamDepth terms (FP64: 2), sized as evenly as the count of
+// passes allows (the larger ones first); a last pass of one term (m odd at
+// FP64) takes the one-term kernel. Buffers as in pml_pairs.
+template <typename T, typename Term>
+int32_t pml_stream_passes(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D, T* E, const double* a,
+                          const double* q, int m, double gs, double c0s, double c1s, Term&& term) {
+  const int64_t ns = 4 * g.N;
+  constexpr int smax = sizeof(T) == 4 ? kPmlStreamDepth : 2;
+  const int npass = (m + smax - 1) / smax;
+  const int base = m / npass, rem = m % npass;
+  const T* vp = S;
+  const T* vpp = nullptr;
+  T* pair_out[2][2] = {{A, B}, {D, E}};
+  int which = 0;
+  int j = 1;
+  for (int p = 0; p < npass; ++p) {
+    const int n = base + (p < rem ? 1 : 0);
+    const bool last = p + 1 == npass;
+    if (n == 1) {
+      // the last term alone (v_{m-1} = vp, v_{m-2} = vpp, neither is S)
+      PmlTerm<T> c{};
+      c.inv_gamma = static_cast<T>(1.0 / gs);
+      c.c0 = static_cast<T>(c0s);
+      c.cpp = static_cast<T>(c1s);
+      split_weight(a[m], &c.a_j, &c.a_j_lo);
+      term(vp, vpp, nullptr, C, S, c, q[m - 1]);
+      if (int32_t rc = check_launch("pml faber last term")) return rc;
+      break;
+    }
+    T* ol = last ? nullptr : pair_out[which][1];
+    T* opv = last ? nullptr : pair_out[which][0];
+    T* acc_out = (last && vp != S) ? S : C;
+    const Src<T> src = make_pml_src<T>(op, 0.0);
+    int32_t rc = EXPW_OK;
+    if constexpr (sizeof(T) == 4) {
+      switch (n) {
+        case 2: rc = launch_pml_stream<T, 2>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, j, a, q, gs, c0s, c1s); break;
+        case 3: rc = launch_pml_stream<T, 3>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, j, a, q, gs, c0s, c1s); break;
+        default: rc = launch_pml_stream<T, 4>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, j, a, q, gs, c0s, c1s); break;
+      }
+    } else {
+      rc = launch_pml_stream<T, 2>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, j, a, q, gs, c0s, c1s);
+    }
+    if (rc != EXPW_OK) return rc;
+    if (last && acc_out == C) {
+      if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
+        return fail(EXPW_EDEVICE, "pml faber: copy failed");
+    }
+    vpp = opv;
+    vp = ol;
+    which ^= 1;
+    j += n;
+  }
+  return EXPW_OK;
+}
+
 // Faber steps (Sec. 3.2) on the PML operator, one term per sweep; the ellipse
 // is the step ellipse of precision T, as for the p/v operator.
 template <typename T>
@@ -2376,6 +2440,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   const int band_w = (tiles_x + 7) / 8;
   const int path = pml_path_for(op, m);
   const bool pairs = path == 3;
+  const bool streamed = path == 4;
   const bool lds = path >= 2;
   const unsigned grid = lds ? 8u * static_cast<unsigned>(band_w) * static_cast<unsigned>(tiles_y) : grid_for(g.N);
   T* D = C + ns;
@@ -2398,10 +2463,14 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
       faber_source_scalars(gs, c0s, c1s, m, p, G.data(), q.data());
       for (int j = 0; j < m; ++j) q[j] *= sc;
     }
-    if (pairs && m >= 2) {
-      if (int32_t rc = pml_pairs<T>(op, g, S, A, B, C, D, E, a.data(), q.data(), m, gs, c0s, c1s, tiles_x, grid,
-                                    term))
+    if ((pairs || streamed) && m >= 2) {
+      if (streamed) {
+        if (int32_t rc = pml_stream_passes<T>(op, g, S, A, B, C, D, E, a.data(), q.data(), m, gs, c0s, c1s, term))
+          return rc;
+      } else if (int32_t rc = pml_pairs<T>(op, g, S, A, B, C, D, E, a.data(), q.data(), m, gs, c0s, c1s, tiles_x,
+                                           grid, term)) {
         return rc;
+      }
       if (traces && op->n_rec > 0) {
         k_gather<T><<<grid_for(op->n_rec), kBlock, 0, op->stream>>>(S, op->rec_dev, op->n_rec, traces + st * op->n_rec);
         if (int32_t rc = check_launch("pml gather")) return rc;
@@ -2762,8 +2831,9 @@ int32_t expw_pml_step_rk4(expw_pml* op, void* state, double t0, double dt, int64
 
 int32_t expw_pml_set_path(expw_pml* op, int32_t path) {
   if (int32_t rc = check_pml(op)) return rc;
-  if (path < 0 || path > 3)
-    return fail(EXPW_EINVAL, "path must be 0 (automatic), 1 (per node), 2 (LDS tiles) or 3 (pairs of terms)");
+  if (path < 0 || path > 4)
+    return fail(EXPW_EINVAL,
+                "path must be 0 (automatic), 1 (per node), 2 (LDS tiles), 3 (pairs of terms) or 4 (row-streamed passes)");
   op->path = path;
   return EXPW_OK;
 }

@@ -911,7 +911,8 @@ class PMLOperator:
         _check(load().expw_pml_step_faber(self.op, state.data_ptr(), t0, dt, m, nsteps, tp))
 
     def set_path(self, path):
-        """0 automatic, 1 one thread per node, 2 LDS tiles, 3 two terms per pass."""
+        """0 automatic, 1 one thread per node, 2 LDS tiles, 3 two terms per pass,
+        4 row-streamed passes."""
         _check(load().expw_pml_set_path(self.op, int(path)))
 
     def path_for(self, m):

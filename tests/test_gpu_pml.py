@@ -50,14 +50,16 @@ def test_apply_matches_oracle(dtype, nx, ny):
         assert np.max(np.abs(got[sl] - ref[sl])) <= APPLY_TOL[dtype] * max(np.max(np.abs(ref[sl])), 1e-300), f
 
 
-@pytest.mark.parametrize("path", [1, 2, 3])
+@pytest.mark.parametrize("path", [1, 2, 3, 4])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 @pytest.mark.parametrize("m", [1, 2, 3, 12, 20])
 def test_faber_steps_with_source_and_receivers_match_oracle(dtype, m, path):
     """Every term kernel: one thread per node; LDS tiles; pairs of terms per
-    pass (m = 2: one pass that is first and last; odd m: a last single term),
-    the tiled ones here with a ragged last tile column and row and the surface
-    rows inside the first tile row."""
+    pass (m = 2: one pass that is first and last; odd m: a last single term);
+    row-streamed passes (FP32: up to 4 terms, m = 3 one pass of 3, m = 12 and
+    20 passes of 4; FP64: passes of 2, odd m a last single term), the tiled
+    ones here with a ragged last tile column and row and the surface rows
+    inside the first tile row."""
     import torch
     op, prob, U0, tdt = _case(45 if path == 1 else 141, 33 if path == 1 else 37, dtype, seed=2)
     op.set_path(path)
@@ -110,11 +112,15 @@ def test_library_ellipse_matches_the_oracle_reading():
     assert np.allclose(op.ellipse, prob.ellipse(), rtol=1e-13, atol=0.0)
 
 
+@pytest.mark.parametrize("path", [0, 4])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-def test_faber_at_a_larger_grid_without_layer(dtype):
-    """512 x 256 without a layer: free surface and zero values only."""
+def test_faber_at_a_larger_grid_without_layer(dtype, path):
+    """512 x 256 without a layer: free surface and zero values only (the
+    row-streamed passes here in three bands, the last one ragged, and four
+    row segments)."""
     import torch
     op, prob, U0, tdt = _case(512, 256, dtype, seed=4, cells=0, beta0=0.0)
+    op.set_path(path)
     U = torch.tensor(U0, dtype=tdt, device="cuda")
     op.step_faber(U, 0.0, 2e-3, 16, 1)
     op.sync()
@@ -127,15 +133,33 @@ def test_lds_and_per_node_kernels_agree_to_rounding(nx, ny):
     import torch
     op, prob, U0, tdt = _case(nx, ny, "float64", seed=6)
     outs = []
-    for path in (1, 2, 3):
+    for path in (1, 2, 3, 4):
         op.set_path(path)
         for m in (6, 7):
             U = torch.tensor(U0, dtype=tdt, device="cuda")
             op.step_faber(U, 0.01, 1e-3, m, 2)
             op.sync()
             outs.append(U.cpu().numpy())
-    for k in range(2, 6):
+    for k in range(2, 8):
         assert rel_l2(outs[k], outs[k % 2]) <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("m", [5, 9])
+def test_streamed_passes_over_bands_and_segments_match_oracle(dtype, m):
+    """Row-streamed passes on 600 x 150 with a 10-cell layer and a source:
+    three bands (the last ragged), two row segments (the surface rows and
+    the top of the layer in the first, its bottom in the second), passes of 3 and 2
+    (m = 5) or of 3, 3 and 3 terms (m = 9) at FP32, of 2 with a last single
+    term at FP64, two steps."""
+    import torch
+    op, prob, U0, tdt = _case(600, 150, dtype, seed=9, cells=10)
+    op.set_path(4)
+    U = torch.tensor(U0, dtype=tdt, device="cuda")
+    op.step_faber(U, 0.02, 1.5e-3, m, 2)
+    op.sync()
+    ref, _, _ = run(prob, "faber", U0, 0.02, 1.5e-3, 2, m=m, p=8, ellipse=prob.ellipse())
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
 
 
 def test_invalid_arguments_are_rejected():
@@ -152,6 +176,6 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(ew.ExpwError):
         op.apply(U, U)
     with pytest.raises(ew.ExpwError):
-        op.set_path(4)
+        op.set_path(5)
     with pytest.raises(ew.ExpwError):  # the free-surface stencils need 9 rows
         type(op)(8, 8, 10.0, torch.ones(64, dtype=tdt, device="cuda"))
