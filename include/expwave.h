@@ -599,14 +599,15 @@ int32_t expw_pml_step_krylov(expw_pml* op, void* state_dev, double t0, double dt
 int32_t expw_pml_step_rk4(expw_pml* op, void* state_dev, double t0, double dt, int64_t nsteps,
                           void* traces_dev);
 
-/* Kernel of the Faber terms: 0 = automatic (FP32: row-streamed passes where
- * the grid gives 512 workgroups of 64 rows or more, else two terms per pass;
- * FP64: LDS tiles of 64 x 16 nodes once the grid has at least 2048 of them,
- * else one thread per node), 1 = one thread per node, 2 = LDS tiles, 3 = two
- * terms per pass on LDS tiles (temporal blocking; an odd last term alone), 4 =
- * row-streamed passes of up to 4 terms at FP32 and 2 at FP64 (no
- * recomputation along y; a last single term alone). Results agree to
- * rounding. */
+/* Kernel of the Faber terms: 0 = automatic (row-streamed passes where the
+ * grid gives them 512 x 256 threads in row segments of 64 rows or more, else
+ * at FP32 two terms per pass and at FP64 LDS tiles of 64 x 16 nodes once the
+ * grid has at least 2048 of them, one thread per node below; a step of one
+ * term takes the LDS tiles or one thread per node), 1 = one thread per node,
+ * 2 = LDS tiles, 3 = two terms per pass on LDS tiles (temporal blocking; an
+ * odd last term alone), 4 = row-streamed passes of up to 4 terms at FP32 and
+ * 2 at FP64 (no recomputation along y; a last single term alone). Results
+ * agree to rounding. */
 int32_t expw_pml_set_path(expw_pml* op, int32_t path);
 
 /* The path (1, 2 or 3) a step of degree m takes under the current setting. */

@@ -2219,14 +2219,17 @@ constexpr int64_t kPmlLdsMinTiles = 2048;
 // FP64 two.
 constexpr int kPmlStreamDepth = 4;
 
-// The term kernel a step of degree m takes: the forced one, else at FP32 the
-// row-streamed passes where the grid gives them enough row segments and pairs
-// of terms on LDS tiles below, and at FP64 LDS tiles from kPmlLdsMinTiles
-// tiles up, one thread per node below.
+// The term kernel a step of degree m takes: the forced one, else the
+// row-streamed passes where the grid gives them enough row segments (8192 x
+// 4096, m = 16: FP32 108 against 44 G grid-pt matvecs/s for pairs, FP64 42
+// against 21 for LDS tiles), below that at FP32 pairs of terms on LDS tiles
+// (1001 x 501: 47 against 6 G/s for three bands of streamed passes), and at
+// FP64 LDS tiles from kPmlLdsMinTiles tiles up, one thread per node below.
 int pml_path_for(const expw_pml* op, int m) {
   if (op->path != 0) return op->path;
   if (op->g.dtype == EXPW_F32 && m >= 2)
-    return pml_stream_fits(op->g.nx, op->g.ny, kPmlStreamDepth) ? 4 : 3;
+    return pml_stream_fits<float>(op->g.nx, op->g.ny, kPmlStreamDepth) ? 4 : 3;
+  if (m >= 2 && pml_stream_fits<double>(op->g.nx, op->g.ny, 2)) return 4;
   const int64_t tiles = ((op->g.nx + kPmlTX - 1) / kPmlTX) * ((op->g.ny + kPmlTY - 1) / kPmlTY);
   return tiles >= kPmlLdsMinTiles ? 2 : 1;
 }

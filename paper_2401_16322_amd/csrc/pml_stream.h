@@ -2,9 +2,10 @@
 // free-surface appendix; Sec. 3.2, Faber recurrence): S consecutive terms per
 // HBM sweep with no recomputation along y.
 //
-// A workgroup of kPsNT threads owns a band of kPsNT - 8S output columns and a
-// segment of rows; thread t owns column t of the band grown by 4S on each
-// side. The operator's stencils reach 4 nodes along each axis (u: -4..4,
+// A workgroup of NT threads (ps_nt: 512 at FP32, 256 at FP64, whose
+// two-term kernel needs more than 256 registers per lane) owns a band of
+// NT - 8S output columns and a segment of rows; thread t owns column t of the
+// band grown by 4S on each side. The operator's stencils reach 4 nodes along each axis (u: -4..4,
 // w_x along x and w_y along y: -4..3) and the free-surface rows 0..3 read u
 // down to row 8 and w_y down to row 7, so the walk goes upwards (decreasing
 // row index): the first rows of the walk are the bottom ones, and by the
@@ -19,7 +20,7 @@
 // the surface) are zero at every level and are pushed like any other row, so
 // a surface row j < 4 finds level r-1's row y in slot 4 + y - j; the queues
 // of u and w_y are 13 and 12 rows deep for that. Level r is valid on columns
-// 4(r + 1) .. kPsNT - 1 - 4(r + 1) of the band, so the last level covers the
+// 4(r + 1) .. NT - 1 - 4(r + 1) of the band, so the last level covers the
 // output band exactly.
 //
 // Each level forms v_{j+r} = F_1 v_{j+r-1} - c_{j+r} v_{j+r-2} (+ q_r times
@@ -38,7 +39,12 @@
 
 namespace expw {
 
-constexpr int kPsNT = 256;
+// threads per workgroup of the streamed pass (8192 x 4096, FP32, m = 16: 108
+// G grid-pt matvecs/s with 512, 103.5 with 256)
+template <typename T>
+constexpr int ps_nt() {
+  return sizeof(T) == 4 ? 512 : 256;
+}
 
 template <typename T, int S>
 struct PmlStreamArgs {
@@ -180,14 +186,15 @@ __device__ __forceinline__ void pml_point_row(const PmlGeo<T>& g, int j, T vc, F
 // last pass). No output may alias vp, vpp or another output; acc_out may
 // alias acc_in.
 template <typename T, int S, bool FIRST>
-__global__ __launch_bounds__(kPsNT) void k_pml_faber_stream(PmlGeo<T> g, const T* __restrict__ vp,
+__global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, const T* __restrict__ vp,
                                                             const T* __restrict__ vpp, const T* acc_in,
                                                             T* __restrict__ out_last, T* __restrict__ out_prev,
                                                             T* acc_out, PmlStreamArgs<T, S> c, Src<T> src) {
   static_assert(S >= 2 && S <= 4, "2 to 4 terms per pass");
-  constexpr int H = 4, W = kPsNT - 2 * H * S;
-  __shared__ T s_u[2][S][kPsNT];
-  __shared__ T s_x[2][S][kPsNT];
+  constexpr int NT = ps_nt<T>();
+  constexpr int H = 4, W = NT - 2 * H * S;
+  __shared__ T s_u[2][S][NT];
+  __shared__ T s_x[2][S][NT];
   const int nx = g.nx, ny = g.ny;
   const int64_t N = g.N;
   const int band = static_cast<int>(blockIdx.x) % c.bands, seg = static_cast<int>(blockIdx.x) / c.bands;
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(kPsNT) void k_pml_faber_stream(PmlGeo<T> g, const T
   const int ic = xin ? i : 0;
   const int z0 = seg * c.zseg;
   const int z1 = min(z0 + c.zseg, ny);
-  const bool out_col = t >= H * S && t < kPsNT - H * S && xin;
+  const bool out_col = t >= H * S && t < NT - H * S && xin;
   const T bxv = xin ? g.bx[ic] : T(0), bxhv = xin ? g.bxh[ic] : T(0);
   // the walk: input rows jstart, jstart - 1, ..., z0 - 4S
   const int jstart = z1 - 1 + 4 * S;
@@ -270,7 +277,7 @@ __global__ __launch_bounds__(kPsNT) void k_pml_faber_stream(PmlGeo<T> g, const T
       auto& P_ = ps_level<R - 1>(q);                                                               \
       const int jr = jin + 4 * (R + 1);                                                            \
       T nv[4] = {T(0), T(0), T(0), T(0)};                                                          \
-      const bool act = t >= H * (R + 1) && t < kPsNT - H * (R + 1) && xin && jr >= 0 && jr < ny;  \
+      const bool act = t >= H * (R + 1) && t < NT - H * (R + 1) && xin && jr >= 0 && jr < ny;     \
       if (act) {                                                                                   \
         const T* LU = s_u[buf][R];                                                                 \
         const T* LX = s_x[buf][R];                                                                 \
@@ -358,7 +365,7 @@ int pml_stream_capacity() {
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void*>(k_pml_faber_stream<T, S, FIRST>), kPsNT, 0) == hipSuccess &&
+            &per, reinterpret_cast<const void*>(k_pml_faber_stream<T, S, FIRST>), ps_nt<T>(), 0) == hipSuccess &&
         cus > 0 && per > 0)
       cap = cus * per;
     else
@@ -386,11 +393,13 @@ inline int pml_stream_zseg(int64_t ny, int bands, int capacity, int S) {
 }
 
 // The streamed passes need long row segments to amortize their 8S-row
-// warm-up: taken automatically when the grid gives 512 workgroups with
-// segments of 64 rows or more.
-inline bool pml_stream_fits(int64_t nx, int64_t ny, int S) {
-  const int64_t bands = (nx + (kPsNT - 8 * S) - 1) / (kPsNT - 8 * S);
-  return bands * ((ny + 63) / 64) >= 512;
+// warm-up: taken automatically when the grid gives 512 workgroups (of the
+// 256-thread kind; 256 of 512 threads) with segments of 64 rows or more.
+template <typename T>
+bool pml_stream_fits(int64_t nx, int64_t ny, int S) {
+  const int W = ps_nt<T>() - 8 * S;
+  const int64_t bands = (nx + W - 1) / W;
+  return bands * ((ny + 63) / 64) * ps_nt<T>() >= 512 * 256;
 }
 
 // Terms j .. j + n - 1 in one streamed pass (n <= S of the instantiations).
@@ -398,7 +407,8 @@ template <typename T, int S>
 int32_t launch_pml_stream(hipStream_t st, const PmlGeo<T>& g, Src<T> src, const T* vp, const T* vpp,
                           const T* acc_in, T* out_last, T* out_prev, T* acc_out, int j, const double* a,
                           const double* q, double gs, double c0s, double c1s) {
-  constexpr int W = kPsNT - 8 * S;
+  constexpr int NT = ps_nt<T>();
+  constexpr int W = NT - 8 * S;
   const bool first = j == 1;
   PmlStreamArgs<T, S> c{};
   c.inv_gamma = static_cast<T>(1.0 / gs);
@@ -416,10 +426,10 @@ int32_t launch_pml_stream(hipStream_t st, const PmlGeo<T>& g, Src<T> src, const 
   const int64_t blocks = static_cast<int64_t>(c.bands) * ((g.ny + c.zseg - 1) / c.zseg);
   if (blocks > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "streamed PML pass: grid too large");
   if (first)
-    k_pml_faber_stream<T, S, true><<<static_cast<unsigned>(blocks), kPsNT, 0, st>>>(
+    k_pml_faber_stream<T, S, true><<<static_cast<unsigned>(blocks), NT, 0, st>>>(
         g, vp, nullptr, nullptr, out_last, out_prev, acc_out, c, src);
   else
-    k_pml_faber_stream<T, S, false><<<static_cast<unsigned>(blocks), kPsNT, 0, st>>>(
+    k_pml_faber_stream<T, S, false><<<static_cast<unsigned>(blocks), NT, 0, st>>>(
         g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "streamed PML pass: %s", hipGetErrorString(e));

@@ -116,8 +116,8 @@ def test_library_ellipse_matches_the_oracle_reading():
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 def test_faber_at_a_larger_grid_without_layer(dtype, path):
     """512 x 256 without a layer: free surface and zero values only (the
-    row-streamed passes here in three bands, the last one ragged, and four
-    row segments)."""
+    row-streamed passes here in two bands at FP32 and three at FP64, the last
+    one ragged, and four row segments)."""
     import torch
     op, prob, U0, tdt = _case(512, 256, dtype, seed=4, cells=0, beta0=0.0)
     op.set_path(path)
@@ -147,13 +147,14 @@ def test_lds_and_per_node_kernels_agree_to_rounding(nx, ny):
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 @pytest.mark.parametrize("m", [5, 9])
 def test_streamed_passes_over_bands_and_segments_match_oracle(dtype, m):
-    """Row-streamed passes on 600 x 150 with a 10-cell layer and a source:
-    three bands (the last ragged), two row segments (the surface rows and
-    the top of the layer in the first, its bottom in the second), passes of 3 and 2
-    (m = 5) or of 3, 3 and 3 terms (m = 9) at FP32, of 2 with a last single
-    term at FP64, two steps."""
+    """Row-streamed passes on 1100 x 150 with a 10-cell layer and a source:
+    three bands of 512 threads at FP32, five of 256 at FP64 (the last one
+    ragged), two row segments (the surface rows and the top of the layer in
+    the first, its bottom in the second), passes of 3 and 2 (m = 5) or of 3,
+    3 and 3 terms (m = 9) at FP32, of 2 with a last single term at FP64, two
+    steps."""
     import torch
-    op, prob, U0, tdt = _case(600, 150, dtype, seed=9, cells=10)
+    op, prob, U0, tdt = _case(1100, 150, dtype, seed=9, cells=10)
     op.set_path(4)
     U = torch.tensor(U0, dtype=tdt, device="cuda")
     op.step_faber(U, 0.02, 1.5e-3, m, 2)
