@@ -198,18 +198,21 @@ int32_t expw_set_ellipse(expw_op* op, double gamma, double c0, double c1);
 /* Kernel tuning for the Faber step: fuse = recurrence terms per HBM sweep
  * (0 = automatic, 1 = one term per sweep, up to 8 accepted). 2D order 4:
  * up to 6 terms at FP32 and 4 at FP64, automatic = 6 at FP32 and 4 at FP64;
- * 2D order 8: up to 4,
- * automatic = 3; 3D FP32 order 4: two terms unless fuse = 1; 3D FP64: one
- * term per sweep. Only zero ghosts fuse. Results do not depend on it beyond
- * rounding order. */
+ * 2D order 8: up to 4 (3 in streamed FP64 passes), automatic = 4 in streamed
+ * FP32 passes and 3 otherwise; 3D FP32 order 4: two terms unless fuse = 1;
+ * 3D FP64: one term per sweep. Only zero ghosts fuse. Results do not depend
+ * on it beyond rounding order. */
 int32_t expw_set_tuning(expw_op* op, int32_t fuse);
 
-/* Kernel of the fused Faber passes on 2D order-4 grids with zero ghosts:
+/* Kernel of the fused Faber passes on 2D grids (order 4 or 8) with zero
+ * ghosts:
  *   EXPW_PASS_AUTO (default): streamed when the grid gives the chip at least
  *     512 workgroups with row segments of 64 rows or more, else tiled;
  *   EXPW_PASS_TILED: each workgroup recomputes the halo of a 2D tile;
  *   EXPW_PASS_STREAMED: each workgroup walks a column band down the grid,
- *     every term two rows behind the previous one (no recomputation in z).
+ *     every term two rows (order 8: four) behind the previous one (no
+ *     recomputation in z); order 8 in FP64 takes at most three terms per
+ *     pass.
  * Results agree to rounding (the same polynomial on the same ellipse). */
 enum { EXPW_PASS_AUTO = 0, EXPW_PASS_TILED = 1, EXPW_PASS_STREAMED = 2 };
 int32_t expw_set_pass_kernel(expw_op* op, int32_t kind);
@@ -217,8 +220,8 @@ int32_t expw_set_pass_kernel(expw_op* op, int32_t kind);
  * is this library's): times expw_step_faber of degree m and step dt on
  * scratch_dev (a state vector of the op's dtype, overwritten) for every
  * terms-per-pass depth the layout admits (2D order 4 FP32: 1..6, FP64 and
- * order 8: 1..4, 3D FP32 order 4: 1..2, else 1) and, for 2D order-4 passes,
- * both pass kernels; keeps the fastest on the operator (as expw_set_tuning
+ * order 8: 1..4, 3D FP32 order 4: 1..2, else 1) and, for 2D passes, both
+ * pass kernels; keeps the fastest on the operator (as expw_set_tuning
  * and expw_set_pass_kernel would; batches created from the operator use
  * its depth) and returns it in fuse_out, pass_kernel_out and ms_out (one
  * step, ms; any may be NULL). cache_path (NULL = none): a text file with one

@@ -478,7 +478,16 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
   faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a);
   for (int j = 0; j < m; ++j) q[j] = 0.0;
   const int p = op->taylor_p;
-  const int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m, g.N);
+  int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m, g.N);
+  if (K == 4 && DIM == 2 && BC == 0 && fuse > 1 &&
+      (op->pass_kernel == EXPW_PASS_STREAMED ||
+       (op->pass_kernel == EXPW_PASS_AUTO && stream2d_fits(g.n[0], g.n[1], 4, K)))) {
+    // streamed passes of order 8: automatically four terms at FP32 (8192 x
+    // 4096, m = 16: 163 against 116 G grid-pt matvecs/s for three; tiles stay
+    // at three), at most three in FP64 (four spill)
+    if (op->fuse == 0 && sizeof(T) == 4) fuse = std::min(4, m);
+    if (sizeof(T) == 8 && fuse > 3) fuse = 3;
+  }
   for (int64_t st = 0; st < nsteps; ++st) {
     const double t = t0 + st * dt;
     if (op->n_src > 0) {
@@ -509,10 +518,10 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
               // the last pass (no terms kept) writes the step's result
               const RecRun<T> rr = state_out ? rec_run(op, traces, st) : RecRun<T>{nullptr, 0, 0};
               recorded = recorded || rr.out != nullptr;
-              if constexpr (K == 2) {
+              if constexpr (K == 2 || K == 4) {
                 if (op->pass_kernel == EXPW_PASS_STREAMED ||
-                    (op->pass_kernel == EXPW_PASS_AUTO && stream2d_fits(g.n[0], g.n[1], n)))
-                  return launch_stream_pass<T>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1, rr);
+                    (op->pass_kernel == EXPW_PASS_AUTO && stream2d_fits(g.n[0], g.n[1], n, K)))
+                  return launch_stream_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1, rr);
                 return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1, rr);
               } else
                 return launch_pass<T, K>(n, op->stream, &op->prof, g, src0, vp, vpp, acc_in, ol, opv, acc_out, state_out, j, first, a, q, el.kappa, el.inv_ws, el.c0, el.c1, rr);
@@ -1908,7 +1917,7 @@ int32_t expw_autotune(expw_op* op, int32_t m, double dt, void* scratch, const ch
     }
   }
   if (fuse < 0) {
-    // candidates: every depth the layout admits, and both 2D order-4 pass kernels
+    // candidates: every depth the layout admits, and both 2D pass kernels
     const bool f32 = g.dtype == EXPW_F32;
     int smax = 1;
     if (g.bc == EXPW_BC_ZERO) {
@@ -1924,7 +1933,7 @@ int32_t expw_autotune(expw_op* op, int32_t m, double dt, void* scratch, const ch
     int32_t rc = EXPW_OK;
     const int reps = 3;
     for (int fz = 1; fz <= std::min(smax, m) && rc == EXPW_OK; ++fz) {
-      const bool two = g.ndim == 2 && g.order == 4 && g.bc == EXPW_BC_ZERO && fz >= 2;
+      const bool two = g.ndim == 2 && g.bc == EXPW_BC_ZERO && fz >= 2;
       for (int pkk : {EXPW_PASS_TILED, EXPW_PASS_STREAMED}) {
         if (!two && pkk == EXPW_PASS_STREAMED) continue;
         op->fuse = fz;

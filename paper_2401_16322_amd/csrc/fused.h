@@ -277,8 +277,9 @@ int fused_depth(int requested, int m, int64_t npts) {
   if (DIM == 3) return (K == 2 && sizeof(T) == 4 && requested != 1 && m >= 2) ? 2 : 1;
   if (3 * npts >= (int64_t(1) << 31)) return 1;
   // order 4: the row-streaming or tiled passes, up to 6 terms at FP32 and 4
-  // at FP64, default 6 (FP32) and 4 (FP64); order 8: the tiled passes, up to
-  // 4, default 3
+  // at FP64, default 6 (FP32) and 4 (FP64); order 8: the tiled or
+  // row-streaming passes, up to 4, default 3 (the Faber step raises it to 4
+  // for streamed FP32 passes and caps streamed FP64 passes at 3)
   const int smax = (K == 2 && sizeof(T) == 4) ? 6 : 4;
   int s = requested == 0 ? (K == 2 ? (sizeof(T) == 4 ? 6 : 4) : 3) : requested;
   if (s > smax) s = smax;

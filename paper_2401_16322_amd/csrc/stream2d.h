@@ -1,6 +1,9 @@
-// Row-streaming Faber pass for 2D grids (order 4, zero ghost values): S
+// Row-streaming Faber pass for 2D grids (order 4 or 8, zero ghost values): S
 // consecutive recurrence terms per HBM sweep (Sec. 3.2, Faber recurrence),
-// with no recomputation along z.
+// with no recomputation along z. The description below is for order 4 (K = 2
+// weights per side); at order 8 (K = 4) every lag, reach and halo of 2 is K
+// (a level K rows behind the previous one, K columns of halo per level, queues
+// of 2K + 1 rows).
 //
 // A workgroup of 512 threads owns a band of 512 - 4S output columns and a
 // segment of rows; thread t owns column t of the band grown by 2S on each
@@ -59,12 +62,12 @@ struct StreamArgs {
 };
 
 // Queue depth of level L (-1 = the input): the z-stencil and the point
-// value of the next level need the last 5 rows, the sum at the last level's
-// row needs 2(S - 1 - L) + 1.
-template <int S, bool FIRST>
+// value of the next level need the last 2K + 1 rows, the sum at the last
+// level's row needs K(S - 1 - L) + 1.
+template <int K, int S, bool FIRST>
 constexpr int queue_depth(int L) {
-  const int need = (L < 0 && !FIRST) ? 5 : 2 * (S - 1 - L) + 1;
-  return need > 5 ? need : 5;
+  const int need = (L < 0 && !FIRST) ? 2 * K + 1 : K * (S - 1 - L) + 1;
+  return need > 2 * K + 1 ? need : 2 * K + 1;
 }
 
 template <typename T, int D>
@@ -87,15 +90,15 @@ struct RowQueue {
   }
 };
 
-template <typename T, int S, bool FIRST>
+template <typename T, int K, int S, bool FIRST>
 struct Levels {
-  RowQueue<T, queue_depth<S, FIRST>(-1)> in;
-  RowQueue<T, queue_depth<S, FIRST>(0)> l0;
-  RowQueue<T, queue_depth<S, FIRST>(1)> l1;
-  RowQueue<T, queue_depth<S, FIRST>(2)> l2;
-  RowQueue<T, queue_depth<S, FIRST>(3)> l3;
-  RowQueue<T, queue_depth<S, FIRST>(4)> l4;
-  RowQueue<T, queue_depth<S, FIRST>(5)> l5;
+  RowQueue<T, queue_depth<K, S, FIRST>(-1)> in;
+  RowQueue<T, queue_depth<K, S, FIRST>(0)> l0;
+  RowQueue<T, queue_depth<K, S, FIRST>(1)> l1;
+  RowQueue<T, queue_depth<K, S, FIRST>(2)> l2;
+  RowQueue<T, queue_depth<K, S, FIRST>(3)> l3;
+  RowQueue<T, queue_depth<K, S, FIRST>(4)> l4;
+  RowQueue<T, queue_depth<K, S, FIRST>(5)> l5;
 };
 
 template <int L, typename Q>
@@ -114,13 +117,14 @@ __device__ __forceinline__ auto& level_q(Q& q) {
 // sum goes to acc_out (FP64), or to state_out rounded to T on a step's last
 // pass (state_out must not alias vp or vpp). out_last / out_prev: the pass's
 // last two terms (nullptr on the last pass). Requires 3 * points < 2^31.
-template <typename T, int S, bool FIRST>
+template <typename T, int K, int S, bool FIRST>
 __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
-    Geo<T, 2, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp,
+    Geo<T, K, 2> g, const T* __restrict__ vp, const T* __restrict__ vpp,
     const double* __restrict__ acc_in, T* __restrict__ out_last, T* __restrict__ out_prev,
     double* __restrict__ acc_out, T* __restrict__ state_out, StreamArgs<T, S> c, Src<T> src) {
   static_assert(S >= 2 && S <= 6, "2 to 6 terms per pass");
-  constexpr int K = 2, W = kStrNT - 2 * K * S;
+  static_assert(K == 2 || K == 4, "order 4 or 8");
+  constexpr int W = kStrNT - 2 * K * S;
   __shared__ T s_p[2][S][kStrNT];
   __shared__ T s_vx[2][S][kStrNT];
   const int nx = static_cast<int>(g.n[0]), nz = static_cast<int>(g.n[1]);
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
   // sources in this column: only rows whose flat index falls in [lo, hi]
   const bool src_col = src.n > 0 && xin;
 
-  Levels<T, S, FIRST> q;
+  Levels<T, K, S, FIRST> q;
   q.in.clear();
   q.l0.clear();
   q.l1.clear();
@@ -150,9 +154,9 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
   q.l4.clear();
   q.l5.clear();
 
-  // the values v_{j-2} of level 0's row (k - 2) and the input row k + 1,
+  // the values v_{j-2} of level 0's row (k - K) and the input row k + 1,
   // loaded one iteration ahead
-  const int kbeg = z0 - 2 * S, kend = z1 - 1 + 2 * S;
+  const int kbeg = z0 - K * S, kend = z1 - 1 + K * S;
   auto ld_row = [&](int z, const T* f, T* out3) {
     const bool in = xin && z >= 0 && z < nz;
     const int gi = in ? z * nx + x : 0;
@@ -162,13 +166,13 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
   };
   T nxt_in[3], nxt_old[3];
   ld_row(kbeg, vp, nxt_in);
-  if (!FIRST) ld_row(kbeg - 2, vpp, nxt_old);
+  if (!FIRST) ld_row(kbeg - K, vpp, nxt_old);
   else nxt_old[0] = nxt_old[1] = nxt_old[2] = T(0);
-  // c^2 of the last 2S + 1 rows (level r reads row k - 2(r + 1): slot 2(r + 1)),
+  // c^2 of the last KS + 1 rows (level r reads row k - K(r + 1): slot K(r + 1)),
   // loaded with the input row
-  T c2q[2 * S + 1];
+  T c2q[K * S + 1];
 #pragma unroll
-  for (int d = 0; d <= 2 * S; ++d) c2q[d] = T(0);
+  for (int d = 0; d <= K * S; ++d) c2q[d] = T(0);
   auto ld_c2 = [&](int z) -> T {
     const bool in = xin && z >= 0 && z < nz;
     return in ? g.c2[z * nx + x] : T(0);
@@ -184,17 +188,18 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
     o3[2] = in ? acc_in[2 * N + gi] : 0.0;
   };
   double nxt_acc[3];
-  ld_acc(kbeg - 2 * S, nxt_acc);
+  ld_acc(kbeg - K * S, nxt_acc);
 
   for (int k = kbeg; k <= kend; ++k) {
     const int buf = k & 1;
     // 1. every level's row that the next level needs at this iteration (the
-    //    row two behind its newest) goes to LDS for the x-stencil
+    //    row K behind its newest after this iteration's push) goes to LDS for
+    //    the x-stencil
 #define EXPW_STAGE(L)                                                       \
     if constexpr (L + 1 < S) {                                              \
       auto& Q_ = level_q<L>(q);                                             \
-      s_p[buf][L + 1][t] = Q_.p[1];                                         \
-      s_vx[buf][L + 1][t] = Q_.vx[1];                                       \
+      s_p[buf][L + 1][t] = Q_.p[K - 1];                                     \
+      s_vx[buf][L + 1][t] = Q_.vx[K - 1];                                   \
     }
     EXPW_STAGE(-1) EXPW_STAGE(0) EXPW_STAGE(1) EXPW_STAGE(2) EXPW_STAGE(3) EXPW_STAGE(4)
 #undef EXPW_STAGE
@@ -203,36 +208,50 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
     const T old0[3] = {nxt_old[0], nxt_old[1], nxt_old[2]};
     const double acc_row[3] = {nxt_acc[0], nxt_acc[1], nxt_acc[2]};
 #pragma unroll
-    for (int d = 2 * S; d > 0; --d) c2q[d] = c2q[d - 1];
+    for (int d = K * S; d > 0; --d) c2q[d] = c2q[d - 1];
     c2q[0] = nxt_c2;
     if (k < kend) {
       ld_row(k + 1, vp, nxt_in);
-      if (!FIRST) ld_row(k - 1, vpp, nxt_old);
+      if (!FIRST) ld_row(k + 1 - K, vpp, nxt_old);
       nxt_c2 = ld_c2(k + 1);
-      ld_acc(k + 1 - 2 * S, nxt_acc);
+      ld_acc(k + 1 - K * S, nxt_acc);
     }
     q.in.push(cur_in[0], cur_in[1], cur_in[2]);
     __syncthreads();
 
-    // 3. levels 0..S-1 in order: level r computes row k - 2(r + 1)
+    // 3. levels 0..S-1 in order: level r computes row k - K(r + 1)
     T lastv[3] = {T(0), T(0), T(0)};  // level S-1's new row
 #define EXPW_LEVEL(R)                                                                      \
     if constexpr (R < S) {                                                                 \
       auto& P_ = level_q<R - 1>(q);                                                        \
-      const int z = k - 2 * (R + 1);                                                       \
+      const int z = k - K * (R + 1);                                                       \
       T nv[3] = {T(0), T(0), T(0)};                                                        \
       const bool act = t >= K * (R + 1) && t < kStrNT - K * (R + 1) && xin && z >= 0 && z < nz; \
       if (act) {                                                                           \
         const T* LP = s_p[buf][R];                                                         \
         const T* LX = s_vx[buf][R];                                                        \
-        const T pc = P_.p[2], vxc = P_.vx[2], vzc = P_.vz[2];                              \
-        const T dvx = w0 * (vxc - LX[t - 1]) + w1 * (LX[t + 1] - LX[t - 2]);               \
-        const T dvz = w0 * (vzc - P_.vz[3]) + w1 * (P_.vz[1] - P_.vz[4]);                  \
-        const T dpx = w0 * (LP[t + 1] - pc) + w1 * (LP[t + 2] - LP[t - 1]);                \
-        const T dpz = w0 * (P_.p[1] - pc) + w1 * (P_.p[0] - P_.p[3]);                      \
+        const T pc = P_.p[K], vxc = P_.vx[K], vzc = P_.vz[K];                              \
+        T dvx, dvz, dpx, dpz;                                                              \
+        if constexpr (K == 2) {                                                            \
+          dvx = w0 * (vxc - LX[t - 1]) + w1 * (LX[t + 1] - LX[t - 2]);                     \
+          dvz = w0 * (vzc - P_.vz[3]) + w1 * (P_.vz[1] - P_.vz[4]);                        \
+          dpx = w0 * (LP[t + 1] - pc) + w1 * (LP[t + 2] - LP[t - 1]);                      \
+          dpz = w0 * (P_.p[1] - pc) + w1 * (P_.p[0] - P_.p[3]);                            \
+        } else {                                                                           \
+          dvx = g.wi[0] * (vxc - LX[t - 1]);                                               \
+          dvz = g.wi[0] * (vzc - P_.vz[K + 1]);                                            \
+          dpx = g.wi[0] * (LP[t + 1] - pc);                                                \
+          dpz = g.wi[0] * (P_.p[K - 1] - pc);                                              \
+          _Pragma("unroll") for (int l = 2; l <= K; ++l) {                                 \
+            dvx += g.wi[l - 1] * (LX[t + l - 1] - LX[t - l]);                              \
+            dvz += g.wi[l - 1] * (P_.vz[K - l + 1] - P_.vz[K + l]);                        \
+            dpx += g.wi[l - 1] * (LP[t + l] - LP[t + 1 - l]);                              \
+            dpz += g.wi[l - 1] * (P_.p[K - l] - P_.p[K - 1 + l]);                          \
+          }                                                                                \
+        }                                                                                  \
         const int gi = z * nx + x;                                                         \
         const T sp_s = sxi_s + g.sint[1][z] * iws;                                         \
-        const T hp = -c2q[2 * (R + 1)] * (dvx + dvz) - sp_s * pc;                          \
+        const T hp = -c2q[K * (R + 1)] * (dvx + dvz) - sp_s * pc;                          \
         const T hvx = -dpx - sxh_s * vxc;                                                  \
         const T hvz = -dpz - g.shalf[1][z] * iws * vzc;                                    \
         T o0, o1, o2;                                                                      \
@@ -242,9 +261,9 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
           o2 = old0[2];                                                                    \
         } else {                                                                           \
           auto& O_ = level_q<R - 2>(q);                                                    \
-          o0 = O_.p[4];                                                                    \
-          o1 = O_.vx[4];                                                                   \
-          o2 = O_.vz[4];                                                                   \
+          o0 = O_.p[2 * K];                                                                \
+          o1 = O_.vx[2 * K];                                                               \
+          o2 = O_.vz[2 * K];                                                               \
         }                                                                                  \
         T src_v = T(0);                                                                    \
         if (src_col && gi >= src.lo && gi <= src.hi) src_v = src_value(src, gi) * c.q[R];  \
@@ -263,16 +282,16 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
     EXPW_LEVEL(0) EXPW_LEVEL(1) EXPW_LEVEL(2) EXPW_LEVEL(3) EXPW_LEVEL(4) EXPW_LEVEL(5)
 #undef EXPW_LEVEL
 
-    // 4. the output row k - 2S: v_last, v_prev and the sum
-    const int zo = k - 2 * S;
+    // 4. the output row k - KS: v_last, v_prev and the sum
+    const int zo = k - K * S;
     if (out_col && zo >= z0 && zo < z1) {
       const int gi = zo * nx + x;
       double s3[3];
       if constexpr (FIRST) {
-        auto& I_ = q.in;  // v_0 at row zo: slot 2S of the input queue
-        s3[0] = c.a_first * static_cast<double>(I_.p[2 * S]);
-        s3[1] = c.a_first * static_cast<double>(I_.vx[2 * S]);
-        s3[2] = c.a_first * static_cast<double>(I_.vz[2 * S]);
+        auto& I_ = q.in;  // v_0 at row zo: slot KS of the input queue
+        s3[0] = c.a_first * static_cast<double>(I_.p[K * S]);
+        s3[1] = c.a_first * static_cast<double>(I_.vx[K * S]);
+        s3[2] = c.a_first * static_cast<double>(I_.vz[K * S]);
       } else {
         s3[0] = acc_row[0];
         s3[1] = acc_row[1];
@@ -281,7 +300,7 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
 #define EXPW_SUM(R)                                                              \
       if constexpr (R + 1 < S) {                                                 \
         auto& Q_ = level_q<R>(q);                                                \
-        constexpr int d = 2 * (S - 1 - R);                                       \
+        constexpr int d = K * (S - 1 - R);                                       \
         s3[0] = fma(c.a[R], static_cast<double>(Q_.p[d]), s3[0]);                \
         s3[1] = fma(c.a[R], static_cast<double>(Q_.vx[d]), s3[1]);               \
         s3[2] = fma(c.a[R], static_cast<double>(Q_.vz[d]), s3[2]);               \
@@ -292,13 +311,13 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
       s3[1] = fma(c.a[S - 1], static_cast<double>(lastv[1]), s3[1]);
       s3[2] = fma(c.a[S - 1], static_cast<double>(lastv[2]), s3[2]);
       if (out_last) {
-        auto& V_ = level_q<S - 2>(q);  // v_prev at row zo: slot 2 of level S-2
+        auto& V_ = level_q<S - 2>(q);  // v_prev at row zo: slot K of level S-2
         out_last[gi] = lastv[0];
         out_last[N + gi] = lastv[1];
         out_last[2 * N + gi] = lastv[2];
-        out_prev[gi] = V_.p[2];
-        out_prev[N + gi] = V_.vx[2];
-        out_prev[2 * N + gi] = V_.vz[2];
+        out_prev[gi] = V_.p[K];
+        out_prev[N + gi] = V_.vx[K];
+        out_prev[2 * N + gi] = V_.vz[K];
       }
       if (state_out) {
         const T pv = static_cast<T>(s3[0]);
@@ -317,7 +336,7 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
 
 // Workgroups of a pass kernel resident on the device at once (CUs times the
 // occupancy of the kernel; 1024 when the runtime cannot say).
-template <typename T, int S, bool FIRST>
+template <typename T, int K, int S, bool FIRST>
 int stream2d_capacity() {
   static int cap = 0;  // per kernel, at first use
   if (cap == 0) {
@@ -325,7 +344,7 @@ int stream2d_capacity() {
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void*>(k_faber_stream2d<T, S, FIRST>), kStrNT, 0) == hipSuccess &&
+            &per, reinterpret_cast<const void*>(k_faber_stream2d<T, K, S, FIRST>), kStrNT, 0) == hipSuccess &&
         cus > 0 && per > 0)
       cap = cus * per;
     else
@@ -354,13 +373,13 @@ inline int stream2d_zseg(int64_t nz, int bands, int capacity, int S) {
   return static_cast<int>((nz + best_segs - 1) / best_segs);
 }
 
-template <typename T, int S>
-int32_t launch_stream2d(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<T> src,
+template <typename T, int K, int S>
+int32_t launch_stream2d(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                         const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
                         double* acc_out, T* state_out, int j, bool first, const double* a,
                         const double* qv, double kappa, double inv_ws, double c0, double c1,
                         RecRun<T> rec) {
-  constexpr int W = kStrNT - 4 * S;
+  constexpr int W = kStrNT - 2 * K * S;
   StreamArgs<T, S> c{};
   c.rec = rec;
   c.kappa = static_cast<T>(kappa);
@@ -374,7 +393,9 @@ int32_t launch_stream2d(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, S
     c.q[r] = static_cast<T>(qv[jj - 1]);
   }
   c.bands = static_cast<int>((g.n[0] + W - 1) / W);
-  c.zseg = stream2d_zseg(g.n[1], c.bands, first ? stream2d_capacity<T, S, true>() : stream2d_capacity<T, S, false>(), S);
+  // (the cost model's warm-up in units of 2 rows: S at order 4, 2S at order 8)
+  c.zseg = stream2d_zseg(g.n[1], c.bands,
+                         first ? stream2d_capacity<T, K, S, true>() : stream2d_capacity<T, K, S, false>(), K * S / 2);
   const int64_t blocks = static_cast<int64_t>(c.bands) * ((g.n[1] + c.zseg - 1) / c.zseg);
   if (blocks > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "streamed Faber pass: grid too large");
   // the source term of a level is q_r amp: src.q is set to 1 so that
@@ -383,11 +404,11 @@ int32_t launch_stream2d(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, S
   const double bytes = (3 + 1 + (first ? 0 : 3) + (out_last ? 6 : 0) + (state_out ? 3 : 0)) * sizeof(T) +
                        ((first ? 0 : 3) + (state_out ? 0 : 3)) * sizeof(double);
   if (first)
-    launch_timed(prof, st, EXPW_KERNEL_FABER, bytes * g.N, k_faber_stream2d<T, S, true>,
+    launch_timed(prof, st, EXPW_KERNEL_FABER, bytes * g.N, k_faber_stream2d<T, K, S, true>,
                  dim3(static_cast<unsigned>(blocks)), dim3(kStrNT), g, vp, vpp, acc_in, out_last,
                  out_prev, acc_out, state_out, c, src);
   else
-    launch_timed(prof, st, EXPW_KERNEL_FABER, bytes * g.N, k_faber_stream2d<T, S, false>,
+    launch_timed(prof, st, EXPW_KERNEL_FABER, bytes * g.N, k_faber_stream2d<T, K, S, false>,
                  dim3(static_cast<unsigned>(blocks)), dim3(kStrNT), g, vp, vpp, acc_in, out_last,
                  out_prev, acc_out, state_out, c, src);
   const hipError_t e = hipGetLastError();
@@ -398,24 +419,31 @@ int32_t launch_stream2d(hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, S
 // The streamed passes need long row segments to amortize their 4S-row
 // warm-up; a grid too small to give the chip 512 workgroups with segments
 // of 64 rows or more takes the tiled passes (fused.h).
-inline bool stream2d_fits(int64_t nx, int64_t nz, int S) {
-  const int64_t bands = (nx + (kStrNT - 4 * S) - 1) / (kStrNT - 4 * S);
+inline bool stream2d_fits(int64_t nx, int64_t nz, int S, int K = 2) {
+  const int W = kStrNT - 2 * K * S;
+  const int64_t bands = (nx + W - 1) / W;
   return bands * ((nz + 63) / 64) >= 512;
 }
 
-template <typename T>
-int32_t launch_stream_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, 2, 2>& g, Src<T> src,
+template <typename T, int K>
+int32_t launch_stream_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                            const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
                            double* acc_out, T* state_out, int j, bool first, const double* a,
                            const double* q, double kappa, double inv_ws, double c0, double c1,
                            RecRun<T> rec) {
 #define EXPW_SPASS(S_)                                                                           \
   case S_:                                                                                       \
-    return launch_stream2d<T, S_>(st, prof, g, src, vp, vpp, acc_in, out_last, out_prev, acc_out, \
+    return launch_stream2d<T, K, S_>(st, prof, g, src, vp, vpp, acc_in, out_last, out_prev, acc_out, \
                                   state_out, j, first, a, q, kappa, inv_ws, c0, c1, rec);
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4 && K == 2) {
     switch (n) {
       EXPW_SPASS(2) EXPW_SPASS(3) EXPW_SPASS(4) EXPW_SPASS(5) EXPW_SPASS(6)
+      default: break;
+    }
+  } else if constexpr (sizeof(T) == 8 && K == 4) {
+    // (four terms of order 8 in FP64 spill: at most three)
+    switch (n) {
+      EXPW_SPASS(2) EXPW_SPASS(3)
       default: break;
     }
   } else {

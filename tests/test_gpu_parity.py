@@ -74,6 +74,32 @@ def test_streamed_passes_match_oracle_and_tiled(dtype, n, m, fuse):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,m,fuse", [((900, 300), 16, 4), ((900, 300), 7, 3), ((257, 129), 9, 2),
+                                      ((150, 70), 10, 4), ((9, 5), 8, 4), ((1, 40), 8, 4), ((70, 1), 9, 3)])
+def test_streamed_passes_order8_match_oracle_and_tiled(dtype, n, m, fuse):
+    """The row-streaming passes at the paper's 8th order (every term four rows
+    behind the previous one, four halo columns per term; FP64 at most three
+    terms per pass): two bands with a ragged last one, row segments with
+    their warm-up, sources, passes of 2..4 terms and a shorter last pass, and
+    degenerate grids. Against the oracle on its own ellipse and against the
+    tiled passes."""
+    from paper_2401_16322_amd.expwave import EXPW_PASS_STREAMED, EXPW_PASS_TILED
+    case = make_case(n, dtype, order=8, seed=23, n_src=3 if min(n) > 2 else 1,
+                     abc=min(6, max(1, min(n) // 3)))
+    case.op.set_tuning(fuse)
+    dt, nst = 2e-3, 2
+    outs = {}
+    for kind in (EXPW_PASS_STREAMED, EXPW_PASS_TILED):
+        case.op.set_pass_kernel(kind)
+        U = to_dev(case, case.U0)
+        case.op.step_faber(U, 0.03, dt, m, nst)
+        outs[kind] = U.cpu().numpy()
+    ref, _, _ = run(case.prob, "faber", case.U0, 0.03, dt, nst, m=m, p=case.p, ellipse=case.prob.ellipse())
+    assert rel_l2(outs[EXPW_PASS_STREAMED], ref) <= TOL[dtype]
+    assert rel_l2(outs[EXPW_PASS_STREAMED], outs[EXPW_PASS_TILED]) <= (1e-13 if dtype == "float64" else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("fuse", [2, 4, 8])
 def test_fused_and_unfused_faber_agree_to_rounding(dtype, fuse):
     """Tiling/fusion invariance: results depend on the fusion depth only through rounding."""
