@@ -494,7 +494,9 @@ def bench_steps(args, w, methods, op, c2_np, tdt, dev):
                    "receivers": int(rec.size), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom, w.name, args.dtype),
+                     # (the counters were taken at order 4 with the automatic tuning)
+                     "traffic": (measured_traffic(dom, w.name, args.dtype)
+                                 if args.order == 4 and args.fuse == 0 else None),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
                      "algorithmic_bytes_per_launch": round(nbytes / launches) if launches else None,
                      "avg_launch_us": round(1e3 * ms / launches, 3) if launches else None,
