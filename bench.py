@@ -36,7 +36,7 @@ CSRC = os.path.join(ROOT, "paper_2401_16322_amd", "csrc")
 # the device headers it includes)
 KERNEL_SOURCES = {
     "krylov_arnoldi": ("arnoldi.h", "device_common.h", "kernels.h"),
-    "faber": ("fused.h", "fused3d.h", "stream2d.h", "term_o4.h", "device_common.h", "kernels.h"),
+    "faber": ("fused.h", "fused3d.h", "stream2d.h", "term_zero.h", "device_common.h", "kernels.h"),
     "pml_faber_pair": ("pml.h", "device_common.h"),
     "pml_faber_stream": ("pml_stream.h", "pml.h", "device_common.h", "kernels.h"),
     "pml_faber_term": ("pml.h", "device_common.h"),

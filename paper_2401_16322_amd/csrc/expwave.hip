@@ -26,7 +26,7 @@
 #include "profiler.h"
 #include "stream.h"
 #include "stream2d.h"
-#include "term_o4.h"
+#include "term_zero.h"
 
 struct expw_op {
   expw_grid g;
@@ -383,21 +383,21 @@ struct WorkEllipse {
   }
 };
 
-// Stencil arithmetic of the one-term order-4 kernel (see k_faber_term_o4):
+// Stencil arithmetic of the one-term zero-ghost kernel (see k_faber_term_zero):
 // difference sums in the storage precision over integer weights.
 template <typename T>
 using TermSC = T;
 
-// One Faber term per sweep: the order-4 zero-ghost kernel where it applies,
-// else the generic one (same arguments and outputs).
+// One Faber term per sweep: the zero-ghost kernel of order 4 or 8 where it
+// applies, else the generic one (same arguments and outputs).
 template <typename T, int K, int BC, int DIM>
 void launch_term(expw_op* op, const Geo<T, K, DIM>& g, double bytes, const T* vp, const T* vpp,
                  T* vout, const double* acc_in, double* acc_out, T* state_out, const FaberTerm& c,
                  const Src<T>& src) {
-  if constexpr (K == 2 && BC == 0) {
+  if constexpr ((K == 2 || K == 4) && BC == 0) {
     if ((DIM + 1) * g.N < (int64_t(1) << 31)) {
-      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, bytes, k_faber_term_o4<T, DIM, TermSC<T>>,
-                   o4_grid<DIM>(g.n), dim3(kO4X * kO4Y), g, vp, vpp, vout, acc_in, acc_out, state_out,
+      launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, bytes, k_faber_term_zero<T, K, DIM, TermSC<T>>,
+                   term_zero_grid<DIM>(g.n), dim3(kTzX * kTzY), g, vp, vpp, vout, acc_in, acc_out, state_out,
                    c, src);
       return;
     }

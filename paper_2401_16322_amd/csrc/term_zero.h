@@ -1,10 +1,11 @@
-// One Faber term per sweep for the order-4 staggered stencil with zero ghost
-// values (Sec. 2.1), in 2D and 3D: the one-term path of the Faber step (3D
-// steps, a single final term after fused passes, depth 1).
+// One Faber term per sweep for the staggered stencils of order 4 and 8 (K = 2
+// or 4 weights per side) with zero ghost values (Sec. 2.1), in 2D and 3D: the
+// one-term path of the Faber step (3D steps, a single final term after fused
+// passes, depth 1).
 //
 // A 64 x 4 workgroup covers 64 consecutive x-points of 4 consecutive rows
 // (one plane z in 3D), so every wave reads 64 consecutive values of a row.
-// Each point's 4 (3D: 4 fields) neighbour values along each axis are loaded
+// Each point's 2K neighbour values of p and of v_a along each axis are loaded
 // with 32-bit offsets that are clamped to the point itself when the
 // neighbour lies outside the grid (the loaded value is then replaced by
 // zero), so no load sits behind a branch and the compiler issues all of a
@@ -25,7 +26,7 @@
 
 namespace expw {
 
-constexpr int kO4X = 64, kO4Y = 4;
+constexpr int kTzX = 64, kTzY = 4;
 
 template <typename T>
 __device__ __forceinline__ T ld_or0(const T* __restrict__ f, int base, int off, bool ok) {
@@ -42,14 +43,15 @@ __device__ __forceinline__ SC to_sc(T v) {
 // (ceil(nx / 64), ceil(nz / 4), 1) in 2D. Requires (DIM + 1) * points < 2^31.
 // Outputs as in k_faber_term (vout may alias vpp, acc_out may alias acc_in,
 // state_out may alias vpp; vp must not alias any output).
-template <typename T, int DIM, typename SC>
-__global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g, const T* __restrict__ vp,
-                                                              const T* vpp, T* vout,
-                                                              const double* acc_in, double* acc_out,
-                                                              T* state_out, FaberTerm c, Src<T> src) {
+template <typename T, int K, int DIM, typename SC>
+__global__ __launch_bounds__(kTzX * kTzY) void k_faber_term_zero(Geo<T, K, DIM> g, const T* __restrict__ vp,
+                                                                const T* vpp, T* vout,
+                                                                const double* acc_in, double* acc_out,
+                                                                T* state_out, FaberTerm c, Src<T> src) {
+  static_assert(K == 2 || K == 4, "order 4 or 8");
   const int nx = static_cast<int>(g.n[0]), n1 = static_cast<int>(g.n[1]);
-  const int i = blockIdx.x * kO4X + (threadIdx.x & (kO4X - 1));
-  const int j = blockIdx.y * kO4Y + (threadIdx.x >> 6);
+  const int i = blockIdx.x * kTzX + (threadIdx.x & (kTzX - 1));
+  const int j = blockIdx.y * kTzY + (threadIdx.x >> 6);
   const int k = DIM == 3 ? static_cast<int>(blockIdx.z) : 0;
   if (i >= nx || j >= n1) return;
   const int n2 = DIM == 3 ? static_cast<int>(g.n[2]) : 1;
@@ -60,21 +62,21 @@ __global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g,
   const int ext[3] = {nx, n1, n2};
   const int str[3] = {1, sy, sz};
   const T* p = vp;
-  // loads: p at the point and at -1, +1, +2 along each axis; v_a at the point
-  // and at -2, -1, +1 along axis a
-  T pm1[DIM], pp1[DIM], pp2[DIM], vm2[DIM], vm1[DIM], vp1[DIM], vc[DIM];
+  // loads: p at the point and at 1-K .. -1, +1 .. +K along each axis (pk[a][l]
+  // = p at offset l - K + 1, l = 0..2K-1, the point itself at l = K - 1); v_a at
+  // -K .. K-1 along axis a (vk[a][l] at offset l - K, the point at l = K)
+  T pk[DIM][2 * K], vk[DIM][2 * K];
   const T pc = p[idx];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const T* v = vp + (1 + a) * N;
     const int x = coord[a], n = ext[a], s = str[a];
-    pm1[a] = ld_or0(p, idx, -s, x >= 1);
-    pp1[a] = ld_or0(p, idx, s, x + 1 < n);
-    pp2[a] = ld_or0(p, idx, 2 * s, x + 2 < n);
-    vm2[a] = ld_or0(v, idx, -2 * s, x >= 2);
-    vm1[a] = ld_or0(v, idx, -s, x >= 1);
-    vp1[a] = ld_or0(v, idx, s, x + 1 < n);
-    vc[a] = v[idx];
+#pragma unroll
+    for (int l = 0; l < 2 * K; ++l) {
+      const int op = l - K + 1, ov = l - K;
+      pk[a][l] = op == 0 ? pc : ld_or0(p, idx, op * s, x + op >= 0 && x + op < n);
+      vk[a][l] = ov == 0 ? v[idx] : ld_or0(v, idx, ov * s, x + ov >= 0 && x + ov < n);
+    }
   }
   const T c2 = g.c2[idx];
   T old[DIM + 1];
@@ -87,8 +89,9 @@ __global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g,
   // H v at the point: difference sums in SC (integer weights unless SC is
   // FP64), the weight factor and the rest in FP64
   constexpr bool kInt = !(sizeof(SC) == 8 && sizeof(T) == 4);
-  const SC w0 = kInt ? static_cast<SC>(g.wi[0]) : static_cast<SC>(g.wd[0]);
-  const SC w1 = kInt ? static_cast<SC>(g.wi[1]) : static_cast<SC>(g.wd[1]);
+  SC w[K];
+#pragma unroll
+  for (int l = 0; l < K; ++l) w[l] = kInt ? static_cast<SC>(g.wi[l]) : static_cast<SC>(g.wd[l]);
   const double wsc = kInt ? g.wscale : 1.0;
   SC div = SC(0);
   double o[DIM + 1], s[DIM + 1];
@@ -96,11 +99,23 @@ __global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g,
   s[0] = static_cast<double>(pc);
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    const SC dv = w0 * (to_sc<SC>(vc[a]) - to_sc<SC>(vm1[a])) + w1 * (to_sc<SC>(vp1[a]) - to_sc<SC>(vm2[a]));
-    const SC dp = w0 * (to_sc<SC>(pp1[a]) - to_sc<SC>(pc)) + w1 * (to_sc<SC>(pp2[a]) - to_sc<SC>(pm1[a]));
+    // dv = sum_l w_l (v[x + l - 1] - v[x - l]), dp = sum_l w_l (p[x + l] - p[x + 1 - l])
+    SC dv, dp;
+    if constexpr (K == 2) {
+      dv = w[0] * (to_sc<SC>(vk[a][2]) - to_sc<SC>(vk[a][1])) + w[1] * (to_sc<SC>(vk[a][3]) - to_sc<SC>(vk[a][0]));
+      dp = w[0] * (to_sc<SC>(pk[a][2]) - to_sc<SC>(pc)) + w[1] * (to_sc<SC>(pk[a][3]) - to_sc<SC>(pk[a][0]));
+    } else {
+      dv = w[0] * (to_sc<SC>(vk[a][K]) - to_sc<SC>(vk[a][K - 1]));
+      dp = w[0] * (to_sc<SC>(pk[a][K]) - to_sc<SC>(pc));
+#pragma unroll
+      for (int l = 2; l <= K; ++l) {
+        dv += w[l - 1] * (to_sc<SC>(vk[a][K + l - 1]) - to_sc<SC>(vk[a][K - l]));
+        dp += w[l - 1] * (to_sc<SC>(pk[a][K + l - 1]) - to_sc<SC>(pk[a][K - l]));
+      }
+    }
     div += dv;
     sp += static_cast<double>(g.sint[a][coord[a]]);
-    s[1 + a] = static_cast<double>(vc[a]);
+    s[1 + a] = static_cast<double>(vk[a][K]);
     o[1 + a] = -static_cast<double>(dp) * wsc - static_cast<double>(g.shalf[a][coord[a]]) * s[1 + a];
   }
   o[0] = -static_cast<double>(c2) * (static_cast<double>(div) * wsc) - sp * s[0];
@@ -123,11 +138,11 @@ __global__ __launch_bounds__(kO4X * kO4Y) void k_faber_term_o4(Geo<T, 2, DIM> g,
 }
 
 template <int DIM>
-inline dim3 o4_grid(const int64_t* n) {
-  return DIM == 3 ? dim3(static_cast<unsigned>((n[0] + kO4X - 1) / kO4X),
-                         static_cast<unsigned>((n[1] + kO4Y - 1) / kO4Y), static_cast<unsigned>(n[2]))
-                  : dim3(static_cast<unsigned>((n[0] + kO4X - 1) / kO4X),
-                         static_cast<unsigned>((n[1] + kO4Y - 1) / kO4Y), 1u);
+inline dim3 term_zero_grid(const int64_t* n) {
+  return DIM == 3 ? dim3(static_cast<unsigned>((n[0] + kTzX - 1) / kTzX),
+                         static_cast<unsigned>((n[1] + kTzY - 1) / kTzY), static_cast<unsigned>(n[2]))
+                  : dim3(static_cast<unsigned>((n[0] + kTzX - 1) / kTzX),
+                         static_cast<unsigned>((n[1] + kTzY - 1) / kTzY), 1u);
 }
 
 }  // namespace expw

@@ -114,6 +114,21 @@ def test_fused_and_unfused_faber_agree_to_rounding(dtype, fuse):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,m", [((21, 17, 13), 5), ((70, 9, 6), 12), ((1, 9, 11), 4), ((37, 29), 7)])
+def test_faber_order8_one_term_kernel_matches_oracle(dtype, n, m):
+    """The paper's 8th-order stencil one term per sweep with zero ghosts (the
+    zero-ghost term kernel at K = 4: every 3D order-8 step, and 2D with fuse
+    = 1), ragged in every direction, with sources, against the oracle."""
+    case = make_case(n, dtype, order=8, seed=27, n_src=2 if min(n) > 2 else 1, abc=2)
+    case.op.set_tuning(1)
+    dt, nst = 1.5e-3, 2
+    U = to_dev(case, case.U0)
+    case.op.step_faber(U, 0.02, dt, m, nst)
+    ref, _, _ = run(case.prob, "faber", case.U0, 0.02, dt, nst, m=m, p=case.p, ellipse=case.prob.ellipse())
+    assert rel_l2(U.cpu().numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n", [(5, 3), (1, 40), (70, 1), (13, 11, 9)])
 def test_faber_tiny_and_degenerate_grids(dtype, n):
     case = make_case(n, dtype, abc=1, seed=4)
