@@ -21,7 +21,9 @@
 // a surface row j < 4 finds level r-1's row y in slot 4 + y - j; the queues
 // of u and w_y are 13 and 12 rows deep for that. Level r is valid on columns
 // 4(r + 1) .. NT - 1 - 4(r + 1) of the band, so the last level covers the
-// output band exactly.
+// output band exactly. Level r's rows below the segment end plus 4(S - 1 - r)
+// feed nothing, so a level begins 8(r + 1) iterations into the walk and
+// pushes zeros before.
 //
 // Each level forms v_{j+r} = F_1 v_{j+r-1} - c_{j+r} v_{j+r-2} (+ q_r times
 // the source amplitude on the v equation) with the arithmetic of the one-term
@@ -277,7 +279,8 @@ __global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, co
       auto& P_ = ps_level<R - 1>(q);                                                               \
       const int jr = jin + 4 * (R + 1);                                                            \
       T nv[4] = {T(0), T(0), T(0), T(0)};                                                          \
-      const bool act = t >= H * (R + 1) && t < NT - H * (R + 1) && xin && jr >= 0 && jr < ny;     \
+      const bool act = t >= H * (R + 1) && t < NT - H * (R + 1) && xin && jr >= 0 && jr < ny &&   \
+                       k >= 8 * (R + 1);                                                           \
       if (act) {                                                                                   \
         const T* LU = s_u[buf][R];                                                                 \
         const T* LX = s_x[buf][R];                                                                 \

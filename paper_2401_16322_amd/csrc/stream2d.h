@@ -21,7 +21,10 @@
 // r is valid on columns 2(r + 1) .. 511 - 2(r + 1) of the band, so the last
 // level covers the output band exactly. Rows outside the grid are zero at
 // every level (the ghost rule), and a segment starts 2S rows early, so no
-// row is recomputed beyond that warm-up.
+// row is recomputed beyond that warm-up. Level r's rows before the segment
+// start minus 2(S - 1 - r) feed nothing (the next level's stencil, the older
+// term and the sum start there), so a level begins 4(r + 1) iterations into
+// the walk and pushes zeros before.
 //
 // The partial sum of an output row is formed when the last level reaches
 // it, in FP64: acc_in + sum_r a_r v_r (+ a_0 v_0 on the first pass), each
@@ -226,7 +229,8 @@ __global__ __launch_bounds__(kStrNT) void k_faber_stream2d(
       auto& P_ = level_q<R - 1>(q);                                                        \
       const int z = k - K * (R + 1);                                                       \
       T nv[3] = {T(0), T(0), T(0)};                                                        \
-      const bool act = t >= K * (R + 1) && t < kStrNT - K * (R + 1) && xin && z >= 0 && z < nz; \
+      const bool act = t >= K * (R + 1) && t < kStrNT - K * (R + 1) && xin && z >= 0 && z < nz && \
+                       k >= kbeg + 2 * K * (R + 1);                                        \
       if (act) {                                                                           \
         const T* LP = s_p[buf][R];                                                         \
         const T* LX = s_vx[buf][R];                                                        \
