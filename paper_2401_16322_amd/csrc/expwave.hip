@@ -30,6 +30,13 @@
 
 struct expw_op {
   expw_grid g;
+  // the Faber coefficients of the last (gamma, c0, c1, dt, m) a step used:
+  // steps taken one call at a time (an inversion's forward, recomputation and
+  // reverse sweeps) reuse them instead of recomputing the (m + 1) M-point
+  // trapezoidal sums (about 80 us on the host at m = 20)
+  double coef_key[4];
+  int coef_m;  // 0: none yet
+  double coef[1025];
   int K;
   double alpha[4];
   const void* c2;
@@ -467,6 +474,26 @@ int32_t faber_unfused(expw_op* op, const Geo<T, K, DIM>& g, const WorkEllipse& e
 // Faber steps; term_traces (nullable) records every term at the receivers
 // and then runs the terms one per sweep. big: the step's buffers
 // (faber_big_bytes); a, q: host scratch of m + 1 and m doubles.
+// a = the Faber coefficients a_0..a_m of the step (Sec. 3.2) for the working
+// ellipse, from the operator's cache when the last step had the same
+// ellipse, dt and m (m <= 1024).
+inline void step_coefficients(expw_op* op, double gamma, double c0, double c1, double dt, int m, double* a) {
+  if (m > 1024) {
+    faber_coefficients(gamma, c0, c1, dt, m, a);
+    return;
+  }
+  if (!(op->coef_m == m && op->coef_key[0] == gamma && op->coef_key[1] == c0 && op->coef_key[2] == c1 &&
+        op->coef_key[3] == dt)) {
+    faber_coefficients(gamma, c0, c1, dt, m, op->coef);
+    op->coef_key[0] = gamma;
+    op->coef_key[1] = c0;
+    op->coef_key[2] = c1;
+    op->coef_key[3] = dt;
+    op->coef_m = m;
+  }
+  std::memcpy(a, op->coef, static_cast<size_t>(m + 1) * sizeof(double));
+}
+
 template <typename T, int K, int BC, int DIM>
 int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nsteps, T* traces,
                    T* term_traces, char* big, double* a, double* q) {
@@ -475,7 +502,7 @@ int32_t faber_impl(expw_op* op, T* S, double t0, double dt, int m, int64_t nstep
   const FaberBufs<T> b = faber_bufs<T>(big, ns);
   double der[EXPW_MAX_TAYLOR], G[EXPW_MAX_TAYLOR];
   const WorkEllipse el(op);
-  faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a);
+  step_coefficients(op, el.gamma, el.c0, el.c1, dt, m, a);
   for (int j = 0; j < m; ++j) q[j] = 0.0;
   const int p = op->taylor_p;
   int fuse = fused_depth<T, K, BC, DIM>(op->fuse, m, g.N);
@@ -882,7 +909,7 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
   const unsigned grid = grid_for(g.N);
   const WorkEllipse el(op);
   std::vector<double> a(m + 1), q(m, 0.0), der(EXPW_MAX_TAYLOR), G(EXPW_MAX_TAYLOR);
-  faber_coefficients(el.gamma, el.c0, el.c1, dt, m, a.data());
+  step_coefficients(op, el.gamma, el.c0, el.c1, dt, m, a.data());
   const int p = op->taylor_p;
   if (op->n_src > 0) {
     source_derivs(op, 0, t, p, der.data());  // a table's row 0: one step per call
@@ -892,12 +919,34 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
     for (int j = 0; j < m; ++j) q[j] *= sc;
   }
   auto v = [&](int j) -> const T* { return j == 0 ? U : terms + (j - 1) * ns; };
-  // forward: v_j = F1 v_{j-1} - c_j v_{j-2} + source, j = 1..m-1
+  // forward: v_j = F1 v_{j-1} - c_j v_{j-2} + source, j = 1..m-1; on 2D
+  // zero-ghost grids in tiled passes of several terms that store every term
+  // (each pass reads its v_{j-1}, v_{j-2} from the terms already stored), a
+  // remaining single term one per sweep
+  int done = 0;
+  if constexpr (DIM == 2 && BC == 0 && (K == 2 || K == 4)) {
+    const int fz = fused_depth<T, K, BC, DIM>(op->fuse, m - 1, g.N);
+    if (fz > 1) {
+      const Src<T> src0 = make_src<T>(op, 0.0);
+      int j = 1;
+      while (m - j >= 2) {
+        const int n = std::min(fz, m - j);
+        if (int32_t rc = launch_pass<T, K>(n, op->stream, &op->prof, g, src0, v(j - 1), j > 1 ? v(j - 2) : nullptr,
+                                           nullptr, nullptr, nullptr, nullptr, nullptr, j, j == 1, a.data(),
+                                           q.data(), el.kappa, el.inv_ws, el.c0, el.c1, RecRun<T>{nullptr, 0, 0},
+                                           terms))
+          return rc;
+        if (int32_t rc = check_launch("adjoint: forward passes")) return rc;
+        j += n;
+      }
+      done = j - 1;
+    }
+  }
   FaberTerm f{};
   f.inv_gamma = 1.0 / el.gamma;
   f.c0 = el.c0;
   const double nf = DIM + 1, pb = static_cast<double>(g.N) * sizeof(T);
-  for (int j = 1; j < m; ++j) {
+  for (int j = done + 1; j < m; ++j) {
     f.cpp = j == 1 ? 0.0 : (j == 2 ? 2.0 * el.c1 : el.c1);
     launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, (nf + 1 + (j > 1 ? nf : 0) + nf) * pb,
                  k_faber_term<T, K, BC, DIM>, dim3(grid), dim3(kBlock), g, v(j - 1),

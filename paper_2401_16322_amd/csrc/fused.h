@@ -55,6 +55,12 @@ struct FusedArgs {
   double a[S];
   T cpp[S], q[S];
   RecRun<T> rec;  // receivers recorded from the sum (last pass of a step only)
+  // when set, every term j0 + r of the pass is also stored, over the tiles,
+  // at terms + (j0 + r - 1) * terms_ld (the terms of a step recomputed for
+  // its reverse sweep)
+  T* terms;
+  int64_t terms_ld;
+  int32_t j0;
 };
 
 // One pass over tile (tx_, ty_) of the recurrence terms r0..S-1 of an S-term
@@ -62,7 +68,8 @@ struct FusedArgs {
 // tile). 2D grids with 3 * points < 2^31.
 // acc_in: the FP64 sum of the previous passes (not read on the first); the
 // sum goes to acc_out (FP64) or, on a step's last pass, to state_out rounded
-// to T (state_out must not alias vp or vpp).
+// to T (state_out must not alias vp or vpp); with neither, the sum is not
+// formed (a pass that only stores its terms through c.terms).
 template <typename T, int S, int K = 2>
 __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __restrict__ vp,
                                              const T* __restrict__ vpp,
@@ -132,8 +139,9 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
     amp[i] = am;
     nv[i][0] = nv[i][1] = nv[i][2] = T(0);
   }
+  const bool sum = acc_out != nullptr || state_out != nullptr;
   // the partial sum of the tile (not read on the first pass)
-  if (!c.first) {
+  if (!c.first && sum) {
     for (int t = tid; t < TX * TY; t += kFusedNT) {
       const int ty = t / TX, tx = t - ty * TX;
       const int gxx = x0 + H + tx, gz = z0 + H + ty;
@@ -206,6 +214,12 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
           sacc[t] = fma(aj, static_cast<double>(nv[i][0]), sacc[t]);
           sacc[TX * TY + t] = fma(aj, static_cast<double>(nv[i][1]), sacc[TX * TY + t]);
           sacc[2 * TX * TY + t] = fma(aj, static_cast<double>(nv[i][2]), sacc[2 * TX * TY + t]);
+          if (c.terms) {
+            T* tr = c.terms + static_cast<int64_t>(c.j0 + r - 1) * c.terms_ld + (z0 + ly) * nx + gx;
+            tr[0] = nv[i][0];
+            tr[N] = nv[i][1];
+            tr[2 * N] = nv[i][2];
+          }
         }
       }
     }
@@ -227,7 +241,7 @@ __device__ __forceinline__ void fused2d_pass(const Geo<T, K, 2>& g, const T* __r
       }
     }
   }
-  for (int t = tid; t < TX * TY; t += kFusedNT) {
+  for (int t = tid; t < TX * TY && sum; t += kFusedNT) {
     const int ty = t / TX, tx = t - ty * TX;
     const int gxx = x0 + H + tx, gz = z0 + H + ty;
     if (gxx >= nx || gz >= nz) continue;
@@ -291,8 +305,12 @@ template <typename T, int S, int K>
 int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                      const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
                      double* acc_out, T* state_out, int j, bool first, const double* a,
-                     const double* q, double kappa, double inv_ws, double c0, double c1, RecRun<T> rec) {
+                     const double* q, double kappa, double inv_ws, double c0, double c1, RecRun<T> rec,
+                     T* terms = nullptr) {
   FusedArgs<T, S> c{};
+  c.terms = terms;
+  c.terms_ld = 3 * g.N;
+  c.j0 = j;
   c.rec = rec;
   c.kappa = static_cast<T>(kappa);
   c.inv_ws = static_cast<T>(inv_ws);
@@ -315,8 +333,10 @@ int32_t launch_fused(hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<
   // algorithmic bytes per point: reads v_{j-1} (3 T), c^2 (1 T), and unless
   // first v_{j-2} (3 T) and the FP64 sum (3 doubles); writes the sum (3
   // doubles, or the step's result: 3 T), and unless last the pair (6 T)
-  const double bytes = (3 + 1 + (first ? 0 : 3) + (out_last ? 6 : 0) + (state_out ? 3 : 0)) * sizeof(T) +
-                       ((first ? 0 : 3) + (state_out ? 0 : 3)) * sizeof(double);
+  const bool sum = acc_out != nullptr || state_out != nullptr;
+  const double bytes = (3 + 1 + (first ? 0 : 3) + (out_last ? 6 : 0) + (state_out ? 3 : 0) + (terms ? 3 * S : 0)) *
+                           sizeof(T) +
+                       ((first || !sum ? 0 : 3) + (state_out || !sum ? 0 : 3)) * sizeof(double);
   launch_timed(prof, st, EXPW_KERNEL_FABER, bytes * g.N, k_faber_fused2d<T, S, K>,
                dim3(blocks), dim3(kFusedNT), g, vp, vpp, acc_in, out_last, out_prev, acc_out,
                state_out, c, src);
@@ -329,11 +349,12 @@ template <typename T, int K>
 int32_t launch_pass(int n, hipStream_t st, Profiler* prof, const Geo<T, K, 2>& g, Src<T> src,
                     const T* vp, const T* vpp, const double* acc_in, T* out_last, T* out_prev,
                     double* acc_out, T* state_out, int j, bool first, const double* a,
-                    const double* q, double kappa, double inv_ws, double c0, double c1, RecRun<T> rec) {
+                    const double* q, double kappa, double inv_ws, double c0, double c1, RecRun<T> rec,
+                    T* terms = nullptr) {
 #define EXPW_PASS(S_)                                                                          \
   case S_:                                                                                     \
     return launch_fused<T, S_, K>(st, prof, g, src, vp, vpp, acc_in, out_last, out_prev,      \
-                                  acc_out, state_out, j, first, a, q, kappa, inv_ws, c0, c1, rec);
+                                  acc_out, state_out, j, first, a, q, kappa, inv_ws, c0, c1, rec, terms);
   if constexpr (sizeof(T) == 4 && K == 2) {
     switch (n) {
       EXPW_PASS(2) EXPW_PASS(3) EXPW_PASS(4) EXPW_PASS(5) EXPW_PASS(6) EXPW_PASS(7) EXPW_PASS(8)
