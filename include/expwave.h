@@ -467,11 +467,13 @@ int32_t expw_set_krylov_expm(expw_op* op, int32_t mode);
 
 /* allow = 1 (default): when the grid fits in registers across one cooperative
  * grid (every thread holding up to two grid points with all their fields,
- * three in 2D), the Arnoldi process runs as one persistent launch with two
- * grid-wide reductions per column (modified Gram-Schmidt's projections from
- * one batched reduction of the dots and the basis Gram entries, by forward
- * substitution); otherwise, and with allow = 0, one launch per matrix-vector
- * product and per Gram-Schmidt step. Results agree to rounding. */
+ * three in 2D), the Arnoldi process runs as one persistent launch with one
+ * grid-wide reduction per column (modified Gram-Schmidt's projections from
+ * one batched reduction of the dots, the basis Gram entries and the column's
+ * norm, by forward substitution) and, in place of a second barrier, waits on
+ * the flags of the workgroups whose part of the new column its stencil
+ * reads; otherwise, and with allow = 0, one launch per matrix-vector product
+ * and four per Gram-Schmidt column. Results agree to rounding. */
 int32_t expw_set_krylov_persistent(expw_op* op, int32_t allow);
 
 /* ------------------------------------------------------------------ timing */
