@@ -1,5 +1,5 @@
 // Two Faber terms per HBM sweep for 3D grids (order 4, zero ghosts): a
-// workgroup owns a 56 x 8 column tile and a chunk of 64 z-planes, and streams
+// workgroup owns a 56 x 8 column tile and a chunk of 32 z-planes, and streams
 // upwards in z. One thread per (x, y) column of the tile grown by 4 cells
 // (64 x 16 threads). At iteration k the plane k of v_{j-1} (u) is loaded;
 // the first term computes v_j (a) at plane k - 2 on the tile grown by 2 (the
@@ -11,12 +11,12 @@
 // five, of a: three). Each plane ring slot is written two iterations before
 // it is read and read one iteration before it is overwritten, so one barrier
 // per iteration separates all of them. Every global load of an iteration is
-// issued one iteration ahead. Per point and pass: reads u, v_{j-2}, the sum (4 words each)
-// and c^2, writes v_{j+1}, v_j and the sum: 25 words for two terms against 42
-// for two one-term sweeps (the sum in FP64: two words more each way). The
-// terms are computed entirely in T with the integer weights and kappa =
-// wscale / gamma on an ellipse where kappa, c0 and c1 are exact in T (as in
-// the streamed 2D passes, stream2d.h); the partial sum is FP64.
+// issued two iterations ahead. Per point and pass: reads u and v_{j-2} (4
+// words each), the FP64 sum (8 words) and c^2, writes v_{j+1}, v_j and the
+// sum: 33 words for two terms against 58 for two one-term sweeps. The terms
+// are computed entirely in T with the integer weights and kappa = wscale /
+// gamma on an ellipse where kappa, c0 and c1 are exact in T (as in the
+// streamed 2D passes, stream2d.h); the partial sum is FP64.
 #pragma once
 
 #include "device_common.h"
