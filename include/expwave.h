@@ -615,7 +615,7 @@ int32_t expw_pml_step_rk4(expw_pml* op, void* state_dev, double t0, double dt, i
  * agree to rounding. */
 int32_t expw_pml_set_path(expw_pml* op, int32_t path);
 
-/* The path (1, 2 or 3) a step of degree m takes under the current setting. */
+/* The path (1 to 4) a step of degree m takes under the current setting. */
 int32_t expw_pml_path_for(const expw_pml* op, int32_t m, int32_t* path);
 
 /* Synchronizes the stream and reports device errors. */

@@ -916,7 +916,7 @@ class PMLOperator:
         _check(load().expw_pml_set_path(self.op, int(path)))
 
     def path_for(self, m):
-        """The term kernel (1, 2 or 3) a step of degree m takes."""
+        """The term kernel (1 to 4) a step of degree m takes."""
         out = _i32(0)
         _check(load().expw_pml_path_for(self.op, int(m), ctypes.byref(out)))
         return out.value
