@@ -334,7 +334,10 @@ int32_t expw_apply_adjoint(expw_op* op, const void* x_dev, void* y_dev);
  * the derivative with respect to c^2 at fixed ellipse and coefficients.
  * terms_dev: caller scratch of (m - 1) state vectors (NULL when m = 1). The
  * ellipse, coefficients and source are those of expw_step_faber at t, so
- * this is the exact transpose of that step's linear part. Uses the workspace. */
+ * this is the exact transpose of that step's linear part. On 2D grids with
+ * zero ghosts the reverse terms run two per launch while j - 1 >= 1 (unless
+ * expw_set_tuning asked for one term per sweep), with results equal to one
+ * term per launch. Uses the workspace. */
 int32_t expw_faber_adjoint_step(expw_op* op, const void* u_dev, void* lam_dev, double t, double dt,
                                 int32_t m, void* grad_c2_dev, void* terms_dev);
 /* Reverse of one Krylov step of dimension k from t (Sec. 3.2, Krylov

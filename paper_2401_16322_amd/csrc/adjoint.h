@@ -170,6 +170,114 @@ __global__ __launch_bounds__(kBlock) void k_faber_adjoint_term(Geo<T, K, DIM> g,
                                c.inv_gamma * mp * velocity_divergence_d<T, K, BC, DIM>(g, vprev, idx, ic));
 }
 
+// Two reverse terms per launch on 2D grids with zero ghosts: mu_j and
+// mu_{j-1} (j - 1 >= 1), with the gradient contributions of both. A
+// workgroup owns a kAdjTX x kAdjTZ tile, one thread per tile point. Phase 1 computes mu_j on the tile
+// grown by K (the reach of H^T) exactly as k_faber_adjoint_term does, from
+// mu1 = mu_{j+1} and mu2 = mu_{j+2} in global memory, and keeps it, rounded
+// to T, in LDS (zero outside the grid, the ghost rule). Phase 2 applies H^T
+// to mu_j from LDS with the same arithmetic in the same order, forms
+// mu_{j-1} on the tile, stores both terms and updates the gradient with term
+// j, then term j - 1. Results equal two launches of k_faber_adjoint_term
+// bit for bit; the launches and the reads of lam and grad are halved. mu1 and
+// mu2 may be NULL (zero); vprev1 = v_{j-1}, vprev2 = v_{j-2}. mu_j and
+// mu_{j-1} must not alias mu1, mu2, lam, the vprev or each other.
+constexpr int kAdjTX = 64, kAdjTZ = 16, kAdjNT = kAdjTX * kAdjTZ;  // one thread per tile point
+
+template <typename T, int K>
+__global__ __launch_bounds__(kAdjNT) void k_faber_adjoint_pair(Geo<T, K, 2> g, const T* mu1, const T* mu2,
+                                                               const T* __restrict__ lam,
+                                                               const T* __restrict__ vprev1,
+                                                               const T* __restrict__ vprev2, T* mu_j, T* mu_jm1,
+                                                               T* __restrict__ grad, AdjointTerm c1,
+                                                               AdjointTerm c2, int32_t tiles_x) {
+  constexpr int GX = kAdjTX + 2 * K, GZ = kAdjTZ + 2 * K;
+  __shared__ T sm[3][GX * GZ];  // mu_j on the grown tile: p, v_x, v_z
+  const int bx = static_cast<int>(blockIdx.x) % tiles_x, bz = static_cast<int>(blockIdx.x) / tiles_x;
+  const int64_t nx = g.n[0], nz = g.n[1];
+  const int64_t x0 = static_cast<int64_t>(bx) * kAdjTX, z0 = static_cast<int64_t>(bz) * kAdjTZ;
+  // phase 1: mu_j on the grown tile
+  for (int i = threadIdx.x; i < GX * GZ; i += kAdjNT) {
+    const int64_t x = x0 - K + i % GX, z = z0 - K + i / GX;
+    if (x < 0 || x >= nx || z < 0 || z >= nz) {
+      sm[0][i] = sm[1][i] = sm[2][i] = T(0);
+      continue;
+    }
+    const int64_t idx = z * nx + x;
+    const int64_t ic[3] = {x, z, 0};
+    double o[3], s[3];
+    if (mu1) {
+      apply_point_adjoint_d<T, K, 0, 2>(g, mu1, idx, ic, o, s);
+    } else {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) o[f] = s[f] = 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const int64_t e = f * g.N + idx;
+      double mu = c1.a_j * static_cast<double>(lam[e]);
+      mu += o[f] * c1.inv_gamma - c1.c0 * s[f];
+      if (mu2) mu -= c1.cnext * static_cast<double>(mu2[e]);
+      sm[f][i] = static_cast<T>(mu);
+    }
+  }
+  __syncthreads();
+  // phase 2: mu_{j-1} on the tile
+  {
+    const int i = threadIdx.x;
+    const int64_t x = x0 + i % kAdjTX, z = z0 + i / kAdjTX;
+    if (x >= nx || z >= nz) return;
+    const int64_t idx = z * nx + x;
+    const int64_t ic[3] = {x, z, 0};
+    const int l = (i / kAdjTX + K) * GX + (i % kAdjTX + K);  // the point in the grown tile
+    // H^T mu_j at the point, as apply_point_adjoint_d with LDS neighbours
+    double o[3], s[3];
+    {
+      const double pc = static_cast<double>(sm[0][l]);
+      s[0] = pc;
+      double div = 0.0, sp = 0.0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T* v = sm[1 + a];
+        const int ls = a == 0 ? 1 : GX;
+        double dv = 0.0, dcp = 0.0;
+#pragma unroll
+        for (int q = 1; q <= K; ++q) {
+          dv += g.wd[q - 1] * (static_cast<double>(v[l + (q - 1) * ls]) - static_cast<double>(v[l - q * ls]));
+          dcp += g.wd[q - 1] *
+                 (static_cast<double>(ldn<T, 0>(g.c2, idx, ic[a], g.n[a], g.st[a], q)) *
+                      static_cast<double>(sm[0][l + q * ls]) -
+                  static_cast<double>(ldn<T, 0>(g.c2, idx, ic[a], g.n[a], g.st[a], 1 - q)) *
+                      static_cast<double>(sm[0][l + (1 - q) * ls]));
+        }
+        div += dv;
+        sp += static_cast<double>(g.sint[a][ic[a]]);
+        const double vc = static_cast<double>(v[l]);
+        s[1 + a] = vc;
+        o[1 + a] = dcp - static_cast<double>(g.shalf[a][ic[a]]) * vc;
+      }
+      o[0] = div - sp * pc;
+    }
+    double mp = 0.0;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const int64_t e = f * g.N + idx;
+      mu_j[e] = sm[f][l];
+      double mu = c2.a_j * static_cast<double>(lam[e]);
+      mu += o[f] * c2.inv_gamma - c2.c0 * s[f];
+      if (mu1) mu -= c2.cnext * static_cast<double>(mu1[e]);
+      const T mt = static_cast<T>(mu);
+      mu_jm1[e] = mt;
+      if (f == 0) mp = static_cast<double>(mt);
+    }
+    const T g1 = static_cast<T>(static_cast<double>(grad[idx]) -
+                                c1.inv_gamma * static_cast<double>(sm[0][l]) *
+                                    velocity_divergence_d<T, K, 0, 2>(g, vprev1, idx, ic));
+    grad[idx] = static_cast<T>(static_cast<double>(g1) -
+                               c2.inv_gamma * mp * velocity_divergence_d<T, K, 0, 2>(g, vprev2, idx, ic));
+  }
+}
+
 // Krylov adjoint (Sec. 3.2, Krylov subspace projection, differentiated): the
 // state adjoint is the Krylov approximation of exp(dt H^T) lam (Arnoldi on
 // H^T from lam, no augmentation), and the c^2 derivative of

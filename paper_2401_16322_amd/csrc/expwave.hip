@@ -954,20 +954,44 @@ int32_t faber_adjoint_impl(expw_op* op, const T* U, T* lam, double t, double dt,
                  make_src<T>(op, q[j - 1]));
     if (int32_t rc = check_launch("adjoint: forward terms")) return rc;
   }
-  // reverse: mu_j for j = m..0 (mu_j into buffer j mod 3, mu_0 into lam)
-  T* mbuf[3] = {reinterpret_cast<T*>(op->ws + op->off_big), nullptr, nullptr};
-  mbuf[1] = mbuf[0] + ns;
-  mbuf[2] = mbuf[1] + ns;
+  // reverse: mu_j for j = m..0 (mu_j into buffer j mod 4, mu_0 into lam); on
+  // 2D zero-ghost grids two terms per launch while j - 1 >= 1 (unless one
+  // term per sweep is asked for), the rest one per launch
+  T* mbuf[4] = {reinterpret_cast<T*>(op->ws + op->off_big), nullptr, nullptr, nullptr};
+  for (int i = 1; i < 4; ++i) mbuf[i] = mbuf[i - 1] + ns;
   auto cc = [&](int j) { return j < 2 ? 0.0 : (j == 2 ? 2.0 * el.c1 : el.c1); };
-  AdjointTerm c{};
-  c.inv_gamma = f.inv_gamma;
-  c.c0 = f.c0;
-  for (int j = m; j >= 0; --j) {
+  auto term_coef = [&](int j) {
+    AdjointTerm c{};
+    c.inv_gamma = f.inv_gamma;
+    c.c0 = f.c0;
     c.a_j = a[j];
     c.cnext = cc(j + 2);
-    const T* mu1 = j + 1 <= m ? mbuf[(j + 1) % 3] : nullptr;
-    const T* mu2 = j + 2 <= m ? mbuf[(j + 2) % 3] : nullptr;
-    T* out = j == 0 ? lam : mbuf[j % 3];
+    return c;
+  };
+  int j = m;
+  if constexpr (DIM == 2 && BC == 0) {
+    if (op->fuse != 1) {
+      const int tiles_x = static_cast<int>((g.n[0] + kAdjTX - 1) / kAdjTX);
+      const int64_t blocks = static_cast<int64_t>(tiles_x) * ((g.n[1] + kAdjTZ - 1) / kAdjTZ);
+      for (; j >= 2; j -= 2) {
+        const T* mu1 = j + 1 <= m ? mbuf[(j + 1) % 4] : nullptr;
+        const T* mu2 = j + 2 <= m ? mbuf[(j + 2) % 4] : nullptr;
+        // reads lam, mu1 (+ c^2), mu2, v_{j-1}, v_{j-2} (velocities), grad;
+        // writes mu_j, mu_{j-1}, grad
+        const double words = 3 * nf + (mu1 ? nf : 0) + 1 + (mu2 ? nf : 0) + 2 * DIM + 2;
+        launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, words * pb, k_faber_adjoint_pair<T, K>,
+                     dim3(static_cast<unsigned>(blocks)), dim3(kAdjNT), g, mu1, mu2, static_cast<const T*>(lam),
+                     v(j - 1), v(j - 2), mbuf[j % 4], mbuf[(j - 1) % 4], grad, term_coef(j), term_coef(j - 1),
+                     tiles_x);
+        if (int32_t rc = check_launch("adjoint term pair")) return rc;
+      }
+    }
+  }
+  for (; j >= 0; --j) {
+    const AdjointTerm c = term_coef(j);
+    const T* mu1 = j + 1 <= m ? mbuf[(j + 1) % 4] : nullptr;
+    const T* mu2 = j + 2 <= m ? mbuf[(j + 2) % 4] : nullptr;
+    T* out = j == 0 ? lam : mbuf[j % 4];
     // reads lam, mu1 (+ c^2 with the stencil), mu2, v_{j-1}; writes mu_j, grad RMW
     const double words = nf + (mu1 ? nf + 1 : 0) + (mu2 ? nf : 0) + nf + (j > 0 ? DIM + 2 : 0);
     launch_timed(&op->prof, op->stream, EXPW_KERNEL_FABER, words * pb,

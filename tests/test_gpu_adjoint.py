@@ -43,6 +43,28 @@ def test_faber_adjoint_step_matches_oracle(dtype, m):
     assert eg <= tol
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("order,m", [(4, 9), (8, 6), (8, 7)])
+def test_faber_adjoint_pairs_match_oracle(dtype, order, m):
+    """Reverse terms two per launch on ragged tiles (131 x 37 against 64 x 16
+    tiles), orders 4 and 8, even and odd degree, with a source."""
+    import torch
+    case = make_case((131, 37), dtype, order=order, seed=36, n_src=2)
+    g = case.prob.grid
+    ell = case.prob.ellipse()
+    lam0 = np.random.default_rng(7).normal(size=g.nstate)
+    u = case.U0
+    lam = to_dev(case, lam0)
+    grad = torch.zeros(g.npts, dtype=case.torch_dtype, device="cuda")
+    case.op.faber_adjoint_step(to_dev(case, u), lam, 0.03, 2e-3, m, grad)
+    mu0, gref = faber_adjoint_step(case.prob, u, lam0, 0.03, 2e-3, m, p=case.p, ellipse=ell)
+    tol = TOL[dtype]
+    el, eg = rel_l2(lam.cpu().numpy(), mu0), rel_l2(grad.cpu().numpy(), gref)
+    print(f"faber adjoint pairs {dtype} order {order} m={m}: lam {el:.2e} grad {eg:.2e}")
+    assert el <= tol
+    assert eg <= tol
+
+
 def test_adjoint_step_dot_product_on_gpu():
     """Without a source: <step(u), lam> = <u, step^T lam> in FP64."""
     import torch
