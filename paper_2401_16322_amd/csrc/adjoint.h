@@ -172,14 +172,14 @@ __global__ __launch_bounds__(kBlock) void k_faber_adjoint_term(Geo<T, K, DIM> g,
 
 // Two reverse terms per launch on 2D grids with zero ghosts: mu_j and
 // mu_{j-1} (j - 1 >= 1), with the gradient contributions of both. A
-// workgroup owns a kAdjTX x kAdjTZ tile, one thread per tile point. Phase 1 computes mu_j on the tile
-// grown by K (the reach of H^T) exactly as k_faber_adjoint_term does, from
-// mu1 = mu_{j+1} and mu2 = mu_{j+2} in global memory, and keeps it, rounded
-// to T, in LDS (zero outside the grid, the ghost rule). Phase 2 applies H^T
-// to mu_j from LDS with the same arithmetic in the same order, forms
-// mu_{j-1} on the tile, stores both terms and updates the gradient with term
-// j, then term j - 1. Results equal two launches of k_faber_adjoint_term
-// bit for bit; the launches and the reads of lam and grad are halved. mu1 and
+// workgroup owns a kAdjTX x kAdjTZ tile, one thread per tile point. Phase 1
+// computes mu_j on the tile grown by K (the reach of H^T) exactly as
+// k_faber_adjoint_term does, from mu1 = mu_{j+1} and mu2 = mu_{j+2} in
+// global memory, and keeps it, rounded to T, in LDS (zero outside the grid,
+// the ghost rule). Phase 2 applies H^T to mu_j from LDS, forms mu_{j-1} on
+// the tile, stores both terms and updates the gradient with term j, then
+// term j - 1. Every value takes the arithmetic of k_faber_adjoint_term in the
+// same order; the launches and the reads of lam and grad are halved. mu1 and
 // mu2 may be NULL (zero); vprev1 = v_{j-1}, vprev2 = v_{j-2}. mu_j and
 // mu_{j-1} must not alias mu1, mu2, lam, the vprev or each other.
 constexpr int kAdjTX = 64, kAdjTZ = 16, kAdjNT = kAdjTX * kAdjTZ;  // one thread per tile point
