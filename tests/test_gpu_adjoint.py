@@ -44,12 +44,15 @@ def test_faber_adjoint_step_matches_oracle(dtype, m):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("order,m", [(4, 9), (8, 6), (8, 7)])
-def test_faber_adjoint_pairs_match_oracle(dtype, order, m):
+@pytest.mark.parametrize("n,order,m", [((131, 37), 4, 9), ((131, 37), 8, 6), ((131, 37), 8, 7),
+                                       ((1, 40), 4, 5), ((40, 1), 8, 4), ((3, 2), 4, 6)])
+def test_faber_adjoint_pairs_match_oracle(dtype, n, order, m):
     """Reverse terms two per launch on ragged tiles (131 x 37 against 64 x 16
-    tiles), orders 4 and 8, even and odd degree, with a source."""
+    tiles) and on degenerate grids (one row, one column, 3 x 2), orders 4 and
+    8, even and odd degree, with a source."""
     import torch
-    case = make_case((131, 37), dtype, order=order, seed=36, n_src=2)
+    case = make_case(n, dtype, order=order, seed=36, n_src=2 if min(n) > 2 else 1,
+                     abc=min(4, max(1, min(n) // 3)))
     g = case.prob.grid
     ell = case.prob.ellipse()
     lam0 = np.random.default_rng(7).normal(size=g.nstate)
@@ -60,7 +63,7 @@ def test_faber_adjoint_pairs_match_oracle(dtype, order, m):
     mu0, gref = faber_adjoint_step(case.prob, u, lam0, 0.03, 2e-3, m, p=case.p, ellipse=ell)
     tol = TOL[dtype]
     el, eg = rel_l2(lam.cpu().numpy(), mu0), rel_l2(grad.cpu().numpy(), gref)
-    print(f"faber adjoint pairs {dtype} order {order} m={m}: lam {el:.2e} grad {eg:.2e}")
+    print(f"faber adjoint pairs {dtype} {n} order {order} m={m}: lam {el:.2e} grad {eg:.2e}")
     assert el <= tol
     assert eg <= tol
 
