@@ -2352,22 +2352,32 @@ PmlGeo<T> make_pml_geo(const expw_pml* op) {
   g.nx = static_cast<int32_t>(op->g.nx);
   g.ny = static_cast<int32_t>(op->g.ny);
   g.N = op->g.nx * op->g.ny;
-  g.ih = static_cast<T>(1.0 / op->g.h);
-  g.ih2 = static_cast<T>(1.0 / (op->g.h * op->g.h));
-  double alpha[4];
+  // the interior weights as integers (exact in T) with one scale each; the
+  // surface tables and 1/h, 1/h^2 as hi + lo in T (lo = 0 in FP64)
+  auto split = [](double w, T& hi, T& lo) {
+    hi = static_cast<T>(w);
+    lo = static_cast<T>(w - static_cast<double>(hi));
+  };
+  const double h = op->g.h;
+  split(1.0 / h, g.ih, g.ih_lo);
+  split(1.0 / (h * h), g.ih2, g.ih2_lo);
+  double wi[4], beta = 0.0;
   int K = 0;
-  stagger_weights(8, alpha, &K);
-  for (int l = 0; l < 4; ++l) g.a[l] = static_cast<T>(alpha[l]);
-  // Sec. 2.1, centred second derivative (read with sums)
-  g.d2c = static_cast<T>(-205.0 / 72.0);
-  const double b[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+  stagger_weights_int(8, wi, &beta, &K);  // alpha_l = beta wi_l, beta = 1/107520
+  for (int l = 0; l < 4; ++l) g.a[l] = static_cast<T>(wi[l]);
+  g.sc1 = static_cast<T>(beta / h);
+  // Sec. 2.1, centred second derivative (read with sums): (-205/72, 8/5,
+  // -1/5, 8/315, -1/560) = (-14350, 8064, -1008, 128, -9) / 5040
+  g.d2c = static_cast<T>(-14350.0);
+  const double b[4] = {8064.0, -1008.0, 128.0, -9.0};
   for (int l = 0; l < 4; ++l) g.d2[l] = static_cast<T>(b[l]);
+  g.sc2 = static_cast<T>(1.0 / (5040.0 * h * h));
   for (int r = 0; r < 4; ++r)
-    for (int k = 0; k < 9; ++k) g.s2[r][k] = static_cast<T>(op->d2[r][k]);
+    for (int k = 0; k < 9; ++k) split(op->d2[r][k], g.s2[r][k], g.s2_lo[r][k]);
   for (int r = 0; r < 3; ++r)
-    for (int k = 0; k < 8; ++k) g.s1[r][k] = static_cast<T>(op->d1[r][k]);
+    for (int k = 0; k < 8; ++k) split(op->d1[r][k], g.s1[r][k], g.s1_lo[r][k]);
   for (int r = 0; r < 4; ++r)
-    for (int k = 0; k < 8; ++k) g.sw[r][k] = static_cast<T>(op->dw[r][k]);
+    for (int k = 0; k < 8; ++k) split(op->dw[r][k], g.sw[r][k], g.sw_lo[r][k]);
   g.c2 = static_cast<const T*>(op->c2);
   g.bx = reinterpret_cast<const T*>(op->ws + op->off_bx);
   g.bxh = reinterpret_cast<const T*>(op->ws + op->off_bxh);

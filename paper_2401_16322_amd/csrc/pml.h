@@ -27,16 +27,26 @@ struct PmlTerm {
   int32_t first;
 };
 
+// The interior stencils use their integer weights, exact in T, and scale
+// each sum once by sc1 = 1/(107520 h) (first derivative) or sc2 = 1/(5040
+// h^2) (second derivative). With the weights rounded to FP32 one by one, a
+// stencil loses its exact consistency (the second-derivative weights no
+// longer sum to zero, for one): an error term of order u / h^2 that a whole
+// FP32 run accumulates as phase error. The rounding of a scale only rescales
+// the operator by at most 2^-24. The one-sided tables of the four surface
+// rows, which are not integers, and 1/h, 1/h^2 are held as hi + lo in T (lo
+// = w - hi rounded to T, zero in FP64).
 template <typename T>
 struct PmlGeo {
   int32_t nx, ny;
   int64_t N;
-  T ih, ih2;        // 1/h, 1/h^2
-  T a[4];           // staggered first derivative
-  T d2c, d2[4];     // centred second derivative: d2c u_i + sum d2_l (u_{i+l} + u_{i-l})
-  T s2[4][9];       // d_yy u at rows 0..3 from u_0..u_8
-  T s1[3][8];       // d_y u at half rows 0..2 from u_0..u_7
-  T sw[4][8];       // d_y w_y at rows 0..3 from w_0..w_7
+  T ih, ih2, ih_lo, ih2_lo;  // 1/h, 1/h^2
+  T sc1, sc2;                // 1/(107520 h), 1/(5040 h^2)
+  T a[4];                    // staggered first derivative: 107520 alpha_l (integers)
+  T d2c, d2[4];              // centred second derivative times 5040: d2c u_i + sum d2_l (u_{i+l} + u_{i-l})
+  T s2[4][9], s2_lo[4][9];   // h^2 d_yy u at rows 0..3 from u_0..u_8
+  T s1[3][8], s1_lo[3][8];   // h d_y u at half rows 0..2 from u_0..u_7
+  T sw[4][8], sw_lo[4][8];   // h d_y w_y at rows 0..3 from w_0..w_7
   const T* __restrict__ c2;
   const T* __restrict__ bx;   // beta_x at nodes, at half points
   const T* __restrict__ bxh;
@@ -48,6 +58,44 @@ struct PmlGeo {
 template <typename T>
 __device__ __forceinline__ T pml_at(const PmlGeo<T>& g, const T* f, int i, int j) {
   return (i >= 0 && i < g.nx && j >= 0 && j < g.ny) ? f[static_cast<int64_t>(j) * g.nx + i] : T(0);
+}
+
+// The components of H x at a node from its derivative sums: i* over the
+// integer interior weights (units of the scales sc2 for ixy, sc1 for iw, ixu,
+// iyu), p* over the surface tables' hi parts and l* over their lo parts
+// (units of 1/h^2 for pxy, lxy and 1/h for the others); s, c^2 and the
+// profiles at the node; surf: a surface row (j < 4), where the tables apply.
+template <typename T>
+__device__ __forceinline__ void pml_combine(const PmlGeo<T>& g, T bx, T bxh, T by, T byh, T c2, T ixy, T iw,
+                                            T ixu, T iyu, T pxy, T pw, T pyu, T lxy, T lw, T lyu, bool surf,
+                                            T o[4], const T s[4]) {
+  T sxy, sw, sxu, syu;
+  if constexpr (sizeof(T) == 4) {
+    sxy = ixy * g.sc2;
+    sw = iw * g.sc1;
+    sxu = ixu * g.sc1;
+    syu = iyu * g.sc1;
+    if (surf) {  // the tables' sums (zero below the surface rows)
+      const T qxy = pxy + lxy, qw = pw + lw, qyu = pyu + lyu;
+      sxy = sxy + (qxy * g.ih2 + qxy * g.ih2_lo);
+      sw = sw + (qw * g.ih + qw * g.ih_lo);
+      syu = syu + (qyu * g.ih + qyu * g.ih_lo);
+    }
+  } else {
+    sxy = ixy * g.sc2;
+    sw = iw * g.sc1;
+    sxu = ixu * g.sc1;
+    syu = iyu * g.sc1;
+    if (surf) {
+      sxy = sxy + pxy * g.ih2;
+      sw = sw + pw * g.ih;
+      syu = syu + pyu * g.ih;
+    }
+  }
+  o[0] = s[1];
+  o[1] = -bx * by * s[0] + c2 * sxy - (bx + by) * s[1] + c2 * sw;
+  o[2] = (by - bxh) * sxu - bxh * s[2];
+  o[3] = (bx - byh) * syu - byh * s[3];
 }
 
 // The four components o of H x at node (i, j), and x itself there (s), with
@@ -62,6 +110,8 @@ __device__ __forceinline__ void pml_point_acc(const PmlGeo<T>& g, int i, int j, 
   s[1] = vc;
   s[2] = WX(0);
   s[3] = WY(0);
+  constexpr bool LO = sizeof(T) == 4;  // add the surface tables' lo parts
+  // x: integer weights
   T dxx = g.d2c * s[0], dwx = T(0), dxu = T(0);
 #pragma unroll
   for (int l = 1; l <= 4; ++l) {
@@ -69,12 +119,22 @@ __device__ __forceinline__ void pml_point_acc(const PmlGeo<T>& g, int i, int j, 
     dwx += g.a[l - 1] * (WX(l - 1) - WX(-l));
     dxu += g.a[l - 1] * (U(l, 0) - U(1 - l, 0));
   }
+  // y: integer weights in the interior, the tables at the surface rows
   T dyy = T(0), dwy = T(0), dyu = T(0);
+  T pyy = T(0), pwy = T(0), pyu = T(0), lyy = T(0), lwy = T(0), lyu = T(0);
   if (j < 4) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) dyy += g.s2[j][k] * U(0, k - j);
+    for (int k = 0; k < 9; ++k) {
+      const T uk = U(0, k - j);
+      pyy += g.s2[j][k] * uk;
+      if constexpr (LO) lyy += g.s2_lo[j][k] * uk;
+    }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) dwy += g.sw[j][k] * WY(k - j);
+    for (int k = 0; k < 8; ++k) {
+      const T wk = WY(k - j);
+      pwy += g.sw[j][k] * wk;
+      if constexpr (LO) lwy += g.sw_lo[j][k] * wk;
+    }
   } else {
     dyy = g.d2c * s[0];
 #pragma unroll
@@ -85,18 +145,18 @@ __device__ __forceinline__ void pml_point_acc(const PmlGeo<T>& g, int i, int j, 
   }
   if (j < 3) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) dyu += g.s1[j][k] * U(0, k - j);
+    for (int k = 0; k < 8; ++k) {
+      const T uk = U(0, k - j);
+      pyu += g.s1[j][k] * uk;
+      if constexpr (LO) lyu += g.s1_lo[j][k] * uk;
+    }
   } else {
 #pragma unroll
     for (int l = 1; l <= 4; ++l) dyu += g.a[l - 1] * (U(0, 1 - l) - U(0, l));
   }
   const int64_t n = static_cast<int64_t>(j) * g.nx + i;
-  const T bx = g.bx[i], bxh = g.bxh[i], by = g.by[j], byh = g.byh[j];
-  const T c2 = g.c2[n];
-  o[0] = s[1];
-  o[1] = -bx * by * s[0] + c2 * ((dxx + dyy) * g.ih2) - (bx + by) * s[1] + c2 * ((dwx + dwy) * g.ih);
-  o[2] = (by - bxh) * (dxu * g.ih) - bxh * s[2];
-  o[3] = (bx - byh) * (dyu * g.ih) - byh * s[3];
+  pml_combine(g, g.bx[i], g.bxh[i], g.by[j], g.byh[j], g.c2[n], dxx + dyy, dwx + dwy, dxu, dyu, pyy, pwy, pyu,
+              lyy, lwy, lyu, j < 4, o, s);
 }
 
 // The same with every read from global memory.

@@ -122,17 +122,26 @@ __device__ __forceinline__ auto& ps_level(Q& q) {
 
 // The y-derivative sums of pml_point_acc at a row known at compile time:
 // JT = 0..3 a surface row (j = JT), JT < 0 an interior row (j >= 4). U(0,
-// dj) and WY(dj) as there; s0 = u at the node.
+// dj) and WY(dj) as there; s0 = u at the node. d*: over the integer interior
+// weights; p*, l*: over the surface tables' hi and lo parts (l* in FP32 only).
 template <int JT, typename T, typename FU, typename FY>
-__device__ __forceinline__ void pml_y_sums(const PmlGeo<T>& g, FU&& U, FY&& WY, T s0, T& dyy, T& dwy, T& dyu) {
-  dyy = T(0);
-  dwy = T(0);
-  dyu = T(0);
+__device__ __forceinline__ void pml_y_sums(const PmlGeo<T>& g, FU&& U, FY&& WY, T s0, T& dyy, T& dwy, T& dyu,
+                                           T& pyy, T& pwy, T& pyu, T& lyy, T& lwy, T& lyu) {
+  constexpr bool LO = sizeof(T) == 4;
+  dyy = dwy = dyu = pyy = pwy = pyu = lyy = lwy = lyu = T(0);
   if constexpr (JT >= 0) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) dyy += g.s2[JT][k] * U(0, k - JT);
+    for (int k = 0; k < 9; ++k) {
+      const T uk = U(0, k - JT);
+      pyy += g.s2[JT][k] * uk;
+      if constexpr (LO) lyy += g.s2_lo[JT][k] * uk;
+    }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) dwy += g.sw[JT][k] * WY(k - JT);
+    for (int k = 0; k < 8; ++k) {
+      const T wk = WY(k - JT);
+      pwy += g.sw[JT][k] * wk;
+      if constexpr (LO) lwy += g.sw_lo[JT][k] * wk;
+    }
   } else {
     dyy = g.d2c * s0;
 #pragma unroll
@@ -143,7 +152,11 @@ __device__ __forceinline__ void pml_y_sums(const PmlGeo<T>& g, FU&& U, FY&& WY, 
   }
   if constexpr (JT >= 0 && JT < 3) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) dyu += g.s1[JT][k] * U(0, k - JT);
+    for (int k = 0; k < 8; ++k) {
+      const T uk = U(0, k - JT);
+      pyu += g.s1[JT][k] * uk;
+      if constexpr (LO) lyu += g.s1_lo[JT][k] * uk;
+    }
   } else {
 #pragma unroll
     for (int l = 1; l <= 4; ++l) dyu += g.a[l - 1] * (U(0, 1 - l) - U(0, l));
@@ -168,16 +181,13 @@ __device__ __forceinline__ void pml_point_row(const PmlGeo<T>& g, int j, T vc, F
     dwx += g.a[l - 1] * (WX(l - 1) - WX(-l));
     dxu += g.a[l - 1] * (U(l, 0) - U(1 - l, 0));
   }
-  T dyy, dwy, dyu;
-  if (j >= 4) pml_y_sums<-1>(g, U, WY, s[0], dyy, dwy, dyu);
-  else if (j == 3) pml_y_sums<3>(g, U, WY, s[0], dyy, dwy, dyu);
-  else if (j == 2) pml_y_sums<2>(g, U, WY, s[0], dyy, dwy, dyu);
-  else if (j == 1) pml_y_sums<1>(g, U, WY, s[0], dyy, dwy, dyu);
-  else pml_y_sums<0>(g, U, WY, s[0], dyy, dwy, dyu);
-  o[0] = s[1];
-  o[1] = -bx * by * s[0] + c2 * ((dxx + dyy) * g.ih2) - (bx + by) * s[1] + c2 * ((dwx + dwy) * g.ih);
-  o[2] = (by - bxh) * (dxu * g.ih) - bxh * s[2];
-  o[3] = (bx - byh) * (dyu * g.ih) - byh * s[3];
+  T dyy, dwy, dyu, pyy, pwy, pyu, lyy, lwy, lyu;
+  if (j >= 4) pml_y_sums<-1>(g, U, WY, s[0], dyy, dwy, dyu, pyy, pwy, pyu, lyy, lwy, lyu);
+  else if (j == 3) pml_y_sums<3>(g, U, WY, s[0], dyy, dwy, dyu, pyy, pwy, pyu, lyy, lwy, lyu);
+  else if (j == 2) pml_y_sums<2>(g, U, WY, s[0], dyy, dwy, dyu, pyy, pwy, pyu, lyy, lwy, lyu);
+  else if (j == 1) pml_y_sums<1>(g, U, WY, s[0], dyy, dwy, dyu, pyy, pwy, pyu, lyy, lwy, lyu);
+  else pml_y_sums<0>(g, U, WY, s[0], dyy, dwy, dyu, pyy, pwy, pyu, lyy, lwy, lyu);
+  pml_combine(g, bx, bxh, by, byh, c2, dxx + dyy, dwx + dwy, dxu, dyu, pyy, pwy, pyu, lyy, lwy, lyu, j < 4, o, s);
 }
 
 // One pass over band (blockIdx.x % bands) and row segment (blockIdx.x /

@@ -8,9 +8,10 @@ calls the HIP library: the inputs come from `synthetic`, every value from
 
     python tests/golden/make_oracle_runs.py <run>
 
-Runs (see RUNS): whole runs for the long-run parity tests, the converged
-reference of the time-to-solution measurement and its dt/2 check, and the
-central planes of the 256^3 workload.
+Runs (see RUNS and PML_RUNS): whole runs for the long-run parity tests, the
+converged reference of the time-to-solution measurement and its dt/2 check,
+the central planes of the 256^3 workload, and a whole run of the paper's PML
+operator.
 """
 from __future__ import annotations
 
@@ -46,6 +47,13 @@ RUNS = {
     "layered3d256_faber24_dt2.5": ("layered3d_256", "faber", 24, 2.5e-3, 1.0, 0.25, "planes"),
 }
 
+# the paper's operator (the PML system with a free surface, Sec. 2) on the
+# small box: name: (workload, PML cells, beta0, method, order, dt, T, snapshot
+# spacing); stores the first field over the whole grid
+PML_RUNS = {
+    "pml241_faber16_dt2": ("layered2d_241x161", 20, 200.0, "faber", 16, 2e-3, 1.0, 0.25),
+}
+
 
 def interior(w, p):
     """Pressure over the physical domain (layer of abc_cells cells excluded)."""
@@ -63,7 +71,40 @@ def planes(w, p):
             np.ascontiguousarray(f[:, :, nx // 2])]
 
 
+def main_pml(name):
+    from oracle import pml
+    wname, cells, beta0, method, order, dt, T, every = PML_RUNS[name]
+    w = get_workload(wname)
+    nx, ny = w.n
+    g = pml.PMLGrid(nx, ny, w.h, abc_cells=cells, beta0=beta0)
+    src = pml.PMLSources((w.source_node(),), (1.0,), w.f_peak, w.t_delay)
+    prob = pml.PMLProblem(g, w.c2(), src)
+    nsteps = int(round(T / dt))
+    per = int(round(every / dt))
+    assert abs(per * dt - every) < 1e-12 and per * (nsteps // per) == nsteps
+    ell = prob.ellipse()
+    U = np.zeros(g.nstate)
+    out = {}
+    t0 = time.time()
+    for n in range(nsteps):
+        U = step(prob, method, U, n * dt, dt, m=order, p=w.taylor_p, ellipse=ell)
+        if (n + 1) % per == 0:
+            k = (n + 1) // per
+            out[f"p{k}"] = np.ascontiguousarray(U[: g.npts].reshape(ny, nx))
+            print(f"{name}: t = {(n + 1) * dt:.3f} s after {time.time() - t0:.0f} s", flush=True)
+            meta = {"workload": wname, "operator": "pml", "pml_cells": cells, "beta0": beta0,
+                    "method": method, "order": order, "dt": dt, "T": T, "snapshot_every": every,
+                    "stored": "pml_first_field", "snapshots_done": k, "taylor_p": w.taylor_p,
+                    "c2": "float32-representable (Workload.c2)", "ellipse": list(ell),
+                    "seconds": time.time() - t0}
+            tmp = os.path.join(HERE, f"oracle_{name}.tmp.npz")
+            np.savez_compressed(tmp, meta=np.array(json.dumps(meta)), **out)
+            os.replace(tmp, os.path.join(HERE, f"oracle_{name}.npz"))
+
+
 def main(name):
+    if name in PML_RUNS:
+        return main_pml(name)
     wname, method, order, dt, T, every, what = RUNS[name]
     w = get_workload(wname)
     g = Grid(w.n, w.h, 4, abc_cells=w.abc_cells, sigma_max=w.sigma_max)

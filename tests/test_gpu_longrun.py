@@ -135,3 +135,36 @@ def test_layered3d_256_whole_run_planes_match_stored_oracle(dtype):
     minutes on one core, so the stored run holds the first snapshot,
     t = 0.25 s after 100 steps)."""
     _check("layered3d256_faber24_dt2.5", dtype)
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+@pytest.mark.parametrize("path", [0, 3, 4])
+def test_pml_whole_run_matches_stored_oracle(dtype, path):
+    """The paper's operator (PML system with a free surface, 8th-order
+    stencils) on the 241 x 161 box with a 20-cell PML (beta0 = 200): 500
+    Faber steps of m = 16 at dt = 2 ms, the first field over the whole grid
+    every 0.25 s, on the automatic path, the two-term pairs and the
+    row-streamed passes."""
+    import torch
+    from paper_2401_16322_amd.expwave import PMLOperator
+    from synthetic import get_workload
+    meta, ref = _load("pml241_faber16_dt2")
+    w = get_workload(meta["workload"])
+    nx, ny = w.n
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    op = PMLOperator(nx, ny, w.h, torch.tensor(w.c2(), dtype=tdt, device="cuda"), abc_cells=meta["pml_cells"],
+                     beta0=meta["beta0"], max_taylor_p=meta["taylor_p"])
+    op.set_source_ricker([w.source_node()], [1.0], w.f_peak, w.t_delay, meta["taylor_p"])
+    op.set_path(path)
+    U = torch.zeros(4 * nx * ny, dtype=tdt, device="cuda")
+    dt, per = meta["dt"], int(round(meta["snapshot_every"] / meta["dt"]))
+    errs = {}
+    for k in range(1, meta["snapshots_done"] + 1):
+        op.step_faber(U, (k - 1) * per * dt, dt, meta["order"], per)
+        got = U[: nx * ny].double().cpu().numpy().reshape(ny, nx)
+        r = ref[f"p{k}"]
+        errs[k] = float(np.linalg.norm(got - r) / np.linalg.norm(r))
+    op.sync()
+    del op
+    print(f"pml whole run {dtype} path {path}: " + " ".join(f"p{k}={e:.2e}" for k, e in errs.items()), flush=True)
+    assert max(errs.values()) <= TOL[dtype], errs
