@@ -2339,8 +2339,8 @@ PmlLayout pml_layout(const expw_pml_grid& g, int kmax, int pmax) {
   L.big = off;
   const int64_t ns = 4 * g.nx * g.ny;
   L.naug_pad = (ns + pmax + 63) / 64 * 64;
-  // Faber: two pairs of terms and the partial sum; Krylov: kmax + 1 basis vectors
-  size_t big = 5 * static_cast<size_t>(ns) * es;
+  // Faber: two pairs of terms and the FP64 partial sum; Krylov: kmax + 1 basis vectors
+  size_t big = 4 * static_cast<size_t>(ns) * es + static_cast<size_t>(ns) * sizeof(double);
   if (kmax > 0) big = std::max(big, static_cast<size_t>(kmax + 1) * L.naug_pad * es);
   L.total = align_up(off + big);
   return L;
@@ -2404,7 +2404,7 @@ Src<T> make_pml_src(const expw_pml* op, double q) {
 // with halos, so it never writes them; a first pass that is also the last
 // (m = 2) sums into C and copies to S.
 template <typename T, typename Term>
-int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D, T* E, const double* a,
+int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, double* C, T* D, T* E, const double* a,
                   const double* q, int m, double gs, double c0s, double c1s, int tiles_x, unsigned grid,
                   Term&& term) {
   const int64_t ns = 4 * g.N;
@@ -2426,7 +2426,9 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
     split_weight(a[j + 1], &t1.a_j, &t1.a_j_lo);
     T* o0 = last ? nullptr : pair_out[which][0];
     T* o1 = last ? nullptr : pair_out[which][1];
-    T* acc_out = (last && vp != S) ? S : C;
+    // the last pass rounds the sum into S, or into A when it reads S (m = 2)
+    double* acc_out = last ? nullptr : C;
+    T* state_out = last ? (vp != S ? S : A) : nullptr;
     // FP32: 1024-thread blocks on 64 x 32 tiles; FP64 (more registers): 256 on 64 x 16
     constexpr int NT = sizeof(T) == 4 ? 1024 : 256, TY = sizeof(T) == 4 ? 32 : 16;
     const int ptx = static_cast<int>((g.nx + kPmlTX - 1) / kPmlTX);
@@ -2434,11 +2436,11 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
     const int pbw = (ptx + 7) / 8;
     const unsigned pgrid = 8u * static_cast<unsigned>(pbw) * static_cast<unsigned>(pty);
     k_pml_faber_pair_lds<T, NT, TY><<<pgrid, NT, 0, op->stream>>>(g, vp, vpp, o0, o1, j == 1 ? nullptr : C, acc_out,
-                                                                  t0, t1, make_pml_src<T>(op, q[j - 1]),
+                                                                  state_out, t0, t1, make_pml_src<T>(op, q[j - 1]),
                                                                   make_pml_src<T>(op, q[j]), ptx, pty, pbw);
     if (int32_t rc = check_launch("pml faber pair")) return rc;
-    if (last && acc_out == C) {
-      if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
+    if (last && state_out == A) {
+      if (hipMemcpyAsync(S, A, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
         return fail(EXPW_EDEVICE, "pml faber: copy failed");
     }
     vpp = pair_out[which][0];
@@ -2452,7 +2454,7 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
     c.c0 = static_cast<T>(c0s);
     c.cpp = static_cast<T>(c1s);
     split_weight(a[m], &c.a_j, &c.a_j_lo);
-    term(vp, vpp, nullptr, C, S, c, q[m - 1]);
+    term(vp, vpp, nullptr, C, nullptr, S, c, q[m - 1]);
     if (int32_t rc = check_launch("pml faber last term")) return rc;
   }
   return EXPW_OK;
@@ -2463,7 +2465,7 @@ int32_t pml_pairs(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D
 // passes allows (the larger ones first); a last pass of one term (m odd at
 // FP64) takes the one-term kernel. Buffers as in pml_pairs.
 template <typename T, typename Term>
-int32_t pml_stream_passes(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T* C, T* D, T* E, const double* a,
+int32_t pml_stream_passes(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, double* C, T* D, T* E, const double* a,
                           const double* q, int m, double gs, double c0s, double c1s, Term&& term) {
   const int64_t ns = 4 * g.N;
   constexpr int smax = sizeof(T) == 4 ? kPmlStreamDepth : 2;
@@ -2484,27 +2486,29 @@ int32_t pml_stream_passes(expw_pml* op, const PmlGeo<T>& g, T* S, T* A, T* B, T*
       c.c0 = static_cast<T>(c0s);
       c.cpp = static_cast<T>(c1s);
       split_weight(a[m], &c.a_j, &c.a_j_lo);
-      term(vp, vpp, nullptr, C, S, c, q[m - 1]);
+      term(vp, vpp, nullptr, C, nullptr, S, c, q[m - 1]);
       if (int32_t rc = check_launch("pml faber last term")) return rc;
       break;
     }
     T* ol = last ? nullptr : pair_out[which][1];
     T* opv = last ? nullptr : pair_out[which][0];
-    T* acc_out = (last && vp != S) ? S : C;
+    // the last pass rounds the sum into S, or into A when it reads S
+    double* acc_out = last ? nullptr : C;
+    T* state_out = last ? (vp != S ? S : A) : nullptr;
     const Src<T> src = make_pml_src<T>(op, 0.0);
     int32_t rc = EXPW_OK;
     if constexpr (sizeof(T) == 4) {
       switch (n) {
-        case 2: rc = launch_pml_stream<T, 2>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, j, a, q, gs, c0s, c1s); break;
-        case 3: rc = launch_pml_stream<T, 3>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, j, a, q, gs, c0s, c1s); break;
-        default: rc = launch_pml_stream<T, 4>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, j, a, q, gs, c0s, c1s); break;
+        case 2: rc = launch_pml_stream<T, 2>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, state_out, j, a, q, gs, c0s, c1s); break;
+        case 3: rc = launch_pml_stream<T, 3>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, state_out, j, a, q, gs, c0s, c1s); break;
+        default: rc = launch_pml_stream<T, 4>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, state_out, j, a, q, gs, c0s, c1s); break;
       }
     } else {
-      rc = launch_pml_stream<T, 2>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, j, a, q, gs, c0s, c1s);
+      rc = launch_pml_stream<T, 2>(op->stream, g, src, vp, vpp, C, ol, opv, acc_out, state_out, j, a, q, gs, c0s, c1s);
     }
     if (rc != EXPW_OK) return rc;
-    if (last && acc_out == C) {
-      if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
+    if (last && state_out == A) {
+      if (hipMemcpyAsync(S, A, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
         return fail(EXPW_EDEVICE, "pml faber: copy failed");
     }
     vpp = opv;
@@ -2523,7 +2527,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   const int64_t ns = 4 * g.N;
   T* A = reinterpret_cast<T*>(op->ws + op->off_big);
   T* B = A + ns;
-  T* C = B + ns;
+  double* C = reinterpret_cast<double*>(B + ns);  // the FP64 partial sum
   double gs, c0s, c1s;
   step_ellipse(sizeof(T) == 4 ? EXPW_F32 : EXPW_F64, op->gamma, op->c0, op->c1, &gs, &c0s, &c1s);
   std::vector<double> a(m + 1), q(m, 0.0), der(EXPW_MAX_TAYLOR), G(EXPW_MAX_TAYLOR);
@@ -2538,16 +2542,17 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
   const bool streamed = path == 4;
   const bool lds = path >= 2;
   const unsigned grid = lds ? 8u * static_cast<unsigned>(band_w) * static_cast<unsigned>(tiles_y) : grid_for(g.N);
-  T* D = C + ns;
+  T* D = reinterpret_cast<T*>(C + ns);
   T* E = D + ns;
-  // one term: the LDS kernel on tiles or one thread per node
-  auto term = [&](const T* vp, const T* vpp, T* vout, const T* acc_in, T* acc_out, const PmlTerm<T>& c,
-                  double qj) {
+  // one term: the LDS kernel on tiles or one thread per node; the sum to
+  // acc_out, or rounded into state_out on the step's last term
+  auto term = [&](const T* vp, const T* vpp, T* vout, const double* acc_in, double* acc_out, T* state_out,
+                  const PmlTerm<T>& c, double qj) {
     if (lds)
-      k_pml_faber_term_lds<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, c,
+      k_pml_faber_term_lds<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, state_out, c,
                                                                make_pml_src<T>(op, qj), tiles_x, tiles_y, band_w);
     else
-      k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, c,
+      k_pml_faber_term<T><<<grid, kBlock, 0, op->stream>>>(g, vp, vpp, vout, acc_in, acc_out, state_out, c,
                                                            make_pml_src<T>(op, qj));
   };
   for (int64_t st = 0; st < nsteps; ++st) {
@@ -2579,11 +2584,11 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
     c.first = 1;
     split_weight(a[0], &c.a_first, &c.a_first_lo);
     split_weight(a[1], &c.a_j, &c.a_j_lo);
-    // (S is read with a halo here, so the sum of a one-term step goes to C first)
-    term(S, nullptr, m == 1 ? nullptr : A, nullptr, C, c, q[0]);
+    // (S is read with a halo here, so a one-term step rounds its sum into A first)
+    term(S, nullptr, m == 1 ? nullptr : A, nullptr, m == 1 ? nullptr : C, m == 1 ? A : nullptr, c, q[0]);
     if (int32_t rc = check_launch("pml faber j=1")) return rc;
     if (m == 1) {
-      if (hipMemcpyAsync(S, C, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
+      if (hipMemcpyAsync(S, A, ns * sizeof(T), hipMemcpyDeviceToDevice, op->stream) != hipSuccess)
         return fail(EXPW_EDEVICE, "pml faber: copy failed");
     } else {
       // j = 2: v2 = F1 v1 - 2 c1 v0 into B
@@ -2591,7 +2596,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
       c.a_first = c.a_first_lo = T(0);
       c.cpp = static_cast<T>(2.0 * c1s);
       split_weight(a[2], &c.a_j, &c.a_j_lo);
-      term(A, S, m == 2 ? nullptr : B, C, m == 2 ? S : C, c, q[1]);
+      term(A, S, m == 2 ? nullptr : B, C, m == 2 ? nullptr : C, m == 2 ? S : nullptr, c, q[1]);
       if (int32_t rc = check_launch("pml faber j=2")) return rc;
       T* last = B;
       T* older = A;
@@ -2599,7 +2604,7 @@ int32_t pml_faber_impl(expw_pml* op, T* S, double t0, double dt, int m, int64_t 
       for (int j = 3; j <= m; ++j) {
         split_weight(a[j], &c.a_j, &c.a_j_lo);
         const bool fin = j == m;
-        term(last, older, fin ? nullptr : older, C, fin ? S : C, c, q[j - 1]);
+        term(last, older, fin ? nullptr : older, C, fin ? nullptr : C, fin ? S : nullptr, c, q[j - 1]);
         if (int32_t rc = check_launch("pml faber term")) return rc;
         std::swap(last, older);
       }

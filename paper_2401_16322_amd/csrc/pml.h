@@ -65,6 +65,14 @@ __device__ __forceinline__ T pml_at(const PmlGeo<T>& g, const T* f, int i, int j
 // iyu), p* over the surface tables' hi parts and l* over their lo parts
 // (units of 1/h^2 for pxy, lxy and 1/h for the others); s, c^2 and the
 // profiles at the node; surf: a surface row (j < 4), where the tables apply.
+// The partial sum of a Faber step on the PML operator is FP64 between terms
+// and passes (FP32 sums drift over long FP32 runs): acc + a x with a given
+// as hi + lo in T.
+template <typename T>
+__device__ __forceinline__ double sum_add(double acc, T hi, T lo, T x) {
+  return fma(static_cast<double>(hi) + static_cast<double>(lo), static_cast<double>(x), acc);
+}
+
 template <typename T>
 __device__ __forceinline__ void pml_combine(const PmlGeo<T>& g, T bx, T bxh, T by, T byh, T c2, T ixy, T iw,
                                             T ixu, T iyu, T pxy, T pw, T pyu, T lxy, T lw, T lyu, bool surf,
@@ -191,13 +199,14 @@ __global__ __launch_bounds__(kBlock) void k_pml_apply(PmlGeo<T> g, const T* __re
 
 // One Faber term (Sec. 3.2) on the PML operator, as k_faber_term, one thread
 // per node with every read from global memory (the path for grids with few
-// tiles). The source enters the v equation. vout may alias vpp and acc_out may
-// alias acc_in or vpp; vp is read with a halo and must not alias an output;
+// tiles). The source enters the v equation. The FP64 sum goes to acc_out, or
+// rounded to T into state_out (the step's last term; acc_out null). acc_out
+// may alias acc_in; vp is read with a halo and must not alias an output;
 // vout == nullptr skips storing v_j.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pml_faber_term(PmlGeo<T> g, const T* vp, const T* vpp,
-                                                           T* vout, const T* acc_in, T* acc_out,
-                                                           PmlTerm<T> c, Src<T> src) {
+                                                           T* vout, const double* acc_in, double* acc_out,
+                                                           T* state_out, PmlTerm<T> c, Src<T> src) {
   const int64_t n = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   if (n >= g.N) return;
   const int j = static_cast<int>(n / g.nx), i = static_cast<int>(n - static_cast<int64_t>(j) * g.nx);
@@ -210,8 +219,10 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term(PmlGeo<T> g, const T*
     if (vpp) v -= c.cpp * vpp[e];
     if (f == 1) v += src_value(src, n);
     if (vout) vout[e] = v;
-    T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, s[f]) : acc_in[e];
-    acc_out[e] = add_weighted(acc, c.a_j, c.a_j_lo, v);
+    double acc = c.first ? sum_add(0.0, c.a_first, c.a_first_lo, s[f]) : acc_in[e];
+    acc = sum_add(acc, c.a_j, c.a_j_lo, v);
+    if (state_out) state_out[e] = static_cast<T>(acc);
+    else acc_out[e] = acc;
   }
 }
 
@@ -234,8 +245,8 @@ __device__ __forceinline__ bool pml_band_tile(int tiles_x, int tiles_y, int band
 // read with a halo and must not alias an output; vout == nullptr skips v_j.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, const T* vp, const T* vpp,
-                                                               T* vout, const T* acc_in, T* acc_out,
-                                                               PmlTerm<T> c, Src<T> src,
+                                                               T* vout, const double* acc_in, double* acc_out,
+                                                               T* state_out, PmlTerm<T> c, Src<T> src,
                                                                int tiles_x, int tiles_y, int band_w) {
   static_assert(kBlock == 256 && kPmlTX == 64, "4 waves, one tile column per lane");
   constexpr int TX = kPmlTX, TY = kPmlTY, HL = kPmlHalo;
@@ -282,8 +293,10 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, cons
       if (vpp) v -= c.cpp * vpp[e];
       if (f == 1) v += src_value(src, n);
       if (vout) vout[e] = v;
-      T acc = c.first ? add_weighted(T(0), c.a_first, c.a_first_lo, s[f]) : acc_in[e];
-      acc_out[e] = add_weighted(acc, c.a_j, c.a_j_lo, v);
+      double acc = c.first ? sum_add(0.0, c.a_first, c.a_first_lo, s[f]) : acc_in[e];
+      acc = sum_add(acc, c.a_j, c.a_j_lo, v);
+      if (state_out) state_out[e] = static_cast<T>(acc);
+      else acc_out[e] = acc;
     }
   }
 }
@@ -297,10 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_pml_faber_term_lds(PmlGeo<T> g, cons
 // skipped when its pointer is null) and the sum acc_in + a_j v_j + a_{j+1}
 // v_{j+1} (for c0.first: a_0 v_{j-1} + ...). vpp (v_{j-2}, null for j = 1)
 // is read on R1, so no output may alias vp or vpp; acc_out may alias acc_in.
+// The FP64 sum goes to acc_out, or rounded to T into state_out (acc_out null).
 template <typename T, int NT, int TY>
 __global__ __launch_bounds__(NT) void k_pml_faber_pair_lds(PmlGeo<T> g, const T* vp, const T* vpp,
-                                                           T* out0, T* out1, const T* acc_in,
-                                                           T* acc_out, PmlTerm<T> c0,
+                                                           T* out0, T* out1, const double* acc_in,
+                                                           double* acc_out, T* state_out, PmlTerm<T> c0,
                                                            PmlTerm<T> c1, Src<T> s0, Src<T> s1,
                                                            int tiles_x, int tiles_y, int band_w) {
   constexpr int TX = kPmlTX, NW = NT / 64;
@@ -385,9 +399,11 @@ __global__ __launch_bounds__(NT) void k_pml_faber_pair_lds(PmlGeo<T> g, const T*
       if (k == 1) val += src_value(s1, n);
       if (out0) out0[e] = sc[k];
       if (out1) out1[e] = val;
-      T acc = c0.first ? add_weighted(T(0), c0.a_first, c0.a_first_lo, old[k]) : acc_in[e];
-      acc = add_weighted(acc, c0.a_j, c0.a_j_lo, sc[k]);
-      acc_out[e] = add_weighted(acc, c1.a_j, c1.a_j_lo, val);
+      double acc = c0.first ? sum_add(0.0, c0.a_first, c0.a_first_lo, old[k]) : acc_in[e];
+      acc = sum_add(acc, c0.a_j, c0.a_j_lo, sc[k]);
+      acc = sum_add(acc, c1.a_j, c1.a_j_lo, val);
+      if (state_out) state_out[e] = static_cast<T>(acc);
+      else acc_out[e] = acc;
     }
   }
 }

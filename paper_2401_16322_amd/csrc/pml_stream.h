@@ -196,12 +196,14 @@ __device__ __forceinline__ void pml_point_row(const PmlGeo<T>& g, int j, T vc, F
 // earlier passes (FIRST: unused); acc_out: the new sum (the step's result on
 // the last pass). out_last, out_prev: v_{j+S-1} and v_{j+S-2} (nullptr on the
 // last pass). No output may alias vp, vpp or another output; acc_out may
-// alias acc_in.
+// alias acc_in. The sum is FP64; state_out (acc_out null): the step's result,
+// rounded to T.
 template <typename T, int S, bool FIRST>
 __global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, const T* __restrict__ vp,
-                                                            const T* __restrict__ vpp, const T* acc_in,
+                                                            const T* __restrict__ vpp, const double* acc_in,
                                                             T* __restrict__ out_last, T* __restrict__ out_prev,
-                                                            T* acc_out, PmlStreamArgs<T, S> c, Src<T> src) {
+                                                            double* acc_out, T* state_out, PmlStreamArgs<T, S> c,
+                                                            Src<T> src) {
   static_assert(S >= 2 && S <= 4, "2 to 4 terms per pass");
   constexpr int NT = ps_nt<T>();
   constexpr int H = 4, W = NT - 2 * H * S;
@@ -234,18 +236,25 @@ __global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, co
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[k] = in ? f[k * N + n] : T(0);
   };
+  auto ld4d = [&](const double* f, int j, bool use, double out[4]) {
+    const bool in = use && xin && j >= 0 && j < ny;
+    const int64_t n = in ? static_cast<int64_t>(j) * nx + i : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = in ? f[k * N + n] : 0.0;
+  };
   auto ld_c2 = [&](int j) -> T {
     const bool in = xin && j >= 0 && j < ny;
     return in ? g.c2[static_cast<int64_t>(j) * nx + i] : T(0);
   };
   // loaded one iteration ahead: the input row, v_{j-2} at level 0's row, the
   // sum at the output row and c^2 at every level's row
-  T nxt_in[4], nxt_old[4], nxt_acc[4], nxt_c2[S];
+  T nxt_in[4], nxt_old[4], nxt_c2[S];
+  double nxt_acc[4];
   ld4(vp, jstart, true, nxt_in);
   ld4(vpp, jstart + 4, !FIRST, nxt_old);
   {
     const int jo = jstart + 4 * S;
-    ld4(acc_in, jo, !FIRST && out_col && jo >= z0 && jo < z1, nxt_acc);
+    ld4d(acc_in, jo, !FIRST && out_col && jo >= z0 && jo < z1, nxt_acc);
   }
 #pragma unroll
   for (int r = 0; r < S; ++r) nxt_c2[r] = ld_c2(jstart + 4 * (r + 1));
@@ -266,7 +275,7 @@ __global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, co
     // 2. the input row enters level -1; the next loads are issued
     const T cur_in[4] = {nxt_in[0], nxt_in[1], nxt_in[2], nxt_in[3]};
     const T old0[4] = {nxt_old[0], nxt_old[1], nxt_old[2], nxt_old[3]};
-    const T acc_row[4] = {nxt_acc[0], nxt_acc[1], nxt_acc[2], nxt_acc[3]};
+    const double acc_row[4] = {nxt_acc[0], nxt_acc[1], nxt_acc[2], nxt_acc[3]};
     T c2l[S];
 #pragma unroll
     for (int r = 0; r < S; ++r) c2l[r] = nxt_c2[r];
@@ -275,7 +284,7 @@ __global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, co
       ld4(vp, jn, true, nxt_in);
       ld4(vpp, jn + 4, !FIRST, nxt_old);
       const int jo = jn + 4 * S;
-      ld4(acc_in, jo, !FIRST && out_col && jo >= z0 && jo < z1, nxt_acc);
+      ld4d(acc_in, jo, !FIRST && out_col && jo >= z0 && jo < z1, nxt_acc);
 #pragma unroll
       for (int r = 0; r < S; ++r) nxt_c2[r] = ld_c2(jn + 4 * (r + 1));
     }
@@ -328,14 +337,14 @@ __global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, co
     const int jo = jin + 4 * S;
     if (out_col && jo >= z0 && jo < z1) {
       const int64_t n = static_cast<int64_t>(jo) * nx + i;
-      T acc[4];
+      double acc[4];
       if constexpr (FIRST) {
         auto& I_ = q.in;  // v_0 at the output row
         constexpr int d = 4 * S;
-        acc[0] = add_weighted(T(0), c.a_first, c.a_first_lo, I_.u[d]);
-        acc[1] = add_weighted(T(0), c.a_first, c.a_first_lo, I_.v[d]);
-        acc[2] = add_weighted(T(0), c.a_first, c.a_first_lo, I_.wx[d]);
-        acc[3] = add_weighted(T(0), c.a_first, c.a_first_lo, I_.wy[d]);
+        acc[0] = sum_add(0.0, c.a_first, c.a_first_lo, I_.u[d]);
+        acc[1] = sum_add(0.0, c.a_first, c.a_first_lo, I_.v[d]);
+        acc[2] = sum_add(0.0, c.a_first, c.a_first_lo, I_.wx[d]);
+        acc[3] = sum_add(0.0, c.a_first, c.a_first_lo, I_.wy[d]);
       } else {
 #pragma unroll
         for (int f = 0; f < 4; ++f) acc[f] = acc_row[f];
@@ -344,15 +353,15 @@ __global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, co
       if constexpr (R + 1 < S) {                                           \
         auto& Q_ = ps_level<R>(q);                                         \
         constexpr int d = 4 * (S - 1 - R);                                 \
-        acc[0] = add_weighted(acc[0], c.a[R], c.a_lo[R], Q_.u[d]);         \
-        acc[1] = add_weighted(acc[1], c.a[R], c.a_lo[R], Q_.v[d]);         \
-        acc[2] = add_weighted(acc[2], c.a[R], c.a_lo[R], Q_.wx[d]);        \
-        acc[3] = add_weighted(acc[3], c.a[R], c.a_lo[R], Q_.wy[d]);        \
+        acc[0] = sum_add(acc[0], c.a[R], c.a_lo[R], Q_.u[d]);              \
+        acc[1] = sum_add(acc[1], c.a[R], c.a_lo[R], Q_.v[d]);              \
+        acc[2] = sum_add(acc[2], c.a[R], c.a_lo[R], Q_.wx[d]);             \
+        acc[3] = sum_add(acc[3], c.a[R], c.a_lo[R], Q_.wy[d]);             \
       }
       EXPW_PS_SUM(0) EXPW_PS_SUM(1) EXPW_PS_SUM(2)
 #undef EXPW_PS_SUM
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc[f] = add_weighted(acc[f], c.a[S - 1], c.a_lo[S - 1], lastv[f]);
+      for (int f = 0; f < 4; ++f) acc[f] = sum_add(acc[f], c.a[S - 1], c.a_lo[S - 1], lastv[f]);
       if (out_last) {
         auto& V_ = ps_level<S - 2>(q);  // v_{j+S-2} at the output row
         const T pv[4] = {V_.u[4], V_.v[4], V_.wx[4], V_.wy[4]};
@@ -363,7 +372,10 @@ __global__ __launch_bounds__(ps_nt<T>()) void k_pml_faber_stream(PmlGeo<T> g, co
         }
       }
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc_out[f * N + n] = acc[f];
+      for (int f = 0; f < 4; ++f) {
+        if (state_out) state_out[f * N + n] = static_cast<T>(acc[f]);
+        else acc_out[f * N + n] = acc[f];
+      }
     }
   }
 }
@@ -418,7 +430,8 @@ bool pml_stream_fits(int64_t nx, int64_t ny, int S) {
 // Terms j .. j + n - 1 in one streamed pass (n <= S of the instantiations).
 template <typename T, int S>
 int32_t launch_pml_stream(hipStream_t st, const PmlGeo<T>& g, Src<T> src, const T* vp, const T* vpp,
-                          const T* acc_in, T* out_last, T* out_prev, T* acc_out, int j, const double* a,
+                          const double* acc_in, T* out_last, T* out_prev, double* acc_out, T* state_out,
+                          int j, const double* a,
                           const double* q, double gs, double c0s, double c1s) {
   constexpr int NT = ps_nt<T>();
   constexpr int W = NT - 8 * S;
@@ -440,10 +453,10 @@ int32_t launch_pml_stream(hipStream_t st, const PmlGeo<T>& g, Src<T> src, const 
   if (blocks > INT32_MAX) return fail(EXPW_EUNSUPPORTED, "streamed PML pass: grid too large");
   if (first)
     k_pml_faber_stream<T, S, true><<<static_cast<unsigned>(blocks), NT, 0, st>>>(
-        g, vp, nullptr, nullptr, out_last, out_prev, acc_out, c, src);
+        g, vp, nullptr, nullptr, out_last, out_prev, acc_out, state_out, c, src);
   else
     k_pml_faber_stream<T, S, false><<<static_cast<unsigned>(blocks), NT, 0, st>>>(
-        g, vp, vpp, acc_in, out_last, out_prev, acc_out, c, src);
+        g, vp, vpp, acc_in, out_last, out_prev, acc_out, state_out, c, src);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(EXPW_EDEVICE, "streamed PML pass: %s", hipGetErrorString(e));
   return EXPW_OK;
