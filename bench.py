@@ -147,23 +147,25 @@ def bench_pml(args, w):
         raise RuntimeError("pml: non-finite wavefield")
     npts = nx * ny
     es = 4 if args.dtype == "f32" else 8
-    # algorithmic words per point per step (four fields: reads of v_{j-1}, v_{j-2}
-    # and the sum, and c^2; writes of the new terms and the sum), by term kernel
+    # algorithmic bytes per point per step (four fields of es bytes: reads of
+    # v_{j-1}, v_{j-2} and c^2, writes of the new terms; the partial sum is FP64,
+    # 32 B read and 32 B written per pass), by term kernel
     path = op.path_for(m)
     if path in (3, 4) and m >= 2:
         # passes of several terms (pairs; row-streamed passes of up to 4 terms at
         # FP32 and 2 at FP64, as evenly sized as their count allows): the first
-        # pass reads v_0 and c^2 and writes the last two terms and the sum (17; 9
-        # if it is also the last); middle passes 13 + 12 = 25; a last pass, or
-        # a last single term, 13 + 4 = 17
+        # pass reads v_0 and c^2 and writes the last two terms and the sum
+        # (13 es + 32; 9 es if it is also the last); middle passes 17 es + 64; a
+        # last pass, or a last single term, 13 es + 32
         smax = 2 if path == 3 else (4 if args.dtype == "f32" else 2)
         npass = -(-m // smax)
-        words = 9 if npass == 1 else 17 + 25 * (npass - 2) + 17
+        bpp = 9 * es if npass == 1 else 2 * (13 * es + 32) + (17 * es + 64) * (npass - 2)
     else:
-        # one term per sweep: first term 13, middle terms 21, last term 17
+        # one term per sweep: first term 9 es + 32, middle terms 17 es + 64, last
+        # term 13 es + 32 (a single term 9 es)
         npass = m
-        words = 13 + 21 * (m - 2) + 17 if m >= 2 else 13
-    gbps = words * npts * es * args.steps / (ms * 1e-3) / 1e9
+        bpp = (9 * es + 32) + (17 * es + 64) * (m - 2) + (13 * es + 32) if m >= 2 else 9 * es
+    gbps = bpp * npts * args.steps / (ms * 1e-3) / 1e9
     kclass = {3: "pml_faber_pair", 4: "pml_faber_stream"}.get(path, "pml_faber_term")
     out = {
         "metric": "grid-pt matvecs/s", "value": npts * m * args.steps / (ms * 1e-3),
